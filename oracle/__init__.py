@@ -1,0 +1,184 @@
+"""CPU oracle for the GPFC fold + box-SNR path (arXiv:2312.02063).
+
+TEST INFRASTRUCTURE ONLY. The oracle is the plain, slow, FP64 statement of
+what the GPU library computes. Only ``tests/``, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py`` may import it; the product path
+(``paper_2312_02063_amd``) never does, and the two share no code.
+
+The arithmetic lives in ``gpfc_oracle.c`` (plain C, binary64,
+``-ffp-contract=off``); this module compiles it with gcc and wraps it with
+ctypes over numpy arrays. Each wrapper names the passage of the paper it
+follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gpfc_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-std=c11"]
+
+
+def build() -> str:
+    """Compile the oracle with gcc (always recompiles)."""
+    tmp = _LIB + ".tmp"
+    subprocess.run(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"], check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    dp = ctypes.POINTER(ctypes.c_double)
+    fp = ctypes.POINTER(ctypes.c_float)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    i64 = ctypes.c_int64
+    i32 = ctypes.c_int32
+    lib.oracle_curve_stats.argtypes = [dp, fp, i64, dp, dp, dp]
+    lib.oracle_curve_stats.restype = None
+    lib.oracle_bin.argtypes = [ctypes.c_double, ctypes.c_double, i32]
+    lib.oracle_bin.restype = i32
+    lib.oracle_fold.argtypes = [dp, fp, i64, dp, i64, i32, ctypes.c_double, dp, dp, ip, ctypes.c_int]
+    lib.oracle_fold.restype = None
+    lib.oracle_means.argtypes = [dp, ip, i64, dp]
+    lib.oracle_means.restype = None
+    lib.oracle_default_widths.argtypes = [i32, ip, i32]
+    lib.oracle_default_widths.restype = i32
+    lib.oracle_score.argtypes = [ip, dp, i64, i32, ctypes.c_double, ip, i32, dp, ip, ip, dp]
+    lib.oracle_score.restype = None
+    lib.oracle_box_snr.argtypes = [ip, dp, i32, ctypes.c_double, i32, i32]
+    lib.oracle_box_snr.restype = ctypes.c_double
+    lib.oracle_grid_size.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    lib.oracle_grid_size.restype = ctypes.c_double
+    _lib = lib
+    return lib
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def curve_stats(t, flux):
+    """Mean, sample std (ddof 1) and max |t| of a curve; sigma is Eq. 2's per-point noise."""
+    lib = _load()
+    t = _f64(t)
+    flux = _f32(flux)
+    m = ctypes.c_double()
+    s = ctypes.c_double()
+    tm = ctypes.c_double()
+    lib.oracle_curve_stats(_p(t, ctypes.c_double), _p(flux, ctypes.c_float), t.size,
+                           ctypes.byref(m), ctypes.byref(s), ctypes.byref(tm))
+    return m.value, s.value, tm.value
+
+
+def phase_bin(t: float, period: float, nbins: int) -> int:
+    """Bin of one sample at one period (Sec. 2.3 steps one and two)."""
+    return int(_load().oracle_bin(float(t), float(period), int(nbins)))
+
+
+def fold(t, flux, periods, nbins, ref=None, nthreads=1):
+    """Fold at every period (Sec. 2.3 steps one to three).
+
+    Returns ``(sums, dsums, counts)`` of shape ``[k, nbins]``: FP64 flux sums,
+    FP64 sums of ``flux - ref`` and int32 counts. ``ref`` defaults to the
+    curve mean.
+    """
+    lib = _load()
+    t = _f64(t)
+    flux = _f32(flux)
+    periods = _f64(periods)
+    if t.size != flux.size:
+        raise ValueError("t and flux differ in length")
+    if ref is None:
+        ref = curve_stats(t, flux)[0]
+    k = periods.size
+    sums = np.empty((k, nbins), np.float64)
+    dsums = np.empty((k, nbins), np.float64)
+    counts = np.empty((k, nbins), np.int32)
+    lib.oracle_fold(_p(t, ctypes.c_double), _p(flux, ctypes.c_float), t.size,
+                    _p(periods, ctypes.c_double), k, int(nbins), float(ref),
+                    _p(sums, ctypes.c_double), _p(dsums, ctypes.c_double),
+                    _p(counts, ctypes.c_int32), int(nthreads))
+    return sums, dsums, counts
+
+
+def means(sums, counts):
+    """Bin means (Sec. 2.3 step five); NaN for empty bins."""
+    lib = _load()
+    sums = _f64(sums)
+    counts = np.ascontiguousarray(counts, dtype=np.int32)
+    out = np.empty_like(sums)
+    lib.oracle_means(_p(sums, ctypes.c_double), _p(counts, ctypes.c_int32), sums.size,
+                     _p(out, ctypes.c_double))
+    return out
+
+
+def default_widths(nbins: int):
+    """Distinct integers nearest sqrt(2)^j in [1, nbins/2]."""
+    lib = _load()
+    buf = np.zeros(64, np.int32)
+    m = lib.oracle_default_widths(int(nbins), _p(buf, ctypes.c_int32), 64)
+    return buf[:m].copy()
+
+
+def score(counts, dsums, sigma, widths=None):
+    """Box-SNR of each folded row (Eq. 2 with the BLS box of Sec. 3.1).
+
+    Returns ``(snr, start, width, depth)``.
+    """
+    lib = _load()
+    counts = np.ascontiguousarray(counts, dtype=np.int32)
+    dsums = _f64(dsums)
+    k, nbins = counts.shape
+    w = default_widths(nbins) if widths is None else np.ascontiguousarray(widths, dtype=np.int32)
+    snr = np.empty(k, np.float64)
+    depth = np.empty(k, np.float64)
+    start = np.empty(k, np.int32)
+    width = np.empty(k, np.int32)
+    lib.oracle_score(_p(counts, ctypes.c_int32), _p(dsums, ctypes.c_double), k, nbins,
+                     float(sigma), _p(w, ctypes.c_int32), w.size, _p(snr, ctypes.c_double),
+                     _p(start, ctypes.c_int32), _p(width, ctypes.c_int32), _p(depth, ctypes.c_double))
+    return snr, start, width, depth
+
+
+def box_snr(counts_row, dsums_row, sigma, s, w):
+    """The statistic of one box on one folded row."""
+    lib = _load()
+    c = np.ascontiguousarray(counts_row, dtype=np.int32)
+    d = _f64(dsums_row)
+    return lib.oracle_box_snr(_p(c, ctypes.c_int32), _p(d, ctypes.c_double), c.size,
+                              float(sigma), int(s), int(w))
+
+
+def grid_size(n_o: float, span: float, width: float) -> float:
+    """Eq. 1 (Sec. 2.1): number of trial periods N_o * T / L."""
+    return _load().oracle_grid_size(float(n_o), float(span), float(width))
+
+
+def fold_score(t, flux, periods, nbins, widths=None, nthreads=1):
+    """Whole path on the CPU: stats, fold, box-SNR. Returns a dict."""
+    mean, sigma, _ = curve_stats(t, flux)
+    sums, dsums, counts = fold(t, flux, periods, nbins, ref=mean, nthreads=nthreads)
+    snr, start, width, depth = score(counts, dsums, sigma, widths)
+    return dict(mean=mean, sigma=sigma, sums=sums, dsums=dsums, counts=counts,
+                snr=snr, start=start, width=width, depth=depth)

@@ -1,0 +1,241 @@
+/*
+ * Reference oracle for the GPFC phase-fold + box-SNR hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY. This file is the plain, slow, obviously correct
+ * CPU statement of what the GPU library computes. Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it; the
+ * product path never does. It shares no code, header, table or constant
+ * with the HIP library.
+ *
+ * Arithmetic: IEEE-754 binary64, round-to-nearest-even, compiled with
+ * -O2 -ffp-contract=off -fno-fast-math so that every operation below is one
+ * correctly rounded step in the order written.
+ *
+ * Paper: Wang, Ge, Willis, Wang, Zhao, "The GPU Phase Folding and Deep
+ * Learning Method for Detecting Exoplanet Transits" (MNRAS 2024,
+ * arXiv:2312.02063).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/*
+ * Curve statistics used by the normalisation and the SNR.
+ * mean  = (sum of flux in sample order) / n                    (sequential)
+ * sigma = sqrt(sum (flux - mean)^2 / (n - 1))                   (two-pass)
+ * sigma is the per-point photometric scatter that Eq. 2 (Sec. 2.6) divides
+ * the depth by. n < 2 gives sigma = 0.
+ */
+void oracle_curve_stats(const double *t, const float *flux, int64_t n,
+                        double *mean_out, double *sigma_out, double *tmax_out) {
+    double s = 0.0, tmax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        s += (double)flux[i];
+        double a = fabs(t[i]);
+        if (a > tmax) tmax = a;
+    }
+    double mean = n > 0 ? s / (double)n : 0.0;
+    double ss = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double d = (double)flux[i] - mean;
+        ss += d * d;
+    }
+    *mean_out = mean;
+    *sigma_out = n > 1 ? sqrt(ss / (double)(n - 1)) : 0.0;
+    if (tmax_out) *tmax_out = tmax;
+}
+
+/*
+ * Phase bin of one sample at one trial period (Sec. 2.3, first two steps of
+ * the five-step fold; Fig. 4 panels a-b): the timestamp is reduced modulo the
+ * trial period and the residual is mapped to one of nbins equal-width bins.
+ *
+ *   x = t / P              one correctly rounded binary64 division
+ *   f = x - floor(x)       phase in cycles, in [0, 1]
+ *   u = f * nbins          exact for a power-of-two nbins
+ *   b = floor(u), clamped to nbins - 1 (f can round up to 1 for x < 0)
+ *
+ * Phase zero is t = 0 of the caller's time scale.
+ */
+int32_t oracle_bin(double t, double period, int32_t nbins) {
+    double x = t / period;
+    double f = x - floor(x);
+    double u = f * (double)nbins;
+    double fb = floor(u);
+    int32_t b;
+    if (!(fb >= 0.0)) b = 0;              /* NaN input: defined as bin 0 */
+    else if (fb >= (double)nbins) b = nbins - 1;
+    else b = (int32_t)fb;
+    return b;
+}
+
+/*
+ * Fold at every trial period (Sec. 2.3 steps one to three and five): for
+ * each period k and each sample i, add one to counts[k][b] and the flux to
+ * sums[k][b]; dsums[k][b] accumulates flux - ref instead (the deviation
+ * sums the box statistic uses). Samples are taken in index order. Output
+ * layout is row-major [k][nbins].
+ *
+ * A period that is not a finite positive number gives an all-zero row.
+ * nthreads > 1 splits the periods over OpenMP threads; every period is
+ * computed by exactly the same sequential loop, so the result does not
+ * depend on nthreads.
+ */
+void oracle_fold(const double *t, const float *flux, int64_t n,
+                 const double *periods, int64_t k, int32_t nbins, double ref,
+                 double *sums, double *dsums, int32_t *counts, int nthreads) {
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+#endif
+    for (int64_t kk = 0; kk < k; ++kk) {
+        double *srow = sums ? sums + kk * nbins : NULL;
+        double *drow = dsums ? dsums + kk * nbins : NULL;
+        int32_t *crow = counts + kk * nbins;
+        for (int32_t b = 0; b < nbins; ++b) {
+            crow[b] = 0;
+            if (srow) srow[b] = 0.0;
+            if (drow) drow[b] = 0.0;
+        }
+        double P = periods[kk];
+        if (!(P > 0.0) || !isfinite(P)) continue;   /* invalid period: empty row */
+        for (int64_t i = 0; i < n; ++i) {
+            int32_t b = oracle_bin(t[i], P, nbins);
+            crow[b] += 1;
+            if (srow) srow[b] += (double)flux[i];
+            if (drow) drow[b] += (double)flux[i] - ref;
+        }
+    }
+    (void)nthreads;
+}
+
+/*
+ * Bin means (Sec. 2.3 step five, Fig. 4 panels d-e): sum / count, NaN for
+ * an empty bin.
+ */
+void oracle_means(const double *sums, const int32_t *counts, int64_t m,
+                  double *means) {
+    for (int64_t j = 0; j < m; ++j)
+        means[j] = counts[j] > 0 ? sums[j] / (double)counts[j] : NAN;
+}
+
+/*
+ * Default box-width set: the distinct integers nearest to sqrt(2)^j that lie
+ * in [1, nbins / 2] (nbins = 1 gives {1}). Ascending. Returns the count.
+ */
+int32_t oracle_default_widths(int32_t nbins, int32_t *out, int32_t cap) {
+    int32_t m = 0, last = 0;
+    int32_t wmax = nbins / 2 > 0 ? nbins / 2 : 1;
+    for (int j = 0; j < 64; ++j) {
+        double v = pow(sqrt(2.0), (double)j);
+        int32_t w = (int32_t)floor(v + 0.5);
+        if (w > wmax) break;
+        if (w != last) {
+            if (m < cap) out[m] = w;
+            ++m;
+            last = w;
+        }
+    }
+    return m;
+}
+
+/*
+ * Box-transit SNR of each folded curve. The paper gives the SNR of a transit
+ * only in closed form (Eq. 2, Sec. 2.6: depth over per-point noise times the
+ * square root of the in-transit sample count) and the box model of BLS
+ * (Sec. 3.1); this is the statistic built from the two, for a box of w
+ * consecutive bins starting at bin s, taken circularly because phase wraps:
+ *
+ *   n_in  = sum_{j<w} c[(s+j) mod B],  D_in = sum_{j<w} D[(s+j) mod B]
+ *   n_out = n - n_in,                  D_out = S - D_in
+ *   depth = D_out / n_out - D_in / n_in          (mean out minus mean in)
+ *   snr   = depth * sqrt(n_in * n_out / n) / sigma
+ *
+ * where c are counts, D deviation sums, n = sum c and S = sum D. Boxes with
+ * n_in = 0 or n_out = 0 are skipped. The result is the largest snr over
+ * widths in ascending order and starts in ascending order, a later box
+ * replacing the best only if strictly larger, starting from 0: only dips
+ * score. With no positive box, or sigma not > 0, snr = 0, depth = 0 and
+ * start = width = -1.
+ */
+void oracle_score(const int32_t *counts, const double *dsums, int64_t k,
+                  int32_t nbins, double sigma, const int32_t *widths,
+                  int32_t nw, double *snr, int32_t *start, int32_t *width,
+                  double *depth) {
+    for (int64_t kk = 0; kk < k; ++kk) {
+        const int32_t *c = counts + kk * nbins;
+        const double *D = dsums + kk * nbins;
+        double best = 0.0, best_depth = 0.0;
+        int32_t bs = -1, bw = -1;
+        int64_t n = 0;
+        double S = 0.0;
+        for (int32_t b = 0; b < nbins; ++b) {
+            n += c[b];
+            S += D[b];
+        }
+        if (sigma > 0.0 && isfinite(sigma)) {
+            for (int32_t wi = 0; wi < nw; ++wi) {
+                int32_t w = widths[wi];
+                for (int32_t s = 0; s < nbins; ++s) {
+                    int64_t n_in = 0;
+                    double D_in = 0.0;
+                    for (int32_t j = 0; j < w; ++j) {
+                        int32_t b = (s + j) % nbins;
+                        n_in += c[b];
+                        D_in += D[b];
+                    }
+                    int64_t n_out = n - n_in;
+                    if (n_in == 0 || n_out == 0) continue;
+                    double dep = (S - D_in) / (double)n_out - D_in / (double)n_in;
+                    double v = dep * sqrt((double)n_in * (double)n_out / (double)n) / sigma;
+                    if (v > best) {
+                        best = v;
+                        best_depth = dep;
+                        bs = s;
+                        bw = w;
+                    }
+                }
+            }
+        }
+        snr[kk] = best;
+        depth[kk] = best_depth;
+        start[kk] = bs;
+        width[kk] = bw;
+    }
+}
+
+/*
+ * Box statistic of one given box (same formula as above); used to judge a
+ * near-tie: the value of the oracle's statistic at another implementation's
+ * chosen (start, width). Returns 0 when the box is empty or full.
+ */
+double oracle_box_snr(const int32_t *c, const double *D, int32_t nbins,
+                      double sigma, int32_t s, int32_t w) {
+    int64_t n = 0, n_in = 0;
+    double S = 0.0, D_in = 0.0;
+    for (int32_t b = 0; b < nbins; ++b) {
+        n += c[b];
+        S += D[b];
+    }
+    for (int32_t j = 0; j < w; ++j) {
+        int32_t b = (s + j) % nbins;
+        n_in += c[b];
+        D_in += D[b];
+    }
+    int64_t n_out = n - n_in;
+    if (n_in == 0 || n_out == 0) return 0.0;
+    double dep = (S - D_in) / (double)n_out - D_in / (double)n_in;
+    return dep * sqrt((double)n_in * (double)n_out / (double)n) / sigma;
+}
+
+/*
+ * Trial-grid size of Eq. 1 (Sec. 2.1): N_sample = N_o * T / L.
+ */
+double oracle_grid_size(double n_o, double span, double width) {
+    return n_o * span / width;
+}
