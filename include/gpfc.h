@@ -1,0 +1,157 @@
+/*
+ * gpfc.h - C ABI of the MI355X (gfx950) phase-fold + box-SNR library.
+ *
+ * Method: GPU phase folding of Wang, Ge, Willis, Wang, Zhao, "The GPU Phase
+ * Folding and Deep Learning Method for Detecting Exoplanet Transits"
+ * (MNRAS 2024, arXiv:2312.02063). A light curve is folded at every trial
+ * period of a grid (Sec. 2.1, Sec. 2.3); each folded curve is binned in phase
+ * and scored.
+ *
+ * Conventions for every call below
+ *  - Array arguments are DEVICE pointers (e.g. torch tensors' data_ptr()) on
+ *    the plan's device, unless the comment says "host". The caller allocates
+ *    and owns them; the library never frees caller memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream). Work
+ *    is enqueued asynchronously on it; outputs are valid once the stream has
+ *    reached that point.
+ *  - Return value: GPFC_OK (0) or a negative error code. Argument checks run
+ *    on the host before any GPU work is enqueued; on an argument error nothing
+ *    is enqueued and no output is touched. No C++ exception crosses the ABI.
+ *  - A plan (and its device workspace) must not be used by two host threads,
+ *    or by two streams that run concurrently, at the same time.
+ *  - Layout of per-period outputs: row-major [k][nbins].
+ *  - Phase zero is t = 0 of the caller's time scale; t need not be sorted.
+ */
+#ifndef GPFC_H
+#define GPFC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GPFC_OK 0
+#define GPFC_EINVAL (-1)   /* null pointer, negative size, nbins < 1, bad widths */
+#define GPFC_ENOTSUP (-2)  /* nbins not a power of two in [1, 256] */
+#define GPFC_ERANGE (-3)   /* n > GPFC_MAX_SAMPLES or k too large for the grid */
+#define GPFC_ENOMEM (-4)   /* device workspace allocation failed */
+#define GPFC_EDEVICE (-5)  /* a HIP call failed; gpfc_last_error() has the text */
+
+#define GPFC_MAX_SAMPLES 262143   /* 2^18 - 1: limit of the packed 64-bit bin counter */
+#define GPFC_MAX_NBINS 256
+#define GPFC_MAX_WIDTHS 16
+
+typedef struct gpfc_plan gpfc_plan;
+
+/* Curve statistics (host struct), filled by gpfc_curve_stats. */
+typedef struct gpfc_curve {
+    double mean;     /* mean flux, FP64 */
+    double sigma;    /* sample std of flux (ddof 1): the per-point noise of Eq. 2 (Sec. 2.6); 0 if n < 2 */
+    double ref;      /* reference flux on the fixed-point grid (multiple of qscale) */
+    double qscale;   /* 2^e: weight of one fixed-point unit of a bin sum */
+    double tmax;     /* max |t| */
+    double maxdev;   /* max |flux - ref| */
+    int64_t n;       /* samples */
+    int32_t exact;   /* 1: every flux - ref is an integer multiple of qscale, bin sums are exact */
+    int32_t finite;  /* 1: every t and flux is finite; 0 makes all results unspecified */
+} gpfc_curve;
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int32_t gpfc_version(void);
+
+/* Static text for an error code. */
+const char *gpfc_strerror(int32_t code);
+
+/* Text of the last GPFC_EDEVICE on the calling host thread ("" if none). */
+const char *gpfc_last_error(void);
+
+/*
+ * Create a plan on HIP device `device`. A plan owns a device workspace that
+ * grows on demand (hipMalloc, so the first call at a new size is not
+ * capturable) and a box-width set, initially the default set: the distinct
+ * integers nearest to sqrt(2)^j in [1, nbins/2]. *out receives the plan.
+ */
+int32_t gpfc_plan_create(gpfc_plan **out, int32_t device);
+
+/* Free a plan and its workspace (synchronises the device first). NULL is a no-op. */
+int32_t gpfc_plan_destroy(gpfc_plan *plan);
+
+/*
+ * Set the box widths (host array, in coarse bins, 1 <= w < nbins at use,
+ * strictly ascending, at most GPFC_MAX_WIDTHS). nw = 0 restores the default
+ * set. Widths not below nbins are skipped when a fold with that nbins is
+ * scored.
+ */
+int32_t gpfc_plan_set_widths(gpfc_plan *plan, const int32_t *widths_host, int32_t nw);
+
+/*
+ * Curve statistics (mean, sigma for Eq. 2's per-point noise, fixed-point
+ * grid): t f64[n], flux f32[n]. Synchronous: waits for `stream`, then fills
+ * the host struct *out.
+ */
+int32_t gpfc_curve_stats(gpfc_plan *plan, const double *t, const float *flux, int64_t n,
+                         gpfc_curve *out_host, void *stream);
+
+/*
+ * Phase fold (Sec. 2.3, five-step fold with equal-width bins; Fig. 4 panels
+ * a, b, d, e): for each trial period P_j and sample i, the bin is
+ *   b = floor(nbins * (x - floor(x))),  x = RN(t_i / P_j)  (binary64),
+ * clamped to nbins - 1 - bit-identical to that IEEE sequence. Outputs:
+ *   sums   f64[k][nbins]  sum of flux in the bin (0 if empty)
+ *   counts i32[k][nbins]  samples in the bin
+ *   means  f64[k][nbins]  sums / counts, NaN if empty (may be NULL)
+ * Inputs: t f64[n], flux f32[n], periods f64[k]; nbins a power of two in
+ * [1, 256]; n <= GPFC_MAX_SAMPLES. A period that is not finite and > 0 gives
+ * an all-zero row (means NaN). n = 0 or k = 0 is valid.
+ */
+int32_t gpfc_fold(gpfc_plan *plan, const double *t, const float *flux, int64_t n,
+                  const double *periods, int64_t k, int32_t nbins,
+                  double *sums, int32_t *counts, double *means, void *stream);
+
+/*
+ * Box-transit SNR of materialised folds (the statistic of Eq. 2, Sec. 2.6,
+ * over the BLS box of Sec. 3.1). For every row of sums/counts ([k][nbins] as
+ * gpfc_fold writes them), over each width w of the plan's set and each
+ * circular start s, with n_in/D_in the box's count and flux-deviation sum:
+ *   depth = (S - D_in)/(n - n_in) - D_in/n_in,
+ *   snr   = depth * sqrt(n_in (n - n_in) / n) / sigma,
+ * keeping the largest positive snr (ties: smaller w, then smaller s).
+ * Outputs f32 snr[k], i32 start[k], i32 width[k] (in coarse bins), f32
+ * depth[k]; a row with no positive box gives snr = depth = 0 and
+ * start = width = -1. sigma is the curve's per-point noise (host value,
+ * e.g. gpfc_curve.sigma); sigma not > 0 gives that empty result for every row.
+ */
+int32_t gpfc_score(gpfc_plan *plan, const double *sums, const int32_t *counts, int64_t k,
+                   int32_t nbins, double sigma, float *snr, int32_t *start, int32_t *width,
+                   float *depth, void *stream);
+
+/*
+ * Fused fold + score: the fold of gpfc_fold followed by the box-SNR of
+ * gpfc_score with sigma = the curve's sample std, without materialising the
+ * folded curves (16 bytes written per period). Same inputs as gpfc_fold; same
+ * outputs as gpfc_score.
+ */
+int32_t gpfc_fold_score(gpfc_plan *plan, const double *t, const float *flux, int64_t n,
+                        const double *periods, int64_t k, int32_t nbins, float *snr,
+                        int32_t *start, int32_t *width, float *depth, void *stream);
+
+/*
+ * Plain GPU fold, the baseline the paper's own design resembles (Sec. 2.3,
+ * Sec. 2.4: atomic accumulation, one thread per sample and period): IEEE
+ * division per update and device-memory atomics. Same contract and outputs
+ * as gpfc_fold without means (sums accumulate in FP64 atomics, so they
+ * differ from gpfc_fold's only in rounding order).
+ */
+int32_t gpfc_fold_naive(gpfc_plan *plan, const double *t, const float *flux, int64_t n,
+                        const double *periods, int64_t k, int32_t nbins, double *sums,
+                        int32_t *counts, void *stream);
+
+/* hipStreamSynchronize(stream); reports an asynchronous device error. */
+int32_t gpfc_sync(void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPFC_H */

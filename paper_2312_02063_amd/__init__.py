@@ -1,0 +1,9 @@
+"""MI355X-native GPU phase folding and box-SNR scoring (GPFC, arXiv:2312.02063).
+
+The compute path is the HIP library ``libgpfc.so`` (gfx950) behind the C ABI
+of ``include/gpfc.h``; ``Plan`` is its thin Python binding. ``synth`` makes
+seeded synthetic light curves and trial grids.
+"""
+from ._lib import GpfcError, Plan, load  # noqa: F401
+
+__all__ = ["Plan", "GpfcError", "load"]

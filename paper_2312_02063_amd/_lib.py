@@ -1,0 +1,213 @@
+"""ctypes binding of ``libgpfc.so`` (the C ABI in ``include/gpfc.h``).
+
+Argument marshalling only: every step of the fold and the score runs in the
+library's HIP kernels. Tensors are torch tensors on the plan's GPU; outputs
+are allocated here with ``torch.empty`` and filled by the library on the
+current torch stream. If the library is missing this module raises: there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgpfc.so")
+
+OK, EINVAL, ENOTSUP, ERANGE, ENOMEM, EDEVICE = 0, -1, -2, -3, -4, -5
+MAX_SAMPLES = 262143
+MAX_NBINS = 256
+MAX_WIDTHS = 16
+
+_lib = None
+
+
+class GpfcError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        lib = load()
+        msg = lib.gpfc_strerror(code).decode()
+        if code == EDEVICE:
+            msg += ": " + lib.gpfc_last_error().decode()
+        super().__init__(f"{what}: {msg} ({code})")
+        self.code = code
+
+
+class Curve(ctypes.Structure):
+    """Host mirror of ``gpfc_curve``."""
+    _fields_ = [("mean", ctypes.c_double), ("sigma", ctypes.c_double), ("ref", ctypes.c_double),
+                ("qscale", ctypes.c_double), ("tmax", ctypes.c_double), ("maxdev", ctypes.c_double),
+                ("n", ctypes.c_int64), ("exact", ctypes.c_int32), ("finite", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def load():
+    """Load ``libgpfc.so``; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2312_02063_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "gpfc_version": ([], i32),
+        "gpfc_strerror": ([i32], ctypes.c_char_p),
+        "gpfc_last_error": ([], ctypes.c_char_p),
+        "gpfc_plan_create": ([ctypes.POINTER(vp), i32], i32),
+        "gpfc_plan_destroy": ([vp], i32),
+        "gpfc_plan_set_widths": ([vp, ctypes.POINTER(ctypes.c_int32), i32], i32),
+        "gpfc_curve_stats": ([vp, vp, vp, i64, ctypes.POINTER(Curve), vp], i32),
+        "gpfc_fold": ([vp, vp, vp, i64, vp, i64, i32, vp, vp, vp, vp], i32),
+        "gpfc_score": ([vp, vp, vp, i64, i32, f64, vp, vp, vp, vp, vp], i32),
+        "gpfc_fold_score": ([vp, vp, vp, i64, vp, i64, i32, vp, vp, vp, vp, vp], i32),
+        "gpfc_fold_naive": ([vp, vp, vp, i64, vp, i64, i32, vp, vp, vp], i32),
+        "gpfc_sync": ([vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    """Names the C ABI declares (see include/gpfc.h)."""
+    return ["gpfc_version", "gpfc_strerror", "gpfc_last_error", "gpfc_plan_create",
+            "gpfc_plan_destroy", "gpfc_plan_set_widths", "gpfc_curve_stats", "gpfc_fold",
+            "gpfc_score", "gpfc_fold_score", "gpfc_fold_naive", "gpfc_sync"]
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise GpfcError(rc, what)
+
+
+def _ptr(x):
+    return ctypes.c_void_p(x.data_ptr()) if x is not None else None
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(x, dtype, name, dev):
+    import torch
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if x.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {x.dtype}")
+    if x.device != dev:
+        raise ValueError(f"{name} is on {x.device}, expected {dev}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Plan:
+    """A library plan on one GPU (owns the device workspace and the width set)."""
+
+    def __init__(self, device: int = 0, widths=None):
+        import torch
+        self.lib = load()
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        _check(self.lib.gpfc_plan_create(ctypes.byref(h), device), "gpfc_plan_create")
+        self.h = h
+        if widths is not None:
+            self.set_widths(widths)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.gpfc_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_widths(self, widths):
+        w = list(widths or [])
+        arr = (ctypes.c_int32 * max(1, len(w)))(*w)
+        _check(self.lib.gpfc_plan_set_widths(self.h, arr, len(w)), "gpfc_plan_set_widths")
+
+    def _inputs(self, t, flux, periods=None):
+        import torch
+        _need(t, torch.float64, "t", self.device)
+        _need(flux, torch.float32, "flux", self.device)
+        if t.numel() != flux.numel():
+            raise ValueError("t and flux differ in length")
+        if periods is not None:
+            _need(periods, torch.float64, "periods", self.device)
+
+    def curve_stats(self, t, flux) -> dict:
+        self._inputs(t, flux)
+        c = Curve()
+        _check(self.lib.gpfc_curve_stats(self.h, _ptr(t), _ptr(flux), t.numel(), ctypes.byref(c),
+                                         _stream()), "gpfc_curve_stats")
+        return c.as_dict()
+
+    def fold(self, t, flux, periods, nbins: int, means: bool = True):
+        """(sums f64[k, nbins], counts i32[k, nbins], means f64[k, nbins] or None)."""
+        import torch
+        self._inputs(t, flux, periods)
+        k = periods.numel()
+        sums = torch.empty((k, nbins), dtype=torch.float64, device=self.device)
+        counts = torch.empty((k, nbins), dtype=torch.int32, device=self.device)
+        mo = torch.empty((k, nbins), dtype=torch.float64, device=self.device) if means else None
+        _check(self.lib.gpfc_fold(self.h, _ptr(t), _ptr(flux), t.numel(), _ptr(periods), k, nbins,
+                                  _ptr(sums), _ptr(counts), _ptr(mo), _stream()), "gpfc_fold")
+        return sums, counts, mo
+
+    def _score_outputs(self, k):
+        import torch
+        return (torch.empty(k, dtype=torch.float32, device=self.device),
+                torch.empty(k, dtype=torch.int32, device=self.device),
+                torch.empty(k, dtype=torch.int32, device=self.device),
+                torch.empty(k, dtype=torch.float32, device=self.device))
+
+    def score(self, sums, counts, sigma: float):
+        """Box-SNR of materialised folds: (snr f32[k], start i32[k], width i32[k], depth f32[k])."""
+        import torch
+        _need(sums, torch.float64, "sums", self.device)
+        _need(counts, torch.int32, "counts", self.device)
+        if sums.dim() != 2 or sums.shape != counts.shape:
+            raise ValueError("sums and counts must both be [k, nbins]")
+        k, nbins = sums.shape
+        snr, start, width, depth = self._score_outputs(k)
+        _check(self.lib.gpfc_score(self.h, _ptr(sums), _ptr(counts), k, nbins, float(sigma),
+                                   _ptr(snr), _ptr(start), _ptr(width), _ptr(depth), _stream()),
+               "gpfc_score")
+        return snr, start, width, depth
+
+    def fold_score(self, t, flux, periods, nbins: int, out=None):
+        """Fused fold + box-SNR: (snr, start, width, depth), each [k]."""
+        self._inputs(t, flux, periods)
+        k = periods.numel()
+        snr, start, width, depth = out if out is not None else self._score_outputs(k)
+        _check(self.lib.gpfc_fold_score(self.h, _ptr(t), _ptr(flux), t.numel(), _ptr(periods), k,
+                                        nbins, _ptr(snr), _ptr(start), _ptr(width), _ptr(depth),
+                                        _stream()), "gpfc_fold_score")
+        return snr, start, width, depth
+
+    def fold_naive(self, t, flux, periods, nbins: int, out=None):
+        """Plain global-atomic GPU fold (baseline): (sums, counts)."""
+        import torch
+        self._inputs(t, flux, periods)
+        k = periods.numel()
+        if out is None:
+            sums = torch.empty((k, nbins), dtype=torch.float64, device=self.device)
+            counts = torch.empty((k, nbins), dtype=torch.int32, device=self.device)
+        else:
+            sums, counts = out
+        _check(self.lib.gpfc_fold_naive(self.h, _ptr(t), _ptr(flux), t.numel(), _ptr(periods), k,
+                                        nbins, _ptr(sums), _ptr(counts), _stream()),
+               "gpfc_fold_naive")
+        return sums, counts
+
+    def sync(self):
+        _check(self.lib.gpfc_sync(_stream()), "gpfc_sync")

@@ -1,0 +1,246 @@
+// Host side of the C ABI declared in include/gpfc.h: argument checks (before
+// any HIP call), plans and their device workspace, error reporting.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <new>
+
+#include "../../include/gpfc.h"
+#include "gpfc_internal.h"
+
+using gpfc::CurveInfo;
+using gpfc::Widths;
+
+struct gpfc_plan {
+    int32_t device = 0;
+    gpfc::Rec* rec = nullptr;     // prepared curve: times and packed contributions
+    int64_t cap = 0;              // records rec can hold
+    CurveInfo* info = nullptr;    // device-resident curve description
+    int32_t widths[GPFC_MAX_WIDTHS];
+    int32_t nw = 0;               // 0: default set
+};
+
+namespace {
+
+thread_local char g_last_error[256] = "";
+
+int32_t device_error(hipError_t e, const char* what) {
+    snprintf(g_last_error, sizeof(g_last_error), "%s: %s", what, hipGetErrorString(e));
+    return GPFC_EDEVICE;
+}
+
+bool pow2_in_range(int32_t nbins) {
+    return nbins >= 1 && nbins <= GPFC_MAX_NBINS && (nbins & (nbins - 1)) == 0;
+}
+
+// Distinct integers nearest sqrt(2)^j in [1, max(1, nbins/2)], ascending.
+Widths default_widths(int32_t nbins) {
+    Widths w{};
+    int32_t last = 0;
+    const int32_t wmax = nbins / 2 > 0 ? nbins / 2 : 1;
+    double v = 1.0;
+    for (int j = 0; j < 64 && w.n < gpfc::kMaxWidths; ++j) {
+        const int32_t r = (int32_t)floor(v + 0.5);
+        if (r > wmax) break;
+        if (r != last) w.w[w.n++] = r;
+        last = r;
+        v *= 1.4142135623730951;
+    }
+    return w;
+}
+
+Widths plan_widths(const gpfc_plan* p, int32_t nbins) {
+    if (p->nw == 0) return default_widths(nbins);
+    Widths w{};
+    for (int i = 0; i < p->nw; ++i) w.w[w.n++] = p->widths[i];
+    return w;
+}
+
+int32_t check_fold_args(const gpfc_plan* p, const void* t, const void* flux, int64_t n,
+                        const void* periods, int64_t k, int32_t nbins) {
+    if (!p) return GPFC_EINVAL;
+    if (n < 0 || k < 0) return GPFC_EINVAL;
+    if (n > 0 && (!t || !flux)) return GPFC_EINVAL;
+    if (k > 0 && !periods) return GPFC_EINVAL;
+    if (nbins < 1) return GPFC_EINVAL;
+    if (!pow2_in_range(nbins)) return GPFC_ENOTSUP;
+    if (n > GPFC_MAX_SAMPLES) return GPFC_ERANGE;
+    if ((k + 63) / 64 > 0x7fffffffLL) return GPFC_ERANGE;
+    return GPFC_OK;
+}
+
+// Make the workspace hold n samples, then run the curve statistics and the
+// packing kernels on `s`.
+int32_t prepare_curve(gpfc_plan* p, const double* t, const float* flux, int64_t n, hipStream_t s) {
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return device_error(e, "hipSetDevice");
+    if (!p->info) {
+        e = hipMalloc(&p->info, sizeof(CurveInfo));
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? GPFC_ENOMEM : device_error(e, "hipMalloc");
+    }
+    const int64_t need = gpfc::prepared_len(n);
+    if (need > p->cap) {
+        const int64_t want = need < 8192 ? 8192 : need;
+        gpfc::Rec* buf = nullptr;
+        e = hipMalloc(&buf, (size_t)want * sizeof(gpfc::Rec));
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? GPFC_ENOMEM : device_error(e, "hipMalloc");
+        if (p->rec) {
+            (void)hipDeviceSynchronize();
+            (void)hipFree(p->rec);
+        }
+        p->rec = buf;
+        p->cap = want;
+    }
+    e = gpfc::launch_curve_stats(t, flux, n, p->info, s);
+    if (e != hipSuccess) return device_error(e, "k_curve_stats launch");
+    e = gpfc::launch_pack(t, flux, n, p->info, p->rec, s);
+    if (e != hipSuccess) return device_error(e, "k_pack launch");
+    return GPFC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t gpfc_version(void) { return 100; }
+
+const char* gpfc_strerror(int32_t code) {
+    switch (code) {
+        case GPFC_OK: return "ok";
+        case GPFC_EINVAL: return "invalid argument";
+        case GPFC_ENOTSUP: return "nbins must be a power of two in [1, 256]";
+        case GPFC_ERANGE: return "size out of range (n > 262143 samples or too many periods)";
+        case GPFC_ENOMEM: return "device memory allocation failed";
+        case GPFC_EDEVICE: return "HIP device error";
+        default: return "unknown error";
+    }
+}
+
+const char* gpfc_last_error(void) { return g_last_error; }
+
+int32_t gpfc_plan_create(gpfc_plan** out, int32_t device) {
+    if (!out) return GPFC_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) return device_error(e, "hipGetDeviceCount");
+    if (device < 0 || device >= count) return GPFC_EINVAL;
+    gpfc_plan* p = new (std::nothrow) gpfc_plan();
+    if (!p) return GPFC_ENOMEM;
+    p->device = device;
+    *out = p;
+    return GPFC_OK;
+}
+
+int32_t gpfc_plan_destroy(gpfc_plan* p) {
+    if (!p) return GPFC_OK;
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    if (p->rec) (void)hipFree(p->rec);
+    if (p->info) (void)hipFree(p->info);
+    delete p;
+    return GPFC_OK;
+}
+
+int32_t gpfc_plan_set_widths(gpfc_plan* p, const int32_t* widths, int32_t nw) {
+    if (!p || nw < 0 || nw > GPFC_MAX_WIDTHS || (nw > 0 && !widths)) return GPFC_EINVAL;
+    for (int i = 0; i < nw; ++i) {
+        if (widths[i] < 1 || widths[i] >= GPFC_MAX_NBINS) return GPFC_EINVAL;
+        if (i > 0 && widths[i] <= widths[i - 1]) return GPFC_EINVAL;
+    }
+    for (int i = 0; i < nw; ++i) p->widths[i] = widths[i];
+    p->nw = nw;
+    return GPFC_OK;
+}
+
+int32_t gpfc_curve_stats(gpfc_plan* p, const double* t, const float* flux, int64_t n,
+                         gpfc_curve* out, void* stream) {
+    int32_t rc = check_fold_args(p, t, flux, n, (const void*)1, 0, 1);
+    if (rc != GPFC_OK) return rc;
+    if (!out) return GPFC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    rc = prepare_curve(p, t, flux, n, s);
+    if (rc != GPFC_OK) return rc;
+    CurveInfo ci;
+    hipError_t e = hipMemcpyAsync(&ci, p->info, sizeof(ci), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_error(e, "curve stats copy");
+    out->mean = ci.mean;
+    out->sigma = ci.sigma;
+    out->ref = ci.ref;
+    out->qscale = ci.qscale;
+    out->tmax = ci.tmax;
+    out->maxdev = ci.maxdev;
+    out->n = ci.n;
+    out->exact = ci.exact;
+    out->finite = ci.finite;
+    return GPFC_OK;
+}
+
+int32_t gpfc_fold(gpfc_plan* p, const double* t, const float* flux, int64_t n,
+                  const double* periods, int64_t k, int32_t nbins, double* sums, int32_t* counts,
+                  double* means, void* stream) {
+    int32_t rc = check_fold_args(p, t, flux, n, periods, k, nbins);
+    if (rc != GPFC_OK) return rc;
+    if (k > 0 && (!sums || !counts)) return GPFC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    rc = prepare_curve(p, t, flux, n, s);
+    if (rc != GPFC_OK) return rc;
+    hipError_t e = gpfc::launch_fold(p->rec, n, periods, k, nbins, p->info, sums, counts, means, s);
+    if (e != hipSuccess) return device_error(e, "k_fold launch");
+    return GPFC_OK;
+}
+
+int32_t gpfc_fold_score(gpfc_plan* p, const double* t, const float* flux, int64_t n,
+                        const double* periods, int64_t k, int32_t nbins, float* snr,
+                        int32_t* start, int32_t* width, float* depth, void* stream) {
+    int32_t rc = check_fold_args(p, t, flux, n, periods, k, nbins);
+    if (rc != GPFC_OK) return rc;
+    if (k > 0 && (!snr || !start || !width || !depth)) return GPFC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    rc = prepare_curve(p, t, flux, n, s);
+    if (rc != GPFC_OK) return rc;
+    hipError_t e = gpfc::launch_fold_score(p->rec, n, periods, k, nbins, p->info,
+                                           plan_widths(p, nbins), snr, start, width, depth, s);
+    if (e != hipSuccess) return device_error(e, "k_fold_score launch");
+    return GPFC_OK;
+}
+
+int32_t gpfc_score(gpfc_plan* p, const double* sums, const int32_t* counts, int64_t k,
+                   int32_t nbins, double sigma, float* snr, int32_t* start, int32_t* width,
+                   float* depth, void* stream) {
+    if (!p || k < 0 || nbins < 1) return GPFC_EINVAL;
+    if (!pow2_in_range(nbins)) return GPFC_ENOTSUP;
+    if (k > 0 && (!sums || !counts || !snr || !start || !width || !depth)) return GPFC_EINVAL;
+    if ((k + 63) / 64 > 0x7fffffffLL) return GPFC_ERANGE;
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return device_error(e, "hipSetDevice");
+    e = gpfc::launch_score(sums, counts, k, nbins, sigma, plan_widths(p, nbins), snr, start, width,
+                           depth, (hipStream_t)stream);
+    if (e != hipSuccess) return device_error(e, "k_score launch");
+    return GPFC_OK;
+}
+
+int32_t gpfc_fold_naive(gpfc_plan* p, const double* t, const float* flux, int64_t n,
+                        const double* periods, int64_t k, int32_t nbins, double* sums,
+                        int32_t* counts, void* stream) {
+    int32_t rc = check_fold_args(p, t, flux, n, periods, k, nbins);
+    if (rc != GPFC_OK) return rc;
+    if (k > 0 && (!sums || !counts)) return GPFC_EINVAL;
+    if (k > 0x7fffffffLL) return GPFC_ERANGE;
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return device_error(e, "hipSetDevice");
+    e = gpfc::launch_fold_naive(t, flux, n, periods, k, nbins, sums, counts, (hipStream_t)stream);
+    if (e != hipSuccess) return device_error(e, "k_fold_naive launch");
+    return GPFC_OK;
+}
+
+int32_t gpfc_sync(void* stream) {
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return device_error(e, "hipStreamSynchronize");
+    return GPFC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// Internal declarations shared by the host entry points and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gpfc {
+
+// One packed histogram bin: the sample count in bits [46, 64) and the sum of
+// (q_i + 2^27) in bits [0, 46), q_i being the sample's flux deviation in
+// fixed-point units of 2^e. Both fields add as one 64-bit integer without
+// carrying into each other for n < 2^18 samples, so a single integer LDS
+// atomic accumulates count and flux sum exactly and in any order.
+constexpr int kCountShift = 46;
+constexpr uint64_t kSumMask = (uint64_t(1) << kCountShift) - 1;
+constexpr int64_t kBias = int64_t(1) << 27;
+constexpr int kFineBins = 256;     // bins of the LDS histogram
+constexpr int kPeriodsPerBlock = 64;
+constexpr int kMaxWidths = 16;
+
+// Device-resident curve description written by k_curve_stats.
+struct CurveInfo {
+    double mean;
+    double sigma;
+    double ref;       // multiple of 2^e
+    double qscale;    // 2^e
+    double tmax;      // max |t|
+    double maxdev;    // max |flux - ref|
+    int64_t n;
+    int32_t e;
+    int32_t exact;
+    int32_t finite;
+    int32_t pad;
+};
+
+// Prepared sample: time and packed contribution (16 bytes).
+struct Rec {
+    double t;
+    uint64_t c;
+};
+
+struct Widths {
+    int32_t w[kMaxWidths];
+    int32_t n;
+};
+
+// Launchers (defined in gpfc_kernels.hip). Each returns the HIP error of the launch.
+hipError_t launch_curve_stats(const double* t, const float* flux, int64_t n, CurveInfo* info,
+                              hipStream_t s);
+// Records the prepared curve of n samples occupies (padding included).
+int64_t prepared_len(int64_t n);
+hipError_t launch_pack(const double* t, const float* flux, int64_t n, const CurveInfo* info,
+                       Rec* rec, hipStream_t s);
+hipError_t launch_fold(const Rec* rec, int64_t n, const double* periods,
+                       int64_t k, int32_t nbins, const CurveInfo* info, double* sums,
+                       int32_t* counts, double* means, hipStream_t s);
+hipError_t launch_fold_score(const Rec* rec, int64_t n,
+                             const double* periods, int64_t k, int32_t nbins,
+                             const CurveInfo* info, const Widths& widths, float* snr,
+                             int32_t* start, int32_t* width, float* depth, hipStream_t s);
+hipError_t launch_score(const double* sums, const int32_t* counts, int64_t k, int32_t nbins,
+                        double sigma, const Widths& widths, float* snr, int32_t* start,
+                        int32_t* width, float* depth, hipStream_t s);
+hipError_t launch_fold_naive(const double* t, const float* flux, int64_t n,
+                             const double* periods, int64_t k, int32_t nbins, double* sums,
+                             int32_t* counts, hipStream_t s);
+
+}  // namespace gpfc

@@ -1,0 +1,664 @@
+// HIP kernels for gfx950 (MI355X): curve statistics, fixed-point packing,
+// the LDS phase fold, the fused fold + box-SNR, box-SNR of materialised
+// folds, and the plain global-atomic fold used as the baseline.
+//
+// Method: GPU phase folding (Sec. 2.3 of arXiv:2312.02063) with equal-width
+// phase bins, scored by the box statistic built from Eq. 2 (Sec. 2.6) and
+// the BLS box (Sec. 3.1).
+#include <math.h>
+
+#include <algorithm>
+
+#include "gpfc_internal.h"
+
+namespace gpfc {
+
+namespace {
+
+constexpr int kWaves = 16;                 // waves per fold block: 4 per SIMD
+constexpr int kThreads = kWaves * 64;
+constexpr int kRowsPerWave = kFineBins / kWaves;
+constexpr int kHalfBytes = kFineBins * 32 * 8;   // one half of the histogram: 32 lanes
+
+// ------------------------------------------------------------------ reductions
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_or_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ------------------------------------------------------------------ curve statistics
+
+// One block of 1024 threads. Pass 1: sum of flux, max |t|, finiteness and the
+// finest binary exponent of the fluxes; pass 2: sum of squared deviations and
+// the largest deviation from the grid-rounded reference. The fixed-point unit
+// 2^e is the ulp of the smallest-magnitude flux, so flux - ref is an exact
+// integer multiple of it whenever that integer stays below 2^27; otherwise a
+// coarser unit with 2^27 of headroom is used and the sums are rounded.
+__global__ __launch_bounds__(1024) void k_curve_stats(const double* __restrict__ t,
+                                                      const float* __restrict__ flux, int64_t n,
+                                                      CurveInfo* __restrict__ info) {
+    __shared__ double sd[16];
+    __shared__ double sd2[16];
+    __shared__ int si[16];
+    __shared__ int si2[16];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    double s = 0.0, tm = 0.0;
+    int emin = 1 << 20, bad = 0;
+    for (int64_t i = tid; i < n; i += 1024) {
+        const float fv = flux[i];
+        const double a = fabs(t[i]);
+        s += (double)fv;
+        if (!(a <= 1.7976931348623157e308)) bad = 1;
+        else tm = fmax(tm, a);
+        if (!isfinite(fv)) bad = 1;
+        else if (fv != 0.0f) emin = min(emin, ilogbf(fv));
+    }
+    s = wave_sum(s);
+    tm = wave_max(tm);
+    emin = wave_min_i(emin);
+    bad = wave_or_i(bad);
+    if (lane == 0) { sd[wv] = s; sd2[wv] = tm; si[wv] = emin; si2[wv] = bad; }
+    __syncthreads();
+    double S = 0.0, TM = 0.0;
+    int EMIN = 1 << 20, BAD = 0;
+    for (int j = 0; j < 16; ++j) { S += sd[j]; TM = fmax(TM, sd2[j]); EMIN = min(EMIN, si[j]); BAD |= si2[j]; }
+    __syncthreads();
+    const double mean = n > 0 ? S / (double)n : 0.0;
+    int e = EMIN == (1 << 20) ? -24 : max(EMIN - 23, -149);
+    double ref = ldexp(rint(ldexp(mean, -e)), e);
+    double ss = 0.0, md = 0.0;
+    for (int64_t i = tid; i < n; i += 1024) {
+        const double f = (double)flux[i];
+        const double d = f - mean;
+        ss += d * d;
+        md = fmax(md, fabs(f - ref));
+    }
+    ss = wave_sum(ss);
+    md = wave_max(md);
+    if (lane == 0) { sd[wv] = ss; sd2[wv] = md; }
+    __syncthreads();
+    if (tid == 0) {
+        double SS = 0.0, MD = 0.0;
+        for (int j = 0; j < 16; ++j) { SS += sd[j]; MD = fmax(MD, sd2[j]); }
+        int exact = (!BAD && MD < ldexp(1.0, e + 27)) ? 1 : 0;
+        if (!exact && MD > 0.0 && isfinite(MD)) {
+            e = ilogb(MD) - 25;
+            ref = ldexp(rint(ldexp(mean, -e)), e);
+        }
+        CurveInfo ci;
+        ci.mean = mean;
+        ci.sigma = n > 1 ? sqrt(SS / (double)(n - 1)) : 0.0;
+        ci.ref = ref;
+        ci.qscale = ldexp(1.0, e);
+        ci.tmax = BAD ? __builtin_inf() : TM;
+        ci.maxdev = MD;
+        ci.n = n;
+        ci.e = e;
+        ci.exact = exact;
+        ci.finite = BAD ? 0 : 1;
+        ci.pad = 0;
+        *info = ci;
+    }
+}
+
+// Prepared curve: record i = {t_i, (1 << 46) + (q_i + 2^27)} with
+// q_i = RN((flux_i - ref) / 2^e) clamped to [-2^27, 2^27]. Records from n up
+// to `total` are {0, 0}: they add nothing to any bin, so folds can run over
+// whole blocks of records without a tail.
+__global__ __launch_bounds__(256) void k_pack(const double* __restrict__ t,
+                                              const float* __restrict__ flux, int64_t n,
+                                              int64_t total, const CurveInfo* __restrict__ info,
+                                              Rec* __restrict__ rec) {
+    const double ref = info->ref;
+    const int e = info->e;
+    const double lim = (double)kBias;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        Rec r{0.0, 0};
+        if (i < n) {
+            double q = rint(ldexp((double)flux[i] - ref, -e));
+            q = fmin(fmax(q, -lim), lim);
+            r.t = t[i];
+            r.c = (uint64_t(1) << kCountShift) + (uint64_t)((int64_t)q + kBias);
+        }
+        rec[i] = r;
+    }
+}
+
+// ------------------------------------------------------------------ phase bin
+
+// The IEEE sequence of the fold's bin definition at 256 fine bins:
+// x = RN(t / P); f = x - floor(x); b = floor(256 f) clamped to 255; NaN -> 0.
+// Used for the rare updates the fast path cannot certify.
+__device__ __forceinline__ uint32_t fine_bin_ieee(double t, double P) {
+    const double x = t / P;
+    const double f = x - floor(x);
+    const double fb = floor(f * 256.0);
+    if (!(fb >= 0.0)) return 0u;
+    if (fb >= 256.0) return 255u;
+    return (uint32_t)fb;
+}
+
+// Per-lane constants of the certified fast path (see k_fold).
+struct LaneSetup {
+    double P;         // the lane's period (1.0 for an invalid lane)
+    double rB;        // 256 * RN(1/P), an exact scaling of RN(1/P)
+    double theta;     // -2^-17 - T 2^-16
+    uint32_t lim;     // 65536 - 2T, or 0 when the fast path is off for the lane
+    bool valid;
+};
+
+__device__ __forceinline__ LaneSetup lane_setup(const double* __restrict__ periods, int64_t kk,
+                                                int64_t k, double tmax) {
+    LaneSetup L;
+    double P = kk < k ? periods[kk] : 1.0;
+    L.valid = kk < k && P > 0.0 && isfinite(P);
+    if (!L.valid) P = 1.0;
+    L.P = P;
+    L.rB = (1.0 / P) * 256.0;
+    // |w - (256 RN(t/P) + theta)| <= 3u zmax + u with u = 2^-53; the bound
+    // below is 2^-50 zmax, < 2^-16 fine bins whenever zmax < 2^34.
+    const double zmax = tmax * L.rB;
+    const bool fast = zmax < 0x1p34;   // false for NaN / inf
+    const uint32_t T = 1u;
+    L.lim = fast ? 65536u - 2u * T : 0u;
+    L.theta = -0x1p-17 - (double)T * 0x1p-16;
+    return L;
+}
+
+// ------------------------------------------------------------------ the LDS fold
+
+// Accumulate one wave's slice of the curve into the block's histogram.
+//
+// Lane j of every wave owns trial period blockIdx*64 + j; the 16 waves split
+// the samples. A sample's time and packed contribution are the same for the
+// whole wave (scalar loads). The histogram bin of (sample, lane) lives at byte
+// half*65536 + bin*256 + (j & 31)*8, half = j >> 5: the 16 lanes of a 64-bit
+// LDS access hit 32 distinct banks, so every update is one conflict-free
+// ds_add_u64.
+//
+// Fast path, certified: w = fma(t, 256 RN(1/P), theta) is within 2^-16 of
+// 256 RN(t/P) + theta. Adding M = 1.5 * 2^36 rounds w to the grid 2^-16 and
+// leaves round(w * 2^16) in the low 32 bits of the sum: bits [16, 24) are
+// the bin (floor of 256 RN(t/P), mod 256) and bits [0, 16) the fraction
+// shifted down by T = 1 unit. When the fraction field is below 65536 - 2T the
+// bin equals that of the exact IEEE sequence; otherwise (about 3 updates in
+// 65536) the lane recomputes the bin with the IEEE sequence.
+__device__ __forceinline__ void fold_update(char* hist, double ti, uint64_t ci, const LaneSetup& L,
+                                            uint32_t laneoff) {
+    const double M = 0x1.8p36;
+    const double w = __builtin_fma(ti, L.rB, L.theta);
+    const double zz = w + M;
+    const uint32_t lo = (uint32_t)__double_as_longlong(zz);
+    // byte0 <- laneoff.byte0, byte1 <- lo.byte2 (the bin), byte2 <- laneoff.byte2
+    uint32_t addr = __builtin_amdgcn_perm(lo, laneoff, 0x0C020600u);
+    if ((lo & 0xFFFFu) >= L.lim) addr = (fine_bin_ieee(ti, L.P) << 8) | laneoff;
+    __hip_atomic_fetch_add(reinterpret_cast<uint64_t*>(hist + addr), ci, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// A wave's slice is a whole number of double blocks of kBlk records. Records
+// come in through scalar loads; block B is requested before block A is
+// processed and A's successor before B is processed, so each wait (which also
+// covers the LDS atomics already issued) sits kBlk updates after its request.
+// The request past the slice end stays inside the padded record array.
+constexpr int kBlk = 8;
+
+// Wait for every outstanding scalar load and LDS operation, and keep the
+// scheduler from moving work across the wait.
+__device__ __forceinline__ void wait_lgkm() {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0), vmcnt and expcnt untouched
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+__device__ __forceinline__ void fold_slice(char* hist, const Rec* __restrict__ rec, int64_t i0,
+                                           int64_t nblk2, const LaneSetup& L, uint32_t laneoff) {
+    const Rec* p = rec + i0;
+    Rec a[kBlk], b[kBlk];
+#pragma unroll
+    for (int j = 0; j < kBlk; ++j) a[j] = p[j];
+    for (int64_t it = 0; it < nblk2; ++it) {
+        wait_lgkm();
+#pragma unroll
+        for (int j = 0; j < kBlk; ++j) b[j] = p[kBlk + j];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < kBlk; ++j) fold_update(hist, a[j].t, a[j].c, L, laneoff);
+        wait_lgkm();
+#pragma unroll
+        for (int j = 0; j < kBlk; ++j) a[j] = p[2 * kBlk + j];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < kBlk; ++j) fold_update(hist, b[j].t, b[j].c, L, laneoff);
+        p += 2 * kBlk;
+    }
+}
+
+__device__ __forceinline__ uint32_t hist_off(int row, int lane) {
+    return (uint32_t)((lane >> 5) * kHalfBytes + row * 256 + (lane & 31) * 8);
+}
+
+__device__ __forceinline__ void decode(uint64_t v, double qscale, uint32_t& cnt, double& dev) {
+    cnt = (uint32_t)(v >> kCountShift);
+    const int64_t sq = (int64_t)(v & kSumMask) - (int64_t)cnt * kBias;
+    dev = (double)sq * qscale;
+}
+
+__device__ __forceinline__ void fold_block(char* hist, const Rec* __restrict__ rec, int64_t per,
+                                           const LaneSetup& L, int lane, int wave) {
+    uint64_t* h64 = reinterpret_cast<uint64_t*>(hist);
+    for (int i = threadIdx.x; i < kFineBins * 64; i += kThreads) h64[i] = 0;
+    __syncthreads();
+    const uint32_t laneoff = (uint32_t)((lane & 31) * 8 + (lane >> 5) * kHalfBytes);
+    fold_slice(hist, rec, (int64_t)wave * per, per / (2 * kBlk), L, laneoff);
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kThreads, 1) void k_fold(
+    const Rec* __restrict__ rec, int64_t per,
+    const double* __restrict__ periods, int64_t k, int32_t log2g,
+    const CurveInfo* __restrict__ info, double* __restrict__ sums, int32_t* __restrict__ counts,
+    double* __restrict__ means) {
+    __shared__ __attribute__((aligned(16))) char hist[kFineBins * 64 * 8];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t kk = (int64_t)blockIdx.x * 64 + lane;
+    const LaneSetup L = lane_setup(periods, kk, k, info->tmax);
+    fold_block(hist, rec, per, L, lane, wave);
+    if (kk >= k) return;
+    const int g = 1 << log2g;
+    const int nb = kFineBins >> log2g;
+    const double ref = info->ref, qs = info->qscale;
+    for (int b = wave; b < nb; b += kWaves) {
+        uint64_t acc = 0;
+        for (int j = 0; j < g; ++j) acc += *reinterpret_cast<const uint64_t*>(hist + hist_off(b * g + j, lane));
+        uint32_t c;
+        double d;
+        decode(acc, qs, c, d);
+        double s = L.valid ? (double)c * ref + d : 0.0;
+        if (!L.valid) c = 0;
+        const int64_t o = kk * nb + b;
+        sums[o] = s;
+        counts[o] = (int32_t)c;
+        if (means) means[o] = c ? s / (double)c : __builtin_nan("");
+    }
+}
+
+// ------------------------------------------------------------------ box scan
+
+// Slot (row r, period lane j) of the prefix table that replaces the
+// histogram in place: inclusive prefix over rows of the count (as float,
+// exact below 2^24) and of the flux-deviation sum (float).
+struct Slot {
+    float c;
+    float d;
+};
+
+__device__ __forceinline__ Slot slot_at(const char* tab, int row, int lane) {
+    return *reinterpret_cast<const Slot*>(tab + hist_off(row, lane));
+}
+
+// Box value proportional to the SNR of the box with count cin and deviation
+// sum din (the factor 1/(sigma sqrt(n)) is common to the row):
+// (S cin - n din) / sqrt(cin (n - cin)); 0 for an empty or full box.
+__device__ __forceinline__ float box_value(float cin, float din, float nf, float Sf) {
+    const float cout = nf - cin;
+    const float num = __builtin_fmaf(Sf, cin, -(nf * din));
+    const float den = cin * cout;
+    const float v = num * __builtin_amdgcn_rsqf(den);
+    return den > 0.5f ? v : 0.0f;
+}
+
+// Prefix of coarse boundary b (0..nb) for a table with `g` rows per coarse bin.
+__device__ __forceinline__ Slot coarse_prefix(const char* tab, int b, int g, int lane) {
+    if (b == 0) return Slot{0.0f, 0.0f};
+    return slot_at(tab, b * g - 1, lane);
+}
+
+// Largest box value of width w over all circular starts of one row.
+__device__ float scan_width(const char* tab, int w, int nb, int g, int lane, float nf, float Sf,
+                            Slot tot) {
+    float best = 0.0f;
+    {
+        const Slot e = coarse_prefix(tab, w, g, lane);
+        best = fmaxf(best, box_value(e.c, e.d, nf, Sf));
+    }
+    for (int s = 1; s + w <= nb; ++s) {
+        const Slot a = slot_at(tab, s * g - 1, lane);
+        const Slot e = slot_at(tab, (s + w) * g - 1, lane);
+        best = fmaxf(best, box_value(e.c - a.c, e.d - a.d, nf, Sf));
+    }
+    for (int s = nb - w + 1; s < nb; ++s) {
+        const Slot a = slot_at(tab, s * g - 1, lane);
+        const Slot e = slot_at(tab, (s + w - nb) * g - 1, lane);
+        best = fmaxf(best, box_value((e.c + tot.c) - a.c, (e.d + tot.d) - a.d, nf, Sf));
+    }
+    return best;
+}
+
+// First start whose box value equals `target` (same arithmetic as scan_width).
+__device__ int find_start(const char* tab, int w, int nb, int g, int lane, float nf, float Sf,
+                          Slot tot, float target) {
+    {
+        const Slot e = coarse_prefix(tab, w, g, lane);
+        if (fmaxf(0.0f, box_value(e.c, e.d, nf, Sf)) == target) return 0;
+    }
+    for (int s = 1; s + w <= nb; ++s) {
+        const Slot a = slot_at(tab, s * g - 1, lane);
+        const Slot e = slot_at(tab, (s + w) * g - 1, lane);
+        if (box_value(e.c - a.c, e.d - a.d, nf, Sf) == target) return s;
+    }
+    for (int s = nb - w + 1; s < nb; ++s) {
+        const Slot a = slot_at(tab, s * g - 1, lane);
+        const Slot e = slot_at(tab, (s + w - nb) * g - 1, lane);
+        if (box_value((e.c + tot.c) - a.c, (e.d + tot.d) - a.d, nf, Sf) == target) return s;
+    }
+    return -1;
+}
+
+// Shared tail of the fused and the materialised scorer: the prefix table for
+// the block's 64 periods is in `tab`, per-period totals in nrow/Srow. Waves
+// take one width each; wave 0 then picks the best width, finds its first
+// start and evaluates the winning box in FP64.
+__device__ void score_table(const char* tab, int nb, int g, const Widths& W, const float* nrow,
+                            const double* Srow, float* bestv, double sigma, bool valid,
+                            int64_t kk, int64_t k, int lane, int wave, float* snr, int32_t* start,
+                            int32_t* width, float* depth) {
+    const float nf = nrow[lane];
+    const float Sf = (float)Srow[lane];
+    const Slot tot = coarse_prefix(tab, nb, g, lane);
+    const bool ok_sigma = sigma > 0.0 && isfinite(sigma);
+    if (wave < W.n) {
+        const int w = W.w[wave];
+        float b = 0.0f;
+        if (w < nb && ok_sigma) b = scan_width(tab, w, nb, g, lane, nf, Sf, tot);
+        bestv[wave * 64 + lane] = b;
+    }
+    __syncthreads();
+    if (wave != 0 || kk >= k) return;
+    float best = 0.0f;
+    int bwi = -1;
+    for (int wi = 0; wi < W.n; ++wi) {
+        const float v = bestv[wi * 64 + lane];
+        if (v > best) { best = v; bwi = wi; }
+    }
+    float o_snr = 0.0f, o_depth = 0.0f;
+    int32_t o_s = -1, o_w = -1;
+    if (bwi >= 0 && valid) {
+        const int w = W.w[bwi];
+        const int s = find_start(tab, w, nb, g, lane, nf, Sf, tot, best);
+        if (s >= 0) {
+            const Slot a = coarse_prefix(tab, s, g, lane);
+            double ec, ed;
+            if (s + w <= nb) {
+                const Slot e = coarse_prefix(tab, s + w, g, lane);
+                ec = e.c; ed = e.d;
+            } else {
+                const Slot e = coarse_prefix(tab, s + w - nb, g, lane);
+                ec = (double)e.c + (double)tot.c;
+                ed = (double)e.d + (double)tot.d;
+            }
+            const double nin = ec - (double)a.c;
+            const double din = ed - (double)a.d;
+            const double n = (double)nf;
+            const double nout = n - nin;
+            const double S = Srow[lane];
+            const double dep = (S - din) / nout - din / nin;
+            o_snr = (float)(dep * sqrt(nin * nout / n) / sigma);
+            o_depth = (float)dep;
+            o_s = s;
+            o_w = w;
+        }
+    }
+    snr[kk] = o_snr;
+    depth[kk] = o_depth;
+    start[kk] = o_s;
+    width[kk] = o_w;
+}
+
+__global__ __launch_bounds__(kThreads, 1) void k_fold_score(
+    const Rec* __restrict__ rec, int64_t per,
+    const double* __restrict__ periods, int64_t k, int32_t log2g,
+    const CurveInfo* __restrict__ info, Widths W, float* __restrict__ snr,
+    int32_t* __restrict__ start, int32_t* __restrict__ width, float* __restrict__ depth) {
+    __shared__ __attribute__((aligned(16))) char hist[kFineBins * 64 * 8];
+    __shared__ uint64_t chunk[kWaves * 64];
+    __shared__ float nrow[64];
+    __shared__ double Srow[64];
+    __shared__ float bestv[kMaxWidths * 64];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t kk = (int64_t)blockIdx.x * 64 + lane;
+    const LaneSetup L = lane_setup(periods, kk, k, info->tmax);
+    fold_block(hist, rec, per, L, lane, wave);
+
+    // Inclusive prefix over the wave's 16 fine rows (packed values add exactly).
+    const int r0 = wave * kRowsPerWave;
+    uint64_t acc = 0;
+    for (int r = r0; r < r0 + kRowsPerWave; ++r) {
+        uint64_t* p = reinterpret_cast<uint64_t*>(hist + hist_off(r, lane));
+        acc += *p;
+        *p = acc;
+    }
+    chunk[wave * 64 + lane] = acc;
+    __syncthreads();
+    uint64_t off = 0, all = 0;
+    for (int w = 0; w < kWaves; ++w) {
+        const uint64_t v = chunk[w * 64 + lane];
+        off += w < wave ? v : 0;
+        all += v;
+    }
+    const double qs = info->qscale;
+    for (int r = r0; r < r0 + kRowsPerWave; ++r) {
+        char* p = hist + hist_off(r, lane);
+        const uint64_t v = *reinterpret_cast<uint64_t*>(p) + off;
+        uint32_t c;
+        double d;
+        decode(v, qs, c, d);
+        Slot sl{(float)c, (float)d};
+        if (!L.valid) sl = Slot{0.0f, 0.0f};
+        *reinterpret_cast<Slot*>(p) = sl;
+    }
+    if (wave == 0) {
+        uint32_t c;
+        double d;
+        decode(all, qs, c, d);
+        nrow[lane] = L.valid ? (float)c : 0.0f;
+        Srow[lane] = L.valid ? d : 0.0;
+    }
+    __syncthreads();
+    const int nb = kFineBins >> log2g;
+    score_table(hist, nb, 1 << log2g, W, nrow, Srow, bestv, info->sigma, L.valid, kk, k, lane, wave,
+                snr, start, width, depth);
+}
+
+// Box-SNR of materialised folds: lane j owns row blockIdx*64 + j; the waves
+// split the bins. Deviations are taken from each row's own mean (the SNR does
+// not depend on the reference).
+__global__ __launch_bounds__(kThreads, 1) void k_score(const double* __restrict__ sums,
+                                                       const int32_t* __restrict__ counts,
+                                                       int64_t k, int32_t nb, double sigma,
+                                                       Widths W, float* __restrict__ snr,
+                                                       int32_t* __restrict__ start,
+                                                       int32_t* __restrict__ width,
+                                                       float* __restrict__ depth) {
+    __shared__ __attribute__((aligned(16))) char tab[kFineBins * 64 * 8];
+    __shared__ double csum[kWaves * 64];
+    __shared__ double ccnt[kWaves * 64];
+    __shared__ float nrow[64];
+    __shared__ double Srow[64];
+    __shared__ float bestv[kMaxWidths * 64];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t kk = (int64_t)blockIdx.x * 64 + lane;
+    const bool valid = kk < k;
+    const int per = (nb + kWaves - 1) / kWaves;
+    const int b0 = min(nb, wave * per), b1 = min(nb, b0 + per);
+    double s = 0.0, c = 0.0;
+    if (valid)
+        for (int b = b0; b < b1; ++b) { s += sums[kk * nb + b]; c += (double)counts[kk * nb + b]; }
+    csum[wave * 64 + lane] = s;
+    ccnt[wave * 64 + lane] = c;
+    __syncthreads();
+    double ts = 0.0, tc = 0.0;
+    for (int w = 0; w < kWaves; ++w) { ts += csum[w * 64 + lane]; tc += ccnt[w * 64 + lane]; }
+    const double ref = tc > 0.0 ? ts / tc : 0.0;
+    double dacc = 0.0, cacc = 0.0;
+    for (int b = b0; b < b1; ++b) {
+        const double cb = valid ? (double)counts[kk * nb + b] : 0.0;
+        const double sb = valid ? sums[kk * nb + b] : 0.0;
+        dacc += sb - cb * ref;
+        cacc += cb;
+    }
+    __syncthreads();
+    csum[wave * 64 + lane] = dacc;
+    ccnt[wave * 64 + lane] = cacc;
+    __syncthreads();
+    double doff = 0.0, coff = 0.0, dall = 0.0, call = 0.0;
+    for (int w = 0; w < kWaves; ++w) {
+        const double dv = csum[w * 64 + lane], cv = ccnt[w * 64 + lane];
+        if (w < wave) { doff += dv; coff += cv; }
+        dall += dv;
+        call += cv;
+    }
+    for (int b = b0; b < b1; ++b) {
+        const double cb = valid ? (double)counts[kk * nb + b] : 0.0;
+        const double sb = valid ? sums[kk * nb + b] : 0.0;
+        doff += sb - cb * ref;
+        coff += cb;
+        *reinterpret_cast<Slot*>(tab + hist_off(b, lane)) = Slot{(float)coff, (float)doff};
+    }
+    if (wave == 0) {
+        nrow[lane] = (float)call;
+        Srow[lane] = dall;
+    }
+    __syncthreads();
+    score_table(tab, nb, 1, W, nrow, Srow, bestv, sigma, valid, kk, k, lane, wave, snr, start,
+                width, depth);
+}
+
+// ------------------------------------------------------------------ plain fold (baseline)
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero(T* __restrict__ p, int64_t m) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256)
+        p[i] = T(0);
+}
+
+// One block per period, one thread per sample: IEEE division, then one
+// device-memory atomic for the count and one FP64 atomic for the sum.
+__global__ __launch_bounds__(256) void k_fold_naive(const double* __restrict__ t,
+                                                    const float* __restrict__ flux, int64_t n,
+                                                    const double* __restrict__ periods,
+                                                    int32_t nbins, double* __restrict__ sums,
+                                                    int32_t* __restrict__ counts) {
+    const int64_t kk = blockIdx.x;
+    const double P = periods[kk];
+    if (!(P > 0.0) || !isfinite(P)) return;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const double x = t[i] / P;
+        const double f = x - floor(x);
+        const double fb = floor(f * (double)nbins);
+        int b = !(fb >= 0.0) ? 0 : (fb >= (double)nbins ? nbins - 1 : (int)fb);
+        atomicAdd(&counts[kk * nbins + b], 1);
+        unsafeAtomicAdd(&sums[kk * nbins + b], (double)flux[i]);
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t launch_curve_stats(const double* t, const float* flux, int64_t n, CurveInfo* info,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_curve_stats, dim3(1), dim3(1024), 0, s, t, flux, n, info);
+    return hipGetLastError();
+}
+
+int64_t fold_slice_len(int64_t n) {
+    const int64_t q = kWaves * 2 * kBlk;
+    const int64_t main = ((n > 0 ? n : 1) + q - 1) / q * q;
+    return main / kWaves;
+}
+
+int64_t prepared_len(int64_t n) { return fold_slice_len(n) * kWaves + 2 * kBlk; }
+
+hipError_t launch_pack(const double* t, const float* flux, int64_t n, const CurveInfo* info,
+                       Rec* rec, hipStream_t s) {
+    const int64_t total = prepared_len(n);
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)blocks), dim3(256), 0, s, t, flux, n, total, info, rec);
+    return hipGetLastError();
+}
+
+static int log2_of(int32_t nbins) {
+    int l = 0;
+    while ((1 << l) < nbins) ++l;
+    return l;
+}
+
+hipError_t launch_fold(const Rec* rec, int64_t n, const double* periods,
+                       int64_t k, int32_t nbins, const CurveInfo* info, double* sums,
+                       int32_t* counts, double* means, hipStream_t s) {
+    if (k == 0) return hipSuccess;
+    const int64_t blocks = (k + 63) / 64;
+    hipLaunchKernelGGL(k_fold, dim3((unsigned)blocks), dim3(kThreads), 0, s, rec, fold_slice_len(n), periods, k,
+                       8 - log2_of(nbins), info, sums, counts, means);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_score(const Rec* rec, int64_t n,
+                             const double* periods, int64_t k, int32_t nbins,
+                             const CurveInfo* info, const Widths& widths, float* snr,
+                             int32_t* start, int32_t* width, float* depth, hipStream_t s) {
+    if (k == 0) return hipSuccess;
+    const int64_t blocks = (k + 63) / 64;
+    hipLaunchKernelGGL(k_fold_score, dim3((unsigned)blocks), dim3(kThreads), 0, s, rec, fold_slice_len(n),
+                       periods, k, 8 - log2_of(nbins), info, widths, snr, start, width, depth);
+    return hipGetLastError();
+}
+
+hipError_t launch_score(const double* sums, const int32_t* counts, int64_t k, int32_t nbins,
+                        double sigma, const Widths& widths, float* snr, int32_t* start,
+                        int32_t* width, float* depth, hipStream_t s) {
+    if (k == 0) return hipSuccess;
+    const int64_t blocks = (k + 63) / 64;
+    hipLaunchKernelGGL(k_score, dim3((unsigned)blocks), dim3(kThreads), 0, s, sums, counts, k,
+                       nbins, sigma, widths, snr, start, width, depth);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_naive(const double* t, const float* flux, int64_t n,
+                             const double* periods, int64_t k, int32_t nbins, double* sums,
+                             int32_t* counts, hipStream_t s) {
+    if (k == 0) return hipSuccess;
+    const int64_t m = k * nbins;
+    const int64_t zb = std::min<int64_t>((m + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_zero<double>, dim3((unsigned)zb), dim3(256), 0, s, sums, m);
+    hipLaunchKernelGGL(k_zero<int32_t>, dim3((unsigned)zb), dim3(256), 0, s, counts, m);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fold_naive, dim3((unsigned)k), dim3(256), 0, s, t, flux, n, periods, nbins,
+                       sums, counts);
+    return hipGetLastError();
+}
+
+}  // namespace gpfc

@@ -1,0 +1,83 @@
+"""C ABI checks that run without a GPU: the library loads, exports every
+function include/gpfc.h declares, and rejects bad arguments on the host
+before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2312_02063_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "gpfc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gpfc_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(_lib.exported_symbols())
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_version_and_strerror():
+    lib = _lib.load()
+    assert lib.gpfc_version() == 100
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.gpfc_strerror(code)
+    assert lib.gpfc_strerror(-99) == b"unknown error"
+
+
+def test_null_plan_and_bad_arguments_rejected_on_host():
+    lib = _lib.load()
+    p = ctypes.c_void_p(1)        # never dereferenced: argument checks fail first
+    null = None
+    assert lib.gpfc_fold(null, None, None, 10, None, 5, 64, None, None, None, None) == _lib.EINVAL
+    assert lib.gpfc_fold_score(null, None, None, 0, None, 0, 64, None, None, None, None, None) == _lib.EINVAL
+    assert lib.gpfc_score(null, None, None, 1, 64, 1.0, None, None, None, None, None) == _lib.EINVAL
+    assert lib.gpfc_fold_naive(null, None, None, 1, None, 1, 64, None, None, None) == _lib.EINVAL
+    assert lib.gpfc_plan_set_widths(null, None, 0) == _lib.EINVAL
+    assert lib.gpfc_plan_create(None, 0) == _lib.EINVAL
+    assert lib.gpfc_plan_destroy(null) == _lib.OK
+    # negative sizes, missing pointers, nbins not a power of two, n too large
+    assert lib.gpfc_fold(p, None, None, -1, None, 0, 64, None, None, None, None) == _lib.EINVAL
+    assert lib.gpfc_fold(p, None, None, 5, None, 0, 64, None, None, None, None) == _lib.EINVAL
+    assert lib.gpfc_fold(p, p, p, 5, None, 3, 64, None, None, None, None) == _lib.EINVAL
+    assert lib.gpfc_fold(p, p, p, 5, p, 3, 0, p, p, None, None) == _lib.EINVAL
+    assert lib.gpfc_fold(p, p, p, 5, p, 3, 48, p, p, None, None) == _lib.ENOTSUP
+    assert lib.gpfc_fold(p, p, p, 5, p, 3, 512, p, p, None, None) == _lib.ENOTSUP
+    assert lib.gpfc_fold(p, p, p, _lib.MAX_SAMPLES + 1, p, 3, 64, p, p, None, None) == _lib.ERANGE
+    assert lib.gpfc_fold(p, p, p, 5, p, 3, 64, None, p, None, None) == _lib.EINVAL
+    assert lib.gpfc_fold_score(p, p, p, 5, p, 3, 64, p, None, p, p, None) == _lib.EINVAL
+    assert lib.gpfc_score(p, p, p, 3, 100, 1.0, p, p, p, p, None) == _lib.ENOTSUP
+    assert lib.gpfc_score(p, p, p, -1, 64, 1.0, p, p, p, p, None) == _lib.EINVAL
+
+
+def test_width_validation():
+    lib = _lib.load()
+    p = ctypes.c_void_p(1)
+    arr = (ctypes.c_int32 * 4)(1, 2, 2, 3)
+    assert lib.gpfc_plan_set_widths(p, arr, 4) == _lib.EINVAL        # not strictly ascending
+    arr = (ctypes.c_int32 * 2)(0, 3)
+    assert lib.gpfc_plan_set_widths(p, arr, 2) == _lib.EINVAL        # w < 1
+    arr = (ctypes.c_int32 * 17)(*range(1, 18))
+    assert lib.gpfc_plan_set_widths(p, arr, 17) == _lib.EINVAL       # too many
+
+
+def test_product_path_has_no_cpu_fallback():
+    # The package must not import the oracle anywhere.
+    pkg = os.path.join(ROOT, "paper_2312_02063_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "gpfc_oracle" not in text, f
