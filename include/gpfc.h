@@ -137,6 +137,25 @@ int32_t gpfc_fold_score(gpfc_plan *plan, const double *t, const float *flux, int
                         int32_t *start, int32_t *width, float *depth, void *stream);
 
 /*
+ * Prepare a curve once for several folds: runs the curve statistics and
+ * writes the plan's prepared curve (times and fixed-point flux, Sec. 2.3's
+ * input to the fold) into its workspace. The *_prepared calls below then fold
+ * that curve against any number of period arrays; a later gpfc_prepare,
+ * gpfc_fold, gpfc_fold_score or gpfc_curve_stats on the same plan replaces
+ * it. Same input contract as gpfc_fold.
+ */
+int32_t gpfc_prepare(gpfc_plan *plan, const double *t, const float *flux, int64_t n, void *stream);
+
+/* gpfc_fold on the plan's prepared curve (GPFC_EINVAL if none). */
+int32_t gpfc_fold_prepared(gpfc_plan *plan, const double *periods, int64_t k, int32_t nbins,
+                           double *sums, int32_t *counts, double *means, void *stream);
+
+/* gpfc_fold_score on the plan's prepared curve (GPFC_EINVAL if none). */
+int32_t gpfc_fold_score_prepared(gpfc_plan *plan, const double *periods, int64_t k,
+                                 int32_t nbins, float *snr, int32_t *start, int32_t *width,
+                                 float *depth, void *stream);
+
+/*
  * Plain GPU fold, the baseline the paper's own design resembles (Sec. 2.3,
  * Sec. 2.4: atomic accumulation, one thread per sample and period): IEEE
  * division per update and device-memory atomics. Same contract and outputs

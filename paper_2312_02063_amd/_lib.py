@@ -63,6 +63,9 @@ def load():
         "gpfc_score": ([vp, vp, vp, i64, i32, f64, vp, vp, vp, vp, vp], i32),
         "gpfc_fold_score": ([vp, vp, vp, i64, vp, i64, i32, vp, vp, vp, vp, vp], i32),
         "gpfc_fold_naive": ([vp, vp, vp, i64, vp, i64, i32, vp, vp, vp], i32),
+        "gpfc_prepare": ([vp, vp, vp, i64, vp], i32),
+        "gpfc_fold_prepared": ([vp, vp, i64, i32, vp, vp, vp, vp], i32),
+        "gpfc_fold_score_prepared": ([vp, vp, i64, i32, vp, vp, vp, vp, vp], i32),
         "gpfc_sync": ([vp], i32),
     }
     for name, (args, res) in sig.items():
@@ -77,7 +80,8 @@ def exported_symbols():
     """Names the C ABI declares (see include/gpfc.h)."""
     return ["gpfc_version", "gpfc_strerror", "gpfc_last_error", "gpfc_plan_create",
             "gpfc_plan_destroy", "gpfc_plan_set_widths", "gpfc_curve_stats", "gpfc_fold",
-            "gpfc_score", "gpfc_fold_score", "gpfc_fold_naive", "gpfc_sync"]
+            "gpfc_score", "gpfc_fold_score", "gpfc_fold_naive", "gpfc_sync", "gpfc_prepare",
+            "gpfc_fold_prepared", "gpfc_fold_score_prepared"]
 
 
 def _check(rc, what):
@@ -192,6 +196,33 @@ class Plan:
         _check(self.lib.gpfc_fold_score(self.h, _ptr(t), _ptr(flux), t.numel(), _ptr(periods), k,
                                         nbins, _ptr(snr), _ptr(start), _ptr(width), _ptr(depth),
                                         _stream()), "gpfc_fold_score")
+        return snr, start, width, depth
+
+    def prepare(self, t, flux):
+        """Prepare a curve in the plan for the *_prepared folds."""
+        self._inputs(t, flux)
+        _check(self.lib.gpfc_prepare(self.h, _ptr(t), _ptr(flux), t.numel(), _stream()),
+               "gpfc_prepare")
+
+    def fold_prepared(self, periods, nbins: int, means: bool = True):
+        import torch
+        _need(periods, torch.float64, "periods", self.device)
+        k = periods.numel()
+        sums = torch.empty((k, nbins), dtype=torch.float64, device=self.device)
+        counts = torch.empty((k, nbins), dtype=torch.int32, device=self.device)
+        mo = torch.empty((k, nbins), dtype=torch.float64, device=self.device) if means else None
+        _check(self.lib.gpfc_fold_prepared(self.h, _ptr(periods), k, nbins, _ptr(sums),
+                                           _ptr(counts), _ptr(mo), _stream()), "gpfc_fold_prepared")
+        return sums, counts, mo
+
+    def fold_score_prepared(self, periods, nbins: int, out=None):
+        import torch
+        _need(periods, torch.float64, "periods", self.device)
+        k = periods.numel()
+        snr, start, width, depth = out if out is not None else self._score_outputs(k)
+        _check(self.lib.gpfc_fold_score_prepared(self.h, _ptr(periods), k, nbins, _ptr(snr),
+                                                 _ptr(start), _ptr(width), _ptr(depth), _stream()),
+               "gpfc_fold_score_prepared")
         return snr, start, width, depth
 
     def fold_naive(self, t, flux, periods, nbins: int, out=None):

@@ -18,6 +18,7 @@ struct gpfc_plan {
     gpfc::Rec* rec = nullptr;     // prepared curve: times and packed contributions
     int64_t cap = 0;              // records rec can hold
     CurveInfo* info = nullptr;    // device-resident curve description
+    int64_t n = -1;               // samples of the prepared curve (-1: none)
     int32_t widths[GPFC_MAX_WIDTHS];
     int32_t nw = 0;               // 0: default set
 };
@@ -97,6 +98,14 @@ int32_t prepare_curve(gpfc_plan* p, const double* t, const float* flux, int64_t 
     if (e != hipSuccess) return device_error(e, "k_curve_stats launch");
     e = gpfc::launch_pack(t, flux, n, p->info, p->rec, s);
     if (e != hipSuccess) return device_error(e, "k_pack launch");
+    p->n = n;
+    return GPFC_OK;
+}
+
+int32_t check_prepared(const gpfc_plan* p, const void* periods, int64_t k, int32_t nbins) {
+    if (!p || p->n < 0 || k < 0 || (k > 0 && !periods) || nbins < 1) return GPFC_EINVAL;
+    if (!pow2_in_range(nbins)) return GPFC_ENOTSUP;
+    if ((k + 63) / 64 > 0x7fffffffLL) return GPFC_ERANGE;
     return GPFC_OK;
 }
 
@@ -176,6 +185,39 @@ int32_t gpfc_curve_stats(gpfc_plan* p, const double* t, const float* flux, int64
     out->n = ci.n;
     out->exact = ci.exact;
     out->finite = ci.finite;
+    return GPFC_OK;
+}
+
+int32_t gpfc_prepare(gpfc_plan* p, const double* t, const float* flux, int64_t n, void* stream) {
+    int32_t rc = check_fold_args(p, t, flux, n, (const void*)1, 0, 1);
+    if (rc != GPFC_OK) return rc;
+    return prepare_curve(p, t, flux, n, (hipStream_t)stream);
+}
+
+int32_t gpfc_fold_prepared(gpfc_plan* p, const double* periods, int64_t k, int32_t nbins,
+                           double* sums, int32_t* counts, double* means, void* stream) {
+    int32_t rc = check_prepared(p, periods, k, nbins);
+    if (rc != GPFC_OK) return rc;
+    if (k > 0 && (!sums || !counts)) return GPFC_EINVAL;
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return device_error(e, "hipSetDevice");
+    e = gpfc::launch_fold(p->rec, p->n, periods, k, nbins, p->info, sums, counts, means,
+                          (hipStream_t)stream);
+    if (e != hipSuccess) return device_error(e, "k_fold launch");
+    return GPFC_OK;
+}
+
+int32_t gpfc_fold_score_prepared(gpfc_plan* p, const double* periods, int64_t k, int32_t nbins,
+                                 float* snr, int32_t* start, int32_t* width, float* depth,
+                                 void* stream) {
+    int32_t rc = check_prepared(p, periods, k, nbins);
+    if (rc != GPFC_OK) return rc;
+    if (k > 0 && (!snr || !start || !width || !depth)) return GPFC_EINVAL;
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return device_error(e, "hipSetDevice");
+    e = gpfc::launch_fold_score(p->rec, p->n, periods, k, nbins, p->info, plan_widths(p, nbins),
+                                snr, start, width, depth, (hipStream_t)stream);
+    if (e != hipSuccess) return device_error(e, "k_fold_score launch");
     return GPFC_OK;
 }
 

@@ -200,17 +200,45 @@ __device__ __forceinline__ LaneSetup lane_setup(const double* __restrict__ perio
 // shifted down by T = 1 unit. When the fraction field is below 65536 - 2T the
 // bin equals that of the exact IEEE sequence; otherwise (about 3 updates in
 // 65536) the lane recomputes the bin with the IEEE sequence.
-__device__ __forceinline__ void fold_update(char* hist, double ti, uint64_t ci, const LaneSetup& L,
-                                            uint32_t laneoff) {
+__device__ __forceinline__ void lds_add(char* hist, uint32_t addr, uint64_t v) {
+    __hip_atomic_fetch_add(reinterpret_cast<uint64_t*>(hist + addr), v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ uint32_t fast_lo(double ti, const LaneSetup& L) {
     const double M = 0x1.8p36;
     const double w = __builtin_fma(ti, L.rB, L.theta);
-    const double zz = w + M;
-    const uint32_t lo = (uint32_t)__double_as_longlong(zz);
-    // byte0 <- laneoff.byte0, byte1 <- lo.byte2 (the bin), byte2 <- laneoff.byte2
-    uint32_t addr = __builtin_amdgcn_perm(lo, laneoff, 0x0C020600u);
-    if ((lo & 0xFFFFu) >= L.lim) addr = (fine_bin_ieee(ti, L.P) << 8) | laneoff;
-    __hip_atomic_fetch_add(reinterpret_cast<uint64_t*>(hist + addr), ci, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_WORKGROUP);
+    return (uint32_t)__double_as_longlong(w + M);
+}
+
+// byte0 <- laneoff.byte0, byte1 <- lo.byte2 (the bin), byte2 <- laneoff.byte2
+__device__ __forceinline__ uint32_t fast_addr(uint32_t lo, uint32_t laneoff) {
+    return __builtin_amdgcn_perm(lo, laneoff, 0x0C020600u);
+}
+
+// One update on the fast path; returns the mask of lanes whose bin the fast
+// path could not certify (their contribution went to the fast bin anyway).
+__device__ __forceinline__ uint64_t fold_update(char* hist, double ti, uint64_t ci,
+                                                const LaneSetup& L, uint32_t laneoff) {
+    const uint32_t lo = fast_lo(ti, L);
+    lds_add(hist, fast_addr(lo, laneoff), ci);
+    return __builtin_amdgcn_uicmp(lo & 0xFFFFu, L.lim, 35 /* unsigned >= */);
+}
+
+// Rare repair of a block in which some lane failed the certificate: for each
+// such update, take the contribution back out of the fast bin and put it in
+// the bin of the IEEE sequence (integer adds, so this is exact).
+__device__ __noinline__ void fold_repair(char* hist, const Rec* blk, int cnt, LaneSetup L,
+                                         uint32_t laneoff) {
+    for (int j = 0; j < cnt; ++j) {
+        const double ti = blk[j].t;
+        const uint64_t ci = blk[j].c;
+        const uint32_t lo = fast_lo(ti, L);
+        if ((lo & 0xFFFFu) >= L.lim) {
+            lds_add(hist, fast_addr(lo, laneoff), uint64_t(0) - ci);
+            lds_add(hist, (fine_bin_ieee(ti, L.P) << 8) | laneoff, ci);
+        }
+    }
 }
 
 // A wave's slice is a whole number of double blocks of kBlk records. Records
@@ -239,14 +267,18 @@ __device__ __forceinline__ void fold_slice(char* hist, const Rec* __restrict__ r
 #pragma unroll
         for (int j = 0; j < kBlk; ++j) b[j] = p[kBlk + j];
         __builtin_amdgcn_sched_barrier(0);
+        uint64_t fail = 0;
 #pragma unroll
-        for (int j = 0; j < kBlk; ++j) fold_update(hist, a[j].t, a[j].c, L, laneoff);
+        for (int j = 0; j < kBlk; ++j) fail |= fold_update(hist, a[j].t, a[j].c, L, laneoff);
+        if (fail) fold_repair(hist, p, kBlk, L, laneoff);
         wait_lgkm();
 #pragma unroll
         for (int j = 0; j < kBlk; ++j) a[j] = p[2 * kBlk + j];
         __builtin_amdgcn_sched_barrier(0);
+        fail = 0;
 #pragma unroll
-        for (int j = 0; j < kBlk; ++j) fold_update(hist, b[j].t, b[j].c, L, laneoff);
+        for (int j = 0; j < kBlk; ++j) fail |= fold_update(hist, b[j].t, b[j].c, L, laneoff);
+        if (fail) fold_repair(hist, p + kBlk, kBlk, L, laneoff);
         p += 2 * kBlk;
     }
 }
@@ -304,26 +336,29 @@ __global__ __launch_bounds__(kThreads, 1) void k_fold(
 // ------------------------------------------------------------------ box scan
 
 // Slot (row r, period lane j) of the prefix table that replaces the
-// histogram in place: inclusive prefix over rows of the count (as float,
-// exact below 2^24) and of the flux-deviation sum (float).
+// histogram in place: inclusive prefixes over rows of the count (float,
+// exact below 2^24) and of n times the flux-deviation sum (float).
 struct Slot {
     float c;
-    float d;
+    float dn;
 };
 
 __device__ __forceinline__ Slot slot_at(const char* tab, int row, int lane) {
     return *reinterpret_cast<const Slot*>(tab + hist_off(row, lane));
 }
 
-// Box value proportional to the SNR of the box with count cin and deviation
-// sum din (the factor 1/(sigma sqrt(n)) is common to the row):
-// (S cin - n din) / sqrt(cin (n - cin)); 0 for an empty or full box.
-__device__ __forceinline__ float box_value(float cin, float din, float nf, float Sf) {
+// Box value proportional to the box SNR (the row's common factor
+// 1/(sigma sqrt(n)) dropped): (S cin - n din) / sqrt(cin (n - cin)), from the
+// box count cin and dn_in = n din. kChecked = false assumes 0 < cin < n or
+// cin = 0 (then dn_in = 0 exactly and the value is NaN, which fmaxf skips);
+// kChecked = true returns 0 for an empty or full box.
+template <bool kChecked>
+__device__ __forceinline__ float box_value(float cin, float dn_in, float nf, float Sf) {
     const float cout = nf - cin;
-    const float num = __builtin_fmaf(Sf, cin, -(nf * din));
-    const float den = cin * cout;
-    const float v = num * __builtin_amdgcn_rsqf(den);
-    return den > 0.5f ? v : 0.0f;
+    const float num = __builtin_fmaf(Sf, cin, -dn_in);
+    const float v = num * __builtin_amdgcn_rsqf(cin * cout);
+    if (kChecked) return (cin > 0.5f && cout > 0.5f) ? v : 0.0f;
+    return v;
 }
 
 // Prefix of coarse boundary b (0..nb) for a table with `g` rows per coarse bin.
@@ -332,100 +367,133 @@ __device__ __forceinline__ Slot coarse_prefix(const char* tab, int b, int g, int
     return slot_at(tab, b * g - 1, lane);
 }
 
+// Value of the box (s, w); the three cases use exactly the expressions of
+// scan_width, so equal boxes give bit-identical values.
+template <bool kChecked>
+__device__ __forceinline__ float box_at(const char* tab, int s, int w, int nb, int g, int lane,
+                                        float nf, float Sf, Slot tot) {
+    if (s == 0) {
+        const Slot e = coarse_prefix(tab, w, g, lane);
+        return box_value<kChecked>(e.c, e.dn, nf, Sf);
+    }
+    const Slot a = slot_at(tab, s * g - 1, lane);
+    if (s + w <= nb) {
+        const Slot e = slot_at(tab, (s + w) * g - 1, lane);
+        return box_value<kChecked>(e.c - a.c, e.dn - a.dn, nf, Sf);
+    }
+    const Slot e = slot_at(tab, (s + w - nb) * g - 1, lane);
+    return box_value<kChecked>((e.c + tot.c) - a.c, (e.dn + tot.dn) - a.dn, nf, Sf);
+}
+
 // Largest box value of width w over all circular starts of one row.
+template <bool kChecked>
 __device__ float scan_width(const char* tab, int w, int nb, int g, int lane, float nf, float Sf,
                             Slot tot) {
     float best = 0.0f;
     {
         const Slot e = coarse_prefix(tab, w, g, lane);
-        best = fmaxf(best, box_value(e.c, e.d, nf, Sf));
+        best = fmaxf(best, box_value<kChecked>(e.c, e.dn, nf, Sf));
     }
+#pragma unroll 4
     for (int s = 1; s + w <= nb; ++s) {
         const Slot a = slot_at(tab, s * g - 1, lane);
         const Slot e = slot_at(tab, (s + w) * g - 1, lane);
-        best = fmaxf(best, box_value(e.c - a.c, e.d - a.d, nf, Sf));
+        best = fmaxf(best, box_value<kChecked>(e.c - a.c, e.dn - a.dn, nf, Sf));
     }
+#pragma unroll 4
     for (int s = nb - w + 1; s < nb; ++s) {
         const Slot a = slot_at(tab, s * g - 1, lane);
         const Slot e = slot_at(tab, (s + w - nb) * g - 1, lane);
-        best = fmaxf(best, box_value((e.c + tot.c) - a.c, (e.d + tot.d) - a.d, nf, Sf));
+        best = fmaxf(best, box_value<kChecked>((e.c + tot.c) - a.c, (e.dn + tot.dn) - a.dn, nf, Sf));
     }
     return best;
 }
 
-// First start whose box value equals `target` (same arithmetic as scan_width).
-__device__ int find_start(const char* tab, int w, int nb, int g, int lane, float nf, float Sf,
-                          Slot tot, float target) {
-    {
-        const Slot e = coarse_prefix(tab, w, g, lane);
-        if (fmaxf(0.0f, box_value(e.c, e.d, nf, Sf)) == target) return 0;
-    }
-    for (int s = 1; s + w <= nb; ++s) {
-        const Slot a = slot_at(tab, s * g - 1, lane);
-        const Slot e = slot_at(tab, (s + w) * g - 1, lane);
-        if (box_value(e.c - a.c, e.d - a.d, nf, Sf) == target) return s;
-    }
-    for (int s = nb - w + 1; s < nb; ++s) {
-        const Slot a = slot_at(tab, s * g - 1, lane);
-        const Slot e = slot_at(tab, (s + w - nb) * g - 1, lane);
-        if (box_value((e.c + tot.c) - a.c, (e.d + tot.d) - a.d, nf, Sf) == target) return s;
-    }
-    return -1;
-}
+// Per-block scratch of the scorer.
+struct ScoreShared {
+    float nrow[64];       // samples per period (float)
+    double Srow[64];      // flux-deviation total per period
+    int32_t nz[64];       // non-empty coarse bins per period
+    float bestv[kMaxWidths * 64];
+    int32_t first[kWaves * 64];
+    int32_t nzc[kWaves * 64];
+};
 
-// Shared tail of the fused and the materialised scorer: the prefix table for
-// the block's 64 periods is in `tab`, per-period totals in nrow/Srow. Waves
-// take one width each; wave 0 then picks the best width, finds its first
-// start and evaluates the winning box in FP64.
-__device__ void score_table(const char* tab, int nb, int g, const Widths& W, const float* nrow,
-                            const double* Srow, float* bestv, double sigma, bool valid,
-                            int64_t kk, int64_t k, int lane, int wave, float* snr, int32_t* start,
-                            int32_t* width, float* depth) {
-    const float nf = nrow[lane];
-    const float Sf = (float)Srow[lane];
+// Shared tail of the fused and the materialised scorer. The prefix table of
+// the block's 64 periods is in `tab`, per-period totals in sh. Each wave scans
+// one width for all 64 periods. A period whose samples fill more coarse bins
+// than the widest box can hold is scanned without per-box checks (no box can
+// be full; an empty box gives NaN, which the max skips); the others use the
+// checked form. Then every wave looks for the first start of the winning
+// width in its own range of starts, and wave 0 takes the smallest and
+// evaluates the box in FP64.
+__device__ void score_table(const char* tab, int nb, int g, const Widths& W, ScoreShared& sh,
+                            double sigma, bool valid, int64_t kk, int64_t k, int lane, int wave,
+                            float* snr, int32_t* start, int32_t* width, float* depth) {
+    const float nf = sh.nrow[lane];
+    const float Sf = (float)sh.Srow[lane];
     const Slot tot = coarse_prefix(tab, nb, g, lane);
     const bool ok_sigma = sigma > 0.0 && isfinite(sigma);
+    int wmax = 0;
+    for (int wi = 0; wi < W.n; ++wi)
+        if (W.w[wi] < nb) wmax = max(wmax, W.w[wi]);
+    const bool fast = g <= kRowsPerWave && sh.nz[lane] > wmax;
     if (wave < W.n) {
         const int w = W.w[wave];
         float b = 0.0f;
-        if (w < nb && ok_sigma) b = scan_width(tab, w, nb, g, lane, nf, Sf, tot);
-        bestv[wave * 64 + lane] = b;
+        if (w < nb && ok_sigma)
+            b = fast ? scan_width<false>(tab, w, nb, g, lane, nf, Sf, tot)
+                     : scan_width<true>(tab, w, nb, g, lane, nf, Sf, tot);
+        sh.bestv[wave * 64 + lane] = b;
     }
     __syncthreads();
-    if (wave != 0 || kk >= k) return;
     float best = 0.0f;
     int bwi = -1;
     for (int wi = 0; wi < W.n; ++wi) {
-        const float v = bestv[wi * 64 + lane];
+        const float v = sh.bestv[wi * 64 + lane];
         if (v > best) { best = v; bwi = wi; }
     }
+    int first = 0x7fffffff;
+    if (bwi >= 0) {
+        const int w = W.w[bwi];
+        const int per = (nb + kWaves - 1) / kWaves;
+        const int s1 = min(nb, (wave + 1) * per);
+        for (int s = wave * per; s < s1; ++s) {
+            const float v = fast ? box_at<false>(tab, s, w, nb, g, lane, nf, Sf, tot)
+                                 : box_at<true>(tab, s, w, nb, g, lane, nf, Sf, tot);
+            if (v == best) { first = s; break; }
+        }
+    }
+    sh.first[wave * 64 + lane] = first;
+    __syncthreads();
+    if (wave != 0 || kk >= k) return;
+    int s = 0x7fffffff;
+    for (int wv = 0; wv < kWaves; ++wv) s = min(s, sh.first[wv * 64 + lane]);
     float o_snr = 0.0f, o_depth = 0.0f;
     int32_t o_s = -1, o_w = -1;
-    if (bwi >= 0 && valid) {
+    if (bwi >= 0 && valid && s < nb) {
         const int w = W.w[bwi];
-        const int s = find_start(tab, w, nb, g, lane, nf, Sf, tot, best);
-        if (s >= 0) {
-            const Slot a = coarse_prefix(tab, s, g, lane);
-            double ec, ed;
-            if (s + w <= nb) {
-                const Slot e = coarse_prefix(tab, s + w, g, lane);
-                ec = e.c; ed = e.d;
-            } else {
-                const Slot e = coarse_prefix(tab, s + w - nb, g, lane);
-                ec = (double)e.c + (double)tot.c;
-                ed = (double)e.d + (double)tot.d;
-            }
-            const double nin = ec - (double)a.c;
-            const double din = ed - (double)a.d;
-            const double n = (double)nf;
-            const double nout = n - nin;
-            const double S = Srow[lane];
-            const double dep = (S - din) / nout - din / nin;
-            o_snr = (float)(dep * sqrt(nin * nout / n) / sigma);
-            o_depth = (float)dep;
-            o_s = s;
-            o_w = w;
+        const Slot a = coarse_prefix(tab, s, g, lane);
+        double ec, edn;
+        if (s + w <= nb) {
+            const Slot e = coarse_prefix(tab, s + w, g, lane);
+            ec = e.c;
+            edn = e.dn;
+        } else {
+            const Slot e = coarse_prefix(tab, s + w - nb, g, lane);
+            ec = (double)e.c + (double)tot.c;
+            edn = (double)e.dn + (double)tot.dn;
         }
+        const double n = (double)nf;
+        const double nin = ec - (double)a.c;
+        const double din = (edn - (double)a.dn) / n;
+        const double nout = n - nin;
+        const double S = sh.Srow[lane];
+        const double dep = (S - din) / nout - din / nin;
+        o_snr = (float)(dep * sqrt(nin * nout / n) / sigma);
+        o_depth = (float)dep;
+        o_s = s;
+        o_w = w;
     }
     snr[kk] = o_snr;
     depth[kk] = o_depth;
@@ -440,9 +508,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_fold_score(
     int32_t* __restrict__ start, int32_t* __restrict__ width, float* __restrict__ depth) {
     __shared__ __attribute__((aligned(16))) char hist[kFineBins * 64 * 8];
     __shared__ uint64_t chunk[kWaves * 64];
-    __shared__ float nrow[64];
-    __shared__ double Srow[64];
-    __shared__ float bestv[kMaxWidths * 64];
+    __shared__ ScoreShared sh;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t kk = (int64_t)blockIdx.x * 64 + lane;
@@ -466,27 +532,44 @@ __global__ __launch_bounds__(kThreads, 1) void k_fold_score(
         all += v;
     }
     const double qs = info->qscale;
+    uint32_t call;
+    double dall;
+    decode(all, qs, call, dall);
+    const float nf = L.valid ? (float)call : 0.0f;
+    // Convert to the float prefix table and count non-empty coarse bins
+    // (coarse bins of g <= 16 rows never straddle two waves' rows).
+    const int g = 1 << log2g;
+    uint32_t cprev = (uint32_t)(off >> kCountShift);
+    int nzl = 0;
     for (int r = r0; r < r0 + kRowsPerWave; ++r) {
         char* p = hist + hist_off(r, lane);
         const uint64_t v = *reinterpret_cast<uint64_t*>(p) + off;
         uint32_t c;
         double d;
         decode(v, qs, c, d);
-        Slot sl{(float)c, (float)d};
+        if (((r + 1) & (g - 1)) == 0) {
+            nzl += c > cprev;
+            cprev = c;
+        }
+        Slot sl{(float)c, (float)((double)nf * d)};
         if (!L.valid) sl = Slot{0.0f, 0.0f};
         *reinterpret_cast<Slot*>(p) = sl;
     }
+    sh.nzc[wave * 64 + lane] = nzl;
     if (wave == 0) {
-        uint32_t c;
-        double d;
-        decode(all, qs, c, d);
-        nrow[lane] = L.valid ? (float)c : 0.0f;
-        Srow[lane] = L.valid ? d : 0.0;
+        sh.nrow[lane] = nf;
+        sh.Srow[lane] = L.valid ? dall : 0.0;
+    }
+    __syncthreads();
+    if (wave == 0) {
+        int nz = 0;
+        for (int w = 0; w < kWaves; ++w) nz += sh.nzc[w * 64 + lane];
+        sh.nz[lane] = nz;
     }
     __syncthreads();
     const int nb = kFineBins >> log2g;
-    score_table(hist, nb, 1 << log2g, W, nrow, Srow, bestv, info->sigma, L.valid, kk, k, lane, wave,
-                snr, start, width, depth);
+    score_table(hist, nb, g, W, sh, info->sigma, L.valid, kk, k, lane, wave, snr, start, width,
+                depth);
 }
 
 // Box-SNR of materialised folds: lane j owns row blockIdx*64 + j; the waves
@@ -502,9 +585,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_score(const double* __restrict_
     __shared__ __attribute__((aligned(16))) char tab[kFineBins * 64 * 8];
     __shared__ double csum[kWaves * 64];
     __shared__ double ccnt[kWaves * 64];
-    __shared__ float nrow[64];
-    __shared__ double Srow[64];
-    __shared__ float bestv[kMaxWidths * 64];
+    __shared__ ScoreShared sh;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t kk = (int64_t)blockIdx.x * 64 + lane;
@@ -521,37 +602,42 @@ __global__ __launch_bounds__(kThreads, 1) void k_score(const double* __restrict_
     for (int w = 0; w < kWaves; ++w) { ts += csum[w * 64 + lane]; tc += ccnt[w * 64 + lane]; }
     const double ref = tc > 0.0 ? ts / tc : 0.0;
     double dacc = 0.0, cacc = 0.0;
+    int nzl = 0;
     for (int b = b0; b < b1; ++b) {
         const double cb = valid ? (double)counts[kk * nb + b] : 0.0;
         const double sb = valid ? sums[kk * nb + b] : 0.0;
         dacc += sb - cb * ref;
         cacc += cb;
+        nzl += cb > 0.0;
     }
     __syncthreads();
     csum[wave * 64 + lane] = dacc;
     ccnt[wave * 64 + lane] = cacc;
+    sh.nzc[wave * 64 + lane] = nzl;
     __syncthreads();
     double doff = 0.0, coff = 0.0, dall = 0.0, call = 0.0;
+    int nz = 0;
     for (int w = 0; w < kWaves; ++w) {
         const double dv = csum[w * 64 + lane], cv = ccnt[w * 64 + lane];
         if (w < wave) { doff += dv; coff += cv; }
         dall += dv;
         call += cv;
+        nz += sh.nzc[w * 64 + lane];
     }
     for (int b = b0; b < b1; ++b) {
         const double cb = valid ? (double)counts[kk * nb + b] : 0.0;
         const double sb = valid ? sums[kk * nb + b] : 0.0;
         doff += sb - cb * ref;
         coff += cb;
-        *reinterpret_cast<Slot*>(tab + hist_off(b, lane)) = Slot{(float)coff, (float)doff};
+        *reinterpret_cast<Slot*>(tab + hist_off(b, lane)) = Slot{(float)coff, (float)(call * doff)};
     }
     if (wave == 0) {
-        nrow[lane] = (float)call;
-        Srow[lane] = dall;
+        sh.nrow[lane] = (float)call;
+        sh.Srow[lane] = dall;
+        sh.nz[lane] = nz;
     }
     __syncthreads();
-    score_table(tab, nb, 1, W, nrow, Srow, bestv, sigma, valid, kk, k, lane, wave, snr, start,
-                width, depth);
+    score_table(tab, nb, 1, W, sh, sigma, valid, kk, k, lane, wave, snr, start, width, depth);
 }
 
 // ------------------------------------------------------------------ plain fold (baseline)
