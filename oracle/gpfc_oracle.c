@@ -157,7 +157,8 @@ int32_t oracle_default_widths(int32_t nbins, int32_t *out, int32_t cap) {
  *   snr   = depth * sqrt(n_in * n_out / n) / sigma
  *
  * where c are counts, D deviation sums, n = sum c and S = sum D. Boxes with
- * n_in = 0 or n_out = 0 are skipped. The result is the largest snr over
+ * n_in = 0 or n_out = 0 are skipped, and so are widths w >= B (a box that
+ * wide leaves no bin outside it). The result is the largest snr over
  * widths in ascending order and starts in ascending order, a later box
  * replacing the best only if strictly larger, starting from 0: only dips
  * score. With no positive box, or sigma not > 0, snr = 0, depth = 0 and
@@ -181,6 +182,7 @@ void oracle_score(const int32_t *counts, const double *dsums, int64_t k,
         if (sigma > 0.0 && isfinite(sigma)) {
             for (int32_t wi = 0; wi < nw; ++wi) {
                 int32_t w = widths[wi];
+                if (w >= nbins) continue;   /* no out-of-box bins, or bins counted twice */
                 for (int32_t s = 0; s < nbins; ++s) {
                     int64_t n_in = 0;
                     double D_in = 0.0;

@@ -375,3 +375,15 @@ def test_injected_period_within_one_step_most_seeds():
         fbest = freqs[int(np.argmax(r["snr"]))]
         hits += abs(fbest - 1.0 / c.truth["period"]) <= step * 1.0001
     assert hits >= 19
+
+
+def test_widths_not_below_nbins_are_skipped():
+    # A box as wide as the fold has no bin outside it (and a wider one would
+    # count bins twice): such widths contribute nothing.
+    rng = np.random.default_rng(12)
+    counts = rng.integers(1, 20, (3, 8)).astype(np.int32)
+    dsums = rng.normal(0, 1e-3, (3, 8))
+    a = oracle.score(counts, dsums, 1e-3, widths=np.array([2, 8, 9]))
+    b = oracle.score(counts, dsums, 1e-3, widths=np.array([2]))
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
