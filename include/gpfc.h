@@ -150,10 +150,55 @@ int32_t gpfc_prepare(gpfc_plan *plan, const double *t, const float *flux, int64_
 int32_t gpfc_fold_prepared(gpfc_plan *plan, const double *periods, int64_t k, int32_t nbins,
                            double *sums, int32_t *counts, double *means, void *stream);
 
-/* gpfc_fold_score on the plan's prepared curve (GPFC_EINVAL if none). */
+/*
+ * gpfc_fold_score on the plan's prepared curve (GPFC_EINVAL if none).
+ * zfold (may be NULL; needs nbins >= 16): also writes each period's folded
+ * curve normalised for the learned scorer (Sec. 2.1: scaled to unit noise
+ * before the CNN), as bfloat16 [k][nbins]: bin means minus their mean over
+ * the non-empty bins, divided by their standard deviation (ddof 0); empty bins
+ * and a zero spread give 0.
+ */
 int32_t gpfc_fold_score_prepared(gpfc_plan *plan, const double *periods, int64_t k,
                                  int32_t nbins, float *snr, int32_t *start, int32_t *width,
-                                 float *depth, void *stream);
+                                 float *depth, uint16_t *zfold, void *stream);
+
+/*
+ * Multi-curve batch: many light curves folded and scored in one persistent
+ * launch (the paper processes a catalogue curve after curve, Sec. 3.4).
+ * Setup (synchronous, allocates): sample_offsets_host[n_curves + 1] and
+ * period_offsets_host[n_curves + 1] (HOST arrays, starting at 0) cut the
+ * concatenated t / flux and periods arrays into curves. Work items (a curve
+ * and a block of 64 of its periods) are queued longest curve first. A later
+ * setup replaces the batch.
+ */
+int32_t gpfc_batch_setup(gpfc_plan *plan, const int64_t *sample_offsets_host,
+                         const int64_t *period_offsets_host, int32_t n_curves);
+
+/*
+ * Fold and score every curve of the batch at its own periods: per-curve
+ * statistics, packing, then one persistent kernel (one block per compute
+ * unit pulling work items from a device counter). t f64[total samples],
+ * flux f32[...], periods f64[total periods]; outputs indexed like periods
+ * (snr, start, width, depth as gpfc_score; zfold as gpfc_fold_score_prepared,
+ * [total periods][nbins], may be NULL). Allocates nothing.
+ */
+int32_t gpfc_batch_fold_score(gpfc_plan *plan, const double *t, const float *flux,
+                              const double *periods, int32_t nbins, float *snr, int32_t *start,
+                              int32_t *width, float *depth, uint16_t *zfold, void *stream);
+
+/*
+ * Record the gpfc_batch_fold_score launch sequence for these buffers into a
+ * HIP graph held by the plan (kernel nodes only). `stream` must be a created
+ * stream, not the null stream. gpfc_batch_replay launches the graph on any
+ * stream; the buffers must stay valid while replays run.
+ */
+int32_t gpfc_batch_capture(gpfc_plan *plan, const double *t, const float *flux,
+                           const double *periods, int32_t nbins, float *snr, int32_t *start,
+                           int32_t *width, float *depth, uint16_t *zfold, void *stream);
+int32_t gpfc_batch_replay(gpfc_plan *plan, void *stream);
+
+/* Per-curve statistics of the last batch run (host array of n_curves); synchronous. */
+int32_t gpfc_batch_curve_stats(gpfc_plan *plan, gpfc_curve *out_host, void *stream);
 
 /*
  * Plain GPU fold, the baseline the paper's own design resembles (Sec. 2.3,

@@ -60,6 +60,8 @@ def _load():
     lib.oracle_score.restype = None
     lib.oracle_box_snr.argtypes = [ip, dp, i32, ctypes.c_double, i32, i32]
     lib.oracle_box_snr.restype = ctypes.c_double
+    lib.oracle_normalize.argtypes = [dp, ip, i64, i32, dp]
+    lib.oracle_normalize.restype = None
     lib.oracle_grid_size.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
     lib.oracle_grid_size.restype = ctypes.c_double
     _lib = lib
@@ -168,6 +170,19 @@ def box_snr(counts_row, dsums_row, sigma, s, w):
     d = _f64(dsums_row)
     return lib.oracle_box_snr(_p(c, ctypes.c_int32), _p(d, ctypes.c_double), c.size,
                               float(sigma), int(s), int(w))
+
+
+def normalize(sums, counts):
+    """Noise-normalised folds for the learned scorer (Sec. 2.1): z-scores of the
+    bin means over non-empty bins (ddof 0); empty bins and zero spread give 0."""
+    lib = _load()
+    sums = _f64(sums)
+    counts = np.ascontiguousarray(counts, dtype=np.int32)
+    k, nbins = sums.shape
+    z = np.empty_like(sums)
+    lib.oracle_normalize(_p(sums, ctypes.c_double), _p(counts, ctypes.c_int32), k, nbins,
+                         _p(z, ctypes.c_double))
+    return z
 
 
 def grid_size(n_o: float, span: float, width: float) -> float:

@@ -236,6 +236,34 @@ double oracle_box_snr(const int32_t *c, const double *D, int32_t nbins,
 }
 
 /*
+ * Noise normalisation of a folded curve before the learned scorer (Sec. 2.1:
+ * each folded curve is scaled to unit noise): over the non-empty bins of a
+ * row, z = (mean_b - mu) / sd with mu and sd the mean and standard deviation
+ * (ddof 0) of those bin means; empty bins, and every bin of a row whose sd
+ * is 0, get 0. The paper also keeps the row's mean; adding a constant to every
+ * input of the first convolution is absorbed by its bias, so it is dropped.
+ */
+void oracle_normalize(const double *sums, const int32_t *counts, int64_t k, int32_t nbins,
+                      double *z) {
+    for (int64_t kk = 0; kk < k; ++kk) {
+        const double *s = sums + kk * nbins;
+        const int32_t *c = counts + kk * nbins;
+        double *zr = z + kk * nbins;
+        int32_t m = 0;
+        double mu = 0.0;
+        for (int32_t b = 0; b < nbins; ++b)
+            if (c[b] > 0) { mu += s[b] / (double)c[b]; ++m; }
+        mu = m > 0 ? mu / (double)m : 0.0;
+        double var = 0.0;
+        for (int32_t b = 0; b < nbins; ++b)
+            if (c[b] > 0) { double d = s[b] / (double)c[b] - mu; var += d * d; }
+        double sd = m > 0 ? sqrt(var / (double)m) : 0.0;
+        for (int32_t b = 0; b < nbins; ++b)
+            zr[b] = (c[b] > 0 && sd > 0.0) ? (s[b] / (double)c[b] - mu) / sd : 0.0;
+    }
+}
+
+/*
  * Trial-grid size of Eq. 1 (Sec. 2.1): N_sample = N_o * T / L.
  */
 double oracle_grid_size(double n_o, double span, double width) {

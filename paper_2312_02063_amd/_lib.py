@@ -65,7 +65,12 @@ def load():
         "gpfc_fold_naive": ([vp, vp, vp, i64, vp, i64, i32, vp, vp, vp], i32),
         "gpfc_prepare": ([vp, vp, vp, i64, vp], i32),
         "gpfc_fold_prepared": ([vp, vp, i64, i32, vp, vp, vp, vp], i32),
-        "gpfc_fold_score_prepared": ([vp, vp, i64, i32, vp, vp, vp, vp, vp], i32),
+        "gpfc_fold_score_prepared": ([vp, vp, i64, i32, vp, vp, vp, vp, vp, vp], i32),
+        "gpfc_batch_setup": ([vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), i32], i32),
+        "gpfc_batch_fold_score": ([vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp], i32),
+        "gpfc_batch_capture": ([vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp], i32),
+        "gpfc_batch_replay": ([vp, vp], i32),
+        "gpfc_batch_curve_stats": ([vp, ctypes.POINTER(Curve), vp], i32),
         "gpfc_sync": ([vp], i32),
     }
     for name, (args, res) in sig.items():
@@ -81,7 +86,9 @@ def exported_symbols():
     return ["gpfc_version", "gpfc_strerror", "gpfc_last_error", "gpfc_plan_create",
             "gpfc_plan_destroy", "gpfc_plan_set_widths", "gpfc_curve_stats", "gpfc_fold",
             "gpfc_score", "gpfc_fold_score", "gpfc_fold_naive", "gpfc_sync", "gpfc_prepare",
-            "gpfc_fold_prepared", "gpfc_fold_score_prepared"]
+            "gpfc_fold_prepared", "gpfc_fold_score_prepared", "gpfc_batch_setup",
+            "gpfc_batch_fold_score", "gpfc_batch_capture", "gpfc_batch_replay",
+            "gpfc_batch_curve_stats"]
 
 
 def _check(rc, what):
@@ -215,15 +222,77 @@ class Plan:
                                            _ptr(counts), _ptr(mo), _stream()), "gpfc_fold_prepared")
         return sums, counts, mo
 
-    def fold_score_prepared(self, periods, nbins: int, out=None):
+    def fold_score_prepared(self, periods, nbins: int, out=None, zfold=None):
+        """Fused fold + score on the prepared curve; ``zfold`` (optional uint16
+        tensor [k, nbins]) receives the normalised folds as bfloat16 bits."""
         import torch
         _need(periods, torch.float64, "periods", self.device)
         k = periods.numel()
         snr, start, width, depth = out if out is not None else self._score_outputs(k)
+        if zfold is not None:
+            _need(zfold, torch.uint16, "zfold", self.device)
+            if zfold.numel() != k * nbins:
+                raise ValueError("zfold must hold k * nbins values")
         _check(self.lib.gpfc_fold_score_prepared(self.h, _ptr(periods), k, nbins, _ptr(snr),
-                                                 _ptr(start), _ptr(width), _ptr(depth), _stream()),
+                                                 _ptr(start), _ptr(width), _ptr(depth),
+                                                 _ptr(zfold), _stream()),
                "gpfc_fold_score_prepared")
         return snr, start, width, depth
+
+    # ---------------------------------------------------------------- batches
+
+    def batch_setup(self, sample_offsets, period_offsets):
+        """Describe a batch of curves by host offsets (length n_curves + 1, from 0)."""
+        so = [int(x) for x in sample_offsets]
+        po = [int(x) for x in period_offsets]
+        if len(so) != len(po) or len(so) < 1:
+            raise ValueError("offset arrays must both have n_curves + 1 entries")
+        a = (ctypes.c_int64 * len(so))(*so)
+        b = (ctypes.c_int64 * len(po))(*po)
+        _check(self.lib.gpfc_batch_setup(self.h, a, b, len(so) - 1), "gpfc_batch_setup")
+        self.batch_n = len(so) - 1
+        self.batch_k = po[-1]
+        self.batch_samples = so[-1]
+
+    def _batch_args(self, t, flux, periods, nbins, out, zfold):
+        import torch
+        _need(t, torch.float64, "t", self.device)
+        _need(flux, torch.float32, "flux", self.device)
+        _need(periods, torch.float64, "periods", self.device)
+        if t.numel() != self.batch_samples or flux.numel() != self.batch_samples:
+            raise ValueError("t / flux do not match the batch's sample offsets")
+        if periods.numel() != self.batch_k:
+            raise ValueError("periods do not match the batch's period offsets")
+        outs = out if out is not None else self._score_outputs(self.batch_k)
+        if zfold is not None:
+            _need(zfold, torch.uint16, "zfold", self.device)
+            if zfold.numel() != self.batch_k * nbins:
+                raise ValueError("zfold must hold total periods * nbins values")
+        return outs
+
+    def batch_fold_score(self, t, flux, periods, nbins: int, out=None, zfold=None):
+        snr, start, width, depth = self._batch_args(t, flux, periods, nbins, out, zfold)
+        _check(self.lib.gpfc_batch_fold_score(self.h, _ptr(t), _ptr(flux), _ptr(periods), nbins,
+                                              _ptr(snr), _ptr(start), _ptr(width), _ptr(depth),
+                                              _ptr(zfold), _stream()), "gpfc_batch_fold_score")
+        return snr, start, width, depth
+
+    def batch_capture(self, t, flux, periods, nbins: int, out=None, zfold=None):
+        """Capture the batch pipeline into a HIP graph on the current (non-default) stream."""
+        snr, start, width, depth = self._batch_args(t, flux, periods, nbins, out, zfold)
+        self._graph_keep = (t, flux, periods, snr, start, width, depth, zfold)
+        _check(self.lib.gpfc_batch_capture(self.h, _ptr(t), _ptr(flux), _ptr(periods), nbins,
+                                           _ptr(snr), _ptr(start), _ptr(width), _ptr(depth),
+                                           _ptr(zfold), _stream()), "gpfc_batch_capture")
+        return snr, start, width, depth
+
+    def batch_replay(self):
+        _check(self.lib.gpfc_batch_replay(self.h, _stream()), "gpfc_batch_replay")
+
+    def batch_curve_stats(self):
+        arr = (Curve * max(1, self.batch_n))()
+        _check(self.lib.gpfc_batch_curve_stats(self.h, arr, _stream()), "gpfc_batch_curve_stats")
+        return [arr[i].as_dict() for i in range(self.batch_n)]
 
     def fold_naive(self, t, flux, periods, nbins: int, out=None):
         """Plain global-atomic GPU fold (baseline): (sums, counts)."""

@@ -4,8 +4,9 @@
 #include <stdio.h>
 #include <string.h>
 
-#include <mutex>
+#include <algorithm>
 #include <new>
+#include <vector>
 
 #include "../../include/gpfc.h"
 #include "gpfc_internal.h"
@@ -21,6 +22,21 @@ struct gpfc_plan {
     int64_t n = -1;               // samples of the prepared curve (-1: none)
     int32_t widths[GPFC_MAX_WIDTHS];
     int32_t nw = 0;               // 0: default set
+    int32_t n_cu = 0;             // compute units (persistent grid size)
+    // multi-curve batch (gpfc_batch_setup)
+    int32_t b_curves = -1;
+    int64_t b_samples = 0, b_periods = 0, b_records = 0, b_max_records = 0;
+    int32_t b_items = 0;
+    void* b_dev = nullptr;        // one allocation: offsets, curves, items, counter, infos, records
+    int64_t* b_soff = nullptr;
+    int64_t* b_roff = nullptr;
+    gpfc::BatchCurve* b_curve = nullptr;
+    int2* b_item = nullptr;
+    int32_t* b_counter = nullptr;
+    CurveInfo* b_info = nullptr;
+    gpfc::Rec* b_rec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
 };
 
 namespace {
@@ -136,9 +152,13 @@ int32_t gpfc_plan_create(gpfc_plan** out, int32_t device) {
     hipError_t e = hipGetDeviceCount(&count);
     if (e != hipSuccess) return device_error(e, "hipGetDeviceCount");
     if (device < 0 || device >= count) return GPFC_EINVAL;
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return device_error(e, "hipGetDeviceProperties");
     gpfc_plan* p = new (std::nothrow) gpfc_plan();
     if (!p) return GPFC_ENOMEM;
     p->device = device;
+    p->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
     *out = p;
     return GPFC_OK;
 }
@@ -149,6 +169,9 @@ int32_t gpfc_plan_destroy(gpfc_plan* p) {
     (void)hipDeviceSynchronize();
     if (p->rec) (void)hipFree(p->rec);
     if (p->info) (void)hipFree(p->info);
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->b_dev) (void)hipFree(p->b_dev);
     delete p;
     return GPFC_OK;
 }
@@ -209,14 +232,15 @@ int32_t gpfc_fold_prepared(gpfc_plan* p, const double* periods, int64_t k, int32
 
 int32_t gpfc_fold_score_prepared(gpfc_plan* p, const double* periods, int64_t k, int32_t nbins,
                                  float* snr, int32_t* start, int32_t* width, float* depth,
-                                 void* stream) {
+                                 uint16_t* zfold, void* stream) {
     int32_t rc = check_prepared(p, periods, k, nbins);
     if (rc != GPFC_OK) return rc;
     if (k > 0 && (!snr || !start || !width || !depth)) return GPFC_EINVAL;
+    if (zfold && nbins < 16) return GPFC_ENOTSUP;
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return device_error(e, "hipSetDevice");
     e = gpfc::launch_fold_score(p->rec, p->n, periods, k, nbins, p->info, plan_widths(p, nbins),
-                                snr, start, width, depth, (hipStream_t)stream);
+                                snr, start, width, depth, zfold, (hipStream_t)stream);
     if (e != hipSuccess) return device_error(e, "k_fold_score launch");
     return GPFC_OK;
 }
@@ -245,7 +269,8 @@ int32_t gpfc_fold_score(gpfc_plan* p, const double* t, const float* flux, int64_
     rc = prepare_curve(p, t, flux, n, s);
     if (rc != GPFC_OK) return rc;
     hipError_t e = gpfc::launch_fold_score(p->rec, n, periods, k, nbins, p->info,
-                                           plan_widths(p, nbins), snr, start, width, depth, s);
+                                           plan_widths(p, nbins), snr, start, width, depth,
+                                           nullptr, s);
     if (e != hipSuccess) return device_error(e, "k_fold_score launch");
     return GPFC_OK;
 }
@@ -276,6 +301,180 @@ int32_t gpfc_fold_naive(gpfc_plan* p, const double* t, const float* flux, int64_
     if (e != hipSuccess) return device_error(e, "hipSetDevice");
     e = gpfc::launch_fold_naive(t, flux, n, periods, k, nbins, sums, counts, (hipStream_t)stream);
     if (e != hipSuccess) return device_error(e, "k_fold_naive launch");
+    return GPFC_OK;
+}
+
+int32_t gpfc_batch_setup(gpfc_plan* p, const int64_t* soff, const int64_t* poff, int32_t n_curves) {
+    if (!p || !soff || !poff || n_curves < 0) return GPFC_EINVAL;
+    if (soff[0] != 0 || poff[0] != 0) return GPFC_EINVAL;
+    int64_t recs = 0, maxr = 0, items = 0;
+    std::vector<int64_t> roff(n_curves + 1);
+    std::vector<gpfc::BatchCurve> curves(n_curves);
+    roff[0] = 0;
+    for (int32_t c = 0; c < n_curves; ++c) {
+        const int64_t n = soff[c + 1] - soff[c];
+        const int64_t k = poff[c + 1] - poff[c];
+        if (n < 0 || k < 0) return GPFC_EINVAL;
+        if (n > GPFC_MAX_SAMPLES) return GPFC_ERANGE;
+        const int64_t r = gpfc::prepared_len(n);
+        curves[c] = gpfc::BatchCurve{recs, gpfc::slice_len(n), poff[c], k};
+        recs += r;
+        roff[c + 1] = recs;
+        maxr = r > maxr ? r : maxr;
+        items += (k + 63) / 64;
+    }
+    if (items > 0x7fffffffLL) return GPFC_ERANGE;
+    // Items, longest curve first (then curve, then block order).
+    std::vector<int2> it;
+    it.reserve((size_t)items);
+    std::vector<int32_t> order(n_curves);
+    for (int32_t c = 0; c < n_curves; ++c) order[c] = c;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return soff[a + 1] - soff[a] > soff[b + 1] - soff[b];
+    });
+    for (int32_t c : order)
+        for (int64_t j = 0; j < (curves[c].k + 63) / 64; ++j) it.push_back(make_int2(c, (int)j));
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return device_error(e, "hipSetDevice");
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t sz_off = al(sizeof(int64_t) * (n_curves + 1));
+    const size_t sz_cur = al(sizeof(gpfc::BatchCurve) * (n_curves > 0 ? n_curves : 1));
+    const size_t sz_it = al(sizeof(int2) * (items > 0 ? items : 1));
+    const size_t sz_ctr = 256;
+    const size_t sz_inf = al(sizeof(CurveInfo) * (n_curves > 0 ? n_curves : 1));
+    const size_t sz_rec = al(sizeof(gpfc::Rec) * (recs > 0 ? recs : 1));
+    const size_t total = 2 * sz_off + sz_cur + sz_it + sz_ctr + sz_inf + sz_rec;
+    if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
+    if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+    if (p->b_dev) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(p->b_dev);
+        p->b_dev = nullptr;
+    }
+    p->b_curves = -1;
+    e = hipMalloc(&p->b_dev, total);
+    if (e != hipSuccess) {
+        p->b_dev = nullptr;
+        return e == hipErrorOutOfMemory ? GPFC_ENOMEM : device_error(e, "hipMalloc");
+    }
+    char* base = (char*)p->b_dev;
+    p->b_soff = (int64_t*)base; base += sz_off;
+    p->b_roff = (int64_t*)base; base += sz_off;
+    p->b_curve = (gpfc::BatchCurve*)base; base += sz_cur;
+    p->b_item = (int2*)base; base += sz_it;
+    p->b_counter = (int32_t*)base; base += sz_ctr;
+    p->b_info = (CurveInfo*)base; base += sz_inf;
+    p->b_rec = (gpfc::Rec*)base;
+    e = hipMemcpy(p->b_soff, soff, sizeof(int64_t) * (n_curves + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->b_roff, roff.data(), sizeof(int64_t) * (n_curves + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess && n_curves > 0)
+        e = hipMemcpy(p->b_curve, curves.data(), sizeof(gpfc::BatchCurve) * n_curves, hipMemcpyHostToDevice);
+    if (e == hipSuccess && items > 0)
+        e = hipMemcpy(p->b_item, it.data(), sizeof(int2) * items, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return device_error(e, "batch table upload");
+    p->b_curves = n_curves;
+    p->b_samples = soff[n_curves];
+    p->b_periods = poff[n_curves];
+    p->b_records = recs;
+    p->b_max_records = maxr;
+    p->b_items = (int32_t)items;
+    return GPFC_OK;
+}
+
+static int32_t batch_enqueue(gpfc_plan* p, const double* t, const float* flux, const double* periods,
+                             int32_t nbins, float* snr, int32_t* start, int32_t* width, float* depth,
+                             uint16_t* zfold, hipStream_t s) {
+    hipError_t e = gpfc::launch_batch_prepare(t, flux, p->b_soff, p->b_roff, p->b_curves,
+                                              p->b_max_records, p->b_info, p->b_rec, s);
+    if (e != hipSuccess) return device_error(e, "batch prepare launch");
+    e = gpfc::launch_batch_fold_score(p->b_rec, p->b_curve, p->b_item, p->b_items, p->b_counter,
+                                      p->b_info, periods, nbins, plan_widths(p, nbins), p->n_cu, snr,
+                                      start, width, depth, zfold, s);
+    if (e != hipSuccess) return device_error(e, "batch fold_score launch");
+    return GPFC_OK;
+}
+
+static int32_t check_batch(const gpfc_plan* p, const void* t, const void* flux, const void* periods,
+                           int32_t nbins, const void* snr, const void* start, const void* width,
+                           const void* depth, const void* zfold) {
+    if (!p || p->b_curves < 0) return GPFC_EINVAL;
+    if (p->b_samples > 0 && (!t || !flux)) return GPFC_EINVAL;
+    if (p->b_periods > 0 && (!periods || !snr || !start || !width || !depth)) return GPFC_EINVAL;
+    if (nbins < 1) return GPFC_EINVAL;
+    if (!pow2_in_range(nbins)) return GPFC_ENOTSUP;
+    if (zfold && nbins < 16) return GPFC_ENOTSUP;
+    return GPFC_OK;
+}
+
+int32_t gpfc_batch_fold_score(gpfc_plan* p, const double* t, const float* flux, const double* periods,
+                              int32_t nbins, float* snr, int32_t* start, int32_t* width, float* depth,
+                              uint16_t* zfold, void* stream) {
+    int32_t rc = check_batch(p, t, flux, periods, nbins, snr, start, width, depth, zfold);
+    if (rc != GPFC_OK) return rc;
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return device_error(e, "hipSetDevice");
+    return batch_enqueue(p, t, flux, periods, nbins, snr, start, width, depth, zfold,
+                         (hipStream_t)stream);
+}
+
+int32_t gpfc_batch_capture(gpfc_plan* p, const double* t, const float* flux, const double* periods,
+                           int32_t nbins, float* snr, int32_t* start, int32_t* width, float* depth,
+                           uint16_t* zfold, void* stream) {
+    int32_t rc = check_batch(p, t, flux, periods, nbins, snr, start, width, depth, zfold);
+    if (rc != GPFC_OK) return rc;
+    if (!stream) return GPFC_EINVAL;   // the null stream cannot be captured
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return device_error(e, "hipSetDevice");
+    if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
+    if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+    hipStream_t s = (hipStream_t)stream;
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return device_error(e, "hipStreamBeginCapture");
+    rc = batch_enqueue(p, t, flux, periods, nbins, snr, start, width, depth, zfold, s);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s, &g);
+    if (rc != GPFC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return device_error(e, "hipStreamEndCapture");
+    p->graph = g;
+    e = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        p->graph_exec = nullptr;
+        return device_error(e, "hipGraphInstantiate");
+    }
+    return GPFC_OK;
+}
+
+int32_t gpfc_batch_replay(gpfc_plan* p, void* stream) {
+    if (!p || !p->graph_exec) return GPFC_EINVAL;
+    hipError_t e = hipGraphLaunch(p->graph_exec, (hipStream_t)stream);
+    if (e != hipSuccess) return device_error(e, "hipGraphLaunch");
+    return GPFC_OK;
+}
+
+int32_t gpfc_batch_curve_stats(gpfc_plan* p, gpfc_curve* out, void* stream) {
+    if (!p || p->b_curves < 0 || (p->b_curves > 0 && !out)) return GPFC_EINVAL;
+    std::vector<CurveInfo> ci(p->b_curves > 0 ? p->b_curves : 1);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (p->b_curves > 0)
+        e = hipMemcpyAsync(ci.data(), p->b_info, sizeof(CurveInfo) * p->b_curves,
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_error(e, "batch curve stats copy");
+    for (int32_t c = 0; c < p->b_curves; ++c) {
+        out[c].mean = ci[c].mean;
+        out[c].sigma = ci[c].sigma;
+        out[c].ref = ci[c].ref;
+        out[c].qscale = ci[c].qscale;
+        out[c].tmax = ci[c].tmax;
+        out[c].maxdev = ci[c].maxdev;
+        out[c].n = ci[c].n;
+        out[c].exact = ci[c].exact;
+        out[c].finite = ci[c].finite;
+    }
     return GPFC_OK;
 }
 

@@ -38,6 +38,15 @@ struct Rec {
     uint64_t c;
 };
 
+// One curve of a multi-curve batch: where its prepared records and periods
+// start, its per-wave slice length and its number of periods.
+struct BatchCurve {
+    int64_t rec_off;
+    int64_t per;
+    int64_t p_off;
+    int64_t k;
+};
+
 struct Widths {
     int32_t w[kMaxWidths];
     int32_t n;
@@ -48,6 +57,8 @@ hipError_t launch_curve_stats(const double* t, const float* flux, int64_t n, Cur
                               hipStream_t s);
 // Records the prepared curve of n samples occupies (padding included).
 int64_t prepared_len(int64_t n);
+// Records per wave slice of a prepared curve of n samples.
+int64_t slice_len(int64_t n);
 hipError_t launch_pack(const double* t, const float* flux, int64_t n, const CurveInfo* info,
                        Rec* rec, hipStream_t s);
 hipError_t launch_fold(const Rec* rec, int64_t n, const double* periods,
@@ -56,7 +67,16 @@ hipError_t launch_fold(const Rec* rec, int64_t n, const double* periods,
 hipError_t launch_fold_score(const Rec* rec, int64_t n,
                              const double* periods, int64_t k, int32_t nbins,
                              const CurveInfo* info, const Widths& widths, float* snr,
-                             int32_t* start, int32_t* width, float* depth, hipStream_t s);
+                             int32_t* start, int32_t* width, float* depth, uint16_t* zfold,
+                             hipStream_t s);
+hipError_t launch_batch_prepare(const double* t, const float* flux, const int64_t* soff,
+                                const int64_t* roff, int32_t n_curves, int64_t max_records,
+                                CurveInfo* infos, Rec* rec, hipStream_t s);
+hipError_t launch_batch_fold_score(const Rec* rec, const BatchCurve* curves, const int2* items,
+                                   int32_t n_items, int32_t* counter, const CurveInfo* infos,
+                                   const double* periods, int32_t nbins, const Widths& widths,
+                                   int32_t grid, float* snr, int32_t* start, int32_t* width,
+                                   float* depth, uint16_t* zfold, hipStream_t s);
 hipError_t launch_score(const double* sums, const int32_t* counts, int64_t k, int32_t nbins,
                         double sigma, const Widths& widths, float* snr, int32_t* start,
                         int32_t* width, float* depth, hipStream_t s);

@@ -51,9 +51,18 @@ __device__ __forceinline__ int wave_or_i(int v) {
 // 2^e is the ulp of the smallest-magnitude flux, so flux - ref is an exact
 // integer multiple of it whenever that integer stays below 2^27; otherwise a
 // coarser unit with 2^27 of headroom is used and the sums are rounded.
+//
+// Block c handles curve c: samples [soff[c], soff[c+1]) (or [0, n1) when soff
+// is null), result in info[c].
 __global__ __launch_bounds__(1024) void k_curve_stats(const double* __restrict__ t,
-                                                      const float* __restrict__ flux, int64_t n,
+                                                      const float* __restrict__ flux,
+                                                      const int64_t* __restrict__ soff, int64_t n1,
                                                       CurveInfo* __restrict__ info) {
+    const int64_t i0 = soff ? soff[blockIdx.x] : 0;
+    const int64_t n = soff ? soff[blockIdx.x + 1] - i0 : n1;
+    t += i0;
+    flux += i0;
+    info += blockIdx.x;
     __shared__ double sd[16];
     __shared__ double sd2[16];
     __shared__ int si[16];
@@ -121,11 +130,24 @@ __global__ __launch_bounds__(1024) void k_curve_stats(const double* __restrict__
 // Prepared curve: record i = {t_i, (1 << 46) + (q_i + 2^27)} with
 // q_i = RN((flux_i - ref) / 2^e) clamped to [-2^27, 2^27]. Records from n up
 // to `total` are {0, 0}: they add nothing to any bin, so folds can run over
-// whole blocks of records without a tail.
+// whole blocks of records without a tail. Block row y handles curve y:
+// samples [soff[y], soff[y+1]) into records [roff[y], roff[y+1]) (one curve
+// of n1 samples and total1 records when soff is null).
 __global__ __launch_bounds__(256) void k_pack(const double* __restrict__ t,
-                                              const float* __restrict__ flux, int64_t n,
-                                              int64_t total, const CurveInfo* __restrict__ info,
+                                              const float* __restrict__ flux,
+                                              const int64_t* __restrict__ soff, int64_t n1,
+                                              const int64_t* __restrict__ roff, int64_t total1,
+                                              const CurveInfo* __restrict__ info,
                                               Rec* __restrict__ rec) {
+    const int c = blockIdx.y;
+    const int64_t i0 = soff ? soff[c] : 0;
+    const int64_t n = soff ? soff[c + 1] - i0 : n1;
+    const int64_t r0 = soff ? roff[c] : 0;
+    const int64_t total = soff ? roff[c + 1] - r0 : total1;
+    t += i0;
+    flux += i0;
+    rec += r0;
+    info += c;
     const double ref = info->ref;
     const int e = info->e;
     const double lim = (double)kBias;
@@ -501,17 +523,28 @@ __device__ void score_table(const char* tab, int nb, int g, const Widths& W, Sco
     width[kk] = o_w;
 }
 
-__global__ __launch_bounds__(kThreads, 1) void k_fold_score(
-    const Rec* __restrict__ rec, int64_t per,
-    const double* __restrict__ periods, int64_t k, int32_t log2g,
-    const CurveInfo* __restrict__ info, Widths W, float* __restrict__ snr,
-    int32_t* __restrict__ start, int32_t* __restrict__ width, float* __restrict__ depth) {
-    __shared__ __attribute__((aligned(16))) char hist[kFineBins * 64 * 8];
-    __shared__ uint64_t chunk[kWaves * 64];
-    __shared__ ScoreShared sh;
+// Round to nearest even bfloat16 (finite inputs).
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// Fold + score of one block of 64 periods of one prepared curve (periods
+// kbase .. kbase+63 of the curve's k). Outputs are indexed by the curve's
+// period index. zfold (optional, nb >= 16): the folded curve of each period as
+// bfloat16 z-scores over its non-empty bins (bin means minus their mean, over
+// their std with ddof 0; empty bins and zero spread give 0) - the input the
+// learned scorer takes.
+__device__ void fold_score_body(char* hist, uint64_t* chunk, ScoreShared& sh,
+                                const Rec* __restrict__ rec, int64_t per,
+                                const CurveInfo* __restrict__ info,
+                                const double* __restrict__ periods, int64_t k, int64_t kbase,
+                                int32_t log2g, const Widths& W, float* snr, int32_t* start,
+                                int32_t* width, float* depth, uint16_t* zfold) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t kk = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t kk = kbase + lane;
     const LaneSetup L = lane_setup(periods, kk, k, info->tmax);
     fold_block(hist, rec, per, L, lane, wave);
 
@@ -531,16 +564,23 @@ __global__ __launch_bounds__(kThreads, 1) void k_fold_score(
         off += w < wave ? v : 0;
         all += v;
     }
+    __syncthreads();   // chunk is reused below
     const double qs = info->qscale;
     uint32_t call;
     double dall;
     decode(all, qs, call, dall);
     const float nf = L.valid ? (float)call : 0.0f;
-    // Convert to the float prefix table and count non-empty coarse bins
-    // (coarse bins of g <= 16 rows never straddle two waves' rows).
+    // Convert to the float prefix table, count non-empty coarse bins and sum
+    // the bin means (coarse bins of g <= 16 rows never straddle two waves).
     const int g = 1 << log2g;
     uint32_t cprev = (uint32_t)(off >> kCountShift);
+    double dprev;
+    {
+        uint32_t c0;
+        decode(off, qs, c0, dprev);
+    }
     int nzl = 0;
+    float zs = 0.0f, zq = 0.0f;
     for (int r = r0; r < r0 + kRowsPerWave; ++r) {
         char* p = hist + hist_off(r, lane);
         const uint64_t v = *reinterpret_cast<uint64_t*>(p) + off;
@@ -548,14 +588,22 @@ __global__ __launch_bounds__(kThreads, 1) void k_fold_score(
         double d;
         decode(v, qs, c, d);
         if (((r + 1) & (g - 1)) == 0) {
-            nzl += c > cprev;
+            if (c > cprev) {
+                const float m = (float)((d - dprev) / (double)(c - cprev));
+                ++nzl;
+                zs += m;
+                zq += m * m;
+            }
             cprev = c;
+            dprev = d;
         }
         Slot sl{(float)c, (float)((double)nf * d)};
         if (!L.valid) sl = Slot{0.0f, 0.0f};
         *reinterpret_cast<Slot*>(p) = sl;
     }
     sh.nzc[wave * 64 + lane] = nzl;
+    float2* zpart = reinterpret_cast<float2*>(chunk);
+    zpart[wave * 64 + lane] = make_float2(zs, zq);
     if (wave == 0) {
         sh.nrow[lane] = nf;
         sh.Srow[lane] = L.valid ? dall : 0.0;
@@ -566,10 +614,81 @@ __global__ __launch_bounds__(kThreads, 1) void k_fold_score(
         for (int w = 0; w < kWaves; ++w) nz += sh.nzc[w * 64 + lane];
         sh.nz[lane] = nz;
     }
-    __syncthreads();
     const int nb = kFineBins >> log2g;
+    if (zfold && g <= kRowsPerWave && kk < k) {
+        int nz = 0;
+        float s1 = 0.0f, s2 = 0.0f;
+        for (int w = 0; w < kWaves; ++w) {
+            nz += sh.nzc[w * 64 + lane];
+            const float2 zp = zpart[w * 64 + lane];
+            s1 += zp.x;
+            s2 += zp.y;
+        }
+        const float mu = nz ? s1 / (float)nz : 0.0f;
+        const float var = nz ? fmaxf(s2 / (float)nz - mu * mu, 0.0f) : 0.0f;
+        const float inv = var > 0.0f ? 1.0f / sqrtf(var) : 0.0f;
+        uint16_t* zrow = zfold + kk * nb;
+        const int b0 = r0 >> log2g, b1 = (r0 + kRowsPerWave) >> log2g;
+        for (int b = b0; b < b1; ++b) {
+            const Slot e = slot_at(hist, (b + 1) * g - 1, lane);
+            const Slot a = b ? slot_at(hist, b * g - 1, lane) : Slot{0.0f, 0.0f};
+            const float cb = e.c - a.c;
+            float z = 0.0f;
+            if (cb > 0.5f && L.valid) z = ((e.dn - a.dn) / (nf * cb) - mu) * inv;
+            zrow[b] = bf16_rne(z);
+        }
+    }
+    __syncthreads();
     score_table(hist, nb, g, W, sh, info->sigma, L.valid, kk, k, lane, wave, snr, start, width,
                 depth);
+}
+
+__global__ __launch_bounds__(kThreads, 1) void k_fold_score(
+    const Rec* __restrict__ rec, int64_t per,
+    const double* __restrict__ periods, int64_t k, int32_t log2g,
+    const CurveInfo* __restrict__ info, Widths W, float* __restrict__ snr,
+    int32_t* __restrict__ start, int32_t* __restrict__ width, float* __restrict__ depth,
+    uint16_t* __restrict__ zfold) {
+    __shared__ __attribute__((aligned(16))) char hist[kFineBins * 64 * 8];
+    __shared__ uint64_t chunk[kWaves * 64];
+    __shared__ ScoreShared sh;
+    fold_score_body(hist, chunk, sh, rec, per, info, periods, k, (int64_t)blockIdx.x * 64, log2g, W,
+                    snr, start, width, depth, zfold);
+}
+
+// Persistent multi-curve fold + score: one block per CU pulls work items
+// (curve, block of 64 of its periods) from a device counter until none are
+// left; items are ordered longest curve first. Every block reaches the exit
+// test on each round, so the grid drains.
+__global__ __launch_bounds__(kThreads, 1) void k_batch_fold_score(
+    const Rec* __restrict__ rec, const BatchCurve* __restrict__ curves,
+    const int2* __restrict__ items, int32_t n_items, int32_t* __restrict__ counter,
+    const CurveInfo* __restrict__ infos, const double* __restrict__ periods, int32_t log2g,
+    Widths W, float* __restrict__ snr, int32_t* __restrict__ start, int32_t* __restrict__ width,
+    float* __restrict__ depth, uint16_t* __restrict__ zfold) {
+    __shared__ __attribute__((aligned(16))) char hist[kFineBins * 64 * 8];
+    __shared__ uint64_t chunk[kWaves * 64];
+    __shared__ ScoreShared sh;
+    __shared__ int32_t cur_item;
+    const int nb = kFineBins >> log2g;
+    for (;;) {
+        if (threadIdx.x == 0) cur_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int32_t it = cur_item;
+        __syncthreads();
+        if (it >= n_items) break;
+        const int2 item = items[it];
+        const BatchCurve bc = curves[item.x];
+        fold_score_body(hist, chunk, sh, rec + bc.rec_off, bc.per, infos + item.x,
+                        periods + bc.p_off, bc.k, (int64_t)item.y * 64, log2g, W, snr + bc.p_off,
+                        start + bc.p_off, width + bc.p_off, depth + bc.p_off,
+                        zfold ? zfold + bc.p_off * nb : nullptr);
+        __syncthreads();
+    }
+}
+
+__global__ void k_set_i32(int32_t* __restrict__ p, int32_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
 // Box-SNR of materialised folds: lane j owns row blockIdx*64 + j; the waves
@@ -674,7 +793,8 @@ __global__ __launch_bounds__(256) void k_fold_naive(const double* __restrict__ t
 
 hipError_t launch_curve_stats(const double* t, const float* flux, int64_t n, CurveInfo* info,
                               hipStream_t s) {
-    hipLaunchKernelGGL(k_curve_stats, dim3(1), dim3(1024), 0, s, t, flux, n, info);
+    hipLaunchKernelGGL(k_curve_stats, dim3(1), dim3(1024), 0, s, t, flux, (const int64_t*)nullptr,
+                       n, info);
     return hipGetLastError();
 }
 
@@ -686,11 +806,14 @@ int64_t fold_slice_len(int64_t n) {
 
 int64_t prepared_len(int64_t n) { return fold_slice_len(n) * kWaves + 2 * kBlk; }
 
+int64_t slice_len(int64_t n) { return fold_slice_len(n); }
+
 hipError_t launch_pack(const double* t, const float* flux, int64_t n, const CurveInfo* info,
                        Rec* rec, hipStream_t s) {
     const int64_t total = prepared_len(n);
     const int64_t blocks = std::min<int64_t>((total + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_pack, dim3((unsigned)blocks), dim3(256), 0, s, t, flux, n, total, info, rec);
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)blocks), dim3(256), 0, s, t, flux,
+                       (const int64_t*)nullptr, n, (const int64_t*)nullptr, total, info, rec);
     return hipGetLastError();
 }
 
@@ -713,11 +836,37 @@ hipError_t launch_fold(const Rec* rec, int64_t n, const double* periods,
 hipError_t launch_fold_score(const Rec* rec, int64_t n,
                              const double* periods, int64_t k, int32_t nbins,
                              const CurveInfo* info, const Widths& widths, float* snr,
-                             int32_t* start, int32_t* width, float* depth, hipStream_t s) {
+                             int32_t* start, int32_t* width, float* depth, uint16_t* zfold,
+                             hipStream_t s) {
     if (k == 0) return hipSuccess;
     const int64_t blocks = (k + 63) / 64;
     hipLaunchKernelGGL(k_fold_score, dim3((unsigned)blocks), dim3(kThreads), 0, s, rec, fold_slice_len(n),
-                       periods, k, 8 - log2_of(nbins), info, widths, snr, start, width, depth);
+                       periods, k, 8 - log2_of(nbins), info, widths, snr, start, width, depth, zfold);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_prepare(const double* t, const float* flux, const int64_t* soff,
+                                const int64_t* roff, int32_t n_curves, int64_t max_records,
+                                CurveInfo* infos, Rec* rec, hipStream_t s) {
+    if (n_curves == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_curve_stats, dim3((unsigned)n_curves), dim3(1024), 0, s, t, flux, soff,
+                       (int64_t)0, infos);
+    const int64_t bx = std::min<int64_t>((max_records + 255) / 256, 64);
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)bx, (unsigned)n_curves), dim3(256), 0, s, t, flux, soff,
+                       (int64_t)0, roff, (int64_t)0, infos, rec);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_fold_score(const Rec* rec, const BatchCurve* curves, const int2* items,
+                                   int32_t n_items, int32_t* counter, const CurveInfo* infos,
+                                   const double* periods, int32_t nbins, const Widths& widths,
+                                   int32_t grid, float* snr, int32_t* start, int32_t* width,
+                                   float* depth, uint16_t* zfold, hipStream_t s) {
+    if (n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(64), 0, s, counter, 0);
+    hipLaunchKernelGGL(k_batch_fold_score, dim3((unsigned)std::min(grid, n_items)), dim3(kThreads), 0,
+                       s, rec, curves, items, n_items, counter, infos, periods, 8 - log2_of(nbins),
+                       widths, snr, start, width, depth, zfold);
     return hipGetLastError();
 }
 

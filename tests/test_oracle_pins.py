@@ -387,3 +387,26 @@ def test_widths_not_below_nbins_are_skipped():
     b = oracle.score(counts, dsums, 1e-3, widths=np.array([2]))
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+def test_normalize_properties():
+    # Non-empty bins get mean 0 and std 1 (ddof 0); empty bins 0; an affine
+    # map of the flux with positive gain leaves z unchanged; a flat fold gives 0.
+    c = synth.plain_curve(seed=1004)
+    periods = synth.freq_grid(1.0, 5.0, 30)
+    m = 200
+    sums, _, counts = oracle.fold(c.t[:m], c.flux[:m], periods, 256)
+    z = oracle.normalize(sums, counts)
+    assert (counts == 0).any()
+    for r in range(z.shape[0]):
+        ne = counts[r] > 0
+        assert (z[r][~ne] == 0).all()
+        assert abs(z[r][ne].mean()) < 1e-12 and abs(z[r][ne].std() - 1) < 1e-12
+    f2 = (3.0 + 2.0 * (c.flux[:m].astype(np.float64) - 1.0))
+    s2 = np.zeros_like(sums)
+    for r, p in enumerate(periods):
+        for ti, fi in zip(c.t[:m], f2):
+            s2[r, oracle.phase_bin(ti, p, 256)] += fi
+    z2 = oracle.normalize(s2, counts)
+    np.testing.assert_allclose(z2, z, atol=1e-9)
+    assert (oracle.normalize(np.ones((1, 8)), np.ones((1, 8), np.int32)) == 0).all()
