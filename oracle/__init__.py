@@ -20,6 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gpfc_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "cnn_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -29,7 +30,7 @@ CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-s
 def build() -> str:
     """Compile the oracle with gcc (always recompiles)."""
     tmp = _LIB + ".tmp"
-    subprocess.run(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"], check=True)
+    subprocess.run(["gcc", *CFLAGS, "-o", tmp, *_SRCS, "-lm"], check=True)
     os.replace(tmp, _LIB)
     return _LIB
 
@@ -38,7 +39,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS):
         build()
     lib = ctypes.CDLL(_LIB)
     dp = ctypes.POINTER(ctypes.c_double)
@@ -62,6 +63,19 @@ def _load():
     lib.oracle_box_snr.restype = ctypes.c_double
     lib.oracle_normalize.argtypes = [dp, ip, i64, i32, dp]
     lib.oracle_normalize.restype = None
+    lib.oracle_cnn_nparams.argtypes = []
+    lib.oracle_cnn_nparams.restype = i64
+    lib.oracle_conv1d_circ.argtypes = [dp, dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+    lib.oracle_conv1d_circ.restype = None
+    lib.oracle_maxpool2.argtypes = [dp, ctypes.c_int, dp, ip]
+    lib.oracle_maxpool2.restype = None
+    lib.oracle_cnn_forward.argtypes = [dp, dp, ctypes.c_int, dp]
+    lib.oracle_cnn_forward.restype = None
+    lib.oracle_cnn_loss_grad.argtypes = [dp, dp, dp, ctypes.c_int, dp]
+    lib.oracle_cnn_loss_grad.restype = ctypes.c_double
+    lib.oracle_adam.argtypes = [dp, dp, dp, dp, i64, i64, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_double]
+    lib.oracle_adam.restype = None
     lib.oracle_grid_size.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
     lib.oracle_grid_size.restype = ctypes.c_double
     _lib = lib
@@ -197,3 +211,69 @@ def fold_score(t, flux, periods, nbins, widths=None, nthreads=1):
     snr, start, width, depth = score(counts, dsums, sigma, widths)
     return dict(mean=mean, sigma=sigma, sums=sums, dsums=dsums, counts=counts,
                 snr=snr, start=start, width=width, depth=depth)
+
+
+# ---------------------------------------------------------------- learned scorer (Sec. 2.5)
+
+def cnn_nparams() -> int:
+    return int(_load().oracle_cnn_nparams())
+
+
+def conv1d_circ(x, w, b):
+    """Circular conv1d, padding 2 by wrap-around: x [B][Cin][L], w [Cout][Cin][5], b [Cout]."""
+    lib = _load()
+    x = _f64(x)
+    w = _f64(w)
+    b = _f64(b)
+    B, Cin, L = x.shape
+    Cout = w.shape[0]
+    y = np.empty((B, Cout, L))
+    lib.oracle_conv1d_circ(_p(x, ctypes.c_double), _p(w, ctypes.c_double), _p(b, ctypes.c_double),
+                           B, Cin, Cout, L, _p(y, ctypes.c_double))
+    return y
+
+
+def maxpool2(r):
+    """Max-pool by 2 with the winner index (first on a tie)."""
+    lib = _load()
+    r = _f64(r)
+    out = np.empty(r.size // 2)
+    idx = np.empty(r.size // 2, np.int32)
+    lib.oracle_maxpool2(_p(r, ctypes.c_double), out.size, _p(out, ctypes.c_double),
+                        _p(idx, ctypes.c_int32))
+    return out, idx
+
+
+def cnn_forward(params, x):
+    """Logits of the network for inputs x [B][256] (FP64)."""
+    lib = _load()
+    params = _f64(params)
+    x = _f64(x)
+    B = x.shape[0]
+    out = np.empty(B)
+    lib.oracle_cnn_forward(_p(params, ctypes.c_double), _p(x, ctypes.c_double), B,
+                           _p(out, ctypes.c_double))
+    return out
+
+
+def cnn_loss_grad(params, x, y):
+    """(mean BCE-with-logits loss, gradient [312449]) for inputs x [B][256], labels y [B]."""
+    lib = _load()
+    params = _f64(params)
+    x = _f64(x)
+    y = _f64(y)
+    g = np.empty(params.size)
+    loss = lib.oracle_cnn_loss_grad(_p(params, ctypes.c_double), _p(x, ctypes.c_double),
+                                    _p(y, ctypes.c_double), x.shape[0], _p(g, ctypes.c_double))
+    return loss, g
+
+
+def adam(p, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One bias-corrected Adam step in place on p, m, v (FP64 arrays)."""
+    lib = _load()
+    for a in (p, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _f64(g)
+    lib.oracle_adam(_p(p, ctypes.c_double), _p(g, ctypes.c_double), _p(m, ctypes.c_double),
+                    _p(v, ctypes.c_double), p.size, int(step), float(lr), float(b1), float(b2),
+                    float(eps))

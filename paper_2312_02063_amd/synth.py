@@ -205,3 +205,29 @@ def training_curve(rng: np.random.Generator, n: int = 4000, positive: bool = Tru
         f = f + trapezoid(t, period, epoch, dur, d, r)
         truth.update(period=period, epoch=epoch, duration=dur, depth=d, alpha=a, ratio=r)
     return Curve(t, f.astype(np.float32), truth)
+
+
+# Learned-scorer parameter layout (canonical): per conv block l weight
+# [Cout][Cin][5] then bias; fc weights [out][in] then bias.
+CNN_LAYERS = [("conv", 1, 16), ("conv", 16, 32), ("conv", 32, 64), ("conv", 64, 64),
+              ("fc", 1024, 256), ("fc", 256, 64), ("fc", 64, 1)]
+
+
+def cnn_param_shapes():
+    shapes = []
+    for kind, cin, cout in CNN_LAYERS:
+        shapes.append((cout, cin, 5) if kind == "conv" else (cout, cin))
+        shapes.append((cout,))
+    return shapes
+
+
+def cnn_init(seed: int = 1003) -> np.ndarray:
+    """He-normal initial weights (std sqrt(2 / fan_in)), zero biases, float64."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for kind, cin, cout in CNN_LAYERS:
+        fan_in = cin * 5 if kind == "conv" else cin
+        shape = (cout, cin, 5) if kind == "conv" else (cout, cin)
+        parts.append(rng.normal(0.0, np.sqrt(2.0 / fan_in), size=shape).ravel())
+        parts.append(np.zeros(cout))
+    return np.concatenate(parts)
