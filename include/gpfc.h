@@ -211,6 +211,57 @@ int32_t gpfc_fold_naive(gpfc_plan *plan, const double *t, const float *flux, int
                         const double *periods, int64_t k, int32_t nbins, double *sums,
                         int32_t *counts, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Learned scorer (Sec. 2.5: a convolutional network scores each noise-
+ * normalised fold; cross-entropy, Adam). Network: 4 x [circular conv1d,
+ * kernel 5, padding 2 by wrap-around -> ReLU -> max-pool 2] with
+ * 1->16->32->64->64 channels over 256 positions, then fully connected
+ * 1024->256->64->1 with ReLU between and a sigmoid output.
+ * Parameters (FP32, 312,449 values) in the canonical layout: conv l weight
+ * [Cout][Cin][5] then bias, l = 1..4; fc weight [out][in] then bias for
+ * 1024->256, 256->64, 64->1; the flatten after block 4 is channel-major
+ * (channel * 16 + position). Inputs x are [B][256] normalised folds, either
+ * bfloat16 bits (x_f32 = 0, as gpfc_fold_score_prepared's zfold) or FP32.
+ * GPFC_CNN_BF16 runs convolutions 2-4 and the first two fully connected
+ * layers on bf16 matrix cores with FP32 accumulation; GPFC_CNN_FP32 runs them
+ * in FP32 (for checking). Master weights, gradients and Adam moments are
+ * always FP32. All pointers are device pointers.
+ * ------------------------------------------------------------------------ */
+#define GPFC_CNN_BF16 0
+#define GPFC_CNN_FP32 1
+
+typedef struct gpfc_cnn gpfc_cnn;
+
+/* Number of parameters (312,449). */
+int32_t gpfc_cnn_nparams(void);
+
+/* Text of the last GPFC_EDEVICE of a gpfc_cnn_* call on this thread. */
+const char *gpfc_cnn_last_error(void);
+
+/* Create a network on `device` with activation buffers for up to max_batch inputs. */
+int32_t gpfc_cnn_create(gpfc_cnn **out, int32_t device, int32_t precision, int64_t max_batch);
+int32_t gpfc_cnn_destroy(gpfc_cnn *cnn);
+
+/* Copy params f32[nparams] in; resets the Adam moments and step count. */
+int32_t gpfc_cnn_set_params(gpfc_cnn *cnn, const float *params, void *stream);
+/* Copy the current parameters out to f32[nparams]. */
+int32_t gpfc_cnn_get_params(gpfc_cnn *cnn, float *out, void *stream);
+
+/* Logits f32[B] (sigmoid of a logit is the transit score). B <= max_batch. */
+int32_t gpfc_cnn_forward(gpfc_cnn *cnn, const void *x, int32_t x_f32, int64_t B, float *logits,
+                         void *stream);
+
+/*
+ * Mean binary cross-entropy with logits against labels f32[B] (1 = transit)
+ * and its gradient, kept in the network for gpfc_cnn_adam; also copied to
+ * loss_out (f32[1]) and grad_out (f32[nparams]) when they are not NULL.
+ */
+int32_t gpfc_cnn_backward(gpfc_cnn *cnn, const void *x, int32_t x_f32, const float *labels,
+                          int64_t B, float *loss_out, float *grad_out, void *stream);
+
+/* One bias-corrected Adam step on the FP32 masters with the last gradient. */
+int32_t gpfc_cnn_adam(gpfc_cnn *cnn, float lr, float beta1, float beta2, float eps, void *stream);
+
 /* hipStreamSynchronize(stream); reports an asynchronous device error. */
 int32_t gpfc_sync(void *stream);
 

@@ -27,7 +27,8 @@ class GpfcError(RuntimeError):
         lib = load()
         msg = lib.gpfc_strerror(code).decode()
         if code == EDEVICE:
-            msg += ": " + lib.gpfc_last_error().decode()
+            err = (lib.gpfc_cnn_last_error() if what.startswith("gpfc_cnn") else lib.gpfc_last_error())
+            msg += ": " + err.decode()
         super().__init__(f"{what}: {msg} ({code})")
         self.code = code
 
@@ -72,6 +73,15 @@ def load():
         "gpfc_batch_replay": ([vp, vp], i32),
         "gpfc_batch_curve_stats": ([vp, ctypes.POINTER(Curve), vp], i32),
         "gpfc_sync": ([vp], i32),
+        "gpfc_cnn_nparams": ([], i32),
+        "gpfc_cnn_last_error": ([], ctypes.c_char_p),
+        "gpfc_cnn_create": ([ctypes.POINTER(vp), i32, i32, i64], i32),
+        "gpfc_cnn_destroy": ([vp], i32),
+        "gpfc_cnn_set_params": ([vp, vp, vp], i32),
+        "gpfc_cnn_get_params": ([vp, vp, vp], i32),
+        "gpfc_cnn_forward": ([vp, vp, i32, i64, vp, vp], i32),
+        "gpfc_cnn_backward": ([vp, vp, i32, vp, i64, vp, vp, vp], i32),
+        "gpfc_cnn_adam": ([vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -88,7 +98,9 @@ def exported_symbols():
             "gpfc_score", "gpfc_fold_score", "gpfc_fold_naive", "gpfc_sync", "gpfc_prepare",
             "gpfc_fold_prepared", "gpfc_fold_score_prepared", "gpfc_batch_setup",
             "gpfc_batch_fold_score", "gpfc_batch_capture", "gpfc_batch_replay",
-            "gpfc_batch_curve_stats"]
+            "gpfc_batch_curve_stats", "gpfc_cnn_nparams", "gpfc_cnn_last_error",
+            "gpfc_cnn_create", "gpfc_cnn_destroy", "gpfc_cnn_set_params", "gpfc_cnn_get_params",
+            "gpfc_cnn_forward", "gpfc_cnn_backward", "gpfc_cnn_adam"]
 
 
 def _check(rc, what):
@@ -311,3 +323,86 @@ class Plan:
 
     def sync(self):
         _check(self.lib.gpfc_sync(_stream()), "gpfc_sync")
+
+
+CNN_BF16, CNN_FP32 = 0, 1
+
+
+class Cnn:
+    """The learned scorer on one GPU (gpfc_cnn_*): FP32 master weights,
+    bf16 (or FP32) matrix-core forward and backward, Adam."""
+
+    def __init__(self, device: int = 0, precision: int = CNN_BF16, max_batch: int = 4096):
+        import torch
+        self.lib = load()
+        self.device = torch.device("cuda", device)
+        self.max_batch = max_batch
+        self.n_params = int(self.lib.gpfc_cnn_nparams())
+        h = ctypes.c_void_p()
+        _check(self.lib.gpfc_cnn_create(ctypes.byref(h), device, precision, max_batch), "gpfc_cnn_create")
+        self.h = h
+        self._loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.gpfc_cnn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        import torch
+        p = torch.as_tensor(params, dtype=torch.float32, device=self.device).contiguous()
+        if p.numel() != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters")
+        _check(self.lib.gpfc_cnn_set_params(self.h, _ptr(p), _stream()), "gpfc_cnn_set_params")
+        torch.cuda.current_stream().synchronize()
+
+    def get_params(self):
+        import torch
+        out = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        _check(self.lib.gpfc_cnn_get_params(self.h, _ptr(out), _stream()), "gpfc_cnn_get_params")
+        return out
+
+    def _x(self, x):
+        import torch
+        if x.dtype == torch.uint16:
+            return 0
+        if x.dtype == torch.float32:
+            return 1
+        raise TypeError("x must be uint16 (bfloat16 bits) or float32")
+
+    def forward(self, x, out=None):
+        """Logits f32[B] for x [B][256]."""
+        import torch
+        xf = self._x(x)
+        _need(x, x.dtype, "x", self.device)
+        B = x.shape[0]
+        logits = out if out is not None else torch.empty(B, dtype=torch.float32, device=self.device)
+        _check(self.lib.gpfc_cnn_forward(self.h, _ptr(x), xf, B, _ptr(logits), _stream()),
+               "gpfc_cnn_forward")
+        return logits
+
+    def backward(self, x, labels, grad_out=None):
+        """Mean BCE loss (device tensor [1]); the gradient stays in the network
+        (also copied to grad_out if given)."""
+        import torch
+        xf = self._x(x)
+        _need(x, x.dtype, "x", self.device)
+        _need(labels, torch.float32, "labels", self.device)
+        _check(self.lib.gpfc_cnn_backward(self.h, _ptr(x), xf, _ptr(labels), x.shape[0],
+                                          _ptr(self._loss), _ptr(grad_out), _stream()),
+               "gpfc_cnn_backward")
+        return self._loss
+
+    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        _check(self.lib.gpfc_cnn_adam(self.h, lr, beta1, beta2, eps, _stream()), "gpfc_cnn_adam")
+
+    def train_step(self, x, labels, lr: float):
+        loss = self.backward(x, labels)
+        self.adam(lr)
+        return loss

@@ -1,0 +1,780 @@
+// Learned scorer on gfx950: a 1-D CNN over noise-normalised folds (Sec. 2.5
+// describes the paper's network: circular convolutions, max-pooling, fully
+// connected ReLU layers, sigmoid output, cross-entropy, Adam). Layers here:
+// 4 x [circular conv1d k5 -> ReLU -> max-pool 2] with 1->16->32->64->64
+// channels over 256 positions, fully connected 1024->256->64->1, sigmoid.
+//
+// Convolutions 2-4 and the first two fully connected layers run as GEMMs on
+// the matrix cores (v_mfma_f32_16x16x32_bf16 with FP32 accumulation, or
+// v_mfma_f32_16x16x4_f32 in the FP32 mode); a convolution is an implicit
+// GEMM whose operand loader gathers the five circularly shifted input rows.
+// Activations are channels-last ([batch][position][channel]) so one lane
+// fetches 8 consecutive channels at one position with a 16-byte load.
+// Master weights, gradients and Adam moments are FP32 in the canonical
+// layout (conv [Cout][Cin][5], fc [out][in], the flatten after block 4
+// channel-major); the GEMMs read packed working copies.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+
+#include <new>
+
+#include "../../include/gpfc.h"
+
+namespace gcnn {
+
+constexpr int kNP = 312449;
+constexpr int CH[5] = {1, 16, 32, 64, 64};
+constexpr int LEN[5] = {256, 128, 64, 32, 16};
+constexpr int64_t kConvW[5] = {0, 0, 96, 2688, 12992};
+constexpr int64_t conv_b(int l) { return kConvW[l] + (int64_t)CH[l] * CH[l - 1] * 5; }
+constexpr int64_t F1W = 33536, F1B = 295680, F2W = 295936, F2B = 312320, F3W = 312384, F3B = 312448;
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);   // NaN stays NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// Element types of the working copies and activations.
+struct BF16 {
+    using T = uint16_t;
+    static constexpr int KSTEP = 32;   // K per MFMA
+    static __device__ __forceinline__ float to_f(T v) { return bf2f(v); }
+    static __device__ __forceinline__ T from_f(float v) { return f2bf(v); }
+};
+struct F32 {
+    using T = float;
+    static constexpr int KSTEP = 4;
+    static __device__ __forceinline__ float to_f(T v) { return v; }
+    static __device__ __forceinline__ T from_f(float v) { return v; }
+};
+
+// ------------------------------------------------------------------ generic MFMA GEMM
+//
+// C[m][n] = sum_k A(m, k) * B(n, k); A and B are given by loaders that fill
+// a lane's fragment: for bf16, 8 values at k .. k+7 of one row; for f32, one
+// value. One wave computes a 32 x 32 tile (2 x 2 MFMA accumulators), four
+// waves a 64 x 64 tile. The epilogue receives (m, n, acc) for every element
+// of the tile inside [0, M) x [0, N).
+
+template <class P, class LA, class LB, class EP>
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, LA la, LB lb, EP ep) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int m0 = blockIdx.x * 64 + (wave & 1) * 32;
+    const int n0 = blockIdx.y * 64 + (wave >> 1) * 32;
+    const int r = lane & 15;
+    const int q = lane >> 4;
+    f32x4 acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < K; k0 += P::KSTEP) {
+        if constexpr (P::KSTEP == 32) {
+            const int kk = k0 + q * 8;
+            bf16x8 a[2], b[2];
+            for (int i = 0; i < 2; ++i) a[i] = la.frag8(m0 + i * 16 + r, kk);
+            for (int j = 0; j < 2; ++j) b[j] = lb.frag8(n0 + j * 16 + r, kk);
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        } else {
+            const int kk = k0 + q;
+            float a[2], b[2];
+            for (int i = 0; i < 2; ++i) a[i] = la.frag1(m0 + i * 16 + r, kk);
+            for (int j = 0; j < 2; ++j) b[j] = lb.frag1(n0 + j * 16 + r, kk);
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            const int n = n0 + j * 16 + r;
+            const int mb = m0 + i * 16 + q * 4;
+            ep(mb, n, acc[i][j], M, N);
+        }
+}
+
+// Loader helpers: a row of `ld` elements of type T at p, k-range checked.
+template <class P>
+struct Rows {
+    using T = typename P::T;
+    const T* p;
+    int rows, ld, K;
+    __device__ __forceinline__ bf16x8 frag8(int m, int k) const {
+        bf16x8 v;
+        if (m < rows && k + 8 <= K) {
+            v = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const uint16_t*>(p) + (int64_t)m * ld + k);
+        } else {
+            for (int j = 0; j < 8; ++j) {
+                uint16_t h = (m < rows && k + j < K) ? reinterpret_cast<const uint16_t*>(p)[(int64_t)m * ld + k + j] : 0;
+                v[j] = __builtin_bit_cast(__bf16, h);
+            }
+        }
+        return v;
+    }
+    __device__ __forceinline__ float frag1(int m, int k) const {
+        return (m < rows && k < K) ? P::to_f(p[(int64_t)m * ld + k]) : 0.0f;
+    }
+};
+
+// Strided operand: element (m, k) at p[k * ld + m] (k-major storage).
+template <class P>
+struct Cols {
+    using T = typename P::T;
+    const T* p;
+    int rows, ld, K;
+    __device__ __forceinline__ bf16x8 frag8(int m, int k) const {
+        bf16x8 v;
+        for (int j = 0; j < 8; ++j) {
+            uint16_t h = (m < rows && k + j < K) ? reinterpret_cast<const uint16_t*>(p)[(int64_t)(k + j) * ld + m] : 0;
+            v[j] = __builtin_bit_cast(__bf16, h);
+        }
+        return v;
+    }
+    __device__ __forceinline__ float frag1(int m, int k) const {
+        return (m < rows && k < K) ? P::to_f(p[(int64_t)k * ld + m]) : 0.0f;
+    }
+};
+
+// Implicit-GEMM rows of a circular conv input: row m = (b, x), k = dx*C + c
+// -> act[b][(x + sgn*(dx - 2)) mod L][c]; sgn = +1 forward, -1 for the
+// gradient with respect to the input.
+template <class P>
+struct ConvRows {
+    using T = typename P::T;
+    const T* act;
+    int L, C, rows, sgn;
+    __device__ __forceinline__ int64_t base(int m, int k) const {
+        const int b = m / L, x = m - b * L;
+        const int dx = k / C, c = k - dx * C;
+        int pos = x + sgn * (dx - 2);
+        pos = pos < 0 ? pos + L : (pos >= L ? pos - L : pos);
+        return ((int64_t)b * L + pos) * C + c;
+    }
+    __device__ __forceinline__ bf16x8 frag8(int m, int k) const {
+        if (m >= rows || k >= 5 * C) return bf16x8{};
+        return *reinterpret_cast<const bf16x8*>(reinterpret_cast<const uint16_t*>(act) + base(m, k));
+    }
+    __device__ __forceinline__ float frag1(int m, int k) const {
+        if (m >= rows || k >= 5 * C) return 0.0f;
+        return P::to_f(act[base(m, k)]);
+    }
+};
+
+// Weight-gradient operand of a conv: element (n = dx*Cin + ci, k = (b, x))
+// = in[b][(x + dx - 2) mod L][ci].
+template <class P>
+struct ConvCols {
+    using T = typename P::T;
+    const T* act;
+    int L, C, K;
+    __device__ __forceinline__ float at(int n, int k) const {
+        if (n >= 5 * C || k >= K) return 0.0f;
+        const int b = k / L, x = k - b * L;
+        const int dx = n / C, c = n - dx * C;
+        int pos = x + dx - 2;
+        pos = pos < 0 ? pos + L : (pos >= L ? pos - L : pos);
+        return P::to_f(act[((int64_t)b * L + pos) * C + c]);
+    }
+    __device__ __forceinline__ bf16x8 frag8(int n, int k) const {
+        bf16x8 v;
+        for (int j = 0; j < 8; ++j) v[j] = __builtin_bit_cast(__bf16, f2bf(at(n, k + j)));
+        return v;
+    }
+    __device__ __forceinline__ float frag1(int n, int k) const { return at(n, k); }
+};
+
+// ---- epilogues
+
+// Conv forward: rows are (b, x) positions (4 consecutive per lane), columns
+// output channels. Bias, ReLU, max-pool over position pairs (both in the
+// lane), store the pooled value and a mask byte (bit 0: the winning
+// position's parity, bit 1: the winner's pre-activation is > 0).
+template <class P>
+struct EpConvFwd {
+    using T = typename P::T;
+    const float* bias;
+    T* out;          // [b][L/2][C]
+    uint8_t* mask;   // [b][L/2][C]
+    int C;
+    __device__ __forceinline__ void operator()(int m, int n, f32x4 a, int M, int N) const {
+        if (n >= N) return;
+        for (int h = 0; h < 2; ++h) {
+            const int mm = m + 2 * h;
+            if (mm >= M) continue;
+            const float p0 = a[2 * h] + bias[n], p1 = a[2 * h + 1] + bias[n];
+            const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
+            const int w = r0 >= r1 ? 0 : 1;
+            const float pv = w ? p1 : p0;
+            const int64_t o = (int64_t)(mm >> 1) * C + n;
+            out[o] = P::from_f(w ? r1 : r0);
+            mask[o] = (uint8_t)(w | (pv > 0.0f ? 2 : 0));
+        }
+    }
+};
+
+// Fully connected forward: rows batch, columns outputs; bias + ReLU.
+template <class P>
+struct EpFcFwd {
+    using T = typename P::T;
+    const float* bias;
+    T* out;
+    int ld;
+    __device__ __forceinline__ void operator()(int m, int n, f32x4 a, int M, int N) const {
+        if (n >= N) return;
+        for (int i = 0; i < 4; ++i)
+            if (m + i < M) out[(int64_t)(m + i) * ld + n] = P::from_f(fmaxf(a[i] + bias[n], 0.0f));
+    }
+};
+
+// Plain store of a data gradient, optionally masked by a ReLU output (> 0).
+template <class P>
+struct EpStore {
+    using T = typename P::T;
+    T* out;
+    const T* relu_of;   // may be null
+    int ld;
+    __device__ __forceinline__ void operator()(int m, int n, f32x4 a, int M, int N) const {
+        if (n >= N) return;
+        for (int i = 0; i < 4; ++i)
+            if (m + i < M) {
+                const int64_t o = (int64_t)(m + i) * ld + n;
+                float v = a[i];
+                if (relu_of && !(P::to_f(relu_of[o]) > 0.0f)) v = 0.0f;
+                out[o] = P::from_f(v);
+            }
+    }
+};
+
+// Weight gradient of conv layer l: rows co, columns n = dx*Cin + ci, written
+// to the canonical [co][ci][dx] position (FP32).
+struct EpConvDW {
+    float* g;
+    int Cin;
+    __device__ __forceinline__ void operator()(int m, int n, f32x4 a, int M, int N) const {
+        if (n >= N) return;
+        const int dx = n / Cin, ci = n - dx * Cin;
+        for (int i = 0; i < 4; ++i)
+            if (m + i < M) g[((int64_t)(m + i) * Cin + ci) * 5 + dx] = a[i];
+    }
+};
+
+// Weight gradient of a fully connected layer: rows outputs, columns inputs.
+// For fc1 the GEMM's input index j = x*64 + c maps to the canonical
+// channel-major c*16 + x.
+struct EpFcDW {
+    float* g;
+    int in;
+    bool fc1;
+    __device__ __forceinline__ void operator()(int m, int n, f32x4 a, int M, int N) const {
+        if (n >= N) return;
+        const int i = fc1 ? ((n & 63) * 16 + (n >> 6)) : n;
+        for (int r = 0; r < 4; ++r)
+            if (m + r < M) g[(int64_t)(m + r) * in + i] = a[r];
+    }
+};
+
+// ------------------------------------------------------------------ small kernels
+
+// Conv block 1 (one input channel) on the vector units: x [B][256] (bf16
+// bits or f32) -> pooled act1 [B][128][16] and mask.
+template <class P>
+__global__ __launch_bounds__(256) void k_conv1_fwd(const void* __restrict__ x, int xf32, int B,
+                                                   const float* __restrict__ w /*[16][5]*/,
+                                                   const float* __restrict__ bias,
+                                                   typename P::T* __restrict__ out,
+                                                   uint8_t* __restrict__ mask) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;   // (b, xp, co)
+    if (idx >= (int64_t)B * 128 * 16) return;
+    const int co = idx & 15;
+    const int xp = (idx >> 4) & 127;
+    const int b = (int)(idx >> 11);
+    float pre[2];
+    for (int h = 0; h < 2; ++h) {
+        const int xx = 2 * xp + h;
+        float s = bias[co];
+        for (int dx = 0; dx < 5; ++dx) {
+            const int pos = (xx + dx - 2) & 255;
+            const int64_t o = (int64_t)b * 256 + pos;
+            const float v = xf32 ? reinterpret_cast<const float*>(x)[o]
+                                 : bf2f(reinterpret_cast<const uint16_t*>(x)[o]);
+            s += w[co * 5 + dx] * P::to_f(P::from_f(v));
+        }
+        pre[h] = s;
+    }
+    const float r0 = fmaxf(pre[0], 0.0f), r1 = fmaxf(pre[1], 0.0f);
+    const int wn = r0 >= r1 ? 0 : 1;
+    out[idx] = P::from_f(wn ? r1 : r0);
+    mask[idx] = (uint8_t)(wn | ((wn ? pre[1] : pre[0]) > 0.0f ? 2 : 0));
+}
+
+// Output layer, loss and its gradient. One block; h2 [B][64] post-ReLU.
+template <class P>
+__global__ __launch_bounds__(256) void k_head(const typename P::T* __restrict__ h2, int B,
+                                              const float* __restrict__ w3, const float* __restrict__ b3,
+                                              const float* __restrict__ labels, float* __restrict__ logits,
+                                              float* __restrict__ loss, float* __restrict__ grad,
+                                              typename P::T* __restrict__ dh2) {
+    __shared__ float red[256];
+    __shared__ float dzs[1024];
+    float lsum = 0.0f, dbsum = 0.0f;
+    for (int b0 = 0; b0 < B; b0 += 1024) {
+        const int nb = min(1024, B - b0);
+        for (int bi = threadIdx.x; bi < nb; bi += 256) {
+            const int b = b0 + bi;
+            float z = b3[0];
+            for (int i = 0; i < 64; ++i) z += P::to_f(h2[(int64_t)b * 64 + i]) * w3[i];
+            if (logits) logits[b] = z;
+            if (labels) {
+                const float y = labels[b];
+                lsum += fmaxf(z, 0.0f) - z * y + log1pf(expf(-fabsf(z)));
+                const float dz = (1.0f / (1.0f + expf(-z)) - y) / (float)B;
+                dzs[bi] = dz;
+                dbsum += dz;
+            }
+        }
+        if (!labels) continue;
+        __syncthreads();
+        // dW3[i] += sum_b dz h2[b][i]; dh2 = dz * w3 masked by h2 > 0
+        for (int i = threadIdx.x; i < 64; i += 256) {
+            float s = 0.0f;
+            for (int bi = 0; bi < nb; ++bi) s += dzs[bi] * P::to_f(h2[(int64_t)(b0 + bi) * 64 + i]);
+            grad[F3W + i] += s;
+        }
+        for (int e = threadIdx.x; e < nb * 64; e += 256) {
+            const int bi = e >> 6, i = e & 63;
+            const int64_t o = (int64_t)(b0 + bi) * 64 + i;
+            dh2[o] = P::from_f(P::to_f(h2[o]) > 0.0f ? dzs[bi] * w3[i] : 0.0f);
+        }
+        __syncthreads();
+    }
+    if (!labels) return;
+    red[threadIdx.x] = lsum;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = red[0] / (float)B;
+    __syncthreads();
+    red[threadIdx.x] = dbsum;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) grad[F3B] += red[0];
+}
+
+// Route a pooled-level gradient to the pre-activation positions with the
+// forward mask: dpre[b][x][c] = dact[b][x/2][c] if x is the winner and its
+// pre-activation was > 0, else 0.
+template <class P>
+__global__ __launch_bounds__(256) void k_unpool(const typename P::T* __restrict__ dact,
+                                                const uint8_t* __restrict__ mask, int64_t npool,
+                                                int C, typename P::T* __restrict__ dpre) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;   // pooled index (b, xp, c)
+    if (i >= npool) return;
+    const int c = (int)(i % C);
+    const int64_t bx = i / C;                                      // b * Lp + xp
+    const uint8_t mk = mask[i];
+    const typename P::T g = (mk & 2) ? dact[i] : P::from_f(0.0f);
+    const typename P::T z = P::from_f(0.0f);
+    dpre[(2 * bx + (mk & 1)) * C + c] = g;
+    dpre[(2 * bx + 1 - (mk & 1)) * C + c] = z;
+}
+
+// Bias gradient: g[o] = sum over rows of d[row][o] (rows x C, FP32 out).
+template <class P>
+__global__ __launch_bounds__(256) void k_bias_grad(const typename P::T* __restrict__ d, int64_t rows,
+                                                   int C, float* __restrict__ g) {
+    __shared__ float red[256];
+    const int c = blockIdx.x;
+    float s = 0.0f;
+    for (int64_t r = threadIdx.x; r < rows; r += 256) s += P::to_f(d[r * C + c]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) g[c] = red[0];
+}
+
+// Conv block 1 weight gradient: dW[co][dx] = sum_{b,x} dpre[b][x][co] x[b][(x+dx-2) mod 256].
+template <class P>
+__global__ __launch_bounds__(256) void k_conv1_dw(const typename P::T* __restrict__ dpre,
+                                                  const void* __restrict__ x, int xf32, int B,
+                                                  float* __restrict__ g) {
+    __shared__ float red[256];
+    const int co = blockIdx.x / 5, dx = blockIdx.x % 5;
+    float s = 0.0f;
+    for (int64_t e = threadIdx.x; e < (int64_t)B * 256; e += 256) {
+        const int b = (int)(e >> 8), xx = (int)(e & 255);
+        const int pos = (xx + dx - 2) & 255;
+        const int64_t o = (int64_t)b * 256 + pos;
+        const float v = xf32 ? reinterpret_cast<const float*>(x)[o]
+                             : bf2f(reinterpret_cast<const uint16_t*>(x)[o]);
+        s += P::to_f(dpre[e * 16 + co]) * P::to_f(P::from_f(v));
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) g[co * 5 + dx] = red[0];
+}
+
+// Working copies of the weights from the FP32 masters.
+template <class P>
+__global__ __launch_bounds__(256) void k_pack(const float* __restrict__ w, typename P::T* __restrict__ wf2,
+                                              typename P::T* __restrict__ wb2, typename P::T* __restrict__ wf3,
+                                              typename P::T* __restrict__ wb3, typename P::T* __restrict__ wf4,
+                                              typename P::T* __restrict__ wb4, typename P::T* __restrict__ f1f,
+                                              typename P::T* __restrict__ f1b, typename P::T* __restrict__ f2f,
+                                              typename P::T* __restrict__ f2b) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    // conv l = 2..4: canonical [co][ci][dx]
+    typename P::T* wf[5] = {nullptr, nullptr, wf2, wf3, wf4};
+    typename P::T* wb[5] = {nullptr, nullptr, wb2, wb3, wb4};
+    for (int l = 2; l <= 4; ++l) {
+        const int Cin = CH[l - 1], Cout = CH[l];
+        const int64_t n = (int64_t)Cout * Cin * 5;
+        if (i < n) {
+            const int dx = (int)(i % 5), ci = (int)((i / 5) % Cin), co = (int)(i / (5 * Cin));
+            const typename P::T v = P::from_f(w[kConvW[l] + i]);
+            wf[l][(int64_t)co * (5 * Cin) + dx * Cin + ci] = v;
+            wb[l][(int64_t)ci * (5 * Cout) + dx * Cout + co] = v;
+        }
+    }
+    if (i < 256 * 1024) {
+        const int o = (int)(i >> 10), ic = (int)(i & 1023);          // canonical c*16 + x
+        const int j = (ic & 15) * 64 + (ic >> 4);                      // position-major x*64 + c
+        const typename P::T v = P::from_f(w[F1W + i]);
+        f1f[(int64_t)o * 1024 + j] = v;
+        f1b[(int64_t)j * 256 + o] = v;
+    }
+    if (i < 64 * 256) {
+        const int o = (int)(i >> 8), ii = (int)(i & 255);
+        const typename P::T v = P::from_f(w[F2W + i]);
+        f2f[i] = v;
+        f2b[(int64_t)ii * 64 + o] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v, int64_t n,
+                                              float lr, float b1, float b2, float eps, float c1,
+                                              float c2) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ __launch_bounds__(256) void k_fill(float* __restrict__ p, int64_t n, float v) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+template <class P, class LA, class LB, class EP>
+hipError_t gemm(int M, int N, int K, LA la, LB lb, EP ep, hipStream_t s) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    dim3 grid((M + 63) / 64, (N + 63) / 64);
+    hipLaunchKernelGGL((k_gemm<P, LA, LB, EP>), grid, dim3(256), 0, s, M, N, K, la, lb, ep);
+    return hipGetLastError();
+}
+
+}  // namespace gcnn
+
+// ------------------------------------------------------------------ C ABI
+
+struct gpfc_cnn {
+    int32_t device = 0;
+    int32_t prec = 0;            // 0 bf16, 1 fp32
+    int64_t max_batch = 0;
+    int64_t step = 0;
+    float* params = nullptr;     // FP32 masters, canonical layout
+    float* grad = nullptr;
+    float* m = nullptr;
+    float* v = nullptr;
+    float* loss = nullptr;
+    void* work = nullptr;        // packed weights + activations
+    bool packed = false;
+    // views into work (element type per prec)
+    void *wf2, *wb2, *wf3, *wb3, *wf4, *wb4, *f1f, *f1b, *f2f, *f2b;
+    void *a1, *a2, *a3, *a4, *h1, *h2;       // activations
+    void *d_a, *d_b;                          // gradient scratch (largest activation size)
+    uint8_t *m1, *m2, *m3, *m4;
+};
+
+namespace {
+
+thread_local char g_cnn_err[256] = "";
+
+int32_t cnn_err(hipError_t e, const char* what) {
+    snprintf(g_cnn_err, sizeof(g_cnn_err), "%s: %s", what, hipGetErrorString(e));
+    return GPFC_EDEVICE;
+}
+
+template <class P>
+int32_t pack(gpfc_cnn* c, hipStream_t s) {
+    using T = typename P::T;
+    hipLaunchKernelGGL((gcnn::k_pack<P>), dim3(gcnn::blocks_for(256 * 1024)), dim3(256), 0, s,
+                       c->params, (T*)c->wf2, (T*)c->wb2, (T*)c->wf3, (T*)c->wb3, (T*)c->wf4,
+                       (T*)c->wb4, (T*)c->f1f, (T*)c->f1b, (T*)c->f2f, (T*)c->f2b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return cnn_err(e, "k_pack");
+    c->packed = true;
+    return GPFC_OK;
+}
+
+template <class P>
+int32_t forward(gpfc_cnn* c, const void* x, int xf32, int B, float* logits, const float* labels,
+                hipStream_t s) {
+    using namespace gcnn;
+    using T = typename P::T;
+    hipError_t e;
+    if (!c->packed) {
+        int32_t rc = pack<P>(c, s);
+        if (rc != GPFC_OK) return rc;
+    }
+    const float* w = c->params;
+    hipLaunchKernelGGL((k_conv1_fwd<P>), dim3(blocks_for((int64_t)B * 128 * 16)), dim3(256), 0, s, x,
+                       xf32, B, w + kConvW[1], w + conv_b(1), (T*)c->a1, c->m1);
+    T* acts[5] = {nullptr, (T*)c->a1, (T*)c->a2, (T*)c->a3, (T*)c->a4};
+    uint8_t* masks[5] = {nullptr, c->m1, c->m2, c->m3, c->m4};
+    void* wfs[5] = {nullptr, nullptr, c->wf2, c->wf3, c->wf4};
+    for (int l = 2; l <= 4; ++l) {
+        const int Cin = CH[l - 1], Cout = CH[l], L = LEN[l - 1];
+        ConvRows<P> la{acts[l - 1], L, Cin, B * L, +1};
+        Rows<P> lb{(const T*)wfs[l], Cout, 5 * Cin, 5 * Cin};
+        EpConvFwd<P> ep{w + conv_b(l), acts[l], masks[l], Cout};
+        e = gemm<P>(B * L, Cout, 5 * Cin, la, lb, ep, s);
+        if (e != hipSuccess) return cnn_err(e, "conv gemm");
+    }
+    e = gemm<P>(B, 256, 1024, Rows<P>{(const T*)c->a4, B, 1024, 1024},
+                Rows<P>{(const T*)c->f1f, 256, 1024, 1024}, EpFcFwd<P>{w + F1B, (T*)c->h1, 256}, s);
+    if (e != hipSuccess) return cnn_err(e, "fc1 gemm");
+    e = gemm<P>(B, 64, 256, Rows<P>{(const T*)c->h1, B, 256, 256},
+                Rows<P>{(const T*)c->f2f, 64, 256, 256}, EpFcFwd<P>{w + F2B, (T*)c->h2, 64}, s);
+    if (e != hipSuccess) return cnn_err(e, "fc2 gemm");
+    hipLaunchKernelGGL((k_head<P>), dim3(1), dim3(256), 0, s, (const T*)c->h2, B, w + F3W, w + F3B,
+                       labels, logits, c->loss, c->grad, (T*)c->d_a);
+    e = hipGetLastError();
+    return e == hipSuccess ? GPFC_OK : cnn_err(e, "k_head");
+}
+
+template <class P>
+int32_t backward(gpfc_cnn* c, const void* x, int xf32, int B, hipStream_t s) {
+    using namespace gcnn;
+    using T = typename P::T;
+    hipError_t e;
+    const float* w = c->params;
+    float* g = c->grad;
+    // dh2 (already masked) is in d_a [B][64]
+    T* dh2 = (T*)c->d_a;
+    e = gemm<P>(64, 256, B, Cols<P>{dh2, 64, 64, B}, Cols<P>{(const T*)c->h1, 256, 256, B},
+                EpFcDW{g + F2W, 256, false}, s);
+    if (e != hipSuccess) return cnn_err(e, "fc2 dW");
+    hipLaunchKernelGGL((k_bias_grad<P>), dim3(64), dim3(256), 0, s, dh2, (int64_t)B, 64, g + F2B);
+    T* dh1 = (T*)c->d_b;   // [B][256], masked by h1 > 0
+    e = gemm<P>(B, 256, 64, Rows<P>{dh2, B, 64, 64}, Rows<P>{(const T*)c->f2b, 256, 64, 64},
+                EpStore<P>{dh1, (const T*)c->h1, 256}, s);
+    if (e != hipSuccess) return cnn_err(e, "fc2 dX");
+    e = gemm<P>(256, 1024, B, Cols<P>{dh1, 256, 256, B}, Cols<P>{(const T*)c->a4, 1024, 1024, B},
+                EpFcDW{g + F1W, 1024, true}, s);
+    if (e != hipSuccess) return cnn_err(e, "fc1 dW");
+    hipLaunchKernelGGL((k_bias_grad<P>), dim3(256), dim3(256), 0, s, dh1, (int64_t)B, 256, g + F1B);
+    T* dact = (T*)c->d_a;  // [B][1024] = pooled gradient of block 4, position-major
+    e = gemm<P>(B, 1024, 256, Rows<P>{dh1, B, 256, 256}, Rows<P>{(const T*)c->f1b, 1024, 256, 256},
+                EpStore<P>{dact, nullptr, 1024}, s);
+    if (e != hipSuccess) return cnn_err(e, "fc1 dX");
+    T* acts[5] = {nullptr, (T*)c->a1, (T*)c->a2, (T*)c->a3, (T*)c->a4};
+    uint8_t* masks[5] = {nullptr, c->m1, c->m2, c->m3, c->m4};
+    void* wbs[5] = {nullptr, nullptr, c->wb2, c->wb3, c->wb4};
+    T* bufA = (T*)c->d_a;
+    T* bufB = (T*)c->d_b;
+    for (int l = 4; l >= 1; --l) {
+        const int Cin = CH[l - 1], Cout = CH[l], L = LEN[l - 1];
+        const int64_t npool = (int64_t)B * (L / 2) * Cout;
+        T* dpre = (bufA == dact) ? bufB : bufA;
+        hipLaunchKernelGGL((k_unpool<P>), dim3(blocks_for(npool)), dim3(256), 0, s, dact, masks[l],
+                           npool, Cout, dpre);
+        hipLaunchKernelGGL((k_bias_grad<P>), dim3(Cout), dim3(256), 0, s, dpre, (int64_t)B * L, Cout,
+                           g + conv_b(l));
+        if (l == 1) {
+            hipLaunchKernelGGL((k_conv1_dw<P>), dim3(16 * 5), dim3(256), 0, s, dpre, x, xf32, B,
+                               g + kConvW[1]);
+            break;
+        }
+        e = gemm<P>(Cout, 5 * Cin, B * L, Cols<P>{dpre, Cout, Cout, B * L},
+                    ConvCols<P>{acts[l - 1], L, Cin, B * L}, EpConvDW{g + kConvW[l], Cin}, s);
+        if (e != hipSuccess) return cnn_err(e, "conv dW");
+        // gradient with respect to the block's input (pooled output of l-1)
+        T* dnext = dact;   // reuse: dact is free once dpre exists
+        e = gemm<P>(B * L, Cin, 5 * Cout, ConvRows<P>{dpre, L, Cout, B * L, -1},
+                    Rows<P>{(const T*)wbs[l], Cin, 5 * Cout, 5 * Cout},
+                    EpStore<P>{dnext, nullptr, Cin}, s);
+        if (e != hipSuccess) return cnn_err(e, "conv dX");
+        dact = dnext;
+        bufA = dact;
+        bufB = dpre;
+    }
+    e = hipGetLastError();
+    return e == hipSuccess ? GPFC_OK : cnn_err(e, "backward");
+}
+
+size_t elt(const gpfc_cnn* c) { return c->prec ? 4 : 2; }
+
+}  // namespace
+
+extern "C" {
+
+int32_t gpfc_cnn_nparams(void) { return gcnn::kNP; }
+
+const char* gpfc_cnn_last_error(void) { return g_cnn_err; }
+
+int32_t gpfc_cnn_create(gpfc_cnn** out, int32_t device, int32_t precision, int64_t max_batch) {
+    if (!out) return GPFC_EINVAL;
+    *out = nullptr;
+    if (precision != GPFC_CNN_BF16 && precision != GPFC_CNN_FP32) return GPFC_EINVAL;
+    if (max_batch < 1 || max_batch > (1 << 22)) return GPFC_EINVAL;
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return cnn_err(e, "hipSetDevice");
+    gpfc_cnn* c = new (std::nothrow) gpfc_cnn();
+    if (!c) return GPFC_ENOMEM;
+    c->device = device;
+    c->prec = precision;
+    c->max_batch = max_batch;
+    const size_t E = elt(c);
+    const int64_t Bm = max_batch;
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    size_t wsz[10] = {32 * 80, 16 * 160, 64 * 160, 32 * 320, 64 * 320, 64 * 320,
+                      256 * 1024, 1024 * 256, 64 * 256, 256 * 64};
+    size_t asz[6] = {(size_t)Bm * 128 * 16, (size_t)Bm * 64 * 32, (size_t)Bm * 32 * 64,
+                     (size_t)Bm * 16 * 64, (size_t)Bm * 256, (size_t)Bm * 64};
+    const size_t dsz = (size_t)Bm * 256 * 16;   // largest pre-pool gradient (block 1)
+    size_t total = 0;
+    for (size_t z : wsz) total += al(z * E);
+    for (size_t z : asz) total += al(z * E);
+    total += 2 * al(dsz * E);
+    for (int i = 0; i < 4; ++i) total += al(asz[i]);   // masks
+    const size_t fsz = al(sizeof(float) * gcnn::kNP);
+    total += 4 * fsz + 256;
+    void* base = nullptr;
+    e = hipMalloc(&base, total);
+    if (e != hipSuccess) {
+        delete c;
+        return e == hipErrorOutOfMemory ? GPFC_ENOMEM : cnn_err(e, "hipMalloc");
+    }
+    c->work = base;
+    char* p = (char*)base;
+    auto take = [&](size_t bytes) { void* r = p; p += al(bytes); return r; };
+    c->params = (float*)take(sizeof(float) * gcnn::kNP);
+    c->grad = (float*)take(sizeof(float) * gcnn::kNP);
+    c->m = (float*)take(sizeof(float) * gcnn::kNP);
+    c->v = (float*)take(sizeof(float) * gcnn::kNP);
+    c->loss = (float*)take(256);
+    void** wv[10] = {&c->wf2, &c->wb2, &c->wf3, &c->wb3, &c->wf4, &c->wb4, &c->f1f, &c->f1b, &c->f2f, &c->f2b};
+    for (int i = 0; i < 10; ++i) *wv[i] = take(wsz[i] * E);
+    void** av[6] = {&c->a1, &c->a2, &c->a3, &c->a4, &c->h1, &c->h2};
+    for (int i = 0; i < 6; ++i) *av[i] = take(asz[i] * E);
+    c->d_a = take(dsz * E);
+    c->d_b = take(dsz * E);
+    uint8_t** mv[4] = {&c->m1, &c->m2, &c->m3, &c->m4};
+    for (int i = 0; i < 4; ++i) *mv[i] = (uint8_t*)take(asz[i]);
+    *out = c;
+    return GPFC_OK;
+}
+
+int32_t gpfc_cnn_destroy(gpfc_cnn* c) {
+    if (!c) return GPFC_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    if (c->work) (void)hipFree(c->work);
+    delete c;
+    return GPFC_OK;
+}
+
+int32_t gpfc_cnn_set_params(gpfc_cnn* c, const float* params, void* stream) {
+    if (!c || !params) return GPFC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(c->params, params, sizeof(float) * gcnn::kNP,
+                                  hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return cnn_err(e, "set params");
+    const unsigned nb = gcnn::blocks_for(gcnn::kNP);
+    hipLaunchKernelGGL(gcnn::k_fill, dim3(nb), dim3(256), 0, s, c->m, (int64_t)gcnn::kNP, 0.0f);
+    hipLaunchKernelGGL(gcnn::k_fill, dim3(nb), dim3(256), 0, s, c->v, (int64_t)gcnn::kNP, 0.0f);
+    c->step = 0;
+    c->packed = false;
+    e = hipGetLastError();
+    return e == hipSuccess ? GPFC_OK : cnn_err(e, "set params");
+}
+
+int32_t gpfc_cnn_get_params(gpfc_cnn* c, float* out, void* stream) {
+    if (!c || !out) return GPFC_EINVAL;
+    hipError_t e = hipMemcpyAsync(out, c->params, sizeof(float) * gcnn::kNP, hipMemcpyDeviceToDevice,
+                                  (hipStream_t)stream);
+    return e == hipSuccess ? GPFC_OK : cnn_err(e, "get params");
+}
+
+int32_t gpfc_cnn_forward(gpfc_cnn* c, const void* x, int32_t x_f32, int64_t B, float* logits,
+                         void* stream) {
+    if (!c || B < 0 || B > c->max_batch || (B > 0 && (!x || !logits))) return GPFC_EINVAL;
+    if (B == 0) return GPFC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    return c->prec ? forward<gcnn::F32>(c, x, x_f32, (int)B, logits, nullptr, s)
+                   : forward<gcnn::BF16>(c, x, x_f32, (int)B, logits, nullptr, s);
+}
+
+int32_t gpfc_cnn_backward(gpfc_cnn* c, const void* x, int32_t x_f32, const float* labels, int64_t B,
+                          float* loss_out, float* grad_out, void* stream) {
+    if (!c || B < 1 || B > c->max_batch || !x || !labels) return GPFC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(gcnn::k_fill, dim3(gcnn::blocks_for(gcnn::kNP)), dim3(256), 0, s, c->grad,
+                       (int64_t)gcnn::kNP, 0.0f);
+    int32_t rc = c->prec ? forward<gcnn::F32>(c, x, x_f32, (int)B, nullptr, labels, s)
+                         : forward<gcnn::BF16>(c, x, x_f32, (int)B, nullptr, labels, s);
+    if (rc != GPFC_OK) return rc;
+    rc = c->prec ? backward<gcnn::F32>(c, x, x_f32, (int)B, s)
+                 : backward<gcnn::BF16>(c, x, x_f32, (int)B, s);
+    if (rc != GPFC_OK) return rc;
+    hipError_t e = hipSuccess;
+    if (loss_out) e = hipMemcpyAsync(loss_out, c->loss, sizeof(float), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && grad_out)
+        e = hipMemcpyAsync(grad_out, c->grad, sizeof(float) * gcnn::kNP, hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? GPFC_OK : cnn_err(e, "copy out");
+}
+
+int32_t gpfc_cnn_adam(gpfc_cnn* c, float lr, float beta1, float beta2, float eps, void* stream) {
+    if (!c || !(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f))
+        return GPFC_EINVAL;
+    c->step += 1;
+    const float c1 = (float)(1.0 - pow((double)beta1, (double)c->step));
+    const float c2 = (float)(1.0 - pow((double)beta2, (double)c->step));
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(gcnn::k_adam, dim3(gcnn::blocks_for(gcnn::kNP)), dim3(256), 0, s, c->params,
+                       c->grad, c->m, c->v, (int64_t)gcnn::kNP, lr, beta1, beta2, eps, c1, c2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return cnn_err(e, "k_adam");
+    c->packed = false;
+    return GPFC_OK;
+}
+
+}  // extern "C"

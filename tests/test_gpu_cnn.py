@@ -1,0 +1,165 @@
+"""Learned scorer on the GPU against the FP64 CNN oracle (runs on an MI355X).
+
+FP32 mode: logits and gradients to 1e-4 relative (norm-wise per tensor; a
+ReLU or pooling decision that flips at a near-tie moves one term, allowed
+for by the norm). bf16 mode: the measured error is printed and bounded
+loosely; its accuracy is judged by what the trained network does.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2312_02063_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+SEGMENTS = [("conv1", 0, 96), ("conv2", 96, 2688), ("conv3", 2688, 12992), ("conv4", 12992, 33536),
+            ("fc1", 33536, 295936), ("fc2", 295936, 312384), ("fc3", 312384, 312449)]
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _params(seed):
+    rng = np.random.default_rng(seed)
+    p = synth.cnn_init(seed)
+    return p + rng.normal(0, 0.02, p.size)
+
+
+def _inputs(seed, B):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(size=(B, 256))
+    y = (rng.uniform(size=B) < 0.5).astype(np.float64)
+    return x, y
+
+
+def _net(torch, precision, params, max_batch=512):
+    from paper_2312_02063_amd import Cnn
+    net = Cnn(0, precision, max_batch)
+    net.set_params(params.astype(np.float32))
+    return net
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def test_forward_fp32_matches_oracle(torch_dev):
+    torch = torch_dev
+    from paper_2312_02063_amd import CNN_FP32
+    p = _params(1)
+    x, _ = _inputs(2, 70)
+    _say("cnn forward fp32 B=70")
+    net = _net(torch, CNN_FP32, p)
+    z = net.forward(torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().numpy()
+    p32 = p.astype(np.float32).astype(np.float64)
+    zo = oracle.cnn_forward(p32, x.astype(np.float32).astype(np.float64))
+    assert np.max(np.abs(z - zo) / np.maximum(1.0, np.abs(zo))) < 1e-4
+
+
+def test_forward_bf16_error_and_bf16_input(torch_dev):
+    torch = torch_dev
+    from paper_2312_02063_amd import CNN_BF16
+    p = _params(3)
+    x, _ = _inputs(4, 129)
+    _say("cnn forward bf16 B=129")
+    net = _net(torch, CNN_BF16, p)
+    xt = torch.tensor(x, dtype=torch.float32, device="cuda")
+    z = net.forward(xt).cpu().numpy()
+    zo = oracle.cnn_forward(p, x)
+    err = _rel(z, zo)
+    print(f"bf16 forward relative L2 error vs FP64: {err:.3e}")
+    assert err < 5e-2
+    # bfloat16-bit input (as the fold kernel writes it) = the f32 input rounded
+    xb = xt.to(torch.bfloat16).view(torch.uint16)
+    zb = net.forward(xb).cpu().numpy()
+    z2 = net.forward(xb.view(torch.bfloat16).to(torch.float32)).cpu().numpy()
+    assert np.array_equal(zb, z2)
+
+
+@pytest.mark.parametrize("prec_name", ["fp32", "bf16"])
+def test_gradient_matches_oracle(torch_dev, prec_name):
+    torch = torch_dev
+    from paper_2312_02063_amd import CNN_BF16, CNN_FP32
+    prec = CNN_FP32 if prec_name == "fp32" else CNN_BF16
+    p = _params(5)
+    x, y = _inputs(6, 96)
+    _say(f"cnn backward {prec_name} B=96")
+    net = _net(torch, prec, p)
+    g = torch.empty(net.n_params, dtype=torch.float32, device="cuda")
+    loss = net.backward(torch.tensor(x, dtype=torch.float32, device="cuda"),
+                        torch.tensor(y, dtype=torch.float32, device="cuda"), grad_out=g)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    p32 = p.astype(np.float32).astype(np.float64)
+    lo, go = oracle.cnn_loss_grad(p32, x.astype(np.float32).astype(np.float64), y)
+    tol = 1e-4 if prec == CNN_FP32 else 1e-1
+    assert abs(loss.item() - lo) <= tol * max(1.0, lo)
+    for name, a, b in SEGMENTS:
+        err = _rel(g[a:b], go[a:b])
+        print(f"{prec_name} grad {name}: relative L2 error {err:.3e}")
+        assert err < tol, name
+
+
+def test_adam_step_matches_oracle(torch_dev):
+    torch = torch_dev
+    from paper_2312_02063_amd import CNN_FP32
+    p = _params(7)
+    x, y = _inputs(8, 64)
+    net = _net(torch, CNN_FP32, p)
+    xt = torch.tensor(x, dtype=torch.float32, device="cuda")
+    yt = torch.tensor(y, dtype=torch.float32, device="cuda")
+    p_ref = p.astype(np.float32).astype(np.float64)
+    m = np.zeros_like(p_ref)
+    v = np.zeros_like(p_ref)
+    g = torch.empty(net.n_params, dtype=torch.float32, device="cuda")
+    for step in range(1, 4):
+        _say(f"cnn adam step {step}")
+        net.backward(xt, yt, grad_out=g)
+        net.adam(1e-3)
+        oracle.adam(p_ref, g.cpu().numpy().astype(np.float64), m, v, step, 1e-3)
+        got = net.get_params().cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(got - p_ref)) < 1e-6
+        p_ref = got.copy()   # continue from the GPU's (FP32) parameters
+
+
+def test_training_on_folds_reduces_loss(torch_dev):
+    """A few hundred Adam steps on normalised folds the fold kernel produces
+    from curves with and without transits lower the loss well below log 2."""
+    torch = torch_dev
+    from paper_2312_02063_amd import CNN_BF16, Plan
+    rng = np.random.default_rng(9)
+    curves = [synth.training_curve(rng, n=2000, positive=bool(i % 2), alpha_range=(12.0, 20.0))
+              for i in range(256)]
+    plan = Plan(0)
+    so = np.concatenate([[0], np.cumsum([c.t.size for c in curves])])
+    po = np.arange(len(curves) + 1)
+    periods = np.array([c.truth.get("period", rng.uniform(0.2, 1.0)) for c in curves])
+    plan.batch_setup(so, po)
+    t = torch.tensor(np.concatenate([c.t for c in curves]), dtype=torch.float64, device="cuda")
+    f = torch.tensor(np.concatenate([c.flux for c in curves]), dtype=torch.float32, device="cuda")
+    pp = torch.tensor(periods, dtype=torch.float64, device="cuda")
+    z = torch.empty((len(curves), 256), dtype=torch.uint16, device="cuda")
+    _say("training folds via batch")
+    plan.batch_fold_score(t, f, pp, 256, zfold=z)
+    labels = torch.tensor([c.truth["label"] for c in curves], dtype=torch.float32, device="cuda")
+    net = _net(torch, CNN_BF16, synth.cnn_init(13))
+    _say("cnn training 300 steps")
+    first = net.backward(z, labels).item()
+    for _ in range(300):
+        net.train_step(z, labels, 1e-3)
+    last = net.backward(z, labels).item()
+    print(f"training loss {first:.4f} -> {last:.4f}")
+    assert last < 0.5 * first
