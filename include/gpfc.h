@@ -163,6 +163,18 @@ int32_t gpfc_fold_score_prepared(gpfc_plan *plan, const double *periods, int64_t
                                  float *depth, uint16_t *zfold, void *stream);
 
 /*
+ * gpfc_fold on the prepared curve with FP32 bin sums, for precision studies:
+ * compensated = 0 adds float(flux - ref) with plain float LDS atomics;
+ * compensated = 1 also accumulates each addition's exact rounding error
+ * (TwoSum on the atomic's returned old value) in a second float array. Counts
+ * and bins are those of gpfc_fold; sums are count * ref + sum (+ error).
+ * Float LDS atomics run far slower than the integer ones gpfc_fold uses.
+ */
+int32_t gpfc_fold_f32_prepared(gpfc_plan *plan, const double *periods, int64_t k, int32_t nbins,
+                               int32_t compensated, double *sums, int32_t *counts, double *means,
+                               void *stream);
+
+/*
  * Multi-curve batch: many light curves folded and scored in one persistent
  * launch (the paper processes a catalogue curve after curve, Sec. 3.4).
  * Setup (synchronous, allocates): sample_offsets_host[n_curves + 1] and
@@ -258,6 +270,20 @@ int32_t gpfc_cnn_forward(gpfc_cnn *cnn, const void *x, int32_t x_f32, int64_t B,
  */
 int32_t gpfc_cnn_backward(gpfc_cnn *cnn, const void *x, int32_t x_f32, const float *labels,
                           int64_t B, float *loss_out, float *grad_out, void *stream);
+
+/*
+ * FP8 inference of a bf16 network: calibration runs the bf16 forward on
+ * x[B][256] and records the largest activation entering each matrix-core
+ * layer (accumulated over calls unless reset != 0; synchronous). Forward in
+ * FP8 then rounds each layer's input, scaled so that maximum maps to 448, and
+ * its weights, scaled per output channel, to OCP E4M3, multiplies on the FP8
+ * matrix cores with FP32 accumulation and rescales in the epilogue.
+ * GPFC_EINVAL if the network is not bf16 or not calibrated.
+ */
+int32_t gpfc_cnn_calibrate_fp8(gpfc_cnn *cnn, const void *x, int32_t x_f32, int64_t B,
+                               int32_t reset, void *stream);
+int32_t gpfc_cnn_forward_fp8(gpfc_cnn *cnn, const void *x, int32_t x_f32, int64_t B, float *logits,
+                             void *stream);
 
 /* One bias-corrected Adam step on the FP32 masters with the last gradient. */
 int32_t gpfc_cnn_adam(gpfc_cnn *cnn, float lr, float beta1, float beta2, float eps, void *stream);

@@ -67,6 +67,7 @@ def load():
         "gpfc_prepare": ([vp, vp, vp, i64, vp], i32),
         "gpfc_fold_prepared": ([vp, vp, i64, i32, vp, vp, vp, vp], i32),
         "gpfc_fold_score_prepared": ([vp, vp, i64, i32, vp, vp, vp, vp, vp, vp], i32),
+        "gpfc_fold_f32_prepared": ([vp, vp, i64, i32, i32, vp, vp, vp, vp], i32),
         "gpfc_batch_setup": ([vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), i32], i32),
         "gpfc_batch_fold_score": ([vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp], i32),
         "gpfc_batch_capture": ([vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp], i32),
@@ -82,6 +83,8 @@ def load():
         "gpfc_cnn_forward": ([vp, vp, i32, i64, vp, vp], i32),
         "gpfc_cnn_backward": ([vp, vp, i32, vp, i64, vp, vp, vp], i32),
         "gpfc_cnn_adam": ([vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp], i32),
+        "gpfc_cnn_calibrate_fp8": ([vp, vp, i32, i64, i32, vp], i32),
+        "gpfc_cnn_forward_fp8": ([vp, vp, i32, i64, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -96,11 +99,13 @@ def exported_symbols():
     return ["gpfc_version", "gpfc_strerror", "gpfc_last_error", "gpfc_plan_create",
             "gpfc_plan_destroy", "gpfc_plan_set_widths", "gpfc_curve_stats", "gpfc_fold",
             "gpfc_score", "gpfc_fold_score", "gpfc_fold_naive", "gpfc_sync", "gpfc_prepare",
-            "gpfc_fold_prepared", "gpfc_fold_score_prepared", "gpfc_batch_setup",
+            "gpfc_fold_prepared", "gpfc_fold_score_prepared", "gpfc_fold_f32_prepared",
+            "gpfc_batch_setup",
             "gpfc_batch_fold_score", "gpfc_batch_capture", "gpfc_batch_replay",
             "gpfc_batch_curve_stats", "gpfc_cnn_nparams", "gpfc_cnn_last_error",
             "gpfc_cnn_create", "gpfc_cnn_destroy", "gpfc_cnn_set_params", "gpfc_cnn_get_params",
-            "gpfc_cnn_forward", "gpfc_cnn_backward", "gpfc_cnn_adam"]
+            "gpfc_cnn_forward", "gpfc_cnn_backward", "gpfc_cnn_adam", "gpfc_cnn_calibrate_fp8",
+            "gpfc_cnn_forward_fp8"]
 
 
 def _check(rc, what):
@@ -233,6 +238,19 @@ class Plan:
         _check(self.lib.gpfc_fold_prepared(self.h, _ptr(periods), k, nbins, _ptr(sums),
                                            _ptr(counts), _ptr(mo), _stream()), "gpfc_fold_prepared")
         return sums, counts, mo
+
+    def fold_f32_prepared(self, periods, nbins: int, compensated: bool):
+        """Fold of the prepared curve with FP32 (optionally TwoSum-compensated) bin sums."""
+        import torch
+        _need(periods, torch.float64, "periods", self.device)
+        k = periods.numel()
+        sums = torch.empty((k, nbins), dtype=torch.float64, device=self.device)
+        counts = torch.empty((k, nbins), dtype=torch.int32, device=self.device)
+        means = torch.empty((k, nbins), dtype=torch.float64, device=self.device)
+        _check(self.lib.gpfc_fold_f32_prepared(self.h, _ptr(periods), k, nbins, int(compensated),
+                                               _ptr(sums), _ptr(counts), _ptr(means), _stream()),
+               "gpfc_fold_f32_prepared")
+        return sums, counts, means
 
     def fold_score_prepared(self, periods, nbins: int, out=None, zfold=None):
         """Fused fold + score on the prepared curve; ``zfold`` (optional uint16
@@ -385,6 +403,24 @@ class Cnn:
         logits = out if out is not None else torch.empty(B, dtype=torch.float32, device=self.device)
         _check(self.lib.gpfc_cnn_forward(self.h, _ptr(x), xf, B, _ptr(logits), _stream()),
                "gpfc_cnn_forward")
+        return logits
+
+    def calibrate_fp8(self, x, reset: bool = True):
+        """Record activation maxima of a bf16 network on calibration folds x."""
+        xf = self._x(x)
+        _need(x, x.dtype, "x", self.device)
+        _check(self.lib.gpfc_cnn_calibrate_fp8(self.h, _ptr(x), xf, x.shape[0], int(reset), _stream()),
+               "gpfc_cnn_calibrate_fp8")
+
+    def forward_fp8(self, x, out=None):
+        """Logits with FP8 E4M3 matrix-core layers (after calibrate_fp8)."""
+        import torch
+        xf = self._x(x)
+        _need(x, x.dtype, "x", self.device)
+        B = x.shape[0]
+        logits = out if out is not None else torch.empty(B, dtype=torch.float32, device=self.device)
+        _check(self.lib.gpfc_cnn_forward_fp8(self.h, _ptr(x), xf, B, _ptr(logits), _stream()),
+               "gpfc_cnn_forward_fp8")
         return logits
 
     def backward(self, x, labels, grad_out=None):

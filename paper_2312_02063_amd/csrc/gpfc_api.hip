@@ -245,6 +245,20 @@ int32_t gpfc_fold_score_prepared(gpfc_plan* p, const double* periods, int64_t k,
     return GPFC_OK;
 }
 
+int32_t gpfc_fold_f32_prepared(gpfc_plan* p, const double* periods, int64_t k, int32_t nbins,
+                               int32_t compensated, double* sums, int32_t* counts, double* means,
+                               void* stream) {
+    int32_t rc = check_prepared(p, periods, k, nbins);
+    if (rc != GPFC_OK) return rc;
+    if (k > 0 && (!sums || !counts)) return GPFC_EINVAL;
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return device_error(e, "hipSetDevice");
+    e = gpfc::launch_fold_f32(p->rec, p->n, periods, k, nbins, compensated, p->info, sums, counts,
+                              means, (hipStream_t)stream);
+    if (e != hipSuccess) return device_error(e, "k_fold_f32 launch");
+    return GPFC_OK;
+}
+
 int32_t gpfc_fold(gpfc_plan* p, const double* t, const float* flux, int64_t n,
                   const double* periods, int64_t k, int32_t nbins, double* sums, int32_t* counts,
                   double* means, void* stream) {

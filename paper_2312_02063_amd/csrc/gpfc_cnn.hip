@@ -18,7 +18,9 @@
 #include <stdint.h>
 #include <stdio.h>
 
+#include <algorithm>
 #include <new>
+#include <string.h>
 
 #include "../../include/gpfc.h"
 
@@ -56,6 +58,32 @@ struct F32 {
     static __device__ __forceinline__ T from_f(float v) { return v; }
 };
 
+// OCP FP8 E4M3 (bias 7, max 448, no infinities): round to nearest even,
+// saturating at +-448; |f| < 2^-6 goes to the subnormals m * 2^-9.
+__device__ __forceinline__ uint8_t f2e4m3(float f) {
+    const uint32_t u = __float_as_uint(f);
+    const uint8_t sign = (uint8_t)((u >> 24) & 0x80);
+    const float a = fabsf(f);
+    if (!(a < 448.0f)) return (uint8_t)(sign | 0x7E);   // saturate (NaN too)
+    if (a < 0.015625f) return (uint8_t)(sign | (uint8_t)rintf(a * 512.0f));
+    uint32_t v = __float_as_uint(a);
+    v += 0x7FFFFu + ((v >> 20) & 1u);                     // RNE to 3 mantissa bits
+    uint32_t code = (v >> 20) - ((127u - 7u) << 3);
+    if (code > 0x7Eu) code = 0x7Eu;
+    return (uint8_t)(sign | code);
+}
+
+// Inference with FP8 E4M3 operands: activations (kept as bf16) are scaled by
+// a per-layer factor and rounded to E4M3 as they are loaded; weights are
+// pre-rounded with one scale per output channel; the epilogue multiplies the
+// FP32 accumulator back by both scales.
+struct FP8 {
+    using T = uint16_t;
+    static constexpr int KSTEP = 32;
+    static __device__ __forceinline__ float to_f(T v) { return bf2f(v); }
+    static __device__ __forceinline__ T from_f(float v) { return f2bf(v); }
+};
+
 // ------------------------------------------------------------------ generic MFMA GEMM
 //
 // C[m][n] = sum_k A(m, k) * B(n, k); A and B are given by loaders that fill
@@ -76,7 +104,15 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, LA la, LB lb,
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     for (int k0 = 0; k0 < K; k0 += P::KSTEP) {
-        if constexpr (P::KSTEP == 32) {
+        if constexpr (__is_same(P, FP8)) {
+            const int kk = k0 + q * 8;
+            long a[2], b[2];
+            for (int i = 0; i < 2; ++i) a[i] = la.frag8q(m0 + i * 16 + r, kk);
+            for (int j = 0; j < 2; ++j) b[j] = lb.frag8q(n0 + j * 16 + r, kk);
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a[i], b[j], acc[i][j], 0, 0, 0);
+        } else if constexpr (P::KSTEP == 32) {
             const int kk = k0 + q * 8;
             bf16x8 a[2], b[2];
             for (int i = 0; i < 2; ++i) a[i] = la.frag8(m0 + i * 16 + r, kk);
@@ -192,6 +228,37 @@ struct ConvCols {
     __device__ __forceinline__ float frag1(int n, int k) const { return at(n, k); }
 };
 
+// FP8 operand from a bf16 loader: scale, round to E4M3, pack 8 bytes.
+template <class Base>
+struct ActQ {
+    Base base;
+    float inv;
+    __device__ __forceinline__ long frag8q(int m, int k) const {
+        const bf16x8 v = base.frag8(m, k);
+        uint64_t r = 0;
+        for (int j = 0; j < 8; ++j) {
+            const float f = bf2f(__builtin_bit_cast(uint16_t, v[j])) * inv;
+            r |= (uint64_t)f2e4m3(f) << (8 * j);
+        }
+        return (long)r;
+    }
+};
+
+// FP8 weights stored as bytes, rows of ld.
+struct WQ {
+    const uint8_t* p;
+    int rows, ld, K;
+    __device__ __forceinline__ long frag8q(int n, int k) const {
+        if (n >= rows || k + 8 > K) {
+            uint64_t r = 0;
+            for (int j = 0; j < 8; ++j)
+                if (n < rows && k + j < K) r |= (uint64_t)p[(int64_t)n * ld + k + j] << (8 * j);
+            return (long)r;
+        }
+        return *reinterpret_cast<const long*>(p + (int64_t)n * ld + k);
+    }
+};
+
 // ---- epilogues
 
 // Conv forward: rows are (b, x) positions (4 consecutive per lane), columns
@@ -205,12 +272,14 @@ struct EpConvFwd {
     T* out;          // [b][L/2][C]
     uint8_t* mask;   // [b][L/2][C]
     int C;
+    const float* colscale;   // FP8 mode: product of the two scales per column
     __device__ __forceinline__ void operator()(int m, int n, f32x4 a, int M, int N) const {
         if (n >= N) return;
+        const float cs = colscale ? colscale[n] : 1.0f;
         for (int h = 0; h < 2; ++h) {
             const int mm = m + 2 * h;
             if (mm >= M) continue;
-            const float p0 = a[2 * h] + bias[n], p1 = a[2 * h + 1] + bias[n];
+            const float p0 = a[2 * h] * cs + bias[n], p1 = a[2 * h + 1] * cs + bias[n];
             const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
             const int w = r0 >= r1 ? 0 : 1;
             const float pv = w ? p1 : p0;
@@ -228,10 +297,12 @@ struct EpFcFwd {
     const float* bias;
     T* out;
     int ld;
+    const float* colscale;
     __device__ __forceinline__ void operator()(int m, int n, f32x4 a, int M, int N) const {
         if (n >= N) return;
+        const float cs = colscale ? colscale[n] : 1.0f;
         for (int i = 0; i < 4; ++i)
-            if (m + i < M) out[(int64_t)(m + i) * ld + n] = P::from_f(fmaxf(a[i] + bias[n], 0.0f));
+            if (m + i < M) out[(int64_t)(m + i) * ld + n] = P::from_f(fmaxf(a[i] * cs + bias[n], 0.0f));
     }
 };
 
@@ -471,6 +542,49 @@ __global__ __launch_bounds__(256) void k_pack(const float* __restrict__ w, typen
     }
 }
 
+// Largest value of a non-negative bf16 activation tensor (float bits order
+// like the values), accumulated into *out.
+__global__ __launch_bounds__(256) void k_absmax(const uint16_t* __restrict__ a, int64_t n,
+                                                uint32_t* __restrict__ out) {
+    __shared__ uint32_t red[256];
+    uint32_t mx = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        mx = max(mx, __float_as_uint(fabsf(bf2f(a[i]))));
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, red[0]);
+}
+
+// FP8 weights: one block per output row of a packed bf16 weight matrix
+// [rows][K]; scale = max|w| / 448 (1 for an all-zero row); the column scale
+// of the GEMM epilogue is scale * act_scale.
+__global__ __launch_bounds__(256) void k_quant_rows(const uint16_t* __restrict__ w, int K,
+                                                    uint8_t* __restrict__ q, float* __restrict__ colscale,
+                                                    const uint32_t* __restrict__ act_max) {
+    __shared__ float red[256];
+    const int row = blockIdx.x;
+    float mx = 0.0f;
+    for (int k = threadIdx.x; k < K; k += 256) mx = fmaxf(mx, fabsf(bf2f(w[(int64_t)row * K + k])));
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    const float sw = red[0] > 0.0f ? red[0] / 448.0f : 1.0f;
+    for (int k = threadIdx.x; k < K; k += 256)
+        q[(int64_t)row * K + k] = f2e4m3(bf2f(w[(int64_t)row * K + k]) / sw);
+    if (threadIdx.x == 0) {
+        const float am = __uint_as_float(*act_max);
+        const float sa = am > 0.0f ? am / 448.0f : 1.0f;
+        colscale[row] = sw * sa;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
                                               float* __restrict__ m, float* __restrict__ v, int64_t n,
                                               float lr, float b1, float b2, float eps, float c1,
@@ -521,6 +635,12 @@ struct gpfc_cnn {
     void *a1, *a2, *a3, *a4, *h1, *h2;       // activations
     void *d_a, *d_b;                          // gradient scratch (largest activation size)
     uint8_t *m1, *m2, *m3, *m4;
+    // FP8 inference (bf16 networks): E4M3 weights, per-column scales, activation maxima
+    uint8_t *q2, *q3, *q4, *qf1, *qf2;
+    float *cs2, *cs3, *cs4, *csf1, *csf2;
+    uint32_t* act_max;                        // [5] float bits: inputs of conv2..4, fc1, fc2
+    float act_max_host[5] = {0, 0, 0, 0, 0};
+    bool calibrated = false, quantized = false;
 };
 
 namespace {
@@ -677,6 +797,10 @@ int32_t gpfc_cnn_create(gpfc_cnn** out, int32_t device, int32_t precision, int64
     for (int i = 0; i < 4; ++i) total += al(asz[i]);   // masks
     const size_t fsz = al(sizeof(float) * gcnn::kNP);
     total += 4 * fsz + 256;
+    const size_t qsz[5] = {32 * 80, 64 * 160, 64 * 320, 256 * 1024, 64 * 256};
+    const size_t csz[5] = {32, 64, 64, 256, 64};
+    for (int i = 0; i < 5; ++i) total += al(qsz[i]) + al(csz[i] * sizeof(float));
+    total += 256;
     void* base = nullptr;
     e = hipMalloc(&base, total);
     if (e != hipSuccess) {
@@ -699,6 +823,13 @@ int32_t gpfc_cnn_create(gpfc_cnn** out, int32_t device, int32_t precision, int64
     c->d_b = take(dsz * E);
     uint8_t** mv[4] = {&c->m1, &c->m2, &c->m3, &c->m4};
     for (int i = 0; i < 4; ++i) *mv[i] = (uint8_t*)take(asz[i]);
+    uint8_t** qv[5] = {&c->q2, &c->q3, &c->q4, &c->qf1, &c->qf2};
+    float** cv[5] = {&c->cs2, &c->cs3, &c->cs4, &c->csf1, &c->csf2};
+    for (int i = 0; i < 5; ++i) {
+        *qv[i] = (uint8_t*)take(qsz[i]);
+        *cv[i] = (float*)take(csz[i] * sizeof(float));
+    }
+    c->act_max = (uint32_t*)take(256);
     *out = c;
     return GPFC_OK;
 }
@@ -723,6 +854,7 @@ int32_t gpfc_cnn_set_params(gpfc_cnn* c, const float* params, void* stream) {
     hipLaunchKernelGGL(gcnn::k_fill, dim3(nb), dim3(256), 0, s, c->v, (int64_t)gcnn::kNP, 0.0f);
     c->step = 0;
     c->packed = false;
+    c->quantized = false;
     e = hipGetLastError();
     return e == hipSuccess ? GPFC_OK : cnn_err(e, "set params");
 }
@@ -774,7 +906,91 @@ int32_t gpfc_cnn_adam(gpfc_cnn* c, float lr, float beta1, float beta2, float eps
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cnn_err(e, "k_adam");
     c->packed = false;
+    c->quantized = false;
     return GPFC_OK;
+}
+
+int32_t gpfc_cnn_calibrate_fp8(gpfc_cnn* c, const void* x, int32_t x_f32, int64_t B, int32_t reset,
+                               void* stream) {
+    if (!c || c->prec != GPFC_CNN_BF16 || B < 1 || B > c->max_batch || !x) return GPFC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (reset || !c->calibrated)
+        hipLaunchKernelGGL(gcnn::k_fill, dim3(1), dim3(256), 0, s, reinterpret_cast<float*>(c->act_max),
+                           (int64_t)5, 0.0f);
+    int32_t rc = forward<gcnn::BF16>(c, x, x_f32, (int)B, nullptr, nullptr, s);
+    // forward with no labels and no logits still fills the activations
+    if (rc != GPFC_OK) return rc;
+    const void* acts[5] = {c->a1, c->a2, c->a3, c->a4, c->h1};
+    const int64_t n[5] = {B * 128 * 16, B * 64 * 32, B * 32 * 64, B * 1024, B * 256};
+    for (int i = 0; i < 5; ++i) {
+        const unsigned nb = (unsigned)std::min<int64_t>((n[i] + 255) / 256, 1024);
+        hipLaunchKernelGGL(gcnn::k_absmax, dim3(nb), dim3(256), 0, s, (const uint16_t*)acts[i], n[i],
+                           c->act_max + i);
+    }
+    uint32_t h[5];
+    hipError_t e = hipMemcpyAsync(h, c->act_max, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return cnn_err(e, "calibrate");
+    for (int i = 0; i < 5; ++i) memcpy(&c->act_max_host[i], &h[i], 4);
+    c->calibrated = true;
+    c->quantized = false;
+    return GPFC_OK;
+}
+
+int32_t gpfc_cnn_forward_fp8(gpfc_cnn* c, const void* x, int32_t x_f32, int64_t B, float* logits,
+                             void* stream) {
+    using namespace gcnn;
+    if (!c || !c->calibrated || B < 0 || B > c->max_batch || (B > 0 && (!x || !logits)))
+        return GPFC_EINVAL;
+    if (B == 0) return GPFC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (!c->packed) {
+        int32_t rc = pack<BF16>(c, s);
+        if (rc != GPFC_OK) return rc;
+    }
+    if (!c->quantized) {
+        const void* wsrc[5] = {c->wf2, c->wf3, c->wf4, c->f1f, c->f2f};
+        const int rows[5] = {32, 64, 64, 256, 64};
+        const int Ks[5] = {80, 160, 320, 1024, 256};
+        uint8_t* qs[5] = {c->q2, c->q3, c->q4, c->qf1, c->qf2};
+        float* cs[5] = {c->cs2, c->cs3, c->cs4, c->csf1, c->csf2};
+        for (int i = 0; i < 5; ++i)
+            hipLaunchKernelGGL(k_quant_rows, dim3(rows[i]), dim3(256), 0, s, (const uint16_t*)wsrc[i],
+                               Ks[i], qs[i], cs[i], c->act_max + i);
+        e = hipGetLastError();
+        if (e != hipSuccess) return cnn_err(e, "k_quant_rows");
+        c->quantized = true;
+    }
+    float inv[5];
+    for (int i = 0; i < 5; ++i) inv[i] = c->act_max_host[i] > 0.0f ? 448.0f / c->act_max_host[i] : 1.0f;
+    const float* w = c->params;
+    using T = uint16_t;
+    const int Bi = (int)B;
+    hipLaunchKernelGGL((k_conv1_fwd<BF16>), dim3(blocks_for(B * 128 * 16)), dim3(256), 0, s, x, x_f32,
+                       Bi, w + kConvW[1], w + conv_b(1), (T*)c->a1, c->m1);
+    T* acts[5] = {nullptr, (T*)c->a1, (T*)c->a2, (T*)c->a3, (T*)c->a4};
+    uint8_t* masks[5] = {nullptr, c->m1, c->m2, c->m3, c->m4};
+    uint8_t* qw[5] = {nullptr, nullptr, c->q2, c->q3, c->q4};
+    float* cs[5] = {nullptr, nullptr, c->cs2, c->cs3, c->cs4};
+    for (int l = 2; l <= 4; ++l) {
+        const int Cin = CH[l - 1], Cout = CH[l], L = LEN[l - 1];
+        ActQ<ConvRows<BF16>> la{ConvRows<BF16>{acts[l - 1], L, Cin, Bi * L, +1}, inv[l - 2]};
+        WQ lb{qw[l], Cout, 5 * Cin, 5 * Cin};
+        EpConvFwd<BF16> ep{w + conv_b(l), acts[l], masks[l], Cout, cs[l]};
+        e = gemm<FP8>(Bi * L, Cout, 5 * Cin, la, lb, ep, s);
+        if (e != hipSuccess) return cnn_err(e, "conv gemm fp8");
+    }
+    e = gemm<FP8>(Bi, 256, 1024, ActQ<Rows<BF16>>{Rows<BF16>{(const T*)c->a4, Bi, 1024, 1024}, inv[3]},
+                  WQ{c->qf1, 256, 1024, 1024}, EpFcFwd<BF16>{w + F1B, (T*)c->h1, 256, c->csf1}, s);
+    if (e != hipSuccess) return cnn_err(e, "fc1 gemm fp8");
+    e = gemm<FP8>(Bi, 64, 256, ActQ<Rows<BF16>>{Rows<BF16>{(const T*)c->h1, Bi, 256, 256}, inv[4]},
+                  WQ{c->qf2, 64, 256, 256}, EpFcFwd<BF16>{w + F2B, (T*)c->h2, 64, c->csf2}, s);
+    if (e != hipSuccess) return cnn_err(e, "fc2 gemm fp8");
+    hipLaunchKernelGGL((k_head<BF16>), dim3(1), dim3(256), 0, s, (const T*)c->h2, Bi, w + F3W, w + F3B,
+                       (const float*)nullptr, logits, c->loss, c->grad, (T*)c->d_a);
+    e = hipGetLastError();
+    return e == hipSuccess ? GPFC_OK : cnn_err(e, "k_head fp8");
 }
 
 }  // extern "C"

@@ -77,6 +77,9 @@ hipError_t launch_batch_fold_score(const Rec* rec, const BatchCurve* curves, con
                                    const double* periods, int32_t nbins, const Widths& widths,
                                    int32_t grid, float* snr, int32_t* start, int32_t* width,
                                    float* depth, uint16_t* zfold, hipStream_t s);
+hipError_t launch_fold_f32(const Rec* rec, int64_t n, const double* periods, int64_t k, int32_t nbins,
+                           int32_t compensated, const CurveInfo* info, double* sums, int32_t* counts,
+                           double* means, hipStream_t s);
 hipError_t launch_score(const double* sums, const int32_t* counts, int64_t k, int32_t nbins,
                         double sigma, const Widths& widths, float* snr, int32_t* start,
                         int32_t* width, float* depth, hipStream_t s);

@@ -355,6 +355,75 @@ __global__ __launch_bounds__(kThreads, 1) void k_fold(
     }
 }
 
+// ------------------------------------------------------------------ FP32 fold sums (precision study)
+
+// Fold with FP32 bin sums accumulated by float LDS atomics, plain or
+// compensated: with kTwoSum the atomic returns the old sum, the lane
+// recomputes the rounded new sum and its exact error (TwoSum, Knuth) and adds
+// the error into a second float array. Deviations enter as float(q) * 2^e,
+// i.e. flux - ref rounded to FP32. 32 periods per block (lanes 32-63 idle):
+// counts u32, sums f32 and errors f32 at [bin][32] fill 96 KB. Bins use the
+// certified fast path with a per-update IEEE fallback.
+template <bool kTwoSum>
+__global__ __launch_bounds__(kThreads, 1) void k_fold_f32(
+    const Rec* __restrict__ rec, int64_t per, const double* __restrict__ periods, int64_t k,
+    int32_t log2g, const CurveInfo* __restrict__ info, double* __restrict__ sums,
+    int32_t* __restrict__ counts, double* __restrict__ means) {
+    __shared__ uint32_t hc[kFineBins * 32];
+    __shared__ float hs[kFineBins * 32];
+    __shared__ float he[kFineBins * 32];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t kk = (int64_t)blockIdx.x * 32 + (lane & 31);
+    const LaneSetup L = lane_setup(periods, kk, k, info->tmax);
+    for (int i = threadIdx.x; i < kFineBins * 32; i += kThreads) { hc[i] = 0; hs[i] = 0.0f; he[i] = 0.0f; }
+    __syncthreads();
+    const float qs = (float)info->qscale;
+    const Rec* p = rec + (int64_t)wave * per;
+    if (lane < 32) {
+        for (int64_t i = 0; i < per; ++i) {
+            const double ti = p[i].t;
+            const uint64_t ci = p[i].c;
+            if (ci == 0) continue;   // padding record
+            const uint32_t lo = fast_lo(ti, L);
+            uint32_t bin = (lo >> 16) & 255u;
+            if ((lo & 0xFFFFu) >= L.lim) bin = fine_bin_ieee(ti, L.P);
+            const int j = (int)bin * 32 + lane;
+            const float x = (float)((int64_t)(ci & kSumMask) - kBias) * qs;
+            atomicAdd(&hc[j], 1u);
+            if (kTwoSum) {
+                const float old = atomicAdd(&hs[j], x);
+                const float s = old + x;
+                const float bp = s - old;
+                const float err = (old - (s - bp)) + (x - bp);
+                atomicAdd(&he[j], err);
+            } else {
+                atomicAdd(&hs[j], x);
+            }
+        }
+    }
+    __syncthreads();
+    if (lane >= 32 || kk >= k) return;
+    const int g = 1 << log2g;
+    const int nb = kFineBins >> log2g;
+    const double ref = info->ref;
+    for (int b = wave; b < nb; b += kWaves) {
+        uint32_t c = 0;
+        double d = 0.0;
+        for (int jj = 0; jj < g; ++jj) {
+            const int j = (b * g + jj) * 32 + lane;
+            c += hc[j];
+            d += (double)hs[j] + (double)he[j];
+        }
+        if (!L.valid) { c = 0; d = 0.0; }
+        const double sm = c ? (double)c * ref + d : 0.0;
+        const int64_t o = kk * nb + b;
+        sums[o] = sm;
+        counts[o] = (int32_t)c;
+        if (means) means[o] = c ? sm / (double)c : __builtin_nan("");
+    }
+}
+
 // ------------------------------------------------------------------ box scan
 
 // Slot (row r, period lane j) of the prefix table that replaces the
@@ -867,6 +936,20 @@ hipError_t launch_batch_fold_score(const Rec* rec, const BatchCurve* curves, con
     hipLaunchKernelGGL(k_batch_fold_score, dim3((unsigned)std::min(grid, n_items)), dim3(kThreads), 0,
                        s, rec, curves, items, n_items, counter, infos, periods, 8 - log2_of(nbins),
                        widths, snr, start, width, depth, zfold);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_f32(const Rec* rec, int64_t n, const double* periods, int64_t k, int32_t nbins,
+                           int32_t compensated, const CurveInfo* info, double* sums, int32_t* counts,
+                           double* means, hipStream_t s) {
+    if (k == 0) return hipSuccess;
+    const int64_t blocks = (k + 31) / 32;
+    if (compensated)
+        hipLaunchKernelGGL(k_fold_f32<true>, dim3((unsigned)blocks), dim3(kThreads), 0, s, rec,
+                           fold_slice_len(n), periods, k, 8 - log2_of(nbins), info, sums, counts, means);
+    else
+        hipLaunchKernelGGL(k_fold_f32<false>, dim3((unsigned)blocks), dim3(kThreads), 0, s, rec,
+                           fold_slice_len(n), periods, k, 8 - log2_of(nbins), info, sums, counts, means);
     return hipGetLastError();
 }
 

@@ -231,3 +231,60 @@ def cnn_init(seed: int = 1003) -> np.ndarray:
         parts.append(rng.normal(0.0, np.sqrt(2.0 / fan_in), size=shape).ravel())
         parts.append(np.zeros(cout))
     return np.concatenate(parts)
+
+
+def training_params(rng: np.random.Generator, m: int, n: int = 4000,
+                    alpha_range: tuple = (3.0, 20.0), depth_range: tuple = (1e-5, 1e-3),
+                    pmin: float = 0.2, pmax: float = 1.0, dur_h: tuple = (0.5, 3.0)) -> dict:
+    """Per-curve parameters of ``m`` transit curves, vectorised (Sec. 2.6-2.7
+    recipe): sigma log-uniform [1e-4, 1e-3]; P log-uniform [pmin, pmax];
+    duration U(dur_h) hours; SNR alpha ~ U(alpha_range) turned into a depth by
+    Eq. 2 and redrawn until it lies in ``depth_range``; trapezoid base ratio
+    r ~ U(0, 1); epoch U[0, P)."""
+    out = {k: np.empty(m) for k in ("sigma", "period", "duration", "alpha", "depth", "ratio", "epoch")}
+    todo = np.arange(m)
+    while todo.size:
+        k = todo.size
+        sig = np.exp(rng.uniform(np.log(1e-4), np.log(1e-3), k))
+        per = np.exp(rng.uniform(np.log(pmin), np.log(pmax), k))
+        dur = rng.uniform(dur_h[0], dur_h[1], k) / 24.0
+        alp = rng.uniform(alpha_range[0], alpha_range[1], k)
+        dep = alp * sig / np.sqrt(n * dur / per)
+        ok = (dep >= depth_range[0]) & (dep <= depth_range[1])
+        idx = todo[ok]
+        for key, val in (("sigma", sig), ("period", per), ("duration", dur), ("alpha", alp), ("depth", dep)):
+            out[key][idx] = val[ok]
+        todo = todo[~ok]
+    out["ratio"] = rng.uniform(0.0, 1.0, m)
+    out["epoch"] = rng.uniform(0.0, 1.0, m) * out["period"]
+    return out
+
+
+def training_flux_torch(params: dict, positive: np.ndarray, noise_sigma: np.ndarray, n: int,
+                        seed: int, device="cuda"):
+    """Flux of a set of uniform-cadence curves (N = n) built on the GPU with a
+    seeded torch generator: 1 + N(0, sigma) plus, where ``positive``, the
+    trapezoid of ``params`` (same definition as ``trapezoid``). Returns
+    (t f64[n] numpy, flux f32[m, n] torch tensor)."""
+    import torch
+    m = positive.size
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    t = np.arange(n, dtype=np.float64) * CADENCE_D
+    tt = torch.tensor(t, dtype=torch.float64, device=device)[None, :]
+    f = torch.randn((m, n), generator=g, dtype=torch.float64, device=device)
+    f = 1.0 + f * torch.tensor(noise_sigma, dtype=torch.float64, device=device)[:, None]
+    pos = np.nonzero(positive)[0]
+    if pos.size:
+        P = torch.tensor(params["period"][pos], dtype=torch.float64, device=device)[:, None]
+        E = torch.tensor(params["epoch"][pos], dtype=torch.float64, device=device)[:, None]
+        L = torch.tensor(params["duration"][pos], dtype=torch.float64, device=device)[:, None]
+        D = torch.tensor(params["depth"][pos], dtype=torch.float64, device=device)[:, None]
+        R = torch.tensor(params["ratio"][pos], dtype=torch.float64, device=device)[:, None]
+        long_b = 2.0 * L / (1.0 + R)
+        short_b = R * long_b
+        x = torch.abs(torch.remainder(tt - E + 0.5 * P, P) - 0.5 * P)
+        ramp = D * (0.5 * long_b - x) / torch.clamp(0.5 * (long_b - short_b), min=1e-300)
+        prof = torch.where(x <= 0.5 * short_b, D, torch.where(x < 0.5 * long_b, ramp, torch.zeros_like(x)))
+        f[torch.tensor(pos, device=device)] -= prof
+    return t, f.to(torch.float32)

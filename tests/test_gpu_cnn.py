@@ -163,3 +163,26 @@ def test_training_on_folds_reduces_loss(torch_dev):
     last = net.backward(z, labels).item()
     print(f"training loss {first:.4f} -> {last:.4f}")
     assert last < 0.5 * first
+
+
+def test_fp8_forward_error(torch_dev):
+    """FP8 E4M3 inference after calibration: error against FP64 printed and
+    bounded; an uncalibrated FP8 call is rejected."""
+    torch = torch_dev
+    from paper_2312_02063_amd import CNN_BF16, GpfcError
+    p = _params(15)
+    xc, _ = _inputs(16, 256)
+    x, _ = _inputs(17, 200)
+    net = _net(torch, CNN_BF16, p)
+    xt = torch.tensor(x, dtype=torch.float32, device="cuda")
+    with pytest.raises(GpfcError):
+        net.forward_fp8(xt)
+    _say("cnn fp8 calibrate + forward")
+    net.calibrate_fp8(torch.tensor(xc, dtype=torch.float32, device="cuda"))
+    z8 = net.forward_fp8(xt).cpu().numpy()
+    zb = net.forward(xt).cpu().numpy()
+    zo = oracle.cnn_forward(p, x)
+    e8, eb = _rel(z8, zo), _rel(zb, zo)
+    print(f"fp8 forward relative L2 error vs FP64: {e8:.3e} (bf16 {eb:.3e})")
+    assert e8 < 0.15
+    assert np.corrcoef(z8, zo)[0, 1] > 0.99

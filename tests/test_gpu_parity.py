@@ -302,3 +302,25 @@ def test_full_size_fold_counts_block(torch_dev, plan):
     c = synth.kepler_long_curve(1002)
     periods = synth.freq_grid(1.0, 5.0, 2_000_000)[1_000_000:1_004_096]
     check_fold(torch_dev, plan, c.t, c.flux, periods, 256, "C2-block")
+
+
+@pytest.mark.parametrize("compensated", [False, True])
+def test_fold_f32_sums(torch_dev, plan, compensated):
+    """FP32 bin sums (plain or TwoSum-compensated): counts bit-exact; bin
+    means within the FP32 bound; compensation is at least as accurate."""
+    torch = torch_dev
+    c = synth.kepler_long_curve(1002)
+    periods = synth.freq_grid(1.0, 5.0, 2_000_000)[::4096][:300]
+    _say(f"fold_f32 compensated={compensated}")
+    plan.prepare(_dev(torch, c.t, torch.float64), _dev(torch, c.flux, torch.float32))
+    sums, counts, means = plan.fold_f32_prepared(_dev(torch, periods, torch.float64), 256, compensated)
+    torch.cuda.synchronize()
+    osums, _, ocounts = oracle.fold(c.t, c.flux, periods, 256, nthreads=8)
+    assert np.array_equal(counts.cpu().numpy(), ocounts)
+    om = oracle.means(osums, ocounts)
+    gm = means.cpu().numpy()
+    ok = ocounts > 0
+    err = np.abs(gm[ok] - om[ok])
+    # each of ~254 float additions of |dev| <~ 2e-3 rounds by <= 2^-24 |partial sum|
+    assert err.max() < 1e-8
+    print(f"fp32 {'compensated' if compensated else 'plain'}: max |bin mean error| {err.max():.3e}")
