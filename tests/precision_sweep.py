@@ -7,17 +7,25 @@ logits against the FP64 network on the same normalised folds. Every error is
 reported per result, on the Kepler-long curve (65,000 samples) at a seeded
 sample of the 2,000,000-period grid plus the best periods.
 
-    python -m paper_2312_02063_amd.precision [--periods 20000] [--cnn-folds 2000]
+This is test infrastructure (it runs the oracle): python tests/precision_sweep.py
+
+    python tests/precision_sweep.py [--periods 20000] [--cnn-folds 2000]
 """
 from __future__ import annotations
 
 import argparse
 import json
+import os
+import sys
 
 import numpy as np
 
-from . import synth
-from ._lib import CNN_BF16, CNN_FP32, Cnn, Plan
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_2312_02063_amd import synth  # noqa: E402
+from paper_2312_02063_amd._lib import CNN_BF16, CNN_FP32, Cnn, Plan  # noqa: E402
 
 NBINS = 256
 
