@@ -57,6 +57,9 @@ def _load():
     lib.oracle_means.restype = None
     lib.oracle_default_widths.argtypes = [i32, ip, i32]
     lib.oracle_default_widths.restype = i32
+    lib.oracle_topk.argtypes = [fp, fp, ctypes.c_float, i64, i64, i32, fp,
+                                ctypes.POINTER(ctypes.c_int64)]
+    lib.oracle_topk.restype = None
     lib.oracle_score.argtypes = [ip, dp, i64, i32, ctypes.c_double, ip, i32, dp, ip, ip, dp]
     lib.oracle_score.restype = None
     lib.oracle_box_snr.argtypes = [ip, dp, i32, ctypes.c_double, i32, i32]
@@ -214,6 +217,24 @@ def fold_score(t, flux, periods, nbins, widths=None, nthreads=1):
 
 
 # ---------------------------------------------------------------- learned scorer (Sec. 2.5)
+
+def topk(values, top, gate=None, gate_min=0.0):
+    """Per-row best `top` entries of a periodogram (Sec. 2.1, Sec. 3.2): value
+    descending, then index ascending; NaN values and entries whose gate is not
+    >= gate_min are skipped; missing places are (-inf, -1).
+    values f32 [rows, len] -> (f32 [rows, top], int64 [rows, top])."""
+    v = np.ascontiguousarray(values, dtype=np.float32)
+    if v.ndim == 1:
+        v = v[None, :]
+    rows, n = v.shape
+    g = None if gate is None else np.ascontiguousarray(gate, dtype=np.float32).reshape(rows, n)
+    ov = np.empty((rows, top), np.float32)
+    oi = np.empty((rows, top), np.int64)
+    _load().oracle_topk(_p(v, ctypes.c_float), None if g is None else _p(g, ctypes.c_float),
+                        ctypes.c_float(gate_min), rows, n, top, _p(ov, ctypes.c_float),
+                        _p(oi, ctypes.c_int64))
+    return ov, oi
+
 
 def cnn_nparams() -> int:
     return int(_load().oracle_cnn_nparams())

@@ -269,3 +269,44 @@ void oracle_normalize(const double *sums, const int32_t *counts, int64_t k, int3
 double oracle_grid_size(double n_o, double span, double width) {
     return n_o * span / width;
 }
+
+/*
+ * Per-curve reduction of a periodogram (Sec. 2.1: the best of the scores over
+ * all trial periods is the curve's detection; Sec. 3.2: the maximum score over
+ * periods is the statistic a threshold is applied to). For each row of `rows`
+ * rows of `len` scores: the `top` best entries, best first, where an entry is
+ * a candidate when its value is not NaN and, if `gate` is given, gate >=
+ * gate_min (a NaN gate never passes); order is by value descending, then by
+ * index ascending. Missing places get value -inf and index -1.
+ *
+ * Plain selection: pick j is the best candidate strictly after pick j-1 in
+ * that order (keys are unique because indices are).
+ */
+void oracle_topk(const float *values, const float *gate, float gate_min, int64_t rows, int64_t len,
+                 int32_t top, float *out_val, int64_t *out_idx) {
+    for (int64_t r = 0; r < rows; ++r) {
+        const float *v = values + r * len;
+        const float *g = gate ? gate + r * len : 0;
+        float pv = 0.0f;
+        int64_t pi = -1;             /* previous pick; -1: none yet */
+        for (int32_t j = 0; j < top; ++j) {
+            int64_t bi = -1;
+            float bv = 0.0f;
+            for (int64_t i = 0; i < len; ++i) {
+                if (isnan(v[i])) continue;
+                if (g && !(g[i] >= gate_min)) continue;
+                /* must come strictly after the previous pick in the order */
+                if (pi >= 0 && !(v[i] < pv || (v[i] == pv && i > pi))) continue;
+                if (bi < 0 || v[i] > bv || (v[i] == bv && i < bi)) { bi = i; bv = v[i]; }
+            }
+            out_val[r * top + j] = bi >= 0 ? bv : -INFINITY;
+            out_idx[r * top + j] = bi;
+            if (bi < 0) {
+                for (int32_t q = j + 1; q < top; ++q) { out_val[r * top + q] = -INFINITY; out_idx[r * top + q] = -1; }
+                break;
+            }
+            pv = bv;
+            pi = bi;
+        }
+    }
+}
