@@ -176,12 +176,13 @@ int32_t gpfc_fold_f32_prepared(gpfc_plan *plan, const double *periods, int64_t k
 
 /*
  * Multi-curve batch: many light curves folded and scored in one persistent
- * launch (the paper processes a catalogue curve after curve, Sec. 3.4).
+ * launch (the paper processes a catalogue curve after curve, overlapping the fold of one
+ * curve with the network on the previous one, Sec. 3.3).
  * Setup (synchronous, allocates): sample_offsets_host[n_curves + 1] and
  * period_offsets_host[n_curves + 1] (HOST arrays, starting at 0) cut the
  * concatenated t / flux and periods arrays into curves. Work items (a curve
  * and a block of 64 of its periods) are queued longest curve first. A later
- * setup replaces the batch.
+ * setup (or gpfc_survey_setup) replaces the batch.
  */
 int32_t gpfc_batch_setup(gpfc_plan *plan, const int64_t *sample_offsets_host,
                          const int64_t *period_offsets_host, int32_t n_curves);
@@ -287,6 +288,78 @@ int32_t gpfc_cnn_forward_fp8(gpfc_cnn *cnn, const void *x, int32_t x_f32, int64_
 
 /* One bias-corrected Adam step on the FP32 masters with the last gradient. */
 int32_t gpfc_cnn_adam(gpfc_cnn *cnn, float lr, float beta1, float beta2, float eps, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Per-curve reduction (Sec. 2.1: a curve's detection is the trial period
+ * with the best score; Sec. 3.2: the maximum score over trial periods is the
+ * statistic thresholded for the ROC). For each of `rows` rows of `len`
+ * scores values[rows][len]: the `top` best entries, best first, ordered by
+ * value descending and then by index ascending, into out_val[rows][top] and
+ * out_idx[rows][top] (index within the row). NaN values are skipped, and so
+ * is every entry whose gate[rows][len] value is not >= gate_min when gate is
+ * not NULL (a NaN gate never passes). Places without an entry get -inf and
+ * -1. 1 <= top <= 64. Device pointers; asynchronous on `stream`.
+ * ------------------------------------------------------------------------ */
+#define GPFC_MAX_TOP 64
+int32_t gpfc_topk(const float *values, int64_t rows, int64_t len, const float *gate,
+                  float gate_min, int32_t top, float *out_val, int64_t *out_idx, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Survey: many curves of uneven length, each folded and scored at the same
+ * K trial periods, and each fold scored by the network (the paper searches
+ * a catalogue curve by curve, Sec. 3.3 and Sec. 4; here the curves share one
+ * persistent launch per chunk). Setup (synchronous, allocates):
+ * sample_offsets_host[n_curves + 1] (HOST, from 0) cut the concatenated
+ * t / flux into curves; every curve uses periods[0..k). Curves are taken in
+ * chunks of max(1, chunk_folds / k) consecutive curves; a chunk's work items
+ * (a curve and 64 of its periods) run longest curve first in one persistent
+ * launch, which writes the chunk's bfloat16 normalised folds to a workspace
+ * of chunk_folds (at least k) x 256 values; the network then scores them.
+ * chunk_folds = 0: no network, all curves in one launch, no workspace.
+ * A later gpfc_survey_setup or gpfc_batch_setup replaces it.
+ * ------------------------------------------------------------------------ */
+typedef struct gpfc_survey_out {
+    float *snr;              /* [n_curves][k] box-SNR, as gpfc_score */
+    int32_t *start;          /* [n_curves][k] */
+    int32_t *width;          /* [n_curves][k] */
+    float *depth;            /* [n_curves][k] */
+    float *logits;           /* [n_curves][k] network logits; NULL: no network */
+    int32_t cnn_fp8;         /* 1: FP8 E4M3 inference (calibrated bf16 network) */
+    int32_t top;             /* 0..64 best entries per curve; 0: no reduction */
+    float *box_val;          /* [n_curves][top] best box-SNRs and their period indices */
+    int64_t *box_idx;
+    float *cnn_val;          /* [n_curves][top] best logits (needs logits), or NULL */
+    int64_t *cnn_idx;
+    float judge_snr;         /* the best logits among periods with snr >= judge_snr */
+    float *judged_val;       /* [n_curves][top], or NULL */
+    int64_t *judged_idx;
+} gpfc_survey_out;
+
+int32_t gpfc_survey_setup(gpfc_plan *plan, const int64_t *sample_offsets_host, int32_t n_curves,
+                          int64_t k, int64_t chunk_folds);
+
+/*
+ * Run the survey: per-curve statistics and packing, then per chunk the
+ * persistent fold + box-SNR (+ normalised folds) launch and, with a network
+ * (cnn not NULL, nbins 256, out->logits not NULL), its forward pass over the
+ * chunk's folds in batches of at most its max_batch; then the per-curve
+ * reductions of out->top. t f64[total samples], flux f32[...], periods
+ * f64[k]. GPFC_EINVAL for a plan without a survey setup, missing outputs, a
+ * network without a workspace or an uncalibrated FP8 request.
+ */
+int32_t gpfc_survey_run(gpfc_plan *plan, gpfc_cnn *cnn, const double *t, const float *flux,
+                        const double *periods, int32_t nbins, const gpfc_survey_out *out,
+                        void *stream);
+
+/*
+ * Record gpfc_survey_run's whole launch sequence for these buffers into the
+ * plan's HIP graph (kernel nodes only; replay with gpfc_batch_replay). The
+ * network's weights are those packed at capture time: capture again after
+ * changing them. `stream` must be a created stream, not the null stream.
+ */
+int32_t gpfc_survey_capture(gpfc_plan *plan, gpfc_cnn *cnn, const double *t, const float *flux,
+                            const double *periods, int32_t nbins, const gpfc_survey_out *out,
+                            void *stream);
 
 /* hipStreamSynchronize(stream); reports an asynchronous device error. */
 int32_t gpfc_sync(void *stream);

@@ -43,6 +43,16 @@ class Curve(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class SurveyOut(ctypes.Structure):
+    """Host mirror of ``gpfc_survey_out`` (device pointers)."""
+    _fields_ = [("snr", ctypes.c_void_p), ("start", ctypes.c_void_p), ("width", ctypes.c_void_p),
+                ("depth", ctypes.c_void_p), ("logits", ctypes.c_void_p), ("cnn_fp8", ctypes.c_int32),
+                ("top", ctypes.c_int32), ("box_val", ctypes.c_void_p), ("box_idx", ctypes.c_void_p),
+                ("cnn_val", ctypes.c_void_p), ("cnn_idx", ctypes.c_void_p),
+                ("judge_snr", ctypes.c_float), ("judged_val", ctypes.c_void_p),
+                ("judged_idx", ctypes.c_void_p)]
+
+
 def load():
     """Load ``libgpfc.so``; raises if it has not been built."""
     global _lib
@@ -74,6 +84,10 @@ def load():
         "gpfc_batch_replay": ([vp, vp], i32),
         "gpfc_batch_curve_stats": ([vp, ctypes.POINTER(Curve), vp], i32),
         "gpfc_sync": ([vp], i32),
+        "gpfc_topk": ([vp, i64, i64, vp, ctypes.c_float, i32, vp, vp, vp], i32),
+        "gpfc_survey_setup": ([vp, ctypes.POINTER(ctypes.c_int64), i32, i64, i64], i32),
+        "gpfc_survey_run": ([vp, vp, vp, vp, vp, i32, ctypes.POINTER(SurveyOut), vp], i32),
+        "gpfc_survey_capture": ([vp, vp, vp, vp, vp, i32, ctypes.POINTER(SurveyOut), vp], i32),
         "gpfc_cnn_nparams": ([], i32),
         "gpfc_cnn_last_error": ([], ctypes.c_char_p),
         "gpfc_cnn_create": ([ctypes.POINTER(vp), i32, i32, i64], i32),
@@ -105,7 +119,8 @@ def exported_symbols():
             "gpfc_batch_curve_stats", "gpfc_cnn_nparams", "gpfc_cnn_last_error",
             "gpfc_cnn_create", "gpfc_cnn_destroy", "gpfc_cnn_set_params", "gpfc_cnn_get_params",
             "gpfc_cnn_forward", "gpfc_cnn_backward", "gpfc_cnn_adam", "gpfc_cnn_calibrate_fp8",
-            "gpfc_cnn_forward_fp8"]
+            "gpfc_cnn_forward_fp8", "gpfc_topk", "gpfc_survey_setup", "gpfc_survey_run",
+            "gpfc_survey_capture"]
 
 
 def _check(rc, what):
@@ -324,6 +339,71 @@ class Plan:
         _check(self.lib.gpfc_batch_curve_stats(self.h, arr, _stream()), "gpfc_batch_curve_stats")
         return [arr[i].as_dict() for i in range(self.batch_n)]
 
+    # ---------------------------------------------------------------- surveys
+
+    def survey_setup(self, sample_offsets, k: int, chunk_folds: int = 0):
+        """Curves cut from concatenated t / flux by host offsets, all folded at
+        the same k periods; chunk_folds > 0 reserves the workspace the network
+        needs (curves are taken max(1, chunk_folds // k) at a time)."""
+        so = [int(x) for x in sample_offsets]
+        a = (ctypes.c_int64 * len(so))(*so)
+        _check(self.lib.gpfc_survey_setup(self.h, a, len(so) - 1, int(k), int(chunk_folds)),
+               "gpfc_survey_setup")
+        self.survey_n = len(so) - 1
+        self.survey_k = int(k)
+        self.survey_samples = so[-1]
+
+    def _survey_args(self, t, flux, periods, cnn, top, judge_snr, fp8):
+        import torch
+        _need(t, torch.float64, "t", self.device)
+        _need(flux, torch.float32, "flux", self.device)
+        _need(periods, torch.float64, "periods", self.device)
+        if t.numel() != self.survey_samples or flux.numel() != self.survey_samples:
+            raise ValueError("t / flux do not match the survey's sample offsets")
+        if periods.numel() != self.survey_k:
+            raise ValueError("periods must hold the survey's k periods")
+        m, k = self.survey_n, self.survey_k
+        e = lambda dt: torch.empty((m, k), dtype=dt, device=self.device)  # noqa: E731
+        r = {"snr": e(torch.float32), "start": e(torch.int32), "width": e(torch.int32),
+             "depth": e(torch.float32)}
+        if cnn is not None:
+            r["logits"] = e(torch.float32)
+        o = SurveyOut(snr=_ptr(r["snr"]), start=_ptr(r["start"]), width=_ptr(r["width"]),
+                      depth=_ptr(r["depth"]), logits=_ptr(r.get("logits")), cnn_fp8=int(bool(fp8)),
+                      top=int(top), judge_snr=float(judge_snr))
+        if top > 0:
+            t2 = lambda dt: torch.empty((m, top), dtype=dt, device=self.device)  # noqa: E731
+            r["box_val"], r["box_idx"] = t2(torch.float32), t2(torch.int64)
+            o.box_val, o.box_idx = _ptr(r["box_val"]), _ptr(r["box_idx"])
+            if cnn is not None:
+                r["cnn_val"], r["cnn_idx"] = t2(torch.float32), t2(torch.int64)
+                r["judged_val"], r["judged_idx"] = t2(torch.float32), t2(torch.int64)
+                o.cnn_val, o.cnn_idx = _ptr(r["cnn_val"]), _ptr(r["cnn_idx"])
+                o.judged_val, o.judged_idx = _ptr(r["judged_val"]), _ptr(r["judged_idx"])
+        return r, o
+
+    def survey_run(self, t, flux, periods, nbins: int = 256, cnn=None, top: int = 1,
+                   judge_snr: float = 0.0, fp8: bool = False):
+        """Fold, box-score and (with `cnn`) network-score every curve at every
+        period; returns a dict of [n_curves, k] periodograms and, for top > 0,
+        the [n_curves, top] best entries by box-SNR, by logit and by logit
+        among periods with snr >= judge_snr."""
+        r, o = self._survey_args(t, flux, periods, cnn, top, judge_snr, fp8)
+        _check(self.lib.gpfc_survey_run(self.h, cnn.h if cnn is not None else None, _ptr(t),
+                                        _ptr(flux), _ptr(periods), nbins, ctypes.byref(o),
+                                        _stream()), "gpfc_survey_run")
+        return r
+
+    def survey_capture(self, t, flux, periods, nbins: int = 256, cnn=None, top: int = 1,
+                       judge_snr: float = 0.0, fp8: bool = False):
+        """Capture survey_run into the plan's HIP graph (replay with batch_replay)."""
+        r, o = self._survey_args(t, flux, periods, cnn, top, judge_snr, fp8)
+        self._graph_keep = (t, flux, periods, r, cnn)
+        _check(self.lib.gpfc_survey_capture(self.h, cnn.h if cnn is not None else None, _ptr(t),
+                                            _ptr(flux), _ptr(periods), nbins, ctypes.byref(o),
+                                            _stream()), "gpfc_survey_capture")
+        return r
+
     def fold_naive(self, t, flux, periods, nbins: int, out=None):
         """Plain global-atomic GPU fold (baseline): (sums, counts)."""
         import torch
@@ -341,6 +421,24 @@ class Plan:
 
     def sync(self):
         _check(self.lib.gpfc_sync(_stream()), "gpfc_sync")
+
+
+def topk(values, top: int = 1, gate=None, gate_min: float = 0.0):
+    """Per-row best `top` (<= 64) entries of values f32 [rows, len] (value
+    descending, index ascending; NaN and gated-out entries skipped; missing
+    places -inf / -1): (f32 [rows, top], int64 [rows, top])."""
+    import torch
+    v = values if values.dim() == 2 else values.reshape(1, -1)
+    _need(v, torch.float32, "values", v.device)
+    if gate is not None:
+        gate = gate.reshape(v.shape)
+        _need(gate, torch.float32, "gate", v.device)
+    rows, n = v.shape
+    ov = torch.empty((rows, top), dtype=torch.float32, device=v.device)
+    oi = torch.empty((rows, top), dtype=torch.int64, device=v.device)
+    _check(load().gpfc_topk(_ptr(v), rows, n, _ptr(gate), float(gate_min), int(top), _ptr(ov),
+                            _ptr(oi), _stream()), "gpfc_topk")
+    return ov, oi
 
 
 CNN_BF16, CNN_FP32 = 0, 1

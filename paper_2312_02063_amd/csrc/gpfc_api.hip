@@ -14,6 +14,12 @@
 using gpfc::CurveInfo;
 using gpfc::Widths;
 
+// Curves [c0, c1) of a survey and their work items [i0, i1).
+struct SurveyChunk {
+    int32_t c0, c1;
+    int32_t i0, i1;
+};
+
 struct gpfc_plan {
     int32_t device = 0;
     gpfc::Rec* rec = nullptr;     // prepared curve: times and packed contributions
@@ -35,6 +41,12 @@ struct gpfc_plan {
     int32_t* b_counter = nullptr;
     CurveInfo* b_info = nullptr;
     gpfc::Rec* b_rec = nullptr;
+    // survey (gpfc_survey_setup): shared period grid, curves in chunks
+    bool b_survey = false;
+    int64_t s_k = 0;                   // periods per curve
+    uint16_t* s_zbuf = nullptr;        // normalised folds of one chunk (inside b_dev)
+    int64_t s_zfolds = 0;              // folds s_zbuf holds (0: no workspace)
+    std::vector<SurveyChunk> s_chunks;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
 };
@@ -318,36 +330,18 @@ int32_t gpfc_fold_naive(gpfc_plan* p, const double* t, const float* flux, int64_
     return GPFC_OK;
 }
 
-int32_t gpfc_batch_setup(gpfc_plan* p, const int64_t* soff, const int64_t* poff, int32_t n_curves) {
-    if (!p || !soff || !poff || n_curves < 0) return GPFC_EINVAL;
-    if (soff[0] != 0 || poff[0] != 0) return GPFC_EINVAL;
-    int64_t recs = 0, maxr = 0, items = 0;
-    std::vector<int64_t> roff(n_curves + 1);
-    std::vector<gpfc::BatchCurve> curves(n_curves);
-    roff[0] = 0;
-    for (int32_t c = 0; c < n_curves; ++c) {
-        const int64_t n = soff[c + 1] - soff[c];
-        const int64_t k = poff[c + 1] - poff[c];
-        if (n < 0 || k < 0) return GPFC_EINVAL;
-        if (n > GPFC_MAX_SAMPLES) return GPFC_ERANGE;
-        const int64_t r = gpfc::prepared_len(n);
-        curves[c] = gpfc::BatchCurve{recs, gpfc::slice_len(n), poff[c], k};
-        recs += r;
-        roff[c + 1] = recs;
-        maxr = r > maxr ? r : maxr;
-        items += (k + 63) / 64;
-    }
-    if (items > 0x7fffffffLL) return GPFC_ERANGE;
-    // Items, longest curve first (then curve, then block order).
-    std::vector<int2> it;
-    it.reserve((size_t)items);
-    std::vector<int32_t> order(n_curves);
-    for (int32_t c = 0; c < n_curves; ++c) order[c] = c;
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        return soff[a + 1] - soff[a] > soff[b + 1] - soff[b];
-    });
-    for (int32_t c : order)
-        for (int64_t j = 0; j < (curves[c].k + 63) / 64; ++j) it.push_back(make_int2(c, (int)j));
+// Allocate and upload a batch: per-curve offsets, curve table, work items,
+// counter, curve statistics, prepared records and `extra` bytes of workspace
+// (returned in *extra_ptr). Replaces any earlier batch or survey.
+static int32_t batch_upload(gpfc_plan* p, const int64_t* soff, int32_t n_curves,
+                            const std::vector<int64_t>& roff,
+                            const std::vector<gpfc::BatchCurve>& curves,
+                            const std::vector<int2>& it, int64_t periods, size_t extra,
+                            void** extra_ptr) {
+    const int64_t recs = roff[n_curves];
+    const int64_t items = (int64_t)it.size();
+    int64_t maxr = 0;
+    for (int32_t c = 0; c < n_curves; ++c) maxr = std::max<int64_t>(maxr, roff[c + 1] - roff[c]);
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return device_error(e, "hipSetDevice");
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
@@ -357,7 +351,7 @@ int32_t gpfc_batch_setup(gpfc_plan* p, const int64_t* soff, const int64_t* poff,
     const size_t sz_ctr = 256;
     const size_t sz_inf = al(sizeof(CurveInfo) * (n_curves > 0 ? n_curves : 1));
     const size_t sz_rec = al(sizeof(gpfc::Rec) * (recs > 0 ? recs : 1));
-    const size_t total = 2 * sz_off + sz_cur + sz_it + sz_ctr + sz_inf + sz_rec;
+    const size_t total = 2 * sz_off + sz_cur + sz_it + sz_ctr + sz_inf + sz_rec + al(extra);
     if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
     if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
     if (p->b_dev) {
@@ -366,6 +360,10 @@ int32_t gpfc_batch_setup(gpfc_plan* p, const int64_t* soff, const int64_t* poff,
         p->b_dev = nullptr;
     }
     p->b_curves = -1;
+    p->b_survey = false;
+    p->s_zbuf = nullptr;
+    p->s_zfolds = 0;
+    p->s_chunks.clear();
     e = hipMalloc(&p->b_dev, total);
     if (e != hipSuccess) {
         p->b_dev = nullptr;
@@ -378,7 +376,8 @@ int32_t gpfc_batch_setup(gpfc_plan* p, const int64_t* soff, const int64_t* poff,
     p->b_item = (int2*)base; base += sz_it;
     p->b_counter = (int32_t*)base; base += sz_ctr;
     p->b_info = (CurveInfo*)base; base += sz_inf;
-    p->b_rec = (gpfc::Rec*)base;
+    p->b_rec = (gpfc::Rec*)base; base += sz_rec;
+    *extra_ptr = extra ? (void*)base : nullptr;
     e = hipMemcpy(p->b_soff, soff, sizeof(int64_t) * (n_curves + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->b_roff, roff.data(), sizeof(int64_t) * (n_curves + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess && n_curves > 0)
@@ -388,10 +387,91 @@ int32_t gpfc_batch_setup(gpfc_plan* p, const int64_t* soff, const int64_t* poff,
     if (e != hipSuccess) return device_error(e, "batch table upload");
     p->b_curves = n_curves;
     p->b_samples = soff[n_curves];
-    p->b_periods = poff[n_curves];
+    p->b_periods = periods;
     p->b_records = recs;
     p->b_max_records = maxr;
     p->b_items = (int32_t)items;
+    return GPFC_OK;
+}
+
+// Work items of curves [c0, c1): every block of 64 periods, longest curve first.
+static void push_items(std::vector<int2>& it, const int64_t* soff, int32_t c0, int32_t c1,
+                       const std::vector<gpfc::BatchCurve>& curves) {
+    std::vector<int32_t> order;
+    for (int32_t c = c0; c < c1; ++c) order.push_back(c);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return soff[a + 1] - soff[a] > soff[b + 1] - soff[b];
+    });
+    for (int32_t c : order)
+        for (int64_t j = 0; j < (curves[c].k + 63) / 64; ++j) it.push_back(make_int2(c, (int)j));
+}
+
+int32_t gpfc_batch_setup(gpfc_plan* p, const int64_t* soff, const int64_t* poff, int32_t n_curves) {
+    if (!p || !soff || !poff || n_curves < 0) return GPFC_EINVAL;
+    if (soff[0] != 0 || poff[0] != 0) return GPFC_EINVAL;
+    int64_t recs = 0, items = 0;
+    std::vector<int64_t> roff(n_curves + 1);
+    std::vector<gpfc::BatchCurve> curves(n_curves);
+    roff[0] = 0;
+    for (int32_t c = 0; c < n_curves; ++c) {
+        const int64_t n = soff[c + 1] - soff[c];
+        const int64_t k = poff[c + 1] - poff[c];
+        if (n < 0 || k < 0) return GPFC_EINVAL;
+        if (n > GPFC_MAX_SAMPLES) return GPFC_ERANGE;
+        curves[c] = gpfc::BatchCurve{recs, gpfc::slice_len(n), poff[c], k, poff[c], poff[c]};
+        recs += gpfc::prepared_len(n);
+        roff[c + 1] = recs;
+        items += (k + 63) / 64;
+    }
+    if (items > 0x7fffffffLL) return GPFC_ERANGE;
+    std::vector<int2> it;
+    it.reserve((size_t)items);
+    push_items(it, soff, 0, n_curves, curves);
+    void* unused = nullptr;
+    return batch_upload(p, soff, n_curves, roff, curves, it, poff[n_curves], 0, &unused);
+}
+
+int32_t gpfc_survey_setup(gpfc_plan* p, const int64_t* soff, int32_t n_curves, int64_t k,
+                          int64_t chunk_folds) {
+    if (!p || !soff || n_curves < 0 || k < 0 || chunk_folds < 0) return GPFC_EINVAL;
+    if (soff[0] != 0) return GPFC_EINVAL;
+    const int64_t per_chunk = chunk_folds == 0 ? std::max<int32_t>(n_curves, 1)
+                                               : std::max<int64_t>(1, k > 0 ? chunk_folds / k : n_curves);
+    const int64_t zfolds = chunk_folds == 0 ? 0 : per_chunk * k;
+    if ((int64_t)n_curves * k > (int64_t(1) << 40)) return GPFC_ERANGE;
+    int64_t recs = 0, items = 0;
+    std::vector<int64_t> roff(n_curves + 1);
+    std::vector<gpfc::BatchCurve> curves(n_curves);
+    std::vector<SurveyChunk> chunks;
+    roff[0] = 0;
+    for (int32_t c = 0; c < n_curves; ++c) {
+        const int64_t n = soff[c + 1] - soff[c];
+        if (n < 0) return GPFC_EINVAL;
+        if (n > GPFC_MAX_SAMPLES) return GPFC_ERANGE;
+        const int64_t first = c - c % per_chunk;   // first curve of this curve's chunk
+        curves[c] = gpfc::BatchCurve{recs, gpfc::slice_len(n), 0, k, (int64_t)c * k, (c - first) * k};
+        recs += gpfc::prepared_len(n);
+        roff[c + 1] = recs;
+        items += (k + 63) / 64;
+    }
+    if (items > 0x7fffffffLL) return GPFC_ERANGE;
+    std::vector<int2> it;
+    it.reserve((size_t)items);
+    for (int64_t c0 = 0; c0 < n_curves; c0 += per_chunk) {
+        const int32_t c1 = (int32_t)std::min<int64_t>(n_curves, c0 + per_chunk);
+        const int32_t i0 = (int32_t)it.size();
+        push_items(it, soff, (int32_t)c0, c1, curves);
+        chunks.push_back(SurveyChunk{(int32_t)c0, c1, i0, (int32_t)it.size()});
+    }
+    void* z = nullptr;
+    int32_t rc = batch_upload(p, soff, n_curves, roff, curves, it, (int64_t)n_curves * k,
+                              (size_t)zfolds * GPFC_MAX_NBINS * sizeof(uint16_t), &z);
+    if (rc != GPFC_OK) return rc;
+    p->b_survey = true;
+    p->s_k = k;
+    p->s_zbuf = (uint16_t*)z;
+    p->s_zfolds = zfolds;
+    p->s_chunks = chunks;
     return GPFC_OK;
 }
 
@@ -411,7 +491,7 @@ static int32_t batch_enqueue(gpfc_plan* p, const double* t, const float* flux, c
 static int32_t check_batch(const gpfc_plan* p, const void* t, const void* flux, const void* periods,
                            int32_t nbins, const void* snr, const void* start, const void* width,
                            const void* depth, const void* zfold) {
-    if (!p || p->b_curves < 0) return GPFC_EINVAL;
+    if (!p || p->b_curves < 0 || p->b_survey) return GPFC_EINVAL;
     if (p->b_samples > 0 && (!t || !flux)) return GPFC_EINVAL;
     if (p->b_periods > 0 && (!periods || !snr || !start || !width || !depth)) return GPFC_EINVAL;
     if (nbins < 1) return GPFC_EINVAL;
@@ -431,20 +511,14 @@ int32_t gpfc_batch_fold_score(gpfc_plan* p, const double* t, const float* flux, 
                          (hipStream_t)stream);
 }
 
-int32_t gpfc_batch_capture(gpfc_plan* p, const double* t, const float* flux, const double* periods,
-                           int32_t nbins, float* snr, int32_t* start, int32_t* width, float* depth,
-                           uint16_t* zfold, void* stream) {
-    int32_t rc = check_batch(p, t, flux, periods, nbins, snr, start, width, depth, zfold);
-    if (rc != GPFC_OK) return rc;
-    if (!stream) return GPFC_EINVAL;   // the null stream cannot be captured
-    hipError_t e = hipSetDevice(p->device);
-    if (e != hipSuccess) return device_error(e, "hipSetDevice");
+// Record what `enqueue(stream)` launches into the plan's graph.
+extern "C++" template <class F>
+static int32_t capture_into_plan(gpfc_plan* p, hipStream_t s, F enqueue) {
     if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
     if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
-    hipStream_t s = (hipStream_t)stream;
-    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return device_error(e, "hipStreamBeginCapture");
-    rc = batch_enqueue(p, t, flux, periods, nbins, snr, start, width, depth, zfold, s);
+    int32_t rc = enqueue(s);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(s, &g);
     if (rc != GPFC_OK) {
@@ -459,6 +533,114 @@ int32_t gpfc_batch_capture(gpfc_plan* p, const double* t, const float* flux, con
         return device_error(e, "hipGraphInstantiate");
     }
     return GPFC_OK;
+}
+
+int32_t gpfc_batch_capture(gpfc_plan* p, const double* t, const float* flux, const double* periods,
+                           int32_t nbins, float* snr, int32_t* start, int32_t* width, float* depth,
+                           uint16_t* zfold, void* stream) {
+    int32_t rc = check_batch(p, t, flux, periods, nbins, snr, start, width, depth, zfold);
+    if (rc != GPFC_OK) return rc;
+    if (!stream) return GPFC_EINVAL;   // the null stream cannot be captured
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return device_error(e, "hipSetDevice");
+    return capture_into_plan(p, (hipStream_t)stream, [&](hipStream_t s) {
+        return batch_enqueue(p, t, flux, periods, nbins, snr, start, width, depth, zfold, s);
+    });
+}
+
+static int32_t check_survey(const gpfc_plan* p, const gpfc_cnn* cnn, const double* t,
+                            const float* flux, const double* periods, int32_t nbins,
+                            const gpfc_survey_out* o) {
+    if (!p || !o || !p->b_survey) return GPFC_EINVAL;
+    if (p->b_samples > 0 && (!t || !flux)) return GPFC_EINVAL;
+    if (p->b_periods > 0 && (!periods || !o->snr || !o->start || !o->width || !o->depth))
+        return GPFC_EINVAL;
+    if (nbins < 1) return GPFC_EINVAL;
+    if (!pow2_in_range(nbins)) return GPFC_ENOTSUP;
+    const bool net = o->logits != nullptr;
+    if (net && (!cnn || nbins != GPFC_MAX_NBINS || p->s_zfolds == 0)) return GPFC_EINVAL;
+    if (o->top < 0 || o->top > GPFC_MAX_TOP) return GPFC_EINVAL;
+    if (o->top > 0) {
+        if (!o->box_val || !o->box_idx) return GPFC_EINVAL;
+        if ((o->cnn_val != nullptr) != (o->cnn_idx != nullptr)) return GPFC_EINVAL;
+        if ((o->judged_val != nullptr) != (o->judged_idx != nullptr)) return GPFC_EINVAL;
+        if (!net && (o->cnn_val || o->judged_val)) return GPFC_EINVAL;
+    }
+    return GPFC_OK;
+}
+
+static int32_t survey_enqueue(gpfc_plan* p, gpfc_cnn* cnn, const double* t, const float* flux,
+                              const double* periods, int32_t nbins, const gpfc_survey_out& o,
+                              hipStream_t s) {
+    hipError_t e = gpfc::launch_batch_prepare(t, flux, p->b_soff, p->b_roff, p->b_curves,
+                                              p->b_max_records, p->b_info, p->b_rec, s);
+    if (e != hipSuccess) return device_error(e, "survey prepare launch");
+    const bool net = o.logits != nullptr;
+    const int64_t K = p->s_k;
+    for (const SurveyChunk& ch : p->s_chunks) {
+        e = gpfc::launch_batch_fold_score(p->b_rec, p->b_curve, p->b_item + ch.i0, ch.i1 - ch.i0,
+                                          p->b_counter, p->b_info, periods, nbins,
+                                          plan_widths(p, nbins), p->n_cu, o.snr, o.start, o.width,
+                                          o.depth, net ? p->s_zbuf : nullptr, s);
+        if (e != hipSuccess) return device_error(e, "survey fold_score launch");
+        if (!net) continue;
+        const int64_t folds = (int64_t)(ch.c1 - ch.c0) * K;
+        const int64_t mb = gpfc::cnn_max_batch(cnn);
+        for (int64_t f0 = 0; f0 < folds; f0 += mb) {
+            const int64_t B = std::min<int64_t>(mb, folds - f0);
+            const uint16_t* x = p->s_zbuf + f0 * GPFC_MAX_NBINS;
+            float* lg = o.logits + (int64_t)ch.c0 * K + f0;
+            const int32_t rc = o.cnn_fp8 ? gpfc_cnn_forward_fp8(cnn, x, 0, B, lg, s)
+                                         : gpfc_cnn_forward(cnn, x, 0, B, lg, s);
+            if (rc != GPFC_OK) return rc;
+        }
+    }
+    if (o.top > 0) {
+        const int64_t rows = p->b_curves;
+        e = gpfc::launch_topk(o.snr, rows, K, nullptr, 0.0f, o.top, o.box_val, o.box_idx, s);
+        if (e == hipSuccess && o.cnn_val)
+            e = gpfc::launch_topk(o.logits, rows, K, nullptr, 0.0f, o.top, o.cnn_val, o.cnn_idx, s);
+        if (e == hipSuccess && o.judged_val)
+            e = gpfc::launch_topk(o.logits, rows, K, o.snr, o.judge_snr, o.top, o.judged_val,
+                                  o.judged_idx, s);
+        if (e != hipSuccess) return device_error(e, "survey top-k launch");
+    }
+    return GPFC_OK;
+}
+
+int32_t gpfc_survey_run(gpfc_plan* p, gpfc_cnn* cnn, const double* t, const float* flux,
+                        const double* periods, int32_t nbins, const gpfc_survey_out* out,
+                        void* stream) {
+    int32_t rc = check_survey(p, cnn, t, flux, periods, nbins, out);
+    if (rc != GPFC_OK) return rc;
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return device_error(e, "hipSetDevice");
+    return survey_enqueue(p, cnn, t, flux, periods, nbins, *out, (hipStream_t)stream);
+}
+
+int32_t gpfc_survey_capture(gpfc_plan* p, gpfc_cnn* cnn, const double* t, const float* flux,
+                            const double* periods, int32_t nbins, const gpfc_survey_out* out,
+                            void* stream) {
+    int32_t rc = check_survey(p, cnn, t, flux, periods, nbins, out);
+    if (rc != GPFC_OK) return rc;
+    if (!stream) return GPFC_EINVAL;
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return device_error(e, "hipSetDevice");
+    const gpfc_survey_out o = *out;
+    return capture_into_plan(p, (hipStream_t)stream, [&](hipStream_t s) {
+        return survey_enqueue(p, cnn, t, flux, periods, nbins, o, s);
+    });
+}
+
+int32_t gpfc_topk(const float* values, int64_t rows, int64_t len, const float* gate,
+                  float gate_min, int32_t top, float* out_val, int64_t* out_idx, void* stream) {
+    if (rows < 0 || len < 0 || top < 1 || top > GPFC_MAX_TOP) return GPFC_EINVAL;
+    if (rows > 0x7fffffffLL) return GPFC_ERANGE;
+    if (rows == 0) return GPFC_OK;
+    if (!out_val || !out_idx || (len > 0 && !values)) return GPFC_EINVAL;
+    hipError_t e = gpfc::launch_topk(values, rows, len, gate, gate_min, top, out_val, out_idx,
+                                     (hipStream_t)stream);
+    return e == hipSuccess ? GPFC_OK : device_error(e, "k_topk_rows launch");
 }
 
 int32_t gpfc_batch_replay(gpfc_plan* p, void* stream) {

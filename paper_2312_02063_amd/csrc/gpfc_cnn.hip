@@ -23,6 +23,7 @@
 #include <string.h>
 
 #include "../../include/gpfc.h"
+#include "gpfc_internal.h"
 
 namespace gcnn {
 
@@ -642,6 +643,8 @@ struct gpfc_cnn {
     float act_max_host[5] = {0, 0, 0, 0, 0};
     bool calibrated = false, quantized = false;
 };
+
+int64_t gpfc::cnn_max_batch(const gpfc_cnn* c) { return c->max_batch; }
 
 namespace {
 

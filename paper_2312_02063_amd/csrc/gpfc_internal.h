@@ -3,7 +3,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct gpfc_cnn;
+
 namespace gpfc {
+
+// Largest batch a network's workspace takes (defined in gpfc_cnn.hip).
+int64_t cnn_max_batch(const gpfc_cnn* c);
 
 // One packed histogram bin: the sample count in bits [46, 64) and the sum of
 // (q_i + 2^27) in bits [0, 46), q_i being the sample's flux deviation in
@@ -39,12 +44,15 @@ struct Rec {
 };
 
 // One curve of a multi-curve batch: where its prepared records and periods
-// start, its per-wave slice length and its number of periods.
+// start, its per-wave slice length, its number of periods, where its rows of
+// the score outputs start and where its rows of the normalised folds start.
 struct BatchCurve {
     int64_t rec_off;
     int64_t per;
     int64_t p_off;
     int64_t k;
+    int64_t o_off;
+    int64_t z_off;
 };
 
 struct Widths {
@@ -83,6 +91,10 @@ hipError_t launch_fold_f32(const Rec* rec, int64_t n, const double* periods, int
 hipError_t launch_score(const double* sums, const int32_t* counts, int64_t k, int32_t nbins,
                         double sigma, const Widths& widths, float* snr, int32_t* start,
                         int32_t* width, float* depth, hipStream_t s);
+// Best `top` (<= 64) entries of each of `rows` rows of `len` scores (value
+// descending, index ascending; NaN and entries with gate < gate_min skipped).
+hipError_t launch_topk(const float* values, int64_t rows, int64_t len, const float* gate,
+                       float gate_min, int32_t top, float* out_val, int64_t* out_idx, hipStream_t s);
 hipError_t launch_fold_naive(const double* t, const float* flux, int64_t n,
                              const double* periods, int64_t k, int32_t nbins, double* sums,
                              int32_t* counts, hipStream_t s);

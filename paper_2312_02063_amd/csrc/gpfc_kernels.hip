@@ -749,9 +749,9 @@ __global__ __launch_bounds__(kThreads, 1) void k_batch_fold_score(
         const int2 item = items[it];
         const BatchCurve bc = curves[item.x];
         fold_score_body(hist, chunk, sh, rec + bc.rec_off, bc.per, infos + item.x,
-                        periods + bc.p_off, bc.k, (int64_t)item.y * 64, log2g, W, snr + bc.p_off,
-                        start + bc.p_off, width + bc.p_off, depth + bc.p_off,
-                        zfold ? zfold + bc.p_off * nb : nullptr);
+                        periods + bc.p_off, bc.k, (int64_t)item.y * 64, log2g, W, snr + bc.o_off,
+                        start + bc.o_off, width + bc.o_off, depth + bc.o_off,
+                        zfold ? zfold + bc.z_off * nb : nullptr);
         __syncthreads();
     }
 }

@@ -81,3 +81,21 @@ def test_product_path_has_no_cpu_fallback():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "gpfc_oracle" not in text, f
+
+
+def test_topk_and_survey_argument_checks():
+    lib = _lib.load()
+    p = ctypes.c_void_p(1)
+    assert lib.gpfc_topk(p, 1, 10, None, 0.0, 0, p, p, None) == _lib.EINVAL      # top < 1
+    assert lib.gpfc_topk(p, 1, 10, None, 0.0, 65, p, p, None) == _lib.EINVAL     # top > 64
+    assert lib.gpfc_topk(p, -1, 10, None, 0.0, 1, p, p, None) == _lib.EINVAL
+    assert lib.gpfc_topk(None, 1, 10, None, 0.0, 1, p, p, None) == _lib.EINVAL
+    assert lib.gpfc_topk(None, 0, 10, None, 0.0, 1, None, None, None) == _lib.OK  # nothing to do
+    so = (ctypes.c_int64 * 2)(0, 10)
+    assert lib.gpfc_survey_setup(None, so, 1, 10, 0) == _lib.EINVAL
+    assert lib.gpfc_survey_setup(p, so, 1, -1, 0) == _lib.EINVAL
+    bad = (ctypes.c_int64 * 2)(3, 10)
+    assert lib.gpfc_survey_setup(p, bad, 1, 10, 0) == _lib.EINVAL
+    out = _lib.SurveyOut()
+    assert lib.gpfc_survey_run(None, None, p, p, p, 256, ctypes.byref(out), None) == _lib.EINVAL
+    assert lib.gpfc_survey_run(p, None, p, p, p, 256, None, None) == _lib.EINVAL

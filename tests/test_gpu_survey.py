@@ -1,0 +1,185 @@
+"""Per-curve reduction and the chunked survey (runs on an MI355X).
+
+gpfc_topk against the oracle bit for bit (values and indices). The survey:
+box-SNR against the oracle (1e-5); the network's logits equal, bit for bit,
+those of gpfc_cnn_forward on the single-curve normalised folds (same
+kernels, deterministic); its reductions equal the oracle's reduction of its
+own periodograms; a captured survey replays to the eager result.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2312_02063_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _dev(torch, a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+@pytest.mark.parametrize("rows,n,top,gated", [(1, 0, 4, False), (3, 50, 64, False), (5, 777, 7, True),
+                                              (600, 333, 1, False), (2, 100_003, 64, True),
+                                              (1, 2_000_000, 16, False)])
+def test_topk_matches_oracle(torch_dev, rows, n, top, gated):
+    from paper_2312_02063_amd import topk
+    torch = torch_dev
+    rng = np.random.default_rng(rows * 7 + n)
+    x = np.round(rng.normal(size=(rows, n)) * 8).astype(np.float32)   # many ties
+    x[rng.uniform(size=(rows, n)) < 0.01] = np.nan
+    if n > 10:
+        x[0, 3] = -np.inf
+    g = rng.uniform(0, 10, (rows, n)).astype(np.float32) if gated else None
+    _say(f"topk rows={rows} n={n} top={top} gated={gated}")
+    v, i = topk(_dev(torch, x, torch.float32), top,
+                _dev(torch, g, torch.float32) if gated else None, 5.0)
+    torch.cuda.synchronize()
+    ov, oi = oracle.topk(x, top, g, 5.0)
+    np.testing.assert_array_equal(i.cpu().numpy(), oi)
+    np.testing.assert_array_equal(v.cpu().numpy(), ov)
+
+
+def test_topk_ascending_worst_case(torch_dev):
+    """Ascending values make every element enter the candidate lists."""
+    from paper_2312_02063_amd import topk
+    torch = torch_dev
+    x = np.arange(200_000, dtype=np.float32).reshape(1, -1)
+    _say("topk ascending")
+    v, i = topk(_dev(torch, x, torch.float32), 64)
+    ov, oi = oracle.topk(x, 64)
+    np.testing.assert_array_equal(i.cpu().numpy(), oi)
+
+
+def _stars(n_stars, seed=21):
+    return synth.multi_star(seed=seed, n_stars=n_stars, nmin=2000, nmax=7000,
+                            n_transit=max(1, n_stars // 3), alpha=(10.0, 20.0))
+
+
+def _survey(torch, stars, k, chunk_folds, net=None, top=8, judge=3.0, capture=False, fp8=False):
+    from paper_2312_02063_amd import Plan
+    plan = Plan(0)
+    periods = synth.freq_grid(1.0, 5.0, k)
+    so = np.concatenate([[0], np.cumsum([s.t.size for s in stars])]).astype(np.int64)
+    plan.survey_setup(so, k, chunk_folds)
+    t = _dev(torch, np.concatenate([s.t for s in stars]), torch.float64)
+    f = _dev(torch, np.concatenate([s.flux for s in stars]), torch.float32)
+    p = _dev(torch, periods, torch.float64)
+    if capture:
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            r = plan.survey_capture(t, f, p, 256, cnn=net, top=top, judge_snr=judge, fp8=fp8)
+        torch.cuda.synchronize()
+        return plan, r, (t, f, p, side, periods)
+    r = plan.survey_run(t, f, p, 256, cnn=net, top=top, judge_snr=judge, fp8=fp8)
+    torch.cuda.synchronize()
+    return plan, {a: b.cpu().numpy() for a, b in r.items()}, periods
+
+
+def _net(torch, max_batch=1500):
+    from paper_2312_02063_amd import CNN_BF16, Cnn
+    net = Cnn(0, CNN_BF16, max_batch)
+    net.set_params(synth.cnn_init(77).astype(np.float32))
+    return net
+
+
+def test_survey_box_only_matches_oracle(torch_dev):
+    torch = torch_dev
+    stars = _stars(7)
+    k = 333
+    _say(f"survey box-only stars={len(stars)} k={k}")
+    _, r, periods = _survey(torch, stars, k, 0, top=5)
+    for c, s in enumerate(stars):
+        mean, sigma, _ = oracle.curve_stats(s.t, s.flux)
+        _, dsums, counts = oracle.fold(s.t, s.flux, periods, 256, ref=mean, nthreads=8)
+        osnr, _, _, _ = oracle.score(counts, dsums, sigma)
+        np.testing.assert_allclose(r["snr"][c], osnr, rtol=1e-5, atol=1e-5)
+    ov, oi = oracle.topk(r["snr"], 5)
+    np.testing.assert_array_equal(r["box_idx"], oi)
+    np.testing.assert_array_equal(r["box_val"], ov)
+
+
+@pytest.mark.parametrize("chunk_folds", [333, 1000, 2600])
+def test_survey_with_network(torch_dev, chunk_folds):
+    """Chunks of 1, 3 and 7 curves; the network runs in batches of 1,500."""
+    from paper_2312_02063_amd import Plan
+    torch = torch_dev
+    stars = _stars(8, seed=31)
+    k = 333
+    net = _net(torch)
+    _say(f"survey + cnn stars={len(stars)} k={k} chunk_folds={chunk_folds}")
+    _, r, periods = _survey(torch, stars, k, chunk_folds, net=net, top=8, judge=3.0)
+    single = Plan(0)
+    pp = _dev(torch, periods, torch.float64)
+    for c, s in enumerate(stars):
+        single.prepare(_dev(torch, s.t, torch.float64), _dev(torch, s.flux, torch.float32))
+        z = torch.empty((k, 256), dtype=torch.uint16, device="cuda")
+        out = single.fold_score_prepared(pp, 256, zfold=z)
+        lg = net.forward(z)
+        torch.cuda.synchronize()
+        assert np.array_equal(r["snr"][c], out[0].cpu().numpy()), c
+        assert np.array_equal(r["logits"][c], lg.cpu().numpy()), c
+    ov, oi = oracle.topk(r["logits"], 8)
+    np.testing.assert_array_equal(r["cnn_idx"], oi)
+    np.testing.assert_array_equal(r["cnn_val"], ov)
+    ov, oi = oracle.topk(r["logits"], 8, r["snr"], 3.0)
+    np.testing.assert_array_equal(r["judged_idx"], oi)
+    np.testing.assert_array_equal(r["judged_val"], ov)
+
+
+def test_survey_capture_replays(torch_dev):
+    torch = torch_dev
+    stars = _stars(5, seed=41)
+    k = 200
+    net = _net(torch, max_batch=512)
+    _say("survey capture")
+    plan, gr, (t, f, p, side, _) = _survey(torch, stars, k, 450, net=net, top=4, capture=True)
+    for rep in range(3):
+        f.mul_(1.0 + 1e-4 * (rep + 1)).add_(-1e-4 * (rep + 1))
+        torch.cuda.synchronize()
+        _say(f"survey eager rep {rep}")
+        er = plan.survey_run(t, f, p, 256, cnn=net, top=4, judge_snr=0.0)
+        er = {a: b.clone() for a, b in er.items()}
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            _say(f"survey replay {rep}")
+            plan.batch_replay()
+        side.synchronize()
+        for key in er:
+            assert torch.equal(gr[key], er[key]), f"replay {rep}: {key}"
+
+
+def test_survey_fp8(torch_dev):
+    torch = torch_dev
+    stars = _stars(3, seed=51)
+    k = 150
+    net = _net(torch, max_batch=512)
+    cal = torch.randn(400, 256, device="cuda")
+    net.calibrate_fp8(cal)
+    _say("survey fp8")
+    _, r, periods = _survey(torch, stars, k, 300, net=net, top=2, fp8=True)
+    from paper_2312_02063_amd import Plan
+    single = Plan(0)
+    pp = _dev(torch, periods, torch.float64)
+    for c, s in enumerate(stars):
+        single.prepare(_dev(torch, s.t, torch.float64), _dev(torch, s.flux, torch.float32))
+        z = torch.empty((k, 256), dtype=torch.uint16, device="cuda")
+        single.fold_score_prepared(pp, 256, zfold=z)
+        lg = net.forward_fp8(z)
+        torch.cuda.synchronize()
+        assert np.array_equal(r["logits"][c], lg.cpu().numpy()), c
