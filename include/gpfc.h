@@ -260,6 +260,13 @@ int32_t gpfc_cnn_set_params(gpfc_cnn *cnn, const float *params, void *stream);
 /* Copy the current parameters out to f32[nparams]. */
 int32_t gpfc_cnn_get_params(gpfc_cnn *cnn, float *out, void *stream);
 
+/*
+ * Inference path of a bf16 network: on (the default), the four convolution
+ * blocks run as one fused kernel that keeps every activation in LDS; off,
+ * layer by layer through device memory. Both give bit-identical logits.
+ */
+int32_t gpfc_cnn_set_fused(gpfc_cnn *cnn, int32_t on);
+
 /* Logits f32[B] (sigmoid of a logit is the transit score). B <= max_batch. */
 int32_t gpfc_cnn_forward(gpfc_cnn *cnn, const void *x, int32_t x_f32, int64_t B, float *logits,
                          void *stream);
@@ -354,8 +361,10 @@ int32_t gpfc_survey_run(gpfc_plan *plan, gpfc_cnn *cnn, const double *t, const f
 /*
  * Record gpfc_survey_run's whole launch sequence for these buffers into the
  * plan's HIP graph (kernel nodes only; replay with gpfc_batch_replay). The
- * network's weights are those packed at capture time: capture again after
- * changing them. `stream` must be a created stream, not the null stream.
+ * graph converts the network's FP32 master weights to its working copies
+ * itself, so each replay uses the weights current at that time (and, for
+ * FP8, the current calibration). `stream` must be a created stream, not the
+ * null stream.
  */
 int32_t gpfc_survey_capture(gpfc_plan *plan, gpfc_cnn *cnn, const double *t, const float *flux,
                             const double *periods, int32_t nbins, const gpfc_survey_out *out,

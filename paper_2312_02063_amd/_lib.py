@@ -94,6 +94,7 @@ def load():
         "gpfc_cnn_destroy": ([vp], i32),
         "gpfc_cnn_set_params": ([vp, vp, vp], i32),
         "gpfc_cnn_get_params": ([vp, vp, vp], i32),
+        "gpfc_cnn_set_fused": ([vp, i32], i32),
         "gpfc_cnn_forward": ([vp, vp, i32, i64, vp, vp], i32),
         "gpfc_cnn_backward": ([vp, vp, i32, vp, i64, vp, vp, vp], i32),
         "gpfc_cnn_adam": ([vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp], i32),
@@ -119,7 +120,7 @@ def exported_symbols():
             "gpfc_batch_curve_stats", "gpfc_cnn_nparams", "gpfc_cnn_last_error",
             "gpfc_cnn_create", "gpfc_cnn_destroy", "gpfc_cnn_set_params", "gpfc_cnn_get_params",
             "gpfc_cnn_forward", "gpfc_cnn_backward", "gpfc_cnn_adam", "gpfc_cnn_calibrate_fp8",
-            "gpfc_cnn_forward_fp8", "gpfc_topk", "gpfc_survey_setup", "gpfc_survey_run",
+            "gpfc_cnn_forward_fp8", "gpfc_cnn_set_fused", "gpfc_topk", "gpfc_survey_setup", "gpfc_survey_run",
             "gpfc_survey_capture"]
 
 
@@ -491,6 +492,10 @@ class Cnn:
         if x.dtype == torch.float32:
             return 1
         raise TypeError("x must be uint16 (bfloat16 bits) or float32")
+
+    def set_fused(self, on: bool):
+        """bf16 inference through the fused convolution-stack kernel (default) or layer by layer."""
+        _check(self.lib.gpfc_cnn_set_fused(self.h, int(bool(on))), "gpfc_cnn_set_fused")
 
     def forward(self, x, out=None):
         """Logits f32[B] for x [B][256]."""

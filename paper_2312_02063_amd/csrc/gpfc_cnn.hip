@@ -36,6 +36,7 @@ constexpr int64_t F1W = 33536, F1B = 295680, F2W = 295936, F2B = 312320, F3W = 3
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -94,7 +95,10 @@ struct FP8 {
 // of the tile inside [0, M) x [0, N).
 
 template <class P, class LA, class LB, class EP>
-__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, LA la, LB lb, EP ep) {
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, int kchunk, LA la, LB lb, EP ep) {
+    // split K: block z sums k in [z * kchunk, min(K, (z + 1) * kchunk))
+    const int kb = blockIdx.z * kchunk;
+    const int ke = min(K, kb + kchunk);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int m0 = blockIdx.x * 64 + (wave & 1) * 32;
@@ -104,7 +108,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, LA la, LB lb,
     f32x4 acc[2][2];
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k0 = 0; k0 < K; k0 += P::KSTEP) {
+    for (int k0 = kb; k0 < ke; k0 += P::KSTEP) {
         if constexpr (__is_same(P, FP8)) {
             const int kk = k0 + q * 8;
             long a[2], b[2];
@@ -235,10 +239,12 @@ struct ActQ {
     Base base;
     float inv;
     __device__ __forceinline__ long frag8q(int m, int k) const {
-        const bf16x8 v = base.frag8(m, k);
+        // whole-vector reinterpretation: a bit_cast of one vector element
+        // (v[j]) is lowered as element 0 by this compiler
+        const u16x8 v = __builtin_bit_cast(u16x8, base.frag8(m, k));
         uint64_t r = 0;
         for (int j = 0; j < 8; ++j) {
-            const float f = bf2f(__builtin_bit_cast(uint16_t, v[j])) * inv;
+            const float f = bf2f(v[j]) * inv;
             r |= (uint64_t)f2e4m3(f) << (8 * j);
         }
         return (long)r;
@@ -286,7 +292,7 @@ struct EpConvFwd {
             const float pv = w ? p1 : p0;
             const int64_t o = (int64_t)(mm >> 1) * C + n;
             out[o] = P::from_f(w ? r1 : r0);
-            mask[o] = (uint8_t)(w | (pv > 0.0f ? 2 : 0));
+            if (mask) mask[o] = (uint8_t)(w | (pv > 0.0f ? 2 : 0));
         }
     }
 };
@@ -331,11 +337,14 @@ struct EpStore {
 struct EpConvDW {
     float* g;
     int Cin;
+    __device__ __forceinline__ void store(int m, int n, float v) const {
+        const int dx = n / Cin, ci = n - dx * Cin;
+        g[((int64_t)m * Cin + ci) * 5 + dx] = v;
+    }
     __device__ __forceinline__ void operator()(int m, int n, f32x4 a, int M, int N) const {
         if (n >= N) return;
-        const int dx = n / Cin, ci = n - dx * Cin;
         for (int i = 0; i < 4; ++i)
-            if (m + i < M) g[((int64_t)(m + i) * Cin + ci) * 5 + dx] = a[i];
+            if (m + i < M) store(m + i, n, a[i]);
     }
 };
 
@@ -346,13 +355,40 @@ struct EpFcDW {
     float* g;
     int in;
     bool fc1;
+    __device__ __forceinline__ void store(int m, int n, float v) const {
+        const int i = fc1 ? ((n & 63) * 16 + (n >> 6)) : n;
+        g[(int64_t)m * in + i] = v;
+    }
     __device__ __forceinline__ void operator()(int m, int n, f32x4 a, int M, int N) const {
         if (n >= N) return;
-        const int i = fc1 ? ((n & 63) * 16 + (n >> 6)) : n;
         for (int r = 0; r < 4; ++r)
-            if (m + r < M) g[(int64_t)(m + r) * in + i] = a[r];
+            if (m + r < M) store(m + r, n, a[r]);
     }
 };
+
+// Split-K partial sums: block z writes its tile to ws[z][m][n].
+struct EpPartial {
+    float* ws;
+    __device__ __forceinline__ void operator()(int m, int n, f32x4 a, int M, int N) const {
+        if (n >= N) return;
+        float* w = ws + (int64_t)blockIdx.z * M * N;
+        for (int r = 0; r < 4; ++r)
+            if (m + r < M) w[(int64_t)(m + r) * N + n] = a[r];
+    }
+};
+
+// Sum the split-K partials in z order (deterministic) and store through the
+// weight-gradient epilogue.
+template <class EP>
+__global__ __launch_bounds__(256) void k_splitk_reduce(const float* __restrict__ ws, int S, int M,
+                                                       int N, EP ep) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t mn = (int64_t)M * N;
+    if (i >= mn) return;
+    float v = 0.0f;
+    for (int z = 0; z < S; ++z) v += ws[z * mn + i];
+    ep.store((int)(i / N), (int)(i % N), v);
+}
 
 // ------------------------------------------------------------------ small kernels
 
@@ -385,7 +421,7 @@ __global__ __launch_bounds__(256) void k_conv1_fwd(const void* __restrict__ x, i
     const float r0 = fmaxf(pre[0], 0.0f), r1 = fmaxf(pre[1], 0.0f);
     const int wn = r0 >= r1 ? 0 : 1;
     out[idx] = P::from_f(wn ? r1 : r0);
-    mask[idx] = (uint8_t)(wn | ((wn ? pre[1] : pre[0]) > 0.0f ? 2 : 0));
+    if (mask) mask[idx] = (uint8_t)(wn | ((wn ? pre[1] : pre[0]) > 0.0f ? 2 : 0));
 }
 
 // Output layer, loss and its gradient. One block; h2 [B][64] post-ReLU.
@@ -444,6 +480,152 @@ __global__ __launch_bounds__(256) void k_head(const typename P::T* __restrict__ 
         __syncthreads();
     }
     if (threadIdx.x == 0) grad[F3B] += red[0];
+}
+
+// ------------------------------------------------------------------ fused inference
+//
+// The four convolution blocks of a bf16 network for inference, one persistent
+// block per compute unit: the conv 2-4 weights (66 KB) are staged in LDS once,
+// then tiles of kTileF inputs run conv1 on the vector units and conv2-4 as
+// implicit GEMMs on the bf16 matrix cores with every activation kept in LDS
+// (channels-last [fold][position][channel]); only the input (512 B) is read
+// and the block-4 output (2 KB, position-major as the fc1 GEMM reads it) is
+// written per input. Arithmetic and summation order are those of
+// k_conv1_fwd and k_gemm with EpConvFwd, so the output is bit-identical to
+// the layer-by-layer path.
+
+constexpr int kTileF = 8;                       // inputs per tile
+constexpr int kFusedThreads = 512;              // 8 waves
+constexpr int kW2Ld = 96, kW3Ld = 160, kW4Ld = 320;   // K of conv2 padded to whole 32-steps
+
+struct ConvStackLds {
+    uint16_t w2[32 * kW2Ld];
+    uint16_t w3[64 * kW3Ld];
+    uint16_t w4[64 * kW4Ld];
+    uint16_t buf0[kTileF * 128 * 16];            // a1, then a3 ([F][32][64], same size)
+    uint16_t buf1[kTileF * 64 * 32];             // a2
+};
+
+// One implicit-GEMM conv layer over the tile: rows (f, x) for x < L, columns
+// output channels, k = dx*CIN + ci. Each wave takes 64 x 32 wave-tiles (4 x 2
+// MFMA blocks of 16 x 16) and, per 32-step of k, loads 4 A and 2 B fragments
+// from LDS. The epilogue adds the bias, applies ReLU and max-pools position
+// pairs (both in the lane), then stores bf16 to `out` ([F][L/2][COUT] at
+// out_stride per input), skipping inputs >= nvalid when `to_global`.
+template <int L, int CIN, int COUT, int WLD>
+__device__ __forceinline__ void conv_tile(const uint16_t* __restrict__ in,
+                                          const uint16_t* __restrict__ w,
+                                          const float* __restrict__ bias, uint16_t* __restrict__ out,
+                                          bool to_global, int nvalid) {
+    constexpr int K = 5 * CIN;
+    constexpr int KSTEPS = (K + 31) / 32;
+    constexpr int M = kTileF * L;
+    constexpr int NCT = COUT / 32;
+    constexpr int NWT = (M / 64) * NCT;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int r = lane & 15, q = lane >> 4;
+    for (int wt = wave; wt < NWT; wt += kFusedThreads / 64) {
+        const int rt = wt / NCT, ct = wt - rt * NCT;
+        f32x4 acc[4][2];
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int ks = 0; ks < KSTEPS; ++ks) {
+            const int k = ks * 32 + q * 8;
+            const int dx = k / CIN, ci0 = k - dx * CIN;
+            bf16x8 a[4], b[2];
+            for (int i = 0; i < 4; ++i) {
+                const int m = rt * 64 + i * 16 + r;
+                const int f = m / L, x = m - f * L;
+                int pos = x + dx - 2;
+                pos = pos < 0 ? pos + L : (pos >= L ? pos - L : pos);
+                a[i] = k < K ? *reinterpret_cast<const bf16x8*>(in + (f * L + pos) * CIN + ci0) : bf16x8{};
+            }
+            for (int j = 0; j < 2; ++j)
+                b[j] = *reinterpret_cast<const bf16x8*>(w + (ct * 32 + j * 16 + r) * WLD + ks * 32 + q * 8);
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        for (int i = 0; i < 4; ++i) {
+            const int m0 = rt * 64 + i * 16 + q * 4;      // 4 consecutive positions of one input
+            const int f = m0 / L, x0 = m0 - f * L;
+            if (to_global && f >= nvalid) continue;
+            for (int j = 0; j < 2; ++j) {
+                const int n = ct * 32 + j * 16 + r;
+                const float bn = bias[n];
+                for (int h = 0; h < 2; ++h) {
+                    const float p0 = acc[i][j][2 * h] + bn, p1 = acc[i][j][2 * h + 1] + bn;
+                    const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
+                    out[(f * (L / 2) + (x0 >> 1) + h) * COUT + n] = f2bf(r0 >= r1 ? r0 : r1);
+                }
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kFusedThreads, 1) void k_convstack_bf16(
+    const void* __restrict__ x, int xf32, int B, const float* __restrict__ w1,
+    const float* __restrict__ b1, const uint16_t* __restrict__ wf2, const float* __restrict__ b2,
+    const uint16_t* __restrict__ wf3, const float* __restrict__ b3,
+    const uint16_t* __restrict__ wf4, const float* __restrict__ b4, uint16_t* __restrict__ a4) {
+    __shared__ __attribute__((aligned(16))) ConvStackLds sm;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < 32 * kW2Ld; i += kFusedThreads) {
+        const int n = i / kW2Ld, k = i - n * kW2Ld;
+        sm.w2[i] = k < 80 ? wf2[n * 80 + k] : (uint16_t)0;
+    }
+    for (int i = tid; i < 64 * kW3Ld; i += kFusedThreads) sm.w3[i] = wf3[i];
+    for (int i = tid; i < 64 * kW4Ld; i += kFusedThreads) sm.w4[i] = wf4[i];
+    const int ntiles = (B + kTileF - 1) / kTileF;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int f0 = tile * kTileF;
+        const int nvalid = min(kTileF, B - f0);
+        __syncthreads();   // weights staged / previous tile's conv4 done with buf0
+        // conv1 (1 -> 16 channels) on the vector units, as k_conv1_fwd
+        for (int idx = tid; idx < kTileF * 128 * 16; idx += kFusedThreads) {
+            const int co = idx & 15, xp = (idx >> 4) & 127, f = idx >> 11;
+            float r = 0.0f;
+            if (f < nvalid) {
+                const int64_t row = (int64_t)(f0 + f) * 256;
+                float pre[2];
+                for (int h = 0; h < 2; ++h) {
+                    const int xx = 2 * xp + h;
+                    float acc = b1[co];
+                    for (int dx = 0; dx < 5; ++dx) {
+                        const int pos = (xx + dx - 2) & 255;
+                        const float v = xf32 ? reinterpret_cast<const float*>(x)[row + pos]
+                                             : bf2f(reinterpret_cast<const uint16_t*>(x)[row + pos]);
+                        acc += w1[co * 5 + dx] * bf2f(f2bf(v));
+                    }
+                    pre[h] = acc;
+                }
+                const float r0 = fmaxf(pre[0], 0.0f), r1 = fmaxf(pre[1], 0.0f);
+                r = r0 >= r1 ? r0 : r1;
+            }
+            sm.buf0[idx] = f2bf(r);
+        }
+        __syncthreads();
+        conv_tile<128, 16, 32, kW2Ld>(sm.buf0, sm.w2, b2, sm.buf1, false, nvalid);
+        __syncthreads();
+        conv_tile<64, 32, 64, kW3Ld>(sm.buf1, sm.w3, b3, sm.buf0, false, nvalid);
+        __syncthreads();
+        conv_tile<32, 64, 64, kW4Ld>(sm.buf0, sm.w4, b4, a4 + (int64_t)f0 * 1024, true, nvalid);
+    }
+}
+
+// Output layer for inference: one thread per input, same summation order as
+// k_head.
+template <class P>
+__global__ __launch_bounds__(256) void k_head_infer(const typename P::T* __restrict__ h2, int B,
+                                                    const float* __restrict__ w3,
+                                                    const float* __restrict__ b3,
+                                                    float* __restrict__ logits) {
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= B) return;
+    float z = b3[0];
+    for (int i = 0; i < 64; ++i) z += P::to_f(h2[(int64_t)b * 64 + i]) * w3[i];
+    logits[b] = z;
 }
 
 // Route a pooled-level gradient to the pre-activation positions with the
@@ -611,7 +793,33 @@ template <class P, class LA, class LB, class EP>
 hipError_t gemm(int M, int N, int K, LA la, LB lb, EP ep, hipStream_t s) {
     if (M <= 0 || N <= 0) return hipSuccess;
     dim3 grid((M + 63) / 64, (N + 63) / 64);
-    hipLaunchKernelGGL((k_gemm<P, LA, LB, EP>), grid, dim3(256), 0, s, M, N, K, la, lb, ep);
+    const int kc = (K + P::KSTEP - 1) / P::KSTEP * P::KSTEP;
+    hipLaunchKernelGGL((k_gemm<P, LA, LB, EP>), grid, dim3(256), 0, s, M, N, K, kc, la, lb, ep);
+    return hipGetLastError();
+}
+
+// Split-K workspace (floats) every network holds.
+constexpr int64_t kSplitWs = int64_t(8) << 20;
+
+// Weight-gradient GEMM with a long K (the batch, or batch x positions): the
+// K range is split over enough blocks to fill the chip, partial tiles go to
+// `ws` and one pass sums them in a fixed order into the epilogue.
+template <class P, class LA, class LB, class EP>
+hipError_t gemm_splitk(int M, int N, int K, LA la, LB lb, EP ep, float* ws, hipStream_t s) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+    int S = std::max(1, 2048 / tiles);                           // about 2048 blocks
+    S = std::min<int64_t>(S, std::max(1, K / 512));             // at least 512 k per block
+    S = (int)std::min<int64_t>(S, kSplitWs / ((int64_t)M * N));
+    if (S <= 1) return gemm<P>(M, N, K, la, lb, ep, s);
+    int kc = (K + S - 1) / S;
+    kc = (kc + P::KSTEP - 1) / P::KSTEP * P::KSTEP;
+    S = (K + kc - 1) / kc;
+    dim3 grid((M + 63) / 64, (N + 63) / 64, S);
+    hipLaunchKernelGGL((k_gemm<P, LA, LB, EpPartial>), grid, dim3(256), 0, s, M, N, K, kc, la, lb,
+                       EpPartial{ws});
+    hipLaunchKernelGGL((k_splitk_reduce<EP>), dim3(blocks_for((int64_t)M * N)), dim3(256), 0, s, ws,
+                       S, M, N, ep);
     return hipGetLastError();
 }
 
@@ -629,8 +837,11 @@ struct gpfc_cnn {
     float* m = nullptr;
     float* v = nullptr;
     float* loss = nullptr;
+    float* ws = nullptr;         // split-K partial sums (kSplitWs floats)
     void* work = nullptr;        // packed weights + activations
     bool packed = false;
+    bool fused = true;           // bf16 inference through k_convstack_bf16
+    int32_t n_cu = 256;
     // views into work (element type per prec)
     void *wf2, *wb2, *wf3, *wb3, *wf4, *wb4, *f1f, *f1b, *f2f, *f2b;
     void *a1, *a2, *a3, *a4, *h1, *h2;       // activations
@@ -655,6 +866,14 @@ int32_t cnn_err(hipError_t e, const char* what) {
     return GPFC_EDEVICE;
 }
 
+// True while `s` records into a graph: work enqueued now has not run yet, so
+// the working copies it makes cannot be marked ready, and a graph must make
+// its own (each replay then uses the network's current weights).
+bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return s && hipStreamIsCapturing(s, &st) == hipSuccess && st == hipStreamCaptureStatusActive;
+}
+
 template <class P>
 int32_t pack(gpfc_cnn* c, hipStream_t s) {
     using T = typename P::T;
@@ -663,7 +882,7 @@ int32_t pack(gpfc_cnn* c, hipStream_t s) {
                        (T*)c->wb4, (T*)c->f1f, (T*)c->f1b, (T*)c->f2f, (T*)c->f2b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cnn_err(e, "k_pack");
-    c->packed = true;
+    c->packed = !capturing(s);   // a captured pack runs only when the graph does
     return GPFC_OK;
 }
 
@@ -673,16 +892,27 @@ int32_t forward(gpfc_cnn* c, const void* x, int xf32, int B, float* logits, cons
     using namespace gcnn;
     using T = typename P::T;
     hipError_t e;
-    if (!c->packed) {
+    if (!c->packed || capturing(s)) {
         int32_t rc = pack<P>(c, s);
         if (rc != GPFC_OK) return rc;
     }
     const float* w = c->params;
-    hipLaunchKernelGGL((k_conv1_fwd<P>), dim3(blocks_for((int64_t)B * 128 * 16)), dim3(256), 0, s, x,
-                       xf32, B, w + kConvW[1], w + conv_b(1), (T*)c->a1, c->m1);
+    const bool train = labels != nullptr;   // pooling masks are kept for the backward pass only
     T* acts[5] = {nullptr, (T*)c->a1, (T*)c->a2, (T*)c->a3, (T*)c->a4};
     uint8_t* masks[5] = {nullptr, c->m1, c->m2, c->m3, c->m4};
+    if (!train) masks[2] = masks[3] = masks[4] = nullptr;
     void* wfs[5] = {nullptr, nullptr, c->wf2, c->wf3, c->wf4};
+    // inference of a bf16 network: the fused convolution stack (bit-identical)
+    const bool fused = __is_same(P, BF16) && !train && logits && c->fused;
+    if (fused) {
+        const int ntiles = (B + kTileF - 1) / kTileF;
+        hipLaunchKernelGGL(k_convstack_bf16, dim3((unsigned)std::min(ntiles, c->n_cu)),
+                           dim3(kFusedThreads), 0, s, x, xf32, B, w + kConvW[1], w + conv_b(1),
+                           (const uint16_t*)c->wf2, w + conv_b(2), (const uint16_t*)c->wf3,
+                           w + conv_b(3), (const uint16_t*)c->wf4, w + conv_b(4), (uint16_t*)c->a4);
+    } else {
+    hipLaunchKernelGGL((k_conv1_fwd<P>), dim3(blocks_for((int64_t)B * 128 * 16)), dim3(256), 0, s, x,
+                       xf32, B, w + kConvW[1], w + conv_b(1), (T*)c->a1, train ? c->m1 : nullptr);
     for (int l = 2; l <= 4; ++l) {
         const int Cin = CH[l - 1], Cout = CH[l], L = LEN[l - 1];
         ConvRows<P> la{acts[l - 1], L, Cin, B * L, +1};
@@ -691,14 +921,19 @@ int32_t forward(gpfc_cnn* c, const void* x, int xf32, int B, float* logits, cons
         e = gemm<P>(B * L, Cout, 5 * Cin, la, lb, ep, s);
         if (e != hipSuccess) return cnn_err(e, "conv gemm");
     }
+    }
     e = gemm<P>(B, 256, 1024, Rows<P>{(const T*)c->a4, B, 1024, 1024},
                 Rows<P>{(const T*)c->f1f, 256, 1024, 1024}, EpFcFwd<P>{w + F1B, (T*)c->h1, 256}, s);
     if (e != hipSuccess) return cnn_err(e, "fc1 gemm");
     e = gemm<P>(B, 64, 256, Rows<P>{(const T*)c->h1, B, 256, 256},
                 Rows<P>{(const T*)c->f2f, 64, 256, 256}, EpFcFwd<P>{w + F2B, (T*)c->h2, 64}, s);
     if (e != hipSuccess) return cnn_err(e, "fc2 gemm");
-    hipLaunchKernelGGL((k_head<P>), dim3(1), dim3(256), 0, s, (const T*)c->h2, B, w + F3W, w + F3B,
-                       labels, logits, c->loss, c->grad, (T*)c->d_a);
+    if (train)
+        hipLaunchKernelGGL((k_head<P>), dim3(1), dim3(256), 0, s, (const T*)c->h2, B, w + F3W,
+                           w + F3B, labels, logits, c->loss, c->grad, (T*)c->d_a);
+    else if (logits)
+        hipLaunchKernelGGL((k_head_infer<P>), dim3(blocks_for(B)), dim3(256), 0, s, (const T*)c->h2,
+                           B, w + F3W, w + F3B, logits);
     e = hipGetLastError();
     return e == hipSuccess ? GPFC_OK : cnn_err(e, "k_head");
 }
@@ -712,16 +947,16 @@ int32_t backward(gpfc_cnn* c, const void* x, int xf32, int B, hipStream_t s) {
     float* g = c->grad;
     // dh2 (already masked) is in d_a [B][64]
     T* dh2 = (T*)c->d_a;
-    e = gemm<P>(64, 256, B, Cols<P>{dh2, 64, 64, B}, Cols<P>{(const T*)c->h1, 256, 256, B},
-                EpFcDW{g + F2W, 256, false}, s);
+    e = gemm_splitk<P>(64, 256, B, Cols<P>{dh2, 64, 64, B}, Cols<P>{(const T*)c->h1, 256, 256, B},
+                       EpFcDW{g + F2W, 256, false}, c->ws, s);
     if (e != hipSuccess) return cnn_err(e, "fc2 dW");
     hipLaunchKernelGGL((k_bias_grad<P>), dim3(64), dim3(256), 0, s, dh2, (int64_t)B, 64, g + F2B);
     T* dh1 = (T*)c->d_b;   // [B][256], masked by h1 > 0
     e = gemm<P>(B, 256, 64, Rows<P>{dh2, B, 64, 64}, Rows<P>{(const T*)c->f2b, 256, 64, 64},
                 EpStore<P>{dh1, (const T*)c->h1, 256}, s);
     if (e != hipSuccess) return cnn_err(e, "fc2 dX");
-    e = gemm<P>(256, 1024, B, Cols<P>{dh1, 256, 256, B}, Cols<P>{(const T*)c->a4, 1024, 1024, B},
-                EpFcDW{g + F1W, 1024, true}, s);
+    e = gemm_splitk<P>(256, 1024, B, Cols<P>{dh1, 256, 256, B},
+                       Cols<P>{(const T*)c->a4, 1024, 1024, B}, EpFcDW{g + F1W, 1024, true}, c->ws, s);
     if (e != hipSuccess) return cnn_err(e, "fc1 dW");
     hipLaunchKernelGGL((k_bias_grad<P>), dim3(256), dim3(256), 0, s, dh1, (int64_t)B, 256, g + F1B);
     T* dact = (T*)c->d_a;  // [B][1024] = pooled gradient of block 4, position-major
@@ -746,8 +981,9 @@ int32_t backward(gpfc_cnn* c, const void* x, int xf32, int B, hipStream_t s) {
                                g + kConvW[1]);
             break;
         }
-        e = gemm<P>(Cout, 5 * Cin, B * L, Cols<P>{dpre, Cout, Cout, B * L},
-                    ConvCols<P>{acts[l - 1], L, Cin, B * L}, EpConvDW{g + kConvW[l], Cin}, s);
+        e = gemm_splitk<P>(Cout, 5 * Cin, B * L, Cols<P>{dpre, Cout, Cout, B * L},
+                           ConvCols<P>{acts[l - 1], L, Cin, B * L}, EpConvDW{g + kConvW[l], Cin},
+                           c->ws, s);
         if (e != hipSuccess) return cnn_err(e, "conv dW");
         // gradient with respect to the block's input (pooled output of l-1)
         T* dnext = dact;   // reuse: dact is free once dpre exists
@@ -784,6 +1020,12 @@ int32_t gpfc_cnn_create(gpfc_cnn** out, int32_t device, int32_t precision, int64
     if (!c) return GPFC_ENOMEM;
     c->device = device;
     c->prec = precision;
+    {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+            ncu > 0)
+            c->n_cu = ncu;
+    }
     c->max_batch = max_batch;
     const size_t E = elt(c);
     const int64_t Bm = max_batch;
@@ -799,7 +1041,7 @@ int32_t gpfc_cnn_create(gpfc_cnn** out, int32_t device, int32_t precision, int64
     total += 2 * al(dsz * E);
     for (int i = 0; i < 4; ++i) total += al(asz[i]);   // masks
     const size_t fsz = al(sizeof(float) * gcnn::kNP);
-    total += 4 * fsz + 256;
+    total += 4 * fsz + 256 + al(sizeof(float) * gcnn::kSplitWs);
     const size_t qsz[5] = {32 * 80, 64 * 160, 64 * 320, 256 * 1024, 64 * 256};
     const size_t csz[5] = {32, 64, 64, 256, 64};
     for (int i = 0; i < 5; ++i) total += al(qsz[i]) + al(csz[i] * sizeof(float));
@@ -818,6 +1060,7 @@ int32_t gpfc_cnn_create(gpfc_cnn** out, int32_t device, int32_t precision, int64
     c->m = (float*)take(sizeof(float) * gcnn::kNP);
     c->v = (float*)take(sizeof(float) * gcnn::kNP);
     c->loss = (float*)take(256);
+    c->ws = (float*)take(sizeof(float) * gcnn::kSplitWs);
     void** wv[10] = {&c->wf2, &c->wb2, &c->wf3, &c->wb3, &c->wf4, &c->wb4, &c->f1f, &c->f1b, &c->f2f, &c->f2b};
     for (int i = 0; i < 10; ++i) *wv[i] = take(wsz[i] * E);
     void** av[6] = {&c->a1, &c->a2, &c->a3, &c->a4, &c->h1, &c->h2};
@@ -860,6 +1103,12 @@ int32_t gpfc_cnn_set_params(gpfc_cnn* c, const float* params, void* stream) {
     c->quantized = false;
     e = hipGetLastError();
     return e == hipSuccess ? GPFC_OK : cnn_err(e, "set params");
+}
+
+int32_t gpfc_cnn_set_fused(gpfc_cnn* c, int32_t on) {
+    if (!c) return GPFC_EINVAL;
+    c->fused = on != 0;
+    return GPFC_OK;
 }
 
 int32_t gpfc_cnn_get_params(gpfc_cnn* c, float* out, void* stream) {
@@ -948,11 +1197,12 @@ int32_t gpfc_cnn_forward_fp8(gpfc_cnn* c, const void* x, int32_t x_f32, int64_t 
     if (B == 0) return GPFC_OK;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
-    if (!c->packed) {
+    const bool cap = capturing(s);
+    if (!c->packed || cap) {
         int32_t rc = pack<BF16>(c, s);
         if (rc != GPFC_OK) return rc;
     }
-    if (!c->quantized) {
+    if (!c->quantized || cap) {
         const void* wsrc[5] = {c->wf2, c->wf3, c->wf4, c->f1f, c->f2f};
         const int rows[5] = {32, 64, 64, 256, 64};
         const int Ks[5] = {80, 160, 320, 1024, 256};
@@ -963,7 +1213,7 @@ int32_t gpfc_cnn_forward_fp8(gpfc_cnn* c, const void* x, int32_t x_f32, int64_t 
                                Ks[i], qs[i], cs[i], c->act_max + i);
         e = hipGetLastError();
         if (e != hipSuccess) return cnn_err(e, "k_quant_rows");
-        c->quantized = true;
+        c->quantized = !cap;
     }
     float inv[5];
     for (int i = 0; i < 5; ++i) inv[i] = c->act_max_host[i] > 0.0f ? 448.0f / c->act_max_host[i] : 1.0f;
@@ -971,16 +1221,15 @@ int32_t gpfc_cnn_forward_fp8(gpfc_cnn* c, const void* x, int32_t x_f32, int64_t 
     using T = uint16_t;
     const int Bi = (int)B;
     hipLaunchKernelGGL((k_conv1_fwd<BF16>), dim3(blocks_for(B * 128 * 16)), dim3(256), 0, s, x, x_f32,
-                       Bi, w + kConvW[1], w + conv_b(1), (T*)c->a1, c->m1);
+                       Bi, w + kConvW[1], w + conv_b(1), (T*)c->a1, (uint8_t*)nullptr);
     T* acts[5] = {nullptr, (T*)c->a1, (T*)c->a2, (T*)c->a3, (T*)c->a4};
-    uint8_t* masks[5] = {nullptr, c->m1, c->m2, c->m3, c->m4};
     uint8_t* qw[5] = {nullptr, nullptr, c->q2, c->q3, c->q4};
     float* cs[5] = {nullptr, nullptr, c->cs2, c->cs3, c->cs4};
     for (int l = 2; l <= 4; ++l) {
         const int Cin = CH[l - 1], Cout = CH[l], L = LEN[l - 1];
         ActQ<ConvRows<BF16>> la{ConvRows<BF16>{acts[l - 1], L, Cin, Bi * L, +1}, inv[l - 2]};
         WQ lb{qw[l], Cout, 5 * Cin, 5 * Cin};
-        EpConvFwd<BF16> ep{w + conv_b(l), acts[l], masks[l], Cout, cs[l]};
+        EpConvFwd<BF16> ep{w + conv_b(l), acts[l], nullptr, Cout, cs[l]};
         e = gemm<FP8>(Bi * L, Cout, 5 * Cin, la, lb, ep, s);
         if (e != hipSuccess) return cnn_err(e, "conv gemm fp8");
     }
@@ -990,8 +1239,8 @@ int32_t gpfc_cnn_forward_fp8(gpfc_cnn* c, const void* x, int32_t x_f32, int64_t 
     e = gemm<FP8>(Bi, 64, 256, ActQ<Rows<BF16>>{Rows<BF16>{(const T*)c->h1, Bi, 256, 256}, inv[4]},
                   WQ{c->qf2, 64, 256, 256}, EpFcFwd<BF16>{w + F2B, (T*)c->h2, 64, c->csf2}, s);
     if (e != hipSuccess) return cnn_err(e, "fc2 gemm fp8");
-    hipLaunchKernelGGL((k_head<BF16>), dim3(1), dim3(256), 0, s, (const T*)c->h2, Bi, w + F3W, w + F3B,
-                       (const float*)nullptr, logits, c->loss, c->grad, (T*)c->d_a);
+    hipLaunchKernelGGL((k_head_infer<BF16>), dim3(blocks_for(B)), dim3(256), 0, s, (const T*)c->h2,
+                       Bi, w + F3W, w + F3B, logits);
     e = hipGetLastError();
     return e == hipSuccess ? GPFC_OK : cnn_err(e, "k_head fp8");
 }

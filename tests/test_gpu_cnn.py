@@ -186,3 +186,28 @@ def test_fp8_forward_error(torch_dev):
     print(f"fp8 forward relative L2 error vs FP64: {e8:.3e} (bf16 {eb:.3e})")
     assert e8 < 0.15
     assert np.corrcoef(z8, zo)[0, 1] > 0.99
+
+
+@pytest.mark.parametrize("B", [1, 7, 8, 9, 300, 4099])
+def test_fused_inference_bit_identical(torch_dev, B):
+    """The fused convolution-stack kernel against the layer-by-layer path:
+    identical logits, ragged last tiles included."""
+    torch = torch_dev
+    from paper_2312_02063_amd import CNN_BF16
+    p = _params(19)
+    x, _ = _inputs(20 + B, B)
+    net = _net(torch, CNN_BF16, p, max_batch=4099)
+    xt = torch.tensor(x, dtype=torch.float32, device="cuda")
+    _say(f"cnn fused vs layered B={B}")
+    zf = net.forward(xt).cpu().numpy()
+    net.set_fused(False)
+    zl = net.forward(xt).cpu().numpy()
+    net.set_fused(True)
+    xb = xt.to(torch.bfloat16).view(torch.uint16)
+    zfb = net.forward(xb).cpu().numpy()
+    net.set_fused(False)
+    zlb = net.forward(xb).cpu().numpy()
+    assert np.array_equal(zf, zl)
+    assert np.array_equal(zfb, zlb)
+    zo = oracle.cnn_forward(p, x)
+    assert _rel(zf, zo) < 5e-2
