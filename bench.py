@@ -77,6 +77,123 @@ def cpu_baseline(c, periods, sample):
             "seconds": dt}
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0                 # dense bf16 matrix cores
+HBM_PEAK_GBS = 8000.0
+CNN_FWD_FLOP = 3.87e6                           # per input: 1.94 M multiply-adds
+CNN_TRAIN_FLOP = 3 * CNN_FWD_FLOP               # forward + data and weight gradients
+
+
+def _events_ms(fn, reps):
+    """Average ms of fn() over reps calls, HIP events on the current stream."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def measure_rows(plan, t, f, pp, periods, survey_stars):
+    """Each step of the path on its own at the benchmark shapes (and the
+    many-star survey), with the roofline that bounds it."""
+    import numpy as np
+    import torch
+    from paper_2312_02063_amd import CNN_BF16, Cnn, synth, topk
+    dev = t.device
+    rows = {}
+    plan.prepare(t, f)
+    # a4: materialised fold (sums f64, counts i32, means f64: 20 B per bin)
+    kf = 200_000
+    pk = pp[:kf].contiguous()
+    ms = _events_ms(lambda: plan.fold_prepared(pk, NBINS), 3)
+    rows["a4_materialised_fold"] = {"periods_per_s": kf / ms * 1e3, "ms": ms, "periods": kf,
+                                    "hbm_written_GBs": kf * NBINS * 20 / ms / 1e6,
+                                    "bound": "lds (the fold); output 5 KB per period"}
+    # a3 form 1: FP32 plain / compensated float sums
+    for comp in (False, True):
+        ms = _events_ms(lambda: plan.fold_f32_prepared(pk[:20_000].contiguous(), NBINS, comp), 2)
+        rows["a3_fp32_" + ("twosum" if comp else "plain")] = {"periods_per_s": 20_000 / ms * 1e3,
+                                                              "ms": ms, "periods": 20_000}
+    # a6: fused fold + score + bf16 normalised folds
+    kz = 500_000
+    pz = pp[:kz].contiguous()
+    z = torch.empty((kz, NBINS), dtype=torch.uint16, device=dev)
+    ms0 = _events_ms(lambda: plan.fold_score_prepared(pz, NBINS), 3)
+    ms1 = _events_ms(lambda: plan.fold_score_prepared(pz, NBINS, zfold=z), 3)
+    rows["a6_normalised_folds"] = {"periods_per_s": kz / ms1 * 1e3, "extra_ms_for_zfold": ms1 - ms0,
+                                   "zfold_GBs": kz * NBINS * 2 / max(ms1 - ms0, 1e-6) / 1e6}
+    # a7: network inference (bf16, fused convolution stack)
+    B = 262_144
+    net = Cnn(0, CNN_BF16, B)
+    net.set_params(synth.cnn_init(1003).astype(np.float32))
+    zz = z[:B] if kz >= B else torch.zeros((B, NBINS), dtype=torch.uint16, device=dev)
+    lg = torch.empty(B, dtype=torch.float32, device=dev)
+    ms = _events_ms(lambda: net.forward(zz, out=lg), 5)
+    tf = B * CNN_FWD_FLOP / ms / 1e9
+    rows["a7_cnn_inference_bf16"] = {"folds_per_s": B / ms * 1e3, "ms": ms, "batch": B,
+                                     "tflops": tf, "bound": "mfma", "peak_tflops": MFMA_BF16_PEAK_TFLOPS,
+                                     "frac": tf / MFMA_BF16_PEAK_TFLOPS}
+    net.set_fused(False)
+    ms_l = _events_ms(lambda: net.forward(zz, out=lg), 3)
+    net.set_fused(True)
+    rows["a7_cnn_inference_bf16"]["layer_by_layer_ms"] = ms_l
+    # a9: training step (forward, backward, Adam) at batch 1024
+    Bt = 1024
+    y = (torch.arange(Bt, device=dev) % 2).float()
+    xt = zz[:Bt].contiguous()
+    ms = _events_ms(lambda: net.train_step(xt, y, 1e-5), 10)
+    tf = Bt * CNN_TRAIN_FLOP / ms / 1e9
+    rows["a9_cnn_training_bf16"] = {"samples_per_s": Bt / ms * 1e3, "ms_per_step": ms, "batch": Bt,
+                                    "tflops": tf, "bound": "mfma", "frac": tf / MFMA_BF16_PEAK_TFLOPS}
+    del net, zz, z
+    # a8: per-curve best-K over the 2,000,000-period box-SNR periodogram
+    snr = plan.fold_score(t, f, pp, NBINS)[0]
+    ms = _events_ms(lambda: topk(snr, 16), 10)
+    rows["a8_topk"] = {"ms": ms, "scores": int(snr.numel()), "top": 16,
+                      "GBs": snr.numel() * 4 / ms / 1e6, "bound": "hbm", "peak_GBs": HBM_PEAK_GBS}
+    # a10: many-star survey (fold + box-SNR + bf16 network + per-curve best-K)
+    if survey_stars > 0:
+        stars = synth.multi_star(seed=1005, n_stars=survey_stars,
+                                 n_transit=max(1, survey_stars // 10))
+        ks = 500_000
+        grid = torch.tensor(synth.freq_grid(FMIN, FMAX, ks), dtype=torch.float64, device=dev)
+        so = np.concatenate([[0], np.cumsum([s.t.size for s in stars])]).astype(np.int64)
+        ts = torch.tensor(np.concatenate([s.t for s in stars]), dtype=torch.float64, device=dev)
+        fs = torch.tensor(np.concatenate([s.flux for s in stars]), dtype=torch.float32, device=dev)
+        sp = Plan(0)
+        sp.survey_setup(so, ks, chunk_folds=4_000_000)
+        snet = Cnn(0, CNN_BF16, 1 << 20)
+        snet.set_params(synth.cnn_init(1003).astype(np.float32))
+        r = sp.survey_run(ts, fs, grid, NBINS, cnn=snet, top=4, judge_snr=4.0)
+        torch.cuda.synchronize()
+        del r
+        t0 = time.perf_counter()
+        r = sp.survey_run(ts, fs, grid, NBINS, cnn=snet, top=4, judge_snr=4.0)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        upd = float(so[-1]) * ks
+        folds = survey_stars * ks
+        truth = [s.truth for s in stars]
+        found = 0
+        idx = r["box_idx"][:, 0].cpu().numpy()
+        gp = grid.cpu().numpy()
+        for j, tr in enumerate(truth):
+            if tr.get("has_transit"):
+                p_best = gp[idx[j]]
+                found += int(abs(p_best - tr["period"]) / tr["period"] < 2e-3)
+        rows["a10_survey"] = {"stars": survey_stars, "periods_per_star": ks, "samples": int(so[-1]),
+                              "seconds": wall, "updates_per_s": upd / wall,
+                              "folds_scored_per_s": folds / wall,
+                              "box_best_at_injected_period": f"{found}/{sum(1 for x in truth if x.get('has_transit'))}"}
+        del r, sp, snet
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +202,9 @@ def main():
     ap.add_argument("--k", type=int, default=K_PERIODS, help="trial periods (default 2,000,000)")
     ap.add_argument("--cpu-sample", type=int, default=20_000, help="oracle sample in periods (0: skip)")
     ap.add_argument("--naive-k", type=int, default=20_000, help="periods for the plain-fold rate (0: skip)")
+    ap.add_argument("--rows", type=int, default=1, help="also measure each step on its own (0: skip)")
+    ap.add_argument("--survey-stars", type=int, default=512,
+                    help="stars in the many-star survey measurement (0: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -161,6 +281,8 @@ def main():
         torch.add(a, 1.0, out=b)
         torch.cuda.synchronize()
 
+    rows = measure_rows(plan, t, f, pp, periods, args.survey_stars) if args.rows else None
+
     cpu = None
     if args.cpu_sample > 0:
         cpu = cpu_baseline(c, periods, min(args.cpu_sample, args.k))
@@ -193,6 +315,7 @@ def main():
         "vs_plain_fold": (value / naive) if naive else None,
         "paper_context": {"periods_per_s": 2.0e4, "hardware": "RTX 3090 Ti",
                           "workload": "70,000-epoch curve, 100,000 periods, 256 bins (fold only)"},
+        "rows": rows,
         "best_period_d": float(periods[best]),
         "injected_period_d": c.truth["period"],
     }

@@ -175,6 +175,31 @@ int32_t gpfc_fold_f32_prepared(gpfc_plan *plan, const double *periods, int64_t k
                                void *stream);
 
 /*
+ * Sample split of the fold + score of one curve: a grid of fewer 64-period
+ * tiles than compute units leaves most of the chip idle, so each tile's
+ * samples can be split over `split` blocks whose histograms are merged with
+ * exact 64-bit integer atomics (results are identical for every split).
+ * split = 0 (default): the value gpfc_autotune found for the prepared
+ * curve's n, the grid size and nbins, else one block per compute unit;
+ * 1..GPFC_MAX_SPLIT: forced. Applies to gpfc_fold_score and
+ * gpfc_fold_score_prepared.
+ */
+#define GPFC_MAX_SPLIT 64
+int32_t gpfc_plan_set_split(gpfc_plan *plan, int32_t split);
+
+/*
+ * Autotuner of the block shape for the prepared curve at these periods and
+ * nbins: times every power-of-two split the grid allows (3 runs each, HIP
+ * events on `stream`; synchronous; allocates a temporary output) and keeps
+ * the fastest in the plan. With cache_path (may be NULL) a line
+ * "<device> <n> <k> <nbins> <split>" is looked up first (then nothing is
+ * timed) and appended after timing. split_out, ms_out (may be NULL): the
+ * choice and its time (-1 when taken from the cache).
+ */
+int32_t gpfc_autotune(gpfc_plan *plan, const double *periods, int64_t k, int32_t nbins,
+                      const char *cache_path, int32_t *split_out, float *ms_out, void *stream);
+
+/*
  * Multi-curve batch: many light curves folded and scored in one persistent
  * launch (the paper processes a catalogue curve after curve, overlapping the fold of one
  * curve with the network on the previous one, Sec. 3.3).

@@ -85,6 +85,9 @@ def load():
         "gpfc_batch_curve_stats": ([vp, ctypes.POINTER(Curve), vp], i32),
         "gpfc_sync": ([vp], i32),
         "gpfc_topk": ([vp, i64, i64, vp, ctypes.c_float, i32, vp, vp, vp], i32),
+        "gpfc_plan_set_split": ([vp, i32], i32),
+        "gpfc_autotune": ([vp, vp, i64, i32, ctypes.c_char_p, ctypes.POINTER(i32),
+                           ctypes.POINTER(ctypes.c_float), vp], i32),
         "gpfc_survey_setup": ([vp, ctypes.POINTER(ctypes.c_int64), i32, i64, i64], i32),
         "gpfc_survey_run": ([vp, vp, vp, vp, vp, i32, ctypes.POINTER(SurveyOut), vp], i32),
         "gpfc_survey_capture": ([vp, vp, vp, vp, vp, i32, ctypes.POINTER(SurveyOut), vp], i32),
@@ -120,7 +123,8 @@ def exported_symbols():
             "gpfc_batch_curve_stats", "gpfc_cnn_nparams", "gpfc_cnn_last_error",
             "gpfc_cnn_create", "gpfc_cnn_destroy", "gpfc_cnn_set_params", "gpfc_cnn_get_params",
             "gpfc_cnn_forward", "gpfc_cnn_backward", "gpfc_cnn_adam", "gpfc_cnn_calibrate_fp8",
-            "gpfc_cnn_forward_fp8", "gpfc_cnn_set_fused", "gpfc_topk", "gpfc_survey_setup", "gpfc_survey_run",
+            "gpfc_cnn_forward_fp8", "gpfc_cnn_set_fused", "gpfc_topk", "gpfc_plan_set_split",
+            "gpfc_autotune", "gpfc_survey_setup", "gpfc_survey_run",
             "gpfc_survey_capture"]
 
 
@@ -339,6 +343,21 @@ class Plan:
         arr = (Curve * max(1, self.batch_n))()
         _check(self.lib.gpfc_batch_curve_stats(self.h, arr, _stream()), "gpfc_batch_curve_stats")
         return [arr[i].as_dict() for i in range(self.batch_n)]
+
+    def set_split(self, split: int):
+        """Sample split of the single-curve fold + score (0: automatic)."""
+        _check(self.lib.gpfc_plan_set_split(self.h, int(split)), "gpfc_plan_set_split")
+
+    def autotune(self, periods, nbins: int, cache_path: str | None = None):
+        """Time the block shapes for the prepared curve at these periods; returns (split, ms)."""
+        import torch
+        _need(periods, torch.float64, "periods", self.device)
+        sp = ctypes.c_int32(0)
+        ms = ctypes.c_float(0.0)
+        _check(self.lib.gpfc_autotune(self.h, _ptr(periods), periods.numel(), nbins,
+                                      cache_path.encode() if cache_path else None,
+                                      ctypes.byref(sp), ctypes.byref(ms), _stream()), "gpfc_autotune")
+        return sp.value, ms.value
 
     # ---------------------------------------------------------------- surveys
 

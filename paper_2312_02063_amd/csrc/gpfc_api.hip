@@ -47,6 +47,13 @@ struct gpfc_plan {
     uint16_t* s_zbuf = nullptr;        // normalised folds of one chunk (inside b_dev)
     int64_t s_zfolds = 0;              // folds s_zbuf holds (0: no workspace)
     std::vector<SurveyChunk> s_chunks;
+    // sample split of the single-curve fold + score (k_fold_score_split)
+    int32_t split = 0;                 // 0: automatic
+    int64_t tuned_n = -1, tuned_k = -1;
+    int32_t tuned_nbins = 0, tuned_split = 1;
+    unsigned long long* split_gh = nullptr;   // n_cu tiles x 256 x 64, zero between launches
+    int32_t* split_arrivals = nullptr;        // n_cu counters, zero between launches
+    char device_name[64] = "";
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
 };
@@ -171,6 +178,22 @@ int32_t gpfc_plan_create(gpfc_plan** out, int32_t device) {
     if (!p) return GPFC_ENOMEM;
     p->device = device;
     p->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+    snprintf(p->device_name, sizeof(p->device_name), "%s", prop.gcnArchName);
+    for (char* c = p->device_name; *c; ++c)
+        if (*c == ' ' || *c == ':') *c = '_';
+    e = hipSetDevice(device);
+    const size_t gh_bytes = (size_t)p->n_cu * gpfc::kFineBins * 64 * sizeof(unsigned long long);
+    if (e == hipSuccess) e = hipMalloc(&p->split_gh, gh_bytes);
+    if (e == hipSuccess) e = hipMalloc(&p->split_arrivals, sizeof(int32_t) * p->n_cu);
+    if (e == hipSuccess) e = hipMemset(p->split_gh, 0, gh_bytes);
+    if (e == hipSuccess) e = hipMemset(p->split_arrivals, 0, sizeof(int32_t) * p->n_cu);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        if (p->split_gh) (void)hipFree(p->split_gh);
+        if (p->split_arrivals) (void)hipFree(p->split_arrivals);
+        delete p;
+        return e == hipErrorOutOfMemory ? GPFC_ENOMEM : device_error(e, "plan workspace");
+    }
     *out = p;
     return GPFC_OK;
 }
@@ -184,6 +207,8 @@ int32_t gpfc_plan_destroy(gpfc_plan* p) {
     if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->b_dev) (void)hipFree(p->b_dev);
+    if (p->split_gh) (void)hipFree(p->split_gh);
+    if (p->split_arrivals) (void)hipFree(p->split_arrivals);
     delete p;
     return GPFC_OK;
 }
@@ -242,6 +267,41 @@ int32_t gpfc_fold_prepared(gpfc_plan* p, const double* periods, int64_t k, int32
     return GPFC_OK;
 }
 
+// Largest power of two <= x (x >= 1).
+static int32_t pow2_floor(int64_t x) {
+    int32_t r = 1;
+    while ((int64_t)r * 2 <= x) r *= 2;
+    return r;
+}
+
+// Sample split for a fold + score of the prepared curve (n samples) at k
+// periods: the forced value, else the autotuned one for this shape, else
+// enough blocks per 64-period tile to give every compute unit one block,
+// keeping at least 512 records per wave per part.
+static int32_t resolve_split(const gpfc_plan* p, int64_t n, int64_t k, int32_t nbins) {
+    const int64_t tiles = (k + 63) / 64;
+    if (tiles == 0 || tiles > p->n_cu) return 1;
+    int32_t sp;
+    if (p->split > 0) sp = p->split;
+    else if (p->tuned_n == n && p->tuned_k == k && p->tuned_nbins == nbins) sp = p->tuned_split;
+    else {
+        const int64_t per = gpfc::slice_len(n);
+        sp = pow2_floor(std::max<int64_t>(1, std::min<int64_t>(p->n_cu / tiles, per / 512)));
+    }
+    return std::max(1, std::min(sp, GPFC_MAX_SPLIT));
+}
+
+static hipError_t enqueue_fold_score(gpfc_plan* p, int64_t n, const double* periods, int64_t k,
+                                     int32_t nbins, float* snr, int32_t* start, int32_t* width,
+                                     float* depth, uint16_t* zfold, int32_t split, hipStream_t s) {
+    if (split <= 1)
+        return gpfc::launch_fold_score(p->rec, n, periods, k, nbins, p->info, plan_widths(p, nbins),
+                                       snr, start, width, depth, zfold, s);
+    return gpfc::launch_fold_score_split(p->rec, n, periods, k, nbins, p->info, plan_widths(p, nbins),
+                                         split, p->split_gh, p->split_arrivals, snr, start, width,
+                                         depth, zfold, s);
+}
+
 int32_t gpfc_fold_score_prepared(gpfc_plan* p, const double* periods, int64_t k, int32_t nbins,
                                  float* snr, int32_t* start, int32_t* width, float* depth,
                                  uint16_t* zfold, void* stream) {
@@ -251,9 +311,91 @@ int32_t gpfc_fold_score_prepared(gpfc_plan* p, const double* periods, int64_t k,
     if (zfold && nbins < 16) return GPFC_ENOTSUP;
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return device_error(e, "hipSetDevice");
-    e = gpfc::launch_fold_score(p->rec, p->n, periods, k, nbins, p->info, plan_widths(p, nbins),
-                                snr, start, width, depth, zfold, (hipStream_t)stream);
+    e = enqueue_fold_score(p, p->n, periods, k, nbins, snr, start, width, depth, zfold,
+                           resolve_split(p, p->n, k, nbins), (hipStream_t)stream);
     if (e != hipSuccess) return device_error(e, "k_fold_score launch");
+    return GPFC_OK;
+}
+
+// Cache lines: "<device> <n> <k> <nbins> <split>".
+static bool cache_lookup(const char* path, const char* dev, int64_t n, int64_t k, int32_t nbins,
+                         int32_t* split) {
+    if (!path) return false;
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char name[64];
+    long long cn, ck;
+    int cb, cs;
+    bool found = false;
+    while (fscanf(f, "%63s %lld %lld %d %d", name, &cn, &ck, &cb, &cs) == 5)
+        if (!strcmp(name, dev) && cn == n && ck == k && cb == nbins && cs >= 1 && cs <= GPFC_MAX_SPLIT) {
+            *split = cs;
+            found = true;
+        }
+    fclose(f);
+    return found;
+}
+
+int32_t gpfc_autotune(gpfc_plan* p, const double* periods, int64_t k, int32_t nbins,
+                      const char* cache_path, int32_t* split_out, float* ms_out, void* stream) {
+    int32_t rc = check_prepared(p, periods, k, nbins);
+    if (rc != GPFC_OK) return rc;
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return device_error(e, "hipSetDevice");
+    const int64_t tiles = (k + 63) / 64;
+    int32_t best = 1;
+    float best_ms = -1.0f;
+    if (cache_lookup(cache_path, p->device_name, p->n, k, nbins, &best)) {
+        // known shape: no timing
+    } else if (tiles >= 1 && tiles <= p->n_cu) {
+        hipStream_t s = (hipStream_t)stream;
+        void* out = nullptr;
+        e = hipMalloc(&out, (size_t)k * 16);
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? GPFC_ENOMEM : device_error(e, "hipMalloc");
+        float* snr = (float*)out;
+        int32_t* st = (int32_t*)(snr + k);
+        int32_t* wd = st + k;
+        float* dp = (float*)(wd + k);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        const int64_t per = gpfc::slice_len(p->n);
+        for (int32_t sp = 1; e == hipSuccess && sp <= GPFC_MAX_SPLIT; sp *= 2) {
+            if (sp > 1 && (tiles * sp > 4 * (int64_t)p->n_cu || per / sp < 32)) break;
+            e = enqueue_fold_score(p, p->n, periods, k, nbins, snr, st, wd, dp, nullptr, sp, s);
+            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            for (int r = 0; r < 3 && e == hipSuccess; ++r)
+                e = enqueue_fold_score(p, p->n, periods, k, nbins, snr, st, wd, dp, nullptr, sp, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            ms /= 3.0f;
+            if (e == hipSuccess && (best_ms < 0.0f || ms < best_ms)) {
+                best_ms = ms;
+                best = sp;
+            }
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(out);
+        if (e != hipSuccess) return device_error(e, "autotune");
+        if (cache_path) {
+            FILE* f = fopen(cache_path, "a");
+            if (f) {
+                fprintf(f, "%s %lld %lld %d %d\n", p->device_name, (long long)p->n, (long long)k,
+                        nbins, best);
+                fclose(f);
+            }
+        }
+    }
+    p->tuned_n = p->n;
+    p->tuned_k = k;
+    p->tuned_nbins = nbins;
+    p->tuned_split = best;
+    if (split_out) *split_out = best;
+    if (ms_out) *ms_out = best_ms;
     return GPFC_OK;
 }
 
@@ -285,6 +427,12 @@ int32_t gpfc_fold(gpfc_plan* p, const double* t, const float* flux, int64_t n,
     return GPFC_OK;
 }
 
+int32_t gpfc_plan_set_split(gpfc_plan* p, int32_t split) {
+    if (!p || split < 0 || split > GPFC_MAX_SPLIT) return GPFC_EINVAL;
+    p->split = split;
+    return GPFC_OK;
+}
+
 int32_t gpfc_fold_score(gpfc_plan* p, const double* t, const float* flux, int64_t n,
                         const double* periods, int64_t k, int32_t nbins, float* snr,
                         int32_t* start, int32_t* width, float* depth, void* stream) {
@@ -294,9 +442,8 @@ int32_t gpfc_fold_score(gpfc_plan* p, const double* t, const float* flux, int64_
     hipStream_t s = (hipStream_t)stream;
     rc = prepare_curve(p, t, flux, n, s);
     if (rc != GPFC_OK) return rc;
-    hipError_t e = gpfc::launch_fold_score(p->rec, n, periods, k, nbins, p->info,
-                                           plan_widths(p, nbins), snr, start, width, depth,
-                                           nullptr, s);
+    hipError_t e = enqueue_fold_score(p, n, periods, k, nbins, snr, start, width, depth, nullptr,
+                                      resolve_split(p, n, k, nbins), s);
     if (e != hipSuccess) return device_error(e, "k_fold_score launch");
     return GPFC_OK;
 }

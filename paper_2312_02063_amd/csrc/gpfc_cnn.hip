@@ -496,23 +496,33 @@ __global__ __launch_bounds__(256) void k_head(const typename P::T* __restrict__ 
 
 constexpr int kTileF = 8;                       // inputs per tile
 constexpr int kFusedThreads = 512;              // 8 waves
-constexpr int kW2Ld = 96, kW3Ld = 160, kW4Ld = 320;   // K of conv2 padded to whole 32-steps
+// LDS row strides (elements). Weight rows hold K padded to whole 32-steps plus
+// 8; activation rows hold the channels plus 8 (conv 2-3 outputs). A row
+// stride that is an odd multiple of 16 bytes spreads the 16 rows an MFMA
+// fragment load touches over distinct bank groups.
+constexpr int kW2Ld = 104, kW3Ld = 168, kW4Ld = 328;
+constexpr int kA1Ld = 16, kA2Ld = 40, kA3Ld = 72;
 
 struct ConvStackLds {
     uint16_t w2[32 * kW2Ld];
     uint16_t w3[64 * kW3Ld];
     uint16_t w4[64 * kW4Ld];
-    uint16_t buf0[kTileF * 128 * 16];            // a1, then a3 ([F][32][64], same size)
-    uint16_t buf1[kTileF * 64 * 32];             // a2
+    float w1[16 * 5];
+    float b1[16];
+    uint16_t xs[kTileF * 256];                     // the tile's inputs (bf16)
+    uint16_t buf0[kTileF * 32 * kA3Ld];            // a1 [F][128][16], then a3 [F][32][72]
+    uint16_t buf1[kTileF * 64 * kA2Ld];            // a2 [F][64][40]
 };
+static_assert(kTileF * 128 * kA1Ld <= kTileF * 32 * kA3Ld, "a1 must fit where a3 goes");
+static_assert(sizeof(ConvStackLds) <= 160 * 1024, "LDS budget");
 
 // One implicit-GEMM conv layer over the tile: rows (f, x) for x < L, columns
 // output channels, k = dx*CIN + ci. Each wave takes 64 x 32 wave-tiles (4 x 2
 // MFMA blocks of 16 x 16) and, per 32-step of k, loads 4 A and 2 B fragments
 // from LDS. The epilogue adds the bias, applies ReLU and max-pools position
-// pairs (both in the lane), then stores bf16 to `out` ([F][L/2][COUT] at
-// out_stride per input), skipping inputs >= nvalid when `to_global`.
-template <int L, int CIN, int COUT, int WLD>
+// pairs (both in the lane), then stores bf16 to `out` ([F][L/2][OLD] rows),
+// skipping inputs >= nvalid when `to_global`.
+template <int L, int CIN, int ILD, int COUT, int WLD, int OLD>
 __device__ __forceinline__ void conv_tile(const uint16_t* __restrict__ in,
                                           const uint16_t* __restrict__ w,
                                           const float* __restrict__ bias, uint16_t* __restrict__ out,
@@ -530,6 +540,7 @@ __device__ __forceinline__ void conv_tile(const uint16_t* __restrict__ in,
         f32x4 acc[4][2];
         for (int i = 0; i < 4; ++i)
             for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
         for (int ks = 0; ks < KSTEPS; ++ks) {
             const int k = ks * 32 + q * 8;
             const int dx = k / CIN, ci0 = k - dx * CIN;
@@ -539,7 +550,7 @@ __device__ __forceinline__ void conv_tile(const uint16_t* __restrict__ in,
                 const int f = m / L, x = m - f * L;
                 int pos = x + dx - 2;
                 pos = pos < 0 ? pos + L : (pos >= L ? pos - L : pos);
-                a[i] = k < K ? *reinterpret_cast<const bf16x8*>(in + (f * L + pos) * CIN + ci0) : bf16x8{};
+                a[i] = k < K ? *reinterpret_cast<const bf16x8*>(in + (f * L + pos) * ILD + ci0) : bf16x8{};
             }
             for (int j = 0; j < 2; ++j)
                 b[j] = *reinterpret_cast<const bf16x8*>(w + (ct * 32 + j * 16 + r) * WLD + ks * 32 + q * 8);
@@ -557,11 +568,26 @@ __device__ __forceinline__ void conv_tile(const uint16_t* __restrict__ in,
                 for (int h = 0; h < 2; ++h) {
                     const float p0 = acc[i][j][2 * h] + bn, p1 = acc[i][j][2 * h + 1] + bn;
                     const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
-                    out[(f * (L / 2) + (x0 >> 1) + h) * COUT + n] = f2bf(r0 >= r1 ? r0 : r1);
+                    out[(f * (L / 2) + (x0 >> 1) + h) * OLD + n] = f2bf(r0 >= r1 ? r0 : r1);
                 }
             }
         }
     }
+}
+
+// The tile's inputs as bf16 bits: thread t holds elements 4t .. 4t+3 of the
+// [kTileF][256] tile (zeros past the last input).
+__device__ __forceinline__ uint2 load_x4(const void* __restrict__ x, int xf32, int f0, int nvalid,
+                                         int tid) {
+    const int e = tid * 4;
+    if ((e >> 8) >= nvalid) return make_uint2(0u, 0u);
+    const int64_t o = (int64_t)f0 * 256 + e;
+    if (xf32) {
+        const float4 v = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(x) + o);
+        return make_uint2((uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16),
+                          (uint32_t)f2bf(v.z) | ((uint32_t)f2bf(v.w) << 16));
+    }
+    return *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(x) + o);
 }
 
 __global__ __launch_bounds__(kFusedThreads, 1) void k_convstack_bf16(
@@ -575,42 +601,58 @@ __global__ __launch_bounds__(kFusedThreads, 1) void k_convstack_bf16(
         const int n = i / kW2Ld, k = i - n * kW2Ld;
         sm.w2[i] = k < 80 ? wf2[n * 80 + k] : (uint16_t)0;
     }
-    for (int i = tid; i < 64 * kW3Ld; i += kFusedThreads) sm.w3[i] = wf3[i];
-    for (int i = tid; i < 64 * kW4Ld; i += kFusedThreads) sm.w4[i] = wf4[i];
+    for (int i = tid; i < 64 * kW3Ld; i += kFusedThreads) {
+        const int n = i / kW3Ld, k = i - n * kW3Ld;
+        sm.w3[i] = k < 160 ? wf3[n * 160 + k] : (uint16_t)0;
+    }
+    for (int i = tid; i < 64 * kW4Ld; i += kFusedThreads) {
+        const int n = i / kW4Ld, k = i - n * kW4Ld;
+        sm.w4[i] = k < 320 ? wf4[n * 320 + k] : (uint16_t)0;
+    }
+    if (tid < 80) sm.w1[tid] = w1[tid];
+    if (tid < 16) sm.b1[tid] = b1[tid];
     const int ntiles = (B + kTileF - 1) / kTileF;
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    int tile = blockIdx.x;
+    // 512 threads x 4 elements = one [8][256] tile
+    uint2 xnext = tile < ntiles ? load_x4(x, xf32, tile * kTileF, min(kTileF, B - tile * kTileF), tid)
+                                : make_uint2(0u, 0u);
+    for (; tile < ntiles; tile += gridDim.x) {
         const int f0 = tile * kTileF;
         const int nvalid = min(kTileF, B - f0);
-        __syncthreads();   // weights staged / previous tile's conv4 done with buf0
-        // conv1 (1 -> 16 channels) on the vector units, as k_conv1_fwd
-        for (int idx = tid; idx < kTileF * 128 * 16; idx += kFusedThreads) {
-            const int co = idx & 15, xp = (idx >> 4) & 127, f = idx >> 11;
-            float r = 0.0f;
-            if (f < nvalid) {
-                const int64_t row = (int64_t)(f0 + f) * 256;
-                float pre[2];
-                for (int h = 0; h < 2; ++h) {
-                    const int xx = 2 * xp + h;
-                    float acc = b1[co];
-                    for (int dx = 0; dx < 5; ++dx) {
-                        const int pos = (xx + dx - 2) & 255;
-                        const float v = xf32 ? reinterpret_cast<const float*>(x)[row + pos]
-                                             : bf2f(reinterpret_cast<const uint16_t*>(x)[row + pos]);
-                        acc += w1[co * 5 + dx] * bf2f(f2bf(v));
-                    }
-                    pre[h] = acc;
+        reinterpret_cast<uint2*>(sm.xs)[tid] = xnext;
+        __syncthreads();   // inputs and weights staged; the previous tile is done with buf0
+        const int tn = tile + gridDim.x;   // prefetch the next tile's inputs
+        if (tn < ntiles) xnext = load_x4(x, xf32, tn * kTileF, min(kTileF, B - tn * kTileF), tid);
+        // conv1 (1 -> 16 channels) on the vector units, as k_conv1_fwd: thread
+        // per (input, pooled position), all 16 channels
+        for (int pi = tid; pi < kTileF * 128; pi += kFusedThreads) {
+            const int f = pi >> 7, xp = pi & 127;
+            float v[6];
+            for (int d = 0; d < 6; ++d) v[d] = bf2f(sm.xs[f * 256 + ((2 * xp + d - 2) & 255)]);
+            uint32_t packed[8];
+            for (int co = 0; co < 16; ++co) {
+                float p0 = sm.b1[co], p1 = sm.b1[co];
+                for (int dx = 0; dx < 5; ++dx) {
+                    p0 += sm.w1[co * 5 + dx] * v[dx];
+                    p1 += sm.w1[co * 5 + dx] * v[dx + 1];
                 }
-                const float r0 = fmaxf(pre[0], 0.0f), r1 = fmaxf(pre[1], 0.0f);
-                r = r0 >= r1 ? r0 : r1;
+                const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
+                const uint32_t hbits = f2bf(r0 >= r1 ? r0 : r1);
+                if (co & 1) packed[co >> 1] |= hbits << 16;
+                else packed[co >> 1] = hbits;
             }
-            sm.buf0[idx] = f2bf(r);
+            uint4* dst = reinterpret_cast<uint4*>(sm.buf0 + (f * 128 + xp) * kA1Ld);
+            dst[0] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
+            dst[1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
         }
         __syncthreads();
-        conv_tile<128, 16, 32, kW2Ld>(sm.buf0, sm.w2, b2, sm.buf1, false, nvalid);
+        conv_tile<128, 16, kA1Ld, 32, kW2Ld, kA2Ld>(sm.buf0, sm.w2, b2, sm.buf1, false, nvalid);
         __syncthreads();
-        conv_tile<64, 32, 64, kW3Ld>(sm.buf1, sm.w3, b3, sm.buf0, false, nvalid);
+        conv_tile<64, 32, kA2Ld, 64, kW3Ld, kA3Ld>(sm.buf1, sm.w3, b3, sm.buf0, false, nvalid);
         __syncthreads();
-        conv_tile<32, 64, 64, kW4Ld>(sm.buf0, sm.w4, b4, a4 + (int64_t)f0 * 1024, true, nvalid);
+        conv_tile<32, 64, kA3Ld, 64, kW4Ld, 64>(sm.buf0, sm.w4, b4, a4 + (int64_t)f0 * 1024, true,
+                                                nvalid);
+        __syncthreads();   // conv4 has read buf0 and every thread is done with xs
     }
 }
 
@@ -903,7 +945,8 @@ int32_t forward(gpfc_cnn* c, const void* x, int xf32, int B, float* logits, cons
     if (!train) masks[2] = masks[3] = masks[4] = nullptr;
     void* wfs[5] = {nullptr, nullptr, c->wf2, c->wf3, c->wf4};
     // inference of a bf16 network: the fused convolution stack (bit-identical)
-    const bool fused = __is_same(P, BF16) && !train && logits && c->fused;
+    const bool fused = __is_same(P, BF16) && !train && logits && c->fused &&
+                       ((uintptr_t)x & 15) == 0;   // the fused kernel loads 16-byte groups
     if (fused) {
         const int ntiles = (B + kTileF - 1) / kTileF;
         hipLaunchKernelGGL(k_convstack_bf16, dim3((unsigned)std::min(ntiles, c->n_cu)),

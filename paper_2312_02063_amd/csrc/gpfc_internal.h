@@ -77,6 +77,14 @@ hipError_t launch_fold_score(const Rec* rec, int64_t n,
                              const CurveInfo* info, const Widths& widths, float* snr,
                              int32_t* start, int32_t* width, float* depth, uint16_t* zfold,
                              hipStream_t s);
+// Fold + score with the samples of each 64-period tile split over `split`
+// blocks merged through gh (tiles x 256 x 64 u64, zero on entry and on exit)
+// and arrivals (tiles int32, zero on entry and on exit).
+hipError_t launch_fold_score_split(const Rec* rec, int64_t n, const double* periods, int64_t k,
+                                   int32_t nbins, const CurveInfo* info, const Widths& widths,
+                                   int32_t split, unsigned long long* gh, int32_t* arrivals,
+                                   float* snr, int32_t* start, int32_t* width, float* depth,
+                                   uint16_t* zfold, hipStream_t s);
 hipError_t launch_batch_prepare(const double* t, const float* flux, const int64_t* soff,
                                 const int64_t* roff, int32_t n_curves, int64_t max_records,
                                 CurveInfo* infos, Rec* rec, hipStream_t s);

@@ -605,6 +605,11 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
 // bfloat16 z-scores over its non-empty bins (bin means minus their mean, over
 // their std with ddof 0; empty bins and zero spread give 0) - the input the
 // learned scorer takes.
+__device__ void score_body(char* hist, uint64_t* chunk, ScoreShared& sh,
+                           const CurveInfo* __restrict__ info, const LaneSetup& L, int64_t kk,
+                           int64_t k, int32_t log2g, const Widths& W, float* snr, int32_t* start,
+                           int32_t* width, float* depth, uint16_t* zfold);
+
 __device__ void fold_score_body(char* hist, uint64_t* chunk, ScoreShared& sh,
                                 const Rec* __restrict__ rec, int64_t per,
                                 const CurveInfo* __restrict__ info,
@@ -616,6 +621,17 @@ __device__ void fold_score_body(char* hist, uint64_t* chunk, ScoreShared& sh,
     const int64_t kk = kbase + lane;
     const LaneSetup L = lane_setup(periods, kk, k, info->tmax);
     fold_block(hist, rec, per, L, lane, wave);
+    score_body(hist, chunk, sh, info, L, kk, k, log2g, W, snr, start, width, depth, zfold);
+}
+
+// Everything after the fold: the block's packed histogram (64 periods x 256
+// fine bins) becomes the fused score, and optionally the normalised folds.
+__device__ void score_body(char* hist, uint64_t* chunk, ScoreShared& sh,
+                           const CurveInfo* __restrict__ info, const LaneSetup& L, int64_t kk,
+                           int64_t k, int32_t log2g, const Widths& W, float* snr, int32_t* start,
+                           int32_t* width, float* depth, uint16_t* zfold) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
     // Inclusive prefix over the wave's 16 fine rows (packed values add exactly).
     const int r0 = wave * kRowsPerWave;
@@ -723,6 +739,55 @@ __global__ __launch_bounds__(kThreads, 1) void k_fold_score(
     __shared__ ScoreShared sh;
     fold_score_body(hist, chunk, sh, rec, per, info, periods, k, (int64_t)blockIdx.x * 64, log2g, W,
                     snr, start, width, depth, zfold);
+}
+
+// Fold + score with the samples split over gridDim.y blocks per 64-period
+// tile, for grids too small to fill the chip: block (tile, s) folds part s of
+// every wave slice into its LDS histogram and adds it into the tile's global
+// histogram with 64-bit integer atomics (exact, any order). The block that
+// arrives last (a device counter per tile, after a release fence) takes the
+// merged histogram back into LDS, clearing the global copy and the counter
+// for the next launch, and scores it like k_fold_score. No block waits on
+// another.
+__global__ __launch_bounds__(kThreads, 1) void k_fold_score_split(
+    const Rec* __restrict__ rec, int64_t per, int64_t per_s,
+    const double* __restrict__ periods, int64_t k, int32_t log2g,
+    const CurveInfo* __restrict__ info, Widths W, float* __restrict__ snr,
+    int32_t* __restrict__ start, int32_t* __restrict__ width, float* __restrict__ depth,
+    uint16_t* __restrict__ zfold, unsigned long long* __restrict__ gh, int32_t* __restrict__ arrivals) {
+    __shared__ __attribute__((aligned(16))) char hist[kFineBins * 64 * 8];
+    __shared__ uint64_t chunk[kWaves * 64];
+    __shared__ ScoreShared sh;
+    __shared__ int32_t is_last;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = blockIdx.x;
+    const int64_t kk = (int64_t)tile * 64 + lane;
+    const LaneSetup L = lane_setup(periods, kk, k, info->tmax);
+    uint64_t* h64 = reinterpret_cast<uint64_t*>(hist);
+    for (int i = threadIdx.x; i < kFineBins * 64; i += kThreads) h64[i] = 0;
+    __syncthreads();
+    const int64_t b0 = (int64_t)blockIdx.y * per_s;
+    const int64_t len = b0 < per ? min(per_s, per - b0) : 0;   // a multiple of 2 kBlk
+    const uint32_t laneoff = (uint32_t)((lane & 31) * 8 + (lane >> 5) * kHalfBytes);
+    // an empty part reads nothing (its first prefetch would lie past the records)
+    if (len > 0) fold_slice(hist, rec, (int64_t)wave * per + b0, len / (2 * kBlk), L, laneoff);
+    __syncthreads();
+    unsigned long long* g = gh + (int64_t)tile * (kFineBins * 64);
+    for (int i = threadIdx.x; i < kFineBins * 64; i += kThreads) {
+        const uint64_t v = h64[i];
+        if (v) atomicAdd(g + i, (unsigned long long)v);
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) is_last = atomicAdd(arrivals + tile, 1) == (int)gridDim.y - 1;
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    for (int i = threadIdx.x; i < kFineBins * 64; i += kThreads) h64[i] = atomicExch(g + i, 0ull);
+    if (threadIdx.x == 0) atomicExch(arrivals + tile, 0);
+    __syncthreads();
+    score_body(hist, chunk, sh, info, L, kk, k, log2g, W, snr, start, width, depth, zfold);
 }
 
 // Persistent multi-curve fold + score: one block per CU pulls work items
@@ -911,6 +976,22 @@ hipError_t launch_fold_score(const Rec* rec, int64_t n,
     const int64_t blocks = (k + 63) / 64;
     hipLaunchKernelGGL(k_fold_score, dim3((unsigned)blocks), dim3(kThreads), 0, s, rec, fold_slice_len(n),
                        periods, k, 8 - log2_of(nbins), info, widths, snr, start, width, depth, zfold);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_score_split(const Rec* rec, int64_t n, const double* periods, int64_t k,
+                                   int32_t nbins, const CurveInfo* info, const Widths& widths,
+                                   int32_t split, unsigned long long* gh, int32_t* arrivals,
+                                   float* snr, int32_t* start, int32_t* width, float* depth,
+                                   uint16_t* zfold, hipStream_t s) {
+    if (k == 0) return hipSuccess;
+    const int64_t tiles = (k + 63) / 64;
+    const int64_t per = fold_slice_len(n);
+    const int64_t q = 2 * kBlk;
+    const int64_t per_s = ((per + split - 1) / split + q - 1) / q * q;
+    hipLaunchKernelGGL(k_fold_score_split, dim3((unsigned)tiles, (unsigned)split), dim3(kThreads), 0, s,
+                       rec, per, per_s, periods, k, 8 - log2_of(nbins), info, widths, snr, start, width,
+                       depth, zfold, gh, arrivals);
     return hipGetLastError();
 }
 

@@ -113,6 +113,33 @@ def train(net, z, labels, epochs: int = 4, batch: int = 256, lr: float = 1e-3, s
     return hist
 
 
+def mine_hard_negatives(plan, net, n_curves: int, per_curve: int, seed: int, periods: np.ndarray,
+                        chunk: int = 250, cnn_batch: int = 65536):
+    """Fold fresh no-transit curves over the whole grid, score every fold and
+    keep each curve's `per_curve` best-scoring folds (per-curve best-K on the
+    GPU): the folds the detection statistic's false positives come from."""
+    import torch
+    from ._lib import topk
+    rng = np.random.Generator(np.random.PCG64(seed))
+    k = periods.size
+    out = []
+    done = 0
+    while done < n_curves:
+        m = min(chunk, n_curves - done)
+        sig = np.exp(rng.uniform(np.log(1e-4), np.log(1e-3), m))
+        t, flux = synth.training_flux_torch({}, np.zeros(m, bool), sig, N_SAMPLES,
+                                            seed=int(rng.integers(1 << 62)))
+        z, _ = _fold_chunk(plan, t, flux, np.tile(periods, m), k)
+        logits = torch.empty(m * k, dtype=torch.float32, device=z.device)
+        for i in range(0, m * k, cnn_batch):
+            net.forward(z[i:i + cnn_batch], out=logits[i:i + cnn_batch])
+        _, idx = topk(logits.view(m, k), per_curve)
+        rows = (idx + torch.arange(m, device=z.device)[:, None] * k).reshape(-1)
+        out.append(z.index_select(0, rows))
+        done += m
+    return torch.cat(out)
+
+
 def evaluate(plan, net, n_pos: int, n_neg: int, seed: int, periods: np.ndarray, chunk: int = 250,
              cnn_batch: int = 65536, log=None, judge_snr: float = 4.0):
     """Per held-out curve: best CNN logit and best box-SNR over all periods."""
@@ -208,6 +235,11 @@ def main():
     ap.add_argument("--save", type=str, default="", help="write the trained FP32 parameters (.npy)")
     ap.add_argument("--snr-cut", type=float, default=0.0,
                     help="label injections below this SNR as negatives (the paper uses 5)")
+    ap.add_argument("--hard-rounds", type=int, default=0,
+                    help="rounds of hard-negative mining after the first training")
+    ap.add_argument("--hard-curves", type=int, default=20000, help="no-transit curves mined per round")
+    ap.add_argument("--hard-per-curve", type=int, default=4, help="best-scoring folds kept per curve")
+    ap.add_argument("--hard-epochs", type=int, default=2, help="epochs after each mining round")
     args = ap.parse_args()
     import torch
 
@@ -225,6 +257,16 @@ def main():
     net.set_params(synth.cnn_init(1003).astype(np.float32))
     t1 = time.time()
     hist = train(net, z, y, args.epochs, args.batch, args.lr, log=log)
+    for rnd in range(args.hard_rounds):
+        hard = mine_hard_negatives(plan, net, args.hard_curves, args.hard_per_curve,
+                                   seed=2000 + rnd, periods=periods)
+        # as many fresh positives as hard negatives keeps the classes balanced
+        zp, yp, _ = make_training_set(plan, hard.shape[0], 0, seed=3000 + rnd, periods=periods,
+                                      snr_cut=args.snr_cut)
+        z = torch.cat([z, hard, zp])
+        y = torch.cat([y, torch.zeros(hard.shape[0], dtype=torch.float32, device=z.device), yp])
+        log(f"hard-negative round {rnd}: +{hard.shape[0]} negatives, +{zp.shape[0]} positives")
+        hist += train(net, z, y, args.hard_epochs, args.batch, args.lr * 0.5, seed=11 + rnd, log=log)
     torch.cuda.synchronize()
     train_s = time.time() - t1
     del z, y
@@ -234,7 +276,8 @@ def main():
     ev = evaluate(plan, net, args.eval, args.eval, seed=1013, periods=periods, log=None)
     eval_s = time.time() - t2
     res = summarize(ev)
-    res.update({"snr_cut": args.snr_cut, "train_curves": 2 * args.train, "eval_curves": 2 * args.eval, "epochs": args.epochs,
+    res.update({"snr_cut": args.snr_cut, "hard_rounds": args.hard_rounds,
+                "train_curves": 2 * args.train, "eval_curves": 2 * args.eval, "epochs": args.epochs,
                 "loss_per_epoch": hist, "train_seconds": train_s, "eval_seconds": eval_s,
                 "periods": args.periods, "folds_scored": 2 * args.eval * args.periods})
     print(json.dumps(res), flush=True)

@@ -324,3 +324,70 @@ def test_fold_f32_sums(torch_dev, plan, compensated):
     # each of ~254 float additions of |dev| <~ 2e-3 rounds by <= 2^-24 |partial sum|
     assert err.max() < 1e-8
     print(f"fp32 {'compensated' if compensated else 'plain'}: max |bin mean error| {err.max():.3e}")
+
+
+@pytest.mark.parametrize("n,k,nbins", [(4000, 1000, 64), (65000, 70, 256), (20000, 1300, 32),
+                                       (100, 64, 256), (16, 5, 16)])
+def test_sample_split_identical_for_every_split(torch_dev, n, k, nbins):
+    """The split fold + score merges integer histograms, so every split gives
+    bit-identical outputs (normalised folds included); checked against the
+    oracle once. Empty parts (split > records per wave) included."""
+    from paper_2312_02063_amd import Plan
+    torch = torch_dev
+    rng = np.random.default_rng(n + k)
+    t = np.sort(rng.uniform(0.0, 1470.0 * n / 65000 + 0.5, n))
+    f = (1.0 + rng.normal(0.0, 3e-4, n)).astype(np.float32)
+    periods = 1.0 / rng.uniform(1.0, 5.0, k)
+    p = Plan(0)
+    tt, ff, pp = _inputs(torch, t, f, periods)
+    p.prepare(tt, ff)
+    ref = None
+    for split in (1, 2, 4, 8, 16, 64):
+        p.set_split(split)
+        _say(f"split fold_score n={n} k={k} nbins={nbins} split={split}")
+        z = torch.empty((k, nbins), dtype=torch.uint16, device="cuda")
+        out = p.fold_score_prepared(pp, nbins, zfold=z)
+        torch.cuda.synchronize()
+        got = [x.cpu().numpy() for x in out] + [z.cpu().numpy()]
+        if ref is None:
+            ref = got
+            mean, sigma, _ = oracle.curve_stats(t, f)
+            _, dsums, counts = oracle.fold(t, f, periods, nbins, ref=mean, nthreads=8)
+            check_score(got[0], got[1], got[2], got[3], oracle.score(counts, dsums, sigma), counts,
+                        dsums, sigma, f"split-ref n={n}")
+        else:
+            for a, b in zip(got, ref):
+                assert np.array_equal(a, b), f"split {split} differs"
+    # twice in a row: the merge buffers are left clean
+    p.set_split(8)
+    out2 = p.fold_score_prepared(pp, nbins)
+    torch.cuda.synchronize()
+    assert np.array_equal(out2[0].cpu().numpy(), ref[0])
+    p.close()
+
+
+def test_autotune_and_cache(torch_dev, tmp_path):
+    from paper_2312_02063_amd import Plan
+    torch = torch_dev
+    c = synth.kepler_long_curve(seed=1002)
+    periods = synth.freq_grid(1.0, 5.0, 3000)
+    tt, ff, pp = _inputs(torch, c.t, c.flux, periods)
+    p = Plan(0)
+    p.prepare(tt, ff)
+    cache = str(tmp_path / "tune.txt")
+    _say("autotune k=3000")
+    sp, ms = p.autotune(pp, 256, cache)
+    assert sp >= 1 and ms > 0
+    line = open(cache).read().split()
+    assert int(line[1]) == c.t.size and int(line[2]) == 3000 and int(line[4]) == sp
+    sp2, ms2 = p.autotune(pp, 256, cache)
+    assert sp2 == sp and ms2 == -1.0
+    p.set_split(0)
+    out = p.fold_score_prepared(pp, 256)
+    p.set_split(1)
+    out1 = p.fold_score_prepared(pp, 256)
+    torch.cuda.synchronize()
+    for a, b in zip(out, out1):
+        assert torch.equal(a, b)
+    print(f"autotuned split {sp}: {ms:.3f} ms")
+    p.close()
