@@ -57,6 +57,8 @@ def _load():
     lib.oracle_means.restype = None
     lib.oracle_default_widths.argtypes = [i32, ip, i32]
     lib.oracle_default_widths.restype = i32
+    lib.oracle_fold_eqcount.argtypes = [dp, fp, i64, dp, i64, i32, i32, dp]
+    lib.oracle_fold_eqcount.restype = None
     lib.oracle_topk.argtypes = [fp, fp, ctypes.c_float, i64, i64, i32, fp,
                                 ctypes.POINTER(ctypes.c_int64)]
     lib.oracle_topk.restype = None
@@ -217,6 +219,22 @@ def fold_score(t, flux, periods, nbins, widths=None, nthreads=1):
 
 
 # ---------------------------------------------------------------- learned scorer (Sec. 2.5)
+
+def fold_eqcount(t, flux, periods, nbins=256, n_mid=4096):
+    """The two-tier equal-count fold of Sec. 2.3 (steps 1-5, Fig. 4): mean
+    flux of nbins final bins holding N / nbins points each, from n_mid
+    equal-width intermediate bins split in proportion at the boundaries.
+    Returns f64 [k, nbins]."""
+    t = _f64(t)
+    flux = _f32(flux)
+    periods = _f64(np.atleast_1d(periods))
+    k = periods.size
+    means = np.empty((k, nbins), np.float64)
+    _load().oracle_fold_eqcount(_p(t, ctypes.c_double), _p(flux, ctypes.c_float), t.size,
+                                _p(periods, ctypes.c_double), k, n_mid, nbins,
+                                _p(means, ctypes.c_double))
+    return means
+
 
 def topk(values, top, gate=None, gate_min=0.0):
     """Per-row best `top` entries of a periodogram (Sec. 2.1, Sec. 3.2): value

@@ -310,3 +310,60 @@ void oracle_topk(const float *values, const float *gate, float gate_min, int64_t
         }
     }
 }
+
+/*
+ * The paper's two-tier equal-count fold (Sec. 2.3, steps 1-5 and Fig. 4):
+ * per period, (1) the modular residual of each timestamp, (2) its bin among
+ * n_mid equal-width intermediate bins (4096 in the paper), (3) counts and
+ * flux sums per intermediate bin, (4) a left-to-right scan that merges the
+ * intermediate bins into nbins final bins holding the same number of points
+ * each, splitting a bin on a boundary in proportion (each split part carries
+ * the bin's mean flux times the points it takes), (5) the mean flux of each
+ * final bin.
+ *
+ * Reading: with N points each final bin holds N / nbins points, generally
+ * fractional; the scan counts in units of 1/nbins point (a sample is nbins
+ * units, a final bin N units), so the partition is exact integer arithmetic.
+ * means f64[k][nbins]; N = 0 or an invalid period gives NaN means.
+ */
+void oracle_fold_eqcount(const double *t, const float *flux, int64_t n, const double *periods,
+                         int64_t k, int32_t n_mid, int32_t nbins, double *means) {
+    int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)n_mid);
+    double *sum = (double *)malloc(sizeof(double) * (size_t)n_mid);
+    for (int64_t kk = 0; kk < k; ++kk) {
+        double *out = means + kk * nbins;
+        const double P = periods[kk];
+        if (n == 0 || !(P > 0.0) || !isfinite(P)) {
+            for (int32_t j = 0; j < nbins; ++j) out[j] = NAN;
+            continue;
+        }
+        for (int32_t b = 0; b < n_mid; ++b) { cnt[b] = 0; sum[b] = 0.0; }
+        for (int64_t i = 0; i < n; ++i) {
+            const int32_t b = oracle_bin(t[i], P, n_mid);
+            cnt[b] += 1;
+            sum[b] += (double)flux[i];
+        }
+        int32_t j = 0;
+        int64_t room = n;          /* units left in final bin j */
+        double acc = 0.0;
+        for (int32_t b = 0; b < n_mid && j < nbins; ++b) {
+            if (cnt[b] == 0) continue;
+            const double mean = sum[b] / (double)cnt[b];
+            int64_t left = cnt[b] * nbins;
+            while (left > 0 && j < nbins) {
+                const int64_t take = left < room ? left : room;
+                acc += mean * (double)take;
+                left -= take;
+                room -= take;
+                if (room == 0) {
+                    out[j] = acc / (double)n;
+                    ++j;
+                    acc = 0.0;
+                    room = n;
+                }
+            }
+        }
+    }
+    free(cnt);
+    free(sum);
+}
