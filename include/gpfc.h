@@ -175,6 +175,20 @@ int32_t gpfc_fold_f32_prepared(gpfc_plan *plan, const double *periods, int64_t k
                                void *stream);
 
 /*
+ * The paper's own two-tier fold (Sec. 2.3 steps 1-5, Fig. 4) of the
+ * prepared curve: each sample goes to one of 4096 equal-width intermediate
+ * phase bins (same bin definition as gpfc_fold at 4096 bins); the bins are
+ * then merged left to right into nbins final bins that hold N / nbins points
+ * each, a bin straddling a boundary split in proportion (each part carries
+ * its mean flux times the points it takes). Outputs (device, either may be
+ * NULL but not both): means f64[k][nbins] (NaN for an invalid period or an
+ * empty curve) and zfold u16[k][nbins], bfloat16 z-scores of the means (the
+ * network's input). 1 <= nbins <= 256, any integer.
+ */
+int32_t gpfc_fold_eqcount_prepared(gpfc_plan *plan, const double *periods, int64_t k,
+                                   int32_t nbins, double *means, uint16_t *zfold, void *stream);
+
+/*
  * Sample split of the fold + score of one curve: a grid of fewer 64-period
  * tiles than compute units leaves most of the chip idle, so each tile's
  * samples can be split over `split` blocks whose histograms are merged with

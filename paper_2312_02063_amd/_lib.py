@@ -86,6 +86,7 @@ def load():
         "gpfc_sync": ([vp], i32),
         "gpfc_topk": ([vp, i64, i64, vp, ctypes.c_float, i32, vp, vp, vp], i32),
         "gpfc_plan_set_split": ([vp, i32], i32),
+        "gpfc_fold_eqcount_prepared": ([vp, vp, i64, i32, vp, vp, vp], i32),
         "gpfc_autotune": ([vp, vp, i64, i32, ctypes.c_char_p, ctypes.POINTER(i32),
                            ctypes.POINTER(ctypes.c_float), vp], i32),
         "gpfc_survey_setup": ([vp, ctypes.POINTER(ctypes.c_int64), i32, i64, i64], i32),
@@ -124,7 +125,7 @@ def exported_symbols():
             "gpfc_cnn_create", "gpfc_cnn_destroy", "gpfc_cnn_set_params", "gpfc_cnn_get_params",
             "gpfc_cnn_forward", "gpfc_cnn_backward", "gpfc_cnn_adam", "gpfc_cnn_calibrate_fp8",
             "gpfc_cnn_forward_fp8", "gpfc_cnn_set_fused", "gpfc_topk", "gpfc_plan_set_split",
-            "gpfc_autotune", "gpfc_survey_setup", "gpfc_survey_run",
+            "gpfc_autotune", "gpfc_fold_eqcount_prepared", "gpfc_survey_setup", "gpfc_survey_run",
             "gpfc_survey_capture"]
 
 
@@ -343,6 +344,21 @@ class Plan:
         arr = (Curve * max(1, self.batch_n))()
         _check(self.lib.gpfc_batch_curve_stats(self.h, arr, _stream()), "gpfc_batch_curve_stats")
         return [arr[i].as_dict() for i in range(self.batch_n)]
+
+    def fold_eqcount_prepared(self, periods, nbins: int = 256, means: bool = True, zfold=None):
+        """The two-tier equal-count fold of the prepared curve: means f64 [k, nbins]
+        (None if means=False) and, if given, zfold u16 [k, nbins] filled."""
+        import torch
+        _need(periods, torch.float64, "periods", self.device)
+        k = periods.numel()
+        m = torch.empty((k, nbins), dtype=torch.float64, device=self.device) if means else None
+        if zfold is not None:
+            _need(zfold, torch.uint16, "zfold", self.device)
+            if zfold.numel() != k * nbins:
+                raise ValueError("zfold must hold k * nbins values")
+        _check(self.lib.gpfc_fold_eqcount_prepared(self.h, _ptr(periods), k, nbins, _ptr(m), _ptr(zfold),
+                                                   _stream()), "gpfc_fold_eqcount_prepared")
+        return m
 
     def set_split(self, split: int):
         """Sample split of the single-curve fold + score (0: automatic)."""

@@ -427,6 +427,20 @@ int32_t gpfc_fold(gpfc_plan* p, const double* t, const float* flux, int64_t n,
     return GPFC_OK;
 }
 
+int32_t gpfc_fold_eqcount_prepared(gpfc_plan* p, const double* periods, int64_t k, int32_t nbins,
+                                   double* means, uint16_t* zfold, void* stream) {
+    if (!p || p->n < 0 || k < 0 || (k > 0 && !periods)) return GPFC_EINVAL;
+    if (nbins < 1 || nbins > GPFC_MAX_NBINS) return GPFC_ENOTSUP;
+    if (k > 0 && !means && !zfold) return GPFC_EINVAL;
+    if ((k + 3) / 4 > 0x7fffffffLL) return GPFC_ERANGE;
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return device_error(e, "hipSetDevice");
+    e = gpfc::launch_fold_eqcount(p->rec, p->n, periods, k, nbins, p->info, means, zfold,
+                                  (hipStream_t)stream);
+    if (e != hipSuccess) return device_error(e, "k_fold_eqcount launch");
+    return GPFC_OK;
+}
+
 int32_t gpfc_plan_set_split(gpfc_plan* p, int32_t split) {
     if (!p || split < 0 || split > GPFC_MAX_SPLIT) return GPFC_EINVAL;
     p->split = split;

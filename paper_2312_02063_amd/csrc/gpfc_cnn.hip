@@ -656,6 +656,88 @@ __global__ __launch_bounds__(kFusedThreads, 1) void k_convstack_bf16(
     }
 }
 
+// Fully connected layer for bf16 inference: out[m][n] = ReLU(bias[n] +
+// sum_k A[m][k] W[n][k]) with A [M][K] activations and W [N][K] weights,
+// both row-major bf16. Block tile 128 x BN, 4 waves of 64 x BN/2; K advances
+// in steps of 64 through double-buffered LDS tiles (rows padded by 8
+// elements) filled from registers loaded one step ahead. Each output's MFMA
+// chain runs k in the same 32-steps as k_gemm, so results are bit-identical.
+constexpr int kFcBK = 64, kFcLd = kFcBK + 8;
+
+template <int BN>
+__global__ __launch_bounds__(256) void k_fc_bf16(int M, int K, const uint16_t* __restrict__ A,
+                                                 const uint16_t* __restrict__ W,
+                                                 const float* __restrict__ bias,
+                                                 uint16_t* __restrict__ out, int ldo) {
+    constexpr int BM = 128;
+    constexpr int WN = BN / 2;                 // columns per wave
+    constexpr int NJ = WN / 16;                // MFMA column blocks per wave
+    constexpr int ACH = BM * kFcBK / 8 / 256;  // 16-byte chunks of A per thread per step (4)
+    constexpr int BCH = BN * kFcBK / 8 / 256;  // ... of W (4 or 2)
+    __shared__ __attribute__((aligned(16))) uint16_t sa[2][BM * kFcLd];
+    __shared__ __attribute__((aligned(16))) uint16_t sb[2][BN * kFcLd];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, q = lane >> 4;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    uint4 ra[ACH], rb[BCH];
+    auto load = [&](int k0) {
+        for (int c = 0; c < ACH; ++c) {
+            const int idx = tid + c * 256, row = idx >> 3, col = (idx & 7) * 8;
+            ra[c] = (m0 + row < M) ? *reinterpret_cast<const uint4*>(A + (int64_t)(m0 + row) * K + k0 + col)
+                                   : make_uint4(0u, 0u, 0u, 0u);
+        }
+        for (int c = 0; c < BCH; ++c) {
+            const int idx = tid + c * 256, row = idx >> 3, col = (idx & 7) * 8;
+            rb[c] = *reinterpret_cast<const uint4*>(W + (int64_t)(n0 + row) * K + k0 + col);
+        }
+    };
+    auto store = [&](int buf) {
+        for (int c = 0; c < ACH; ++c) {
+            const int idx = tid + c * 256, row = idx >> 3, col = (idx & 7) * 8;
+            *reinterpret_cast<uint4*>(&sa[buf][row * kFcLd + col]) = ra[c];
+        }
+        for (int c = 0; c < BCH; ++c) {
+            const int idx = tid + c * 256, row = idx >> 3, col = (idx & 7) * 8;
+            *reinterpret_cast<uint4*>(&sb[buf][row * kFcLd + col]) = rb[c];
+        }
+    };
+    f32x4 acc[4][NJ];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < NJ; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    load(0);
+    store(0);
+    __syncthreads();
+    const int steps = K / kFcBK;
+    for (int st = 0; st < steps; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < steps) load((st + 1) * kFcBK);
+#pragma unroll
+        for (int kk = 0; kk < kFcBK; kk += 32) {
+            bf16x8 a[4], b[NJ];
+            for (int i = 0; i < 4; ++i)
+                a[i] = *reinterpret_cast<const bf16x8*>(&sa[buf][(wm * 64 + i * 16 + r) * kFcLd + kk + q * 8]);
+            for (int j = 0; j < NJ; ++j)
+                b[j] = *reinterpret_cast<const bf16x8*>(&sb[buf][(wn * WN + j * 16 + r) * kFcLd + kk + q * 8]);
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < NJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        if (st + 1 < steps) {
+            store(buf ^ 1);   // the other buffer was last read in step st - 1
+            __syncthreads();
+        }
+    }
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < NJ; ++j) {
+            const int n = n0 + wn * WN + j * 16 + r;
+            const float bn = bias[n];
+            const int mb = m0 + wm * 64 + i * 16 + q * 4;
+            for (int e = 0; e < 4; ++e)
+                if (mb + e < M) out[(int64_t)(mb + e) * ldo + n] = f2bf(fmaxf(acc[i][j][e] + bn, 0.0f));
+        }
+}
+
 // Output layer for inference: one thread per input, same summation order as
 // k_head.
 template <class P>
@@ -965,12 +1047,23 @@ int32_t forward(gpfc_cnn* c, const void* x, int xf32, int B, float* logits, cons
         if (e != hipSuccess) return cnn_err(e, "conv gemm");
     }
     }
+    if (fused) {
+        hipLaunchKernelGGL(k_fc_bf16<128>, dim3((unsigned)((B + 127) / 128), 2), dim3(256), 0, s, B,
+                           1024, (const uint16_t*)c->a4, (const uint16_t*)c->f1f, w + F1B,
+                           (uint16_t*)c->h1, 256);
+        hipLaunchKernelGGL(k_fc_bf16<64>, dim3((unsigned)((B + 127) / 128), 1), dim3(256), 0, s, B, 256,
+                           (const uint16_t*)c->h1, (const uint16_t*)c->f2f, w + F2B, (uint16_t*)c->h2,
+                           64);
+        e = hipGetLastError();
+        if (e != hipSuccess) return cnn_err(e, "fc gemm");
+    } else {
     e = gemm<P>(B, 256, 1024, Rows<P>{(const T*)c->a4, B, 1024, 1024},
                 Rows<P>{(const T*)c->f1f, 256, 1024, 1024}, EpFcFwd<P>{w + F1B, (T*)c->h1, 256}, s);
     if (e != hipSuccess) return cnn_err(e, "fc1 gemm");
     e = gemm<P>(B, 64, 256, Rows<P>{(const T*)c->h1, B, 256, 256},
                 Rows<P>{(const T*)c->f2f, 64, 256, 256}, EpFcFwd<P>{w + F2B, (T*)c->h2, 64}, s);
     if (e != hipSuccess) return cnn_err(e, "fc2 gemm");
+    }
     if (train)
         hipLaunchKernelGGL((k_head<P>), dim3(1), dim3(256), 0, s, (const T*)c->h2, B, w + F3W,
                            w + F3B, labels, logits, c->loss, c->grad, (T*)c->d_a);

@@ -85,6 +85,10 @@ hipError_t launch_fold_score_split(const Rec* rec, int64_t n, const double* peri
                                    int32_t split, unsigned long long* gh, int32_t* arrivals,
                                    float* snr, int32_t* start, int32_t* width, float* depth,
                                    uint16_t* zfold, hipStream_t s);
+// The two-tier equal-count fold: means f64[k][nbins] and/or bf16 z-scores.
+hipError_t launch_fold_eqcount(const Rec* rec, int64_t n, const double* periods, int64_t k,
+                               int32_t nbins, const CurveInfo* info, double* means,
+                               uint16_t* zfold, hipStream_t s);
 hipError_t launch_batch_prepare(const double* t, const float* flux, const int64_t* soff,
                                 const int64_t* roff, int32_t n_curves, int64_t max_records,
                                 CurveInfo* infos, Rec* rec, hipStream_t s);

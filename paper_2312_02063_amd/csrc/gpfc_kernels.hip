@@ -923,6 +923,160 @@ __global__ __launch_bounds__(256) void k_fold_naive(const double* __restrict__ t
 
 }  // namespace
 
+// ------------------------------------------------------------------ equal-count fold
+//
+// The paper's two-tier fold (Sec. 2.3 steps 1-5, Fig. 4): 4096 equal-width
+// intermediate bins, then final bins holding N / nbins points each, a bin on
+// a boundary split in proportion. One block of 16 waves folds 4 periods: 4
+// waves per period, lanes take consecutive records (coalesced 16-byte loads),
+// each update one 64-bit integer LDS atomic into the period's 4096-bin packed
+// histogram (count and fixed-point flux sum, exact). The bin comes from the
+// certified fast path at 4096 bins (fraction field 16 bits below the bin);
+// a lane whose fraction it cannot certify takes the IEEE sequence instead.
+// Then one wave per period scans the histogram: in units of 1/nbins point
+// (a sample is nbins units, a final bin N units) every boundary j*N falls in
+// one intermediate bin, whose lane records the cumulative deviation sum there
+// as an exact integer part (the bins before it) plus the interpolated share of
+// that bin; a final bin's sum is the difference of its two boundaries.
+constexpr int kMid = 4096;
+constexpr int kEqPeriods = 4;
+constexpr int kEqMaxBins = 256;
+
+struct EqBoundary {
+    int64_t ipart;    // cumulative fixed-point deviation of the bins before
+    double frac;      // share of the boundary's own bin, in the same units
+};
+
+__device__ __forceinline__ uint32_t mid_bin_ieee(double t, double P) {
+    const double x = t / P;
+    const double f = x - floor(x);
+    const double fb = floor(f * (double)kMid);
+    if (!(fb >= 0.0)) return 0u;
+    if (fb >= (double)kMid) return kMid - 1;
+    return (uint32_t)fb;
+}
+
+__global__ __launch_bounds__(kThreads, 1) void k_fold_eqcount(
+    const Rec* __restrict__ rec, int64_t nrec, const double* __restrict__ periods, int64_t k,
+    int32_t nbins, const CurveInfo* __restrict__ info, double* __restrict__ means,
+    uint16_t* __restrict__ zfold) {
+    __shared__ __attribute__((aligned(16))) uint64_t hist[kEqPeriods * kMid];
+    __shared__ EqBoundary bnd[kEqPeriods][kEqMaxBins + 1];
+    __shared__ int64_t eqn[kEqPeriods];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int pw = wave & (kEqPeriods - 1);           // the wave's period within the block
+    const int quarter = wave >> 2;                    // its share of the records
+    for (int i = threadIdx.x; i < kEqPeriods * kMid; i += kThreads) hist[i] = 0;
+    const int64_t kk = (int64_t)blockIdx.x * kEqPeriods + pw;
+    double P = kk < k ? periods[kk] : 1.0;
+    const bool valid = kk < k && P > 0.0 && isfinite(P);
+    if (!valid) P = 1.0;
+    const double rB = (1.0 / P) * (double)kMid;
+    const double zmax = info->tmax * rB;
+    const uint32_t lim = zmax < 0x1p34 ? 65536u - 2u : 0u;
+    const double theta = -0x1p-17 - 0x1p-16;
+    __syncthreads();
+    uint64_t* h = hist + pw * kMid;
+    const int64_t per_q = (nrec + 3) / 4;
+    const int64_t i0 = quarter * per_q, i1 = min(nrec, i0 + per_q);
+    if (valid) {
+        for (int64_t i = i0 + lane; i < i1; i += 64) {
+            const Rec r = rec[i];
+            const double w = __builtin_fma(r.t, rB, theta);
+            const uint32_t lo = (uint32_t)__double_as_longlong(w + 0x1.8p36);
+            uint32_t b = (lo >> 16) & (kMid - 1);
+            if ((lo & 0xFFFFu) >= lim) b = mid_bin_ieee(r.t, P);
+            __hip_atomic_fetch_add(h + b, r.c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+    __syncthreads();
+    if (wave < kEqPeriods) {
+        const int p2 = wave;
+        const int64_t k2 = (int64_t)blockIdx.x * kEqPeriods + p2;
+        const double P2 = k2 < k ? periods[k2] : 1.0;
+        const bool v2 = k2 < k && P2 > 0.0 && isfinite(P2);
+        const uint64_t* hh = hist + p2 * kMid;
+        // lane owns bins [64 lane, 64 lane + 64): its totals, then wave prefixes
+        int64_t lc = 0, ls = 0;
+        for (int b = lane * 64; b < lane * 64 + 64; ++b) {
+            const uint64_t v = hh[b];
+            const int64_t c = (int64_t)(v >> kCountShift);
+            lc += c;
+            ls += (int64_t)(v & kSumMask) - c * kBias;
+        }
+        int64_t pc = lc, ps = ls;            // inclusive prefix over lanes
+        for (int d = 1; d < 64; d <<= 1) {
+            const int64_t oc = __shfl_up(pc, d), os = __shfl_up(ps, d);
+            if (lane >= d) { pc += oc; ps += os; }
+        }
+        const int64_t N = __shfl(pc, 63);
+        const int64_t Stot = __shfl(ps, 63);
+        int64_t C = pc - lc, S = ps - ls;    // exclusive: before the lane's first bin
+        if (v2 && N > 0) {
+            for (int b = lane * 64; b < lane * 64 + 64; ++b) {
+                const uint64_t v = hh[b];
+                const int64_t c = (int64_t)(v >> kCountShift);
+                if (c == 0) continue;
+                const int64_t d = (int64_t)(v & kSumMask) - c * kBias;
+                const int64_t u0 = C * nbins, u1 = (C + c) * nbins;   // the bin's units
+                // interior boundaries j N (0 < j < nbins) inside [u0, u1)
+                for (int64_t j = (u0 + N - 1) / N; j * N < u1; ++j) {
+                    if (j == 0) continue;
+                    bnd[p2][j].ipart = S;
+                    bnd[p2][j].frac = (double)(j * N - u0) / (double)(c * nbins) * (double)d;
+                }
+                C += c;
+                S += d;
+            }
+            if (lane == 0) {
+                bnd[p2][0] = EqBoundary{0, 0.0};
+                bnd[p2][nbins] = EqBoundary{Stot, 0.0};
+            }
+        }
+        if (lane == 0) eqn[p2] = (v2 && k2 < k) ? N : -1;
+    }
+    __syncthreads();
+    if (wave < kEqPeriods) {
+        const int p2 = wave;
+        const int64_t k2 = (int64_t)blockIdx.x * kEqPeriods + p2;
+        const int64_t N = eqn[p2];           // -1: invalid period
+        if (k2 < k) {
+            const double qs = info->qscale, ref = info->ref;
+            const bool any = N > 0;
+            float zs = 0.0f, zq = 0.0f;
+            float mloc[kEqMaxBins / 64];
+            int nl = 0;
+            for (int j = lane; j < nbins; j += 64, ++nl) {
+                double m = __builtin_nan("");
+                mloc[nl] = 0.0f;
+                if (any) {
+                    const EqBoundary a = bnd[p2][j], e = bnd[p2][j + 1];
+                    const double dsum = (double)(e.ipart - a.ipart) + (e.frac - a.frac);
+                    const double dm = qs * dsum * (double)nbins / (double)N;
+                    m = ref + dm;
+                    mloc[nl] = (float)dm;
+                    zs += mloc[nl];
+                    zq += mloc[nl] * mloc[nl];
+                }
+                if (means) means[k2 * nbins + j] = m;
+            }
+            if (zfold) {
+                for (int d = 32; d > 0; d >>= 1) {
+                    zs += __shfl_xor(zs, d);
+                    zq += __shfl_xor(zq, d);
+                }
+                const float mu = any ? zs / (float)nbins : 0.0f;
+                const float var = any ? fmaxf(zq / (float)nbins - mu * mu, 0.0f) : 0.0f;
+                const float inv = var > 0.0f ? 1.0f / sqrtf(var) : 0.0f;
+                nl = 0;
+                for (int j = lane; j < nbins; j += 64, ++nl)
+                    zfold[k2 * nbins + j] = bf16_rne(any ? (mloc[nl] - mu) * inv : 0.0f);
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 
 hipError_t launch_curve_stats(const double* t, const float* flux, int64_t n, CurveInfo* info,
@@ -992,6 +1146,16 @@ hipError_t launch_fold_score_split(const Rec* rec, int64_t n, const double* peri
     hipLaunchKernelGGL(k_fold_score_split, dim3((unsigned)tiles, (unsigned)split), dim3(kThreads), 0, s,
                        rec, per, per_s, periods, k, 8 - log2_of(nbins), info, widths, snr, start, width,
                        depth, zfold, gh, arrivals);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_eqcount(const Rec* rec, int64_t n, const double* periods, int64_t k,
+                               int32_t nbins, const CurveInfo* info, double* means,
+                               uint16_t* zfold, hipStream_t s) {
+    if (k == 0) return hipSuccess;
+    const int64_t blocks = (k + kEqPeriods - 1) / kEqPeriods;
+    hipLaunchKernelGGL(k_fold_eqcount, dim3((unsigned)blocks), dim3(kThreads), 0, s, rec,
+                       fold_slice_len(n) * kWaves, periods, k, nbins, info, means, zfold);
     return hipGetLastError();
 }
 

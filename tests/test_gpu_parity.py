@@ -391,3 +391,40 @@ def test_autotune_and_cache(torch_dev, tmp_path):
         assert torch.equal(a, b)
     print(f"autotuned split {sp}: {ms:.3f} ms")
     p.close()
+
+
+@pytest.mark.parametrize("n,k,nbins", [(4000, 300, 256), (65000, 97, 256), (1000, 130, 64),
+                                       (250, 9, 100), (3, 5, 256), (0, 4, 32)])
+def test_equal_count_fold_matches_oracle(torch_dev, n, k, nbins):
+    """The paper's two-tier fold (4096 -> nbins equal-count bins) against the
+    oracle: means within 1e-5 relative of the fold's deviation scale (the
+    sums are exact integers; the split shares are FP64), invalid periods NaN,
+    and the bf16 z-scores."""
+    from paper_2312_02063_amd import Plan
+    torch = torch_dev
+    rng = np.random.default_rng(7 * n + k)
+    t = np.sort(rng.uniform(0.0, 1470.0 * max(n, 1) / 65000 + 0.3, n))
+    f = (1.0 + rng.normal(0.0, 5e-4, n)).astype(np.float32)
+    periods = 1.0 / rng.uniform(1.0, 5.0, k)
+    periods[1] = -1.0
+    p = Plan(0)
+    tt, ff, pp = _inputs(torch, t, f, periods)
+    _say(f"equal-count fold n={n} k={k} nbins={nbins}")
+    p.prepare(tt, ff)
+    z = torch.empty((k, nbins), dtype=torch.uint16, device="cuda")
+    m = p.fold_eqcount_prepared(pp, nbins, zfold=z).cpu().numpy()
+    torch.cuda.synchronize()
+    mo = oracle.fold_eqcount(t, f, periods, nbins)
+    assert np.array_equal(np.isnan(m), np.isnan(mo))
+    ok = ~np.isnan(mo)
+    if ok.any():
+        scale = max(float(np.abs(f.astype(np.float64) - f.mean()).max()), 1e-30)
+        err = np.abs(m[ok] - mo[ok]).max()
+        assert err <= 1e-5 * scale + 1e-12, err
+        zo = mo - mo.mean(axis=1, keepdims=True)
+        sd = zo.std(axis=1, keepdims=True)
+        zo = np.where(sd > 0, zo / np.where(sd > 0, sd, 1), 0.0)
+        zg = (z.cpu().numpy().astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+        rows = ~np.isnan(mo).any(axis=1)
+        assert np.abs(zg[rows] - zo[rows]).max() <= 2e-2 + 2 ** -8 * np.abs(zo[rows]).max()
+    p.close()
