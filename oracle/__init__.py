@@ -59,6 +59,9 @@ def _load():
     lib.oracle_default_widths.restype = i32
     lib.oracle_fold_eqcount.argtypes = [dp, fp, i64, dp, i64, i32, i32, dp]
     lib.oracle_fold_eqcount.restype = None
+    lib.oracle_periodogram.argtypes = [fp, dp, i64, i64, ctypes.c_float, i32, i32, fp, fp, fp, ip, fp,
+                                       ctypes.POINTER(ctypes.c_int64), ip, ip]
+    lib.oracle_periodogram.restype = None
     lib.oracle_topk.argtypes = [fp, fp, ctypes.c_float, i64, i64, i32, fp,
                                 ctypes.POINTER(ctypes.c_int64)]
     lib.oracle_topk.restype = None
@@ -234,6 +237,28 @@ def fold_eqcount(t, flux, periods, nbins=256, n_mid=4096):
                                 _p(periods, ctypes.c_double), k, n_mid, nbins,
                                 _p(means, ctypes.c_double))
     return means
+
+
+def periodogram(values, periods=None, nsigma=3.0, min_width=3, max_peaks=8):
+    """SDE (Eq. 3), peaks above mean + nsigma sd wider than min_width points
+    (Sec. 4.2) and harmonic codes of the best max_peaks peaks, per row of
+    values f32 [rows, len]. Returns a dict of arrays."""
+    v = np.ascontiguousarray(values, dtype=np.float32)
+    if v.ndim == 1:
+        v = v[None, :]
+    rows, n = v.shape
+    per = None if periods is None else _f64(periods)
+    out = {"sde": np.empty(rows, np.float32), "mean": np.empty(rows, np.float32),
+           "sd": np.empty(rows, np.float32), "n_peaks": np.empty(rows, np.int32),
+           "val": np.empty((rows, max_peaks), np.float32), "idx": np.empty((rows, max_peaks), np.int64),
+           "width": np.empty((rows, max_peaks), np.int32), "harmonic": np.empty((rows, max_peaks), np.int32)}
+    _load().oracle_periodogram(_p(v, ctypes.c_float), None if per is None else _p(per, ctypes.c_double),
+                               rows, n, ctypes.c_float(nsigma), min_width, max_peaks,
+                               _p(out["sde"], ctypes.c_float), _p(out["mean"], ctypes.c_float),
+                               _p(out["sd"], ctypes.c_float), _p(out["n_peaks"], ctypes.c_int32),
+                               _p(out["val"], ctypes.c_float), _p(out["idx"], ctypes.c_int64),
+                               _p(out["width"], ctypes.c_int32), _p(out["harmonic"], ctypes.c_int32))
+    return out
 
 
 def topk(values, top, gate=None, gate_min=0.0):

@@ -367,3 +367,79 @@ void oracle_fold_eqcount(const double *t, const float *flux, int64_t n, const do
     free(cnt);
     free(sum);
 }
+
+/*
+ * Periodogram post-processing, per row of `len` scores (one curve's
+ * periodogram over its trial periods):
+ *  - SDE (Eq. 3): (max - mean) / sd over the non-NaN scores, sd with ddof 0
+ *    (0 when sd = 0 or no score);
+ *  - peaks (Sec. 4.2: the best peak among those higher than 3 sigma and wider
+ *    than 3 points): maximal runs of consecutive scores > mean + nsigma * sd
+ *    (a NaN ends a run) longer than min_width points; a peak's value is the
+ *    run's maximum, its index the first position of that maximum, its width
+ *    the run length; peaks ordered by value descending, then index ascending;
+ *  - harmonics: with periods given, code h (2, 3) for a peak at h times the
+ *    best peak's period and -h at 1/h of it, within a relative 1e-3; 1 for the
+ *    best peak itself; 0 otherwise.
+ * Outputs per row: sde, mean, sd, n_peaks (all qualifying runs) and the first
+ * max_peaks peaks (value -inf, index -1, width 0, code 0 where missing).
+ */
+void oracle_periodogram(const float *values, const double *periods, int64_t rows, int64_t len,
+                        float nsigma, int32_t min_width, int32_t max_peaks, float *sde,
+                        float *mean_out, float *sd_out, int32_t *n_peaks, float *pval,
+                        int64_t *pidx, int32_t *pwidth, int32_t *pharm) {
+    for (int64_t r = 0; r < rows; ++r) {
+        const float *v = values + r * len;
+        double s = 0.0, mx = -INFINITY;
+        int64_t m = 0;
+        for (int64_t i = 0; i < len; ++i)
+            if (!isnan(v[i])) { s += v[i]; ++m; if (v[i] > mx) mx = v[i]; }
+        const double mean = m ? s / (double)m : 0.0;
+        double q = 0.0;
+        for (int64_t i = 0; i < len; ++i)
+            if (!isnan(v[i])) { const double d = v[i] - mean; q += d * d; }
+        const double sd = m ? sqrt(q / (double)m) : 0.0;
+        sde[r] = (float)((m && sd > 0.0) ? (mx - mean) / sd : 0.0);
+        mean_out[r] = (float)mean;
+        sd_out[r] = (float)sd;
+        const double thr = mean + (double)nsigma * sd;
+        float *ov = pval + r * max_peaks;
+        int64_t *oi = pidx + r * max_peaks;
+        int32_t *ow = pwidth + r * max_peaks;
+        int32_t *oh = pharm + r * max_peaks;
+        for (int32_t j = 0; j < max_peaks; ++j) { ov[j] = -INFINITY; oi[j] = -1; ow[j] = 0; oh[j] = 0; }
+        int32_t np = 0;
+        int64_t i = 0;
+        while (i < len) {
+            if (isnan(v[i]) || !(v[i] > thr)) { ++i; continue; }
+            int64_t j = i, best = i;
+            while (j < len && !isnan(v[j]) && v[j] > thr) { if (v[j] > v[best]) best = j; ++j; }
+            const int64_t w = j - i;
+            if (w > min_width) {
+                ++np;
+                /* insert (v[best], best, w) into the sorted list */
+                int32_t pos = max_peaks;
+                for (int32_t a = 0; a < max_peaks; ++a)
+                    if (v[best] > ov[a] || (v[best] == ov[a] && (oi[a] < 0 || best < oi[a]))) { pos = a; break; }
+                if (pos < max_peaks) {
+                    for (int32_t a = max_peaks - 1; a > pos; --a) { ov[a] = ov[a - 1]; oi[a] = oi[a - 1]; ow[a] = ow[a - 1]; }
+                    ov[pos] = v[best]; oi[pos] = best; ow[pos] = (int32_t)w;
+                }
+            }
+            i = j;
+        }
+        n_peaks[r] = np;
+        if (periods && max_peaks > 0 && oi[0] >= 0) {
+            const double p0 = periods[oi[0]];
+            oh[0] = 1;
+            for (int32_t a = 1; a < max_peaks; ++a) {
+                if (oi[a] < 0) break;
+                const double ratio = periods[oi[a]] / p0;
+                for (int h = 2; h <= 3; ++h) {
+                    if (fabs(ratio - h) <= 1e-3 * h) oh[a] = h;
+                    if (fabs(1.0 / ratio - h) <= 1e-3 * h) oh[a] = -h;
+                }
+            }
+        }
+    }
+}
