@@ -103,7 +103,7 @@ def measure_rows(plan, t, f, pp, periods, survey_stars):
     many-star survey), with the roofline that bounds it."""
     import numpy as np
     import torch
-    from paper_2312_02063_amd import CNN_BF16, Cnn, synth, topk
+    from paper_2312_02063_amd import CNN_BF16, Cnn, periodogram_peaks, synth, topk
     dev = t.device
     rows = {}
     plan.prepare(t, f)
@@ -156,6 +156,22 @@ def measure_rows(plan, t, f, pp, periods, survey_stars):
     ms = _events_ms(lambda: topk(snr, 16), 10)
     rows["a8_topk"] = {"ms": ms, "scores": int(snr.numel()), "top": 16,
                       "GBs": snr.numel() * 4 / ms / 1e6, "bound": "hbm", "peak_GBs": HBM_PEAK_GBS}
+    # next: periodogram post-processing (SDE, peaks, harmonics) of the same periodogram
+    ms = _events_ms(lambda: periodogram_peaks(snr, pp), 5)
+    pk = periodogram_peaks(snr, pp)
+    rows["next_periodogram_peaks"] = {"ms": ms, "scores": int(snr.numel()),
+                                      "GBs": 3 * snr.numel() * 4 / ms / 1e6, "bound": "hbm (3 passes)",
+                                      "sde": float(pk["sde"][0]), "n_peaks": int(pk["n_peaks"][0]),
+                                      "best_peak_period_d": float(periods[int(pk["idx"][0, 0])])}
+    # next: the paper's two-tier equal-count fold (4096 -> 256 equal-count bins)
+    ke = 200_000
+    pe = pp[:ke].contiguous()
+    me = torch.empty((ke, NBINS), dtype=torch.uint16, device=dev)
+    ms = _events_ms(lambda: plan.fold_eqcount_prepared(pe, NBINS, means=False, zfold=me), 3)
+    rows["next_equal_count_fold"] = {"periods_per_s": ke / ms * 1e3, "ms": ms, "periods": ke,
+                                     "updates_per_s": float(N_SAMPLES) * ke / ms * 1e3,
+                                     "bound": "lds (random-bank 64-bit atomics)"}
+    del me
     # a10: many-star survey (fold + box-SNR + bf16 network + per-curve best-K)
     if survey_stars > 0:
         stars = synth.multi_star(seed=1005, n_stars=survey_stars,

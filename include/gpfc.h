@@ -350,6 +350,28 @@ int32_t gpfc_cnn_adam(gpfc_cnn *cnn, float lr, float beta1, float beta2, float e
 int32_t gpfc_topk(const float *values, int64_t rows, int64_t len, const float *gate,
                   float gate_min, int32_t top, float *out_val, int64_t *out_idx, void *stream);
 
+/*
+ * Periodogram post-processing, per row of `len` scores (a curve's box-SNR or
+ * network periodogram over its trial periods): SDE (Eq. 3) = (max - mean) /
+ * sd over the non-NaN scores (sd with ddof 0; 0 when sd = 0); peaks (Sec. 4.2:
+ * the best peak among those higher than 3 sigma and wider than 3 points) =
+ * maximal runs of consecutive scores > mean + nsigma * sd (a NaN ends a run)
+ * longer than min_width, valued by their maximum (index: its first
+ * position), ordered by value descending then index ascending; n_peaks counts
+ * them all and the first max_peaks (1..GPFC_MAX_PEAKS) are returned (value
+ * -inf, index -1, width 0 where missing). With periods f64[len] (may be NULL)
+ * peak_harmonic holds 1 for the best peak, h (2, 3) for a peak at h times its
+ * period and -h at 1/h of it (within 1e-3 relative), else 0. Outputs: sde,
+ * mean, sd f32[rows]; n_peaks i32[rows]; peak_val f32, peak_idx i64,
+ * peak_width i32, peak_harmonic i32, each [rows][max_peaks]. Device pointers.
+ */
+#define GPFC_MAX_PEAKS 8
+int32_t gpfc_periodogram_peaks(const float *values, int64_t rows, int64_t len,
+                               const double *periods, float nsigma, int32_t min_width,
+                               int32_t max_peaks, float *sde, float *mean, float *sd,
+                               int32_t *n_peaks, float *peak_val, int64_t *peak_idx,
+                               int32_t *peak_width, int32_t *peak_harmonic, void *stream);
+
 /* ------------------------------------------------------------------------
  * Survey: many curves of uneven length, each folded and scored at the same
  * K trial periods, and each fold scored by the network (the paper searches

@@ -87,6 +87,8 @@ def load():
         "gpfc_topk": ([vp, i64, i64, vp, ctypes.c_float, i32, vp, vp, vp], i32),
         "gpfc_plan_set_split": ([vp, i32], i32),
         "gpfc_fold_eqcount_prepared": ([vp, vp, i64, i32, vp, vp, vp], i32),
+        "gpfc_periodogram_peaks": ([vp, i64, i64, vp, ctypes.c_float, i32, i32, vp, vp, vp, vp, vp, vp,
+                                    vp, vp, vp], i32),
         "gpfc_autotune": ([vp, vp, i64, i32, ctypes.c_char_p, ctypes.POINTER(i32),
                            ctypes.POINTER(ctypes.c_float), vp], i32),
         "gpfc_survey_setup": ([vp, ctypes.POINTER(ctypes.c_int64), i32, i64, i64], i32),
@@ -125,7 +127,7 @@ def exported_symbols():
             "gpfc_cnn_create", "gpfc_cnn_destroy", "gpfc_cnn_set_params", "gpfc_cnn_get_params",
             "gpfc_cnn_forward", "gpfc_cnn_backward", "gpfc_cnn_adam", "gpfc_cnn_calibrate_fp8",
             "gpfc_cnn_forward_fp8", "gpfc_cnn_set_fused", "gpfc_topk", "gpfc_plan_set_split",
-            "gpfc_autotune", "gpfc_fold_eqcount_prepared", "gpfc_survey_setup", "gpfc_survey_run",
+            "gpfc_autotune", "gpfc_fold_eqcount_prepared", "gpfc_periodogram_peaks", "gpfc_survey_setup", "gpfc_survey_run",
             "gpfc_survey_capture"]
 
 
@@ -475,6 +477,35 @@ def topk(values, top: int = 1, gate=None, gate_min: float = 0.0):
     _check(load().gpfc_topk(_ptr(v), rows, n, _ptr(gate), float(gate_min), int(top), _ptr(ov),
                             _ptr(oi), _stream()), "gpfc_topk")
     return ov, oi
+
+
+def periodogram_peaks(values, periods=None, nsigma: float = 3.0, min_width: int = 3,
+                      max_peaks: int = 8):
+    """SDE, mean, sd, peak count and the best max_peaks peaks (value, index,
+    width, harmonic code) of each row of values f32 [rows, len]."""
+    import torch
+    v = values if values.dim() == 2 else values.reshape(1, -1)
+    _need(v, torch.float32, "values", v.device)
+    if periods is not None:
+        _need(periods, torch.float64, "periods", v.device)
+        if periods.numel() != v.shape[1]:
+            raise ValueError("periods must hold one period per column")
+    rows = v.shape[0]
+    d = v.device
+    r = {"sde": torch.empty(rows, dtype=torch.float32, device=d),
+         "mean": torch.empty(rows, dtype=torch.float32, device=d),
+         "sd": torch.empty(rows, dtype=torch.float32, device=d),
+         "n_peaks": torch.empty(rows, dtype=torch.int32, device=d),
+         "val": torch.empty((rows, max_peaks), dtype=torch.float32, device=d),
+         "idx": torch.empty((rows, max_peaks), dtype=torch.int64, device=d),
+         "width": torch.empty((rows, max_peaks), dtype=torch.int32, device=d),
+         "harmonic": torch.empty((rows, max_peaks), dtype=torch.int32, device=d)}
+    _check(load().gpfc_periodogram_peaks(_ptr(v), rows, v.shape[1], _ptr(periods), float(nsigma),
+                                         int(min_width), int(max_peaks), _ptr(r["sde"]), _ptr(r["mean"]),
+                                         _ptr(r["sd"]), _ptr(r["n_peaks"]), _ptr(r["val"]), _ptr(r["idx"]),
+                                         _ptr(r["width"]), _ptr(r["harmonic"]), _stream()),
+           "gpfc_periodogram_peaks")
+    return r
 
 
 CNN_BF16, CNN_FP32 = 0, 1

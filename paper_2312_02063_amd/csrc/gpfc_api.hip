@@ -793,6 +793,25 @@ int32_t gpfc_survey_capture(gpfc_plan* p, gpfc_cnn* cnn, const double* t, const 
     });
 }
 
+int32_t gpfc_periodogram_peaks(const float* values, int64_t rows, int64_t len, const double* periods,
+                               float nsigma, int32_t min_width, int32_t max_peaks, float* sde,
+                               float* mean, float* sd, int32_t* n_peaks, float* peak_val,
+                               int64_t* peak_idx, int32_t* peak_width, int32_t* peak_harmonic,
+                               void* stream) {
+    if (rows < 0 || len < 0 || min_width < 0 || max_peaks < 1 || max_peaks > GPFC_MAX_PEAKS ||
+        !(nsigma >= 0.0f))
+        return GPFC_EINVAL;
+    if (rows > 0x7fffffffLL) return GPFC_ERANGE;
+    if (rows == 0) return GPFC_OK;
+    if ((len > 0 && !values) || !sde || !mean || !sd || !n_peaks || !peak_val || !peak_idx ||
+        !peak_width || !peak_harmonic)
+        return GPFC_EINVAL;
+    hipError_t e = gpfc::launch_periodogram(values, rows, len, periods, nsigma, min_width, max_peaks,
+                                            sde, mean, sd, n_peaks, peak_val, peak_idx, peak_width,
+                                            peak_harmonic, (hipStream_t)stream);
+    return e == hipSuccess ? GPFC_OK : device_error(e, "k_periodogram launch");
+}
+
 int32_t gpfc_topk(const float* values, int64_t rows, int64_t len, const float* gate,
                   float gate_min, int32_t top, float* out_val, int64_t* out_idx, void* stream) {
     if (rows < 0 || len < 0 || top < 1 || top > GPFC_MAX_TOP) return GPFC_EINVAL;

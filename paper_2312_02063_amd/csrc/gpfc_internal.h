@@ -107,6 +107,11 @@ hipError_t launch_score(const double* sums, const int32_t* counts, int64_t k, in
 // descending, index ascending; NaN and entries with gate < gate_min skipped).
 hipError_t launch_topk(const float* values, int64_t rows, int64_t len, const float* gate,
                        float gate_min, int32_t top, float* out_val, int64_t* out_idx, hipStream_t s);
+// SDE, mean, sd, peak count and the best max_peaks (<= 8) peaks of each row.
+hipError_t launch_periodogram(const float* values, int64_t rows, int64_t len, const double* periods,
+                              float nsigma, int32_t min_width, int32_t max_peaks, float* sde,
+                              float* mean, float* sd, int32_t* n_peaks, float* pval, int64_t* pidx,
+                              int32_t* pwidth, int32_t* pharm, hipStream_t s);
 hipError_t launch_fold_naive(const double* t, const float* flux, int64_t n,
                              const double* periods, int64_t k, int32_t nbins, double* sums,
                              int32_t* counts, hipStream_t s);

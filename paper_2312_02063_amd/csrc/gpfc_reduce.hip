@@ -108,7 +108,245 @@ __global__ __launch_bounds__(kTopThreads) void k_topk_rows(const float* __restri
     }
 }
 
+// ------------------------------------------------------------------ periodogram peaks
+//
+// One block of 16 waves per row: (1) count, sum and first maximum of the
+// non-NaN scores, (2) the sum of squared deviations (two passes, FP64), so
+// SDE = (max - mean) / sd; (3) runs above mean + nsigma sd: each thread scans
+// a contiguous chunk, keeps its best internal runs (not touching the chunk
+// ends) in a sorted list of kMaxPeaks and records the runs touching its ends;
+// thread 0 joins those boundary runs across chunks in order; the per-thread
+// lists are merged wave by wave and then with the joined runs. Peaks order by
+// value descending, then index ascending, as the oracle.
+
+constexpr int kMaxPeaks = 8;
+
+struct Run {
+    int64_t len;
+    float mx;
+    int64_t arg;
+};
+
+__device__ __forceinline__ Run join(Run a, Run b) {
+    if (a.len == 0) return b;
+    if (b.len == 0) return a;
+    Run r;
+    r.len = a.len + b.len;
+    const bool tb = b.mx > a.mx;     // a comes first: it keeps ties
+    r.mx = tb ? b.mx : a.mx;
+    r.arg = tb ? b.arg : a.arg;
+    return r;
+}
+
+struct PeakList {
+    float v[kMaxPeaks];
+    int64_t i[kMaxPeaks];
+    int32_t w[kMaxPeaks];
+    __device__ void init() {
+        for (int a = 0; a < kMaxPeaks; ++a) { v[a] = -INFINITY; i[a] = INT64_MAX; w[a] = 0; }
+    }
+    __device__ void insert(float pv, int64_t pi, int32_t pw) {
+        if (!beats(pv, pi, v[kMaxPeaks - 1], i[kMaxPeaks - 1])) return;
+        int pos = kMaxPeaks - 1;
+        while (pos > 0 && beats(pv, pi, v[pos - 1], i[pos - 1])) {
+            v[pos] = v[pos - 1];
+            i[pos] = i[pos - 1];
+            w[pos] = w[pos - 1];
+            --pos;
+        }
+        v[pos] = pv;
+        i[pos] = pi;
+        w[pos] = pw;
+    }
+};
+
+struct PeriodogramLds {
+    double dred[kTopThreads / 64];
+    int64_t cred[kTopThreads / 64];
+    float mred[kTopThreads / 64];
+    int64_t ared[kTopThreads / 64];
+    int32_t nred[kTopThreads / 64];
+    Run head[kTopThreads];
+    Run tail[kTopThreads];
+    uint8_t full[kTopThreads];
+    float wv[kTopThreads / 64][kMaxPeaks];
+    int64_t wi[kTopThreads / 64][kMaxPeaks];
+    int32_t ww[kTopThreads / 64][kMaxPeaks];
+    double mean, sd, thr;
+    float mx;
+    int64_t amx, m;
+};
+
+__global__ __launch_bounds__(kTopThreads) void k_periodogram(
+    const float* __restrict__ values, const double* __restrict__ periods, int64_t len, float nsigma,
+    int32_t min_width, int32_t max_peaks, float* __restrict__ sde, float* __restrict__ mean_out,
+    float* __restrict__ sd_out, int32_t* __restrict__ n_peaks, float* __restrict__ pval,
+    int64_t* __restrict__ pidx, int32_t* __restrict__ pwidth, int32_t* __restrict__ pharm) {
+    __shared__ PeriodogramLds sm;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t row = blockIdx.x;
+    const float* v = values + row * len;
+    const int64_t cs = (len + kTopThreads - 1) / kTopThreads;
+    const int64_t c0 = min(len, (int64_t)tid * cs), c1 = min(len, c0 + cs);
+    // (1) count, sum, first maximum (strided: coalesced; the maximum's order
+    // does not depend on the visiting order)
+    int64_t m = 0;
+    double s = 0.0;
+    float mx = -INFINITY;
+    int64_t amx = INT64_MAX;
+    for (int64_t i = tid; i < len; i += kTopThreads) {
+        const float x = v[i];
+        if (__builtin_isnan(x)) continue;
+        ++m;
+        s += x;
+        if (beats(x, i, mx, amx)) { mx = x; amx = i; }
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+        m += __shfl_xor(m, d);
+        s += __shfl_xor(s, d);
+        const float om = __shfl_xor(mx, d);
+        const int64_t oa = shfl_xor64(amx, d);
+        if (beats(om, oa, mx, amx)) { mx = om; amx = oa; }
+    }
+    if (lane == 0) { sm.cred[wave] = m; sm.dred[wave] = s; sm.mred[wave] = mx; sm.ared[wave] = amx; }
+    __syncthreads();
+    if (tid == 0) {
+        int64_t tm = 0;
+        double ts = 0.0;
+        float bm = -INFINITY;
+        int64_t ba = INT64_MAX;
+        for (int w = 0; w < kTopThreads / 64; ++w) {
+            tm += sm.cred[w];
+            ts += sm.dred[w];
+            if (beats(sm.mred[w], sm.ared[w], bm, ba)) { bm = sm.mred[w]; ba = sm.ared[w]; }
+        }
+        sm.m = tm;
+        sm.mean = tm ? ts / (double)tm : 0.0;
+        sm.mx = bm;
+        sm.amx = ba;
+    }
+    __syncthreads();
+    // (2) squared deviations
+    const double mean = sm.mean;
+    double q = 0.0;
+    for (int64_t i = tid; i < len; i += kTopThreads) {
+        const float x = v[i];
+        if (!__builtin_isnan(x)) { const double d = x - mean; q += d * d; }
+    }
+    for (int d = 32; d > 0; d >>= 1) q += __shfl_xor(q, d);
+    if (lane == 0) sm.dred[wave] = q;
+    __syncthreads();
+    if (tid == 0) {
+        double tq = 0.0;
+        for (int w = 0; w < kTopThreads / 64; ++w) tq += sm.dred[w];
+        sm.sd = sm.m ? sqrt(tq / (double)sm.m) : 0.0;
+        sm.thr = sm.mean + (double)nsigma * sm.sd;
+    }
+    __syncthreads();
+    // (3) runs
+    const double thr = sm.thr;
+    PeakList pl;
+    pl.init();
+    int32_t np = 0;
+    Run head{0, -INFINITY, INT64_MAX}, cur{0, -INFINITY, INT64_MAX};
+    bool in_head = true;     // still inside a run that starts at c0
+    for (int64_t i = c0; i < c1; ++i) {
+        const float x = v[i];
+        const bool above = !__builtin_isnan(x) && (double)x > thr;
+        if (above) {
+            cur = join(cur, Run{1, x, i});
+        } else {
+            if (in_head) head = cur;
+            else if (cur.len > min_width) { ++np; pl.insert(cur.mx, cur.arg, (int32_t)cur.len); }
+            cur = Run{0, -INFINITY, INT64_MAX};
+            in_head = false;
+        }
+    }
+    const bool full = in_head;     // every score of the chunk is above (an empty chunk too)
+    sm.full[tid] = full ? 1 : 0;
+    sm.head[tid] = full ? cur : head;
+    sm.tail[tid] = full ? Run{0, -INFINITY, INT64_MAX} : cur;
+    // merge the per-thread lists wave by wave: kMaxPeaks rounds of a wave argmax
+    int h = 0;
+    for (int rnd = 0; rnd < kMaxPeaks; ++rnd) {
+        float bv = h < kMaxPeaks ? pl.v[h] : -INFINITY;
+        int64_t bi = h < kMaxPeaks ? pl.i[h] : INT64_MAX;
+        int bl = lane;
+        for (int d = 32; d > 0; d >>= 1) {
+            const float ov = __shfl_xor(bv, d);
+            const int64_t oi = shfl_xor64(bi, d);
+            const int ol = __shfl_xor(bl, d);
+            if (beats(ov, oi, bv, bi) || (ov == bv && oi == bi && ol < bl)) { bv = ov; bi = oi; bl = ol; }
+        }
+        int32_t bw = 0;
+        for (int a = 0; a < kMaxPeaks; ++a)     // the winner's width (compile-time slots)
+            if (lane == bl && a == h) bw = pl.w[a];
+        bw = __shfl(bw, bl);
+        if (lane == 0) { sm.wv[wave][rnd] = bv; sm.wi[wave][rnd] = bi; sm.ww[wave][rnd] = bw; }
+        if (lane == bl) ++h;
+    }
+    for (int d = 32; d > 0; d >>= 1) np += __shfl_xor(np, d);
+    if (lane == 0) sm.nred[wave] = np;
+    __syncthreads();
+    if (tid != 0) return;
+    // thread 0: join boundary runs across chunks, then merge everything
+    PeakList fin;
+    fin.init();
+    int32_t total = 0;
+    for (int w = 0; w < kTopThreads / 64; ++w) {
+        total += sm.nred[w];
+        for (int a = 0; a < kMaxPeaks; ++a)
+            if (sm.wi[w][a] != INT64_MAX) fin.insert(sm.wv[w][a], sm.wi[w][a], sm.ww[w][a]);
+    }
+    Run open{0, -INFINITY, INT64_MAX};
+    for (int t = 0; t < kTopThreads; ++t) {
+        if (sm.full[t]) {
+            open = join(open, sm.head[t]);
+        } else {
+            const Run r = join(open, sm.head[t]);
+            if (r.len > min_width) { ++total; fin.insert(r.mx, r.arg, (int32_t)r.len); }
+            open = sm.tail[t];
+        }
+    }
+    if (open.len > min_width) { ++total; fin.insert(open.mx, open.arg, (int32_t)open.len); }
+    const int64_t m_all = sm.m;
+    const double sdv = sm.sd;
+    sde[row] = (float)((m_all && sdv > 0.0) ? ((double)sm.mx - sm.mean) / sdv : 0.0);
+    mean_out[row] = (float)sm.mean;
+    sd_out[row] = (float)sdv;
+    n_peaks[row] = total;
+    const double p0 = (periods && fin.i[0] != INT64_MAX) ? periods[fin.i[0]] : 0.0;
+    for (int a = 0; a < max_peaks; ++a) {
+        const bool has = fin.i[a] != INT64_MAX;
+        pval[row * max_peaks + a] = has ? fin.v[a] : -INFINITY;
+        pidx[row * max_peaks + a] = has ? fin.i[a] : -1;
+        pwidth[row * max_peaks + a] = has ? fin.w[a] : 0;
+        int32_t code = 0;
+        if (has && periods) {
+            if (a == 0) code = 1;
+            else {
+                const double ratio = periods[fin.i[a]] / p0;
+                for (int hh = 2; hh <= 3; ++hh) {
+                    if (fabs(ratio - hh) <= 1e-3 * hh) code = hh;
+                    if (fabs(1.0 / ratio - hh) <= 1e-3 * hh) code = -hh;
+                }
+            }
+        }
+        pharm[row * max_peaks + a] = code;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_periodogram(const float* values, int64_t rows, int64_t len, const double* periods,
+                              float nsigma, int32_t min_width, int32_t max_peaks, float* sde,
+                              float* mean, float* sd, int32_t* n_peaks, float* pval, int64_t* pidx,
+                              int32_t* pwidth, int32_t* pharm, hipStream_t s) {
+    if (rows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_periodogram, dim3((unsigned)rows), dim3(kTopThreads), 0, s, values, periods, len,
+                       nsigma, min_width, max_peaks, sde, mean, sd, n_peaks, pval, pidx, pwidth, pharm);
+    return hipGetLastError();
+}
 
 hipError_t launch_topk(const float* values, int64_t rows, int64_t len, const float* gate,
                        float gate_min, int32_t top, float* out_val, int64_t* out_idx, hipStream_t s) {

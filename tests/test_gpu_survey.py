@@ -190,3 +190,36 @@ def test_survey_fp8(torch_dev):
         lg = net.forward_fp8(z)
         torch.cuda.synchronize()
         assert np.array_equal(r["logits"][c], lg.cpu().numpy()), c
+
+
+@pytest.mark.parametrize("rows,n,nsig,mw", [(1, 0, 3.0, 3), (3, 40, 0.5, 0), (4, 5000, 1.0, 3),
+                                            (2, 100_003, 2.0, 2), (1, 2_000_000, 3.0, 3)])
+def test_periodogram_peaks_match_oracle(torch_dev, rows, n, nsig, mw):
+    """SDE, mean, sd, peak count and the best peaks against the oracle: values
+    and indices exact, statistics to FP32 rounding. Smooth rows make long runs
+    that cross the kernel's per-thread chunks."""
+    from paper_2312_02063_amd import periodogram_peaks
+    torch = torch_dev
+    rng = np.random.default_rng(rows * 31 + n)
+    x = rng.normal(size=(rows, n))
+    if n > 100:
+        # red noise: runs of hundreds of points above threshold
+        k = np.exp(-np.arange(200) / 40.0)
+        x = np.array([np.convolve(r, k, mode="same") for r in x])
+    x = x.astype(np.float32)
+    if n > 10:
+        x[0, n // 2] = np.nan
+    periods = 1.0 / np.linspace(1.0, 5.0, max(n, 1))[:n]
+    _say(f"periodogram rows={rows} n={n} nsigma={nsig} min_width={mw}")
+    r = periodogram_peaks(_dev(torch, x, torch.float32), _dev(torch, periods, torch.float64), nsig, mw, 6)
+    torch.cuda.synchronize()
+    o = oracle.periodogram(x, periods, nsig, mw, 6)
+    g = {k: v.cpu().numpy() for k, v in r.items()}
+    np.testing.assert_array_equal(g["n_peaks"], o["n_peaks"])
+    np.testing.assert_array_equal(g["idx"], o["idx"])
+    np.testing.assert_array_equal(g["val"], o["val"])
+    np.testing.assert_array_equal(g["width"], o["width"])
+    np.testing.assert_array_equal(g["harmonic"], o["harmonic"])
+    np.testing.assert_allclose(g["sde"], o["sde"], rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(g["mean"], o["mean"], rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(g["sd"], o["sd"], rtol=1e-5, atol=1e-6)
