@@ -98,12 +98,27 @@ def _events_ms(fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def cnn_inference_row(dev, reps, B=262_144):
+    """bf16 network inference on B normalised folds (random bf16 inputs)."""
+    import numpy as np
+    import torch
+    from paper_2312_02063_amd import CNN_BF16, Cnn, synth
+    net = Cnn(0, CNN_BF16, B)
+    net.set_params(synth.cnn_init(1003).astype(np.float32))
+    x = torch.randn(B, NBINS, device=dev).to(torch.bfloat16).view(torch.uint16)
+    lg = torch.empty(B, dtype=torch.float32, device=dev)
+    ms = _events_ms(lambda: net.forward(x, out=lg), reps)
+    tf = B * CNN_FWD_FLOP / ms / 1e9
+    return {"row": "a7_cnn_inference_bf16", "folds_per_s": B / ms * 1e3, "ms": ms, "batch": B,
+            "tflops": tf, "peak_tflops": MFMA_BF16_PEAK_TFLOPS, "frac": tf / MFMA_BF16_PEAK_TFLOPS}
+
+
 def measure_rows(plan, t, f, pp, periods, survey_stars):
     """Each step of the path on its own at the benchmark shapes (and the
     many-star survey), with the roofline that bounds it."""
     import numpy as np
     import torch
-    from paper_2312_02063_amd import CNN_BF16, Cnn, periodogram_peaks, synth, topk
+    from paper_2312_02063_amd import CNN_BF16, Cnn, Plan, periodogram_peaks, synth, topk
     dev = t.device
     rows = {}
     plan.prepare(t, f)
@@ -221,6 +236,8 @@ def main():
     ap.add_argument("--rows", type=int, default=1, help="also measure each step on its own (0: skip)")
     ap.add_argument("--survey-stars", type=int, default=512,
                     help="stars in the many-star survey measurement (0: skip)")
+    ap.add_argument("--cnn-only", action="store_true",
+                    help="only the bf16 network inference measurement (for counter runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -238,6 +255,9 @@ def main():
         print(json.dumps({"error": "no GPU visible"}), flush=True)
         sys.exit(1)
     dev = torch.device("cuda", 0)
+    if args.cnn_only:
+        print(json.dumps(cnn_inference_row(dev, max(1, args.steps))), flush=True)
+        return
     c = synth.kepler_long_curve(seed=1002)
     assert c.t.size == N_SAMPLES
     periods = synth.freq_grid(FMIN, FMAX, args.k)
