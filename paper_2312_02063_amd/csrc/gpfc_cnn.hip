@@ -738,6 +738,76 @@ __global__ __launch_bounds__(256) void k_fc_bf16(int M, int K, const uint16_t* _
         }
 }
 
+// The first fully connected layer for bf16 inference (N = 256 outputs): one
+// block of 8 waves computes 256 rows x all 256 columns, so every activation
+// row is read once; waves are 4 x 2, each 64 x 128 (4 x 8 MFMA blocks).
+// K advances in steps of 64 through two LDS stages (rows padded by 8)
+// filled from registers loaded one step ahead. Same MFMA chains and
+// epilogue as k_gemm with EpFcFwd: bit-identical output.
+__global__ __launch_bounds__(512, 1) void k_fc1_bf16(int M, int K, const uint16_t* __restrict__ A,
+                                                   const uint16_t* __restrict__ W,
+                                                   const float* __restrict__ bias,
+                                                   uint16_t* __restrict__ out) {
+    constexpr int BM = 256, BN = 256, NT = 512;
+    constexpr int CH = BM * kFcBK / 8 / NT;       // 16-byte chunks per thread per operand (4)
+    __shared__ __attribute__((aligned(16))) uint16_t sa[2][BM * kFcLd];
+    __shared__ __attribute__((aligned(16))) uint16_t sb[2][BN * kFcLd];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, q = lane >> 4;
+    const int wm = wave & 3, wn = wave >> 2;
+    const int m0 = blockIdx.x * BM;
+    uint4 ra[CH], rb[CH];
+    auto load = [&](int k0) {
+        for (int c = 0; c < CH; ++c) {
+            const int idx = tid + c * NT, row = idx >> 3, col = (idx & 7) * 8;
+            ra[c] = (m0 + row < M) ? *reinterpret_cast<const uint4*>(A + (int64_t)(m0 + row) * K + k0 + col)
+                                   : make_uint4(0u, 0u, 0u, 0u);
+            rb[c] = *reinterpret_cast<const uint4*>(W + (int64_t)row * K + k0 + col);
+        }
+    };
+    auto store = [&](int buf) {
+        for (int c = 0; c < CH; ++c) {
+            const int idx = tid + c * NT, row = idx >> 3, col = (idx & 7) * 8;
+            *reinterpret_cast<uint4*>(&sa[buf][row * kFcLd + col]) = ra[c];
+            *reinterpret_cast<uint4*>(&sb[buf][row * kFcLd + col]) = rb[c];
+        }
+    };
+    f32x4 acc[4][8];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    load(0);
+    store(0);
+    __syncthreads();
+    const int steps = K / kFcBK;
+    for (int st = 0; st < steps; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < steps) load((st + 1) * kFcBK);
+#pragma unroll
+        for (int kk = 0; kk < kFcBK; kk += 32) {
+            bf16x8 a[4], b[8];
+            for (int i = 0; i < 4; ++i)
+                a[i] = *reinterpret_cast<const bf16x8*>(&sa[buf][(wm * 64 + i * 16 + r) * kFcLd + kk + q * 8]);
+            for (int j = 0; j < 8; ++j)
+                b[j] = *reinterpret_cast<const bf16x8*>(&sb[buf][(wn * 128 + j * 16 + r) * kFcLd + kk + q * 8]);
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 8; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        if (st + 1 < steps) {
+            store(buf ^ 1);
+            __syncthreads();
+        }
+    }
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 8; ++j) {
+            const int n = wn * 128 + j * 16 + r;
+            const float bn = bias[n];
+            const int mb = m0 + wm * 64 + i * 16 + q * 4;
+            for (int e = 0; e < 4; ++e)
+                if (mb + e < M) out[(int64_t)(mb + e) * BN + n] = f2bf(fmaxf(acc[i][j][e] + bn, 0.0f));
+        }
+}
+
 // Output layer for inference: one thread per input, same summation order as
 // k_head.
 template <class P>
@@ -771,45 +841,84 @@ __global__ __launch_bounds__(256) void k_unpool(const typename P::T* __restrict_
 }
 
 // Bias gradient: g[o] = sum over rows of d[row][o] (rows x C, FP32 out).
+// Block (c-group, part): 256 threads = 256 / C' row lanes x C' channels
+// (C' = min(C, 64) consecutive channels, coalesced), rows split over
+// gridDim.y parts; each part writes its sums to part_out[part][c], summed in
+// part order by k_sum_parts (deterministic).
 template <class P>
 __global__ __launch_bounds__(256) void k_bias_grad(const typename P::T* __restrict__ d, int64_t rows,
-                                                   int C, float* __restrict__ g) {
+                                                   int C, float* __restrict__ part_out) {
     __shared__ float red[256];
-    const int c = blockIdx.x;
+    const int cg = C < 64 ? C : 64;                  // channels per block
+    const int lanes = 256 / cg;                      // row lanes per block
+    const int c = blockIdx.x * cg + threadIdx.x % cg;
+    const int rl = threadIdx.x / cg;
+    const int64_t per = (rows + gridDim.y - 1) / gridDim.y;
+    const int64_t r0 = (int64_t)blockIdx.y * per, r1 = min(rows, r0 + per);
     float s = 0.0f;
-    for (int64_t r = threadIdx.x; r < rows; r += 256) s += P::to_f(d[r * C + c]);
+    if (rl < lanes)
+        for (int64_t r = r0 + rl; r < r1; r += lanes) s += P::to_f(d[r * C + c]);
     red[threadIdx.x] = s;
     __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-        __syncthreads();
+    if (threadIdx.x < cg) {
+        float t = 0.0f;
+        for (int j = 0; j < lanes; ++j) t += red[j * cg + threadIdx.x];
+        part_out[(int64_t)blockIdx.y * C + c] = t;
     }
-    if (threadIdx.x == 0) g[c] = red[0];
+}
+
+// out[i] = sum_p parts[p][i] for p = 0 .. nparts-1 (in order).
+__global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ parts, int nparts, int n,
+                                                   float* __restrict__ out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float t = 0.0f;
+    for (int p = 0; p < nparts; ++p) t += parts[(int64_t)p * n + i];
+    out[i] = t;
 }
 
 // Conv block 1 weight gradient: dW[co][dx] = sum_{b,x} dpre[b][x][co] x[b][(x+dx-2) mod 256].
+// Thread = one position of one part of the batch, all 16 x 5 products at
+// once (the 16 channel gradients are 32 contiguous bytes); the block's 80
+// sums are reduced in LDS and written to part_out[part][co*5+dx], summed in
+// part order by k_sum_parts.
 template <class P>
 __global__ __launch_bounds__(256) void k_conv1_dw(const typename P::T* __restrict__ dpre,
                                                   const void* __restrict__ x, int xf32, int B,
-                                                  float* __restrict__ g) {
-    __shared__ float red[256];
-    const int co = blockIdx.x / 5, dx = blockIdx.x % 5;
-    float s = 0.0f;
-    for (int64_t e = threadIdx.x; e < (int64_t)B * 256; e += 256) {
+                                                  float* __restrict__ part_out) {
+    __shared__ float red[80][33];
+    const int64_t total = (int64_t)B * 256;
+    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+    const int64_t e0 = (int64_t)blockIdx.x * per, e1 = min(total, e0 + per);
+    float acc[80];
+    for (int j = 0; j < 80; ++j) acc[j] = 0.0f;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
         const int b = (int)(e >> 8), xx = (int)(e & 255);
-        const int pos = (xx + dx - 2) & 255;
-        const int64_t o = (int64_t)b * 256 + pos;
-        const float v = xf32 ? reinterpret_cast<const float*>(x)[o]
-                             : bf2f(reinterpret_cast<const uint16_t*>(x)[o]);
-        s += P::to_f(dpre[e * 16 + co]) * P::to_f(P::from_f(v));
+        float xv[5];
+        for (int dx = 0; dx < 5; ++dx) {
+            const int64_t o = (int64_t)b * 256 + ((xx + dx - 2) & 255);
+            const float v = xf32 ? reinterpret_cast<const float*>(x)[o]
+                                 : bf2f(reinterpret_cast<const uint16_t*>(x)[o]);
+            xv[dx] = P::to_f(P::from_f(v));
+        }
+        for (int co = 0; co < 16; ++co) {
+            const float dv = P::to_f(dpre[e * 16 + co]);
+            for (int dx = 0; dx < 5; ++dx) acc[co * 5 + dx] += dv * xv[dx];
+        }
     }
-    red[threadIdx.x] = s;
+    // wave sums, then the block's 4 waves... via LDS columns of 32 (8 threads per slot)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j = 0; j < 80; ++j) {
+        float v = acc[j];
+        for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d);
+        if (lane == 0) red[j][wave] = v;
+    }
     __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-        __syncthreads();
+    if (threadIdx.x < 80) {
+        float t = 0.0f;
+        for (int w = 0; w < 4; ++w) t += red[threadIdx.x][w];
+        part_out[(int64_t)blockIdx.x * 80 + threadIdx.x] = t;
     }
-    if (threadIdx.x == 0) g[co * 5 + dx] = red[0];
 }
 
 // Working copies of the weights from the FP32 masters.
@@ -919,6 +1028,19 @@ hipError_t gemm(int M, int N, int K, LA la, LB lb, EP ep, hipStream_t s) {
     dim3 grid((M + 63) / 64, (N + 63) / 64);
     const int kc = (K + P::KSTEP - 1) / P::KSTEP * P::KSTEP;
     hipLaunchKernelGGL((k_gemm<P, LA, LB, EP>), grid, dim3(256), 0, s, M, N, K, kc, la, lb, ep);
+    return hipGetLastError();
+}
+
+// Bias gradient over `rows` rows of C channels into g[C]: enough row parts to
+// fill the chip, partial sums in ws, summed in part order.
+template <class P>
+hipError_t bias_grad(const typename P::T* d, int64_t rows, int C, float* g, float* ws, hipStream_t s) {
+    const int cg = C < 64 ? C : 64;
+    const int groups = C / cg;
+    const int parts = (int)std::max<int64_t>(1, std::min<int64_t>(2048 / groups, rows / 256));
+    hipLaunchKernelGGL((k_bias_grad<P>), dim3((unsigned)groups, (unsigned)parts), dim3(256), 0, s, d, rows,
+                       C, ws);
+    hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(C)), dim3(256), 0, s, ws, parts, C, g);
     return hipGetLastError();
 }
 
@@ -1048,9 +1170,8 @@ int32_t forward(gpfc_cnn* c, const void* x, int xf32, int B, float* logits, cons
     }
     }
     if (fused) {
-        hipLaunchKernelGGL(k_fc_bf16<128>, dim3((unsigned)((B + 127) / 128), 2), dim3(256), 0, s, B,
-                           1024, (const uint16_t*)c->a4, (const uint16_t*)c->f1f, w + F1B,
-                           (uint16_t*)c->h1, 256);
+        hipLaunchKernelGGL(k_fc1_bf16, dim3((unsigned)((B + 255) / 256)), dim3(512), 0, s, B, 1024,
+                           (const uint16_t*)c->a4, (const uint16_t*)c->f1f, w + F1B, (uint16_t*)c->h1);
         hipLaunchKernelGGL(k_fc_bf16<64>, dim3((unsigned)((B + 127) / 128), 1), dim3(256), 0, s, B, 256,
                            (const uint16_t*)c->h1, (const uint16_t*)c->f2f, w + F2B, (uint16_t*)c->h2,
                            64);
@@ -1086,7 +1207,8 @@ int32_t backward(gpfc_cnn* c, const void* x, int xf32, int B, hipStream_t s) {
     e = gemm_splitk<P>(64, 256, B, Cols<P>{dh2, 64, 64, B}, Cols<P>{(const T*)c->h1, 256, 256, B},
                        EpFcDW{g + F2W, 256, false}, c->ws, s);
     if (e != hipSuccess) return cnn_err(e, "fc2 dW");
-    hipLaunchKernelGGL((k_bias_grad<P>), dim3(64), dim3(256), 0, s, dh2, (int64_t)B, 64, g + F2B);
+    e = bias_grad<P>(dh2, B, 64, g + F2B, c->ws, s);
+    if (e != hipSuccess) return cnn_err(e, "fc2 bias grad");
     T* dh1 = (T*)c->d_b;   // [B][256], masked by h1 > 0
     e = gemm<P>(B, 256, 64, Rows<P>{dh2, B, 64, 64}, Rows<P>{(const T*)c->f2b, 256, 64, 64},
                 EpStore<P>{dh1, (const T*)c->h1, 256}, s);
@@ -1094,7 +1216,8 @@ int32_t backward(gpfc_cnn* c, const void* x, int xf32, int B, hipStream_t s) {
     e = gemm_splitk<P>(256, 1024, B, Cols<P>{dh1, 256, 256, B},
                        Cols<P>{(const T*)c->a4, 1024, 1024, B}, EpFcDW{g + F1W, 1024, true}, c->ws, s);
     if (e != hipSuccess) return cnn_err(e, "fc1 dW");
-    hipLaunchKernelGGL((k_bias_grad<P>), dim3(256), dim3(256), 0, s, dh1, (int64_t)B, 256, g + F1B);
+    e = bias_grad<P>(dh1, B, 256, g + F1B, c->ws, s);
+    if (e != hipSuccess) return cnn_err(e, "fc1 bias grad");
     T* dact = (T*)c->d_a;  // [B][1024] = pooled gradient of block 4, position-major
     e = gemm<P>(B, 1024, 256, Rows<P>{dh1, B, 256, 256}, Rows<P>{(const T*)c->f1b, 1024, 256, 256},
                 EpStore<P>{dact, nullptr, 1024}, s);
@@ -1110,11 +1233,12 @@ int32_t backward(gpfc_cnn* c, const void* x, int xf32, int B, hipStream_t s) {
         T* dpre = (bufA == dact) ? bufB : bufA;
         hipLaunchKernelGGL((k_unpool<P>), dim3(blocks_for(npool)), dim3(256), 0, s, dact, masks[l],
                            npool, Cout, dpre);
-        hipLaunchKernelGGL((k_bias_grad<P>), dim3(Cout), dim3(256), 0, s, dpre, (int64_t)B * L, Cout,
-                           g + conv_b(l));
+        e = bias_grad<P>(dpre, (int64_t)B * L, Cout, g + conv_b(l), c->ws, s);
+        if (e != hipSuccess) return cnn_err(e, "conv bias grad");
         if (l == 1) {
-            hipLaunchKernelGGL((k_conv1_dw<P>), dim3(16 * 5), dim3(256), 0, s, dpre, x, xf32, B,
-                               g + kConvW[1]);
+            const int parts = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (int64_t)B * 256 / 1024));
+            hipLaunchKernelGGL((k_conv1_dw<P>), dim3(parts), dim3(256), 0, s, dpre, x, xf32, B, c->ws);
+            hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, c->ws, parts, 80, g + kConvW[1]);
             break;
         }
         e = gemm_splitk<P>(Cout, 5 * Cin, B * L, Cols<P>{dpre, Cout, Cout, B * L},

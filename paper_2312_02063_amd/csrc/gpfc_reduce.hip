@@ -59,14 +59,27 @@ __global__ __launch_bounds__(kTopThreads) void k_topk_rows(const float* __restri
     float wv = -INFINITY;        // the list's worst entry and the lane holding it
     int64_t wi = kNoIndex;
     int wpos = 0;
-    for (int64_t base = (int64_t)wave * 64; base < len; base += kTopThreads) {
-        const int64_t i = base + lane;
-        float x = 0.0f;
-        bool cand = false;
+    // kUnroll chunks of 64 per wave are loaded before any is examined, so
+    // their memory latencies overlap
+    constexpr int kUnroll = 8;
+    for (int64_t base0 = (int64_t)wave * 64; base0 < len; base0 += (int64_t)kTopThreads * kUnroll) {
+      float xs[kUnroll];
+      bool ok[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int64_t i = base0 + (int64_t)u * kTopThreads + lane;
+        xs[u] = 0.0f;
+        ok[u] = false;
         if (i < len) {
-            x = v[i];
-            cand = !__builtin_isnan(x) && (!g || g[i] >= gate_min) && beats(x, i, wv, wi);
+            xs[u] = v[i];
+            ok[u] = !g || g[i] >= gate_min;
         }
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int64_t i = base0 + (int64_t)u * kTopThreads + lane;
+        const float x = xs[u];
+        const bool cand = ok[u] && !__builtin_isnan(x) && beats(x, i, wv, wi);
         uint64_t m = __ballot(cand);
         while (m) {
             const int s = __builtin_ctzll(m);
@@ -91,6 +104,7 @@ __global__ __launch_bounds__(kTopThreads) void k_topk_rows(const float* __restri
             wi = ri;
             wpos = rp;
         }
+      }
     }
     lv_s[threadIdx.x] = lv;
     li_s[threadIdx.x] = li;
@@ -194,12 +208,22 @@ __global__ __launch_bounds__(kTopThreads) void k_periodogram(
     double s = 0.0;
     float mx = -INFINITY;
     int64_t amx = INT64_MAX;
-    for (int64_t i = tid; i < len; i += kTopThreads) {
-        const float x = v[i];
-        if (__builtin_isnan(x)) continue;
-        ++m;
-        s += x;
-        if (beats(x, i, mx, amx)) { mx = x; amx = i; }
+    for (int64_t i0 = tid; i0 < len; i0 += 4 * kTopThreads) {
+        float xs[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = i0 + (int64_t)u * kTopThreads;
+            xs[u] = i < len ? v[i] : __builtin_nanf("");
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = i0 + (int64_t)u * kTopThreads;
+            const float x = xs[u];
+            if (__builtin_isnan(x)) continue;
+            ++m;
+            s += x;
+            if (beats(x, i, mx, amx)) { mx = x; amx = i; }
+        }
     }
     for (int d = 32; d > 0; d >>= 1) {
         m += __shfl_xor(m, d);
@@ -229,9 +253,16 @@ __global__ __launch_bounds__(kTopThreads) void k_periodogram(
     // (2) squared deviations
     const double mean = sm.mean;
     double q = 0.0;
-    for (int64_t i = tid; i < len; i += kTopThreads) {
-        const float x = v[i];
-        if (!__builtin_isnan(x)) { const double d = x - mean; q += d * d; }
+    for (int64_t i0 = tid; i0 < len; i0 += 4 * kTopThreads) {
+        float xs[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = i0 + (int64_t)u * kTopThreads;
+            xs[u] = i < len ? v[i] : __builtin_nanf("");
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (!__builtin_isnan(xs[u])) { const double d = xs[u] - mean; q += d * d; }
     }
     for (int d = 32; d > 0; d >>= 1) q += __shfl_xor(q, d);
     if (lane == 0) sm.dred[wave] = q;
