@@ -223,3 +223,23 @@ def test_periodogram_peaks_match_oracle(torch_dev, rows, n, nsig, mw):
     np.testing.assert_allclose(g["sde"], o["sde"], rtol=1e-5, atol=1e-6)
     np.testing.assert_allclose(g["mean"], o["mean"], rtol=1e-5, atol=1e-6)
     np.testing.assert_allclose(g["sd"], o["sd"], rtol=1e-5, atol=1e-6)
+
+
+def test_survey_replay_uses_current_weights(torch_dev):
+    """A captured survey re-packs the network's weights on every replay: after
+    new parameters are set, the replay's logits equal an eager run's."""
+    torch = torch_dev
+    stars = _stars(3, seed=61)
+    k = 128
+    net = _net(torch, max_batch=512)
+    _say("survey capture, then new weights")
+    plan, gr, (t, f, p, side, _) = _survey(torch, stars, k, 256, net=net, top=2, capture=True)
+    net.set_params((synth.cnn_init(78) * 0.9).astype(np.float32))
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        plan.batch_replay()
+    side.synchronize()
+    er = plan.survey_run(t, f, p, 256, cnn=net, top=2, judge_snr=3.0)
+    torch.cuda.synchronize()
+    assert torch.equal(gr["logits"], er["logits"])
+    assert torch.equal(gr["cnn_idx"], er["cnn_idx"])
