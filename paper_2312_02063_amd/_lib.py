@@ -559,9 +559,10 @@ class Cnn:
             return 1
         raise TypeError("x must be uint16 (bfloat16 bits) or float32")
 
-    def set_fused(self, on: bool):
-        """bf16 inference through the fused convolution-stack kernel (default) or layer by layer."""
-        _check(self.lib.gpfc_cnn_set_fused(self.h, int(bool(on))), "gpfc_cnn_set_fused")
+    def set_fused(self, on):
+        """bf16 inference path: 1 / True fused convolution stack (default), 2 fused with
+        register-held weights, 0 / False layer by layer."""
+        _check(self.lib.gpfc_cnn_set_fused(self.h, int(on)), "gpfc_cnn_set_fused")
 
     def forward(self, x, out=None):
         """Logits f32[B] for x [B][256]."""

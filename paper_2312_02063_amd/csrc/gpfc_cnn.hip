@@ -656,6 +656,140 @@ __global__ __launch_bounds__(kFusedThreads, 1) void k_convstack_bf16(
     }
 }
 
+// Variant of the fused convolution stack with one wave per SIMD (4 waves):
+// each wave keeps its weight fragments in registers for the whole launch (a
+// wave always computes the same 32 output channels of a layer), so LDS holds
+// only activations and carries only the A-fragment traffic. Same arithmetic,
+// bit-identical output.
+constexpr int kRThreads = 256;
+
+struct ConvStackLdsR {
+    float w1[16 * 5];
+    float b1[16];
+    uint16_t xs[kTileF * 256];
+    uint16_t buf0[kTileF * 32 * kA3Ld];
+    uint16_t buf1[kTileF * 64 * kA2Ld];
+};
+
+// B fragments of one layer for column tile ct: [j][ks] (j = 16-column block).
+template <int CIN, int KSTEPS>
+__device__ __forceinline__ void load_wfrags(const uint16_t* __restrict__ wf, int ct,
+                                            bf16x8 (&b)[2][KSTEPS]) {
+    constexpr int K = 5 * CIN;
+    const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int ks = 0; ks < KSTEPS; ++ks) {
+            const int n = ct * 32 + j * 16 + r, k = ks * 32 + q * 8;
+            b[j][ks] = k < K ? *reinterpret_cast<const bf16x8*>(wf + n * K + k) : bf16x8{};
+        }
+}
+
+template <int L, int CIN, int ILD, int OLD, int KSTEPS>
+__device__ __forceinline__ void conv_wave_tile(const uint16_t* __restrict__ in,
+                                               const bf16x8 (&b)[2][KSTEPS], int rt, int ct,
+                                               const float* __restrict__ bias,
+                                               uint16_t* __restrict__ out, bool to_global, int nvalid) {
+    constexpr int K = 5 * CIN;
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15, q = lane >> 4;
+    f32x4 acc[4][2];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < KSTEPS; ++ks) {
+        const int k = ks * 32 + q * 8;
+        const int dx = k / CIN, ci0 = k - dx * CIN;
+        bf16x8 a[4];
+        for (int i = 0; i < 4; ++i) {
+            const int m = rt * 64 + i * 16 + r;
+            const int f = m / L, x = m - f * L;
+            int pos = x + dx - 2;
+            pos = pos < 0 ? pos + L : (pos >= L ? pos - L : pos);
+            a[i] = k < K ? *reinterpret_cast<const bf16x8*>(in + (f * L + pos) * ILD + ci0) : bf16x8{};
+        }
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j][ks], acc[i][j], 0, 0, 0);
+    }
+    for (int i = 0; i < 4; ++i) {
+        const int m0 = rt * 64 + i * 16 + q * 4;
+        const int f = m0 / L, x0 = m0 - f * L;
+        if (to_global && f >= nvalid) continue;
+        for (int j = 0; j < 2; ++j) {
+            const int n = ct * 32 + j * 16 + r;
+            const float bn = bias[n];
+            for (int h = 0; h < 2; ++h) {
+                const float p0 = acc[i][j][2 * h] + bn, p1 = acc[i][j][2 * h + 1] + bn;
+                const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
+                out[(f * (L / 2) + (x0 >> 1) + h) * OLD + n] = f2bf(r0 >= r1 ? r0 : r1);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kRThreads, 1) void k_convstack_bf16_r(
+    const void* __restrict__ x, int xf32, int B, const float* __restrict__ w1,
+    const float* __restrict__ b1, const uint16_t* __restrict__ wf2, const float* __restrict__ b2,
+    const uint16_t* __restrict__ wf3, const float* __restrict__ b3,
+    const uint16_t* __restrict__ wf4, const float* __restrict__ b4, uint16_t* __restrict__ a4) {
+    __shared__ __attribute__((aligned(16))) ConvStackLdsR sm;
+    const int tid = threadIdx.x, wave = tid >> 6;
+    // conv2: row tiles wave + 4i (one column tile); conv3 / conv4: column tile
+    // wave & 1, row tiles (wave >> 1) + 2i
+    bf16x8 bw2[2][3], bw3[2][5], bw4[2][10];
+    load_wfrags<16, 3>(wf2, 0, bw2);
+    load_wfrags<32, 5>(wf3, wave & 1, bw3);
+    load_wfrags<64, 10>(wf4, wave & 1, bw4);
+    if (tid < 80) sm.w1[tid] = w1[tid];
+    if (tid < 16) sm.b1[tid] = b1[tid];
+    const int ntiles = (B + kTileF - 1) / kTileF;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int f0 = tile * kTileF;
+        const int nvalid = min(kTileF, B - f0);
+        // 256 threads x 8 elements = one [8][256] tile
+        for (int h = 0; h < 2; ++h) {
+            const uint2 v = load_x4(x, xf32, f0, nvalid, tid + h * kRThreads);
+            reinterpret_cast<uint2*>(sm.xs)[tid + h * kRThreads] = v;
+        }
+        __syncthreads();
+        for (int pi = tid; pi < kTileF * 128; pi += kRThreads) {
+            const int f = pi >> 7, xp = pi & 127;
+            float v[6];
+            for (int d = 0; d < 6; ++d) v[d] = bf2f(sm.xs[f * 256 + ((2 * xp + d - 2) & 255)]);
+            uint32_t packed[8];
+            for (int co = 0; co < 16; ++co) {
+                float p0 = sm.b1[co], p1 = sm.b1[co];
+                for (int dx = 0; dx < 5; ++dx) {
+                    p0 += sm.w1[co * 5 + dx] * v[dx];
+                    p1 += sm.w1[co * 5 + dx] * v[dx + 1];
+                }
+                const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
+                const uint32_t hbits = f2bf(r0 >= r1 ? r0 : r1);
+                if (co & 1) packed[co >> 1] |= hbits << 16;
+                else packed[co >> 1] = hbits;
+            }
+            uint4* dst = reinterpret_cast<uint4*>(sm.buf0 + (f * 128 + xp) * kA1Ld);
+            dst[0] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
+            dst[1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
+        }
+        __syncthreads();
+        for (int i = 0; i < 4; ++i)
+            conv_wave_tile<128, 16, kA1Ld, kA2Ld, 3>(sm.buf0, bw2, wave + 4 * i, 0, b2, sm.buf1, false,
+                                                     nvalid);
+        __syncthreads();
+        for (int i = 0; i < 4; ++i)
+            conv_wave_tile<64, 32, kA2Ld, kA3Ld, 5>(sm.buf1, bw3, (wave >> 1) + 2 * i, wave & 1, b3,
+                                                    sm.buf0, false, nvalid);
+        __syncthreads();
+        for (int i = 0; i < 2; ++i)
+            conv_wave_tile<32, 64, kA3Ld, 64, 10>(sm.buf0, bw4, (wave >> 1) + 2 * i, wave & 1, b4,
+                                                  a4 + (int64_t)f0 * 1024, true, nvalid);
+        __syncthreads();
+    }
+}
+
 // Fully connected layer for bf16 inference: out[m][n] = ReLU(bias[n] +
 // sum_k A[m][k] W[n][k]) with A [M][K] activations and W [N][K] weights,
 // both row-major bf16. Block tile 128 x BN, 4 waves of 64 x BN/2; K advances
@@ -1086,7 +1220,8 @@ struct gpfc_cnn {
     float* ws = nullptr;         // split-K partial sums (kSplitWs floats)
     void* work = nullptr;        // packed weights + activations
     bool packed = false;
-    bool fused = true;           // bf16 inference through k_convstack_bf16
+    bool fused = true;           // bf16 inference through the fused convolution stack
+    int32_t fused_mode = 1;      // 1: weights in LDS, 2: weights in registers
     int32_t n_cu = 256;
     // views into work (element type per prec)
     void *wf2, *wb2, *wf3, *wb3, *wf4, *wb4, *f1f, *f1b, *f2f, *f2b;
@@ -1153,10 +1288,16 @@ int32_t forward(gpfc_cnn* c, const void* x, int xf32, int B, float* logits, cons
                        ((uintptr_t)x & 15) == 0;   // the fused kernel loads 16-byte groups
     if (fused) {
         const int ntiles = (B + kTileF - 1) / kTileF;
-        hipLaunchKernelGGL(k_convstack_bf16, dim3((unsigned)std::min(ntiles, c->n_cu)),
-                           dim3(kFusedThreads), 0, s, x, xf32, B, w + kConvW[1], w + conv_b(1),
-                           (const uint16_t*)c->wf2, w + conv_b(2), (const uint16_t*)c->wf3,
-                           w + conv_b(3), (const uint16_t*)c->wf4, w + conv_b(4), (uint16_t*)c->a4);
+        if (c->fused_mode == 2)
+            hipLaunchKernelGGL(k_convstack_bf16_r, dim3((unsigned)std::min(ntiles, c->n_cu)),
+                               dim3(kRThreads), 0, s, x, xf32, B, w + kConvW[1], w + conv_b(1),
+                               (const uint16_t*)c->wf2, w + conv_b(2), (const uint16_t*)c->wf3,
+                               w + conv_b(3), (const uint16_t*)c->wf4, w + conv_b(4), (uint16_t*)c->a4);
+        else
+            hipLaunchKernelGGL(k_convstack_bf16, dim3((unsigned)std::min(ntiles, c->n_cu)),
+                               dim3(kFusedThreads), 0, s, x, xf32, B, w + kConvW[1], w + conv_b(1),
+                               (const uint16_t*)c->wf2, w + conv_b(2), (const uint16_t*)c->wf3,
+                               w + conv_b(3), (const uint16_t*)c->wf4, w + conv_b(4), (uint16_t*)c->a4);
     } else {
     hipLaunchKernelGGL((k_conv1_fwd<P>), dim3(blocks_for((int64_t)B * 128 * 16)), dim3(256), 0, s, x,
                        xf32, B, w + kConvW[1], w + conv_b(1), (T*)c->a1, train ? c->m1 : nullptr);
@@ -1367,7 +1508,9 @@ int32_t gpfc_cnn_set_params(gpfc_cnn* c, const float* params, void* stream) {
 
 int32_t gpfc_cnn_set_fused(gpfc_cnn* c, int32_t on) {
     if (!c) return GPFC_EINVAL;
+    if (on < 0 || on > 2) return GPFC_EINVAL;
     c->fused = on != 0;
+    if (on) c->fused_mode = on;
     return GPFC_OK;
 }
 

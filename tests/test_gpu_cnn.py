@@ -209,5 +209,9 @@ def test_fused_inference_bit_identical(torch_dev, B):
     zlb = net.forward(xb).cpu().numpy()
     assert np.array_equal(zf, zl)
     assert np.array_equal(zfb, zlb)
+    net.set_fused(2)
+    zr = net.forward(xt).cpu().numpy()
+    net.set_fused(1)
+    assert np.array_equal(zr, zl)
     zo = oracle.cnn_forward(p, x)
     assert _rel(zf, zo) < 5e-2
