@@ -334,8 +334,23 @@ int32_t gpfc_cnn_calibrate_fp8(gpfc_cnn *cnn, const void *x, int32_t x_f32, int6
 int32_t gpfc_cnn_forward_fp8(gpfc_cnn *cnn, const void *x, int32_t x_f32, int64_t B, float *logits,
                              void *stream);
 
-/* One bias-corrected Adam step on the FP32 masters with the last gradient. */
+/* One bias-corrected Adam step on the FP32 masters with the last gradient
+ * (the step count lives on the device; gpfc_cnn_set_params resets it). */
 int32_t gpfc_cnn_adam(gpfc_cnn *cnn, float lr, float beta1, float beta2, float eps, void *stream);
+
+/*
+ * A whole training step (gpfc_cnn_backward then gpfc_cnn_adam) recorded
+ * into a HIP graph held by the network, for the launch-bound small batches
+ * of training: replays read x[B][256] and labels[B] from the same buffers
+ * (fill them before each replay), re-pack the weights the previous step
+ * changed, and write the step's mean loss to loss_out (f32[1], may be NULL).
+ * `stream` must be a created stream, not the null stream. A later capture
+ * replaces the graph.
+ */
+int32_t gpfc_cnn_train_capture(gpfc_cnn *cnn, const void *x, int32_t x_f32, const float *labels,
+                               int64_t B, float lr, float beta1, float beta2, float eps,
+                               float *loss_out, void *stream);
+int32_t gpfc_cnn_train_replay(gpfc_cnn *cnn, void *stream);
 
 /* ------------------------------------------------------------------------
  * Per-curve reduction (Sec. 2.1: a curve's detection is the trial period

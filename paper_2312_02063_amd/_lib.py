@@ -106,6 +106,9 @@ def load():
         "gpfc_cnn_adam": ([vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp], i32),
         "gpfc_cnn_calibrate_fp8": ([vp, vp, i32, i64, i32, vp], i32),
         "gpfc_cnn_forward_fp8": ([vp, vp, i32, i64, vp, vp], i32),
+        "gpfc_cnn_train_capture": ([vp, vp, i32, vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float, vp, vp], i32),
+        "gpfc_cnn_train_replay": ([vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -126,7 +129,8 @@ def exported_symbols():
             "gpfc_batch_curve_stats", "gpfc_cnn_nparams", "gpfc_cnn_last_error",
             "gpfc_cnn_create", "gpfc_cnn_destroy", "gpfc_cnn_set_params", "gpfc_cnn_get_params",
             "gpfc_cnn_forward", "gpfc_cnn_backward", "gpfc_cnn_adam", "gpfc_cnn_calibrate_fp8",
-            "gpfc_cnn_forward_fp8", "gpfc_cnn_set_fused", "gpfc_topk", "gpfc_plan_set_split",
+            "gpfc_cnn_forward_fp8", "gpfc_cnn_set_fused", "gpfc_cnn_train_capture",
+            "gpfc_cnn_train_replay", "gpfc_topk", "gpfc_plan_set_split",
             "gpfc_autotune", "gpfc_fold_eqcount_prepared", "gpfc_periodogram_peaks", "gpfc_survey_setup", "gpfc_survey_run",
             "gpfc_survey_capture"]
 
@@ -607,6 +611,28 @@ class Cnn:
 
     def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
         _check(self.lib.gpfc_cnn_adam(self.h, lr, beta1, beta2, eps, _stream()), "gpfc_cnn_adam")
+
+    def train_capture(self, x, labels, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                      eps: float = 1e-8):
+        """Record one training step on x / labels into a HIP graph (on a side
+        stream); returns the device loss buffer each replay writes."""
+        import torch
+        xf = self._x(x)
+        _need(x, x.dtype, "x", self.device)
+        _need(labels, torch.float32, "labels", self.device)
+        self._train_keep = (x, labels)
+        self._train_loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+        self._train_stream = torch.cuda.Stream(device=self.device)
+        with torch.cuda.stream(self._train_stream):
+            _check(self.lib.gpfc_cnn_train_capture(self.h, _ptr(x), xf, _ptr(labels), x.shape[0], lr,
+                                                   beta1, beta2, eps, _ptr(self._train_loss),
+                                                   _stream()), "gpfc_cnn_train_capture")
+        return self._train_loss
+
+    def train_replay(self):
+        """One captured training step, ordered after the current stream's work."""
+        _check(self.lib.gpfc_cnn_train_replay(self.h, _stream()), "gpfc_cnn_train_replay")
+        return self._train_loss
 
     def train_step(self, x, labels, lr: float):
         loss = self.backward(x, labels)

@@ -1135,18 +1135,36 @@ __global__ __launch_bounds__(256) void k_quant_rows(const uint16_t* __restrict__
     }
 }
 
+// Adam with the step count on the device (so a captured training step can be
+// replayed): k_step_inc advances it, k_adam derives the bias corrections.
+__global__ void k_step_inc(int32_t* __restrict__ step) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1;
+}
+
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
                                               float* __restrict__ m, float* __restrict__ v, int64_t n,
-                                              float lr, float b1, float b2, float eps, float c1,
-                                              float c2) {
+                                              float lr, float b1, float b2, float eps,
+                                              const int32_t* __restrict__ step) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
+    const double t = (double)*step;
+    const float c1 = (float)(1.0 - pow((double)b1, t));
+    const float c2 = (float)(1.0 - pow((double)b2, t));
     const float gi = g[i];
     const float mi = b1 * m[i] + (1.0f - b1) * gi;
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void k_copy_f32(const float* __restrict__ src, float* __restrict__ dst, int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+__global__ void k_set_i32c(int32_t* __restrict__ p, int32_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
 __global__ __launch_bounds__(256) void k_fill(float* __restrict__ p, int64_t n, float v) {
@@ -1211,7 +1229,9 @@ struct gpfc_cnn {
     int32_t device = 0;
     int32_t prec = 0;            // 0 bf16, 1 fp32
     int64_t max_batch = 0;
-    int64_t step = 0;
+    int32_t* step_dev = nullptr;  // Adam step count (device)
+    hipGraph_t train_graph = nullptr;
+    hipGraphExec_t train_exec = nullptr;
     float* params = nullptr;     // FP32 masters, canonical layout
     float* grad = nullptr;
     float* m = nullptr;
@@ -1477,6 +1497,7 @@ int32_t gpfc_cnn_create(gpfc_cnn** out, int32_t device, int32_t precision, int64
         *cv[i] = (float*)take(csz[i] * sizeof(float));
     }
     c->act_max = (uint32_t*)take(256);
+    c->step_dev = (int32_t*)take(256);
     *out = c;
     return GPFC_OK;
 }
@@ -1485,6 +1506,8 @@ int32_t gpfc_cnn_destroy(gpfc_cnn* c) {
     if (!c) return GPFC_OK;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
+    if (c->train_exec) (void)hipGraphExecDestroy(c->train_exec);
+    if (c->train_graph) (void)hipGraphDestroy(c->train_graph);
     if (c->work) (void)hipFree(c->work);
     delete c;
     return GPFC_OK;
@@ -1499,7 +1522,7 @@ int32_t gpfc_cnn_set_params(gpfc_cnn* c, const float* params, void* stream) {
     const unsigned nb = gcnn::blocks_for(gcnn::kNP);
     hipLaunchKernelGGL(gcnn::k_fill, dim3(nb), dim3(256), 0, s, c->m, (int64_t)gcnn::kNP, 0.0f);
     hipLaunchKernelGGL(gcnn::k_fill, dim3(nb), dim3(256), 0, s, c->v, (int64_t)gcnn::kNP, 0.0f);
-    c->step = 0;
+    hipLaunchKernelGGL(gcnn::k_set_i32c, dim3(1), dim3(64), 0, s, c->step_dev, 0);
     c->packed = false;
     c->quantized = false;
     e = hipGetLastError();
@@ -1549,20 +1572,63 @@ int32_t gpfc_cnn_backward(gpfc_cnn* c, const void* x, int32_t x_f32, const float
     return e == hipSuccess ? GPFC_OK : cnn_err(e, "copy out");
 }
 
-int32_t gpfc_cnn_adam(gpfc_cnn* c, float lr, float beta1, float beta2, float eps, void* stream) {
-    if (!c || !(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f))
-        return GPFC_EINVAL;
-    c->step += 1;
-    const float c1 = (float)(1.0 - pow((double)beta1, (double)c->step));
-    const float c2 = (float)(1.0 - pow((double)beta2, (double)c->step));
-    hipStream_t s = (hipStream_t)stream;
+static bool adam_args_ok(float lr, float beta1, float beta2) {
+    return lr >= 0.0f && beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f;
+}
+
+static int32_t enqueue_adam(gpfc_cnn* c, float lr, float beta1, float beta2, float eps, hipStream_t s) {
+    hipLaunchKernelGGL(gcnn::k_step_inc, dim3(1), dim3(64), 0, s, c->step_dev);
     hipLaunchKernelGGL(gcnn::k_adam, dim3(gcnn::blocks_for(gcnn::kNP)), dim3(256), 0, s, c->params,
-                       c->grad, c->m, c->v, (int64_t)gcnn::kNP, lr, beta1, beta2, eps, c1, c2);
+                       c->grad, c->m, c->v, (int64_t)gcnn::kNP, lr, beta1, beta2, eps, c->step_dev);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cnn_err(e, "k_adam");
     c->packed = false;
     c->quantized = false;
     return GPFC_OK;
+}
+
+int32_t gpfc_cnn_adam(gpfc_cnn* c, float lr, float beta1, float beta2, float eps, void* stream) {
+    if (!c || !adam_args_ok(lr, beta1, beta2)) return GPFC_EINVAL;
+    return enqueue_adam(c, lr, beta1, beta2, eps, (hipStream_t)stream);
+}
+
+int32_t gpfc_cnn_train_capture(gpfc_cnn* c, const void* x, int32_t x_f32, const float* labels,
+                               int64_t B, float lr, float beta1, float beta2, float eps,
+                               float* loss_out, void* stream) {
+    if (!c || B < 1 || B > c->max_batch || !x || !labels || !adam_args_ok(lr, beta1, beta2))
+        return GPFC_EINVAL;
+    if (!stream) return GPFC_EINVAL;   // the null stream cannot be captured
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return cnn_err(e, "hipSetDevice");
+    if (c->train_exec) { (void)hipGraphExecDestroy(c->train_exec); c->train_exec = nullptr; }
+    if (c->train_graph) { (void)hipGraphDestroy(c->train_graph); c->train_graph = nullptr; }
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return cnn_err(e, "hipStreamBeginCapture");
+    int32_t rc = gpfc_cnn_backward(c, x, x_f32, labels, B, nullptr, nullptr, stream);
+    if (rc == GPFC_OK) rc = enqueue_adam(c, lr, beta1, beta2, eps, s);
+    if (rc == GPFC_OK && loss_out)
+        hipLaunchKernelGGL(gcnn::k_copy_f32, dim3(1), dim3(256), 0, s, c->loss, loss_out, 1);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s, &g);
+    if (rc != GPFC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return cnn_err(e, "hipStreamEndCapture");
+    c->train_graph = g;
+    e = hipGraphInstantiate(&c->train_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        c->train_exec = nullptr;
+        return cnn_err(e, "hipGraphInstantiate");
+    }
+    return GPFC_OK;
+}
+
+int32_t gpfc_cnn_train_replay(gpfc_cnn* c, void* stream) {
+    if (!c || !c->train_exec) return GPFC_EINVAL;
+    hipError_t e = hipGraphLaunch(c->train_exec, (hipStream_t)stream);
+    return e == hipSuccess ? GPFC_OK : cnn_err(e, "hipGraphLaunch");
 }
 
 int32_t gpfc_cnn_calibrate_fp8(gpfc_cnn* c, const void* x, int32_t x_f32, int64_t B, int32_t reset,

@@ -91,22 +91,29 @@ def make_training_set(plan, n_pos: int, n_neg: int, seed: int, periods: np.ndarr
 
 
 def train(net, z, labels, epochs: int = 4, batch: int = 256, lr: float = 1e-3, seed: int = 7,
-          log=None):
-    """Adam on mini-batches of the kernel folds; returns the mean loss per epoch."""
+          log=None, graph: bool = True):
+    """Adam on mini-batches of the kernel folds; returns the mean loss per epoch.
+    With graph=True each step is one replay of a captured training step (the
+    batch is gathered into the captured buffers first)."""
     import torch
     rng = np.random.Generator(np.random.PCG64(seed))
     n = z.shape[0]
     hist = []
+    xbuf = torch.empty((batch, z.shape[1]), dtype=z.dtype, device=z.device)
+    ybuf = torch.empty(batch, dtype=torch.float32, device=z.device)
+    if graph and n >= batch:
+        net.train_capture(xbuf, ybuf, lr)
     for ep in range(epochs):
         perm = torch.as_tensor(rng.permutation(n), device=z.device)
-        tot, cnt = 0.0, 0
-        losses = []
+        acc = torch.zeros(1, dtype=torch.float32, device=z.device)
+        steps = 0
         for i in range(0, n - batch + 1, batch):
             idx = perm[i:i + batch]
-            xb = z.index_select(0, idx).contiguous()
-            yb = labels.index_select(0, idx).contiguous()
-            losses.append(net.train_step(xb, yb, lr).clone())
-        tot = torch.cat(losses).mean().item() if losses else float("nan")
+            torch.index_select(z, 0, idx, out=xbuf)
+            torch.index_select(labels, 0, idx, out=ybuf)
+            acc += net.train_replay() if graph else net.train_step(xbuf, ybuf, lr)
+            steps += 1
+        tot = (acc / max(steps, 1)).item() if steps else float("nan")
         hist.append(tot)
         if log:
             log(f"epoch {ep}: mean loss {tot:.5f}")

@@ -215,3 +215,29 @@ def test_fused_inference_bit_identical(torch_dev, B):
     assert np.array_equal(zr, zl)
     zo = oracle.cnn_forward(p, x)
     assert _rel(zf, zo) < 5e-2
+
+
+def test_captured_training_step_equals_eager(torch_dev):
+    """Graph replays of a training step (new batches copied into the captured
+    buffers each time) give the same parameters and losses as eager steps."""
+    torch = torch_dev
+    from paper_2312_02063_amd import CNN_BF16
+    p = _params(21)
+    B = 128
+    xs = [torch.tensor(_inputs(30 + i, B)[0], dtype=torch.float32, device="cuda") for i in range(4)]
+    ys = [torch.tensor(_inputs(30 + i, B)[1], dtype=torch.float32, device="cuda") for i in range(4)]
+    eager = _net(torch, CNN_BF16, p)
+    graph = _net(torch, CNN_BF16, p)
+    xbuf = torch.empty_like(xs[0])
+    ybuf = torch.empty_like(ys[0])
+    _say("cnn training graph capture")
+    loss_buf = graph.train_capture(xbuf, ybuf, 1e-3)
+    torch.cuda.synchronize()
+    for i in range(4):
+        le = eager.train_step(xs[i], ys[i], 1e-3).item()
+        xbuf.copy_(xs[i])
+        ybuf.copy_(ys[i])
+        lg = graph.train_replay().item()
+        assert lg == le, (i, lg, le)
+    torch.cuda.synchronize()
+    assert torch.equal(eager.get_params(), graph.get_params())
