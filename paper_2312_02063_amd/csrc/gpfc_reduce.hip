@@ -281,16 +281,22 @@ __global__ __launch_bounds__(kTopThreads) void k_periodogram(
     int32_t np = 0;
     Run head{0, -INFINITY, INT64_MAX}, cur{0, -INFINITY, INT64_MAX};
     bool in_head = true;     // still inside a run that starts at c0
-    for (int64_t i = c0; i < c1; ++i) {
-        const float x = v[i];
-        const bool above = !__builtin_isnan(x) && (double)x > thr;
-        if (above) {
-            cur = join(cur, Run{1, x, i});
-        } else {
-            if (in_head) head = cur;
-            else if (cur.len > min_width) { ++np; pl.insert(cur.mx, cur.arg, (int32_t)cur.len); }
-            cur = Run{0, -INFINITY, INT64_MAX};
-            in_head = false;
+    for (int64_t i0 = c0; i0 < c1; i0 += 8) {
+        float xs[8];     // loaded together so their latencies overlap
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xs[u] = i0 + u < c1 ? v[i0 + u] : 0.0f;
+        for (int u = 0; u < 8 && i0 + u < c1; ++u) {
+            const int64_t i = i0 + u;
+            const float x = xs[u];
+            const bool above = !__builtin_isnan(x) && (double)x > thr;
+            if (above) {
+                cur = join(cur, Run{1, x, i});
+            } else {
+                if (in_head) head = cur;
+                else if (cur.len > min_width) { ++np; pl.insert(cur.mx, cur.arg, (int32_t)cur.len); }
+                cur = Run{0, -INFINITY, INT64_MAX};
+                in_head = false;
+            }
         }
     }
     const bool full = in_head;     // every score of the chunk is above (an empty chunk too)
