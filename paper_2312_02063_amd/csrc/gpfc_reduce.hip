@@ -285,8 +285,10 @@ __global__ __launch_bounds__(kTopThreads) void k_periodogram(
         float xs[8];     // loaded together so their latencies overlap
 #pragma unroll
         for (int u = 0; u < 8; ++u) xs[u] = i0 + u < c1 ? v[i0 + u] : 0.0f;
-        for (int u = 0; u < 8 && i0 + u < c1; ++u) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
             const int64_t i = i0 + u;
+            if (i >= c1) break;
             const float x = xs[u];
             const bool above = !__builtin_isnan(x) && (double)x > thr;
             if (above) {
