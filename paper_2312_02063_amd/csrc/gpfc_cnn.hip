@@ -13,6 +13,14 @@
 // Master weights, gradients and Adam moments are FP32 in the canonical
 // layout (conv [Cout][Cin][5], fc [out][in], the flatten after block 4
 // channel-major); the GEMMs read packed working copies.
+//
+// Inference of a bf16 network runs the four convolution blocks as one
+// persistent kernel with every activation in LDS (k_convstack_bf16, or
+// k_convstack_bf16_r with register-held weights) and the fully connected
+// layers as LDS-tiled GEMMs (k_fc1_bf16, k_fc_bf16); training runs layer by
+// layer through device memory (it keeps activations and pooling masks for
+// the backward pass) and can be replayed as one HIP graph per step. Every
+// inference path gives the same bits as the layer path.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
