@@ -529,42 +529,13 @@ __device__ void score_table(const char* tab, int nb, int g, const Widths& W, Sco
     for (int wi = 0; wi < W.n; ++wi)
         if (W.w[wi] < nb) wmax = max(wmax, W.w[wi]);
     const bool fast = g <= kRowsPerWave && sh.nz[lane] > wmax;
-    // Each wave takes a range of starts for every width: the prefix at the
-    // start is loaded once and reused by all widths. A width's best over the
-    // waves is an integer max of the (non-negative) float bits in LDS.
-    for (int i = threadIdx.x; i < kMaxWidths * 64; i += kThreads) sh.bestv[i] = 0.0f;
-    __syncthreads();
-    if (ok_sigma) {
-        float best[kMaxWidths];
-#pragma unroll
-        for (int wi = 0; wi < kMaxWidths; ++wi) best[wi] = 0.0f;
-        const int per = (nb + kWaves - 1) / kWaves;
-        const int s0 = wave * per, s1 = min(nb, s0 + per);
-        for (int s = s0; s < s1; ++s) {
-            const Slot a = coarse_prefix(tab, s, g, lane);
-#pragma unroll
-            for (int wi = 0; wi < kMaxWidths; ++wi) {
-                if (wi >= W.n) break;
-                const int w = W.w[wi];
-                if (w >= nb) continue;
-                float v;
-                if (s + w <= nb) {
-                    const Slot e = coarse_prefix(tab, s + w, g, lane);
-                    v = fast ? box_value<false>(e.c - a.c, e.dn - a.dn, nf, Sf)
-                             : box_value<true>(e.c - a.c, e.dn - a.dn, nf, Sf);
-                } else {
-                    const Slot e = coarse_prefix(tab, s + w - nb, g, lane);
-                    const float cin = (e.c + tot.c) - a.c, din = (e.dn + tot.dn) - a.dn;
-                    v = fast ? box_value<false>(cin, din, nf, Sf) : box_value<true>(cin, din, nf, Sf);
-                }
-                best[wi] = fmaxf(best[wi], v);
-            }
-        }
-#pragma unroll
-        for (int wi = 0; wi < kMaxWidths; ++wi)
-            if (wi < W.n && best[wi] > 0.0f)
-                atomicMax(reinterpret_cast<unsigned int*>(&sh.bestv[wi * 64 + lane]),
-                          __float_as_uint(best[wi]));
+    if (wave < W.n) {
+        const int w = W.w[wave];
+        float b = 0.0f;
+        if (w < nb && ok_sigma)
+            b = fast ? scan_width<false>(tab, w, nb, g, lane, nf, Sf, tot)
+                     : scan_width<true>(tab, w, nb, g, lane, nf, Sf, tot);
+        sh.bestv[wave * 64 + lane] = b;
     }
     __syncthreads();
     float best = 0.0f;
