@@ -19,6 +19,11 @@ def test_precision_sweep_small():
         assert mode["snr_rel_error"]["max"] < 1e-5
     assert fold["int64_exact"]["bin_mean_abs_error"]["max"] < 1e-15
     assert fold["fp32_twosum"]["bin_mean_abs_error"]["max"] <= fold["fp32_plain"]["bin_mean_abs_error"]["max"]
+    var = r["fold_variable_star"]
+    for mode in var.values():
+        assert mode["counts_bit_exact"]
+    assert var["int64_exact"]["bin_mean_abs_error"]["max"] < 1e-14
+    assert var["fp32_twosum"]["bin_mean_abs_error"]["max"] <= var["fp32_plain"]["bin_mean_abs_error"]["max"]
     cnn = r["cnn"]
     assert cnn["fp32"]["logit_abs_error"]["max"] < cnn["bf16"]["logit_abs_error"]["max"]
     assert cnn["bf16"]["logit_abs_error"]["rms"] <= cnn["fp8_e4m3"]["logit_abs_error"]["rms"] * 1.5
