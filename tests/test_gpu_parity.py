@@ -428,3 +428,18 @@ def test_equal_count_fold_matches_oracle(torch_dev, n, k, nbins):
         rows = ~np.isnan(mo).any(axis=1)
         assert np.abs(zg[rows] - zo[rows]).max() <= 2e-2 + 2 ** -8 * np.abs(zo[rows]).max()
     p.close()
+
+
+def test_maximum_samples_all_in_one_bin(torch_dev, plan):
+    """GPFC_MAX_SAMPLES samples at whole multiples of the period: one bin holds
+    every count and the whole flux sum (the packed 64-bit bin at its limits),
+    plus a second period that spreads them; fused score and materialised fold."""
+    torch = torch_dev
+    n = 262143
+    rng = np.random.default_rng(12)
+    t = 0.5 * np.arange(n, dtype=np.float64)                 # P = 0.5: residual 0 for all
+    f = (1.0 + rng.normal(0, 2e-3, n)).astype(np.float32)
+    periods = np.array([0.5, 0.37, 1.0 / 3.0])
+    _say(f"max samples n={n}")
+    check_fold(torch, plan, t, f, periods, 256, "nmax")
+    check_fold_score(torch, plan, t, f, periods, 256, "nmax")
