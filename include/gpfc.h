@@ -302,8 +302,9 @@ int32_t gpfc_cnn_get_params(gpfc_cnn *cnn, float *out, void *stream);
 /*
  * Inference path of a bf16 network: on = 1 (the default), the four
  * convolution blocks run as one fused kernel (8 waves per compute unit) that
- * keeps every activation and the convolution weights in LDS; 2, the same
- * with 4 waves that hold their weight fragments in registers; 0, layer by
+ * keeps the convolution weights in LDS and every activation in a wave's own
+ * LDS slice, each wave taking whole inputs on its own (no block-wide waits);
+ * 2, the same fused stack over tiles of 8 inputs in lockstep; 0, layer by
  * layer through device memory. All give bit-identical logits.
  */
 int32_t gpfc_cnn_set_fused(gpfc_cnn *cnn, int32_t on);

@@ -564,8 +564,8 @@ class Cnn:
         raise TypeError("x must be uint16 (bfloat16 bits) or float32")
 
     def set_fused(self, on):
-        """bf16 inference path: 1 / True fused convolution stack (default), 2 fused with
-        register-held weights, 0 / False layer by layer."""
+        """bf16 inference path: 1 / True fused convolution stack with wave-private inputs
+        (default), 2 fused over tiles of 8 inputs in lockstep, 0 / False layer by layer."""
         _check(self.lib.gpfc_cnn_set_fused(self.h, int(on)), "gpfc_cnn_set_fused")
 
     def forward(self, x, out=None):

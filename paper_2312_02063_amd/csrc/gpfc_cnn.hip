@@ -15,8 +15,8 @@
 // channel-major); the GEMMs read packed working copies.
 //
 // Inference of a bf16 network runs the four convolution blocks as one
-// persistent kernel with every activation in LDS (k_convstack_bf16, or
-// k_convstack_bf16_r with register-held weights) and the fully connected
+// persistent kernel with every activation in LDS (k_convstack_bf16_w with
+// wave-private inputs, or k_convstack_bf16 with tiles of 8) and the fully connected
 // layers as LDS-tiled GEMMs (k_fc1_bf16, k_fc_bf16); training runs layer by
 // layer through device memory (it keeps activations and pooling masks for
 // the backward pass) and can be replayed as one HIP graph per step. Every
@@ -522,6 +522,16 @@ struct ConvStackLds {
     uint16_t buf1[kTileF * 64 * kA2Ld];            // a2 [F][64][40]
 };
 static_assert(kTileF * 128 * kA1Ld <= kTileF * 32 * kA3Ld, "a1 must fit where a3 goes");
+
+// Element offset of (row, first channel ci0 of an 8-channel group) in an LDS
+// activation buffer of row stride ILD. Rows of a1 are only 32 bytes, so the
+// two 16-byte groups of a row swap places on rows with bit 3 set: the 16 rows
+// an MFMA fragment load touches then cover all LDS banks once.
+template <int ILD>
+__device__ __forceinline__ int act_off(int row, int ci0) {
+    if constexpr (ILD == 16) return row * 16 + (ci0 ^ (((row >> 3) & 1) << 3));
+    return row * ILD + ci0;
+}
 static_assert(sizeof(ConvStackLds) <= 160 * 1024, "LDS budget");
 
 // One implicit-GEMM conv layer over the tile: rows (f, x) for x < L, columns
@@ -558,7 +568,7 @@ __device__ __forceinline__ void conv_tile(const uint16_t* __restrict__ in,
                 const int f = m / L, x = m - f * L;
                 int pos = x + dx - 2;
                 pos = pos < 0 ? pos + L : (pos >= L ? pos - L : pos);
-                a[i] = k < K ? *reinterpret_cast<const bf16x8*>(in + (f * L + pos) * ILD + ci0) : bf16x8{};
+                a[i] = k < K ? *reinterpret_cast<const bf16x8*>(in + act_off<ILD>(f * L + pos, ci0)) : bf16x8{};
             }
             for (int j = 0; j < 2; ++j)
                 b[j] = *reinterpret_cast<const bf16x8*>(w + (ct * 32 + j * 16 + r) * WLD + ks * 32 + q * 8);
@@ -649,9 +659,11 @@ __global__ __launch_bounds__(kFusedThreads, 1) void k_convstack_bf16(
                 if (co & 1) packed[co >> 1] |= hbits << 16;
                 else packed[co >> 1] = hbits;
             }
-            uint4* dst = reinterpret_cast<uint4*>(sm.buf0 + (f * 128 + xp) * kA1Ld);
-            dst[0] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
-            dst[1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
+            const int row = f * 128 + xp;
+            const int sw = (row >> 3) & 1;     // the a1 swizzle of act_off<16>
+            uint4* dst = reinterpret_cast<uint4*>(sm.buf0 + row * kA1Ld);
+            dst[sw] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
+            dst[sw ^ 1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
         }
         __syncthreads();
         conv_tile<128, 16, kA1Ld, 32, kW2Ld, kA2Ld>(sm.buf0, sm.w2, b2, sm.buf1, false, nvalid);
@@ -664,108 +676,131 @@ __global__ __launch_bounds__(kFusedThreads, 1) void k_convstack_bf16(
     }
 }
 
-// Variant of the fused convolution stack with one wave per SIMD (4 waves):
-// each wave keeps its weight fragments in registers for the whole launch (a
-// wave always computes the same 32 output channels of a layer), so LDS holds
-// only activations and carries only the A-fragment traffic. Same arithmetic,
-// bit-identical output.
-constexpr int kRThreads = 256;
+// Variant of the fused convolution stack in which every wave takes whole
+// inputs through all four blocks on its own: the block shares only the
+// weights staged in LDS, each wave has a private slice of LDS for one input's
+// activations, and nothing inside the loop waits for another wave, so one
+// wave's vector work (conv1, epilogues) overlaps others' matrix work. Same
+// arithmetic and summation order: bit-identical output.
+constexpr int kWP = 8;                           // waves (inputs in flight) per block
 
-struct ConvStackLdsR {
-    float w1[16 * 5];
-    float b1[16];
-    uint16_t xs[kTileF * 256];
-    uint16_t buf0[kTileF * 32 * kA3Ld];
-    uint16_t buf1[kTileF * 64 * kA2Ld];
+struct WaveSlice {
+    uint16_t xs[256];                            // the input (bf16)
+    uint16_t buf0[32 * kA3Ld];                   // a1 [128][16] (swizzled), then a3 [32][72]
+    uint16_t buf1[64 * kA2Ld];                   // a2 [64][40]
 };
 
-// B fragments of one layer for column tile ct: [j][ks] (j = 16-column block).
-template <int CIN, int KSTEPS>
-__device__ __forceinline__ void load_wfrags(const uint16_t* __restrict__ wf, int ct,
-                                            bf16x8 (&b)[2][KSTEPS]) {
-    constexpr int K = 5 * CIN;
-    const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int ks = 0; ks < KSTEPS; ++ks) {
-            const int n = ct * 32 + j * 16 + r, k = ks * 32 + q * 8;
-            b[j][ks] = k < K ? *reinterpret_cast<const bf16x8*>(wf + n * K + k) : bf16x8{};
-        }
+struct ConvStackLdsW {
+    uint16_t w2[32 * kW2Ld];
+    uint16_t w3[64 * kW3Ld];
+    uint16_t w4[64 * kW4Ld];
+    float w1[16 * 5];
+    float b1[16];
+    WaveSlice wv[kWP];
+};
+static_assert(128 * kA1Ld <= 32 * kA3Ld, "a1 must fit where a3 goes");
+static_assert(sizeof(ConvStackLdsW) <= 160 * 1024, "LDS budget");
+
+// LDS writes of this wave become visible to its later LDS reads.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int L, int CIN, int ILD, int OLD, int KSTEPS>
-__device__ __forceinline__ void conv_wave_tile(const uint16_t* __restrict__ in,
-                                               const bf16x8 (&b)[2][KSTEPS], int rt, int ct,
-                                               const float* __restrict__ bias,
-                                               uint16_t* __restrict__ out, bool to_global, int nvalid) {
+// One conv layer of one input by one wave: rows x < L, tiles of RB x CB MFMA
+// blocks, as conv_tile (same k order, same epilogue).
+template <int L, int CIN, int ILD, int COUT, int WLD, int OLD, int RB, int CB>
+__device__ __forceinline__ void conv_one(const uint16_t* __restrict__ in, const uint16_t* __restrict__ w,
+                                         const float* __restrict__ bias, uint16_t* __restrict__ out) {
     constexpr int K = 5 * CIN;
+    constexpr int KSTEPS = (K + 31) / 32;
+    constexpr int NRT = L / (16 * RB), NCT = COUT / (16 * CB);
     const int lane = threadIdx.x & 63;
     const int r = lane & 15, q = lane >> 4;
-    f32x4 acc[4][2];
-    for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int t = 0; t < NRT * NCT; ++t) {
+        const int rt = t / NCT, ct = t - rt * NCT;
+        f32x4 acc[RB][CB];
+        for (int i = 0; i < RB; ++i)
+            for (int j = 0; j < CB; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int ks = 0; ks < KSTEPS; ++ks) {
-        const int k = ks * 32 + q * 8;
-        const int dx = k / CIN, ci0 = k - dx * CIN;
-        bf16x8 a[4];
-        for (int i = 0; i < 4; ++i) {
-            const int m = rt * 64 + i * 16 + r;
-            const int f = m / L, x = m - f * L;
-            int pos = x + dx - 2;
-            pos = pos < 0 ? pos + L : (pos >= L ? pos - L : pos);
-            a[i] = k < K ? *reinterpret_cast<const bf16x8*>(in + (f * L + pos) * ILD + ci0) : bf16x8{};
+        for (int ks = 0; ks < KSTEPS; ++ks) {
+            const int k = ks * 32 + q * 8;
+            const int dx = k / CIN, ci0 = k - dx * CIN;
+            bf16x8 a[RB], b[CB];
+            for (int i = 0; i < RB; ++i) {
+                const int x = rt * 16 * RB + i * 16 + r;
+                int pos = x + dx - 2;
+                pos = pos < 0 ? pos + L : (pos >= L ? pos - L : pos);
+                a[i] = k < K ? *reinterpret_cast<const bf16x8*>(in + act_off<ILD>(pos, ci0)) : bf16x8{};
+            }
+            for (int j = 0; j < CB; ++j)
+                b[j] = *reinterpret_cast<const bf16x8*>(w + (ct * 16 * CB + j * 16 + r) * WLD + ks * 32 + q * 8);
+            for (int i = 0; i < RB; ++i)
+                for (int j = 0; j < CB; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         }
-        for (int i = 0; i < 4; ++i)
-            for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j][ks], acc[i][j], 0, 0, 0);
-    }
-    for (int i = 0; i < 4; ++i) {
-        const int m0 = rt * 64 + i * 16 + q * 4;
-        const int f = m0 / L, x0 = m0 - f * L;
-        if (to_global && f >= nvalid) continue;
-        for (int j = 0; j < 2; ++j) {
-            const int n = ct * 32 + j * 16 + r;
-            const float bn = bias[n];
-            for (int h = 0; h < 2; ++h) {
-                const float p0 = acc[i][j][2 * h] + bn, p1 = acc[i][j][2 * h + 1] + bn;
-                const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
-                out[(f * (L / 2) + (x0 >> 1) + h) * OLD + n] = f2bf(r0 >= r1 ? r0 : r1);
+        for (int i = 0; i < RB; ++i) {
+            const int x0 = rt * 16 * RB + i * 16 + q * 4;
+            for (int j = 0; j < CB; ++j) {
+                const int n = ct * 16 * CB + j * 16 + r;
+                const float bn = bias[n];
+                for (int h = 0; h < 2; ++h) {
+                    const float p0 = acc[i][j][2 * h] + bn, p1 = acc[i][j][2 * h + 1] + bn;
+                    const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
+                    out[((x0 >> 1) + h) * OLD + n] = f2bf(r0 >= r1 ? r0 : r1);
+                }
             }
         }
     }
 }
 
-__global__ __launch_bounds__(kRThreads, 1) void k_convstack_bf16_r(
+__global__ __launch_bounds__(kWP * 64, 1) void k_convstack_bf16_w(
     const void* __restrict__ x, int xf32, int B, const float* __restrict__ w1,
     const float* __restrict__ b1, const uint16_t* __restrict__ wf2, const float* __restrict__ b2,
     const uint16_t* __restrict__ wf3, const float* __restrict__ b3,
     const uint16_t* __restrict__ wf4, const float* __restrict__ b4, uint16_t* __restrict__ a4) {
-    __shared__ __attribute__((aligned(16))) ConvStackLdsR sm;
-    const int tid = threadIdx.x, wave = tid >> 6;
-    // conv2: row tiles wave + 4i (one column tile); conv3 / conv4: column tile
-    // wave & 1, row tiles (wave >> 1) + 2i
-    bf16x8 bw2[2][3], bw3[2][5], bw4[2][10];
-    load_wfrags<16, 3>(wf2, 0, bw2);
-    load_wfrags<32, 5>(wf3, wave & 1, bw3);
-    load_wfrags<64, 10>(wf4, wave & 1, bw4);
+    __shared__ __attribute__((aligned(16))) ConvStackLdsW sm;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = tid; i < 32 * kW2Ld; i += kWP * 64) {
+        const int n = i / kW2Ld, k = i - n * kW2Ld;
+        sm.w2[i] = k < 80 ? wf2[n * 80 + k] : (uint16_t)0;
+    }
+    for (int i = tid; i < 64 * kW3Ld; i += kWP * 64) {
+        const int n = i / kW3Ld, k = i - n * kW3Ld;
+        sm.w3[i] = k < 160 ? wf3[n * 160 + k] : (uint16_t)0;
+    }
+    for (int i = tid; i < 64 * kW4Ld; i += kWP * 64) {
+        const int n = i / kW4Ld, k = i - n * kW4Ld;
+        sm.w4[i] = k < 320 ? wf4[n * 320 + k] : (uint16_t)0;
+    }
     if (tid < 80) sm.w1[tid] = w1[tid];
     if (tid < 16) sm.b1[tid] = b1[tid];
-    const int ntiles = (B + kTileF - 1) / kTileF;
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int f0 = tile * kTileF;
-        const int nvalid = min(kTileF, B - f0);
-        // 256 threads x 8 elements = one [8][256] tile
-        for (int h = 0; h < 2; ++h) {
-            const uint2 v = load_x4(x, xf32, f0, nvalid, tid + h * kRThreads);
-            reinterpret_cast<uint2*>(sm.xs)[tid + h * kRThreads] = v;
+    __syncthreads();   // the only block-wide wait: weights staged
+    WaveSlice& ws = sm.wv[wave];
+    const int64_t stride = (int64_t)gridDim.x * kWP;
+    // the wave's inputs: blockIdx * kWP + wave, + stride, ...; the next one's
+    // 8 bytes per lane are loaded while the current one is computed
+    int64_t fi = (int64_t)blockIdx.x * kWP + wave;
+    auto load_in = [&](int64_t f) -> uint2 {
+        if (f >= B) return make_uint2(0u, 0u);
+        const int64_t o = f * 256 + lane * 4;
+        if (xf32) {
+            const float4 v = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(x) + o);
+            return make_uint2((uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16),
+                              (uint32_t)f2bf(v.z) | ((uint32_t)f2bf(v.w) << 16));
         }
-        __syncthreads();
-        for (int pi = tid; pi < kTileF * 128; pi += kRThreads) {
-            const int f = pi >> 7, xp = pi & 127;
+        return *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(x) + o);
+    };
+    uint2 xnext = load_in(fi);
+    for (; fi < B; fi += stride) {
+        reinterpret_cast<uint2*>(ws.xs)[lane] = xnext;
+        xnext = load_in(fi + stride);
+        wave_lds_sync();
+        // conv1: lane = 2 pooled positions, all 16 channels (as k_conv1_fwd)
+        for (int xp = lane; xp < 128; xp += 64) {
             float v[6];
-            for (int d = 0; d < 6; ++d) v[d] = bf2f(sm.xs[f * 256 + ((2 * xp + d - 2) & 255)]);
+            for (int d = 0; d < 6; ++d) v[d] = bf2f(ws.xs[(2 * xp + d - 2) & 255]);
             uint32_t packed[8];
             for (int co = 0; co < 16; ++co) {
                 float p0 = sm.b1[co], p1 = sm.b1[co];
@@ -778,23 +813,18 @@ __global__ __launch_bounds__(kRThreads, 1) void k_convstack_bf16_r(
                 if (co & 1) packed[co >> 1] |= hbits << 16;
                 else packed[co >> 1] = hbits;
             }
-            uint4* dst = reinterpret_cast<uint4*>(sm.buf0 + (f * 128 + xp) * kA1Ld);
-            dst[0] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
-            dst[1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
+            const int sw = (xp >> 3) & 1;     // the a1 swizzle of act_off<16>
+            uint4* dst = reinterpret_cast<uint4*>(ws.buf0 + xp * kA1Ld);
+            dst[sw] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
+            dst[sw ^ 1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
         }
-        __syncthreads();
-        for (int i = 0; i < 4; ++i)
-            conv_wave_tile<128, 16, kA1Ld, kA2Ld, 3>(sm.buf0, bw2, wave + 4 * i, 0, b2, sm.buf1, false,
-                                                     nvalid);
-        __syncthreads();
-        for (int i = 0; i < 4; ++i)
-            conv_wave_tile<64, 32, kA2Ld, kA3Ld, 5>(sm.buf1, bw3, (wave >> 1) + 2 * i, wave & 1, b3,
-                                                    sm.buf0, false, nvalid);
-        __syncthreads();
-        for (int i = 0; i < 2; ++i)
-            conv_wave_tile<32, 64, kA3Ld, 64, 10>(sm.buf0, bw4, (wave >> 1) + 2 * i, wave & 1, b4,
-                                                  a4 + (int64_t)f0 * 1024, true, nvalid);
-        __syncthreads();
+        wave_lds_sync();
+        conv_one<128, 16, kA1Ld, 32, kW2Ld, kA2Ld, 4, 2>(ws.buf0, sm.w2, b2, ws.buf1);
+        wave_lds_sync();
+        conv_one<64, 32, kA2Ld, 64, kW3Ld, kA3Ld, 4, 2>(ws.buf1, sm.w3, b3, ws.buf0);
+        wave_lds_sync();
+        conv_one<32, 64, kA3Ld, 64, kW4Ld, 64, 2, 4>(ws.buf0, sm.w4, b4, a4 + fi * 1024);
+        wave_lds_sync();   // buf0 and xs are reused by the next input
     }
 }
 
@@ -881,68 +911,91 @@ __global__ __launch_bounds__(256) void k_fc_bf16(int M, int K, const uint16_t* _
 }
 
 // The first fully connected layer for bf16 inference (N = 256 outputs): one
-// block of 8 waves computes 256 rows x all 256 columns, so every activation
-// row is read once; waves are 4 x 2, each 64 x 128 (4 x 8 MFMA blocks).
-// K advances in steps of 64 through two LDS stages (rows padded by 8)
-// filled from registers loaded one step ahead. Same MFMA chains and
-// epilogue as k_gemm with EpFcFwd: bit-identical output.
+// block of 8 waves computes 128 rows x all 256 columns (waves 2 x 4, each
+// 64 x 64), so every activation row is read once. K advances in steps of 64
+// through two LDS stages (rows padded by 8); global loads run two steps
+// ahead in two register sets, so a step's loads have two steps of matrix
+// work to arrive. Same MFMA chains and epilogue as k_gemm with EpFcFwd:
+// bit-identical output.
 __global__ __launch_bounds__(512, 1) void k_fc1_bf16(int M, int K, const uint16_t* __restrict__ A,
                                                    const uint16_t* __restrict__ W,
                                                    const float* __restrict__ bias,
                                                    uint16_t* __restrict__ out) {
-    constexpr int BM = 256, BN = 256, NT = 512;
-    constexpr int CH = BM * kFcBK / 8 / NT;       // 16-byte chunks per thread per operand (4)
+    constexpr int BM = 128, BN = 256, NT = 512;
+    constexpr int ACH = BM * kFcBK / 8 / NT;      // 16-byte chunks of A per thread per step (2)
+    constexpr int BCH = BN * kFcBK / 8 / NT;      // ... of W (4)
     __shared__ __attribute__((aligned(16))) uint16_t sa[2][BM * kFcLd];
     __shared__ __attribute__((aligned(16))) uint16_t sb[2][BN * kFcLd];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, q = lane >> 4;
-    const int wm = wave & 3, wn = wave >> 2;
+    const int wm = wave & 1, wn = wave >> 1;
     const int m0 = blockIdx.x * BM;
-    uint4 ra[CH], rb[CH];
-    auto load = [&](int k0) {
-        for (int c = 0; c < CH; ++c) {
+    uint4 ra0[ACH], rb0[BCH], ra1[ACH], rb1[BCH];   // the two register sets
+    auto load = [&](uint4 (&xa)[ACH], uint4 (&xb)[BCH], int k0) {
+#pragma unroll
+        for (int c = 0; c < ACH; ++c) {
             const int idx = tid + c * NT, row = idx >> 3, col = (idx & 7) * 8;
-            ra[c] = (m0 + row < M) ? *reinterpret_cast<const uint4*>(A + (int64_t)(m0 + row) * K + k0 + col)
+            xa[c] = (m0 + row < M) ? *reinterpret_cast<const uint4*>(A + (int64_t)(m0 + row) * K + k0 + col)
                                    : make_uint4(0u, 0u, 0u, 0u);
-            rb[c] = *reinterpret_cast<const uint4*>(W + (int64_t)row * K + k0 + col);
         }
-    };
-    auto store = [&](int buf) {
-        for (int c = 0; c < CH; ++c) {
+#pragma unroll
+        for (int c = 0; c < BCH; ++c) {
             const int idx = tid + c * NT, row = idx >> 3, col = (idx & 7) * 8;
-            *reinterpret_cast<uint4*>(&sa[buf][row * kFcLd + col]) = ra[c];
-            *reinterpret_cast<uint4*>(&sb[buf][row * kFcLd + col]) = rb[c];
+            xb[c] = *reinterpret_cast<const uint4*>(W + (int64_t)row * K + k0 + col);
         }
     };
-    f32x4 acc[4][8];
+    auto store = [&](const uint4 (&xa)[ACH], const uint4 (&xb)[BCH], int buf) {
+#pragma unroll
+        for (int c = 0; c < ACH; ++c) {
+            const int idx = tid + c * NT, row = idx >> 3, col = (idx & 7) * 8;
+            *reinterpret_cast<uint4*>(&sa[buf][row * kFcLd + col]) = xa[c];
+        }
+#pragma unroll
+        for (int c = 0; c < BCH; ++c) {
+            const int idx = tid + c * NT, row = idx >> 3, col = (idx & 7) * 8;
+            *reinterpret_cast<uint4*>(&sb[buf][row * kFcLd + col]) = xb[c];
+        }
+    };
+    f32x4 acc[4][4];
     for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    load(0);
-    store(0);
-    __syncthreads();
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     const int steps = K / kFcBK;
-    for (int st = 0; st < steps; ++st) {
-        const int buf = st & 1;
-        if (st + 1 < steps) load((st + 1) * kFcBK);
+    load(ra0, rb0, 0);
+    store(ra0, rb0, 0);
+    if (steps > 1) load(ra1, rb1, kFcBK);
+    __syncthreads();
+    auto compute = [&](int buf) {
 #pragma unroll
         for (int kk = 0; kk < kFcBK; kk += 32) {
-            bf16x8 a[4], b[8];
+            bf16x8 a[4], b[4];
             for (int i = 0; i < 4; ++i)
                 a[i] = *reinterpret_cast<const bf16x8*>(&sa[buf][(wm * 64 + i * 16 + r) * kFcLd + kk + q * 8]);
-            for (int j = 0; j < 8; ++j)
-                b[j] = *reinterpret_cast<const bf16x8*>(&sb[buf][(wn * 128 + j * 16 + r) * kFcLd + kk + q * 8]);
+            for (int j = 0; j < 4; ++j)
+                b[j] = *reinterpret_cast<const bf16x8*>(&sb[buf][(wn * 64 + j * 16 + r) * kFcLd + kk + q * 8]);
             for (int i = 0; i < 4; ++i)
-                for (int j = 0; j < 8; ++j)
+                for (int j = 0; j < 4; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         }
-        if (st + 1 < steps) {
-            store(buf ^ 1);
+    };
+    // two steps per iteration so each register set and LDS stage is named
+    // statically: even steps read stage 0, odd steps stage 1; step s + 2 is
+    // loaded into the register set step s came through
+    for (int st = 0; st < steps; st += 2) {
+        if (st + 2 < steps) load(ra0, rb0, (st + 2) * kFcBK);
+        compute(0);
+        if (st + 1 >= steps) break;
+        store(ra1, rb1, 1);
+        __syncthreads();
+        if (st + 3 < steps) load(ra1, rb1, (st + 3) * kFcBK);
+        compute(1);
+        if (st + 2 < steps) {
+            store(ra0, rb0, 0);
             __syncthreads();
         }
     }
     for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 8; ++j) {
-            const int n = wn * 128 + j * 16 + r;
+        for (int j = 0; j < 4; ++j) {
+            const int n = wn * 64 + j * 16 + r;
             const float bn = bias[n];
             const int mb = m0 + wm * 64 + i * 16 + q * 4;
             for (int e = 0; e < 4; ++e)
@@ -1249,7 +1302,7 @@ struct gpfc_cnn {
     void* work = nullptr;        // packed weights + activations
     bool packed = false;
     bool fused = true;           // bf16 inference through the fused convolution stack
-    int32_t fused_mode = 1;      // 1: weights in LDS, 2: weights in registers
+    int32_t fused_mode = 1;      // 1: wave-private inputs, 2: tiles of 8 inputs in lockstep
     int32_t n_cu = 256;
     // views into work (element type per prec)
     void *wf2, *wb2, *wf3, *wb3, *wf4, *wb4, *f1f, *f1b, *f2f, *f2b;
@@ -1316,9 +1369,9 @@ int32_t forward(gpfc_cnn* c, const void* x, int xf32, int B, float* logits, cons
                        ((uintptr_t)x & 15) == 0;   // the fused kernel loads 16-byte groups
     if (fused) {
         const int ntiles = (B + kTileF - 1) / kTileF;
-        if (c->fused_mode == 2)
-            hipLaunchKernelGGL(k_convstack_bf16_r, dim3((unsigned)std::min(ntiles, c->n_cu)),
-                               dim3(kRThreads), 0, s, x, xf32, B, w + kConvW[1], w + conv_b(1),
+        if (c->fused_mode == 1)
+            hipLaunchKernelGGL(k_convstack_bf16_w, dim3((unsigned)std::min<int64_t>((B + kWP - 1) / kWP, c->n_cu)),
+                               dim3(kWP * 64), 0, s, x, xf32, B, w + kConvW[1], w + conv_b(1),
                                (const uint16_t*)c->wf2, w + conv_b(2), (const uint16_t*)c->wf3,
                                w + conv_b(3), (const uint16_t*)c->wf4, w + conv_b(4), (uint16_t*)c->a4);
         else
@@ -1339,7 +1392,7 @@ int32_t forward(gpfc_cnn* c, const void* x, int xf32, int B, float* logits, cons
     }
     }
     if (fused) {
-        hipLaunchKernelGGL(k_fc1_bf16, dim3((unsigned)((B + 255) / 256)), dim3(512), 0, s, B, 1024,
+        hipLaunchKernelGGL(k_fc1_bf16, dim3((unsigned)((B + 127) / 128)), dim3(512), 0, s, B, 1024,
                            (const uint16_t*)c->a4, (const uint16_t*)c->f1f, w + F1B, (uint16_t*)c->h1);
         hipLaunchKernelGGL(k_fc_bf16<64>, dim3((unsigned)((B + 127) / 128), 1), dim3(256), 0, s, B, 256,
                            (const uint16_t*)c->h1, (const uint16_t*)c->f2f, w + F2B, (uint16_t*)c->h2,
