@@ -34,7 +34,7 @@ CUS, CLOCK = 256, 2.4e9
 LDS_PEAK_GBS = CUS * 128 * CLOCK / 1e9          # 78,643 GB/s
 LDS_U64_ATOMIC_MEASURED = 6.17e12               # conflict-free ds_add_u64 lane-ops/s (probe)
 VALU_PEAK_LANE_OPS = CUS * 64 * CLOCK           # 3.93e13 lane-ops/s (FP64 and 32-bit ops alike)
-VALU_OPS_PER_UPDATE = 5                         # fma, add, perm, cmp, mov in the gfx950 ISA
+VALU_OPS_PER_UPDATE = 3.5                       # fma, perm, mov_b64, half a max3_u16 (gfx950 ISA)
 BYTES_PER_UPDATE = 8                            # one 64-bit packed (count, sum) LDS increment
 
 

@@ -177,14 +177,17 @@ __device__ __forceinline__ uint32_t fine_bin_ieee(double t, double P) {
     return (uint32_t)fb;
 }
 
-// Per-lane constants of the certified fast path (see k_fold).
+// Per-lane constants of the certified fast path (see fast_lo).
 struct LaneSetup {
     double P;         // the lane's period (1.0 for an invalid lane)
     double rB;        // 256 * RN(1/P), an exact scaling of RN(1/P)
-    double theta;     // -2^-17 - T 2^-16
-    uint32_t lim;     // 65536 - 2T, or 0 when the fast path is off for the lane
+    uint32_t lim;     // 65536 - 2, or 0 when the fast path is off for the lane
     bool valid;
 };
+
+// Added inside the phase FMA: 1.5 * 2^36 - 2^-16, exactly representable (the
+// binade [2^36, 2^37) has spacing 2^-16).
+constexpr double kPhaseC = 0x1.8p36 - 0x1p-16;
 
 __device__ __forceinline__ LaneSetup lane_setup(const double* __restrict__ periods, int64_t kk,
                                                 int64_t k, double tmax) {
@@ -194,13 +197,12 @@ __device__ __forceinline__ LaneSetup lane_setup(const double* __restrict__ perio
     if (!L.valid) P = 1.0;
     L.P = P;
     L.rB = (1.0 / P) * 256.0;
-    // |w - (256 RN(t/P) + theta)| <= 3u zmax + u with u = 2^-53; the bound
-    // below is 2^-50 zmax, < 2^-16 fine bins whenever zmax < 2^34.
+    // |t rB - 256 RN(t/P)| <= 2u zmax (1 + u), u = 2^-53: below 2^-18
+    // whenever zmax = max|t| rB < 2^34, which also keeps t rB + kPhaseC in
+    // the binade of kPhaseC.
     const double zmax = tmax * L.rB;
     const bool fast = zmax < 0x1p34;   // false for NaN / inf
-    const uint32_t T = 1u;
-    L.lim = fast ? 65536u - 2u * T : 0u;
-    L.theta = -0x1p-17 - (double)T * 0x1p-16;
+    L.lim = fast ? 65536u - 2u : 0u;
     return L;
 }
 
@@ -215,22 +217,22 @@ __device__ __forceinline__ LaneSetup lane_setup(const double* __restrict__ perio
 // LDS access hit 32 distinct banks, so every update is one conflict-free
 // ds_add_u64.
 //
-// Fast path, certified: w = fma(t, 256 RN(1/P), theta) is within 2^-16 of
-// 256 RN(t/P) + theta. Adding M = 1.5 * 2^36 rounds w to the grid 2^-16 and
-// leaves round(w * 2^16) in the low 32 bits of the sum: bits [16, 24) are
-// the bin (floor of 256 RN(t/P), mod 256) and bits [0, 16) the fraction
-// shifted down by T = 1 unit. When the fraction field is below 65536 - 2T the
-// bin equals that of the exact IEEE sequence; otherwise (about 3 updates in
-// 65536) the lane recomputes the bin with the IEEE sequence.
+// Fast path, certified: y = fma(t, 256 RN(1/P), kPhaseC) rounds t * rB once,
+// to the 2^-16 grid of kPhaseC's binade, so the low 32 bits of y hold G - 1,
+// G = round(2^16 t rB) (2^52 * 1.5 vanishes mod 2^32): bits [16, 24) are the
+// bin and bits [0, 16) the fraction shifted down by one unit. With z = 256
+// RN(t/P), the IEEE sequence's bin is floor(z) mod 256 and |G 2^-16 - z| <=
+// 2^-17 + 2^-18 < 2^-16; a fraction field below 65534 means G mod 2^16 lies in
+// [1, 65534], so z is strictly inside the unit interval of (G - 1) 2^-16 and
+// the bin field is exact. Otherwise (about 2 updates in 65536) the lane
+// recomputes the bin with the IEEE sequence.
 __device__ __forceinline__ void lds_add(char* hist, uint32_t addr, uint64_t v) {
     __hip_atomic_fetch_add(reinterpret_cast<uint64_t*>(hist + addr), v, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__device__ __forceinline__ uint32_t fast_lo(double ti, const LaneSetup& L) {
-    const double M = 0x1.8p36;
-    const double w = __builtin_fma(ti, L.rB, L.theta);
-    return (uint32_t)__double_as_longlong(w + M);
+__device__ __forceinline__ uint32_t fast_lo(double ti, double rB) {
+    return (uint32_t)__double_as_longlong(__builtin_fma(ti, rB, kPhaseC));
 }
 
 // byte0 <- laneoff.byte0, byte1 <- lo.byte2 (the bin), byte2 <- laneoff.byte2
@@ -238,24 +240,33 @@ __device__ __forceinline__ uint32_t fast_addr(uint32_t lo, uint32_t laneoff) {
     return __builtin_amdgcn_perm(lo, laneoff, 0x0C020600u);
 }
 
-// One update on the fast path; returns the mask of lanes whose bin the fast
-// path could not certify (their contribution went to the fast bin anyway).
-__device__ __forceinline__ uint64_t fold_update(char* hist, double ti, uint64_t ci,
-                                                const LaneSetup& L, uint32_t laneoff) {
-    const uint32_t lo = fast_lo(ti, L);
+// One update on the fast path; returns its low word, whose fraction field the
+// caller checks against the certificate (the contribution goes to the fast
+// bin either way).
+__device__ __forceinline__ uint32_t fold_update(char* hist, double ti, uint64_t ci, double rB,
+                                                uint32_t laneoff) {
+    const uint32_t lo = fast_lo(ti, rB);
     lds_add(hist, fast_addr(lo, laneoff), ci);
-    return __builtin_amdgcn_uicmp(lo & 0xFFFFu, L.lim, 35 /* unsigned >= */);
+    return lo;
+}
+
+// Largest fraction field (low 16 bits) of three words, in the low 16 bits of
+// the result: one v_max3_u16, which the compiler does not form by itself.
+__device__ __forceinline__ uint32_t max3_frac(uint32_t m, uint32_t a, uint32_t b) {
+    uint32_t r;
+    asm("v_max3_u16 %0, %1, %2, %3" : "=v"(r) : "v"(m), "v"(a), "v"(b));
+    return r;
 }
 
 // Rare repair of a block in which some lane failed the certificate: for each
 // such update, take the contribution back out of the fast bin and put it in
 // the bin of the IEEE sequence (integer adds, so this is exact).
-__device__ __noinline__ void fold_repair(char* hist, const Rec* blk, int cnt, LaneSetup L,
+__device__ __forceinline__ void fold_repair(char* hist, const Rec* blk, int cnt, LaneSetup L,
                                          uint32_t laneoff) {
     for (int j = 0; j < cnt; ++j) {
         const double ti = blk[j].t;
         const uint64_t ci = blk[j].c;
-        const uint32_t lo = fast_lo(ti, L);
+        const uint32_t lo = fast_lo(ti, L.rB);
         if ((lo & 0xFFFFu) >= L.lim) {
             lds_add(hist, fast_addr(lo, laneoff), uint64_t(0) - ci);
             lds_add(hist, (fine_bin_ieee(ti, L.P) << 8) | laneoff, ci);
@@ -289,18 +300,24 @@ __device__ __forceinline__ void fold_slice(char* hist, const Rec* __restrict__ r
 #pragma unroll
         for (int j = 0; j < kBlk; ++j) b[j] = p[kBlk + j];
         __builtin_amdgcn_sched_barrier(0);
-        uint64_t fail = 0;
+        uint32_t m = 0;
 #pragma unroll
-        for (int j = 0; j < kBlk; ++j) fail |= fold_update(hist, a[j].t, a[j].c, L, laneoff);
-        if (fail) fold_repair(hist, p, kBlk, L, laneoff);
+        for (int j = 0; j < kBlk; j += 2)
+            m = max3_frac(m, fold_update(hist, a[j].t, a[j].c, L.rB, laneoff),
+                          fold_update(hist, a[j + 1].t, a[j + 1].c, L.rB, laneoff));
+        if (__builtin_amdgcn_uicmp(m & 0xFFFFu, L.lim, 35 /* unsigned >= */))
+            fold_repair(hist, p, kBlk, L, laneoff);
         wait_lgkm();
 #pragma unroll
         for (int j = 0; j < kBlk; ++j) a[j] = p[2 * kBlk + j];
         __builtin_amdgcn_sched_barrier(0);
-        fail = 0;
+        m = 0;
 #pragma unroll
-        for (int j = 0; j < kBlk; ++j) fail |= fold_update(hist, b[j].t, b[j].c, L, laneoff);
-        if (fail) fold_repair(hist, p + kBlk, kBlk, L, laneoff);
+        for (int j = 0; j < kBlk; j += 2)
+            m = max3_frac(m, fold_update(hist, b[j].t, b[j].c, L.rB, laneoff),
+                          fold_update(hist, b[j + 1].t, b[j + 1].c, L.rB, laneoff));
+        if (__builtin_amdgcn_uicmp(m & 0xFFFFu, L.lim, 35 /* unsigned >= */))
+            fold_repair(hist, p + kBlk, kBlk, L, laneoff);
         p += 2 * kBlk;
     }
 }
@@ -385,7 +402,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_fold_f32(
             const double ti = p[i].t;
             const uint64_t ci = p[i].c;
             if (ci == 0) continue;   // padding record
-            const uint32_t lo = fast_lo(ti, L);
+            const uint32_t lo = fast_lo(ti, L.rB);
             uint32_t bin = (lo >> 16) & 255u;
             if ((lo & 0xFFFFu) >= L.lim) bin = fine_bin_ieee(ti, L.P);
             const int j = (int)bin * 32 + lane;
@@ -975,7 +992,6 @@ __global__ __launch_bounds__(kThreads, 1) void k_fold_eqcount(
     const double rB = (1.0 / P) * (double)kMid;
     const double zmax = info->tmax * rB;
     const uint32_t lim = zmax < 0x1p34 ? 65536u - 2u : 0u;
-    const double theta = -0x1p-17 - 0x1p-16;
     __syncthreads();
     uint64_t* h = hist + pw * kMid;
     const int64_t per_q = (nrec + 3) / 4;
@@ -983,8 +999,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_fold_eqcount(
     if (valid) {
         for (int64_t i = i0 + lane; i < i1; i += 64) {
             const Rec r = rec[i];
-            const double w = __builtin_fma(r.t, rB, theta);
-            const uint32_t lo = (uint32_t)__double_as_longlong(w + 0x1.8p36);
+            const uint32_t lo = fast_lo(r.t, rB);   // the certified path, at 4096 bins
             uint32_t b = (lo >> 16) & (kMid - 1);
             if ((lo & 0xFFFFu) >= lim) b = mid_bin_ieee(r.t, P);
             __hip_atomic_fetch_add(h + b, r.c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
