@@ -446,7 +446,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_fold_f32(
 // Slot (row r, period lane j) of the prefix table that replaces the
 // histogram in place: inclusive prefixes over rows of the count (float,
 // exact below 2^24) and of n times the flux-deviation sum (float).
-struct Slot {
+struct alignas(8) Slot {
     float c;
     float dn;
 };
@@ -475,41 +475,49 @@ __device__ __forceinline__ Slot coarse_prefix(const char* tab, int b, int g, int
     return slot_at(tab, b * g - 1, lane);
 }
 
-// Value of the box (s, w); the three cases use exactly the expressions of
-// scan_width, so equal boxes give bit-identical values.
-template <bool kChecked>
-__device__ __forceinline__ float box_at(const char* tab, int s, int w, int nb, int g, int lane,
-                                        float nf, float Sf, Slot tot) {
+// Largest box value of width w over the circular starts [s0, s1) of one row.
+// Starts whose box wraps past the last bin add the row total to the end
+// prefix; start 0 takes the end prefix alone. kG1: one fine row per coarse
+// bin (g = 1), so consecutive starts are consecutive rows and the slot
+// addresses of an unrolled step differ by constants.
+template <bool kChecked, bool kG1>
+__device__ float scan_range(const char* tab, int w, int s0, int s1, int nb, int g_rt, int lane,
+                            float nf, float Sf, Slot tot) {
+    const int g = kG1 ? 1 : g_rt;
+    float best = 0.0f;
+    int s = s0;
     if (s == 0) {
         const Slot e = coarse_prefix(tab, w, g, lane);
-        return box_value<kChecked>(e.c, e.dn, nf, Sf);
-    }
-    const Slot a = slot_at(tab, s * g - 1, lane);
-    if (s + w <= nb) {
-        const Slot e = slot_at(tab, (s + w) * g - 1, lane);
-        return box_value<kChecked>(e.c - a.c, e.dn - a.dn, nf, Sf);
-    }
-    const Slot e = slot_at(tab, (s + w - nb) * g - 1, lane);
-    return box_value<kChecked>((e.c + tot.c) - a.c, (e.dn + tot.dn) - a.dn, nf, Sf);
-}
-
-// Largest box value of width w over all circular starts of one row.
-template <bool kChecked>
-__device__ float scan_width(const char* tab, int w, int nb, int g, int lane, float nf, float Sf,
-                            Slot tot) {
-    float best = 0.0f;
-    {
-        const Slot e = coarse_prefix(tab, w, g, lane);
         best = fmaxf(best, box_value<kChecked>(e.c, e.dn, nf, Sf));
+        s = 1;
+    }
+    const int m1 = min(s1, nb - w + 1);   // boxes that end inside the row: s + w <= nb
+    if (kG1) {
+        const char* pa = tab + hist_off(s - 1, lane);
+        const char* pe = pa + w * 256;
+#pragma unroll 4
+        for (; s < m1; ++s, pa += 256, pe += 256) {
+            const Slot a = *reinterpret_cast<const Slot*>(pa);
+            const Slot e = *reinterpret_cast<const Slot*>(pe);
+            best = fmaxf(best, box_value<kChecked>(e.c - a.c, e.dn - a.dn, nf, Sf));
+        }
+        pe -= nb * 256;
+#pragma unroll 4
+        for (; s < s1; ++s, pa += 256, pe += 256) {
+            const Slot a = *reinterpret_cast<const Slot*>(pa);
+            const Slot e = *reinterpret_cast<const Slot*>(pe);
+            best = fmaxf(best, box_value<kChecked>((e.c + tot.c) - a.c, (e.dn + tot.dn) - a.dn, nf, Sf));
+        }
+        return best;
     }
 #pragma unroll 4
-    for (int s = 1; s + w <= nb; ++s) {
+    for (; s < m1; ++s) {
         const Slot a = slot_at(tab, s * g - 1, lane);
         const Slot e = slot_at(tab, (s + w) * g - 1, lane);
         best = fmaxf(best, box_value<kChecked>(e.c - a.c, e.dn - a.dn, nf, Sf));
     }
 #pragma unroll 4
-    for (int s = nb - w + 1; s < nb; ++s) {
+    for (; s < s1; ++s) {
         const Slot a = slot_at(tab, s * g - 1, lane);
         const Slot e = slot_at(tab, (s + w - nb) * g - 1, lane);
         best = fmaxf(best, box_value<kChecked>((e.c + tot.c) - a.c, (e.dn + tot.dn) - a.dn, nf, Sf));
@@ -528,13 +536,16 @@ struct ScoreShared {
 };
 
 // Shared tail of the fused and the materialised scorer. The prefix table of
-// the block's 64 periods is in `tab`, per-period totals in sh. Each wave scans
-// one width for all 64 periods. A period whose samples fill more coarse bins
-// than the widest box can hold is scanned without per-box checks (no box can
-// be full; an empty box gives NaN, which the max skips); the others use the
-// checked form. Then every wave looks for the first start of the winning
-// width in its own range of starts, and wave 0 takes the smallest and
-// evaluates the box in FP64.
+// the block's 64 periods is in `tab`, per-period totals in sh. The (width,
+// start) boxes are cut into 16 equal runs of consecutive starts, one per
+// wave, each covering at most two widths; a wave's run maximum of a width is
+// merged into that width's maximum by an integer max of the bit patterns
+// (exact: every value is >= +0). A period whose samples fill more coarse
+// bins than the widest box can hold is scanned without per-box checks (no
+// box can be full; an empty box gives NaN, which the max skips); the others
+// use the checked form. Then every wave evaluates the winning width at its
+// own range of starts and keeps the first start whose value equals the
+// maximum, and wave 0 takes the smallest and evaluates the box in FP64.
 __device__ void score_table(const char* tab, int nb, int g, const Widths& W, ScoreShared& sh,
                             double sigma, bool valid, int64_t kk, int64_t k, int lane, int wave,
                             float* snr, int32_t* start, int32_t* width, float* depth) {
@@ -542,17 +553,37 @@ __device__ void score_table(const char* tab, int nb, int g, const Widths& W, Sco
     const float Sf = (float)sh.Srow[lane];
     const Slot tot = coarse_prefix(tab, nb, g, lane);
     const bool ok_sigma = sigma > 0.0 && isfinite(sigma);
-    int wmax = 0;
+    int wmax = 0, nact = 0;
     for (int wi = 0; wi < W.n; ++wi)
-        if (W.w[wi] < nb) wmax = max(wmax, W.w[wi]);
+        if (W.w[wi] < nb) { wmax = max(wmax, W.w[wi]); ++nact; }
     const bool fast = g <= kRowsPerWave && sh.nz[lane] > wmax;
-    if (wave < W.n) {
-        const int w = W.w[wave];
-        float b = 0.0f;
-        if (w < nb && ok_sigma)
-            b = fast ? scan_width<false>(tab, w, nb, g, lane, nf, Sf, tot)
-                     : scan_width<true>(tab, w, nb, g, lane, nf, Sf, tot);
-        sh.bestv[wave * 64 + lane] = b;
+    uint32_t* bestu = reinterpret_cast<uint32_t*>(sh.bestv);
+    for (int i = threadIdx.x; i < kMaxWidths * 64; i += kThreads) bestu[i] = 0u;
+    __syncthreads();
+    if (ok_sigma) {
+        // runs of E consecutive boxes in width-major order over the widths < nb
+        const int log2nb = 31 - __builtin_clz(nb);
+        const int total = nact << log2nb;
+        const int E = (total + kWaves - 1) / kWaves;
+        int idx = wave * E;
+        const int hi = min(total, idx + E);
+        while (idx < hi) {
+            const int ai = idx >> log2nb, s0 = idx & (nb - 1);
+            const int s1 = min(nb, s0 + (hi - idx));
+            int wi = -1;   // the ai-th width below nb
+            for (int j = 0, c = 0; j < W.n; ++j)
+                if (W.w[j] < nb) { if (c == ai) wi = j; ++c; }
+            const int w = W.w[wi];
+            float b;
+            if (g == 1)
+                b = fast ? scan_range<false, true>(tab, w, s0, s1, nb, g, lane, nf, Sf, tot)
+                         : scan_range<true, true>(tab, w, s0, s1, nb, g, lane, nf, Sf, tot);
+            else
+                b = fast ? scan_range<false, false>(tab, w, s0, s1, nb, g, lane, nf, Sf, tot)
+                         : scan_range<true, false>(tab, w, s0, s1, nb, g, lane, nf, Sf, tot);
+            if (b > 0.0f) atomicMax(&bestu[wi * 64 + lane], __float_as_uint(b));
+            idx += s1 - s0;
+        }
     }
     __syncthreads();
     float best = 0.0f;
@@ -561,15 +592,27 @@ __device__ void score_table(const char* tab, int nb, int g, const Widths& W, Sco
         const float v = sh.bestv[wi * 64 + lane];
         if (v > best) { best = v; bwi = wi; }
     }
+    // first start of the winning width with the maximum value: the boxes of
+    // this wave's starts are evaluated with the scan's expressions (same
+    // bits), their slots loaded together
     int first = 0x7fffffff;
     if (bwi >= 0) {
         const int w = W.w[bwi];
-        const int per = (nb + kWaves - 1) / kWaves;
-        const int s1 = min(nb, (wave + 1) * per);
-        for (int s = wave * per; s < s1; ++s) {
-            const float v = fast ? box_at<false>(tab, s, w, nb, g, lane, nf, Sf, tot)
-                                 : box_at<true>(tab, s, w, nb, g, lane, nf, Sf, tot);
-            if (v == best) { first = s; break; }
+        const int per = (nb + kWaves - 1) / kWaves;   // <= 16
+        const int sb = wave * per;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int st = sb + j;
+            if (j < per && st < nb) {
+                const Slot a = st ? slot_at(tab, st * g - 1, lane) : Slot{0.0f, 0.0f};
+                const bool wrap = st + w > nb;
+                const Slot e = slot_at(tab, (wrap ? st + w - nb : st + w) * g - 1, lane);
+                const float ec = wrap ? e.c + tot.c : e.c;
+                const float ed = wrap ? e.dn + tot.dn : e.dn;
+                const float v = fast ? box_value<false>(ec - a.c, ed - a.dn, nf, Sf)
+                                     : box_value<true>(ec - a.c, ed - a.dn, nf, Sf);
+                if (v == best) first = min(first, st);
+            }
         }
     }
     sh.first[wave * 64 + lane] = first;
@@ -672,8 +715,9 @@ __device__ void score_body(char* hist, uint64_t* chunk, ScoreShared& sh,
     double dall;
     decode(all, qs, call, dall);
     const float nf = L.valid ? (float)call : 0.0f;
-    // Convert to the float prefix table, count non-empty coarse bins and sum
-    // the bin means (coarse bins of g <= 16 rows never straddle two waves).
+    // Convert to the float prefix table, count non-empty coarse bins and (for
+    // the normalised folds) sum the bin means (coarse bins of g <= 16 rows
+    // never straddle two waves).
     const int g = 1 << log2g;
     uint32_t cprev = (uint32_t)(off >> kCountShift);
     double dprev;
@@ -691,10 +735,12 @@ __device__ void score_body(char* hist, uint64_t* chunk, ScoreShared& sh,
         decode(v, qs, c, d);
         if (((r + 1) & (g - 1)) == 0) {
             if (c > cprev) {
-                const float m = (float)((d - dprev) / (double)(c - cprev));
                 ++nzl;
-                zs += m;
-                zq += m * m;
+                if (zfold) {   // bin-mean moments, for the normalised folds only
+                    const float m = (float)((d - dprev) / (double)(c - cprev));
+                    zs += m;
+                    zq += m * m;
+                }
             }
             cprev = c;
             dprev = d;
