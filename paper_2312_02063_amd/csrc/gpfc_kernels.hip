@@ -274,11 +274,11 @@ __device__ __forceinline__ void fold_repair(char* hist, const Rec* blk, int cnt,
     }
 }
 
-// A wave's slice is a whole number of double blocks of kBlk records. Records
-// come in through scalar loads; block B is requested before block A is
-// processed and A's successor before B is processed, so each wait (which also
-// covers the LDS atomics already issued) sits kBlk updates after its request.
-// The request past the slice end stays inside the padded record array.
+// Records come in through scalar loads, kBlk per request, two requests per
+// chunk of 2 kBlk: the second half of a chunk is requested before the first
+// is processed and the next chunk's first half before the second is
+// processed, so each wait (which also covers the LDS atomics already issued)
+// sits kBlk updates after its request.
 constexpr int kBlk = 8;
 
 // Wait for every outstanding scalar load and LDS operation, and keep the
@@ -289,13 +289,39 @@ __device__ __forceinline__ void wait_lgkm() {
     __builtin_amdgcn_sched_barrier(0);
 }
 
-__device__ __forceinline__ void fold_slice(char* hist, const Rec* __restrict__ rec, int64_t i0,
-                                           int64_t nblk2, const LaneSetup& L, uint32_t laneoff) {
-    const Rec* p = rec + i0;
+// Fold a block's records with the chunks handed out dynamically: each wave
+// takes the next chunk index from a counter in LDS (one lane's atomic, read
+// after the next wait), so waves that the LDS arbiter serves less often
+// take fewer chunks and all finish together; with fixed equal slices the
+// last-served waves ran alone for a fifth of the fold. The sums are
+// integers, so the order of the updates does not change them. Chunk c lies
+// at rec + (c / cps) * stride + (c % cps) * 2 kBlk (cps chunks per segment,
+// segments `stride` records apart), or at rec + c * 2 kBlk when kContig.
+template <bool kContig>
+__device__ __forceinline__ void fold_chunks(char* hist, uint32_t* ctr, const Rec* __restrict__ rec,
+                                            int64_t nch, int64_t cps, int64_t stride,
+                                            const LaneSetup& L, uint32_t laneoff, int lane) {
+    auto at = [&](int64_t c) -> const Rec* {
+        if (kContig) return rec + c * (2 * kBlk);
+        const int64_t sg = c / cps;
+        return rec + sg * stride + (c - sg * cps) * (2 * kBlk);
+    };
+    // ds_inc_rtn (an increment that wraps at 2^32 - 1): unlike an add, the
+    // compiler does not rewrite it into a wave-level pattern that waits for
+    // the returned value at once
+    auto grab = [&]() -> uint32_t {
+        uint32_t v = 0;
+        if (lane == 0) v = atomicInc(ctr, 0xFFFFFFFFu);
+        return v;
+    };
+    int64_t c = (int64_t)__builtin_amdgcn_readfirstlane(grab());
+    if (c >= nch) return;
+    const Rec* p = at(c);
     Rec a[kBlk], b[kBlk];
 #pragma unroll
     for (int j = 0; j < kBlk; ++j) a[j] = p[j];
-    for (int64_t it = 0; it < nblk2; ++it) {
+    uint32_t vn = grab();
+    for (;;) {
         wait_lgkm();
 #pragma unroll
         for (int j = 0; j < kBlk; ++j) b[j] = p[kBlk + j];
@@ -307,9 +333,15 @@ __device__ __forceinline__ void fold_slice(char* hist, const Rec* __restrict__ r
                           fold_update(hist, a[j + 1].t, a[j + 1].c, L.rB, laneoff));
         if (__builtin_amdgcn_uicmp(m & 0xFFFFu, L.lim, 35 /* unsigned >= */))
             fold_repair(hist, p, kBlk, L, laneoff);
+        const int64_t cn = (int64_t)__builtin_amdgcn_readfirstlane(vn);
+        const bool more = cn < nch;
+        const Rec* pn = more ? at(cn) : p;
         wait_lgkm();
+        if (more) {
 #pragma unroll
-        for (int j = 0; j < kBlk; ++j) a[j] = p[2 * kBlk + j];
+            for (int j = 0; j < kBlk; ++j) a[j] = pn[j];
+            vn = grab();
+        }
         __builtin_amdgcn_sched_barrier(0);
         m = 0;
 #pragma unroll
@@ -318,7 +350,8 @@ __device__ __forceinline__ void fold_slice(char* hist, const Rec* __restrict__ r
                           fold_update(hist, b[j + 1].t, b[j + 1].c, L.rB, laneoff));
         if (__builtin_amdgcn_uicmp(m & 0xFFFFu, L.lim, 35 /* unsigned >= */))
             fold_repair(hist, p + kBlk, kBlk, L, laneoff);
-        p += 2 * kBlk;
+        if (!more) break;
+        p = pn;
     }
 }
 
@@ -332,13 +365,17 @@ __device__ __forceinline__ void decode(uint64_t v, double qscale, uint32_t& cnt,
     dev = (double)sq * qscale;
 }
 
+// The block's histogram of its 64 periods over all kWaves * per records.
 __device__ __forceinline__ void fold_block(char* hist, const Rec* __restrict__ rec, int64_t per,
                                            const LaneSetup& L, int lane, int wave) {
+    __shared__ uint32_t ctr;
     uint64_t* h64 = reinterpret_cast<uint64_t*>(hist);
     for (int i = threadIdx.x; i < kFineBins * 64; i += kThreads) h64[i] = 0;
+    if (threadIdx.x == 0) ctr = 0u;
     __syncthreads();
     const uint32_t laneoff = (uint32_t)((lane & 31) * 8 + (lane >> 5) * kHalfBytes);
-    fold_slice(hist, rec, (int64_t)wave * per, per / (2 * kBlk), L, laneoff);
+    const int64_t nch = per * kWaves / (2 * kBlk);
+    fold_chunks<true>(hist, &ctr, rec, nch, nch, 0, L, laneoff, lane);
     __syncthreads();
 }
 
@@ -822,6 +859,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_fold_score_split(
     __shared__ uint64_t chunk[kWaves * 64];
     __shared__ ScoreShared sh;
     __shared__ int32_t is_last;
+    __shared__ uint32_t ctr;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tile = blockIdx.x;
@@ -829,12 +867,14 @@ __global__ __launch_bounds__(kThreads, 1) void k_fold_score_split(
     const LaneSetup L = lane_setup(periods, kk, k, info->tmax);
     uint64_t* h64 = reinterpret_cast<uint64_t*>(hist);
     for (int i = threadIdx.x; i < kFineBins * 64; i += kThreads) h64[i] = 0;
+    if (threadIdx.x == 0) ctr = 0u;
     __syncthreads();
+    // part y of the records: [b0, b0 + len) of each of the kWaves segments
     const int64_t b0 = (int64_t)blockIdx.y * per_s;
     const int64_t len = b0 < per ? min(per_s, per - b0) : 0;   // a multiple of 2 kBlk
     const uint32_t laneoff = (uint32_t)((lane & 31) * 8 + (lane >> 5) * kHalfBytes);
-    // an empty part reads nothing (its first prefetch would lie past the records)
-    if (len > 0) fold_slice(hist, rec, (int64_t)wave * per + b0, len / (2 * kBlk), L, laneoff);
+    const int64_t cps = len / (2 * kBlk);
+    if (cps > 0) fold_chunks<false>(hist, &ctr, rec + b0, cps * kWaves, cps, per, L, laneoff, lane);
     __syncthreads();
     unsigned long long* g = gh + (int64_t)tile * (kFineBins * 64);
     for (int i = threadIdx.x; i < kFineBins * 64; i += kThreads) {
