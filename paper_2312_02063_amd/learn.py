@@ -12,7 +12,15 @@ over the whole trial grid and compares, at a 1% false-positive rate, the
 recall of the best CNN score per curve with that of the best box-SNR per curve
 (the box statistic is also the fallback scorer when no network is given).
 
+The paper's own training set is also available (``--data direct``, Sec. 2.7):
+vectors of length 256 made directly, noise plus a trapezoid at SNR 6-10 for
+positives, pure noise and weak dips labelled by the SNR cut-off 5 for
+negatives. ``--auc-vs-periods`` repeats the evaluation over several trial-grid
+sizes (Sec. 3.2: detection quality against the number of trial periods).
+
     python -m paper_2312_02063_amd.learn --train 200000 --eval 10000 --epochs 4
+    python -m paper_2312_02063_amd.learn --data direct --train 1000000 --eval 2000 \
+        --auc-vs-periods 100,1000,10000
 """
 from __future__ import annotations
 
@@ -86,6 +94,36 @@ def make_training_set(plan, n_pos: int, n_neg: int, seed: int, periods: np.ndarr
                 lab[alpha < snr_cut] = 0.0
             ys.append(torch.tensor(lab, dtype=torch.float32, device=z.device))
             alphas.append(alpha)
+            done += m
+    return torch.cat(zs), torch.cat(ys), np.concatenate(alphas)
+
+
+def make_direct_set(n_pos: int, n_neg: int, seed: int, snr_cut: float = 5.0,
+                    weak_range: tuple = (1.0, 5.0), chunk: int = 100000, device="cuda"):
+    """Training vectors made directly rather than folded (Sec. 2.7): positives
+    are noise plus a trapezoid at SNR 6-10; negatives are half pure noise and
+    half noise plus a weak trapezoid (SNR in ``weak_range``), labelled by the
+    SNR cut (at or above: 1, below: 0). Each vector is z-scored over its bins
+    (ddof 0), as the fold kernel normalises folds, and kept as bf16 bits.
+    Returns (z uint16 [N, 256], labels f32 [N], alpha [N])."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(seed))
+    zs, ys, alphas = [], [], []
+    parts = ((n_pos, True, (6.0, 10.0)), (n_neg - n_neg // 2, False, (0.0, 0.0)),
+             (n_neg // 2, True, weak_range))
+    for count, transit, arange_ in parts:
+        done = 0
+        while done < count:
+            m = min(chunk, count - done)
+            v, a = synth.direct_folds(rng, m, arange_, transit=transit, nbins=NBINS)
+            x = torch.tensor(v, device=device)
+            mu = x.mean(dim=1, keepdim=True)
+            sd = x.std(dim=1, unbiased=False, keepdim=True)
+            z = torch.where(sd > 0, (x - mu) / sd, torch.zeros_like(x))
+            zs.append(z.to(torch.bfloat16).view(torch.uint16))
+            lab = (a >= snr_cut).astype(np.float32) if transit else np.zeros(m, np.float32)
+            ys.append(torch.tensor(lab, device=device))
+            alphas.append(a)
             done += m
     return torch.cat(zs), torch.cat(ys), np.concatenate(alphas)
 
@@ -192,6 +230,24 @@ def evaluate(plan, net, n_pos: int, n_neg: int, seed: int, periods: np.ndarray, 
     return {key: np.concatenate(v) for key, v in out.items()}
 
 
+def auc_vs_periods(plan, net, ks, n_eval: int, seed: int = 1013, log=None):
+    """Detection quality as the trial grid grows (Sec. 3.2): for each grid
+    size k, the same held-out curves are folded over k periods and judged by
+    their best CNN score and best box-SNR; more periods give noise more
+    chances to look like a transit."""
+    rows = []
+    for k in ks:
+        ev = evaluate(plan, net, n_eval, n_eval, seed=seed, periods=grid(int(k)))
+        sm = summarize(ev)
+        rows.append({"periods": int(k),
+                     "cnn_auc": sm["cnn"]["auc"], "box_auc": sm["box"]["auc"],
+                     "cnn_recall_at_1pct_fpr": sm["cnn"]["recall_at_1pct_fpr"],
+                     "box_recall_at_1pct_fpr": sm["box"]["recall_at_1pct_fpr"]})
+        if log:
+            log(f"periods {k}: " + json.dumps(rows[-1]))
+    return rows
+
+
 def recall_at_fpr(stat, label, fpr=0.01):
     """Recall at the threshold that lets through at most `fpr` of the negatives."""
     neg = np.sort(stat[label == 0])
@@ -247,6 +303,11 @@ def main():
     ap.add_argument("--hard-curves", type=int, default=20000, help="no-transit curves mined per round")
     ap.add_argument("--hard-per-curve", type=int, default=4, help="best-scoring folds kept per curve")
     ap.add_argument("--hard-epochs", type=int, default=2, help="epochs after each mining round")
+    ap.add_argument("--data", choices=("folds", "direct"), default="folds",
+                    help="training set: kernel folds of synthetic curves, or vectors made directly "
+                         "(noise + trapezoid at SNR 6-10, weak-transit and pure-noise negatives, cut 5)")
+    ap.add_argument("--auc-vs-periods", type=str, default="",
+                    help="comma-separated grid sizes: AUC of CNN and box-SNR per size (--eval curves)")
     args = ap.parse_args()
     import torch
 
@@ -256,8 +317,12 @@ def main():
     periods = grid(args.periods)
     plan = Plan(0)
     t0 = time.time()
-    z, y, _ = make_training_set(plan, args.train, args.train, seed=1003, periods=periods,
-                                snr_cut=args.snr_cut)
+    if args.data == "direct":
+        z, y, _ = make_direct_set(args.train, args.train, seed=1003,
+                                  snr_cut=args.snr_cut if args.snr_cut > 0 else 5.0)
+    else:
+        z, y, _ = make_training_set(plan, args.train, args.train, seed=1003, periods=periods,
+                                    snr_cut=args.snr_cut)
     torch.cuda.synchronize()
     log(f"training folds {tuple(z.shape)} in {time.time() - t0:.1f} s")
     net = Cnn(0, CNN_BF16, max_batch=65536)
@@ -283,7 +348,10 @@ def main():
     ev = evaluate(plan, net, args.eval, args.eval, seed=1013, periods=periods, log=None)
     eval_s = time.time() - t2
     res = summarize(ev)
-    res.update({"snr_cut": args.snr_cut, "hard_rounds": args.hard_rounds,
+    if args.auc_vs_periods:
+        ks = [int(x) for x in args.auc_vs_periods.split(",") if x]
+        res["auc_vs_periods"] = auc_vs_periods(plan, net, ks, args.eval, log=log)
+    res.update({"data": args.data, "snr_cut": args.snr_cut, "hard_rounds": args.hard_rounds,
                 "train_curves": 2 * args.train, "eval_curves": 2 * args.eval, "epochs": args.epochs,
                 "loss_per_epoch": hist, "train_seconds": train_s, "eval_seconds": eval_s,
                 "periods": args.periods, "folds_scored": 2 * args.eval * args.periods})

@@ -207,6 +207,36 @@ def training_curve(rng: np.random.Generator, n: int = 4000, positive: bool = Tru
     return Curve(t, f.astype(np.float32), truth)
 
 
+def direct_folds(rng: np.random.Generator, m: int, alpha_range: tuple = (6.0, 10.0),
+                 transit: bool = True, nbins: int = 256, pmin: float = 0.2, pmax: float = 1.0,
+                 dur_h: tuple = (0.5, 3.0)):
+    """Folded curves made directly as length-``nbins`` vectors (Sec. 2.7):
+    one unit of Gaussian noise per bin and, when ``transit``, a trapezoid dip
+    of SNR alpha ~ U(alpha_range). The dip's width at half depth is the
+    phase fraction q = duration / P (P log-uniform [pmin, pmax], duration
+    U(dur_h) hours, q at most 1/2), its depth alpha / sqrt(nbins q) (Eq. 2 with
+    one noise unit per bin and nbins q bins in transit), its base ratio
+    r ~ U(0, 1) and its centre uniform in phase; the profile is evaluated at
+    the bin centres. Returns (vectors f32 [m, nbins], alpha [m])."""
+    v = rng.standard_normal((m, nbins))
+    alpha = np.zeros(m)
+    if transit and m:
+        per = np.exp(rng.uniform(np.log(pmin), np.log(pmax), m))
+        q = np.minimum(rng.uniform(dur_h[0], dur_h[1], m) / 24.0 / per, 0.5)
+        alpha = rng.uniform(alpha_range[0], alpha_range[1], m)
+        depth = alpha / np.sqrt(nbins * q)
+        r = rng.uniform(0.0, 1.0, m)
+        centre = rng.uniform(0.0, 1.0, m)
+        x = (np.arange(nbins) + 0.5) / nbins
+        dist = np.abs(np.mod(x[None, :] - centre[:, None] + 0.5, 1.0) - 0.5)
+        long_b = (2.0 * q / (1.0 + r))[:, None]
+        short_b = r[:, None] * long_b
+        ramp = depth[:, None] * (0.5 * long_b - dist) / np.maximum(0.5 * (long_b - short_b), 1e-300)
+        prof = np.where(dist <= 0.5 * short_b, depth[:, None], np.where(dist < 0.5 * long_b, ramp, 0.0))
+        v = v - prof
+    return v.astype(np.float32), alpha
+
+
 # Learned-scorer parameter layout (canonical): per conv block l weight
 # [Cout][Cin][5] then bias; fc weights [out][in] then bias.
 CNN_LAYERS = [("conv", 1, 16), ("conv", 16, 32), ("conv", 32, 64), ("conv", 64, 64),
