@@ -37,6 +37,7 @@ extern "C" {
 #define GPFC_ERANGE (-3)   /* n > GPFC_MAX_SAMPLES or k too large for the grid */
 #define GPFC_ENOMEM (-4)   /* device workspace allocation failed */
 #define GPFC_EDEVICE (-5)  /* a HIP call failed; gpfc_last_error() has the text */
+#define GPFC_EIO (-6)      /* a network file could not be written, read, or is not one */
 
 #define GPFC_MAX_SAMPLES 262143   /* 2^18 - 1: limit of the packed 64-bit bin counter */
 #define GPFC_MAX_NBINS 256
@@ -300,6 +301,18 @@ int32_t gpfc_cnn_set_params(gpfc_cnn *cnn, const float *params, void *stream);
 int32_t gpfc_cnn_get_params(gpfc_cnn *cnn, float *out, void *stream);
 
 /*
+ * Write the parameters to a file at host path `path` (an 8-byte tag
+ * "GPFCCNN1", the int64 parameter count, then the FP32 parameters in the
+ * canonical order, little-endian), or read such a file back (as
+ * gpfc_cnn_set_params: resets the Adam state). Both wait for `stream`.
+ * GPFC_EIO when the file cannot be written or read, or is not a network file
+ * of this architecture (wrong tag, count or length); the network is then
+ * unchanged.
+ */
+int32_t gpfc_cnn_save(gpfc_cnn *cnn, const char *path, void *stream);
+int32_t gpfc_cnn_load(gpfc_cnn *cnn, const char *path, void *stream);
+
+/*
  * Inference path of a bf16 network: on = 1 (the default), the four
  * convolution blocks run as one fused kernel (8 waves per compute unit) that
  * keeps the convolution weights in LDS and every activation in a wave's own
@@ -338,6 +351,12 @@ int32_t gpfc_cnn_forward_fp8(gpfc_cnn *cnn, const void *x, int32_t x_f32, int64_
 /* One bias-corrected Adam step on the FP32 masters with the last gradient
  * (the step count lives on the device; gpfc_cnn_set_params resets it). */
 int32_t gpfc_cnn_adam(gpfc_cnn *cnn, float lr, float beta1, float beta2, float eps, void *stream);
+
+/* One training step: gpfc_cnn_backward on x[B][256] and labels[B] (mean
+ * loss to loss_out, f32[1], when not NULL), then gpfc_cnn_adam. */
+int32_t gpfc_cnn_train_step(gpfc_cnn *cnn, const void *x, int32_t x_f32, const float *labels,
+                            int64_t B, float lr, float beta1, float beta2, float eps,
+                            float *loss_out, void *stream);
 
 /*
  * A whole training step (gpfc_cnn_backward then gpfc_cnn_adam) recorded

@@ -14,7 +14,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgpfc.so")
 
-OK, EINVAL, ENOTSUP, ERANGE, ENOMEM, EDEVICE = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOTSUP, ERANGE, ENOMEM, EDEVICE, EIO = 0, -1, -2, -3, -4, -5, -6
 MAX_SAMPLES = 262143
 MAX_NBINS = 256
 MAX_WIDTHS = 16
@@ -109,6 +109,10 @@ def load():
         "gpfc_cnn_train_capture": ([vp, vp, i32, vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                     ctypes.c_float, vp, vp], i32),
         "gpfc_cnn_train_replay": ([vp, vp], i32),
+        "gpfc_cnn_train_step": ([vp, vp, i32, vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float, vp, vp], i32),
+        "gpfc_cnn_save": ([vp, ctypes.c_char_p, vp], i32),
+        "gpfc_cnn_load": ([vp, ctypes.c_char_p, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -132,7 +136,7 @@ def exported_symbols():
             "gpfc_cnn_forward_fp8", "gpfc_cnn_set_fused", "gpfc_cnn_train_capture",
             "gpfc_cnn_train_replay", "gpfc_topk", "gpfc_plan_set_split",
             "gpfc_autotune", "gpfc_fold_eqcount_prepared", "gpfc_periodogram_peaks", "gpfc_survey_setup", "gpfc_survey_run",
-            "gpfc_survey_capture"]
+            "gpfc_survey_capture", "gpfc_cnn_train_step", "gpfc_cnn_save", "gpfc_cnn_load"]
 
 
 def _check(rc, what):
@@ -634,7 +638,22 @@ class Cnn:
         _check(self.lib.gpfc_cnn_train_replay(self.h, _stream()), "gpfc_cnn_train_replay")
         return self._train_loss
 
-    def train_step(self, x, labels, lr: float):
-        loss = self.backward(x, labels)
-        self.adam(lr)
-        return loss
+    def train_step(self, x, labels, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                   eps: float = 1e-8):
+        """Backward then Adam in one call; returns the device loss buffer."""
+        import torch
+        xf = self._x(x)
+        _need(x, x.dtype, "x", self.device)
+        _need(labels, torch.float32, "labels", self.device)
+        _check(self.lib.gpfc_cnn_train_step(self.h, _ptr(x), xf, _ptr(labels), x.shape[0], lr, beta1,
+                                            beta2, eps, _ptr(self._loss), _stream()),
+               "gpfc_cnn_train_step")
+        return self._loss
+
+    def save(self, path: str):
+        """Write the parameters to a network file (tag, count, FP32 values)."""
+        _check(self.lib.gpfc_cnn_save(self.h, str(path).encode(), _stream()), "gpfc_cnn_save")
+
+    def load(self, path: str):
+        """Read a network file written by save (resets the Adam state)."""
+        _check(self.lib.gpfc_cnn_load(self.h, str(path).encode(), _stream()), "gpfc_cnn_load")

@@ -158,6 +158,7 @@ const char* gpfc_strerror(int32_t code) {
         case GPFC_ERANGE: return "size out of range (n > 262143 samples or too many periods)";
         case GPFC_ENOMEM: return "device memory allocation failed";
         case GPFC_EDEVICE: return "HIP device error";
+        case GPFC_EIO: return "network file could not be written or read, or is not a network file";
         default: return "unknown error";
     }
 }

@@ -1574,20 +1574,69 @@ int32_t gpfc_cnn_destroy(gpfc_cnn* c) {
     return GPFC_OK;
 }
 
-int32_t gpfc_cnn_set_params(gpfc_cnn* c, const float* params, void* stream) {
-    if (!c || !params) return GPFC_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
-    hipError_t e = hipMemcpyAsync(c->params, params, sizeof(float) * gcnn::kNP,
-                                  hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return cnn_err(e, "set params");
+// After new parameters: Adam moments and step count back to zero, working
+// copies to be re-packed.
+static int32_t reset_after_params(gpfc_cnn* c, hipStream_t s) {
     const unsigned nb = gcnn::blocks_for(gcnn::kNP);
     hipLaunchKernelGGL(gcnn::k_fill, dim3(nb), dim3(256), 0, s, c->m, (int64_t)gcnn::kNP, 0.0f);
     hipLaunchKernelGGL(gcnn::k_fill, dim3(nb), dim3(256), 0, s, c->v, (int64_t)gcnn::kNP, 0.0f);
     hipLaunchKernelGGL(gcnn::k_set_i32c, dim3(1), dim3(64), 0, s, c->step_dev, 0);
     c->packed = false;
     c->quantized = false;
-    e = hipGetLastError();
+    const hipError_t e = hipGetLastError();
     return e == hipSuccess ? GPFC_OK : cnn_err(e, "set params");
+}
+
+int32_t gpfc_cnn_set_params(gpfc_cnn* c, const float* params, void* stream) {
+    if (!c || !params) return GPFC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(c->params, params, sizeof(float) * gcnn::kNP,
+                                  hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return cnn_err(e, "set params");
+    return reset_after_params(c, s);
+}
+
+// Network file: 8-byte tag, int64 parameter count, then the FP32 parameters
+// in the canonical order, little-endian.
+static const char kCnnFileTag[8] = {'G', 'P', 'F', 'C', 'C', 'N', 'N', '1'};
+
+int32_t gpfc_cnn_save(gpfc_cnn* c, const char* path, void* stream) {
+    if (!c || !path) return GPFC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    float* h = new (std::nothrow) float[gcnn::kNP];
+    if (!h) return GPFC_ENOMEM;
+    hipError_t e = hipMemcpyAsync(h, c->params, sizeof(float) * gcnn::kNP, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { delete[] h; return cnn_err(e, "save"); }
+    FILE* f = fopen(path, "wb");
+    if (!f) { delete[] h; return GPFC_EIO; }
+    const int64_t n = gcnn::kNP;
+    bool ok = fwrite(kCnnFileTag, 1, 8, f) == 8 && fwrite(&n, sizeof(n), 1, f) == 1 &&
+              fwrite(h, sizeof(float), (size_t)n, f) == (size_t)n;
+    ok = (fclose(f) == 0) && ok;
+    delete[] h;
+    return ok ? GPFC_OK : GPFC_EIO;
+}
+
+int32_t gpfc_cnn_load(gpfc_cnn* c, const char* path, void* stream) {
+    if (!c || !path) return GPFC_EINVAL;
+    FILE* f = fopen(path, "rb");
+    if (!f) return GPFC_EIO;
+    char tag[8];
+    int64_t n = 0;
+    bool ok = fread(tag, 1, 8, f) == 8 && memcmp(tag, kCnnFileTag, 8) == 0 &&
+              fread(&n, sizeof(n), 1, f) == 1 && n == gcnn::kNP;
+    float* h = ok ? new (std::nothrow) float[gcnn::kNP] : nullptr;
+    if (ok && !h) { fclose(f); return GPFC_ENOMEM; }
+    ok = ok && fread(h, sizeof(float), (size_t)n, f) == (size_t)n && fgetc(f) == EOF;
+    fclose(f);
+    if (!ok) { delete[] h; return GPFC_EIO; }
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(c->params, h, sizeof(float) * gcnn::kNP, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);   // the host copy is freed next
+    delete[] h;
+    if (e != hipSuccess) return cnn_err(e, "load");
+    return reset_after_params(c, s);
 }
 
 int32_t gpfc_cnn_set_fused(gpfc_cnn* c, int32_t on) {
@@ -1650,6 +1699,15 @@ static int32_t enqueue_adam(gpfc_cnn* c, float lr, float beta1, float beta2, flo
 
 int32_t gpfc_cnn_adam(gpfc_cnn* c, float lr, float beta1, float beta2, float eps, void* stream) {
     if (!c || !adam_args_ok(lr, beta1, beta2)) return GPFC_EINVAL;
+    return enqueue_adam(c, lr, beta1, beta2, eps, (hipStream_t)stream);
+}
+
+int32_t gpfc_cnn_train_step(gpfc_cnn* c, const void* x, int32_t x_f32, const float* labels,
+                            int64_t B, float lr, float beta1, float beta2, float eps, float* loss_out,
+                            void* stream) {
+    if (!c || !adam_args_ok(lr, beta1, beta2)) return GPFC_EINVAL;
+    const int32_t rc = gpfc_cnn_backward(c, x, x_f32, labels, B, loss_out, nullptr, stream);
+    if (rc != GPFC_OK) return rc;
     return enqueue_adam(c, lr, beta1, beta2, eps, (hipStream_t)stream);
 }
 

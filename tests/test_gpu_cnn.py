@@ -241,3 +241,54 @@ def test_captured_training_step_equals_eager(torch_dev):
         assert lg == le, (i, lg, le)
     torch.cuda.synchronize()
     assert torch.equal(eager.get_params(), graph.get_params())
+
+
+def test_save_load_round_trip(torch_dev, tmp_path):
+    """A saved network loads back bit for bit; files that are not network
+    files (wrong tag, wrong count, short, missing) are refused with
+    GPFC_EIO and leave the network unchanged."""
+    torch = torch_dev
+    from paper_2312_02063_amd import CNN_BF16
+    from paper_2312_02063_amd._lib import EIO, GpfcError
+    p = _params(31).astype(np.float32)
+    a = _net(torch, CNN_BF16, p, 64)
+    path = tmp_path / "net.gpfc"
+    _say("cnn save/load")
+    a.save(path)
+    raw = path.read_bytes()
+    assert raw[:8] == b"GPFCCNN1" and int.from_bytes(raw[8:16], "little") == p.size
+    assert np.array_equal(np.frombuffer(raw[16:], dtype="<f4"), p)
+    b = _net(torch, CNN_BF16, _params(32).astype(np.float32), 64)
+    b.load(path)
+    x = torch.tensor(_inputs(3, 50)[0], dtype=torch.float32, device="cuda")
+    assert torch.equal(a.forward(x), b.forward(x))
+    bad = {"tag": b"GPFCCNN0" + raw[8:], "count": raw[:8] + (5).to_bytes(8, "little") + raw[16:],
+           "short": raw[:-4], "long": raw + b"\0\0\0\0"}
+    for name, blob in bad.items():
+        f = tmp_path / name
+        f.write_bytes(blob)
+        with pytest.raises(GpfcError) as e:
+            b.load(f)
+        assert e.value.code == EIO, name
+    with pytest.raises(GpfcError) as e:
+        b.load(tmp_path / "missing")
+    assert e.value.code == EIO
+    assert np.array_equal(b.get_params().cpu().numpy(), p)
+
+
+def test_train_step_equals_backward_then_adam(torch_dev):
+    torch = torch_dev
+    from paper_2312_02063_amd import CNN_BF16
+    p = _params(33)
+    x, y = _inputs(34, 128)
+    xt = torch.tensor(x, dtype=torch.float32, device="cuda")
+    yt = torch.tensor(y, dtype=torch.float32, device="cuda")
+    a = _net(torch, CNN_BF16, p, 256)
+    b = _net(torch, CNN_BF16, p, 256)
+    _say("cnn train_step vs backward + adam")
+    for _ in range(3):
+        la = a.train_step(xt, yt, 1e-3).clone()
+        lb = b.backward(xt, yt).clone()
+        b.adam(1e-3)
+        assert torch.equal(la, lb)
+    assert torch.equal(a.get_params(), b.get_params())
