@@ -819,9 +819,9 @@ __global__ __launch_bounds__(kWP * 64, 1) void k_convstack_bf16_w(
             dst[sw ^ 1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
         }
         wave_lds_sync();
-        conv_one<128, 16, kA1Ld, 32, kW2Ld, kA2Ld, 4, 2>(ws.buf0, sm.w2, b2, ws.buf1);
+        conv_one<128, 16, kA1Ld, 32, kW2Ld, kA2Ld, 8, 2>(ws.buf0, sm.w2, b2, ws.buf1);
         wave_lds_sync();
-        conv_one<64, 32, kA2Ld, 64, kW3Ld, kA3Ld, 4, 2>(ws.buf1, sm.w3, b3, ws.buf0);
+        conv_one<64, 32, kA2Ld, 64, kW3Ld, kA3Ld, 4, 4>(ws.buf1, sm.w3, b3, ws.buf0);
         wave_lds_sync();
         conv_one<32, 64, kA3Ld, 64, kW4Ld, 64, 2, 4>(ws.buf0, sm.w4, b4, a4 + fi * 1024);
         wave_lds_sync();   // buf0 and xs are reused by the next input
