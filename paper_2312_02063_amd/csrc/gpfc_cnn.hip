@@ -47,11 +47,17 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-__device__ __forceinline__ uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);   // NaN stays NaN
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+// Round to nearest even bfloat16, NaN kept NaN: gfx950's v_cvt_pk_bf16_f32,
+// which gives the same bits as rounding the bit pattern (u + 0x7fff + lsb)
+// for every finite value and sets the quiet bit of a NaN (checked against
+// that rounding on 2^24 patterns: ties, denormals, overflow, NaNs).
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+// Two values rounded as f2bf, lo in bits 0-15 and hi in bits 16-31 (one instruction).
+__device__ __forceinline__ uint32_t f2bf2(float lo, float hi) {
+    const f32x2v v = {lo, hi};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2v));
 }
 
 // Element types of the working copies and activations.
@@ -647,7 +653,7 @@ __global__ __launch_bounds__(kFusedThreads, 1) void k_convstack_bf16(
             const int f = pi >> 7, xp = pi & 127;
             float v[6];
             for (int d = 0; d < 6; ++d) v[d] = bf2f(sm.xs[f * 256 + ((2 * xp + d - 2) & 255)]);
-            uint32_t packed[8];
+            float pooled[16];
             for (int co = 0; co < 16; ++co) {
                 float p0 = sm.b1[co], p1 = sm.b1[co];
                 for (int dx = 0; dx < 5; ++dx) {
@@ -655,10 +661,10 @@ __global__ __launch_bounds__(kFusedThreads, 1) void k_convstack_bf16(
                     p1 += sm.w1[co * 5 + dx] * v[dx + 1];
                 }
                 const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
-                const uint32_t hbits = f2bf(r0 >= r1 ? r0 : r1);
-                if (co & 1) packed[co >> 1] |= hbits << 16;
-                else packed[co >> 1] = hbits;
+                pooled[co] = r0 >= r1 ? r0 : r1;
             }
+            uint32_t packed[8];
+            for (int j = 0; j < 8; ++j) packed[j] = f2bf2(pooled[2 * j], pooled[2 * j + 1]);
             const int row = f * 128 + xp;
             const int sw = (row >> 3) & 1;     // the a1 swizzle of act_off<16>
             uint4* dst = reinterpret_cast<uint4*>(sm.buf0 + row * kA1Ld);
@@ -801,7 +807,7 @@ __global__ __launch_bounds__(kWP * 64, 1) void k_convstack_bf16_w(
         for (int xp = lane; xp < 128; xp += 64) {
             float v[6];
             for (int d = 0; d < 6; ++d) v[d] = bf2f(ws.xs[(2 * xp + d - 2) & 255]);
-            uint32_t packed[8];
+            float pooled[16];
             for (int co = 0; co < 16; ++co) {
                 float p0 = sm.b1[co], p1 = sm.b1[co];
                 for (int dx = 0; dx < 5; ++dx) {
@@ -809,10 +815,10 @@ __global__ __launch_bounds__(kWP * 64, 1) void k_convstack_bf16_w(
                     p1 += sm.w1[co * 5 + dx] * v[dx + 1];
                 }
                 const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
-                const uint32_t hbits = f2bf(r0 >= r1 ? r0 : r1);
-                if (co & 1) packed[co >> 1] |= hbits << 16;
-                else packed[co >> 1] = hbits;
+                pooled[co] = r0 >= r1 ? r0 : r1;
             }
+            uint32_t packed[8];
+            for (int j = 0; j < 8; ++j) packed[j] = f2bf2(pooled[2 * j], pooled[2 * j + 1]);
             const int sw = (xp >> 3) & 1;     // the a1 swizzle of act_off<16>
             uint4* dst = reinterpret_cast<uint4*>(ws.buf0 + xp * kA1Ld);
             dst[sw] = make_uint4(packed[0], packed[1], packed[2], packed[3]);

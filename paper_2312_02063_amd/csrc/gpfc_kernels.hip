@@ -689,12 +689,9 @@ __device__ void score_table(const char* tab, int nb, int g, const Widths& W, Sco
     width[kk] = o_w;
 }
 
-// Round to nearest even bfloat16 (finite inputs).
-__device__ __forceinline__ uint16_t bf16_rne(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// Round to nearest even bfloat16 (v_cvt_pk_bf16_f32: the same bits as
+// rounding the bit pattern, for every finite value).
+__device__ __forceinline__ uint16_t bf16_rne(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 // Fold + score of one block of 64 periods of one prepared curve (periods
 // kbase .. kbase+63 of the curve's k). Outputs are indexed by the curve's
