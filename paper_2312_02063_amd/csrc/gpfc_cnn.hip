@@ -428,7 +428,7 @@ __global__ __launch_bounds__(256) void k_conv1_fwd(const void* __restrict__ x, i
             const int64_t o = (int64_t)b * 256 + pos;
             const float v = xf32 ? reinterpret_cast<const float*>(x)[o]
                                  : bf2f(reinterpret_cast<const uint16_t*>(x)[o]);
-            s += w[co * 5 + dx] * P::to_f(P::from_f(v));
+            s = __builtin_fmaf(w[co * 5 + dx], P::to_f(P::from_f(v)), s);
         }
         pre[h] = s;
     }
@@ -657,8 +657,8 @@ __global__ __launch_bounds__(kFusedThreads, 1) void k_convstack_bf16(
             for (int co = 0; co < 16; ++co) {
                 float p0 = sm.b1[co], p1 = sm.b1[co];
                 for (int dx = 0; dx < 5; ++dx) {
-                    p0 += sm.w1[co * 5 + dx] * v[dx];
-                    p1 += sm.w1[co * 5 + dx] * v[dx + 1];
+                    p0 = __builtin_fmaf(sm.w1[co * 5 + dx], v[dx], p0);
+                    p1 = __builtin_fmaf(sm.w1[co * 5 + dx], v[dx + 1], p1);
                 }
                 const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
                 pooled[co] = r0 >= r1 ? r0 : r1;
@@ -700,8 +700,6 @@ struct ConvStackLdsW {
     uint16_t w2[32 * kW2Ld];
     uint16_t w3[64 * kW3Ld];
     uint16_t w4[64 * kW4Ld];
-    float w1[16 * 5];
-    float b1[16];
     WaveSlice wv[kWP];
 };
 static_assert(128 * kA1Ld <= 32 * kA3Ld, "a1 must fit where a3 goes");
@@ -780,8 +778,6 @@ __global__ __launch_bounds__(kWP * 64, 1) void k_convstack_bf16_w(
         const int n = i / kW4Ld, k = i - n * kW4Ld;
         sm.w4[i] = k < 320 ? wf4[n * 320 + k] : (uint16_t)0;
     }
-    if (tid < 80) sm.w1[tid] = w1[tid];
-    if (tid < 16) sm.b1[tid] = b1[tid];
     __syncthreads();   // the only block-wide wait: weights staged
     WaveSlice& ws = sm.wv[wave];
     const int64_t stride = (int64_t)gridDim.x * kWP;
@@ -803,16 +799,17 @@ __global__ __launch_bounds__(kWP * 64, 1) void k_convstack_bf16_w(
         reinterpret_cast<uint2*>(ws.xs)[lane] = xnext;
         xnext = load_in(fi + stride);
         wave_lds_sync();
-        // conv1: lane = 2 pooled positions, all 16 channels (as k_conv1_fwd)
+        // conv1: lane = 2 pooled positions, all 16 channels (as k_conv1_fwd;
+        // weights and biases are wave-uniform: scalar loads)
         for (int xp = lane; xp < 128; xp += 64) {
             float v[6];
             for (int d = 0; d < 6; ++d) v[d] = bf2f(ws.xs[(2 * xp + d - 2) & 255]);
             float pooled[16];
             for (int co = 0; co < 16; ++co) {
-                float p0 = sm.b1[co], p1 = sm.b1[co];
+                float p0 = b1[co], p1 = b1[co];
                 for (int dx = 0; dx < 5; ++dx) {
-                    p0 += sm.w1[co * 5 + dx] * v[dx];
-                    p1 += sm.w1[co * 5 + dx] * v[dx + 1];
+                    p0 = __builtin_fmaf(w1[co * 5 + dx], v[dx], p0);
+                    p1 = __builtin_fmaf(w1[co * 5 + dx], v[dx + 1], p1);
                 }
                 const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
                 pooled[co] = r0 >= r1 ? r0 : r1;
