@@ -916,84 +916,84 @@ __global__ __launch_bounds__(256) void k_fc_bf16(int M, int K, const uint16_t* _
 // The first fully connected layer for bf16 inference (N = 256 outputs): one
 // block of 8 waves computes 128 rows x all 256 columns (waves 2 x 4, each
 // 64 x 64), so every activation row is read once. K advances in steps of 64
-// through two LDS stages (rows padded by 8); global loads run two steps
-// ahead in two register sets, so a step's loads have two steps of matrix
-// work to arrive. Same MFMA chains and epilogue as k_gemm with EpFcFwd:
-// bit-identical output.
+// through three LDS stages filled straight from global memory
+// (global_load_lds_dwordx4: a wave's 64 lanes write 1 KB of LDS in lane
+// order, no registers in between), issued two steps ahead, with one block
+// barrier per step. A row of a stage is 128 B of 16-byte chunks stored
+// XOR-swizzled (chunk c of row r at chunk slot c ^ (r & 7)), so the 16 rows
+// a fragment read touches fall on distinct banks in groups of 8. Same MFMA
+// chains and epilogue as k_gemm with EpFcFwd: bit-identical output.
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+constexpr int kF1BM = 128, kF1BN = 256, kF1Stages = 3;
+constexpr int kF1StageA = kF1BM * 128, kF1StageB = kF1BN * 128;   // bytes per stage
+
 __global__ __launch_bounds__(512, 1) void k_fc1_bf16(int M, int K, const uint16_t* __restrict__ A,
                                                    const uint16_t* __restrict__ W,
                                                    const float* __restrict__ bias,
                                                    uint16_t* __restrict__ out) {
-    constexpr int BM = 128, BN = 256, NT = 512;
-    constexpr int ACH = BM * kFcBK / 8 / NT;      // 16-byte chunks of A per thread per step (2)
-    constexpr int BCH = BN * kFcBK / 8 / NT;      // ... of W (4)
-    __shared__ __attribute__((aligned(16))) uint16_t sa[2][BM * kFcLd];
-    __shared__ __attribute__((aligned(16))) uint16_t sb[2][BN * kFcLd];
+    __shared__ __attribute__((aligned(1024))) char smem[kF1Stages * (kF1StageA + kF1StageB)];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, q = lane >> 4;
     const int wm = wave & 1, wn = wave >> 1;
-    const int m0 = blockIdx.x * BM;
-    uint4 ra0[ACH], rb0[BCH], ra1[ACH], rb1[BCH];   // the two register sets
-    auto load = [&](uint4 (&xa)[ACH], uint4 (&xb)[BCH], int k0) {
-#pragma unroll
-        for (int c = 0; c < ACH; ++c) {
-            const int idx = tid + c * NT, row = idx >> 3, col = (idx & 7) * 8;
-            xa[c] = (m0 + row < M) ? *reinterpret_cast<const uint4*>(A + (int64_t)(m0 + row) * K + k0 + col)
-                                   : make_uint4(0u, 0u, 0u, 0u);
-        }
-#pragma unroll
-        for (int c = 0; c < BCH; ++c) {
-            const int idx = tid + c * NT, row = idx >> 3, col = (idx & 7) * 8;
-            xb[c] = *reinterpret_cast<const uint4*>(W + (int64_t)row * K + k0 + col);
-        }
+    const int m0 = blockIdx.x * kF1BM;
+    // this lane's chunk in each 1 KB wave load: row (lane >> 3) of the load's
+    // 8 rows, global chunk (lane & 7) ^ (row & 7), placed at slot lane & 7
+    const int lrow = lane >> 3, lchunk = (lane & 7) ^ lrow;
+    // A: loads 2 wave, 2 wave + 1 (rows 8 L ...); W: loads 4 wave ... 4 wave + 3
+    const uint16_t* ga[2];
+    const uint16_t* gw[4];
+    for (int j = 0; j < 2; ++j) {
+        const int row = (2 * wave + j) * 8 + lrow;
+        const int mr = min(m0 + row, M - 1);   // rows past M load a valid row, never stored
+        ga[j] = A + (int64_t)mr * K + lchunk * 8;
+    }
+    for (int j = 0; j < 4; ++j) gw[j] = W + (int64_t)((4 * wave + j) * 8 + lrow) * K + lchunk * 8;
+    auto stage_a = [&](int st) { return smem + st * (kF1StageA + kF1StageB); };
+    auto stage_b = [&](int st) { return smem + st * (kF1StageA + kF1StageB) + kF1StageA; };
+    auto issue = [&](int step) {
+        const int st = step % kF1Stages, k0 = step * kFcBK;
+        char* sa = stage_a(st);
+        char* sb = stage_b(st);
+        for (int j = 0; j < 2; ++j)
+            __builtin_amdgcn_global_load_lds((glb_void_t*)(ga[j] + k0), (lds_void_t*)(sa + (2 * wave + j) * 1024),
+                                             16, 0, 0);
+        for (int j = 0; j < 4; ++j)
+            __builtin_amdgcn_global_load_lds((glb_void_t*)(gw[j] + k0), (lds_void_t*)(sb + (4 * wave + j) * 1024),
+                                             16, 0, 0);
     };
-    auto store = [&](const uint4 (&xa)[ACH], const uint4 (&xb)[BCH], int buf) {
-#pragma unroll
-        for (int c = 0; c < ACH; ++c) {
-            const int idx = tid + c * NT, row = idx >> 3, col = (idx & 7) * 8;
-            *reinterpret_cast<uint4*>(&sa[buf][row * kFcLd + col]) = xa[c];
-        }
-#pragma unroll
-        for (int c = 0; c < BCH; ++c) {
-            const int idx = tid + c * NT, row = idx >> 3, col = (idx & 7) * 8;
-            *reinterpret_cast<uint4*>(&sb[buf][row * kFcLd + col]) = xb[c];
-        }
+    auto frag = [&](const char* base, int row, int chunk) {
+        return *reinterpret_cast<const bf16x8*>(base + row * 128 + ((chunk ^ (row & 7)) << 4));
     };
     f32x4 acc[4][4];
     for (int i = 0; i < 4; ++i)
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     const int steps = K / kFcBK;
-    load(ra0, rb0, 0);
-    store(ra0, rb0, 0);
-    if (steps > 1) load(ra1, rb1, kFcBK);
-    __syncthreads();
-    auto compute = [&](int buf) {
+    issue(0);
+    if (steps > 1) issue(1);
+    for (int st = 0; st < steps; ++st) {
+        // this wave's loads of step st are done (6 per step; those of st + 1
+        // may still be in flight), then every wave's, and every wave is done
+        // reading the stage that step st + 2 refills
+        // (a bare barrier: __syncthreads' fence would also wait for the loads
+        // of step st + 1)
+        if (st + 1 < steps) __builtin_amdgcn_s_waitcnt(0x0F76);   // vmcnt(6)
+        else __builtin_amdgcn_s_waitcnt(0x0F70);                  // vmcnt(0)
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_sched_barrier(0);
+        if (st + 2 < steps) issue(st + 2);
+        const char* sa = stage_a(st % kF1Stages);
+        const char* sb = stage_b(st % kF1Stages);
 #pragma unroll
         for (int kk = 0; kk < kFcBK; kk += 32) {
             bf16x8 a[4], b[4];
-            for (int i = 0; i < 4; ++i)
-                a[i] = *reinterpret_cast<const bf16x8*>(&sa[buf][(wm * 64 + i * 16 + r) * kFcLd + kk + q * 8]);
-            for (int j = 0; j < 4; ++j)
-                b[j] = *reinterpret_cast<const bf16x8*>(&sb[buf][(wn * 64 + j * 16 + r) * kFcLd + kk + q * 8]);
+            const int c = kk / 8 + q;
+            for (int i = 0; i < 4; ++i) a[i] = frag(sa, wm * 64 + i * 16 + r, c);
+            for (int j = 0; j < 4; ++j) b[j] = frag(sb, wn * 64 + j * 16 + r, c);
             for (int i = 0; i < 4; ++i)
                 for (int j = 0; j < 4; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-        }
-    };
-    // two steps per iteration so each register set and LDS stage is named
-    // statically: even steps read stage 0, odd steps stage 1; step s + 2 is
-    // loaded into the register set step s came through
-    for (int st = 0; st < steps; st += 2) {
-        if (st + 2 < steps) load(ra0, rb0, (st + 2) * kFcBK);
-        compute(0);
-        if (st + 1 >= steps) break;
-        store(ra1, rb1, 1);
-        __syncthreads();
-        if (st + 3 < steps) load(ra1, rb1, (st + 3) * kFcBK);
-        compute(1);
-        if (st + 2 < steps) {
-            store(ra0, rb0, 0);
-            __syncthreads();
         }
     }
     for (int i = 0; i < 4; ++i)
@@ -1002,7 +1002,7 @@ __global__ __launch_bounds__(512, 1) void k_fc1_bf16(int M, int K, const uint16_
             const float bn = bias[n];
             const int mb = m0 + wm * 64 + i * 16 + q * 4;
             for (int e = 0; e < 4; ++e)
-                if (mb + e < M) out[(int64_t)(mb + e) * BN + n] = f2bf(fmaxf(acc[i][j][e] + bn, 0.0f));
+                if (mb + e < M) out[(int64_t)(mb + e) * kF1BN + n] = f2bf(fmaxf(acc[i][j][e] + bn, 0.0f));
         }
 }
 
