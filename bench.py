@@ -175,6 +175,19 @@ def measure_rows(plan, t, f, pp, periods, survey_stars):
     tf = Bt * CNN_TRAIN_FLOP / ms / 1e9
     rows["a9_cnn_training_bf16"] = {"samples_per_s": Bt / ms * 1e3, "ms_per_step": ms, "batch": Bt,
                                     "tflops": tf, "bound": "mfma", "frac": tf / MFMA_BF16_PEAK_TFLOPS}
+    # the same step replayed from its captured HIP graph (how the trainer runs it)
+    net.train_capture(xt, y, 1e-5)
+    ms_g = _events_ms(lambda: net.train_replay(), 10)
+    rows["a9_cnn_training_bf16"]["graph_replay"] = {"ms_per_step": ms_g, "samples_per_s": Bt / ms_g * 1e3,
+                                                    "tflops": Bt * CNN_TRAIN_FLOP / ms_g / 1e9}
+    # a batch large enough that the step is not launch-bound
+    Bl = 16384
+    yl = (torch.arange(Bl, device=dev) % 2).float()
+    xl = zz[:Bl].contiguous()
+    ms_l = _events_ms(lambda: net.train_step(xl, yl, 1e-5), 5)
+    tf_l = Bl * CNN_TRAIN_FLOP / ms_l / 1e9
+    rows["a9_cnn_training_bf16"]["batch_16384"] = {"ms_per_step": ms_l, "samples_per_s": Bl / ms_l * 1e3,
+                                                   "tflops": tf_l, "frac": tf_l / MFMA_BF16_PEAK_TFLOPS}
     del net, zz, z
     # a8: per-curve best-K over the 2,000,000-period box-SNR periodogram
     snr = plan.fold_score(t, f, pp, NBINS)[0]
