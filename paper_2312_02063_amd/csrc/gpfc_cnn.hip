@@ -438,62 +438,90 @@ __global__ __launch_bounds__(256) void k_conv1_fwd(const void* __restrict__ x, i
     if (mask) mask[idx] = (uint8_t)(wn | ((wn ? pre[1] : pre[0]) > 0.0f ? 2 : 0));
 }
 
-// Output layer, loss and its gradient. One block; h2 [B][64] post-ReLU.
+// Output layer of a training step, loss and its gradient (h2 [B][64] post-ReLU),
+// in four passes with a fixed summation order (deterministic):
+// k_head_rows: per input z = b3 + sum_i h2[i] w3[i] (the order of
+//   k_head_infer), the logit if asked, dz = (sigmoid(z) - y) / B into
+//   rows[0, B) and the loss term max(z, 0) - z y + log1p(exp(-|z|)) into
+//   rows[B, 2B);
+// k_head_dh2: dh2[b][i] = dz[b] w3[i] where h2[b][i] > 0, else 0;
+// k_head_parts: row parts' sums of dz h2[.][i] (64), dz and the loss terms;
+// k_head_final: the part sums added in part order into dW3, db3 and the loss.
 template <class P>
-__global__ __launch_bounds__(256) void k_head(const typename P::T* __restrict__ h2, int B,
-                                              const float* __restrict__ w3, const float* __restrict__ b3,
-                                              const float* __restrict__ labels, float* __restrict__ logits,
-                                              float* __restrict__ loss, float* __restrict__ grad,
-                                              typename P::T* __restrict__ dh2) {
-    __shared__ float red[256];
-    __shared__ float dzs[1024];
-    float lsum = 0.0f, dbsum = 0.0f;
-    for (int b0 = 0; b0 < B; b0 += 1024) {
-        const int nb = min(1024, B - b0);
-        for (int bi = threadIdx.x; bi < nb; bi += 256) {
-            const int b = b0 + bi;
-            float z = b3[0];
-            for (int i = 0; i < 64; ++i) z += P::to_f(h2[(int64_t)b * 64 + i]) * w3[i];
-            if (logits) logits[b] = z;
-            if (labels) {
-                const float y = labels[b];
-                lsum += fmaxf(z, 0.0f) - z * y + log1pf(expf(-fabsf(z)));
-                const float dz = (1.0f / (1.0f + expf(-z)) - y) / (float)B;
-                dzs[bi] = dz;
-                dbsum += dz;
-            }
-        }
-        if (!labels) continue;
-        __syncthreads();
-        // dW3[i] += sum_b dz h2[b][i]; dh2 = dz * w3 masked by h2 > 0
-        for (int i = threadIdx.x; i < 64; i += 256) {
-            float s = 0.0f;
-            for (int bi = 0; bi < nb; ++bi) s += dzs[bi] * P::to_f(h2[(int64_t)(b0 + bi) * 64 + i]);
-            grad[F3W + i] += s;
-        }
-        for (int e = threadIdx.x; e < nb * 64; e += 256) {
-            const int bi = e >> 6, i = e & 63;
-            const int64_t o = (int64_t)(b0 + bi) * 64 + i;
-            dh2[o] = P::from_f(P::to_f(h2[o]) > 0.0f ? dzs[bi] * w3[i] : 0.0f);
-        }
-        __syncthreads();
+__global__ __launch_bounds__(256) void k_head_rows(const typename P::T* __restrict__ h2, int B,
+                                                   const float* __restrict__ w3,
+                                                   const float* __restrict__ b3,
+                                                   const float* __restrict__ labels,
+                                                   float* __restrict__ logits, float* __restrict__ rows) {
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= B) return;
+    float z = b3[0];
+    for (int i = 0; i < 64; ++i) z += P::to_f(h2[(int64_t)b * 64 + i]) * w3[i];
+    if (logits) logits[b] = z;
+    const float y = labels[b];
+    rows[B + b] = fmaxf(z, 0.0f) - z * y + log1pf(expf(-fabsf(z)));
+    rows[b] = (1.0f / (1.0f + expf(-z)) - y) / (float)B;
+}
+
+template <class P>
+__global__ __launch_bounds__(256) void k_head_dh2(const typename P::T* __restrict__ h2, int B,
+                                                  const float* __restrict__ w3,
+                                                  const float* __restrict__ rows,
+                                                  typename P::T* __restrict__ dh2) {
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= (int64_t)B * 64) return;
+    const int i = (int)(o & 63);
+    dh2[o] = P::from_f(P::to_f(h2[o]) > 0.0f ? rows[o >> 6] * w3[i] : 0.0f);
+}
+
+constexpr int kHeadSums = 66;   // dW3[64], db3, loss
+
+// Block = one part of the rows; thread (row lane rl of 4, column i): sums over
+// the part's rows rl, rl + 4, ...; lanes merged in order in LDS.
+template <class P>
+__global__ __launch_bounds__(256) void k_head_parts(const typename P::T* __restrict__ h2, int B,
+                                                    const float* __restrict__ rows,
+                                                    float* __restrict__ part_out) {
+    __shared__ float red[4][kHeadSums];
+    const int i = threadIdx.x & 63, rl = threadIdx.x >> 6;
+    const int64_t per = ((int64_t)B + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min((int64_t)B, r0 + per);
+    float sw = 0.0f, sb = 0.0f, sl = 0.0f;
+    for (int64_t r = r0 + rl; r < r1; r += 4) {
+        const float dz = rows[r];
+        sw += dz * P::to_f(h2[r * 64 + i]);
+        if (i == 0) { sb += dz; sl += rows[B + r]; }
     }
-    if (!labels) return;
-    red[threadIdx.x] = lsum;
+    red[rl][i] = sw;
+    if (i == 0) { red[rl][64] = sb; red[rl][65] = sl; }
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
+    if (threadIdx.x < kHeadSums) {
+        float t = 0.0f;
+        for (int l = 0; l < 4; ++l) t += red[l][threadIdx.x];
+        part_out[(int64_t)blockIdx.x * kHeadSums + threadIdx.x] = t;
     }
-    if (threadIdx.x == 0) *loss = red[0] / (float)B;
-    __syncthreads();
-    red[threadIdx.x] = dbsum;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) grad[F3B] += red[0];
+}
+
+// One wave per sum j: lane l adds parts l, l + 64, ... in order, then the
+// lanes are added by a fixed butterfly.
+__device__ __forceinline__ float wave_sum_parts(const float* __restrict__ parts, int nparts, int n, int j,
+                                                int lane) {
+    float t = 0.0f;
+    for (int p = lane; p < nparts; p += 64) t += parts[(int64_t)p * n + j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    return t;
+}
+
+__global__ __launch_bounds__(256) void k_head_final(const float* __restrict__ parts, int nparts, int B,
+                                                    float* __restrict__ grad, float* __restrict__ loss) {
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (j >= kHeadSums) return;
+    const float v = wave_sum_parts(parts, nparts, kHeadSums, j, lane);
+    if (lane) return;
+    if (j < 64) grad[F3W + j] = v;
+    else if (j == 64) grad[F3B] = v;
+    else *loss = v / (float)B;
 }
 
 // ------------------------------------------------------------------ fused inference
@@ -1065,14 +1093,15 @@ __global__ __launch_bounds__(256) void k_bias_grad(const typename P::T* __restri
     }
 }
 
-// out[i] = sum_p parts[p][i] for p = 0 .. nparts-1 (in order).
+// out[i] = sum_p parts[p][i] for p = 0 .. nparts-1, one wave per output in
+// a fixed order (wave_sum_parts): deterministic. Launch with 4 outputs per
+// 256-thread block.
 __global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ parts, int nparts, int n,
                                                    float* __restrict__ out) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (i >= n) return;
-    float t = 0.0f;
-    for (int p = 0; p < nparts; ++p) t += parts[(int64_t)p * n + i];
-    out[i] = t;
+    const float t = wave_sum_parts(parts, nparts, n, i, lane);
+    if (lane == 0) out[i] = t;
 }
 
 // Conv block 1 weight gradient: dW[co][dx] = sum_{b,x} dpre[b][x][co] x[b][(x+dx-2) mod 256].
@@ -1256,7 +1285,7 @@ hipError_t bias_grad(const typename P::T* d, int64_t rows, int C, float* g, floa
     const int parts = (int)std::max<int64_t>(1, std::min<int64_t>(2048 / groups, rows / 256));
     hipLaunchKernelGGL((k_bias_grad<P>), dim3((unsigned)groups, (unsigned)parts), dim3(256), 0, s, d, rows,
                        C, ws);
-    hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(C)), dim3(256), 0, s, ws, parts, C, g);
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((C + 3) / 4)), dim3(256), 0, s, ws, parts, C, g);
     return hipGetLastError();
 }
 
@@ -1410,10 +1439,20 @@ int32_t forward(gpfc_cnn* c, const void* x, int xf32, int B, float* logits, cons
                 Rows<P>{(const T*)c->f2f, 64, 256, 256}, EpFcFwd<P>{w + F2B, (T*)c->h2, 64}, s);
     if (e != hipSuccess) return cnn_err(e, "fc2 gemm");
     }
-    if (train)
-        hipLaunchKernelGGL((k_head<P>), dim3(1), dim3(256), 0, s, (const T*)c->h2, B, w + F3W,
-                           w + F3B, labels, logits, c->loss, c->grad, (T*)c->d_a);
-    else if (logits)
+    if (train) {
+        // workspace: rows [2 B], then the part sums [parts][kHeadSums]
+        const int parts = (int)std::max<int64_t>(1, std::min<int64_t>(1024, B / 256));
+        float* rows = c->ws;
+        float* psum = c->ws + 2 * (int64_t)B;
+        hipLaunchKernelGGL((k_head_rows<P>), dim3(blocks_for(B)), dim3(256), 0, s, (const T*)c->h2, B,
+                           w + F3W, w + F3B, labels, logits, rows);
+        hipLaunchKernelGGL((k_head_dh2<P>), dim3(blocks_for((int64_t)B * 64)), dim3(256), 0, s,
+                           (const T*)c->h2, B, w + F3W, rows, (T*)c->d_a);
+        hipLaunchKernelGGL((k_head_parts<P>), dim3((unsigned)parts), dim3(256), 0, s, (const T*)c->h2, B,
+                           rows, psum);
+        hipLaunchKernelGGL(k_head_final, dim3((kHeadSums + 3) / 4), dim3(256), 0, s, psum, parts, B,
+                           c->grad, c->loss);
+    } else if (logits)
         hipLaunchKernelGGL((k_head_infer<P>), dim3(blocks_for(B)), dim3(256), 0, s, (const T*)c->h2,
                            B, w + F3W, w + F3B, logits);
     e = hipGetLastError();
@@ -1463,7 +1502,7 @@ int32_t backward(gpfc_cnn* c, const void* x, int xf32, int B, hipStream_t s) {
         if (l == 1) {
             const int parts = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (int64_t)B * 256 / 1024));
             hipLaunchKernelGGL((k_conv1_dw<P>), dim3(parts), dim3(256), 0, s, dpre, x, xf32, B, c->ws);
-            hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, c->ws, parts, 80, g + kConvW[1]);
+            hipLaunchKernelGGL(k_sum_parts, dim3(20), dim3(256), 0, s, c->ws, parts, 80, g + kConvW[1]);
             break;
         }
         e = gemm_splitk<P>(Cout, 5 * Cin, B * L, Cols<P>{dpre, Cout, Cout, B * L},
@@ -1526,7 +1565,9 @@ int32_t gpfc_cnn_create(gpfc_cnn** out, int32_t device, int32_t precision, int64
     total += 2 * al(dsz * E);
     for (int i = 0; i < 4; ++i) total += al(asz[i]);   // masks
     const size_t fsz = al(sizeof(float) * gcnn::kNP);
-    total += 4 * fsz + 256 + al(sizeof(float) * gcnn::kSplitWs);
+    // the reduction workspace also holds the output layer's rows and part sums
+    const int64_t wsn = std::max<int64_t>(gcnn::kSplitWs, 2 * Bm + 1024 * gcnn::kHeadSums);
+    total += 4 * fsz + 256 + al(sizeof(float) * wsn);
     const size_t qsz[5] = {32 * 80, 64 * 160, 64 * 320, 256 * 1024, 64 * 256};
     const size_t csz[5] = {32, 64, 64, 256, 64};
     for (int i = 0; i < 5; ++i) total += al(qsz[i]) + al(csz[i] * sizeof(float));
@@ -1545,7 +1586,7 @@ int32_t gpfc_cnn_create(gpfc_cnn** out, int32_t device, int32_t precision, int64
     c->m = (float*)take(sizeof(float) * gcnn::kNP);
     c->v = (float*)take(sizeof(float) * gcnn::kNP);
     c->loss = (float*)take(256);
-    c->ws = (float*)take(sizeof(float) * gcnn::kSplitWs);
+    c->ws = (float*)take(sizeof(float) * wsn);
     void** wv[10] = {&c->wf2, &c->wb2, &c->wf3, &c->wb3, &c->wf4, &c->wb4, &c->f1f, &c->f1b, &c->f2f, &c->f2b};
     for (int i = 0; i < 10; ++i) *wv[i] = take(wsz[i] * E);
     void** av[6] = {&c->a1, &c->a2, &c->a3, &c->a4, &c->h1, &c->h2};
