@@ -187,12 +187,14 @@ struct Cols {
     const T* p;
     int rows, ld, K;
     __device__ __forceinline__ bf16x8 frag8(int m, int k) const {
-        bf16x8 v;
-        for (int j = 0; j < 8; ++j) {
-            uint16_t h = (m < rows && k + j < K) ? reinterpret_cast<const uint16_t*>(p)[(int64_t)(k + j) * ld + m] : 0;
-            v[j] = __builtin_bit_cast(__bf16, h);
+        const uint16_t* q = reinterpret_cast<const uint16_t*>(p) + (int64_t)k * ld + m;
+        u16x8 h;
+        if (m < rows && k + 8 <= K) {
+            for (int j = 0; j < 8; ++j) h[j] = q[(int64_t)j * ld];
+        } else {
+            for (int j = 0; j < 8; ++j) h[j] = (m < rows && k + j < K) ? q[(int64_t)j * ld] : (uint16_t)0;
         }
-        return v;
+        return __builtin_bit_cast(bf16x8, h);
     }
     __device__ __forceinline__ float frag1(int m, int k) const {
         return (m < rows && k < K) ? P::to_f(p[(int64_t)k * ld + m]) : 0.0f;
@@ -239,10 +241,24 @@ struct ConvCols {
         pos = pos < 0 ? pos + L : (pos >= L ? pos - L : pos);
         return P::to_f(act[((int64_t)b * L + pos) * C + c]);
     }
+    // bf16 elements are copied as they are (a bf16 -> float -> bf16 round trip
+    // is exact); the index arithmetic is done once per fragment: k is a
+    // multiple of 8 and L of 8, so the 8 positions lie in one input
     __device__ __forceinline__ bf16x8 frag8(int n, int k) const {
-        bf16x8 v;
-        for (int j = 0; j < 8; ++j) v[j] = __builtin_bit_cast(__bf16, f2bf(at(n, k + j)));
-        return v;
+        u16x8 h;
+        if (n < 5 * C && k + 8 <= K && (L & 7) == 0 && (k & 7) == 0) {
+            const int b = k / L, x = k - b * L;
+            const int dx = n / C, c = n - dx * C;
+            const uint16_t* row = reinterpret_cast<const uint16_t*>(act) + (int64_t)b * L * C + c;
+            for (int j = 0; j < 8; ++j) {
+                int pos = x + j + dx - 2;
+                pos = pos < 0 ? pos + L : (pos >= L ? pos - L : pos);
+                h[j] = row[(int64_t)pos * C];
+            }
+        } else {
+            for (int j = 0; j < 8; ++j) h[j] = f2bf(at(n, k + j));
+        }
+        return __builtin_bit_cast(bf16x8, h);
     }
     __device__ __forceinline__ float frag1(int n, int k) const { return at(n, k); }
 };
@@ -402,6 +418,23 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const float* __restrict__
     float v = 0.0f;
     for (int z = 0; z < S; ++z) v += ws[z * mn + i];
     ep.store((int)(i / N), (int)(i % N), v);
+}
+
+// The same with one wave per output for few outputs and many partials (the
+// convolution weight gradients): lane l adds partials l, l + 64, ... in order,
+// the lanes are added by a fixed butterfly (deterministic).
+template <class EP>
+__global__ __launch_bounds__(256) void k_splitk_reduce_w(const float* __restrict__ ws, int S, int M,
+                                                         int N, EP ep) {
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t mn = (int64_t)M * N;
+    if (i >= mn) return;
+    float v = 0.0f;
+    for (int z = lane; z < S; z += 64) v += ws[z * mn + i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) ep.store((int)(i / N), (int)(i % N), v);
 }
 
 // ------------------------------------------------------------------ small kernels
@@ -1309,8 +1342,12 @@ hipError_t gemm_splitk(int M, int N, int K, LA la, LB lb, EP ep, float* ws, hipS
     dim3 grid((M + 63) / 64, (N + 63) / 64, S);
     hipLaunchKernelGGL((k_gemm<P, LA, LB, EpPartial>), grid, dim3(256), 0, s, M, N, K, kc, la, lb,
                        EpPartial{ws});
-    hipLaunchKernelGGL((k_splitk_reduce<EP>), dim3(blocks_for((int64_t)M * N)), dim3(256), 0, s, ws,
-                       S, M, N, ep);
+    if (S >= 16 && (int64_t)M * N <= 65536)
+        hipLaunchKernelGGL((k_splitk_reduce_w<EP>), dim3((unsigned)(((int64_t)M * N + 3) / 4)), dim3(256), 0,
+                           s, ws, S, M, N, ep);
+    else
+        hipLaunchKernelGGL((k_splitk_reduce<EP>), dim3(blocks_for((int64_t)M * N)), dim3(256), 0, s, ws,
+                           S, M, N, ep);
     return hipGetLastError();
 }
 
