@@ -60,6 +60,12 @@ __device__ __forceinline__ uint32_t f2bf2(float lo, float hi) {
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2v));
 }
 
+// Bias-added pre-activations of a position pair -> the pooled activation:
+// max(p0, p1, 0), i.e. ReLU then max-pool (one v_max3_f32). Every forward
+// path (layer, fused, training) pools through this, so their outputs agree
+// bit for bit; the training mask is taken from the same pair separately.
+__device__ __forceinline__ float pool_relu(float p0, float p1) { return fmaxf(fmaxf(p0, p1), 0.0f); }
+
 // Element types of the working copies and activations.
 struct BF16 {
     using T = uint16_t;
@@ -317,12 +323,13 @@ struct EpConvFwd {
             const int mm = m + 2 * h;
             if (mm >= M) continue;
             const float p0 = a[2 * h] * cs + bias[n], p1 = a[2 * h + 1] * cs + bias[n];
-            const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
-            const int w = r0 >= r1 ? 0 : 1;
-            const float pv = w ? p1 : p0;
             const int64_t o = (int64_t)(mm >> 1) * C + n;
-            out[o] = P::from_f(w ? r1 : r0);
-            if (mask) mask[o] = (uint8_t)(w | (pv > 0.0f ? 2 : 0));
+            out[o] = P::from_f(pool_relu(p0, p1));
+            if (mask) {
+                const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
+                const int w = r0 >= r1 ? 0 : 1;
+                mask[o] = (uint8_t)(w | ((w ? p1 : p0) > 0.0f ? 2 : 0));
+            }
         }
     }
 };
@@ -465,10 +472,12 @@ __global__ __launch_bounds__(256) void k_conv1_fwd(const void* __restrict__ x, i
         }
         pre[h] = s;
     }
-    const float r0 = fmaxf(pre[0], 0.0f), r1 = fmaxf(pre[1], 0.0f);
-    const int wn = r0 >= r1 ? 0 : 1;
-    out[idx] = P::from_f(wn ? r1 : r0);
-    if (mask) mask[idx] = (uint8_t)(wn | ((wn ? pre[1] : pre[0]) > 0.0f ? 2 : 0));
+    out[idx] = P::from_f(pool_relu(pre[0], pre[1]));
+    if (mask) {
+        const float r0 = fmaxf(pre[0], 0.0f), r1 = fmaxf(pre[1], 0.0f);
+        const int wn = r0 >= r1 ? 0 : 1;
+        mask[idx] = (uint8_t)(wn | ((wn ? pre[1] : pre[0]) > 0.0f ? 2 : 0));
+    }
 }
 
 // Output layer of a training step, loss and its gradient (h2 [B][64] post-ReLU),
@@ -652,8 +661,7 @@ __device__ __forceinline__ void conv_tile(const uint16_t* __restrict__ in,
                 const float bn = bias[n];
                 for (int h = 0; h < 2; ++h) {
                     const float p0 = acc[i][j][2 * h] + bn, p1 = acc[i][j][2 * h + 1] + bn;
-                    const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
-                    out[(f * (L / 2) + (x0 >> 1) + h) * OLD + n] = f2bf(r0 >= r1 ? r0 : r1);
+                    out[(f * (L / 2) + (x0 >> 1) + h) * OLD + n] = f2bf(pool_relu(p0, p1));
                 }
             }
         }
@@ -721,8 +729,7 @@ __global__ __launch_bounds__(kFusedThreads, 1) void k_convstack_bf16(
                     p0 = __builtin_fmaf(sm.w1[co * 5 + dx], v[dx], p0);
                     p1 = __builtin_fmaf(sm.w1[co * 5 + dx], v[dx + 1], p1);
                 }
-                const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
-                pooled[co] = r0 >= r1 ? r0 : r1;
+                pooled[co] = pool_relu(p0, p1);
             }
             uint32_t packed[8];
             for (int j = 0; j < 8; ++j) packed[j] = f2bf2(pooled[2 * j], pooled[2 * j + 1]);
@@ -812,8 +819,7 @@ __device__ __forceinline__ void conv_one(const uint16_t* __restrict__ in, const 
                 const float bn = bias[n];
                 for (int h = 0; h < 2; ++h) {
                     const float p0 = acc[i][j][2 * h] + bn, p1 = acc[i][j][2 * h + 1] + bn;
-                    const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
-                    out[((x0 >> 1) + h) * OLD + n] = f2bf(r0 >= r1 ? r0 : r1);
+                    out[((x0 >> 1) + h) * OLD + n] = f2bf(pool_relu(p0, p1));
                 }
             }
         }
@@ -872,8 +878,7 @@ __global__ __launch_bounds__(kWP * 64, 1) void k_convstack_bf16_w(
                     p0 = __builtin_fmaf(w1[co * 5 + dx], v[dx], p0);
                     p1 = __builtin_fmaf(w1[co * 5 + dx], v[dx + 1], p1);
                 }
-                const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
-                pooled[co] = r0 >= r1 ? r0 : r1;
+                pooled[co] = pool_relu(p0, p1);
             }
             uint32_t packed[8];
             for (int j = 0; j < 8; ++j) packed[j] = f2bf2(pooled[2 * j], pooled[2 * j + 1]);
