@@ -782,9 +782,15 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // One conv layer of one input by one wave: rows x < L, tiles of RB x CB MFMA
 // blocks, as conv_tile (same k order, same epilogue).
-template <int L, int CIN, int ILD, int COUT, int WLD, int OLD, int RB, int CB>
+// kTrain: also write each pooled output to gout (if not null: the layer's
+// activation in HBM, [L/2][COUT]) and its mask byte to gmask (bit 0: the
+// winning position's parity, bit 1: the winner's pre-activation is > 0), as
+// EpConvFwd does for the backward pass.
+template <int L, int CIN, int ILD, int COUT, int WLD, int OLD, int RB, int CB, bool kTrain = false>
 __device__ __forceinline__ void conv_one(const uint16_t* __restrict__ in, const uint16_t* __restrict__ w,
-                                         const float* __restrict__ bias, uint16_t* __restrict__ out) {
+                                         const float* __restrict__ bias, uint16_t* __restrict__ out,
+                                         uint16_t* __restrict__ gout = nullptr,
+                                         uint8_t* __restrict__ gmask = nullptr) {
     constexpr int K = 5 * CIN;
     constexpr int KSTEPS = (K + 31) / 32;
     constexpr int NRT = L / (16 * RB), NCT = COUT / (16 * CB);
@@ -819,18 +825,34 @@ __device__ __forceinline__ void conv_one(const uint16_t* __restrict__ in, const 
                 const float bn = bias[n];
                 for (int h = 0; h < 2; ++h) {
                     const float p0 = acc[i][j][2 * h] + bn, p1 = acc[i][j][2 * h + 1] + bn;
-                    out[((x0 >> 1) + h) * OLD + n] = f2bf(pool_relu(p0, p1));
+                    const uint16_t hv = f2bf(pool_relu(p0, p1));
+                    out[((x0 >> 1) + h) * OLD + n] = hv;
+                    if constexpr (kTrain) {
+                        const int po = ((x0 >> 1) + h) * COUT + n;
+                        if (gout) gout[po] = hv;
+                        const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
+                        const int wn = r0 >= r1 ? 0 : 1;
+                        gmask[po] = (uint8_t)(wn | ((wn ? p1 : p0) > 0.0f ? 2 : 0));
+                    }
                 }
             }
         }
     }
 }
 
+// kTrain: the forward pass of a training step: besides a4, every block's
+// pooled activations (a1 [B][128][16], a2 [B][64][32], a3 [B][32][64]) and
+// pooling masks (m1 ... m4, the same layouts) go to HBM for the backward
+// pass, with the values k_conv1_fwd and the EpConvFwd GEMMs would store.
+template <bool kTrain>
 __global__ __launch_bounds__(kWP * 64, 1) void k_convstack_bf16_w(
     const void* __restrict__ x, int xf32, int B, const float* __restrict__ w1,
     const float* __restrict__ b1, const uint16_t* __restrict__ wf2, const float* __restrict__ b2,
     const uint16_t* __restrict__ wf3, const float* __restrict__ b3,
-    const uint16_t* __restrict__ wf4, const float* __restrict__ b4, uint16_t* __restrict__ a4) {
+    const uint16_t* __restrict__ wf4, const float* __restrict__ b4, uint16_t* __restrict__ a4,
+    uint16_t* __restrict__ a1g, uint16_t* __restrict__ a2g, uint16_t* __restrict__ a3g,
+    uint8_t* __restrict__ m1, uint8_t* __restrict__ m2, uint8_t* __restrict__ m3,
+    uint8_t* __restrict__ m4) {
     __shared__ __attribute__((aligned(16))) ConvStackLdsW sm;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int i = tid; i < 32 * kW2Ld; i += kWP * 64) {
@@ -872,6 +894,7 @@ __global__ __launch_bounds__(kWP * 64, 1) void k_convstack_bf16_w(
             float v[6];
             for (int d = 0; d < 6; ++d) v[d] = bf2f(ws.xs[(2 * xp + d - 2) & 255]);
             float pooled[16];
+            uint32_t mk[4] = {0u, 0u, 0u, 0u};
             for (int co = 0; co < 16; ++co) {
                 float p0 = b1[co], p1 = b1[co];
                 for (int dx = 0; dx < 5; ++dx) {
@@ -879,6 +902,12 @@ __global__ __launch_bounds__(kWP * 64, 1) void k_convstack_bf16_w(
                     p1 = __builtin_fmaf(w1[co * 5 + dx], v[dx + 1], p1);
                 }
                 pooled[co] = pool_relu(p0, p1);
+                if constexpr (kTrain) {
+                    const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
+                    const int wn = r0 >= r1 ? 0 : 1;
+                    const uint32_t byte = (uint32_t)(wn | ((wn ? p1 : p0) > 0.0f ? 2 : 0));
+                    mk[co >> 2] |= byte << (8 * (co & 3));
+                }
             }
             uint32_t packed[8];
             for (int j = 0; j < 8; ++j) packed[j] = f2bf2(pooled[2 * j], pooled[2 * j + 1]);
@@ -886,13 +915,23 @@ __global__ __launch_bounds__(kWP * 64, 1) void k_convstack_bf16_w(
             uint4* dst = reinterpret_cast<uint4*>(ws.buf0 + xp * kA1Ld);
             dst[sw] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
             dst[sw ^ 1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
+            if constexpr (kTrain) {
+                const int64_t o = (fi * 128 + xp) * 16;
+                uint4* g = reinterpret_cast<uint4*>(a1g + o);
+                g[0] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
+                g[1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
+                *reinterpret_cast<uint4*>(m1 + o) = make_uint4(mk[0], mk[1], mk[2], mk[3]);
+            }
         }
         wave_lds_sync();
-        conv_one<128, 16, kA1Ld, 32, kW2Ld, kA2Ld, 8, 2>(ws.buf0, sm.w2, b2, ws.buf1);
+        conv_one<128, 16, kA1Ld, 32, kW2Ld, kA2Ld, 8, 2, kTrain>(
+            ws.buf0, sm.w2, b2, ws.buf1, kTrain ? a2g + fi * 2048 : nullptr, kTrain ? m2 + fi * 2048 : nullptr);
         wave_lds_sync();
-        conv_one<64, 32, kA2Ld, 64, kW3Ld, kA3Ld, 4, 4>(ws.buf1, sm.w3, b3, ws.buf0);
+        conv_one<64, 32, kA2Ld, 64, kW3Ld, kA3Ld, 4, 4, kTrain>(
+            ws.buf1, sm.w3, b3, ws.buf0, kTrain ? a3g + fi * 2048 : nullptr, kTrain ? m3 + fi * 2048 : nullptr);
         wave_lds_sync();
-        conv_one<32, 64, kA3Ld, 64, kW4Ld, 64, 2, 4>(ws.buf0, sm.w4, b4, a4 + fi * 1024);
+        conv_one<32, 64, kA3Ld, 64, kW4Ld, 64, 2, 4, kTrain>(ws.buf0, sm.w4, b4, a4 + fi * 1024, nullptr,
+                                                             kTrain ? m4 + fi * 1024 : nullptr);
         wave_lds_sync();   // buf0 and xs are reused by the next input
     }
 }
@@ -1438,16 +1477,26 @@ int32_t forward(gpfc_cnn* c, const void* x, int xf32, int B, float* logits, cons
     uint8_t* masks[5] = {nullptr, c->m1, c->m2, c->m3, c->m4};
     if (!train) masks[2] = masks[3] = masks[4] = nullptr;
     void* wfs[5] = {nullptr, nullptr, c->wf2, c->wf3, c->wf4};
-    // inference of a bf16 network: the fused convolution stack (bit-identical)
-    const bool fused = __is_same(P, BF16) && !train && logits && c->fused &&
+    // a bf16 network runs the fused convolution stack (bit-identical to the
+    // layer path); a training step's forward also writes the activations and
+    // masks the backward pass reads
+    const bool fused = __is_same(P, BF16) && (train || logits) && c->fused &&
                        ((uintptr_t)x & 15) == 0;   // the fused kernel loads 16-byte groups
     if (fused) {
         const int ntiles = (B + kTileF - 1) / kTileF;
-        if (c->fused_mode == 1)
-            hipLaunchKernelGGL(k_convstack_bf16_w, dim3((unsigned)std::min<int64_t>((B + kWP - 1) / kWP, c->n_cu)),
-                               dim3(kWP * 64), 0, s, x, xf32, B, w + kConvW[1], w + conv_b(1),
-                               (const uint16_t*)c->wf2, w + conv_b(2), (const uint16_t*)c->wf3,
-                               w + conv_b(3), (const uint16_t*)c->wf4, w + conv_b(4), (uint16_t*)c->a4);
+        const dim3 wgrid((unsigned)std::min<int64_t>((B + kWP - 1) / kWP, c->n_cu));
+        if (train)
+            hipLaunchKernelGGL(k_convstack_bf16_w<true>, wgrid, dim3(kWP * 64), 0, s, x, xf32, B,
+                               w + kConvW[1], w + conv_b(1), (const uint16_t*)c->wf2, w + conv_b(2),
+                               (const uint16_t*)c->wf3, w + conv_b(3), (const uint16_t*)c->wf4,
+                               w + conv_b(4), (uint16_t*)c->a4, (uint16_t*)c->a1, (uint16_t*)c->a2,
+                               (uint16_t*)c->a3, c->m1, c->m2, c->m3, c->m4);
+        else if (c->fused_mode == 1)
+            hipLaunchKernelGGL(k_convstack_bf16_w<false>, wgrid, dim3(kWP * 64), 0, s, x, xf32, B,
+                               w + kConvW[1], w + conv_b(1), (const uint16_t*)c->wf2, w + conv_b(2),
+                               (const uint16_t*)c->wf3, w + conv_b(3), (const uint16_t*)c->wf4,
+                               w + conv_b(4), (uint16_t*)c->a4, nullptr, nullptr, nullptr, nullptr,
+                               nullptr, nullptr, nullptr);
         else
             hipLaunchKernelGGL(k_convstack_bf16, dim3((unsigned)std::min(ntiles, c->n_cu)),
                                dim3(kFusedThreads), 0, s, x, xf32, B, w + kConvW[1], w + conv_b(1),

@@ -292,3 +292,26 @@ def test_train_step_equals_backward_then_adam(torch_dev):
         b.adam(1e-3)
         assert torch.equal(la, lb)
     assert torch.equal(a.get_params(), b.get_params())
+
+
+@pytest.mark.parametrize("B", [7, 300])
+def test_fused_training_forward_bit_identical(torch_dev, B):
+    """A training step whose forward runs the fused convolution stack (it also
+    writes the activations and pooling masks the backward pass reads) gives the
+    same loss and parameters, bit for bit, as one whose forward runs layer by
+    layer."""
+    torch = torch_dev
+    from paper_2312_02063_amd import CNN_BF16
+    p = _params(35)
+    x, y = _inputs(36, B)
+    xt = torch.tensor(x, dtype=torch.float32, device="cuda")
+    yt = torch.tensor(y, dtype=torch.float32, device="cuda")
+    a = _net(torch, CNN_BF16, p, 512)
+    b = _net(torch, CNN_BF16, p, 512)
+    b.set_fused(False)
+    _say(f"cnn fused vs layered training step B={B}")
+    for _ in range(2):
+        la = a.train_step(xt, yt, 1e-3).clone()
+        lb = b.train_step(xt, yt, 1e-3).clone()
+        assert torch.equal(la, lb)
+    assert torch.equal(a.get_params(), b.get_params())
