@@ -381,7 +381,10 @@ int32_t gpfc_cnn_train_replay(gpfc_cnn *cnn, void *stream);
  * out_idx[rows][top] (index within the row). NaN values are skipped, and so
  * is every entry whose gate[rows][len] value is not >= gate_min when gate is
  * not NULL (a NaN gate never passes). Places without an entry get -inf and
- * -1. 1 <= top <= 64. Device pointers; asynchronous on `stream`.
+ * -1. 1 <= top <= 64; len < 2^32 (GPFC_ERANGE beyond). Device pointers;
+ * asynchronous on `stream`. A few long rows are split over many blocks whose
+ * lists are merged, with stream-ordered scratch memory (not inside a graph
+ * capture, where a row takes one block).
  * ------------------------------------------------------------------------ */
 #define GPFC_MAX_TOP 64
 int32_t gpfc_topk(const float *values, int64_t rows, int64_t len, const float *gate,

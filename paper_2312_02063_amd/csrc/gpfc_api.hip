@@ -816,7 +816,7 @@ int32_t gpfc_periodogram_peaks(const float* values, int64_t rows, int64_t len, c
 int32_t gpfc_topk(const float* values, int64_t rows, int64_t len, const float* gate,
                   float gate_min, int32_t top, float* out_val, int64_t* out_idx, void* stream) {
     if (rows < 0 || len < 0 || top < 1 || top > GPFC_MAX_TOP) return GPFC_EINVAL;
-    if (rows > 0x7fffffffLL) return GPFC_ERANGE;
+    if (rows > 0x7fffffffLL || len > 0xffffffffLL) return GPFC_ERANGE;
     if (rows == 0) return GPFC_OK;
     if (!out_val || !out_idx || (len > 0 && !values)) return GPFC_EINVAL;
     hipError_t e = gpfc::launch_topk(values, rows, len, gate, gate_min, top, out_val, out_idx,

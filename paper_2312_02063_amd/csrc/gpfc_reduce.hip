@@ -3,15 +3,17 @@
 // the trial periods, Sec. 2.1; the maximum over periods is the statistic that
 // is thresholded, Sec. 3.2).
 //
-// One block of 16 waves per row. Each wave streams a strided share of the row
-// and keeps a 64-entry candidate list, one entry per lane, plus the list's
-// worst entry broadcast to every lane: an element enters only when it beats
-// that worst entry, so after the first few hundred elements almost every
-// chunk is rejected by one compare and one ballot. The 16 lists (1024
-// entries) are then ranked in LDS: an entry's place is the number of entries
-// that beat it (keys are unique because indices are).
+// One block of 16 waves per row (or per part of a long row). Each wave
+// streams a strided share of the row and keeps a `top`-entry candidate list,
+// one entry per lane, plus the list's worst entry broadcast to every lane:
+// an element enters only when it beats that worst entry, so after the first
+// few hundred elements almost every chunk is rejected by one compare and one
+// ballot. The 16 lists are then ranked in LDS: an entry's place is the
+// number of entries that beat it (keys are unique because indices are).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "gpfc_internal.h"
 
@@ -39,86 +41,164 @@ __device__ __forceinline__ int64_t shfl_xor64(int64_t x, int m) {
     return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
+// Block b takes part b % parts of row b / parts (parts > 1 splits a long
+// row over many blocks; their lists are merged by a second launch over the
+// parts' entries) and writes its best `top` to out[b][top]. With idx_in the
+// entries carry their own indices (the merge; a negative index is an empty
+// place), otherwise an entry's index is its position in the row.
+// An entry's order as one 64-bit key, larger = better: the value's bits
+// mapped to an unsigned order (-0 taken as +0, so equal values tie) in the
+// high word, the complement of the index (< 2^32) in the low word. Key 0 is
+// below every entry: an empty place.
+__device__ __forceinline__ uint64_t top_key(float x, int64_t i) {
+    const uint32_t u = __float_as_uint(x == 0.0f ? 0.0f : x);
+    const uint32_t o = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    return ((uint64_t)o << 32) | (uint32_t)~(uint32_t)i;
+}
+
+// Smallest key of the wave, in every lane: within each row of 16 lanes by
+// DPP (swap neighbours, swap pairs, mirror 8, mirror 16), then across rows.
+__device__ __forceinline__ uint64_t wave_min_key(uint64_t k) {
+    auto dpp = [](uint64_t v, int ctrl) -> uint64_t {
+        const int lo = (int)(uint32_t)v, hi = (int)(v >> 32);
+        int rlo, rhi;
+        switch (ctrl) {   // the control must be a constant
+            case 0: rlo = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false);
+                    rhi = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false); break;
+            case 1: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false);
+                    rhi = __builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false); break;
+            case 2: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x141, 0xF, 0xF, false);
+                    rhi = __builtin_amdgcn_update_dpp(0, hi, 0x141, 0xF, 0xF, false); break;
+            default: rlo = __builtin_amdgcn_update_dpp(0, lo, 0x140, 0xF, 0xF, false);
+                     rhi = __builtin_amdgcn_update_dpp(0, hi, 0x140, 0xF, 0xF, false); break;
+        }
+        return ((uint64_t)(uint32_t)rhi << 32) | (uint32_t)rlo;
+    };
+    for (int c = 0; c < 4; ++c) {
+        const uint64_t o = dpp(k, c);
+        k = o < k ? o : k;
+    }
+    for (int d = 16; d < 64; d <<= 1) {
+        const uint64_t o = (uint64_t)shfl_xor64((int64_t)k, d);
+        k = o < k ? o : k;
+    }
+    return k;
+}
+
+// Block b takes part b % parts of row b / parts (parts > 1 splits a long
+// row over many blocks; their lists are merged by a second launch over the
+// parts' entries) and writes its best `top` to out[b][top]. With idx_in the
+// entries carry their own indices (the merge; a negative index is an empty
+// place), otherwise an entry's index is its position in the row.
 __global__ __launch_bounds__(kTopThreads) void k_topk_rows(const float* __restrict__ values,
                                                            const float* __restrict__ gate,
                                                            float gate_min, int64_t len, int32_t top,
                                                            float* __restrict__ out_val,
-                                                           int64_t* __restrict__ out_idx) {
-    __shared__ float lv_s[kTopThreads];
-    __shared__ int64_t li_s[kTopThreads];
+                                                           int64_t* __restrict__ out_idx, int parts,
+                                                           const int64_t* __restrict__ idx_in) {
+    __shared__ uint64_t lk_s[kTopThreads];
     __shared__ float ov_s[64];
     __shared__ int64_t oi_s[64];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int64_t row = blockIdx.x;
+    const int64_t row = blockIdx.x / parts;
+    const int part = blockIdx.x - (int)row * parts;
+    const int64_t chunk = ((len + parts - 1) / parts + 63) / 64 * 64;
+    const int64_t lo = min(len, (int64_t)part * chunk), hi = min(len, lo + chunk);
     const float* v = values + row * len;
     const float* g = gate ? gate + row * len : nullptr;
+    const int64_t* ix = idx_in ? idx_in + row * len : nullptr;
+    // element p of the row: its value, key and whether it may enter
+    auto fetch = [&](int64_t p, float& x, uint64_t& k) -> bool {
+        if (p >= hi) return false;
+        x = v[p];
+        bool ok = !__builtin_isnan(x) && (!g || g[p] >= gate_min);
+        int64_t i = p;
+        if (ix) {
+            i = ix[p];
+            ok = ok && i >= 0;
+        }
+        k = top_key(x, i);
+        return ok;
+    };
 
-    float lv = -INFINITY;        // this lane's list entry
-    int64_t li = kNoIndex;
-    float wv = -INFINITY;        // the list's worst entry and the lane holding it
-    int64_t wi = kNoIndex;
-    int wpos = 0;
+    // The wave's list has `top` places, one per lane below `top`; lanes
+    // above hold a key above every entry, so the list's worst is always a
+    // real place and the threshold an element must beat is the top-th best
+    // seen so far. With top = 64 the list starts as the wave's first 64
+    // elements, one per lane.
+    constexpr uint64_t kAbove = ~0ull;
+    float lv = -INFINITY;        // this lane's list entry (value, key)
+    uint64_t lk = lane < top ? 0 : kAbove;
+    int64_t first = lo + (int64_t)wave * 64;
+    if (top == 64) {
+        float x;
+        uint64_t k;
+        if (fetch(first + lane, x, k)) { lv = x; lk = k; }
+        first += kTopThreads;
+    }
+    uint64_t wk = wave_min_key(lk);   // the list's worst key and the lane holding it
+    int wpos = __builtin_ctzll(__ballot(lk == wk));
     // kUnroll chunks of 64 per wave are loaded before any is examined, so
     // their memory latencies overlap
     constexpr int kUnroll = 8;
-    for (int64_t base0 = (int64_t)wave * 64; base0 < len; base0 += (int64_t)kTopThreads * kUnroll) {
+    for (int64_t base0 = first; base0 < hi; base0 += (int64_t)kTopThreads * kUnroll) {
       float xs[kUnroll];
+      uint64_t ks[kUnroll];
       bool ok[kUnroll];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
-        const int64_t i = base0 + (int64_t)u * kTopThreads + lane;
         xs[u] = 0.0f;
-        ok[u] = false;
-        if (i < len) {
-            xs[u] = v[i];
-            ok[u] = !g || g[i] >= gate_min;
-        }
+        ks[u] = 0;
+        ok[u] = fetch(base0 + (int64_t)u * kTopThreads + lane, xs[u], ks[u]);
       }
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
-        const int64_t i = base0 + (int64_t)u * kTopThreads + lane;
-        const float x = xs[u];
-        const bool cand = ok[u] && !__builtin_isnan(x) && beats(x, i, wv, wi);
-        uint64_t m = __ballot(cand);
+        uint64_t m = __ballot(ok[u] && ks[u] > wk);
         while (m) {
-            const int s = __builtin_ctzll(m);
+            const int src = __builtin_ctzll(m);
             m &= m - 1;
-            const float sv = __shfl(x, s);
-            const int64_t si = shfl64(i, s);
-            if (!beats(sv, si, wv, wi)) continue;     // the list moved on meanwhile
-            if (lane == wpos) { lv = sv; li = si; }
-            // new worst: the entry every other entry beats
-            float rv = lv;
-            int64_t ri = li;
-            int rp = lane;
-            for (int d = 1; d < 64; d <<= 1) {
-                const float ov = __shfl_xor(rv, d);
-                const int64_t oi = shfl_xor64(ri, d);
-                const int op = __shfl_xor(rp, d);
-                // keep the worse one; equal keys (sentinels only): lower lane
-                const bool take = beats(rv, ri, ov, oi) || (rv == ov && ri == oi && op < rp);
-                if (take) { rv = ov; ri = oi; rp = op; }
-            }
-            wv = rv;
-            wi = ri;
-            wpos = rp;
+            const uint64_t sk = (uint64_t)shfl64((int64_t)ks[u], src);
+            if (sk <= wk) continue;                  // the list moved on meanwhile
+            const float sv = __shfl(xs[u], src);
+            if (lane == wpos) { lv = sv; lk = sk; }
+            wk = wave_min_key(lk);
+            wpos = __builtin_ctzll(__ballot(lk == wk));
         }
       }
     }
-    lv_s[threadIdx.x] = lv;
-    li_s[threadIdx.x] = li;
+    // place of an entry = number of entries with a larger key (keys are
+    // unique): each wave sorts its list by rank within the wave, then an
+    // entry that can still place counts the larger keys of every other
+    // wave's sorted list by binary search
+    if (lk == kAbove) lk = 0;
+    lk_s[threadIdx.x] = lk;
     if (threadIdx.x < 64) { ov_s[threadIdx.x] = -INFINITY; oi_s[threadIdx.x] = -1; }
     __syncthreads();
-    if (li != kNoIndex) {
-        int rank = 0;
-        for (int j = 0; j < kTopThreads; ++j) rank += beats(lv_s[j], li_s[j], lv, li) ? 1 : 0;
-        if (rank < top) { ov_s[rank] = lv; oi_s[rank] = li; }
+    int lr = 0;
+    for (int j = 0; j < 64; ++j) lr += lk_s[wave * 64 + j] > lk ? 1 : 0;
+    __syncthreads();
+    lk_s[wave * 64 + lr] = lk;   // each wave's keys, descending
+    __syncthreads();
+    if (lk != 0 && lr < top) {
+        int rank = lr;
+        for (int w = 0; w < kTopWaves; ++w) {
+            if (w == wave) continue;
+            const uint64_t* a = lk_s + w * 64;
+            int l = 0, h = 64;   // a[0, l) > lk >= a[h, 64)
+            while (l < h) {
+                const int mid = (l + h) >> 1;
+                if (a[mid] > lk) l = mid + 1;
+                else h = mid;
+            }
+            rank += l;
+        }
+        if (rank < top) { ov_s[rank] = lv; oi_s[rank] = (int64_t)(uint32_t)~(uint32_t)lk; }
     }
     __syncthreads();
     if (threadIdx.x < top) {
-        out_val[row * top + threadIdx.x] = ov_s[threadIdx.x];
-        out_idx[row * top + threadIdx.x] = oi_s[threadIdx.x];
+        out_val[(int64_t)blockIdx.x * top + threadIdx.x] = ov_s[threadIdx.x];
+        out_idx[(int64_t)blockIdx.x * top + threadIdx.x] = oi_s[threadIdx.x];
     }
 }
 
@@ -390,9 +470,41 @@ hipError_t launch_periodogram(const float* values, int64_t rows, int64_t len, co
 hipError_t launch_topk(const float* values, int64_t rows, int64_t len, const float* gate,
                        float gate_min, int32_t top, float* out_val, int64_t* out_idx, hipStream_t s) {
     if (rows == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_topk_rows, dim3((unsigned)rows), dim3(kTopThreads), 0, s, values, gate,
-                       gate_min, len, top, out_val, out_idx);
-    return hipGetLastError();
+    // few long rows: split each over enough blocks to fill the chip (each
+    // part at least 8k scores), then merge the parts' lists; not inside a
+    // graph capture (the split takes stream-ordered scratch memory)
+    int parts = 1;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+        int dev = 0, n_cu = 256;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+        const int64_t want = (2 * (int64_t)n_cu + rows - 1) / rows;
+        parts = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(want, 256), len / 8192));
+    }
+    if (parts <= 1) {
+        hipLaunchKernelGGL(k_topk_rows, dim3((unsigned)rows), dim3(kTopThreads), 0, s, values, gate,
+                           gate_min, len, top, out_val, out_idx, 1, (const int64_t*)nullptr);
+        return hipGetLastError();
+    }
+    const int64_t nc = rows * parts * top;
+    float* cv = nullptr;
+    int64_t* ci = nullptr;
+    hipError_t e = hipMallocAsync((void**)&cv, sizeof(float) * nc, s);
+    if (e == hipSuccess) e = hipMallocAsync((void**)&ci, sizeof(int64_t) * nc, s);
+    if (e != hipSuccess) {
+        if (cv) (void)hipFreeAsync(cv, s);
+        return e;
+    }
+    hipLaunchKernelGGL(k_topk_rows, dim3((unsigned)(rows * parts)), dim3(kTopThreads), 0, s, values, gate,
+                       gate_min, len, top, cv, ci, parts, (const int64_t*)nullptr);
+    hipLaunchKernelGGL(k_topk_rows, dim3((unsigned)rows), dim3(kTopThreads), 0, s, (const float*)cv,
+                       (const float*)nullptr, 0.0f, (int64_t)parts * top, top, out_val, out_idx, 1,
+                       (const int64_t*)ci);
+    e = hipGetLastError();
+    (void)hipFreeAsync(cv, s);
+    (void)hipFreeAsync(ci, s);
+    return e;
 }
 
 }  // namespace gpfc

@@ -55,6 +55,21 @@ def test_topk_matches_oracle(torch_dev, rows, n, top, gated):
     np.testing.assert_array_equal(v.cpu().numpy(), ov)
 
 
+def test_topk_split_row_mostly_empty(torch_dev):
+    """A long row split over many blocks where most parts hold fewer than
+    `top` valid scores (99.9% NaN): the merge sees empty places."""
+    from paper_2312_02063_amd import topk
+    torch = torch_dev
+    rng = np.random.default_rng(77)
+    x = np.round(rng.normal(size=(1, 1_500_000)) * 4).astype(np.float32)
+    x[rng.uniform(size=x.shape) < 0.999] = np.nan
+    _say("topk split row mostly NaN")
+    v, i = topk(_dev(torch, x, torch.float32), 64)
+    ov, oi = oracle.topk(x, 64)
+    np.testing.assert_array_equal(i.cpu().numpy(), oi)
+    np.testing.assert_array_equal(v.cpu().numpy(), ov)
+
+
 def test_topk_ascending_worst_case(torch_dev):
     """Ascending values make every element enter the candidate lists."""
     from paper_2312_02063_amd import topk
