@@ -269,7 +269,72 @@ struct PeriodogramLds {
     double mean, sd, thr;
     float mx;
     int64_t amx, m;
+    // per wave: its threads' boundary runs joined (see join_block_runs)
+    Run whead[kTopWaves], wtail[kTopWaves];
+    uint8_t wfull[kTopWaves];
+    int32_t wcnt[kTopWaves];
+    float jv[kTopWaves][kMaxPeaks];
+    int64_t ji[kTopWaves][kMaxPeaks];
+    int32_t jw[kTopWaves][kMaxPeaks];
 };
+
+// Join the runs that cross the per-thread chunks, in chunk order: first each
+// wave's lane 0 joins its 64 threads (runs completed inside the wave are
+// counted and listed; the run touching the wave's first chunk start and the
+// one touching its last chunk end are kept), then thread 0 joins the 16
+// waves the same way. Called by every thread of the block; on thread 0 it
+// adds the completed runs to fin / total and returns the block's head run
+// (touching its first score), tail run (touching its last score) and
+// whether every score of the block is above (then head is the whole block).
+__device__ void join_block_runs(PeriodogramLds& sm, int32_t min_width, PeakList& fin, int32_t& total,
+                                Run& bhead, Run& btail, bool& bfull) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const Run none{0, -INFINITY, INT64_MAX};
+    if (lane == 0) {
+        PeakList wl;
+        wl.init();
+        int32_t cnt = 0;
+        Run open = none, head = none;
+        bool first = true;
+        for (int t = wave * 64; t < wave * 64 + 64; ++t) {
+            if (sm.full[t]) {
+                open = join(open, sm.head[t]);
+            } else {
+                const Run r = join(open, sm.head[t]);
+                if (first) head = r;
+                else if (r.len > min_width) { ++cnt; wl.insert(r.mx, r.arg, (int32_t)r.len); }
+                first = false;
+                open = sm.tail[t];
+            }
+        }
+        sm.wfull[wave] = first ? 1 : 0;
+        sm.whead[wave] = first ? open : head;
+        sm.wtail[wave] = first ? none : open;
+        sm.wcnt[wave] = cnt;
+        for (int a = 0; a < kMaxPeaks; ++a) { sm.jv[wave][a] = wl.v[a]; sm.ji[wave][a] = wl.i[a]; sm.jw[wave][a] = wl.w[a]; }
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    Run open = none, head = none;
+    bool first = true;
+    for (int w = 0; w < kTopWaves; ++w) {
+        total += sm.wcnt[w];
+        for (int a = 0; a < kMaxPeaks; ++a)
+            if (sm.ji[w][a] != INT64_MAX) fin.insert(sm.jv[w][a], sm.ji[w][a], sm.jw[w][a]);
+        if (sm.wfull[w]) {
+            open = join(open, sm.whead[w]);
+        } else {
+            const Run r = join(open, sm.whead[w]);
+            if (first) head = r;
+            else if (r.len > min_width) { ++total; fin.insert(r.mx, r.arg, (int32_t)r.len); }
+            first = false;
+            open = sm.wtail[w];
+        }
+    }
+    bfull = first;
+    bhead = first ? open : head;
+    btail = first ? none : open;
+}
 
 __global__ __launch_bounds__(kTopThreads) void k_periodogram(
     const float* __restrict__ values, const double* __restrict__ periods, int64_t len, float nsigma,
@@ -407,31 +472,288 @@ __global__ __launch_bounds__(kTopThreads) void k_periodogram(
     for (int d = 32; d > 0; d >>= 1) np += __shfl_xor(np, d);
     if (lane == 0) sm.nred[wave] = np;
     __syncthreads();
-    if (tid != 0) return;
-    // thread 0: join boundary runs across chunks, then merge everything
+    // join boundary runs across chunks, then merge everything (thread 0)
     PeakList fin;
     fin.init();
     int32_t total = 0;
+    Run bhead, btail;
+    bool bfull;
+    join_block_runs(sm, min_width, fin, total, bhead, btail, bfull);
+    if (tid != 0) return;
     for (int w = 0; w < kTopThreads / 64; ++w) {
         total += sm.nred[w];
         for (int a = 0; a < kMaxPeaks; ++a)
             if (sm.wi[w][a] != INT64_MAX) fin.insert(sm.wv[w][a], sm.wi[w][a], sm.ww[w][a]);
     }
-    Run open{0, -INFINITY, INT64_MAX};
-    for (int t = 0; t < kTopThreads; ++t) {
-        if (sm.full[t]) {
-            open = join(open, sm.head[t]);
-        } else {
-            const Run r = join(open, sm.head[t]);
-            if (r.len > min_width) { ++total; fin.insert(r.mx, r.arg, (int32_t)r.len); }
-            open = sm.tail[t];
-        }
-    }
-    if (open.len > min_width) { ++total; fin.insert(open.mx, open.arg, (int32_t)open.len); }
+    // the row's first and last runs are complete
+    if (bhead.len > min_width) { ++total; fin.insert(bhead.mx, bhead.arg, (int32_t)bhead.len); }
+    if (!bfull && btail.len > min_width) { ++total; fin.insert(btail.mx, btail.arg, (int32_t)btail.len); }
     const int64_t m_all = sm.m;
     const double sdv = sm.sd;
     sde[row] = (float)((m_all && sdv > 0.0) ? ((double)sm.mx - sm.mean) / sdv : 0.0);
     mean_out[row] = (float)sm.mean;
+    sd_out[row] = (float)sdv;
+    n_peaks[row] = total;
+    const double p0 = (periods && fin.i[0] != INT64_MAX) ? periods[fin.i[0]] : 0.0;
+    for (int a = 0; a < max_peaks; ++a) {
+        const bool has = fin.i[a] != INT64_MAX;
+        pval[row * max_peaks + a] = has ? fin.v[a] : -INFINITY;
+        pidx[row * max_peaks + a] = has ? fin.i[a] : -1;
+        pwidth[row * max_peaks + a] = has ? fin.w[a] : 0;
+        int32_t code = 0;
+        if (has && periods) {
+            if (a == 0) code = 1;
+            else {
+                const double ratio = periods[fin.i[a]] / p0;
+                for (int hh = 2; hh <= 3; ++hh) {
+                    if (fabs(ratio - hh) <= 1e-3 * hh) code = hh;
+                    if (fabs(1.0 / ratio - hh) <= 1e-3 * hh) code = -hh;
+                }
+            }
+        }
+        pharm[row * max_peaks + a] = code;
+    }
+}
+
+// ---- the same for a few long rows, split over `parts` blocks per row:
+// pass 1 and pass 2 write each part's count, sum, first maximum and sum of
+// squared deviations; every later block derives the row's mean and sd from
+// the parts in part order (the same values in every block); pass 3 finds
+// each part's runs (its internal runs listed and counted, and the runs
+// touching its ends); the last kernel joins those across the parts in order.
+struct PartStats {
+    int64_t m;
+    double s, q;
+    float mx;
+    int64_t amx;
+    Run head, tail;      // runs touching the part's first and last score
+    int32_t full, np;    // every score of the part above; internal runs counted
+    float pv[kMaxPeaks];
+    int64_t pi[kMaxPeaks];
+    int32_t pw[kMaxPeaks];
+};
+
+__device__ __forceinline__ void row_mean_sd(const PartStats* ps, int parts, bool want_sd, int64_t& m,
+                                            double& mean, double& sd) {
+    m = 0;
+    double ts = 0.0, tq = 0.0;
+    for (int p = 0; p < parts; ++p) { m += ps[p].m; ts += ps[p].s; }
+    mean = m ? ts / (double)m : 0.0;
+    sd = 0.0;
+    if (want_sd) {
+        for (int p = 0; p < parts; ++p) tq += ps[p].q;
+        sd = m ? sqrt(tq / (double)m) : 0.0;
+    }
+}
+
+// pass 1 (stage 0) or pass 2 (stage 1) over one part of a row
+__global__ __launch_bounds__(kTopThreads) void k_pgram_stats(const float* __restrict__ values, int64_t len,
+                                                             int parts, int stage,
+                                                             PartStats* __restrict__ ps) {
+    __shared__ double dred[kTopWaves];
+    __shared__ int64_t cred[kTopWaves];
+    __shared__ float mred[kTopWaves];
+    __shared__ int64_t ared[kTopWaves];
+    __shared__ double mean_s;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t row = blockIdx.x / parts;
+    const int part = blockIdx.x - (int)row * parts;
+    const int64_t chunk = ((len + parts - 1) / parts + 63) / 64 * 64;
+    const int64_t lo = min(len, (int64_t)part * chunk), hi = min(len, lo + chunk);
+    const float* v = values + row * len;
+    PartStats* rp = ps + row * parts;
+    if (stage == 1) {
+        if (tid == 0) {
+            int64_t m;
+            double mean, sd;
+            row_mean_sd(rp, parts, false, m, mean, sd);
+            mean_s = mean;
+        }
+        __syncthreads();
+    }
+    int64_t m = 0;
+    double acc = 0.0;
+    float mx = -INFINITY;
+    int64_t amx = INT64_MAX;
+    const double mean = stage == 1 ? mean_s : 0.0;
+    for (int64_t i0 = lo + tid; i0 < hi; i0 += 4 * kTopThreads) {
+        float xs[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = i0 + (int64_t)u * kTopThreads;
+            xs[u] = i < hi ? v[i] : __builtin_nanf("");
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = i0 + (int64_t)u * kTopThreads;
+            const float x = xs[u];
+            if (__builtin_isnan(x)) continue;
+            if (stage == 0) {
+                ++m;
+                acc += x;
+                if (beats(x, i, mx, amx)) { mx = x; amx = i; }
+            } else {
+                const double d = x - mean;
+                acc += d * d;
+            }
+        }
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+        m += __shfl_xor(m, d);
+        acc += __shfl_xor(acc, d);
+        const float om = __shfl_xor(mx, d);
+        const int64_t oa = shfl_xor64(amx, d);
+        if (beats(om, oa, mx, amx)) { mx = om; amx = oa; }
+    }
+    if (lane == 0) { cred[wave] = m; dred[wave] = acc; mred[wave] = mx; ared[wave] = amx; }
+    __syncthreads();
+    if (tid != 0) return;
+    int64_t tm = 0;
+    double ta = 0.0;
+    float bm = -INFINITY;
+    int64_t ba = INT64_MAX;
+    for (int w = 0; w < kTopWaves; ++w) {
+        tm += cred[w];
+        ta += dred[w];
+        if (beats(mred[w], ared[w], bm, ba)) { bm = mred[w]; ba = ared[w]; }
+    }
+    PartStats& o = rp[part];
+    if (stage == 0) { o.m = tm; o.s = ta; o.mx = bm; o.amx = ba; }
+    else o.q = ta;
+}
+
+// pass 3 over one part of a row
+__global__ __launch_bounds__(kTopThreads) void k_pgram_runs(const float* __restrict__ values, int64_t len,
+                                                            int parts, float nsigma, int32_t min_width,
+                                                            PartStats* __restrict__ ps) {
+    __shared__ PeriodogramLds sm;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t row = blockIdx.x / parts;
+    const int part = blockIdx.x - (int)row * parts;
+    const int64_t chunk = ((len + parts - 1) / parts + 63) / 64 * 64;
+    const int64_t lo = min(len, (int64_t)part * chunk), hi = min(len, lo + chunk);
+    const float* v = values + row * len;
+    PartStats* rp = ps + row * parts;
+    if (tid == 0) {
+        int64_t m;
+        double mean, sd;
+        row_mean_sd(rp, parts, true, m, mean, sd);
+        sm.thr = mean + (double)nsigma * sd;
+    }
+    __syncthreads();
+    const double thr = sm.thr;
+    const int64_t cs = (hi - lo + kTopThreads - 1) / kTopThreads;
+    const int64_t c0 = min(hi, lo + (int64_t)tid * cs), c1 = min(hi, c0 + cs);
+    PeakList pl;
+    pl.init();
+    int32_t np = 0;
+    Run head{0, -INFINITY, INT64_MAX}, cur{0, -INFINITY, INT64_MAX};
+    bool in_head = true;
+    for (int64_t i0 = c0; i0 < c1; i0 += 8) {
+        float xs[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xs[u] = i0 + u < c1 ? v[i0 + u] : 0.0f;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t i = i0 + u;
+            if (i >= c1) break;
+            const float x = xs[u];
+            const bool above = !__builtin_isnan(x) && (double)x > thr;
+            if (above) {
+                cur = join(cur, Run{1, x, i});
+            } else {
+                if (in_head) head = cur;
+                else if (cur.len > min_width) { ++np; pl.insert(cur.mx, cur.arg, (int32_t)cur.len); }
+                cur = Run{0, -INFINITY, INT64_MAX};
+                in_head = false;
+            }
+        }
+    }
+    const bool full = in_head;
+    sm.full[tid] = full ? 1 : 0;
+    sm.head[tid] = full ? cur : head;
+    sm.tail[tid] = full ? Run{0, -INFINITY, INT64_MAX} : cur;
+    int h = 0;
+    for (int rnd = 0; rnd < kMaxPeaks; ++rnd) {
+        float bv = h < kMaxPeaks ? pl.v[h] : -INFINITY;
+        int64_t bi = h < kMaxPeaks ? pl.i[h] : INT64_MAX;
+        int bl = lane;
+        for (int d = 32; d > 0; d >>= 1) {
+            const float ov = __shfl_xor(bv, d);
+            const int64_t oi = shfl_xor64(bi, d);
+            const int ol = __shfl_xor(bl, d);
+            if (beats(ov, oi, bv, bi) || (ov == bv && oi == bi && ol < bl)) { bv = ov; bi = oi; bl = ol; }
+        }
+        int32_t bw = 0;
+        for (int a = 0; a < kMaxPeaks; ++a)
+            if (lane == bl && a == h) bw = pl.w[a];
+        bw = __shfl(bw, bl);
+        if (lane == 0) { sm.wv[wave][rnd] = bv; sm.wi[wave][rnd] = bi; sm.ww[wave][rnd] = bw; }
+        if (lane == bl) ++h;
+    }
+    for (int d = 32; d > 0; d >>= 1) np += __shfl_xor(np, d);
+    if (lane == 0) sm.nred[wave] = np;
+    __syncthreads();
+    // the part's internal runs: those of the threads, and those joined
+    // across threads that touch neither end of the part
+    PeakList fin;
+    fin.init();
+    int32_t total = 0;
+    Run bhead, btail;
+    bool bfull;
+    join_block_runs(sm, min_width, fin, total, bhead, btail, bfull);
+    if (tid != 0) return;
+    for (int w = 0; w < kTopWaves; ++w) {
+        total += sm.nred[w];
+        for (int a = 0; a < kMaxPeaks; ++a)
+            if (sm.wi[w][a] != INT64_MAX) fin.insert(sm.wv[w][a], sm.wi[w][a], sm.ww[w][a]);
+    }
+    PartStats& o = rp[part];
+    o.full = bfull ? 1 : 0;
+    o.head = bhead;
+    o.tail = btail;
+    o.np = total;
+    for (int a = 0; a < kMaxPeaks; ++a) { o.pv[a] = fin.v[a]; o.pi[a] = fin.i[a]; o.pw[a] = fin.w[a]; }
+}
+
+// last kernel: one thread per row joins the parts in order and writes the
+// row's results as k_periodogram does
+__global__ __launch_bounds__(64) void k_pgram_final(const PartStats* __restrict__ ps, int64_t rows, int parts,
+                                                    const double* __restrict__ periods, int32_t min_width,
+                                                    int32_t max_peaks, float* __restrict__ sde,
+                                                    float* __restrict__ mean_out, float* __restrict__ sd_out,
+                                                    int32_t* __restrict__ n_peaks, float* __restrict__ pval,
+                                                    int64_t* __restrict__ pidx, int32_t* __restrict__ pwidth,
+                                                    int32_t* __restrict__ pharm) {
+    const int64_t row = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (row >= rows) return;
+    const PartStats* rp = ps + row * parts;
+    int64_t m;
+    double mean, sdv;
+    row_mean_sd(rp, parts, true, m, mean, sdv);
+    float mx = -INFINITY;
+    int64_t amx = INT64_MAX;
+    PeakList fin;
+    fin.init();
+    int32_t total = 0;
+    Run open{0, -INFINITY, INT64_MAX};
+    for (int p = 0; p < parts; ++p) {
+        const PartStats& o = rp[p];
+        if (beats(o.mx, o.amx, mx, amx)) { mx = o.mx; amx = o.amx; }
+        total += o.np;
+        for (int a = 0; a < kMaxPeaks; ++a)
+            if (o.pi[a] != INT64_MAX) fin.insert(o.pv[a], o.pi[a], o.pw[a]);
+        if (o.full) {
+            open = join(open, o.head);
+        } else {
+            const Run r = join(open, o.head);
+            if (r.len > min_width) { ++total; fin.insert(r.mx, r.arg, (int32_t)r.len); }
+            open = o.tail;
+        }
+    }
+    if (open.len > min_width) { ++total; fin.insert(open.mx, open.arg, (int32_t)open.len); }
+    sde[row] = (float)((m && sdv > 0.0) ? ((double)mx - mean) / sdv : 0.0);
+    mean_out[row] = (float)mean;
     sd_out[row] = (float)sdv;
     n_peaks[row] = total;
     const double p0 = (periods && fin.i[0] != INT64_MAX) ? periods[fin.i[0]] : 0.0;
@@ -462,9 +784,37 @@ hipError_t launch_periodogram(const float* values, int64_t rows, int64_t len, co
                               float* mean, float* sd, int32_t* n_peaks, float* pval, int64_t* pidx,
                               int32_t* pwidth, int32_t* pharm, hipStream_t s) {
     if (rows == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_periodogram, dim3((unsigned)rows), dim3(kTopThreads), 0, s, values, periods, len,
-                       nsigma, min_width, max_peaks, sde, mean, sd, n_peaks, pval, pidx, pwidth, pharm);
-    return hipGetLastError();
+    // few long rows: each split over enough blocks to fill the chip (parts
+    // of at least 16k scores), with stream-ordered scratch for the parts'
+    // results; one block per row otherwise, and inside a graph capture
+    int parts = 1;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+        int dev = 0, n_cu = 256;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+        const int64_t want = (2 * (int64_t)n_cu + rows - 1) / rows;
+        parts = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(want, 256), len / 16384));
+    }
+    if (parts <= 1) {
+        hipLaunchKernelGGL(k_periodogram, dim3((unsigned)rows), dim3(kTopThreads), 0, s, values, periods,
+                           len, nsigma, min_width, max_peaks, sde, mean, sd, n_peaks, pval, pidx, pwidth,
+                           pharm);
+        return hipGetLastError();
+    }
+    PartStats* ps = nullptr;
+    hipError_t e = hipMallocAsync((void**)&ps, sizeof(PartStats) * rows * parts, s);
+    if (e != hipSuccess) return e;
+    const dim3 grid((unsigned)(rows * parts));
+    hipLaunchKernelGGL(k_pgram_stats, grid, dim3(kTopThreads), 0, s, values, len, parts, 0, ps);
+    hipLaunchKernelGGL(k_pgram_stats, grid, dim3(kTopThreads), 0, s, values, len, parts, 1, ps);
+    hipLaunchKernelGGL(k_pgram_runs, grid, dim3(kTopThreads), 0, s, values, len, parts, nsigma, min_width, ps);
+    hipLaunchKernelGGL(k_pgram_final, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, s, (const PartStats*)ps,
+                       rows, parts, periods, min_width, max_peaks, sde, mean, sd, n_peaks, pval, pidx, pwidth,
+                       pharm);
+    e = hipGetLastError();
+    (void)hipFreeAsync(ps, s);
+    return e;
 }
 
 hipError_t launch_topk(const float* values, int64_t rows, int64_t len, const float* gate,

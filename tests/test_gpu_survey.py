@@ -208,11 +208,13 @@ def test_survey_fp8(torch_dev):
 
 
 @pytest.mark.parametrize("rows,n,nsig,mw", [(1, 0, 3.0, 3), (3, 40, 0.5, 0), (4, 5000, 1.0, 3),
-                                            (2, 100_003, 2.0, 2), (1, 2_000_000, 3.0, 3)])
+                                            (2, 100_003, 2.0, 2), (1, 2_000_000, 3.0, 3),
+                                            (1, 300_001, 0.0, 3)])
 def test_periodogram_peaks_match_oracle(torch_dev, rows, n, nsig, mw):
     """SDE, mean, sd, peak count and the best peaks against the oracle: values
     and indices exact, statistics to FP32 rounding. Smooth rows make long runs
-    that cross the kernel's per-thread chunks."""
+    that cross the kernel's per-thread chunks; long rows are split over many
+    blocks."""
     from paper_2312_02063_amd import periodogram_peaks
     torch = torch_dev
     rng = np.random.default_rng(rows * 31 + n)
@@ -238,6 +240,31 @@ def test_periodogram_peaks_match_oracle(torch_dev, rows, n, nsig, mw):
     np.testing.assert_allclose(g["sde"], o["sde"], rtol=1e-5, atol=1e-6)
     np.testing.assert_allclose(g["mean"], o["mean"], rtol=1e-5, atol=1e-6)
     np.testing.assert_allclose(g["sd"], o["sd"], rtol=1e-5, atol=1e-6)
+
+
+def test_periodogram_run_spanning_many_parts(torch_dev):
+    """A long row split over many blocks with one plateau far above the
+    threshold covering whole parts, and a second plateau ending at the row's
+    last score: runs joined across parts, and a run touching the row's end."""
+    from paper_2312_02063_amd import periodogram_peaks
+    torch = torch_dev
+    rng = np.random.default_rng(5)
+    n = 2_000_000
+    x = rng.normal(size=(1, n)).astype(np.float32)
+    x[0, 50_000:180_000] = 20.0           # mean 1.45, sd 5.4: threshold 17.7
+    x[0, 120_001] = 25.0                  # the plateau's maximum, inside a middle part
+    x[0, 1_990_000:] = 30.0
+    periods = 1.0 / np.linspace(1.0, 5.0, n)
+    _say("periodogram plateau over many parts")
+    r = periodogram_peaks(_dev(torch, x, torch.float32), _dev(torch, periods, torch.float64), 3.0, 3, 6)
+    torch.cuda.synchronize()
+    o = oracle.periodogram(x, periods, 3.0, 3, 6)
+    g = {k: v.cpu().numpy() for k, v in r.items()}
+    for key in ("n_peaks", "idx", "val", "width", "harmonic"):
+        np.testing.assert_array_equal(g[key], o[key])
+    assert g["idx"][0, 0] == 1_990_000 and g["width"][0, 0] == 10_000
+    assert g["idx"][0, 1] == 120_001 and g["width"][0, 1] == 130_000
+    np.testing.assert_allclose(g["sde"], o["sde"], rtol=1e-5, atol=1e-6)
 
 
 def test_survey_replay_uses_current_weights(torch_dev):
