@@ -1225,6 +1225,433 @@ __global__ __launch_bounds__(256) void k_conv1_dw(const typename P::T* __restric
     }
 }
 
+// ------------------------------------------------------------------ fused backward of the convolution blocks (bf16)
+//
+// Data gradients. One wave per input carries the pooled gradient of block 4
+// down to block 1, as k_convstack_bf16_w carries the input up: the block's
+// gradient is unpooled with its mask into LDS, the transposed circular
+// convolution runs on MFMA with the backward weights (k in the same 32-steps
+// as k_gemm with ConvRows and sgn -1, rounded as EpStore rounds: the result is
+// bit-identical to the layer path), and the result (the pooled gradient of
+// the block below) goes to HBM for that block's weight gradient and, unpooled
+// with that block's mask, into LDS for the next step down.
+constexpr int kBP = 4;                                // waves (inputs in flight) per block
+constexpr int kP4Ld = 72, kP3Ld = 72, kP2Ld = 40;     // rows of dpre4 [32][64], dpre3 [64][64], dpre2 [128][32]
+constexpr int kB4Ld = 328, kB3Ld = 328, kB2Ld = 168;  // rows of the backward weights [Cin][5 Cout]
+
+struct BwdSlice {
+    uint16_t buf0[128 * kP2Ld];   // dpre4 [32][kP4Ld] with m3 bytes [32][64] after it; then dpre2
+    uint16_t buf1[64 * kP3Ld];    // dpre3
+    uint8_t m2[64 * 32];
+};
+struct BwdLds {
+    uint16_t w4[64 * kB4Ld];
+    uint16_t w3[32 * kB3Ld];
+    uint16_t w2[16 * kB2Ld];
+    BwdSlice wv[kBP];
+};
+constexpr int kM3Off = 32 * kP4Ld * 2;                // byte offset of m3 in buf0
+static_assert(kM3Off + 32 * 64 <= 128 * kP2Ld * 2, "dpre4 and m3 share buf0");
+static_assert(kM3Off % 16 == 0 && sizeof(BwdSlice) % 16 == 0, "16-byte LDS groups");
+static_assert(sizeof(BwdLds) <= 160 * 1024, "LDS budget");
+
+// The transposed conv of one input by one wave. dpre [L][PLD]: gradient at
+// the block's COUT pre-activations; w [CIN][WLD]: backward weights, k =
+// dx*COUT + co. Output (x, ci) = sum_k dpre[(x - dx + 2) mod L][co] w[ci][k],
+// rounded to bf16, stored to gout [L][CIN]; with kNext also unpooled with the
+// lower block's mask ([L][CIN] bytes: bit 0 the winner's parity, bit 1 its
+// pre-activation > 0) into next [2L][NLD].
+template <int L, int CIN, int COUT, int PLD, int WLD, int NLD, int RB, int CB, bool kNext>
+__device__ __forceinline__ void convT_one(const uint16_t* __restrict__ dpre, const uint16_t* __restrict__ w,
+                                          uint16_t* __restrict__ gout, const uint8_t* __restrict__ mask,
+                                          uint16_t* __restrict__ next) {
+    constexpr int K = 5 * COUT;
+    static_assert(K % 32 == 0 && COUT % 8 == 0, "k steps within one dx");
+    constexpr int KSTEPS = K / 32;
+    constexpr int NRT = L / (16 * RB), NCT = CIN / (16 * CB);
+    static_assert(NRT * 16 * RB == L && NCT * 16 * CB == CIN, "tiles cover the output");
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15, q = lane >> 4;
+    for (int t = 0; t < NRT * NCT; ++t) {
+        const int rt = t / NCT, ct = t - rt * NCT;
+        f32x4 acc[RB][CB];
+        for (int i = 0; i < RB; ++i)
+            for (int j = 0; j < CB; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < KSTEPS; ++ks) {
+            const int k = ks * 32 + q * 8;
+            const int dx = k / COUT, c0 = k - dx * COUT;
+            bf16x8 a[RB], b[CB];
+            for (int i = 0; i < RB; ++i) {
+                int pos = rt * 16 * RB + i * 16 + r - dx + 2;
+                pos = pos < 0 ? pos + L : (pos >= L ? pos - L : pos);
+                a[i] = *reinterpret_cast<const bf16x8*>(dpre + pos * PLD + c0);
+            }
+            for (int j = 0; j < CB; ++j)
+                b[j] = *reinterpret_cast<const bf16x8*>(w + (ct * 16 * CB + j * 16 + r) * WLD + k);
+            for (int i = 0; i < RB; ++i)
+                for (int j = 0; j < CB; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        for (int i = 0; i < RB; ++i) {
+            const int x0 = rt * 16 * RB + i * 16 + q * 4;
+            for (int j = 0; j < CB; ++j) {
+                const int n = ct * 16 * CB + j * 16 + r;
+                for (int e = 0; e < 4; ++e) {
+                    const int xx = x0 + e;
+                    const uint16_t h = f2bf(acc[i][j][e]);
+                    gout[xx * CIN + n] = h;
+                    if constexpr (kNext) {
+                        const uint32_t mk = mask[xx * CIN + n];
+                        const int par = (int)(mk & 1u);
+                        next[(2 * xx + par) * NLD + n] = (mk & 2u) ? h : (uint16_t)0;
+                        next[(2 * xx + 1 - par) * NLD + n] = 0;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Unpool 8 channels of one pooled position: g = 8 bf16 gradients, k = their
+// 8 mask bytes; e0 / e1 receive the values at the even / odd position.
+__device__ __forceinline__ void unpool8(uint4 g, uint2 k, uint4& e0, uint4& e1) {
+    const uint32_t gv[4] = {g.x, g.y, g.z, g.w};
+    uint32_t r0[4], r1[4];
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t kb = (j < 2 ? k.x : k.y) >> (16 * (j & 1));
+        const uint32_t ma = kb & 3u, mb = (kb >> 8) & 3u;
+        const uint32_t lo = gv[j] & 0xffffu, hi = gv[j] & 0xffff0000u;
+        r0[j] = (ma == 2u ? lo : 0u) | (mb == 2u ? hi : 0u);
+        r1[j] = (ma == 3u ? lo : 0u) | (mb == 3u ? hi : 0u);
+    }
+    e0 = make_uint4(r0[0], r0[1], r0[2], r0[3]);
+    e1 = make_uint4(r1[0], r1[1], r1[2], r1[3]);
+}
+
+// The values of 8 channels kept at the position whose mask bits 0-1 equal
+// sel (2: the even one, 3: the odd one); the others are 0.
+__device__ __forceinline__ uint4 unpool_at(uint4 g, uint2 k, uint32_t sel) {
+    const uint32_t gv[4] = {g.x, g.y, g.z, g.w};
+    uint32_t r[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t kb = (j < 2 ? k.x : k.y) >> (16 * (j & 1));
+        r[j] = ((kb & 3u) == sel ? gv[j] & 0xffffu : 0u) | (((kb >> 8) & 3u) == sel ? gv[j] & 0xffff0000u : 0u);
+    }
+    return make_uint4(r[0], r[1], r[2], r[3]);
+}
+
+// d4 [B][16][64], m4 [B][16][64], m3 [B][32][64], m2 [B][64][32] -> d3 [B][32][64],
+// d2 [B][64][32], d1 [B][128][16] (pooled gradients of blocks 3, 2, 1).
+__global__ __launch_bounds__(kBP * 64, 1) void k_convstack_bwd_bf16(
+    int B, const uint16_t* __restrict__ wb4, const uint16_t* __restrict__ wb3,
+    const uint16_t* __restrict__ wb2, const uint16_t* __restrict__ d4, const uint8_t* __restrict__ m4,
+    const uint8_t* __restrict__ m3, const uint8_t* __restrict__ m2, uint16_t* __restrict__ d3,
+    uint16_t* __restrict__ d2, uint16_t* __restrict__ d1) {
+    __shared__ __attribute__((aligned(16))) BwdLds sm;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = tid; i < 64 * kB4Ld; i += kBP * 64) {
+        const int n = i / kB4Ld, k = i - n * kB4Ld;
+        sm.w4[i] = k < 320 ? wb4[n * 320 + k] : (uint16_t)0;
+    }
+    for (int i = tid; i < 32 * kB3Ld; i += kBP * 64) {
+        const int n = i / kB3Ld, k = i - n * kB3Ld;
+        sm.w3[i] = k < 320 ? wb3[n * 320 + k] : (uint16_t)0;
+    }
+    for (int i = tid; i < 16 * kB2Ld; i += kBP * 64) {
+        const int n = i / kB2Ld, k = i - n * kB2Ld;
+        sm.w2[i] = k < 160 ? wb2[n * 160 + k] : (uint16_t)0;
+    }
+    __syncthreads();   // the only block-wide wait: weights staged
+    BwdSlice& ws = sm.wv[wave];
+    uint8_t* m3s = reinterpret_cast<uint8_t*>(ws.buf0) + kM3Off;
+    const int64_t stride = (int64_t)gridDim.x * kBP;
+    int64_t fi = (int64_t)blockIdx.x * kBP + wave;
+    // the next input's data, loaded while the current one is computed: its
+    // gradient and mask of block 4 (two groups of 8 per lane) and the masks
+    // of blocks 3 and 2 (two 16-byte groups each)
+    uint4 ng[2], nk3[2], nk2[2];
+    uint2 nk4[2];
+    auto load = [&](int64_t f) {
+        for (int h = 0; h < 2; ++h) {
+            if (f < B) {
+                ng[h] = *reinterpret_cast<const uint4*>(d4 + f * 1024 + h * 512 + lane * 8);
+                nk4[h] = *reinterpret_cast<const uint2*>(m4 + f * 1024 + h * 512 + lane * 8);
+                nk3[h] = *reinterpret_cast<const uint4*>(m3 + f * 2048 + h * 1024 + lane * 16);
+                nk2[h] = *reinterpret_cast<const uint4*>(m2 + f * 2048 + h * 1024 + lane * 16);
+            } else {
+                ng[h] = nk3[h] = nk2[h] = make_uint4(0u, 0u, 0u, 0u);
+                nk4[h] = make_uint2(0u, 0u);
+            }
+        }
+    };
+    load(fi);
+    for (; fi < B; fi += stride) {
+        for (int h = 0; h < 2; ++h) {
+            *reinterpret_cast<uint4*>(m3s + h * 1024 + lane * 16) = nk3[h];
+            *reinterpret_cast<uint4*>(ws.m2 + h * 1024 + lane * 16) = nk2[h];
+            const int e0 = h * 512 + lane * 8, xp = e0 >> 6, c0 = e0 & 63;
+            uint4 ev, od;
+            unpool8(ng[h], nk4[h], ev, od);
+            *reinterpret_cast<uint4*>(ws.buf0 + (2 * xp) * kP4Ld + c0) = ev;
+            *reinterpret_cast<uint4*>(ws.buf0 + (2 * xp + 1) * kP4Ld + c0) = od;
+        }
+        load(fi + stride);
+        wave_lds_sync();
+        convT_one<32, 64, 64, kP4Ld, kB4Ld, kP3Ld, 2, 4, true>(ws.buf0, sm.w4, d3 + fi * 2048, m3s, ws.buf1);
+        wave_lds_sync();
+        convT_one<64, 32, 64, kP3Ld, kB3Ld, kP2Ld, 4, 2, true>(ws.buf1, sm.w3, d2 + fi * 2048, ws.m2, ws.buf0);
+        wave_lds_sync();
+        convT_one<128, 16, 32, kP2Ld, kB2Ld, 0, 8, 1, false>(ws.buf0, sm.w2, d1 + fi * 2048, nullptr, nullptr);
+        wave_lds_sync();   // buf0 and the masks are reused by the next input
+    }
+}
+
+// Weight and bias gradients of conv block l = 2 .. 4 (bf16). The batch is cut
+// into groups of 8 inputs and each block takes a contiguous range of groups.
+// For 32 output positions at a time, the gradient at the block's
+// pre-activations (its pooled gradient unpooled with the mask) and the
+// block's input at those positions -2 .. +2 are staged in LDS with the 8
+// inputs innermost ([position][channel][8]), so that an MFMA k-step is 4
+// positions x 8 inputs and every operand fragment is one aligned 16-byte
+// read. Channel slots are XOR-swizzled within groups of 8 by the position,
+// which keeps both the transposing writes and the fragment reads free of
+// most bank conflicts. The waves split the output columns (n = dx*CIN + ci)
+// in WN parts and the k-steps in WK; each block writes its FP32 sums to
+// part_out[block][COUT][5 CIN] and its bias sums to bias_out[block][COUT],
+// which are added up in block order (deterministic).
+__device__ __forceinline__ int dw_slot(int pos, int c, int C) {
+    return pos * C + (c ^ (((c >> 3) + pos) & 7));
+}
+
+// out[j] = channel j of the 8 inputs in v (v[s] = 8 channels of input s).
+__device__ __forceinline__ uint4 tr8(const uint4 (&v)[8], int j) {
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t a = (&v[2 * k].x)[j >> 1], b = (&v[2 * k + 1].x)[j >> 1];
+        w[k] = (j & 1) ? ((a >> 16) | (b & 0xffff0000u)) : ((a & 0xffffu) | (b << 16));
+    }
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+template <int L, int CIN, int COUT, int WN, int WK>
+struct DwShape {
+    static constexpr int MT = COUT / 16, NT = 5 * CIN / 16, NTW = NT / WN;
+    static constexpr int DQ = 32 * COUT * 8, AQ = 36 * CIN * 8;           // bf16 elements
+    static constexpr int RED = (WK - 1) * WN * MT * NTW * 256;            // floats
+    static constexpr int STAGE = 2 * (DQ + AQ), REDB = 4 * RED, DBB = 4 * 256 * 4;
+    static constexpr int BYTES = STAGE > REDB ? (STAGE > DBB ? STAGE : DBB) : (REDB > DBB ? REDB : DBB);
+};
+
+template <int L, int CIN, int COUT, int WN, int WK>
+__global__ __launch_bounds__(256, 2) void k_conv_dw_bf16(int B, int groups_per_block,
+                                                         const uint16_t* __restrict__ dact,
+                                                         const uint8_t* __restrict__ mask,
+                                                         const uint16_t* __restrict__ act,
+                                                         float* __restrict__ part_out,
+                                                         float* __restrict__ bias_out) {
+    using S = DwShape<L, CIN, COUT, WN, WK>;
+    constexpr int MT = S::MT, NTW = S::NTW;
+    static_assert(WN * WK == 4 && S::NT % WN == 0, "wave split");
+    static_assert(L % 32 == 0 && CIN % 16 == 0 && COUT % 16 == 0, "tile shapes");
+    __shared__ __attribute__((aligned(16))) uint8_t smem[S::BYTES];
+    uint16_t* dq = reinterpret_cast<uint16_t*>(smem);
+    uint16_t* aq = dq + S::DQ;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, q = lane >> 4;
+    const int nw = wave % WN, kw = wave / WN;
+    f32x4 acc[MT][NTW];
+    for (int i = 0; i < MT; ++i)
+        for (int j = 0; j < NTW; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    float db[4] = {0, 0, 0, 0};
+    // byte offsets of the lane's A and B fragments for k-steps kw and kw + WK
+    int abase[2][MT], bbase[2][NTW];
+    for (int hm = 0; hm < 2; ++hm) {
+        const int p = (kw + hm * WK) * 4 + q;   // position within the chunk
+        for (int i = 0; i < MT; ++i) abase[hm][i] = dw_slot(p, i * 16 + r, COUT) * 16;
+        for (int j = 0; j < NTW; ++j) {
+            const int n = (nw * NTW + j) * 16 + r;
+            const int dx = n / CIN, ci = n - dx * CIN;
+            bbase[hm][j] = S::DQ * 2 + dw_slot(p + dx, ci, CIN) * 16;
+        }
+    }
+    const int ngroups = (B + 7) / 8;
+    const int g0 = blockIdx.x * groups_per_block;
+    const int g1 = min(ngroups, g0 + groups_per_block);
+#pragma unroll 1
+    for (int g = g0; g < g1; ++g) {
+#pragma unroll 1
+        for (int c = 0; c < L / 32; ++c) {
+            __syncthreads();   // the previous chunk's fragments are read
+            // input positions c*32 - 2 ... c*32 + 33 (circular)
+#pragma unroll 1
+            for (int t = tid; t < 36 * (CIN / 8); t += 256) {
+                const int pi = t / (CIN / 8), cg = t - pi * (CIN / 8);
+                int pos = c * 32 + pi - 2;
+                pos = pos < 0 ? pos + L : (pos >= L ? pos - L : pos);
+                uint4 v[8];
+                for (int s = 0; s < 8; ++s) {
+                    const int64_t b = (int64_t)g * 8 + s;
+                    v[s] = b < B ? *reinterpret_cast<const uint4*>(act + (b * L + pos) * CIN + cg * 8)
+                                 : make_uint4(0u, 0u, 0u, 0u);
+                }
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    *reinterpret_cast<uint4*>(aq + dw_slot(pi, cg * 8 + j, CIN) * 8) = tr8(v, j);
+            }
+            // gradient at pre-activation positions c*32 ... c*32 + 31, 4
+            // channels of one pooled position per task: the even positions'
+            // values are formed and stored, then the odd ones'
+#pragma unroll 1
+            for (int t = tid; t < 16 * (COUT / 4); t += 256) {
+                const int xi = t / (COUT / 4), og = t - xi * (COUT / 4);
+                const int xp = c * 16 + xi;
+                uint2 gv[8];
+                uint32_t kv[8];
+#pragma unroll
+                for (int s = 0; s < 8; ++s) {
+                    const int64_t b = (int64_t)g * 8 + s;
+                    gv[s] = make_uint2(0u, 0u);
+                    kv[s] = 0u;
+                    if (b < B) {
+                        const int64_t o = (b * (L / 2) + xp) * COUT + og * 4;
+                        gv[s] = *reinterpret_cast<const uint2*>(dact + o);
+                        kv[s] = *reinterpret_cast<const uint32_t*>(mask + o);
+                    }
+                }
+#pragma unroll
+                for (int s = 0; s < 8; ++s)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const uint32_t h = (j < 2 ? gv[s].x : gv[s].y) >> (16 * (j & 1));
+                        db[j] += (kv[s] >> (8 * j) & 2u) ? bf2f((uint16_t)h) : 0.0f;
+                    }
+#pragma unroll
+                for (int par = 0; par < 2; ++par) {
+                    const uint32_t sel = 2u | (uint32_t)par;
+                    uint32_t e[8][4];
+#pragma unroll
+                    for (int s = 0; s < 8; ++s)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const uint32_t h = ((j < 2 ? gv[s].x : gv[s].y) >> (16 * (j & 1))) & 0xffffu;
+                            e[s][j] = ((kv[s] >> (8 * j)) & 3u) == sel ? h : 0u;
+                        }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        *reinterpret_cast<uint4*>(dq + dw_slot(2 * xi + par, og * 4 + j, COUT) * 8) =
+                            make_uint4(e[0][j] | (e[1][j] << 16), e[2][j] | (e[3][j] << 16),
+                                       e[4][j] | (e[5][j] << 16), e[6][j] | (e[7][j] << 16));
+                }
+            }
+            __syncthreads();
+            // wave kw takes k-steps kw + m*WK (4 positions each); steps m and
+            // m + 2 are 8*WK positions apart and use the same swizzle, so the
+            // fragment addresses are two per-lane bases plus constant offsets
+#pragma unroll 2
+            for (int m = 0; m < 8 / WK; ++m) {
+                const int hm = m & 1, step = (m >> 1) * 8 * WK * 16;   // 8 WK positions, 16 bytes a slot
+                bf16x8 a[MT], bb[NTW];
+                for (int i = 0; i < MT; ++i)
+                    a[i] = *reinterpret_cast<const bf16x8*>(smem + abase[hm][i] + step * COUT);
+                for (int j = 0; j < NTW; ++j)
+                    bb[j] = *reinterpret_cast<const bf16x8*>(smem + bbase[hm][j] + step * CIN);
+                for (int i = 0; i < MT; ++i)
+                    for (int j = 0; j < NTW; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bb[j], acc[i][j], 0, 0, 0);
+            }
+        }
+    }
+    __syncthreads();   // staging space becomes reduction space
+    float* red = reinterpret_cast<float*>(smem);
+    constexpr int TILES = MT * NTW;
+    if constexpr (WK > 1) {
+        if (kw > 0)
+            for (int i = 0; i < MT; ++i)
+                for (int j = 0; j < NTW; ++j)
+                    for (int e = 0; e < 4; ++e)
+                        red[(((kw - 1) * WN + nw) * TILES + i * NTW + j) * 256 + e * 64 + lane] = acc[i][j][e];
+        __syncthreads();
+    }
+    if (kw == 0) {
+        float* out = part_out + (int64_t)blockIdx.x * COUT * (5 * CIN);
+        for (int i = 0; i < MT; ++i)
+            for (int j = 0; j < NTW; ++j)
+                for (int e = 0; e < 4; ++e) {
+                    float v = acc[i][j][e];
+                    for (int z = 1; z < WK; ++z) v += red[(((z - 1) * WN + nw) * TILES + i * NTW + j) * 256 + e * 64 + lane];
+                    const int m = i * 16 + q * 4 + e, n = (nw * NTW + j) * 16 + r;
+                    out[m * (5 * CIN) + n] = v;
+                }
+    }
+    __syncthreads();
+    for (int j = 0; j < 4; ++j) red[tid * 4 + j] = db[j];
+    __syncthreads();
+    if (tid < COUT) {
+        const int og = tid >> 2, j = tid & 3;
+        float s = 0.0f;
+        for (int t = og; t < 256; t += COUT / 4) s += red[t * 4 + j];
+        bias_out[(int64_t)blockIdx.x * COUT + tid] = s;
+    }
+}
+
+// Weight and bias gradients of conv block 1 (one input channel) from its
+// pooled gradient and mask (the unpooling folded in): thread = one pooled
+// position of one input, all 16 channels (the input rounded to bf16 as the
+// forward pass saw it). Per-block sums go to part_out[block][96] (80 weights
+// [co][dx], then 16 biases: the canonical order), added up in block order.
+__global__ __launch_bounds__(256) void k_conv1_dw_bf16(const uint16_t* __restrict__ dact,
+                                                       const uint8_t* __restrict__ mask,
+                                                       const void* __restrict__ x, int xf32, int B,
+                                                       float* __restrict__ part_out) {
+    __shared__ float red[96][4];
+    const int64_t total = (int64_t)B * 128;
+    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+    const int64_t e0 = (int64_t)blockIdx.x * per, e1 = min(total, e0 + per);
+    float acc[96];
+    for (int j = 0; j < 96; ++j) acc[j] = 0.0f;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+        const int64_t b = e >> 7;
+        const int xp = (int)(e & 127);
+        float xv[6];
+        for (int d = 0; d < 6; ++d) {
+            const int64_t o = b * 256 + ((2 * xp + d - 2) & 255);
+            const float v = xf32 ? reinterpret_cast<const float*>(x)[o]
+                                 : bf2f(reinterpret_cast<const uint16_t*>(x)[o]);
+            xv[d] = bf2f(f2bf(v));
+        }
+        const uint4 ga = reinterpret_cast<const uint4*>(dact + e * 16)[0];
+        const uint4 gb = reinterpret_cast<const uint4*>(dact + e * 16)[1];
+        const uint4 mk = *reinterpret_cast<const uint4*>(mask + e * 16);
+        const uint32_t gw[8] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
+        const uint32_t kw[4] = {mk.x, mk.y, mk.z, mk.w};
+#pragma unroll
+        for (int co = 0; co < 16; ++co) {
+            const uint32_t m = (kw[co >> 2] >> (8 * (co & 3))) & 3u;
+            const float gv = (m & 2u) ? bf2f((uint16_t)(gw[co >> 1] >> (16 * (co & 1)))) : 0.0f;
+            const int par = (int)(m & 1u);
+#pragma unroll
+            for (int dx = 0; dx < 5; ++dx) acc[co * 5 + dx] += gv * (par ? xv[dx + 1] : xv[dx]);
+            acc[80 + co] += gv;
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < 96; ++j) {
+        float v = acc[j];
+        for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d);
+        if (lane == 0) red[j][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 96) {
+        float t = 0.0f;
+        for (int w = 0; w < 4; ++w) t += red[threadIdx.x][w];
+        part_out[(int64_t)blockIdx.x * 96 + threadIdx.x] = t;
+    }
+}
+
 // Working copies of the weights from the FP32 masters.
 template <class P>
 __global__ __launch_bounds__(256) void k_pack(const float* __restrict__ w, typename P::T* __restrict__ wf2,
@@ -1550,6 +1977,54 @@ int32_t forward(gpfc_cnn* c, const void* x, int xf32, int B, float* logits, cons
     return e == hipSuccess ? GPFC_OK : cnn_err(e, "k_head");
 }
 
+// Backward of the four convolution blocks of a bf16 network from the pooled
+// gradient of block 4 (in d_a): the data gradients in one pass down the
+// blocks, then each block's weight and bias gradients from its pooled
+// gradient, mask and input.
+template <int L, int CIN, int COUT, int WN, int WK>
+hipError_t conv_dw_bf16(const gpfc_cnn* c, int B, const uint16_t* dact, const uint8_t* mask,
+                        const uint16_t* act, float* gw, float* gb, hipStream_t s) {
+    using namespace gcnn;
+    const int64_t mn = (int64_t)COUT * 5 * CIN;
+    const int groups = (B + 7) / 8;
+    int blocks = (int)std::min<int64_t>(std::min(groups, 2 * c->n_cu), kSplitWs / (mn + COUT));
+    const int gpb = (groups + blocks - 1) / blocks;
+    blocks = (groups + gpb - 1) / gpb;
+    float* part = c->ws;
+    float* bpart = c->ws + (int64_t)blocks * mn;
+    hipLaunchKernelGGL((k_conv_dw_bf16<L, CIN, COUT, WN, WK>), dim3((unsigned)blocks), dim3(256), 0, s, B, gpb,
+                       dact, mask, act, part, bpart);
+    hipLaunchKernelGGL((k_splitk_reduce_w<EpConvDW>), dim3((unsigned)((mn + 3) / 4)), dim3(256), 0, s, part,
+                       blocks, COUT, 5 * CIN, EpConvDW{gw, CIN});
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((COUT + 3) / 4)), dim3(256), 0, s, bpart, blocks, COUT, gb);
+    return hipGetLastError();
+}
+
+int32_t backward_convs_bf16(gpfc_cnn* c, const void* x, int xf32, int B, hipStream_t s) {
+    using namespace gcnn;
+    float* g = c->grad;
+    const uint16_t* d4 = (const uint16_t*)c->d_a;                 // [B][16][64]
+    uint16_t* d3 = (uint16_t*)c->d_b;                              // [B][32][64]
+    uint16_t* d2 = (uint16_t*)c->d_b + (int64_t)B * 2048;          // [B][64][32]
+    uint16_t* d1 = (uint16_t*)c->d_a + (int64_t)B * 2048;          // [B][128][16]
+    const dim3 grid((unsigned)std::min<int64_t>((B + kBP - 1) / kBP, c->n_cu));
+    hipLaunchKernelGGL(k_convstack_bwd_bf16, grid, dim3(kBP * 64), 0, s, B, (const uint16_t*)c->wb4,
+                       (const uint16_t*)c->wb3, (const uint16_t*)c->wb2, d4, c->m4, c->m3, c->m2, d3, d2, d1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return cnn_err(e, "k_convstack_bwd_bf16");
+    e = conv_dw_bf16<32, 64, 64, 4, 1>(c, B, d4, c->m4, (const uint16_t*)c->a3, g + kConvW[4], g + conv_b(4), s);
+    if (e == hipSuccess)
+        e = conv_dw_bf16<64, 32, 64, 2, 2>(c, B, d3, c->m3, (const uint16_t*)c->a2, g + kConvW[3], g + conv_b(3), s);
+    if (e == hipSuccess)
+        e = conv_dw_bf16<128, 16, 32, 1, 4>(c, B, d2, c->m2, (const uint16_t*)c->a1, g + kConvW[2], g + conv_b(2), s);
+    if (e != hipSuccess) return cnn_err(e, "k_conv_dw_bf16");
+    const int parts = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (int64_t)B * 128 / 2048));
+    hipLaunchKernelGGL(k_conv1_dw_bf16, dim3((unsigned)parts), dim3(256), 0, s, d1, c->m1, x, xf32, B, c->ws);
+    hipLaunchKernelGGL(k_sum_parts, dim3(24), dim3(256), 0, s, c->ws, parts, 96, g + kConvW[1]);
+    e = hipGetLastError();
+    return e == hipSuccess ? GPFC_OK : cnn_err(e, "k_conv1_dw_bf16");
+}
+
 template <class P>
 int32_t backward(gpfc_cnn* c, const void* x, int xf32, int B, hipStream_t s) {
     using namespace gcnn;
@@ -1577,6 +2052,8 @@ int32_t backward(gpfc_cnn* c, const void* x, int xf32, int B, hipStream_t s) {
     e = gemm<P>(B, 1024, 256, Rows<P>{dh1, B, 256, 256}, Rows<P>{(const T*)c->f1b, 1024, 256, 256},
                 EpStore<P>{dact, nullptr, 1024}, s);
     if (e != hipSuccess) return cnn_err(e, "fc1 dX");
+    if constexpr (__is_same(P, BF16))
+        if (c->fused) return backward_convs_bf16(c, x, xf32, B, s);
     T* acts[5] = {nullptr, (T*)c->a1, (T*)c->a2, (T*)c->a3, (T*)c->a4};
     uint8_t* masks[5] = {nullptr, c->m1, c->m2, c->m3, c->m4};
     void* wbs[5] = {nullptr, nullptr, c->wb2, c->wb3, c->wb4};

@@ -294,24 +294,43 @@ def test_train_step_equals_backward_then_adam(torch_dev):
     assert torch.equal(a.get_params(), b.get_params())
 
 
-@pytest.mark.parametrize("B", [7, 300])
-def test_fused_training_forward_bit_identical(torch_dev, B):
-    """A training step whose forward runs the fused convolution stack (it also
-    writes the activations and pooling masks the backward pass reads) gives the
-    same loss and parameters, bit for bit, as one whose forward runs layer by
-    layer."""
+@pytest.mark.parametrize("B", [7, 300, 5000])
+def test_fused_training_matches_layer_path(torch_dev, B):
+    """A bf16 training step through the fused kernels (the convolution stack
+    forward, which also writes the activations and pooling masks; the
+    backward data gradients carried down the blocks in one pass; per-block
+    weight gradients over groups of 8 inputs) against the same step layer by
+    layer: the loss and the fully connected layers' gradients are identical
+    bit for bit, the convolution gradients differ only by FP32 summation
+    order (the data gradients they are formed from are bit-identical, so a
+    relative difference above 1e-5 would mean a wrong term)."""
     torch = torch_dev
     from paper_2312_02063_amd import CNN_BF16
     p = _params(35)
     x, y = _inputs(36, B)
     xt = torch.tensor(x, dtype=torch.float32, device="cuda")
     yt = torch.tensor(y, dtype=torch.float32, device="cuda")
-    a = _net(torch, CNN_BF16, p, 512)
-    b = _net(torch, CNN_BF16, p, 512)
+    a = _net(torch, CNN_BF16, p, max(B, 512))
+    b = _net(torch, CNN_BF16, p, max(B, 512))
     b.set_fused(False)
-    _say(f"cnn fused vs layered training step B={B}")
+    _say(f"cnn fused vs layered backward B={B}")
+    ga = torch.empty(a.n_params, dtype=torch.float32, device="cuda")
+    gb = torch.empty(b.n_params, dtype=torch.float32, device="cuda")
+    la = a.backward(xt, yt, grad_out=ga).clone()
+    lb = b.backward(xt, yt, grad_out=gb).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(la, lb)
+    ga = ga.cpu().numpy().astype(np.float64)
+    gb = gb.cpu().numpy().astype(np.float64)
+    for name, lo, hi in SEGMENTS:
+        if name.startswith("fc"):
+            assert np.array_equal(ga[lo:hi], gb[lo:hi]), name
+        else:
+            err = _rel(ga[lo:hi], gb[lo:hi])
+            print(f"B={B} {name}: fused vs layer path relative difference {err:.2e}")
+            assert err < 1e-5, name
+    # and the same holds through training steps: losses stay within rounding
     for _ in range(2):
-        la = a.train_step(xt, yt, 1e-3).clone()
-        lb = b.train_step(xt, yt, 1e-3).clone()
-        assert torch.equal(la, lb)
-    assert torch.equal(a.get_params(), b.get_params())
+        la = a.train_step(xt, yt, 1e-3).item()
+        lb = b.train_step(xt, yt, 1e-3).item()
+        assert abs(la - lb) <= 1e-5 * max(1.0, abs(lb)), (la, lb)
