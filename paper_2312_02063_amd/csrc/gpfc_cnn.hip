@@ -427,22 +427,42 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const float* __restrict__
     ep.store((int)(i / N), (int)(i % N), v);
 }
 
-// The same with one wave per output for few outputs and many partials (the
-// convolution weight gradients): lane l adds partials l, l + 64, ... in order,
-// the lanes are added by a fixed butterfly (deterministic).
+// The same for many partials: 64 consecutive outputs per block of 16 waves,
+// one output per lane (each partial row is read coalesced); wave w adds
+// partials w, w + 16, ... in that order, then the 16 wave sums are added in
+// wave order (deterministic). Launch with ceil(M*N / 64) blocks of 1024.
 template <class EP>
-__global__ __launch_bounds__(256) void k_splitk_reduce_w(const float* __restrict__ ws, int S, int M,
-                                                         int N, EP ep) {
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
+__global__ __launch_bounds__(1024) void k_splitk_reduce_w(const float* __restrict__ ws, int S, int M,
+                                                          int N, EP ep) {
+    __shared__ float red[16][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t mn = (int64_t)M * N;
-    if (i >= mn) return;
+    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
     float v = 0.0f;
-    for (int z = lane; z < S; z += 64) v += ws[z * mn + i];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if (lane == 0) ep.store((int)(i / N), (int)(i % N), v);
+    if (i < mn)
+        for (int z = wave; z < S; z += 16) v += ws[z * mn + i];
+    red[wave][lane] = v;
+    __syncthreads();
+    if (wave == 0 && i < mn) {
+        float t = 0.0f;
+        for (int w = 0; w < 16; ++w) t += red[w][lane];
+        ep.store((int)(i / N), (int)(i % N), t);
+    }
 }
+
+// Weight and bias gradients of a conv block reduced together: partial rows
+// hold [COUT][5 CIN] weight sums, then COUT bias sums (M = 1, N = mn + COUT).
+struct EpConvDWB {
+    float* gw;
+    float* gb;
+    int Cin, mn;
+    __device__ __forceinline__ void store(int, int j, float v) const {
+        if (j >= mn) { gb[j - mn] = v; return; }
+        const int m = j / (5 * Cin), n = j - m * (5 * Cin);
+        const int dx = n / Cin, ci = n - dx * Cin;
+        gw[((int64_t)m * Cin + ci) * 5 + dx] = v;
+    }
+};
 
 // ------------------------------------------------------------------ small kernels
 
@@ -944,8 +964,12 @@ __global__ __launch_bounds__(kWP * 64, 1) void k_convstack_bf16_w(
 // chain runs k in the same 32-steps as k_gemm, so results are bit-identical.
 constexpr int kFcBK = 64, kFcLd = kFcBK + 8;
 
-template <int BN>
-__global__ __launch_bounds__(256) void k_fc_bf16(int M, int K, const uint16_t* __restrict__ A,
+// EPI selects the epilogue: kFcRelu (bias + ReLU, the forward layer) or
+// kFcStore (plain store: a data gradient, as EpStore). Blocks along y take
+// further column tiles of BN.
+constexpr int kFcRelu = 0, kFcStore = 1;
+template <int BN, int EPI = kFcRelu>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_fc_bf16(int M, int K, const uint16_t* __restrict__ A,
                                                  const uint16_t* __restrict__ W,
                                                  const float* __restrict__ bias,
                                                  uint16_t* __restrict__ out, int ldo) {
@@ -962,21 +986,25 @@ __global__ __launch_bounds__(256) void k_fc_bf16(int M, int K, const uint16_t* _
     const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
     uint4 ra[ACH], rb[BCH];
     auto load = [&](int k0) {
+#pragma unroll
         for (int c = 0; c < ACH; ++c) {
             const int idx = tid + c * 256, row = idx >> 3, col = (idx & 7) * 8;
             ra[c] = (m0 + row < M) ? *reinterpret_cast<const uint4*>(A + (int64_t)(m0 + row) * K + k0 + col)
                                    : make_uint4(0u, 0u, 0u, 0u);
         }
+#pragma unroll
         for (int c = 0; c < BCH; ++c) {
             const int idx = tid + c * 256, row = idx >> 3, col = (idx & 7) * 8;
             rb[c] = *reinterpret_cast<const uint4*>(W + (int64_t)(n0 + row) * K + k0 + col);
         }
     };
     auto store = [&](int buf) {
+#pragma unroll
         for (int c = 0; c < ACH; ++c) {
             const int idx = tid + c * 256, row = idx >> 3, col = (idx & 7) * 8;
             *reinterpret_cast<uint4*>(&sa[buf][row * kFcLd + col]) = ra[c];
         }
+#pragma unroll
         for (int c = 0; c < BCH; ++c) {
             const int idx = tid + c * 256, row = idx >> 3, col = (idx & 7) * 8;
             *reinterpret_cast<uint4*>(&sb[buf][row * kFcLd + col]) = rb[c];
@@ -1011,10 +1039,13 @@ __global__ __launch_bounds__(256) void k_fc_bf16(int M, int K, const uint16_t* _
     for (int i = 0; i < 4; ++i)
         for (int j = 0; j < NJ; ++j) {
             const int n = n0 + wn * WN + j * 16 + r;
-            const float bn = bias[n];
             const int mb = m0 + wm * 64 + i * 16 + q * 4;
-            for (int e = 0; e < 4; ++e)
-                if (mb + e < M) out[(int64_t)(mb + e) * ldo + n] = f2bf(fmaxf(acc[i][j][e] + bn, 0.0f));
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float v = acc[i][j][e];
+                if constexpr (EPI == kFcRelu) v = fmaxf(v + bias[n], 0.0f);
+                if (mb + e < M) out[(int64_t)(mb + e) * ldo + n] = f2bf(v);
+            }
         }
 }
 
@@ -1187,7 +1218,8 @@ __global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ par
 // sums are reduced in LDS and written to part_out[part][co*5+dx], summed in
 // part order by k_sum_parts.
 template <class P>
-__global__ __launch_bounds__(256) void k_conv1_dw(const typename P::T* __restrict__ dpre,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_conv1_dw(
+    const typename P::T* __restrict__ dpre,
                                                   const void* __restrict__ x, int xf32, int B,
                                                   float* __restrict__ part_out) {
     __shared__ float red[80][33];
@@ -1255,12 +1287,28 @@ static_assert(kM3Off + 32 * 64 <= 128 * kP2Ld * 2, "dpre4 and m3 share buf0");
 static_assert(kM3Off % 16 == 0 && sizeof(BwdSlice) % 16 == 0, "16-byte LDS groups");
 static_assert(sizeof(BwdLds) <= 160 * 1024, "LDS budget");
 
+// The values of 8 channels kept at the position whose mask bits 0-1 equal
+// sel (2: the even one, 3: the odd one); the others are 0.
+__device__ __forceinline__ uint4 unpool_at(uint4 g, uint2 k, uint32_t sel) {
+    const uint32_t gv[4] = {g.x, g.y, g.z, g.w};
+    uint32_t r[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t kb = (j < 2 ? k.x : k.y) >> (16 * (j & 1));
+        r[j] = ((kb & 3u) == sel ? gv[j] & 0xffffu : 0u) | (((kb >> 8) & 3u) == sel ? gv[j] & 0xffff0000u : 0u);
+    }
+    return make_uint4(r[0], r[1], r[2], r[3]);
+}
+
 // The transposed conv of one input by one wave. dpre [L][PLD]: gradient at
 // the block's COUT pre-activations; w [CIN][WLD]: backward weights, k =
 // dx*COUT + co. Output (x, ci) = sum_k dpre[(x - dx + 2) mod L][co] w[ci][k],
 // rounded to bf16, stored to gout [L][CIN]; with kNext also unpooled with the
 // lower block's mask ([L][CIN] bytes: bit 0 the winner's parity, bit 1 its
-// pre-activation > 0) into next [2L][NLD].
+// pre-activation > 0) into next [2L][NLD]. The MFMA takes the weights as its
+// first operand, so a lane ends with 4 consecutive channels of one position
+// (8-byte stores, one 4-byte mask read); the products and their k order are
+// those of k_gemm with ConvRows (sgn -1), whose output is the transpose.
 template <int L, int CIN, int COUT, int PLD, int WLD, int NLD, int RB, int CB, bool kNext>
 __device__ __forceinline__ void convT_one(const uint16_t* __restrict__ dpre, const uint16_t* __restrict__ w,
                                           uint16_t* __restrict__ gout, const uint8_t* __restrict__ mask,
@@ -1274,9 +1322,9 @@ __device__ __forceinline__ void convT_one(const uint16_t* __restrict__ dpre, con
     const int r = lane & 15, q = lane >> 4;
     for (int t = 0; t < NRT * NCT; ++t) {
         const int rt = t / NCT, ct = t - rt * NCT;
-        f32x4 acc[RB][CB];
-        for (int i = 0; i < RB; ++i)
-            for (int j = 0; j < CB; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        f32x4 acc[CB][RB];
+        for (int j = 0; j < CB; ++j)
+            for (int i = 0; i < RB; ++i) acc[j][i] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int ks = 0; ks < KSTEPS; ++ks) {
             const int k = ks * 32 + q * 8;
@@ -1289,24 +1337,23 @@ __device__ __forceinline__ void convT_one(const uint16_t* __restrict__ dpre, con
             }
             for (int j = 0; j < CB; ++j)
                 b[j] = *reinterpret_cast<const bf16x8*>(w + (ct * 16 * CB + j * 16 + r) * WLD + k);
-            for (int i = 0; i < RB; ++i)
-                for (int j = 0; j < CB; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < CB; ++j)
+                for (int i = 0; i < RB; ++i)
+                    acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j], a[i], acc[j][i], 0, 0, 0);
         }
-        for (int i = 0; i < RB; ++i) {
-            const int x0 = rt * 16 * RB + i * 16 + q * 4;
-            for (int j = 0; j < CB; ++j) {
-                const int n = ct * 16 * CB + j * 16 + r;
-                for (int e = 0; e < 4; ++e) {
-                    const int xx = x0 + e;
-                    const uint16_t h = f2bf(acc[i][j][e]);
-                    gout[xx * CIN + n] = h;
-                    if constexpr (kNext) {
-                        const uint32_t mk = mask[xx * CIN + n];
-                        const int par = (int)(mk & 1u);
-                        next[(2 * xx + par) * NLD + n] = (mk & 2u) ? h : (uint16_t)0;
-                        next[(2 * xx + 1 - par) * NLD + n] = 0;
-                    }
+        for (int j = 0; j < CB; ++j) {
+            const int n0 = ct * 16 * CB + j * 16 + q * 4;   // 4 channels n0 .. n0 + 3
+            for (int i = 0; i < RB; ++i) {
+                const int xx = rt * 16 * RB + i * 16 + r;
+                const uint32_t h01 = f2bf2(acc[j][i][0], acc[j][i][1]);
+                const uint32_t h23 = f2bf2(acc[j][i][2], acc[j][i][3]);
+                *reinterpret_cast<uint2*>(gout + xx * CIN + n0) = make_uint2(h01, h23);
+                if constexpr (kNext) {
+                    const uint32_t mk = *reinterpret_cast<const uint32_t*>(mask + xx * CIN + n0);
+                    const uint4 ev = unpool_at(make_uint4(h01, h23, 0u, 0u), make_uint2(mk, 0u), 2u);
+                    const uint4 od = unpool_at(make_uint4(h01, h23, 0u, 0u), make_uint2(mk, 0u), 3u);
+                    *reinterpret_cast<uint2*>(next + (2 * xx) * NLD + n0) = make_uint2(ev.x, ev.y);
+                    *reinterpret_cast<uint2*>(next + (2 * xx + 1) * NLD + n0) = make_uint2(od.x, od.y);
                 }
             }
         }
@@ -1327,19 +1374,6 @@ __device__ __forceinline__ void unpool8(uint4 g, uint2 k, uint4& e0, uint4& e1) 
     }
     e0 = make_uint4(r0[0], r0[1], r0[2], r0[3]);
     e1 = make_uint4(r1[0], r1[1], r1[2], r1[3]);
-}
-
-// The values of 8 channels kept at the position whose mask bits 0-1 equal
-// sel (2: the even one, 3: the odd one); the others are 0.
-__device__ __forceinline__ uint4 unpool_at(uint4 g, uint2 k, uint32_t sel) {
-    const uint32_t gv[4] = {g.x, g.y, g.z, g.w};
-    uint32_t r[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const uint32_t kb = (j < 2 ? k.x : k.y) >> (16 * (j & 1));
-        r[j] = ((kb & 3u) == sel ? gv[j] & 0xffffu : 0u) | (((kb >> 8) & 3u) == sel ? gv[j] & 0xffff0000u : 0u);
-    }
-    return make_uint4(r[0], r[1], r[2], r[3]);
 }
 
 // d4 [B][16][64], m4 [B][16][64], m3 [B][32][64], m2 [B][64][32] -> d3 [B][32][64],
@@ -1418,9 +1452,9 @@ __global__ __launch_bounds__(kBP * 64, 1) void k_convstack_bwd_bf16(
 // read. Channel slots are XOR-swizzled within groups of 8 by the position,
 // which keeps both the transposing writes and the fragment reads free of
 // most bank conflicts. The waves split the output columns (n = dx*CIN + ci)
-// in WN parts and the k-steps in WK; each block writes its FP32 sums to
-// part_out[block][COUT][5 CIN] and its bias sums to bias_out[block][COUT],
-// which are added up in block order (deterministic).
+// in WN parts and the k-steps in WK; each block writes one row of FP32 sums
+// to part_out: [COUT][5 CIN] weight sums, then COUT bias sums; the rows are
+// added up in block order (deterministic).
 __device__ __forceinline__ int dw_slot(int pos, int c, int C) {
     return pos * C + (c ^ (((c >> 3) + pos) & 7));
 }
@@ -1450,8 +1484,7 @@ __global__ __launch_bounds__(256, 2) void k_conv_dw_bf16(int B, int groups_per_b
                                                          const uint16_t* __restrict__ dact,
                                                          const uint8_t* __restrict__ mask,
                                                          const uint16_t* __restrict__ act,
-                                                         float* __restrict__ part_out,
-                                                         float* __restrict__ bias_out) {
+                                                         float* __restrict__ part_out) {
     using S = DwShape<L, CIN, COUT, WN, WK>;
     constexpr int MT = S::MT, NTW = S::NTW;
     static_assert(WN * WK == 4 && S::NT % WN == 0, "wave split");
@@ -1576,7 +1609,7 @@ __global__ __launch_bounds__(256, 2) void k_conv_dw_bf16(int B, int groups_per_b
         __syncthreads();
     }
     if (kw == 0) {
-        float* out = part_out + (int64_t)blockIdx.x * COUT * (5 * CIN);
+        float* out = part_out + (int64_t)blockIdx.x * (COUT * (5 * CIN) + COUT);
         for (int i = 0; i < MT; ++i)
             for (int j = 0; j < NTW; ++j)
                 for (int e = 0; e < 4; ++e) {
@@ -1593,62 +1626,117 @@ __global__ __launch_bounds__(256, 2) void k_conv_dw_bf16(int B, int groups_per_b
         const int og = tid >> 2, j = tid & 3;
         float s = 0.0f;
         for (int t = og; t < 256; t += COUT / 4) s += red[t * 4 + j];
-        bias_out[(int64_t)blockIdx.x * COUT + tid] = s;
+        part_out[(int64_t)blockIdx.x * (COUT * (5 * CIN) + COUT) + COUT * (5 * CIN) + tid] = s;
     }
 }
 
+// Sum over a wave's 64 lanes, the same bits in every lane: within rows of 16
+// lanes by DPP (swap neighbours, swap pairs, mirror 8, mirror 16), then
+// across rows; a fixed order (deterministic).
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    return v;
+}
+
 // Weight and bias gradients of conv block 1 (one input channel) from its
-// pooled gradient and mask (the unpooling folded in): thread = one pooled
-// position of one input, all 16 channels (the input rounded to bf16 as the
-// forward pass saw it). Per-block sums go to part_out[block][96] (80 weights
-// [co][dx], then 16 biases: the canonical order), added up in block order.
-__global__ __launch_bounds__(256) void k_conv1_dw_bf16(const uint16_t* __restrict__ dact,
-                                                       const uint8_t* __restrict__ mask,
-                                                       const void* __restrict__ x, int xf32, int B,
-                                                       float* __restrict__ part_out) {
+// pooled gradient and mask (the unpooling folded in). A block takes groups
+// of 8 consecutive inputs: their gradients (32 KB), masks (16 KB) and inputs
+// (rounded to bf16 as the forward pass saw them, 4 KB) are copied to LDS with
+// 16-byte loads issued together (the next group's while the current one is
+// computed), then thread = one pooled position of one input, all 16
+// channels. Per-block sums go to part_out[block][96] (80 weights [co][dx],
+// then 16 biases: the canonical order), added up in block order.
+template <bool kXF32>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_conv1_dw_bf16(
+    const uint16_t* __restrict__ dact, const uint8_t* __restrict__ mask, const void* __restrict__ x, int B,
+    int groups_per_block, float* __restrict__ part_out) {
+    __shared__ __attribute__((aligned(16))) uint16_t sd[8 * 128 * 16];
+    __shared__ __attribute__((aligned(16))) uint8_t smk[8 * 128 * 16];
+    __shared__ __attribute__((aligned(16))) uint16_t sx[8 * 256];
     __shared__ float red[96][4];
-    const int64_t total = (int64_t)B * 128;
-    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
-    const int64_t e0 = (int64_t)blockIdx.x * per, e1 = min(total, e0 + per);
+    const int tid = threadIdx.x;
+    const int ngroups = (B + 7) / 8;
+    const int g0 = blockIdx.x * groups_per_block;
+    const int g1 = min(ngroups, g0 + groups_per_block);
     float acc[96];
     for (int j = 0; j < 96; ++j) acc[j] = 0.0f;
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
-        const int64_t b = e >> 7;
-        const int xp = (int)(e & 127);
-        float xv[6];
-        for (int d = 0; d < 6; ++d) {
-            const int64_t o = b * 256 + ((2 * xp + d - 2) & 255);
-            const float v = xf32 ? reinterpret_cast<const float*>(x)[o]
-                                 : bf2f(reinterpret_cast<const uint16_t*>(x)[o]);
-            xv[d] = bf2f(f2bf(v));
-        }
-        const uint4 ga = reinterpret_cast<const uint4*>(dact + e * 16)[0];
-        const uint4 gb = reinterpret_cast<const uint4*>(dact + e * 16)[1];
-        const uint4 mk = *reinterpret_cast<const uint4*>(mask + e * 16);
-        const uint32_t gw[8] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
-        const uint32_t kw[4] = {mk.x, mk.y, mk.z, mk.w};
+    uint4 rd[8], rm[4], rx;
+    auto load = [&](int g) {
+        const int64_t b0 = (int64_t)g * 8;
+        const int nb = (int)min<int64_t>(8, B - b0);   // inputs in the group
 #pragma unroll
-        for (int co = 0; co < 16; ++co) {
-            const uint32_t m = (kw[co >> 2] >> (8 * (co & 3))) & 3u;
-            const float gv = (m & 2u) ? bf2f((uint16_t)(gw[co >> 1] >> (16 * (co & 1)))) : 0.0f;
-            const int par = (int)(m & 1u);
-#pragma unroll
-            for (int dx = 0; dx < 5; ++dx) acc[co * 5 + dx] += gv * (par ? xv[dx + 1] : xv[dx]);
-            acc[80 + co] += gv;
+        for (int i = 0; i < 8; ++i) {                  // 256 chunks of 16 B per input
+            const int c = tid + i * 256;
+            rd[i] = (c >> 8) < nb ? *reinterpret_cast<const uint4*>(dact + b0 * 2048 + (int64_t)c * 8)
+                                  : make_uint4(0u, 0u, 0u, 0u);
         }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {                  // 128 chunks per input
+            const int c = tid + i * 256;
+            rm[i] = (c >> 7) < nb ? *reinterpret_cast<const uint4*>(mask + b0 * 2048 + (int64_t)c * 16)
+                                  : make_uint4(0u, 0u, 0u, 0u);
+        }
+        rx = make_uint4(0u, 0u, 0u, 0u);               // 32 chunks of 8 values per input
+        if ((tid >> 5) < nb) {
+            if constexpr (kXF32) {
+                const float4* xf = reinterpret_cast<const float4*>(reinterpret_cast<const float*>(x) +
+                                                                   b0 * 256 + (int64_t)tid * 8);
+                const float4 u = xf[0], v = xf[1];
+                rx = make_uint4(f2bf2(u.x, u.y), f2bf2(u.z, u.w), f2bf2(v.x, v.y), f2bf2(v.z, v.w));
+            } else {
+                rx = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(x) + b0 * 256 +
+                                                     (int64_t)tid * 8);
+            }
+        }
+    };
+    if (g0 < g1) load(g0);
+    for (int g = g0; g < g1; ++g) {
+        for (int i = 0; i < 8; ++i) reinterpret_cast<uint4*>(sd)[tid + i * 256] = rd[i];
+        for (int i = 0; i < 4; ++i) reinterpret_cast<uint4*>(smk)[tid + i * 256] = rm[i];
+        reinterpret_cast<uint4*>(sx)[tid] = rx;
+        __syncthreads();
+        if (g + 1 < g1) load(g + 1);
+        for (int j = 0; j < 4; ++j) {
+            const int p = tid + j * 256, sp = p >> 7, xp = p & 127;
+            float xv[6];   // input positions 2xp - 2 ... 2xp + 3: pairs xp - 1, xp, xp + 1 (circular)
+            for (int h = 0; h < 3; ++h) {
+                const uint32_t v = reinterpret_cast<const uint32_t*>(sx)[sp * 128 + ((xp + h - 1) & 127)];
+                xv[2 * h] = bf2f((uint16_t)(v & 0xffffu));
+                xv[2 * h + 1] = bf2f((uint16_t)(v >> 16));
+            }
+            const uint4 ga = reinterpret_cast<const uint4*>(sd)[p * 2];
+            const uint4 gb = reinterpret_cast<const uint4*>(sd)[p * 2 + 1];
+            const uint4 mk = reinterpret_cast<const uint4*>(smk)[p];
+            const uint32_t gw[8] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
+            const uint32_t kw[4] = {mk.x, mk.y, mk.z, mk.w};
+#pragma unroll
+            for (int co = 0; co < 16; ++co) {
+                const uint32_t m = (kw[co >> 2] >> (8 * (co & 3))) & 3u;
+                const float gv = (m & 2u) ? bf2f((uint16_t)(gw[co >> 1] >> (16 * (co & 1)))) : 0.0f;
+                const int par = (int)(m & 1u);
+#pragma unroll
+                for (int dx = 0; dx < 5; ++dx) acc[co * 5 + dx] += gv * (par ? xv[dx + 1] : xv[dx]);
+                acc[80 + co] += gv;
+            }
+        }
+        __syncthreads();   // the group's LDS copy is read
     }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
     for (int j = 0; j < 96; ++j) {
-        float v = acc[j];
-        for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d);
+        const float v = wave_sum_dpp(acc[j]);
         if (lane == 0) red[j][wave] = v;
     }
     __syncthreads();
-    if (threadIdx.x < 96) {
+    if (tid < 96) {
         float t = 0.0f;
-        for (int w = 0; w < 4; ++w) t += red[threadIdx.x][w];
-        part_out[(int64_t)blockIdx.x * 96 + threadIdx.x] = t;
+        for (int w = 0; w < 4; ++w) t += red[tid][w];
+        part_out[(int64_t)blockIdx.x * 96 + tid] = t;
     }
 }
 
@@ -1786,7 +1874,7 @@ template <class P>
 hipError_t bias_grad(const typename P::T* d, int64_t rows, int C, float* g, float* ws, hipStream_t s) {
     const int cg = C < 64 ? C : 64;
     const int groups = C / cg;
-    const int parts = (int)std::max<int64_t>(1, std::min<int64_t>(2048 / groups, rows / 256));
+    const int parts = (int)std::max<int64_t>(1, std::min<int64_t>(2048 / groups, rows / 32));
     hipLaunchKernelGGL((k_bias_grad<P>), dim3((unsigned)groups, (unsigned)parts), dim3(256), 0, s, d, rows,
                        C, ws);
     hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((C + 3) / 4)), dim3(256), 0, s, ws, parts, C, g);
@@ -1813,8 +1901,8 @@ hipError_t gemm_splitk(int M, int N, int K, LA la, LB lb, EP ep, float* ws, hipS
     dim3 grid((M + 63) / 64, (N + 63) / 64, S);
     hipLaunchKernelGGL((k_gemm<P, LA, LB, EpPartial>), grid, dim3(256), 0, s, M, N, K, kc, la, lb,
                        EpPartial{ws});
-    if (S >= 16 && (int64_t)M * N <= 65536)
-        hipLaunchKernelGGL((k_splitk_reduce_w<EP>), dim3((unsigned)(((int64_t)M * N + 3) / 4)), dim3(256), 0,
+    if (S >= 16)
+        hipLaunchKernelGGL((k_splitk_reduce_w<EP>), dim3((unsigned)(((int64_t)M * N + 63) / 64)), dim3(1024), 0,
                            s, ws, S, M, N, ep);
     else
         hipLaunchKernelGGL((k_splitk_reduce<EP>), dim3(blocks_for((int64_t)M * N)), dim3(256), 0, s, ws,
@@ -1987,16 +2075,14 @@ hipError_t conv_dw_bf16(const gpfc_cnn* c, int B, const uint16_t* dact, const ui
     using namespace gcnn;
     const int64_t mn = (int64_t)COUT * 5 * CIN;
     const int groups = (B + 7) / 8;
-    int blocks = (int)std::min<int64_t>(std::min(groups, 2 * c->n_cu), kSplitWs / (mn + COUT));
+    const int64_t row = mn + COUT;
+    int blocks = (int)std::min<int64_t>(std::min(groups, 2 * c->n_cu), kSplitWs / row);
     const int gpb = (groups + blocks - 1) / blocks;
     blocks = (groups + gpb - 1) / gpb;
-    float* part = c->ws;
-    float* bpart = c->ws + (int64_t)blocks * mn;
     hipLaunchKernelGGL((k_conv_dw_bf16<L, CIN, COUT, WN, WK>), dim3((unsigned)blocks), dim3(256), 0, s, B, gpb,
-                       dact, mask, act, part, bpart);
-    hipLaunchKernelGGL((k_splitk_reduce_w<EpConvDW>), dim3((unsigned)((mn + 3) / 4)), dim3(256), 0, s, part,
-                       blocks, COUT, 5 * CIN, EpConvDW{gw, CIN});
-    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((COUT + 3) / 4)), dim3(256), 0, s, bpart, blocks, COUT, gb);
+                       dact, mask, act, c->ws);
+    hipLaunchKernelGGL((k_splitk_reduce_w<EpConvDWB>), dim3((unsigned)((row + 63) / 64)), dim3(1024), 0, s,
+                       c->ws, blocks, 1, (int)row, EpConvDWB{gw, gb, CIN, (int)mn});
     return hipGetLastError();
 }
 
@@ -2018,8 +2104,16 @@ int32_t backward_convs_bf16(gpfc_cnn* c, const void* x, int xf32, int B, hipStre
     if (e == hipSuccess)
         e = conv_dw_bf16<128, 16, 32, 1, 4>(c, B, d2, c->m2, (const uint16_t*)c->a1, g + kConvW[2], g + conv_b(2), s);
     if (e != hipSuccess) return cnn_err(e, "k_conv_dw_bf16");
-    const int parts = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (int64_t)B * 128 / 2048));
-    hipLaunchKernelGGL(k_conv1_dw_bf16, dim3((unsigned)parts), dim3(256), 0, s, d1, c->m1, x, xf32, B, c->ws);
+    const int groups = (B + 7) / 8;
+    int parts = std::min(groups, 2 * c->n_cu);   // two blocks per CU overlap one's loads with the other's sums
+    const int gpb = (groups + parts - 1) / parts;
+    parts = (groups + gpb - 1) / gpb;
+    if (xf32)
+        hipLaunchKernelGGL(k_conv1_dw_bf16<true>, dim3((unsigned)parts), dim3(256), 0, s, d1, c->m1, x, B, gpb,
+                           c->ws);
+    else
+        hipLaunchKernelGGL(k_conv1_dw_bf16<false>, dim3((unsigned)parts), dim3(256), 0, s, d1, c->m1, x, B, gpb,
+                           c->ws);
     hipLaunchKernelGGL(k_sum_parts, dim3(24), dim3(256), 0, s, c->ws, parts, 96, g + kConvW[1]);
     e = hipGetLastError();
     return e == hipSuccess ? GPFC_OK : cnn_err(e, "k_conv1_dw_bf16");
@@ -2049,11 +2143,18 @@ int32_t backward(gpfc_cnn* c, const void* x, int xf32, int B, hipStream_t s) {
     e = bias_grad<P>(dh1, B, 256, g + F1B, c->ws, s);
     if (e != hipSuccess) return cnn_err(e, "fc1 bias grad");
     T* dact = (T*)c->d_a;  // [B][1024] = pooled gradient of block 4, position-major
-    e = gemm<P>(B, 1024, 256, Rows<P>{dh1, B, 256, 256}, Rows<P>{(const T*)c->f1b, 1024, 256, 256},
-                EpStore<P>{dact, nullptr, 1024}, s);
+    // bf16: the staged kernel (same MFMA chains and rounding as the GEMM)
+    if (__is_same(P, BF16) && c->fused) {
+        hipLaunchKernelGGL((k_fc_bf16<128, kFcStore>), dim3((unsigned)((B + 127) / 128), 8), dim3(256), 0, s, B,
+                           256, (const uint16_t*)dh1, (const uint16_t*)c->f1b, nullptr, (uint16_t*)dact, 1024);
+        e = hipGetLastError();
+    } else
+        e = gemm<P>(B, 1024, 256, Rows<P>{dh1, B, 256, 256}, Rows<P>{(const T*)c->f1b, 1024, 256, 256},
+                    EpStore<P>{dact, nullptr, 1024}, s);
     if (e != hipSuccess) return cnn_err(e, "fc1 dX");
     if constexpr (__is_same(P, BF16))
-        if (c->fused) return backward_convs_bf16(c, x, xf32, B, s);
+        if (c->fused && ((uintptr_t)x & 15) == 0)   // block 1 reads the input in aligned pairs
+            return backward_convs_bf16(c, x, xf32, B, s);
     T* acts[5] = {nullptr, (T*)c->a1, (T*)c->a2, (T*)c->a3, (T*)c->a4};
     uint8_t* masks[5] = {nullptr, c->m1, c->m2, c->m3, c->m4};
     void* wbs[5] = {nullptr, nullptr, c->wb2, c->wb3, c->wb4};
