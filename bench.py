@@ -123,6 +123,22 @@ def cnn_inference_row(dev, reps, B=262_144):
             "tflops": tf, "peak_tflops": MFMA_BF16_PEAK_TFLOPS, "frac": tf / MFMA_BF16_PEAK_TFLOPS}
 
 
+def cnn_training_row(dev, reps, B=16_384):
+    """bf16 training steps (forward, backward, Adam) at batch B (random bf16
+    inputs, alternating labels)."""
+    import numpy as np
+    import torch
+    from paper_2312_02063_amd import CNN_BF16, Cnn, synth
+    net = Cnn(0, CNN_BF16, B)
+    net.set_params(synth.cnn_init(1003).astype(np.float32))
+    x = torch.randn(B, NBINS, device=dev).to(torch.bfloat16).view(torch.uint16)
+    y = (torch.arange(B, device=dev) % 2).float()
+    ms = _events_ms(lambda: net.train_step(x, y, 1e-5), reps)
+    tf = B * CNN_TRAIN_FLOP / ms / 1e9
+    return {"row": "a9_cnn_training_bf16", "samples_per_s": B / ms * 1e3, "ms_per_step": ms, "batch": B,
+            "tflops": tf, "peak_tflops": MFMA_BF16_PEAK_TFLOPS, "frac": tf / MFMA_BF16_PEAK_TFLOPS}
+
+
 def measure_rows(plan, t, f, pp, periods, survey_stars):
     """Each step of the path on its own at the benchmark shapes (and the
     many-star survey), with the roofline that bounds it."""
@@ -261,6 +277,8 @@ def main():
                     help="stars in the many-star survey measurement (0: skip)")
     ap.add_argument("--cnn-only", action="store_true",
                     help="only the bf16 network inference measurement (for counter runs)")
+    ap.add_argument("--train-only", action="store_true",
+                    help="only the bf16 training step at batch 16,384 (for trace runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -280,6 +298,9 @@ def main():
     dev = torch.device("cuda", 0)
     if args.cnn_only:
         print(json.dumps(cnn_inference_row(dev, max(1, args.steps))), flush=True)
+        return
+    if args.train_only:
+        print(json.dumps(cnn_training_row(dev, max(1, args.steps))), flush=True)
         return
     c = synth.kepler_long_curve(seed=1002)
     assert c.t.size == N_SAMPLES
