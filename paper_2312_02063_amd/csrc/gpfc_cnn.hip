@@ -600,12 +600,18 @@ __global__ __launch_bounds__(256) void k_head_final(const float* __restrict__ pa
 
 constexpr int kTileF = 8;                       // inputs per tile
 constexpr int kFusedThreads = 512;              // 8 waves
-// LDS row strides (elements). Weight rows hold K padded to whole 32-steps plus
-// 8; activation rows hold the channels plus 8 (conv 2-3 outputs). A row
-// stride that is an odd multiple of 16 bytes spreads the 16 rows an MFMA
-// fragment load touches over distinct bank groups.
-constexpr int kW2Ld = 104, kW3Ld = 168, kW4Ld = 328;
-constexpr int kA1Ld = 16, kA2Ld = 40, kA3Ld = 72;
+// LDS layouts. gfx950 serves a 16-byte-per-lane LDS read in four passes, over
+// lanes {0-7, 24-31}, {8-15, 16-23}, {32-39, 56-63} and {40-47, 48-55} (found
+// with bank-conflict counters on a probe of 20 access patterns); a pass is
+// conflict-free when its 16 lanes hit distinct 16-byte slots modulo 256 bytes.
+// An MFMA fragment load has lane (r, q) read row r, 16-byte chunk q, so:
+// weight rows are padded to a stride of 32 mod 64 bytes (K padded to whole
+// 32-steps plus 16), and activation rows keep their exact length with the
+// chunks of a row XOR-swizzled (act_off): none for 32-byte rows (a1), chunk
+// ^ 2*bit 2 of the row for 64-byte rows (a2), chunk ^ (row & 7) for 128-byte
+// rows (a3).
+constexpr int kW2Ld = 112, kW3Ld = 176, kW4Ld = 336;
+constexpr int kA1Ld = 16, kA2Ld = 32, kA3Ld = 64;
 
 struct ConvStackLds {
     uint16_t w2[32 * kW2Ld];
@@ -614,19 +620,19 @@ struct ConvStackLds {
     float w1[16 * 5];
     float b1[16];
     uint16_t xs[kTileF * 256];                     // the tile's inputs (bf16)
-    uint16_t buf0[kTileF * 32 * kA3Ld];            // a1 [F][128][16], then a3 [F][32][72]
-    uint16_t buf1[kTileF * 64 * kA2Ld];            // a2 [F][64][40]
+    uint16_t buf0[kTileF * 32 * kA3Ld];            // a1 [F][128][16], then a3 [F][32][64]
+    uint16_t buf1[kTileF * 64 * kA2Ld];            // a2 [F][64][32]
 };
 static_assert(kTileF * 128 * kA1Ld <= kTileF * 32 * kA3Ld, "a1 must fit where a3 goes");
 
 // Element offset of (row, first channel ci0 of an 8-channel group) in an LDS
-// activation buffer of row stride ILD. Rows of a1 are only 32 bytes, so the
-// two 16-byte groups of a row swap places on rows with bit 3 set: the 16 rows
-// an MFMA fragment load touches then cover all LDS banks once.
+// activation buffer with rows of ILD channels (the swizzles above).
 template <int ILD>
 __device__ __forceinline__ int act_off(int row, int ci0) {
-    if constexpr (ILD == 16) return row * 16 + (ci0 ^ (((row >> 3) & 1) << 3));
-    return row * ILD + ci0;
+    static_assert(ILD == 16 || ILD == 32 || ILD == 64, "activation row lengths");
+    if constexpr (ILD == 32) return row * 32 + (ci0 ^ (((row >> 2) & 1) << 4));
+    if constexpr (ILD == 64) return row * 64 + (ci0 ^ ((row & 7) << 3));
+    return row * 16 + ci0;
 }
 static_assert(sizeof(ConvStackLds) <= 160 * 1024, "LDS budget");
 
@@ -681,7 +687,9 @@ __device__ __forceinline__ void conv_tile(const uint16_t* __restrict__ in,
                 const float bn = bias[n];
                 for (int h = 0; h < 2; ++h) {
                     const float p0 = acc[i][j][2 * h] + bn, p1 = acc[i][j][2 * h + 1] + bn;
-                    out[(f * (L / 2) + (x0 >> 1) + h) * OLD + n] = f2bf(pool_relu(p0, p1));
+                    const int row = f * (L / 2) + (x0 >> 1) + h;
+                    const int o = to_global ? row * OLD + n : act_off<OLD>(row, n & ~7) + (n & 7);
+                    out[o] = f2bf(pool_relu(p0, p1));
                 }
             }
         }
@@ -754,10 +762,9 @@ __global__ __launch_bounds__(kFusedThreads, 1) void k_convstack_bf16(
             uint32_t packed[8];
             for (int j = 0; j < 8; ++j) packed[j] = f2bf2(pooled[2 * j], pooled[2 * j + 1]);
             const int row = f * 128 + xp;
-            const int sw = (row >> 3) & 1;     // the a1 swizzle of act_off<16>
             uint4* dst = reinterpret_cast<uint4*>(sm.buf0 + row * kA1Ld);
-            dst[sw] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
-            dst[sw ^ 1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
+            dst[0] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
+            dst[1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
         }
         __syncthreads();
         conv_tile<128, 16, kA1Ld, 32, kW2Ld, kA2Ld>(sm.buf0, sm.w2, b2, sm.buf1, false, nvalid);
@@ -780,8 +787,8 @@ constexpr int kWP = 8;                           // waves (inputs in flight) per
 
 struct WaveSlice {
     uint16_t xs[256];                            // the input (bf16)
-    uint16_t buf0[32 * kA3Ld];                   // a1 [128][16] (swizzled), then a3 [32][72]
-    uint16_t buf1[64 * kA2Ld];                   // a2 [64][40]
+    uint16_t buf0[32 * kA3Ld];                   // a1 [128][16], then a3 [32][64] (swizzled rows)
+    uint16_t buf1[64 * kA2Ld];                   // a2 [64][32] (swizzled rows)
 };
 
 struct ConvStackLdsW {
@@ -806,7 +813,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 // activation in HBM, [L/2][COUT]) and its mask byte to gmask (bit 0: the
 // winning position's parity, bit 1: the winner's pre-activation is > 0), as
 // EpConvFwd does for the backward pass.
-template <int L, int CIN, int ILD, int COUT, int WLD, int OLD, int RB, int CB, bool kTrain = false>
+template <int L, int CIN, int ILD, int COUT, int WLD, int OLD, int RB, int CB, bool kTrain = false,
+          bool kOutLds = true>
 __device__ __forceinline__ void conv_one(const uint16_t* __restrict__ in, const uint16_t* __restrict__ w,
                                          const float* __restrict__ bias, uint16_t* __restrict__ out,
                                          uint16_t* __restrict__ gout = nullptr,
@@ -846,7 +854,8 @@ __device__ __forceinline__ void conv_one(const uint16_t* __restrict__ in, const 
                 for (int h = 0; h < 2; ++h) {
                     const float p0 = acc[i][j][2 * h] + bn, p1 = acc[i][j][2 * h + 1] + bn;
                     const uint16_t hv = f2bf(pool_relu(p0, p1));
-                    out[((x0 >> 1) + h) * OLD + n] = hv;
+                    const int row = (x0 >> 1) + h;
+                    out[kOutLds ? act_off<OLD>(row, n & ~7) + (n & 7) : row * OLD + n] = hv;
                     if constexpr (kTrain) {
                         const int po = ((x0 >> 1) + h) * COUT + n;
                         if (gout) gout[po] = hv;
@@ -931,10 +940,9 @@ __global__ __launch_bounds__(kWP * 64, 1) void k_convstack_bf16_w(
             }
             uint32_t packed[8];
             for (int j = 0; j < 8; ++j) packed[j] = f2bf2(pooled[2 * j], pooled[2 * j + 1]);
-            const int sw = (xp >> 3) & 1;     // the a1 swizzle of act_off<16>
             uint4* dst = reinterpret_cast<uint4*>(ws.buf0 + xp * kA1Ld);
-            dst[sw] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
-            dst[sw ^ 1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
+            dst[0] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
+            dst[1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
             if constexpr (kTrain) {
                 const int64_t o = (fi * 128 + xp) * 16;
                 uint4* g = reinterpret_cast<uint4*>(a1g + o);
@@ -950,7 +958,7 @@ __global__ __launch_bounds__(kWP * 64, 1) void k_convstack_bf16_w(
         conv_one<64, 32, kA2Ld, 64, kW3Ld, kA3Ld, 4, 4, kTrain>(
             ws.buf1, sm.w3, b3, ws.buf0, kTrain ? a3g + fi * 2048 : nullptr, kTrain ? m3 + fi * 2048 : nullptr);
         wave_lds_sync();
-        conv_one<32, 64, kA3Ld, 64, kW4Ld, 64, 2, 4, kTrain>(ws.buf0, sm.w4, b4, a4 + fi * 1024, nullptr,
+        conv_one<32, 64, kA3Ld, 64, kW4Ld, 64, 2, 4, kTrain, false>(ws.buf0, sm.w4, b4, a4 + fi * 1024, nullptr,
                                                              kTrain ? m4 + fi * 1024 : nullptr);
         wave_lds_sync();   // buf0 and xs are reused by the next input
     }
@@ -959,10 +967,10 @@ __global__ __launch_bounds__(kWP * 64, 1) void k_convstack_bf16_w(
 // Fully connected layer for bf16 inference: out[m][n] = ReLU(bias[n] +
 // sum_k A[m][k] W[n][k]) with A [M][K] activations and W [N][K] weights,
 // both row-major bf16. Block tile 128 x BN, 4 waves of 64 x BN/2; K advances
-// in steps of 64 through double-buffered LDS tiles (rows padded by 8
+// in steps of 64 through double-buffered LDS tiles (rows padded by 16
 // elements) filled from registers loaded one step ahead. Each output's MFMA
 // chain runs k in the same 32-steps as k_gemm, so results are bit-identical.
-constexpr int kFcBK = 64, kFcLd = kFcBK + 8;
+constexpr int kFcBK = 64, kFcLd = kFcBK + 16;   // rows of 160 bytes: conflict-free fragment reads
 
 // EPI selects the epilogue: kFcRelu (bias + ReLU, the forward layer) or
 // kFcStore (plain store: a data gradient, as EpStore). Blocks along y take
@@ -1267,13 +1275,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 // bit-identical to the layer path), and the result (the pooled gradient of
 // the block below) goes to HBM for that block's weight gradient and, unpooled
 // with that block's mask, into LDS for the next step down.
+// LDS layouts as in the forward stack: unpooled gradients dpre4 [32][64],
+// dpre3 [64][64], dpre2 [128][32] in rows of their exact length with the
+// act_off chunk swizzle; backward weights [Cin][5 Cout] in rows padded to a
+// stride of 32 mod 64 bytes.
 constexpr int kBP = 4;                                // waves (inputs in flight) per block
-constexpr int kP4Ld = 72, kP3Ld = 72, kP2Ld = 40;     // rows of dpre4 [32][64], dpre3 [64][64], dpre2 [128][32]
-constexpr int kB4Ld = 328, kB3Ld = 328, kB2Ld = 168;  // rows of the backward weights [Cin][5 Cout]
+constexpr int kB4Ld = 336, kB3Ld = 336, kB2Ld = 176;  // rows of the backward weights
 
 struct BwdSlice {
-    uint16_t buf0[128 * kP2Ld];   // dpre4 [32][kP4Ld] with m3 bytes [32][64] after it; then dpre2
-    uint16_t buf1[64 * kP3Ld];    // dpre3
+    uint16_t buf0[128 * 32];      // dpre4 [32][64] with m3 bytes [32][64] after it; then dpre2
+    uint16_t buf1[64 * 64];       // dpre3
     uint8_t m2[64 * 32];
 };
 struct BwdLds {
@@ -1282,8 +1293,8 @@ struct BwdLds {
     uint16_t w2[16 * kB2Ld];
     BwdSlice wv[kBP];
 };
-constexpr int kM3Off = 32 * kP4Ld * 2;                // byte offset of m3 in buf0
-static_assert(kM3Off + 32 * 64 <= 128 * kP2Ld * 2, "dpre4 and m3 share buf0");
+constexpr int kM3Off = 32 * 64 * 2;                  // byte offset of m3 in buf0
+static_assert(kM3Off + 32 * 64 <= 128 * 32 * 2, "dpre4 and m3 share buf0");
 static_assert(kM3Off % 16 == 0 && sizeof(BwdSlice) % 16 == 0, "16-byte LDS groups");
 static_assert(sizeof(BwdLds) <= 160 * 1024, "LDS budget");
 
@@ -1300,12 +1311,13 @@ __device__ __forceinline__ uint4 unpool_at(uint4 g, uint2 k, uint32_t sel) {
     return make_uint4(r[0], r[1], r[2], r[3]);
 }
 
-// The transposed conv of one input by one wave. dpre [L][PLD]: gradient at
-// the block's COUT pre-activations; w [CIN][WLD]: backward weights, k =
+// The transposed conv of one input by one wave. dpre [L][PLD = COUT]
+// (act_off rows): gradient at the block's COUT pre-activations; w
+// [CIN][WLD]: backward weights, k =
 // dx*COUT + co. Output (x, ci) = sum_k dpre[(x - dx + 2) mod L][co] w[ci][k],
 // rounded to bf16, stored to gout [L][CIN]; with kNext also unpooled with the
 // lower block's mask ([L][CIN] bytes: bit 0 the winner's parity, bit 1 its
-// pre-activation > 0) into next [2L][NLD]. The MFMA takes the weights as its
+// pre-activation > 0) into next [2L][NLD = CIN] (act_off rows). The MFMA takes the weights as its
 // first operand, so a lane ends with 4 consecutive channels of one position
 // (8-byte stores, one 4-byte mask read); the products and their k order are
 // those of k_gemm with ConvRows (sgn -1), whose output is the transpose.
@@ -1333,7 +1345,7 @@ __device__ __forceinline__ void convT_one(const uint16_t* __restrict__ dpre, con
             for (int i = 0; i < RB; ++i) {
                 int pos = rt * 16 * RB + i * 16 + r - dx + 2;
                 pos = pos < 0 ? pos + L : (pos >= L ? pos - L : pos);
-                a[i] = *reinterpret_cast<const bf16x8*>(dpre + pos * PLD + c0);
+                a[i] = *reinterpret_cast<const bf16x8*>(dpre + act_off<PLD>(pos, c0));
             }
             for (int j = 0; j < CB; ++j)
                 b[j] = *reinterpret_cast<const bf16x8*>(w + (ct * 16 * CB + j * 16 + r) * WLD + k);
@@ -1352,8 +1364,10 @@ __device__ __forceinline__ void convT_one(const uint16_t* __restrict__ dpre, con
                     const uint32_t mk = *reinterpret_cast<const uint32_t*>(mask + xx * CIN + n0);
                     const uint4 ev = unpool_at(make_uint4(h01, h23, 0u, 0u), make_uint2(mk, 0u), 2u);
                     const uint4 od = unpool_at(make_uint4(h01, h23, 0u, 0u), make_uint2(mk, 0u), 3u);
-                    *reinterpret_cast<uint2*>(next + (2 * xx) * NLD + n0) = make_uint2(ev.x, ev.y);
-                    *reinterpret_cast<uint2*>(next + (2 * xx + 1) * NLD + n0) = make_uint2(od.x, od.y);
+                    *reinterpret_cast<uint2*>(next + act_off<NLD>(2 * xx, n0 & ~7) + (n0 & 7)) =
+                        make_uint2(ev.x, ev.y);
+                    *reinterpret_cast<uint2*>(next + act_off<NLD>(2 * xx + 1, n0 & ~7) + (n0 & 7)) =
+                        make_uint2(od.x, od.y);
                 }
             }
         }
@@ -1428,16 +1442,16 @@ __global__ __launch_bounds__(kBP * 64, 1) void k_convstack_bwd_bf16(
             const int e0 = h * 512 + lane * 8, xp = e0 >> 6, c0 = e0 & 63;
             uint4 ev, od;
             unpool8(ng[h], nk4[h], ev, od);
-            *reinterpret_cast<uint4*>(ws.buf0 + (2 * xp) * kP4Ld + c0) = ev;
-            *reinterpret_cast<uint4*>(ws.buf0 + (2 * xp + 1) * kP4Ld + c0) = od;
+            *reinterpret_cast<uint4*>(ws.buf0 + act_off<64>(2 * xp, c0)) = ev;
+            *reinterpret_cast<uint4*>(ws.buf0 + act_off<64>(2 * xp + 1, c0)) = od;
         }
         load(fi + stride);
         wave_lds_sync();
-        convT_one<32, 64, 64, kP4Ld, kB4Ld, kP3Ld, 2, 4, true>(ws.buf0, sm.w4, d3 + fi * 2048, m3s, ws.buf1);
+        convT_one<32, 64, 64, 64, kB4Ld, 64, 2, 4, true>(ws.buf0, sm.w4, d3 + fi * 2048, m3s, ws.buf1);
         wave_lds_sync();
-        convT_one<64, 32, 64, kP3Ld, kB3Ld, kP2Ld, 4, 2, true>(ws.buf1, sm.w3, d2 + fi * 2048, ws.m2, ws.buf0);
+        convT_one<64, 32, 64, 64, kB3Ld, 32, 4, 2, true>(ws.buf1, sm.w3, d2 + fi * 2048, ws.m2, ws.buf0);
         wave_lds_sync();
-        convT_one<128, 16, 32, kP2Ld, kB2Ld, 0, 8, 1, false>(ws.buf0, sm.w2, d1 + fi * 2048, nullptr, nullptr);
+        convT_one<128, 16, 32, 32, kB2Ld, 16, 8, 1, false>(ws.buf0, sm.w2, d1 + fi * 2048, nullptr, nullptr);
         wave_lds_sync();   // buf0 and the masks are reused by the next input
     }
 }
