@@ -1279,7 +1279,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 // dpre3 [64][64], dpre2 [128][32] in rows of their exact length with the
 // act_off chunk swizzle; backward weights [Cin][5 Cout] in rows padded to a
 // stride of 32 mod 64 bytes.
-constexpr int kBP = 4;                                // waves (inputs in flight) per block
+constexpr int kBP = 5;                                // waves (inputs in flight) per block
 constexpr int kB4Ld = 336, kB3Ld = 336, kB2Ld = 176;  // rows of the backward weights
 
 struct BwdSlice {
