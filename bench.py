@@ -29,7 +29,8 @@ NBINS = 256
 FMIN, FMAX = 1.0, 5.0                   # 1/d: periods 0.2-1.0 d
 METRIC = "fold+score trial periods/s (65k-pt curve, 256 bins) vs plain fold; roofline %"
 
-# MI355X: 256 CUs at 2.4 GHz; LDS 128 B/clk/CU (32 banks x 4 B).
+# MI355X: 256 CUs at 2.4 GHz; LDS atomics 128 B/clk/CU (a wave's 64-bit atomic, 512 B, takes
+# at least 4 LDS cycles; plain reads run at 256 B/clk).
 CUS, CLOCK = 256, 2.4e9
 LDS_PEAK_GBS = CUS * 128 * CLOCK / 1e9          # 78,643 GB/s
 LDS_U64_ATOMIC_MEASURED = 6.17e12               # conflict-free ds_add_u64 lane-ops/s (probe)
