@@ -1058,87 +1058,73 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 }
 
 // The first fully connected layer for bf16 inference (N = 256 outputs): one
-// block of 8 waves computes 128 rows x all 256 columns (waves 2 x 4, each
-// 64 x 64), so every activation row is read once. K advances in steps of 64
-// through three LDS stages filled straight from global memory
-// (global_load_lds_dwordx4: a wave's 64 lanes write 1 KB of LDS in lane
-// order, no registers in between), issued two steps ahead, with one block
-// barrier per step. A row of a stage is 128 B of 16-byte chunks stored
-// XOR-swizzled (chunk c of row r at chunk slot c ^ (r & 7)), so the 16 rows
-// a fragment read touches fall on distinct banks in groups of 8. Same MFMA
-// chains and epilogue as k_gemm with EpFcFwd: bit-identical output.
+// block of 16 waves computes 256 rows x all 256 columns (waves 4 x 4, each
+// 64 x 64), so every activation row is read once and the weights once per
+// 256 rows. K advances in steps of 32 through four LDS stages filled straight
+// from global memory (global_load_lds_dwordx4: a wave's 64 lanes write 1 KB of
+// LDS in lane order, no registers in between), issued three steps ahead with
+// one block barrier per step: 48 KB of activations in flight per CU, which
+// the HBM stream needs (two steps of 128-row tiles kept too little of it in
+// flight). A row of a stage is 64 B of 16-byte chunks stored XOR-swizzled
+// (chunk c of row r at slot c ^ 2*bit 2 of r), conflict-free for the fragment
+// reads. Same MFMA chains and epilogue as k_gemm with EpFcFwd: bit-identical
+// output.
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) void glb_void_t;
-constexpr int kF1BM = 128, kF1BN = 256, kF1Stages = 3;
-constexpr int kF1StageA = kF1BM * 128, kF1StageB = kF1BN * 128;   // bytes per stage
+constexpr int kF1BM = 256, kF1BN = 256, kF1BK = 32, kF1Stages = 4;
+constexpr int kF1StageA = kF1BM * kF1BK * 2, kF1StageB = kF1BN * kF1BK * 2;   // bytes per stage
 
-__global__ __launch_bounds__(512, 1) void k_fc1_bf16(int M, int K, const uint16_t* __restrict__ A,
-                                                   const uint16_t* __restrict__ W,
-                                                   const float* __restrict__ bias,
-                                                   uint16_t* __restrict__ out) {
+__global__ __launch_bounds__(1024, 1) void k_fc1_bf16(int M, int K, const uint16_t* __restrict__ A,
+                                                    const uint16_t* __restrict__ W,
+                                                    const float* __restrict__ bias,
+                                                    uint16_t* __restrict__ out) {
     __shared__ __attribute__((aligned(1024))) char smem[kF1Stages * (kF1StageA + kF1StageB)];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, q = lane >> 4;
-    const int wm = wave & 1, wn = wave >> 1;
+    const int wm = wave & 3, wn = wave >> 2;
     const int m0 = blockIdx.x * kF1BM;
-    // this lane's chunk in each 1 KB wave load: row (lane >> 3) of the load's
-    // 8 rows, global chunk (lane & 7) ^ (row & 7), placed at slot lane & 7
-    const int lrow = lane >> 3, lchunk = (lane & 7) ^ lrow;
-    // A: loads 2 wave, 2 wave + 1 (rows 8 L ...); W: loads 4 wave ... 4 wave + 3
-    const uint16_t* ga[2];
-    const uint16_t* gw[4];
-    for (int j = 0; j < 2; ++j) {
-        const int row = (2 * wave + j) * 8 + lrow;
-        const int mr = min(m0 + row, M - 1);   // rows past M load a valid row, never stored
-        ga[j] = A + (int64_t)mr * K + lchunk * 8;
-    }
-    for (int j = 0; j < 4; ++j) gw[j] = W + (int64_t)((4 * wave + j) * 8 + lrow) * K + lchunk * 8;
+    // a wave's 1 KB load is 16 rows x 4 chunks: this lane's row is
+    // 16 wave + (lane >> 2), its slot lane & 3, holding global chunk
+    // (lane & 3) ^ 2*bit 2 of the row
+    const int row = wave * 16 + (lane >> 2);
+    const int lchunk = (lane & 3) ^ (((row >> 2) & 1) << 1);
+    const uint16_t* ga = A + (int64_t)min(m0 + row, M - 1) * K + lchunk * 8;   // rows past M: never stored
+    const uint16_t* gw = W + (int64_t)row * K + lchunk * 8;
     auto stage_a = [&](int st) { return smem + st * (kF1StageA + kF1StageB); };
     auto stage_b = [&](int st) { return smem + st * (kF1StageA + kF1StageB) + kF1StageA; };
     auto issue = [&](int step) {
-        const int st = step % kF1Stages, k0 = step * kFcBK;
-        char* sa = stage_a(st);
-        char* sb = stage_b(st);
-        for (int j = 0; j < 2; ++j)
-            __builtin_amdgcn_global_load_lds((glb_void_t*)(ga[j] + k0), (lds_void_t*)(sa + (2 * wave + j) * 1024),
-                                             16, 0, 0);
-        for (int j = 0; j < 4; ++j)
-            __builtin_amdgcn_global_load_lds((glb_void_t*)(gw[j] + k0), (lds_void_t*)(sb + (4 * wave + j) * 1024),
-                                             16, 0, 0);
+        const int st = step % kF1Stages, k0 = step * kF1BK;
+        __builtin_amdgcn_global_load_lds((glb_void_t*)(ga + k0), (lds_void_t*)(stage_a(st) + wave * 1024), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((glb_void_t*)(gw + k0), (lds_void_t*)(stage_b(st) + wave * 1024), 16, 0, 0);
     };
-    auto frag = [&](const char* base, int row, int chunk) {
-        return *reinterpret_cast<const bf16x8*>(base + row * 128 + ((chunk ^ (row & 7)) << 4));
+    auto frag = [&](const char* base, int rw, int chunk) {
+        return *reinterpret_cast<const bf16x8*>(base + rw * 64 + ((chunk ^ (((rw >> 2) & 1) << 1)) << 4));
     };
     f32x4 acc[4][4];
     for (int i = 0; i < 4; ++i)
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    const int steps = K / kFcBK;
-    issue(0);
-    if (steps > 1) issue(1);
+    const int steps = K / kF1BK;
+    for (int i = 0; i < kF1Stages - 1 && i < steps; ++i) issue(i);
     for (int st = 0; st < steps; ++st) {
-        // this wave's loads of step st are done (6 per step; those of st + 1
-        // may still be in flight), then every wave's, and every wave is done
-        // reading the stage that step st + 2 refills
-        // (a bare barrier: __syncthreads' fence would also wait for the loads
-        // of step st + 1)
-        if (st + 1 < steps) __builtin_amdgcn_s_waitcnt(0x0F76);   // vmcnt(6)
-        else __builtin_amdgcn_s_waitcnt(0x0F70);                  // vmcnt(0)
+        // this wave's loads of step st are done (2 per step; those of the
+        // next steps may still be in flight), then every wave's, and every
+        // wave is done reading the stage that step st + 3 refills (a bare
+        // barrier: __syncthreads' fence would also wait for the later loads)
+        if (st + 2 < steps) __builtin_amdgcn_s_waitcnt(0x0F74);        // vmcnt(4)
+        else if (st + 1 < steps) __builtin_amdgcn_s_waitcnt(0x0F72);   // vmcnt(2)
+        else __builtin_amdgcn_s_waitcnt(0x0F70);                       // vmcnt(0)
         __builtin_amdgcn_sched_barrier(0);
         __builtin_amdgcn_s_barrier();
         __builtin_amdgcn_sched_barrier(0);
-        if (st + 2 < steps) issue(st + 2);
+        if (st + kF1Stages - 1 < steps) issue(st + kF1Stages - 1);
         const char* sa = stage_a(st % kF1Stages);
         const char* sb = stage_b(st % kF1Stages);
-#pragma unroll
-        for (int kk = 0; kk < kFcBK; kk += 32) {
-            bf16x8 a[4], b[4];
-            const int c = kk / 8 + q;
-            for (int i = 0; i < 4; ++i) a[i] = frag(sa, wm * 64 + i * 16 + r, c);
-            for (int j = 0; j < 4; ++j) b[j] = frag(sb, wn * 64 + j * 16 + r, c);
-            for (int i = 0; i < 4; ++i)
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-        }
+        bf16x8 a[4], b[4];
+        for (int i = 0; i < 4; ++i) a[i] = frag(sa, wm * 64 + i * 16 + r, q);
+        for (int j = 0; j < 4; ++j) b[j] = frag(sb, wn * 64 + j * 16 + r, q);
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     for (int i = 0; i < 4; ++i)
         for (int j = 0; j < 4; ++j) {
@@ -2044,7 +2030,7 @@ int32_t forward(gpfc_cnn* c, const void* x, int xf32, int B, float* logits, cons
     }
     }
     if (fused) {
-        hipLaunchKernelGGL(k_fc1_bf16, dim3((unsigned)((B + 127) / 128)), dim3(512), 0, s, B, 1024,
+        hipLaunchKernelGGL(k_fc1_bf16, dim3((unsigned)((B + kF1BM - 1) / kF1BM)), dim3(1024), 0, s, B, 1024,
                            (const uint16_t*)c->a4, (const uint16_t*)c->f1f, w + F1B, (uint16_t*)c->h1);
         hipLaunchKernelGGL(k_fc_bf16<64>, dim3((unsigned)((B + 127) / 128), 1), dim3(256), 0, s, B, 256,
                            (const uint16_t*)c->h1, (const uint16_t*)c->f2f, w + F2B, (uint16_t*)c->h2,
