@@ -318,7 +318,11 @@ int32_t gpfc_cnn_load(gpfc_cnn *cnn, const char *path, void *stream);
  * keeps the convolution weights in LDS and every activation in a wave's own
  * LDS slice, each wave taking whole inputs on its own (no block-wide waits);
  * 2, the same fused stack over tiles of 8 inputs in lockstep; 0, layer by
- * layer through device memory. All give bit-identical logits.
+ * layer through device memory. All give bit-identical logits. The setting
+ * also selects the training path of a bf16 network: fused (on != 0; the
+ * input must be 16-byte aligned, else the layer path is taken) or layer by
+ * layer (0). Both give the same loss and fully connected gradients bit for
+ * bit; the convolution weight gradients differ only in FP32 summation order.
  */
 int32_t gpfc_cnn_set_fused(gpfc_cnn *cnn, int32_t on);
 

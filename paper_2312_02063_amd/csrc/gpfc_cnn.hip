@@ -17,10 +17,15 @@
 // Inference of a bf16 network runs the four convolution blocks as one
 // persistent kernel with every activation in LDS (k_convstack_bf16_w with
 // wave-private inputs, or k_convstack_bf16 with tiles of 8) and the fully connected
-// layers as LDS-tiled GEMMs (k_fc1_bf16, k_fc_bf16); training runs layer by
-// layer through device memory (it keeps activations and pooling masks for
-// the backward pass) and can be replayed as one HIP graph per step. Every
-// inference path gives the same bits as the layer path.
+// layers as LDS-tiled GEMMs (k_fc1_bf16, k_fc_bf16). A bf16 training step runs
+// the same stack in a variant that also writes the activations and pooling
+// masks to device memory, the backward data gradients down the blocks in one
+// kernel (k_convstack_bwd_bf16) and the convolution weight gradients over LDS
+// tiles of 8 interleaved inputs (k_conv_dw_bf16, k_conv1_dw_bf16); FP32
+// networks and the layer path (gpfc_cnn_set_fused(0)) run layer by layer
+// through device memory. A step can be replayed as one HIP graph. Every fused
+// path gives the same bits as the layer path, except the convolution weight
+// gradients, which differ only in FP32 summation order.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
