@@ -294,7 +294,7 @@ def test_train_step_equals_backward_then_adam(torch_dev):
     assert torch.equal(a.get_params(), b.get_params())
 
 
-@pytest.mark.parametrize("B", [7, 300, 5000])
+@pytest.mark.parametrize("B", [1, 7, 257, 300, 5000])
 def test_fused_training_matches_layer_path(torch_dev, B):
     """A bf16 training step through the fused kernels (the convolution stack
     forward, which also writes the activations and pooling masks; the
