@@ -1076,31 +1076,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 // output.
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) void glb_void_t;
-constexpr int kF1BM = 256, kF1BN = 256, kF1BK = 32, kF1Stages = 4;
-constexpr int kF1StageA = kF1BM * kF1BK * 2, kF1StageB = kF1BN * kF1BK * 2;   // bytes per stage
+constexpr int kF1BN = 256, kF1BK = 32, kF1Stages = 4;
 
-__global__ __launch_bounds__(1024, 1) void k_fc1_bf16(int M, int K, const uint16_t* __restrict__ A,
-                                                    const uint16_t* __restrict__ W,
-                                                    const float* __restrict__ bias,
-                                                    uint16_t* __restrict__ out) {
-    __shared__ __attribute__((aligned(1024))) char smem[kF1Stages * (kF1StageA + kF1StageB)];
+// BM = 256 (16 waves) when the rows fill the chip, else 128 (8 waves).
+template <int BM>
+__global__ __launch_bounds__(BM * 4, 1) void k_fc1_bf16(int M, int K, const uint16_t* __restrict__ A,
+                                                      const uint16_t* __restrict__ W,
+                                                      const float* __restrict__ bias,
+                                                      uint16_t* __restrict__ out) {
+    constexpr int kWaves = BM / 16;                   // 16 rows of A per wave per step
+    constexpr int kWLoads = kF1BN / 16 / kWaves;      // W loads per wave per step
+    constexpr int kLoads = 1 + kWLoads;               // loads per wave per step
+    constexpr int kStageA = BM * kF1BK * 2, kStageB = kF1BN * kF1BK * 2;   // bytes per stage
+    __shared__ __attribute__((aligned(1024))) char smem[kF1Stages * (kStageA + kStageB)];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, q = lane >> 4;
-    const int wm = wave & 3, wn = wave >> 2;
-    const int m0 = blockIdx.x * kF1BM;
+    const int wm = wave % (BM / 64), wn = wave / (BM / 64);
+    const int m0 = blockIdx.x * BM;
     // a wave's 1 KB load is 16 rows x 4 chunks: this lane's row is
-    // 16 wave + (lane >> 2), its slot lane & 3, holding global chunk
+    // 16 w + (lane >> 2) of load w, its slot lane & 3, holding global chunk
     // (lane & 3) ^ 2*bit 2 of the row
-    const int row = wave * 16 + (lane >> 2);
-    const int lchunk = (lane & 3) ^ (((row >> 2) & 1) << 1);
-    const uint16_t* ga = A + (int64_t)min(m0 + row, M - 1) * K + lchunk * 8;   // rows past M: never stored
-    const uint16_t* gw = W + (int64_t)row * K + lchunk * 8;
-    auto stage_a = [&](int st) { return smem + st * (kF1StageA + kF1StageB); };
-    auto stage_b = [&](int st) { return smem + st * (kF1StageA + kF1StageB) + kF1StageA; };
+    const int lr = lane >> 2;
+    const int lchunk = (lane & 3) ^ (((lr >> 2) & 1) << 1);
+    const uint16_t* ga = A + (int64_t)min(m0 + wave * 16 + lr, M - 1) * K + lchunk * 8;   // rows past M: never stored
+    const uint16_t* gw[kWLoads];
+    for (int j = 0; j < kWLoads; ++j) gw[j] = W + (int64_t)((wave * kWLoads + j) * 16 + lr) * K + lchunk * 8;
+    auto stage_a = [&](int st) { return smem + st * (kStageA + kStageB); };
+    auto stage_b = [&](int st) { return smem + st * (kStageA + kStageB) + kStageA; };
     auto issue = [&](int step) {
         const int st = step % kF1Stages, k0 = step * kF1BK;
         __builtin_amdgcn_global_load_lds((glb_void_t*)(ga + k0), (lds_void_t*)(stage_a(st) + wave * 1024), 16, 0, 0);
-        __builtin_amdgcn_global_load_lds((glb_void_t*)(gw + k0), (lds_void_t*)(stage_b(st) + wave * 1024), 16, 0, 0);
+        for (int j = 0; j < kWLoads; ++j)
+            __builtin_amdgcn_global_load_lds((glb_void_t*)(gw[j] + k0),
+                                             (lds_void_t*)(stage_b(st) + (wave * kWLoads + j) * 1024), 16, 0, 0);
     };
     auto frag = [&](const char* base, int rw, int chunk) {
         return *reinterpret_cast<const bf16x8*>(base + rw * 64 + ((chunk ^ (((rw >> 2) & 1) << 1)) << 4));
@@ -1115,9 +1123,9 @@ __global__ __launch_bounds__(1024, 1) void k_fc1_bf16(int M, int K, const uint16
         // next steps may still be in flight), then every wave's, and every
         // wave is done reading the stage that step st + 3 refills (a bare
         // barrier: __syncthreads' fence would also wait for the later loads)
-        if (st + 2 < steps) __builtin_amdgcn_s_waitcnt(0x0F74);        // vmcnt(4)
-        else if (st + 1 < steps) __builtin_amdgcn_s_waitcnt(0x0F72);   // vmcnt(2)
-        else __builtin_amdgcn_s_waitcnt(0x0F70);                       // vmcnt(0)
+        if (st + 2 < steps) __builtin_amdgcn_s_waitcnt(0x0F70 | (2 * kLoads));   // vmcnt(2 steps)
+        else if (st + 1 < steps) __builtin_amdgcn_s_waitcnt(0x0F70 | kLoads);   // vmcnt(1 step)
+        else __builtin_amdgcn_s_waitcnt(0x0F70);                                // vmcnt(0)
         __builtin_amdgcn_sched_barrier(0);
         __builtin_amdgcn_s_barrier();
         __builtin_amdgcn_sched_barrier(0);
@@ -1485,7 +1493,7 @@ struct DwShape {
 };
 
 template <int L, int CIN, int COUT, int WN, int WK>
-__global__ __launch_bounds__(256, 2) void k_conv_dw_bf16(int B, int groups_per_block,
+__global__ __launch_bounds__(256, CIN == 16 ? 3 : 2) void k_conv_dw_bf16(int B, int groups_per_block,
                                                          const uint16_t* __restrict__ dact,
                                                          const uint8_t* __restrict__ mask,
                                                          const uint16_t* __restrict__ act,
@@ -2035,8 +2043,12 @@ int32_t forward(gpfc_cnn* c, const void* x, int xf32, int B, float* logits, cons
     }
     }
     if (fused) {
-        hipLaunchKernelGGL(k_fc1_bf16, dim3((unsigned)((B + kF1BM - 1) / kF1BM)), dim3(1024), 0, s, B, 1024,
-                           (const uint16_t*)c->a4, (const uint16_t*)c->f1f, w + F1B, (uint16_t*)c->h1);
+        if ((B + 255) / 256 >= c->n_cu)
+            hipLaunchKernelGGL(k_fc1_bf16<256>, dim3((unsigned)((B + 255) / 256)), dim3(1024), 0, s, B, 1024,
+                               (const uint16_t*)c->a4, (const uint16_t*)c->f1f, w + F1B, (uint16_t*)c->h1);
+        else
+            hipLaunchKernelGGL(k_fc1_bf16<128>, dim3((unsigned)((B + 127) / 128)), dim3(512), 0, s, B, 1024,
+                               (const uint16_t*)c->a4, (const uint16_t*)c->f1f, w + F1B, (uint16_t*)c->h1);
         hipLaunchKernelGGL(k_fc_bf16<64>, dim3((unsigned)((B + 127) / 128), 1), dim3(256), 0, s, B, 256,
                            (const uint16_t*)c->h1, (const uint16_t*)c->f2f, w + F2B, (uint16_t*)c->h2,
                            64);
@@ -2081,7 +2093,7 @@ hipError_t conv_dw_bf16(const gpfc_cnn* c, int B, const uint16_t* dact, const ui
     const int64_t mn = (int64_t)COUT * 5 * CIN;
     const int groups = (B + 7) / 8;
     const int64_t row = mn + COUT;
-    int blocks = (int)std::min<int64_t>(std::min(groups, 2 * c->n_cu), kSplitWs / row);
+    int blocks = (int)std::min<int64_t>(std::min(groups, (CIN == 16 ? 3 : 2) * c->n_cu), kSplitWs / row);
     const int gpb = (groups + blocks - 1) / blocks;
     blocks = (groups + gpb - 1) / gpb;
     hipLaunchKernelGGL((k_conv_dw_bf16<L, CIN, COUT, WN, WK>), dim3((unsigned)blocks), dim3(256), 0, s, B, gpb,

@@ -188,15 +188,16 @@ def test_fp8_forward_error(torch_dev):
     assert np.corrcoef(z8, zo)[0, 1] > 0.9
 
 
-@pytest.mark.parametrize("B", [1, 7, 8, 9, 300, 4099])
+@pytest.mark.parametrize("B", [1, 7, 8, 9, 300, 4099, 65541])
 def test_fused_inference_bit_identical(torch_dev, B):
     """The fused convolution-stack kernel against the layer-by-layer path:
-    identical logits, ragged last tiles included."""
+    identical logits, ragged last tiles included (65,541 inputs: enough rows
+    for the 256-row FC1 tiles, with a ragged last one)."""
     torch = torch_dev
     from paper_2312_02063_amd import CNN_BF16
     p = _params(19)
     x, _ = _inputs(20 + B, B)
-    net = _net(torch, CNN_BF16, p, max_batch=4099)
+    net = _net(torch, CNN_BF16, p, max_batch=max(B, 4099))
     xt = torch.tensor(x, dtype=torch.float32, device="cuda")
     _say(f"cnn fused vs layered B={B}")
     zf = net.forward(xt).cpu().numpy()
@@ -213,8 +214,10 @@ def test_fused_inference_bit_identical(torch_dev, B):
     zr = net.forward(xt).cpu().numpy()
     net.set_fused(1)
     assert np.array_equal(zr, zl)
-    zo = oracle.cnn_forward(p, x)
-    assert _rel(zf, zo) < 5e-2
+    # the FP64 oracle on at most 600 inputs (the first 512 and the ragged tail)
+    rows = np.arange(B) if B <= 600 else np.r_[0:512, B - 88:B]
+    zo = oracle.cnn_forward(p, x[rows])
+    assert _rel(zf[rows], zo) < 5e-2
 
 
 def test_captured_training_step_equals_eager(torch_dev):
