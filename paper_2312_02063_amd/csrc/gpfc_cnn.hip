@@ -2141,7 +2141,6 @@ int32_t backward(gpfc_cnn* c, const void* x, int xf32, int B, hipStream_t s) {
     using namespace gcnn;
     using T = typename P::T;
     hipError_t e;
-    const float* w = c->params;
     float* g = c->grad;
     // dh2 (already masked) is in d_a [B][64]
     T* dh2 = (T*)c->d_a;

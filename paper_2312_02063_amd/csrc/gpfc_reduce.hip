@@ -22,7 +22,6 @@ namespace {
 
 constexpr int kTopWaves = 16;
 constexpr int kTopThreads = kTopWaves * 64;
-constexpr int64_t kNoIndex = INT64_MAX;
 
 // Order: value descending, then index ascending.
 __device__ __forceinline__ bool beats(float v, int64_t i, float w, int64_t j) {
