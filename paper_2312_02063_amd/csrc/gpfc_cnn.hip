@@ -2043,12 +2043,17 @@ int32_t forward(gpfc_cnn* c, const void* x, int xf32, int B, float* logits, cons
     }
     }
     if (fused) {
+        // tiles that keep the chip busy: 256 rows, 128 rows, or for small
+        // batches 128 x 64 tiles of the generic staged kernel (same bits)
         if ((B + 255) / 256 >= c->n_cu)
             hipLaunchKernelGGL(k_fc1_bf16<256>, dim3((unsigned)((B + 255) / 256)), dim3(1024), 0, s, B, 1024,
                                (const uint16_t*)c->a4, (const uint16_t*)c->f1f, w + F1B, (uint16_t*)c->h1);
-        else
+        else if ((B + 127) / 128 >= c->n_cu / 2)
             hipLaunchKernelGGL(k_fc1_bf16<128>, dim3((unsigned)((B + 127) / 128)), dim3(512), 0, s, B, 1024,
                                (const uint16_t*)c->a4, (const uint16_t*)c->f1f, w + F1B, (uint16_t*)c->h1);
+        else
+            hipLaunchKernelGGL((k_fc_bf16<64, kFcRelu>), dim3((unsigned)((B + 127) / 128), 4), dim3(256), 0, s, B,
+                               1024, (const uint16_t*)c->a4, (const uint16_t*)c->f1f, w + F1B, (uint16_t*)c->h1, 256);
         hipLaunchKernelGGL(k_fc_bf16<64>, dim3((unsigned)((B + 127) / 128), 1), dim3(256), 0, s, B, 256,
                            (const uint16_t*)c->h1, (const uint16_t*)c->f2f, w + F2B, (uint16_t*)c->h2,
                            64);
