@@ -48,7 +48,7 @@ def run(n_periods: int = 20000, n_top: int = 100, cnn_folds: int = 2000, params=
     plan = Plan(0)
     t = torch.tensor(c.t, dtype=torch.float64, device=dev)
     f = torch.tensor(c.flux, dtype=torch.float32, device=dev)
-    # the best periods of the full grid by the GPU box-SNR, plus a seeded sample
+    # the best periods of the full grid by the box-SNR computed on the GPU, plus a seeded sample
     snr_all = plan.fold_score(t, f, torch.tensor(grid, dtype=torch.float64, device=dev), NBINS)[0]
     top = torch.topk(snr_all, n_top).indices.cpu().numpy()
     idx = np.unique(np.concatenate([rng.choice(grid.size, n_periods, replace=False), top]))
