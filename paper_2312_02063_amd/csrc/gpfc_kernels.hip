@@ -811,13 +811,22 @@ __device__ void score_body(char* hist, uint64_t* chunk, ScoreShared& sh,
         const float inv = var > 0.0f ? 1.0f / sqrtf(var) : 0.0f;
         uint16_t* zrow = zfold + kk * nb;
         const int b0 = r0 >> log2g, b1 = (r0 + kRowsPerWave) >> log2g;
-        for (int b = b0; b < b1; ++b) {
+        auto zval = [&](int b) {
             const Slot e = slot_at(hist, (b + 1) * g - 1, lane);
             const Slot a = b ? slot_at(hist, b * g - 1, lane) : Slot{0.0f, 0.0f};
             const float cb = e.c - a.c;
             float z = 0.0f;
             if (cb > 0.5f && L.valid) z = ((e.dn - a.dn) / (nf * cb) - mu) * inv;
-            zrow[b] = bf16_rne(z);
+            return (uint32_t)bf16_rne(z);
+        };
+        if (b1 - b0 == 16) {   // the wave's 16 bins of this period: two 16-byte stores
+            uint32_t pk[8];
+            for (int j = 0; j < 8; ++j) pk[j] = zval(b0 + 2 * j) | (zval(b0 + 2 * j + 1) << 16);
+            uint4* dst = reinterpret_cast<uint4*>(zrow + b0);
+            dst[0] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+            dst[1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
+        } else {
+            for (int b = b0; b < b1; ++b) zrow[b] = (uint16_t)zval(b);
         }
     }
     __syncthreads();
