@@ -394,18 +394,43 @@ __global__ __launch_bounds__(kThreads, 1) void k_fold(
     const int g = 1 << log2g;
     const int nb = kFineBins >> log2g;
     const double ref = info->ref, qs = info->qscale;
-    for (int b = wave; b < nb; b += kWaves) {
+    auto bin = [&](int b, double& s, int32_t& c, double& m) {
         uint64_t acc = 0;
         for (int j = 0; j < g; ++j) acc += *reinterpret_cast<const uint64_t*>(hist + hist_off(b * g + j, lane));
-        uint32_t c;
+        uint32_t cu;
         double d;
-        decode(acc, qs, c, d);
-        double s = L.valid ? (double)c * ref + d : 0.0;
-        if (!L.valid) c = 0;
+        decode(acc, qs, cu, d);
+        s = L.valid ? (double)cu * ref + d : 0.0;
+        if (!L.valid) cu = 0;
+        c = (int32_t)cu;
+        m = cu ? s / (double)cu : __builtin_nan("");
+    };
+    const bool aligned = ((((uintptr_t)sums | (uintptr_t)means) & 15) | ((uintptr_t)counts & 7)) == 0;
+    if (nb >= 2 * kWaves && aligned) {
+        // each wave a contiguous run of bins of every period, written as bin
+        // pairs: 16-byte sums and means, 8-byte counts (the caller's buffers
+        // aligned to those sizes; otherwise the loop below)
+        const int per_wave = nb / kWaves;
+        for (int b = wave * per_wave; b < (wave + 1) * per_wave; b += 2) {
+            double s0, s1, m0, m1;
+            int32_t c0, c1;
+            bin(b, s0, c0, m0);
+            bin(b + 1, s1, c1, m1);
+            const int64_t o = kk * nb + b;
+            *reinterpret_cast<double2*>(sums + o) = make_double2(s0, s1);
+            *reinterpret_cast<int2*>(counts + o) = make_int2(c0, c1);
+            if (means) *reinterpret_cast<double2*>(means + o) = make_double2(m0, m1);
+        }
+        return;
+    }
+    for (int b = wave; b < nb; b += kWaves) {
+        double s, m;
+        int32_t c;
+        bin(b, s, c, m);
         const int64_t o = kk * nb + b;
         sums[o] = s;
-        counts[o] = (int32_t)c;
-        if (means) means[o] = c ? s / (double)c : __builtin_nan("");
+        counts[o] = c;
+        if (means) means[o] = m;
     }
 }
 
