@@ -17,7 +17,8 @@
 // Inference of a bf16 network runs the four convolution blocks as one
 // persistent kernel with every activation in LDS (k_convstack_bf16_w with
 // wave-private inputs, or k_convstack_bf16 with tiles of 8) and the fully connected
-// layers as LDS-tiled GEMMs (k_fc1_bf16, k_fc_bf16). A bf16 training step runs
+// layers as LDS-tiled GEMMs (k_fc1_bf16, k_fc_bf16, the second with the
+// output layer in its epilogue). A bf16 training step runs
 // the same stack in a variant that also writes the activations and pooling
 // masks to device memory, the backward data gradients down the blocks in one
 // kernel (k_convstack_bwd_bf16) and the convolution weight gradients over LDS
@@ -977,15 +978,19 @@ __global__ __launch_bounds__(kWP * 64, 1) void k_convstack_bf16_w(
 // chain runs k in the same 32-steps as k_gemm, so results are bit-identical.
 constexpr int kFcBK = 64, kFcLd = kFcBK + 16;   // rows of 160 bytes: conflict-free fragment reads
 
-// EPI selects the epilogue: kFcRelu (bias + ReLU, the forward layer) or
-// kFcStore (plain store: a data gradient, as EpStore). Blocks along y take
-// further column tiles of BN.
-constexpr int kFcRelu = 0, kFcStore = 1;
+// EPI selects the epilogue: kFcRelu (bias + ReLU, the forward layer),
+// kFcStore (plain store: a data gradient, as EpStore) or kFcHead (bias +
+// ReLU of the second dense layer, then the output layer on the block's rows:
+// hw holds the 64 output weights and the bias, logits receives one value per
+// row, out is not written; needs BN = 64 and one column tile). Blocks along y
+// take further column tiles of BN.
+constexpr int kFcRelu = 0, kFcStore = 1, kFcHead = 2;
 template <int BN, int EPI = kFcRelu>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_fc_bf16(int M, int K, const uint16_t* __restrict__ A,
                                                  const uint16_t* __restrict__ W,
                                                  const float* __restrict__ bias,
-                                                 uint16_t* __restrict__ out, int ldo) {
+                                                 uint16_t* __restrict__ out, int ldo,
+                                                 const float* __restrict__ hw, float* __restrict__ logits) {
     constexpr int BM = 128;
     constexpr int WN = BN / 2;                 // columns per wave
     constexpr int NJ = WN / 16;                // MFMA column blocks per wave
@@ -1049,6 +1054,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
             __syncthreads();
         }
     }
+    if constexpr (EPI == kFcHead) {
+        static_assert(BN == 64, "the output layer reads whole 64-wide rows");
+        // the block's 128 x 64 bf16 activations in LDS, rows of 144 bytes
+        // (16 consecutive rows hit distinct 16-byte slots), then one thread
+        // per row sums bias + h[i] w[i] over i in index order, the same
+        // FP32 sequence as k_head_infer
+        constexpr int kHLd = 72;
+        static_assert(BM * kHLd <= BM * kFcLd, "fits the first A buffer");
+        uint16_t* hs = sa[0];
+        __syncthreads();   // every wave has finished its last fragment reads
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < NJ; ++j) {
+                const int n = wn * WN + j * 16 + r;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    hs[(wm * 64 + i * 16 + q * 4 + e) * kHLd + n] = f2bf(fmaxf(acc[i][j][e] + bias[n], 0.0f));
+            }
+        __syncthreads();
+        if (tid < BM && m0 + tid < M) {
+            float z = hw[64];
+#pragma unroll
+            for (int c8 = 0; c8 < 8; ++c8) {
+                const uint4 v = *reinterpret_cast<const uint4*>(&hs[tid * kHLd + c8 * 8]);
+                const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    z += bf2f((uint16_t)(u[k] & 0xFFFFu)) * hw[c8 * 8 + 2 * k];
+                    z += bf2f((uint16_t)(u[k] >> 16)) * hw[c8 * 8 + 2 * k + 1];
+                }
+            }
+            logits[m0 + tid] = z;
+        }
+    } else {
     for (int i = 0; i < 4; ++i)
         for (int j = 0; j < NJ; ++j) {
             const int n = n0 + wn * WN + j * 16 + r;
@@ -1060,6 +1098,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
                 if (mb + e < M) out[(int64_t)(mb + e) * ldo + n] = f2bf(v);
             }
         }
+    }
 }
 
 // The first fully connected layer for bf16 inference (N = 256 outputs): one
@@ -2053,10 +2092,18 @@ int32_t forward(gpfc_cnn* c, const void* x, int xf32, int B, float* logits, cons
                                (const uint16_t*)c->a4, (const uint16_t*)c->f1f, w + F1B, (uint16_t*)c->h1);
         else
             hipLaunchKernelGGL((k_fc_bf16<64, kFcRelu>), dim3((unsigned)((B + 127) / 128), 4), dim3(256), 0, s, B,
-                               1024, (const uint16_t*)c->a4, (const uint16_t*)c->f1f, w + F1B, (uint16_t*)c->h1, 256);
-        hipLaunchKernelGGL(k_fc_bf16<64>, dim3((unsigned)((B + 127) / 128), 1), dim3(256), 0, s, B, 256,
-                           (const uint16_t*)c->h1, (const uint16_t*)c->f2f, w + F2B, (uint16_t*)c->h2,
-                           64);
+                               1024, (const uint16_t*)c->a4, (const uint16_t*)c->f1f, w + F1B, (uint16_t*)c->h1, 256,
+                               nullptr, nullptr);
+        // inference: the output layer runs in the second dense layer's
+        // epilogue (h2 never reaches memory); training keeps h2 for backward
+        if (!train)
+            hipLaunchKernelGGL((k_fc_bf16<64, kFcHead>), dim3((unsigned)((B + 127) / 128), 1), dim3(256), 0, s, B,
+                               256, (const uint16_t*)c->h1, (const uint16_t*)c->f2f, w + F2B, nullptr, 64, w + F3W,
+                               logits);
+        else
+            hipLaunchKernelGGL(k_fc_bf16<64>, dim3((unsigned)((B + 127) / 128), 1), dim3(256), 0, s, B, 256,
+                               (const uint16_t*)c->h1, (const uint16_t*)c->f2f, w + F2B, (uint16_t*)c->h2,
+                               64, nullptr, nullptr);
         e = hipGetLastError();
         if (e != hipSuccess) return cnn_err(e, "fc gemm");
     } else {
@@ -2080,7 +2127,7 @@ int32_t forward(gpfc_cnn* c, const void* x, int xf32, int B, float* logits, cons
                            rows, psum);
         hipLaunchKernelGGL(k_head_final, dim3((kHeadSums + 3) / 4), dim3(256), 0, s, psum, parts, B,
                            c->grad, c->loss);
-    } else if (logits)
+    } else if (logits && !fused)
         hipLaunchKernelGGL((k_head_infer<P>), dim3(blocks_for(B)), dim3(256), 0, s, (const T*)c->h2,
                            B, w + F3W, w + F3B, logits);
     e = hipGetLastError();
@@ -2167,7 +2214,8 @@ int32_t backward(gpfc_cnn* c, const void* x, int xf32, int B, hipStream_t s) {
     // bf16: the staged kernel (same MFMA chains and rounding as the GEMM)
     if (__is_same(P, BF16) && c->fused) {
         hipLaunchKernelGGL((k_fc_bf16<128, kFcStore>), dim3((unsigned)((B + 127) / 128), 8), dim3(256), 0, s, B,
-                           256, (const uint16_t*)dh1, (const uint16_t*)c->f1b, nullptr, (uint16_t*)dact, 1024);
+                           256, (const uint16_t*)dh1, (const uint16_t*)c->f1b, nullptr, (uint16_t*)dact, 1024,
+                           nullptr, nullptr);
         e = hipGetLastError();
     } else
         e = gemm<P>(B, 1024, 256, Rows<P>{dh1, B, 256, 256}, Rows<P>{(const T*)c->f1b, 1024, 256, 256},
