@@ -715,8 +715,15 @@ __global__ __launch_bounds__(kTopThreads) void k_pgram_runs(const float* __restr
     for (int a = 0; a < kMaxPeaks; ++a) { o.pv[a] = fin.v[a]; o.pi[a] = fin.i[a]; o.pw[a] = fin.w[a]; }
 }
 
-// last kernel: one thread per row joins the parts in order and writes the
-// row's results as k_periodogram does
+// last kernel: one wave per row. Lanes take parts lane, lane + 64, ...:
+// the row's maximum, the parts' peak counts and internal peaks (into each
+// lane's own list), and a copy of the part records in LDS; lane 0 then sums
+// the statistics and joins the boundary runs in part order from that copy;
+// the 64 lists merge into the row's best peaks by rounds of wave argmax (the
+// same entries and order as one list fed everything). Results as
+// k_periodogram writes them.
+constexpr int kMaxParts = 256;   // parts per row in the split path
+
 __global__ __launch_bounds__(64) void k_pgram_final(const PartStats* __restrict__ ps, int64_t rows, int parts,
                                                     const double* __restrict__ periods, int32_t min_width,
                                                     int32_t max_peaks, float* __restrict__ sde,
@@ -724,33 +731,68 @@ __global__ __launch_bounds__(64) void k_pgram_final(const PartStats* __restrict_
                                                     int32_t* __restrict__ n_peaks, float* __restrict__ pval,
                                                     int64_t* __restrict__ pidx, int32_t* __restrict__ pwidth,
                                                     int32_t* __restrict__ pharm) {
-    const int64_t row = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    if (row >= rows) return;
+    __shared__ PartStats sps[kMaxParts];
+    const int64_t row = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (row >= rows || parts > kMaxParts) return;
     const PartStats* rp = ps + row * parts;
-    int64_t m;
-    double mean, sdv;
-    row_mean_sd(rp, parts, true, m, mean, sdv);
     float mx = -INFINITY;
     int64_t amx = INT64_MAX;
-    PeakList fin;
-    fin.init();
+    PeakList pl;
+    pl.init();
     int32_t total = 0;
-    Run open{0, -INFINITY, INT64_MAX};
-    for (int p = 0; p < parts; ++p) {
+    for (int p = lane; p < parts; p += 64) {
         const PartStats& o = rp[p];
+        sps[p] = o;
         if (beats(o.mx, o.amx, mx, amx)) { mx = o.mx; amx = o.amx; }
         total += o.np;
         for (int a = 0; a < kMaxPeaks; ++a)
-            if (o.pi[a] != INT64_MAX) fin.insert(o.pv[a], o.pi[a], o.pw[a]);
-        if (o.full) {
-            open = join(open, o.head);
-        } else {
-            const Run r = join(open, o.head);
-            if (r.len > min_width) { ++total; fin.insert(r.mx, r.arg, (int32_t)r.len); }
-            open = o.tail;
-        }
+            if (o.pi[a] != INT64_MAX) pl.insert(o.pv[a], o.pi[a], o.pw[a]);
     }
-    if (open.len > min_width) { ++total; fin.insert(open.mx, open.arg, (int32_t)open.len); }
+    __syncthreads();
+    int64_t m = 0;
+    double mean = 0.0, sdv = 0.0;
+    if (lane == 0) {
+        row_mean_sd(sps, parts, true, m, mean, sdv);
+        Run open{0, -INFINITY, INT64_MAX};
+        for (int p = 0; p < parts; ++p) {
+            const PartStats& o = sps[p];
+            if (o.full) {
+                open = join(open, o.head);
+            } else {
+                const Run r = join(open, o.head);
+                if (r.len > min_width) { ++total; pl.insert(r.mx, r.arg, (int32_t)r.len); }
+                open = o.tail;
+            }
+        }
+        if (open.len > min_width) { ++total; pl.insert(open.mx, open.arg, (int32_t)open.len); }
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+        total += __shfl_xor(total, d);
+        const float ov = __shfl_xor(mx, d);
+        const int64_t oa = shfl_xor64(amx, d);
+        if (beats(ov, oa, mx, amx)) { mx = ov; amx = oa; }
+    }
+    PeakList fin;
+    int h = 0;
+    for (int rnd = 0; rnd < kMaxPeaks; ++rnd) {
+        float bv = h < kMaxPeaks ? pl.v[h] : -INFINITY;
+        int64_t bi = h < kMaxPeaks ? pl.i[h] : INT64_MAX;
+        int bl = lane;
+        for (int d = 32; d > 0; d >>= 1) {
+            const float ov = __shfl_xor(bv, d);
+            const int64_t oi = shfl_xor64(bi, d);
+            const int ol = __shfl_xor(bl, d);
+            if (beats(ov, oi, bv, bi) || (ov == bv && oi == bi && ol < bl)) { bv = ov; bi = oi; bl = ol; }
+        }
+        int32_t bw = (lane == bl && h < kMaxPeaks) ? pl.w[h] : 0;
+        bw = __shfl(bw, bl);
+        fin.v[rnd] = bv;
+        fin.i[rnd] = bi;
+        fin.w[rnd] = bw;
+        if (lane == bl) ++h;
+    }
+    if (lane != 0) return;
     sde[row] = (float)((m && sdv > 0.0) ? ((double)mx - mean) / sdv : 0.0);
     mean_out[row] = (float)mean;
     sd_out[row] = (float)sdv;
@@ -793,7 +835,7 @@ hipError_t launch_periodogram(const float* values, int64_t rows, int64_t len, co
         if (hipGetDevice(&dev) == hipSuccess)
             (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
         const int64_t want = (2 * (int64_t)n_cu + rows - 1) / rows;
-        parts = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(want, 256), len / 16384));
+        parts = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(want, kMaxParts), len / 16384));
     }
     if (parts <= 1) {
         hipLaunchKernelGGL(k_periodogram, dim3((unsigned)rows), dim3(kTopThreads), 0, s, values, periods,
@@ -808,7 +850,7 @@ hipError_t launch_periodogram(const float* values, int64_t rows, int64_t len, co
     hipLaunchKernelGGL(k_pgram_stats, grid, dim3(kTopThreads), 0, s, values, len, parts, 0, ps);
     hipLaunchKernelGGL(k_pgram_stats, grid, dim3(kTopThreads), 0, s, values, len, parts, 1, ps);
     hipLaunchKernelGGL(k_pgram_runs, grid, dim3(kTopThreads), 0, s, values, len, parts, nsigma, min_width, ps);
-    hipLaunchKernelGGL(k_pgram_final, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, s, (const PartStats*)ps,
+    hipLaunchKernelGGL(k_pgram_final, dim3((unsigned)rows), dim3(64), 0, s, (const PartStats*)ps,
                        rows, parts, periods, min_width, max_peaks, sde, mean, sd, n_peaks, pval, pidx, pwidth,
                        pharm);
     e = hipGetLastError();
