@@ -238,18 +238,34 @@ struct PeakList {
     __device__ void init() {
         for (int a = 0; a < kMaxPeaks; ++a) { v[a] = -INFINITY; i[a] = INT64_MAX; w[a] = 0; }
     }
+    // the entry walks down the list and changes places with every entry it
+    // beats (the list stays sorted, its last entry drops out); fixed slots,
+    // so the list stays in registers
     __device__ void insert(float pv, int64_t pi, int32_t pw) {
         if (!beats(pv, pi, v[kMaxPeaks - 1], i[kMaxPeaks - 1])) return;
-        int pos = kMaxPeaks - 1;
-        while (pos > 0 && beats(pv, pi, v[pos - 1], i[pos - 1])) {
-            v[pos] = v[pos - 1];
-            i[pos] = i[pos - 1];
-            w[pos] = w[pos - 1];
-            --pos;
+#pragma unroll
+        for (int a = 0; a < kMaxPeaks; ++a) {
+            if (beats(pv, pi, v[a], i[a])) {
+                const float tv = v[a];
+                const int64_t ti = i[a];
+                const int32_t tw = w[a];
+                v[a] = pv;
+                i[a] = pi;
+                w[a] = pw;
+                pv = tv;
+                pi = ti;
+                pw = tw;
+            }
         }
-        v[pos] = pv;
-        i[pos] = pi;
-        w[pos] = pw;
+    }
+    // entry h (kMaxPeaks and above: an empty place), read by fixed slots
+    __device__ void at(int h, float& ov, int64_t& oi, int32_t& ow) const {
+        ov = -INFINITY;
+        oi = INT64_MAX;
+        ow = 0;
+#pragma unroll
+        for (int a = 0; a < kMaxPeaks; ++a)
+            if (a == h) { ov = v[a]; oi = i[a]; ow = w[a]; }
     }
 };
 
@@ -452,8 +468,10 @@ __global__ __launch_bounds__(kTopThreads) void k_periodogram(
     // merge the per-thread lists wave by wave: kMaxPeaks rounds of a wave argmax
     int h = 0;
     for (int rnd = 0; rnd < kMaxPeaks; ++rnd) {
-        float bv = h < kMaxPeaks ? pl.v[h] : -INFINITY;
-        int64_t bi = h < kMaxPeaks ? pl.i[h] : INT64_MAX;
+        float bv;
+        int64_t bi;
+        int32_t bw;
+        pl.at(h, bv, bi, bw);
         int bl = lane;
         for (int d = 32; d > 0; d >>= 1) {
             const float ov = __shfl_xor(bv, d);
@@ -461,10 +479,7 @@ __global__ __launch_bounds__(kTopThreads) void k_periodogram(
             const int ol = __shfl_xor(bl, d);
             if (beats(ov, oi, bv, bi) || (ov == bv && oi == bi && ol < bl)) { bv = ov; bi = oi; bl = ol; }
         }
-        int32_t bw = 0;
-        for (int a = 0; a < kMaxPeaks; ++a)     // the winner's width (compile-time slots)
-            if (lane == bl && a == h) bw = pl.w[a];
-        bw = __shfl(bw, bl);
+        bw = __shfl(bw, bl);   // the winner's width
         if (lane == 0) { sm.wv[wave][rnd] = bv; sm.wi[wave][rnd] = bi; sm.ww[wave][rnd] = bw; }
         if (lane == bl) ++h;
     }
@@ -494,7 +509,9 @@ __global__ __launch_bounds__(kTopThreads) void k_periodogram(
     sd_out[row] = (float)sdv;
     n_peaks[row] = total;
     const double p0 = (periods && fin.i[0] != INT64_MAX) ? periods[fin.i[0]] : 0.0;
-    for (int a = 0; a < max_peaks; ++a) {
+#pragma unroll
+    for (int a = 0; a < kMaxPeaks; ++a) {
+        if (a >= max_peaks) break;
         const bool has = fin.i[a] != INT64_MAX;
         pval[row * max_peaks + a] = has ? fin.v[a] : -INFINITY;
         pidx[row * max_peaks + a] = has ? fin.i[a] : -1;
@@ -674,8 +691,10 @@ __global__ __launch_bounds__(kTopThreads) void k_pgram_runs(const float* __restr
     sm.tail[tid] = full ? Run{0, -INFINITY, INT64_MAX} : cur;
     int h = 0;
     for (int rnd = 0; rnd < kMaxPeaks; ++rnd) {
-        float bv = h < kMaxPeaks ? pl.v[h] : -INFINITY;
-        int64_t bi = h < kMaxPeaks ? pl.i[h] : INT64_MAX;
+        float bv;
+        int64_t bi;
+        int32_t bw;
+        pl.at(h, bv, bi, bw);
         int bl = lane;
         for (int d = 32; d > 0; d >>= 1) {
             const float ov = __shfl_xor(bv, d);
@@ -683,10 +702,7 @@ __global__ __launch_bounds__(kTopThreads) void k_pgram_runs(const float* __restr
             const int ol = __shfl_xor(bl, d);
             if (beats(ov, oi, bv, bi) || (ov == bv && oi == bi && ol < bl)) { bv = ov; bi = oi; bl = ol; }
         }
-        int32_t bw = 0;
-        for (int a = 0; a < kMaxPeaks; ++a)
-            if (lane == bl && a == h) bw = pl.w[a];
-        bw = __shfl(bw, bl);
+        bw = __shfl(bw, bl);   // the winner's width
         if (lane == 0) { sm.wv[wave][rnd] = bv; sm.wi[wave][rnd] = bi; sm.ww[wave][rnd] = bw; }
         if (lane == bl) ++h;
     }
@@ -775,9 +791,12 @@ __global__ __launch_bounds__(64) void k_pgram_final(const PartStats* __restrict_
     }
     PeakList fin;
     int h = 0;
+#pragma unroll
     for (int rnd = 0; rnd < kMaxPeaks; ++rnd) {
-        float bv = h < kMaxPeaks ? pl.v[h] : -INFINITY;
-        int64_t bi = h < kMaxPeaks ? pl.i[h] : INT64_MAX;
+        float bv;
+        int64_t bi;
+        int32_t bw;
+        pl.at(h, bv, bi, bw);
         int bl = lane;
         for (int d = 32; d > 0; d >>= 1) {
             const float ov = __shfl_xor(bv, d);
@@ -785,8 +804,7 @@ __global__ __launch_bounds__(64) void k_pgram_final(const PartStats* __restrict_
             const int ol = __shfl_xor(bl, d);
             if (beats(ov, oi, bv, bi) || (ov == bv && oi == bi && ol < bl)) { bv = ov; bi = oi; bl = ol; }
         }
-        int32_t bw = (lane == bl && h < kMaxPeaks) ? pl.w[h] : 0;
-        bw = __shfl(bw, bl);
+        bw = __shfl(bw, bl);   // the winner's width
         fin.v[rnd] = bv;
         fin.i[rnd] = bi;
         fin.w[rnd] = bw;
@@ -798,7 +816,9 @@ __global__ __launch_bounds__(64) void k_pgram_final(const PartStats* __restrict_
     sd_out[row] = (float)sdv;
     n_peaks[row] = total;
     const double p0 = (periods && fin.i[0] != INT64_MAX) ? periods[fin.i[0]] : 0.0;
-    for (int a = 0; a < max_peaks; ++a) {
+#pragma unroll
+    for (int a = 0; a < kMaxPeaks; ++a) {
+        if (a >= max_peaks) break;
         const bool has = fin.i[a] != INT64_MAX;
         pval[row * max_peaks + a] = has ? fin.v[a] : -INFINITY;
         pidx[row * max_peaks + a] = has ? fin.i[a] : -1;
