@@ -549,7 +549,19 @@ struct PartStats {
     int32_t pw[kMaxPeaks];
 };
 
-__device__ __forceinline__ void row_mean_sd(const PartStats* ps, int parts, bool want_sd, int64_t& m,
+constexpr int kMaxParts = 256;   // parts per row in the split path
+
+// A part's count and sums, copied to LDS by many threads at once so that
+// the serial sums below read LDS rather than a chain of global loads.
+struct PartSums {
+    int64_t m;
+    double s, q;
+};
+
+// Row count, mean and (with want_sd) standard deviation from the parts'
+// records (PartStats or PartSums), summed in part order.
+template <class S>
+__device__ __forceinline__ void row_mean_sd(const S* ps, int parts, bool want_sd, int64_t& m,
                                             double& mean, double& sd) {
     m = 0;
     double ts = 0.0, tq = 0.0;
@@ -571,6 +583,8 @@ __global__ __launch_bounds__(kTopThreads) void k_pgram_stats(const float* __rest
     __shared__ float mred[kTopWaves];
     __shared__ int64_t ared[kTopWaves];
     __shared__ double mean_s;
+    __shared__ PartSums psums[kMaxParts];
+    if (parts > kMaxParts) return;   // the host splits a row into at most kMaxParts parts
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t row = blockIdx.x / parts;
     const int part = blockIdx.x - (int)row * parts;
@@ -579,10 +593,12 @@ __global__ __launch_bounds__(kTopThreads) void k_pgram_stats(const float* __rest
     const float* v = values + row * len;
     PartStats* rp = ps + row * parts;
     if (stage == 1) {
+        for (int p = tid; p < parts; p += kTopThreads) psums[p] = PartSums{rp[p].m, rp[p].s, 0.0};
+        __syncthreads();
         if (tid == 0) {
             int64_t m;
             double mean, sd;
-            row_mean_sd(rp, parts, false, m, mean, sd);
+            row_mean_sd(psums, parts, false, m, mean, sd);
             mean_s = mean;
         }
         __syncthreads();
@@ -643,6 +659,8 @@ __global__ __launch_bounds__(kTopThreads) void k_pgram_runs(const float* __restr
                                                             int parts, float nsigma, int32_t min_width,
                                                             PartStats* __restrict__ ps) {
     __shared__ PeriodogramLds sm;
+    __shared__ PartSums psums[kMaxParts];
+    if (parts > kMaxParts) return;   // the host splits a row into at most kMaxParts parts
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t row = blockIdx.x / parts;
     const int part = blockIdx.x - (int)row * parts;
@@ -650,10 +668,12 @@ __global__ __launch_bounds__(kTopThreads) void k_pgram_runs(const float* __restr
     const int64_t lo = min(len, (int64_t)part * chunk), hi = min(len, lo + chunk);
     const float* v = values + row * len;
     PartStats* rp = ps + row * parts;
+    for (int p = tid; p < parts; p += kTopThreads) psums[p] = PartSums{rp[p].m, rp[p].s, rp[p].q};
+    __syncthreads();
     if (tid == 0) {
         int64_t m;
         double mean, sd;
-        row_mean_sd(rp, parts, true, m, mean, sd);
+        row_mean_sd(psums, parts, true, m, mean, sd);
         sm.thr = mean + (double)nsigma * sd;
     }
     __syncthreads();
@@ -738,8 +758,6 @@ __global__ __launch_bounds__(kTopThreads) void k_pgram_runs(const float* __restr
 // the 64 lists merge into the row's best peaks by rounds of wave argmax (the
 // same entries and order as one list fed everything). Results as
 // k_periodogram writes them.
-constexpr int kMaxParts = 256;   // parts per row in the split path
-
 __global__ __launch_bounds__(64) void k_pgram_final(const PartStats* __restrict__ ps, int64_t rows, int parts,
                                                     const double* __restrict__ periods, int32_t min_width,
                                                     int32_t max_peaks, float* __restrict__ sde,
