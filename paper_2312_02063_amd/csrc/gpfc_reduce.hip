@@ -174,8 +174,14 @@ __global__ __launch_bounds__(kTopThreads) void k_topk_rows(const float* __restri
     lk_s[threadIdx.x] = lk;
     if (threadIdx.x < 64) { ov_s[threadIdx.x] = -INFINITY; oi_s[threadIdx.x] = -1; }
     __syncthreads();
+    // rank within the wave; equal keys (only empty places, key 0, can be
+    // equal) are ordered by lane, so the ranks are a permutation of 0..63 and
+    // the scatter below fills every slot of the wave's sorted list
     int lr = 0;
-    for (int j = 0; j < 64; ++j) lr += lk_s[wave * 64 + j] > lk ? 1 : 0;
+    for (int j = 0; j < 64; ++j) {
+        const uint64_t o = lk_s[wave * 64 + j];
+        lr += (o > lk || (o == lk && j < lane)) ? 1 : 0;
+    }
     __syncthreads();
     lk_s[wave * 64 + lr] = lk;   // each wave's keys, descending
     __syncthreads();

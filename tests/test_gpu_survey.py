@@ -70,6 +70,32 @@ def test_topk_split_row_mostly_empty(torch_dev):
     np.testing.assert_array_equal(v.cpu().numpy(), ov)
 
 
+@pytest.mark.parametrize("rows,n,top,nan_frac,gate_pass,seed", [
+    (1, 1024, 64, 0.9, None, 1), (1, 1024, 64, 0.9, None, 2), (4, 1024, 64, 0.95, None, 3),
+    (1, 1024, 64, 0.0, 0.7, 4), (3, 5000, 64, 0.3, 0.3, 5), (2, 1024, 48, 0.9, None, 6),
+    (1, 900_000, 64, 0.9995, None, 7), (1, 600_000, 64, 0.0, 0.0003, 8)])
+def test_topk_wave_lists_with_holes(torch_dev, rows, n, top, nan_frac, gate_pass, seed):
+    """Rows where a wave's first 64 elements leave empty places at scattered
+    lanes (NaN or gated out) and the wave sees fewer than `top` entries in
+    all: the per-wave sorted lists must still be a permutation of the places.
+    The long rows run split over many blocks whose parts leave holes too."""
+    from paper_2312_02063_amd import topk
+    torch = torch_dev
+    rng = np.random.default_rng(seed)
+    x = np.round(rng.normal(size=(rows, n)) * 6).astype(np.float32)
+    x[rng.uniform(size=(rows, n)) < nan_frac] = np.nan
+    g = None
+    if gate_pass is not None:
+        g = np.where(rng.uniform(size=(rows, n)) < gate_pass, 9.0, 1.0).astype(np.float32)
+    _say(f"topk holes rows={rows} n={n} top={top} nan={nan_frac} gate={gate_pass} seed={seed}")
+    v, i = topk(_dev(torch, x, torch.float32), top,
+                None if g is None else _dev(torch, g, torch.float32), 5.0)
+    torch.cuda.synchronize()
+    ov, oi = oracle.topk(x, top, g, 5.0)
+    np.testing.assert_array_equal(i.cpu().numpy(), oi)
+    np.testing.assert_array_equal(v.cpu().numpy(), ov)
+
+
 def test_topk_ascending_worst_case(torch_dev):
     """Ascending values make every element enter the candidate lists."""
     from paper_2312_02063_amd import topk
