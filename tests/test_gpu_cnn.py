@@ -183,9 +183,10 @@ def test_fp8_forward_error(torch_dev):
     zb = net.forward(xt).cpu().numpy()
     zo = oracle.cnn_forward(p, x)
     e8, eb = _rel(z8, zo), _rel(zb, zo)
-    print(f"fp8 forward relative L2 error vs FP64: {e8:.3e} (bf16 {eb:.3e})")
+    cc = np.corrcoef(z8, zo)[0, 1]
+    print(f"fp8 forward relative L2 error vs FP64: {e8:.3e} (bf16 {eb:.3e}); correlation {cc:.5f}")
     assert e8 < 0.15
-    assert np.corrcoef(z8, zo)[0, 1] > 0.9
+    assert cc > 0.99
 
 
 @pytest.mark.parametrize("B", [1, 7, 8, 9, 300, 4099, 65541])

@@ -109,3 +109,70 @@ def test_training_reduces_loss():
         oracle.adam(p, g, m, v, step, lr=1e-3)
     l1, _ = oracle.cnn_loss_grad(p, x, y)
     assert l1 < l0
+
+
+def _layout():
+    """Offsets of the canonical parameter layout: conv l weight [Cout][Cin][5]
+    then bias, then fc weight [out][in] then bias, in network order."""
+    shapes = synth.cnn_param_shapes()
+    offs, o = [], 0
+    for s in shapes:
+        offs.append(o)
+        o += int(np.prod(s))
+    return shapes, offs
+
+
+def test_dense_head_closed_form():
+    """Hand-set weights make the whole network a known piecewise-linear
+    function of the input: every convolution passes channel 0 through its
+    centre tap (other channels 0), so block 4 holds, in channel 0 only,
+    M_p = max(0, max of x over positions 16p..16p+15); the fully connected
+    layers then combine the M_p through ReLUs that are active for some inputs
+    and not for others. A forward pass that flattened position-major, dropped
+    a ReLU, or mixed up a layer's weights or biases gives another value."""
+    shapes, offs = _layout()
+    p = np.zeros(NP)
+
+    def put(i, idx, v):
+        a = p[offs[i]:offs[i] + int(np.prod(shapes[i]))].reshape(shapes[i])
+        a[idx] = v
+
+    for layer in range(4):                     # conv weights at even indices, biases odd
+        put(2 * layer, (0, 0, 2), 1.0)
+    # FC1 (params 8, 9): h1 = relu(W1 a + b1) over the channel-major flatten
+    put(8, (0, slice(0, 16)), 1.0)
+    put(9, 0, -20.0)
+    put(8, (1, 0), 1.0)
+    put(8, (1, 1), -1.0)
+    put(8, (2, 0), -1.0)
+    put(8, (2, 1), 1.0)
+    put(8, (3, 5), 2.0)
+    put(9, 3, -1.0)
+    # FC2 (params 10, 11)
+    put(10, (0, 0), 1.0)
+    put(10, (0, 1), -2.0)
+    put(11, 0, 0.5)
+    put(10, (1, 2), 1.0)
+    put(10, (1, 0), -1.0)
+    put(10, (2, 3), 1.0)
+    put(10, (2, 1), 1.0)
+    # FC3 (params 12, 13)
+    put(12, (0, 0), 1.5)
+    put(12, (0, 1), -0.7)
+    put(12, (0, 2), 0.25)
+    put(13, 0, 0.1)
+
+    rng = np.random.default_rng(21)
+    x = rng.normal(size=(64, 256)) * rng.uniform(0.2, 2.0, size=(64, 1))
+    relu = lambda v: np.maximum(v, 0.0)          # noqa: E731
+    M = relu(x.reshape(64, 16, 16).max(axis=2))  # [input][p]
+    h1 = np.stack([relu(M.sum(axis=1) - 20.0), relu(M[:, 0] - M[:, 1]), relu(M[:, 1] - M[:, 0]),
+                   relu(2.0 * M[:, 5] - 1.0)], axis=1)
+    h2 = np.stack([relu(h1[:, 0] - 2.0 * h1[:, 1] + 0.5), relu(h1[:, 2] - h1[:, 0]),
+                   relu(h1[:, 3] + h1[:, 1])], axis=1)
+    want = 1.5 * h2[:, 0] - 0.7 * h2[:, 1] + 0.25 * h2[:, 2] + 0.1
+    # the inputs exercise both sides of every ReLU that decides the result
+    assert (M.sum(axis=1) > 20).any() and (M.sum(axis=1) < 20).any()
+    assert ((h1[:, 0] - 2 * h1[:, 1] + 0.5) < 0).any() and ((h1[:, 0] - 2 * h1[:, 1] + 0.5) > 0).any()
+    assert ((h1[:, 2] - h1[:, 0]) < 0).any() and ((h1[:, 2] - h1[:, 0]) > 0).any()
+    np.testing.assert_allclose(oracle.cnn_forward(p, x), want, rtol=1e-12, atol=1e-12)
