@@ -30,11 +30,12 @@ FMIN, FMAX = 1.0, 5.0                   # 1/d: periods 0.2-1.0 d
 METRIC = "fold+score trial periods/s (65k-pt curve, 256 bins) vs plain fold; roofline %"
 
 # MI355X: 256 CUs at 2.4 GHz; LDS atomics 128 B/clk/CU (a wave's 64-bit atomic, 512 B, takes
-# at least 4 LDS cycles; plain reads run at 256 B/clk).
+# at least 4 LDS cycles; plain reads run at 256 B/clk). The measured denominators come from the
+# library's micro-benchmarks (gpfc_roof_probe), run live by this script.
 CUS, CLOCK = 256, 2.4e9
 LDS_PEAK_GBS = CUS * 128 * CLOCK / 1e9          # 78,643 GB/s
-LDS_U64_ATOMIC_MEASURED = 6.17e12               # conflict-free ds_add_u64 lane-ops/s (probe)
 VALU_PEAK_LANE_OPS = CUS * 64 * CLOCK           # 3.93e13 lane-ops/s (FP64 and 32-bit ops alike)
+FP64_PEAK_FLOPS = 78.6e12                       # published FP64 vector peak
 VALU_OPS_PER_UPDATE = 3.5                       # fma, perm, mov_b64, half a max3_u16 (gfx950 ISA)
 BYTES_PER_UPDATE = 8                            # one 64-bit packed (count, sum) LDS increment
 
@@ -58,6 +59,39 @@ def measured_traffic():
     if d.get("kernel_src_hash") != kernel_src_hash():
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+def host_cpu():
+    """CPU model and logical core count of the host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count()}
+
+
+def roof_probes():
+    """The roofline denominators measured on this GPU (gpfc_roof_probe)."""
+    from paper_2312_02063_amd import _lib
+    out = {}
+    for name, kind, unit in (("lds_u64_atomic", _lib.ROOF_LDS_U64, "lane-ops/s"),
+                             ("lds_u32_atomic", _lib.ROOF_LDS_U32, "lane-ops/s"),
+                             ("lds_f32_atomic", _lib.ROOF_LDS_F32, "lane-ops/s"),
+                             ("fp64_fma", _lib.ROOF_FP64_FMA, "flop/s"),
+                             ("hbm_copy", _lib.ROOF_HBM_COPY, "B/s")):
+        rate, ms = _lib.roof_probe(kind)
+        out[name] = {"rate": rate, "unit": unit, "ms": ms}
+    out["lds_u64_atomic"]["lanes_per_clk_per_cu"] = out["lds_u64_atomic"]["rate"] / CUS / CLOCK
+    out["lds_u32_atomic"]["lanes_per_clk_per_cu"] = out["lds_u32_atomic"]["rate"] / CUS / CLOCK
+    out["lds_f32_atomic"]["lanes_per_clk_per_cu"] = out["lds_f32_atomic"]["rate"] / CUS / CLOCK
+    out["fp64_fma"]["frac_of_published"] = out["fp64_fma"]["rate"] / FP64_PEAK_FLOPS
+    out["hbm_copy"]["frac_of_published"] = out["hbm_copy"]["rate"] / (HBM_PEAK_GBS * 1e9)
+    return out
 
 
 def cpu_baseline(c, periods, sample):
@@ -84,7 +118,7 @@ def cpu_baseline(c, periods, sample):
     return {"value": n_par / dt_par, "unit": "periods/s", "cores": cores, "kind": "oracle",
             "sample": f"{n_par} periods drawn (seed 2024) from the 2,000,000-period grid, same "
                       f"65,000-sample curve, fold + box-SNR in FP64, OpenMP over periods on {cores} threads",
-            "seconds": dt_par,
+            "seconds": dt_par, "host": host_cpu(),
             "one_core": {"value": (sample // 4) / dt_one, "periods": sample // 4, "seconds": dt_one}}
 
 
@@ -282,6 +316,8 @@ def main():
                     help="only the bf16 training step at batch 16,384 (for trace runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (HBM counter calibration)")
+    ap.add_argument("--roof", action="store_true",
+                    help="only the roofline micro-benchmarks (LDS atomics, FP64 FMA, HBM copy)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -297,6 +333,9 @@ def main():
         print(json.dumps({"error": "no GPU visible"}), flush=True)
         sys.exit(1)
     dev = torch.device("cuda", 0)
+    if args.roof:
+        print(json.dumps(roof_probes()), flush=True)
+        return
     if args.cnn_only:
         print(json.dumps(cnn_inference_row(dev, max(1, args.steps))), flush=True)
         return
@@ -362,6 +401,9 @@ def main():
         torch.add(a, 1.0, out=b)
         torch.cuda.synchronize()
 
+    roof = roof_probes()
+    u64_rate = roof["lds_u64_atomic"]["rate"]
+
     rows = measure_rows(plan, t, f, pp, periods, args.survey_stars) if args.rows else None
 
     cpu = None
@@ -379,7 +421,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64+i64",
+        "dtype_detail": "FP64 phase reduction; bin counts and flux sums as exact 64-bit integer "
+                        "fixed-point sums; box scan in FP32 with the winning box re-evaluated in FP64",
         "data": "synthetic",
         "config": {"workload": "kepler-long fold+score: 65,000 samples over 1,470 d (10% in gaps, "
                                "white + AR(1) noise, one box transit), 2,000,000 periods uniform in "
@@ -388,8 +432,10 @@ def main():
         "roofline": {"bound": "lds", "achieved": achieved_gbs, "peak": LDS_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved_gbs / LDS_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_fold_score", "kernel_ms": kms,
-                     "frac_of_measured_ds_add_u64": updates / (kms / 1e3) / LDS_U64_ATOMIC_MEASURED,
+                     "measured_ds_add_u64_lane_ops_per_s": u64_rate,
+                     "frac_of_measured_ds_add_u64": updates / (kms / 1e3) / u64_rate,
                      "valu_frac": VALU_OPS_PER_UPDATE * updates / (kms / 1e3) / VALU_PEAK_LANE_OPS},
+        "roof_probes": roof,
         "cpu_baseline": cpu,
         "updates_per_s": updates / (ms_step / 1e3),
         "plain_fold_periods_per_s": naive,

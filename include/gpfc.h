@@ -32,16 +32,22 @@ extern "C" {
 #endif
 
 #define GPFC_OK 0
-#define GPFC_EINVAL (-1)   /* null pointer, negative size, nbins < 1, bad widths */
-#define GPFC_ENOTSUP (-2)  /* nbins not a power of two in [1, 256] */
-#define GPFC_ERANGE (-3)   /* n > GPFC_MAX_SAMPLES or k too large for the grid */
+#define GPFC_EINVAL (-1)   /* null pointer, negative size, nbins < 1, bad widths,
+                              non-finite t or flux (reported by gpfc_sync / gpfc_curve_stats) */
+#define GPFC_ENOTSUP (-2)  /* nbins not a power of two in [1, 4096] (or outside the
+                              narrower range a call states) */
+#define GPFC_ERANGE (-3)   /* n or k beyond what the call takes */
 #define GPFC_ENOMEM (-4)   /* device workspace allocation failed */
 #define GPFC_EDEVICE (-5)  /* a HIP call failed; gpfc_last_error() has the text */
 #define GPFC_EIO (-6)      /* a network file could not be written, read, or is not one */
 
-#define GPFC_MAX_SAMPLES 262143   /* 2^18 - 1: limit of the packed 64-bit bin counter */
-#define GPFC_MAX_NBINS 256
-#define GPFC_MAX_WIDTHS 16
+#define GPFC_MAX_SAMPLES 2147483647LL   /* 2^31 - 1 samples per curve */
+#define GPFC_MAX_PACKED 262143          /* 2^18 - 1: curves the fused kernels fold in one
+                                           pass (the packed 64-bit bin counter); longer
+                                           single curves take the general path */
+#define GPFC_MAX_NBINS 4096
+#define GPFC_FUSED_MAX_NBINS 256        /* nbins of the fused kernels, the batch and the survey */
+#define GPFC_MAX_WIDTHS 24
 
 typedef struct gpfc_plan gpfc_plan;
 
@@ -54,8 +60,15 @@ typedef struct gpfc_curve {
     double tmax;     /* max |t| */
     double maxdev;   /* max |flux - ref| */
     int64_t n;       /* samples */
-    int32_t exact;   /* 1: every flux - ref is an integer multiple of qscale, bin sums are exact */
-    int32_t finite;  /* 1: every t and flux is finite; 0 makes all results unspecified */
+    int32_t exact;   /* 1: bin sums are exact (every flux - ref is an integer multiple of the
+                        fixed-point unit); 0: each sample's deviation was rounded to a unit of
+                        about maxdev * 2^-52 (flux spanning more than 53 bits of range) */
+    int32_t finite;  /* 1: every t and flux is finite; 0 makes all results unspecified and
+                        is reported as GPFC_EINVAL by gpfc_curve_stats and gpfc_sync */
+    int32_t words;   /* 1: one 27-bit fixed-point word per sample; 2: two words (deviations
+                        needing more than 27 bits, e.g. zero-centred flux): the fused folds
+                        then take two passes of 32 periods per block */
+    int32_t pad;
 } gpfc_curve;
 
 /* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
@@ -75,21 +88,48 @@ const char *gpfc_last_error(void);
  */
 int32_t gpfc_plan_create(gpfc_plan **out, int32_t device);
 
+/*
+ * Plan options (host struct) for gpfc_plan_create_opts; zero fields take the
+ * defaults of gpfc_plan_create.
+ *   widths[nw]      box widths, as gpfc_plan_set_widths (nw = 0: default set)
+ *   split           sample split, as gpfc_plan_set_split (0: automatic)
+ *   tune_cache      autotuner cache path gpfc_autotune uses when its own
+ *                   cache_path is NULL (NULL or "": none); copied
+ *   workspace_bytes largest device workspace a chunk of the general path
+ *                   (nbins > 256 or n > GPFC_MAX_PACKED) may take
+ *                   (0: 1 GiB; at least one 64-period chunk is always taken)
+ * The fold's precision is not an option: bin counts and sums are exact
+ * integers (gpfc_fold_f32_prepared gives the FP32 forms for comparison).
+ */
+typedef struct gpfc_plan_opts {
+    int32_t device;
+    int32_t nw;
+    int32_t widths[GPFC_MAX_WIDTHS];
+    int32_t split;
+    int32_t pad;
+    const char *tune_cache;
+    int64_t workspace_bytes;
+} gpfc_plan_opts;
+
+int32_t gpfc_plan_create_opts(gpfc_plan **out, const gpfc_plan_opts *opts_host);
+
 /* Free a plan and its workspace (synchronises the device first). NULL is a no-op. */
 int32_t gpfc_plan_destroy(gpfc_plan *plan);
 
 /*
- * Set the box widths (host array, in coarse bins, 1 <= w < nbins at use,
+ * Set the box widths (host array, in coarse bins, 1 <= w < GPFC_MAX_NBINS,
  * strictly ascending, at most GPFC_MAX_WIDTHS). nw = 0 restores the default
  * set. Widths not below nbins are skipped when a fold with that nbins is
- * scored.
+ * scored. The fused kernels hold 16 widths: with more below nbins, single
+ * curves take the general path and batches and surveys return GPFC_ENOTSUP.
  */
 int32_t gpfc_plan_set_widths(gpfc_plan *plan, const int32_t *widths_host, int32_t nw);
 
 /*
  * Curve statistics (mean, sigma for Eq. 2's per-point noise, fixed-point
  * grid): t f64[n], flux f32[n]. Synchronous: waits for `stream`, then fills
- * the host struct *out.
+ * the host struct *out. Returns GPFC_EINVAL (after filling *out, finite = 0)
+ * when some t or flux is not finite.
  */
 int32_t gpfc_curve_stats(gpfc_plan *plan, const double *t, const float *flux, int64_t n,
                          gpfc_curve *out_host, void *stream);
@@ -103,8 +143,14 @@ int32_t gpfc_curve_stats(gpfc_plan *plan, const double *t, const float *flux, in
  *   counts i32[k][nbins]  samples in the bin
  *   means  f64[k][nbins]  sums / counts, NaN if empty (may be NULL)
  * Inputs: t f64[n], flux f32[n], periods f64[k]; nbins a power of two in
- * [1, 256]; n <= GPFC_MAX_SAMPLES. A period that is not finite and > 0 gives
- * an all-zero row (means NaN). n = 0 or k = 0 is valid.
+ * [1, 4096]; n <= GPFC_MAX_SAMPLES; k < 2^31. A period that is not finite and
+ * > 0 gives an all-zero row (means NaN). n = 0 or k = 0 is valid. Bin sums are
+ * count * ref + (exact fixed-point deviation sum), each term rounded once to
+ * binary64 (see gpfc_curve.exact). nbins <= 256 with n <= GPFC_MAX_PACKED runs
+ * the fused LDS kernel; other shapes run the general path (integer histograms
+ * of sample parts accumulated in a plan workspace that grows on demand), with
+ * identical results where both apply. Non-finite t or flux makes the results
+ * unspecified and is reported by the next gpfc_sync.
  */
 int32_t gpfc_fold(gpfc_plan *plan, const double *t, const float *flux, int64_t n,
                   const double *periods, int64_t k, int32_t nbins,
@@ -122,6 +168,9 @@ int32_t gpfc_fold(gpfc_plan *plan, const double *t, const float *flux, int64_t n
  * depth[k]; a row with no positive box gives snr = depth = 0 and
  * start = width = -1. sigma is the curve's per-point noise (host value,
  * e.g. gpfc_curve.sigma); sigma not > 0 gives that empty result for every row.
+ * nbins a power of two in [1, 4096]. Boxes are compared in FP32 and the
+ * winner evaluated in FP64 (a near-tie may pick a box whose FP64 SNR is
+ * within FP32 rounding of the largest).
  */
 int32_t gpfc_score(gpfc_plan *plan, const double *sums, const int32_t *counts, int64_t k,
                    int32_t nbins, double sigma, float *snr, int32_t *start, int32_t *width,
@@ -130,8 +179,9 @@ int32_t gpfc_score(gpfc_plan *plan, const double *sums, const int32_t *counts, i
 /*
  * Fused fold + score: the fold of gpfc_fold followed by the box-SNR of
  * gpfc_score with sigma = the curve's sample std, without materialising the
- * folded curves (16 bytes written per period). Same inputs as gpfc_fold; same
- * outputs as gpfc_score.
+ * folded curves (16 bytes written per period) when nbins <= 256 and
+ * n <= GPFC_MAX_PACKED; other shapes materialise chunks of folds in the plan's
+ * workspace. Same inputs as gpfc_fold; same outputs as gpfc_score.
  */
 int32_t gpfc_fold_score(gpfc_plan *plan, const double *t, const float *flux, int64_t n,
                         const double *periods, int64_t k, int32_t nbins, float *snr,
@@ -153,7 +203,7 @@ int32_t gpfc_fold_prepared(gpfc_plan *plan, const double *periods, int64_t k, in
 
 /*
  * gpfc_fold_score on the plan's prepared curve (GPFC_EINVAL if none).
- * zfold (may be NULL; needs nbins >= 16): also writes each period's folded
+ * zfold (may be NULL; needs 16 <= nbins <= 256): also writes each period's folded
  * curve normalised for the learned scorer (Sec. 2.1: scaled to unit noise
  * before the CNN), as bfloat16 [k][nbins]: bin means minus their mean over
  * the non-empty bins, divided by their standard deviation (ddof 0); empty bins
@@ -184,7 +234,8 @@ int32_t gpfc_fold_f32_prepared(gpfc_plan *plan, const double *periods, int64_t k
  * its mean flux times the points it takes). Outputs (device, either may be
  * NULL but not both): means f64[k][nbins] (NaN for an invalid period or an
  * empty curve) and zfold u16[k][nbins], bfloat16 z-scores of the means (the
- * network's input). 1 <= nbins <= 256, any integer.
+ * network's input). 1 <= nbins <= 256, any integer; n <= GPFC_MAX_PACKED
+ * (GPFC_ERANGE beyond).
  */
 int32_t gpfc_fold_eqcount_prepared(gpfc_plan *plan, const double *periods, int64_t k,
                                    int32_t nbins, double *means, uint16_t *zfold, void *stream);
@@ -222,7 +273,9 @@ int32_t gpfc_autotune(gpfc_plan *plan, const double *periods, int64_t k, int32_t
  * period_offsets_host[n_curves + 1] (HOST arrays, starting at 0) cut the
  * concatenated t / flux and periods arrays into curves. Work items (a curve
  * and a block of 64 of its periods) are queued longest curve first. A later
- * setup (or gpfc_survey_setup) replaces the batch.
+ * setup (or gpfc_survey_setup) replaces the batch. Each curve holds at most
+ * GPFC_MAX_PACKED samples (GPFC_ERANGE beyond); batch folds take
+ * nbins <= GPFC_FUSED_MAX_NBINS.
  */
 int32_t gpfc_batch_setup(gpfc_plan *plan, const int64_t *sample_offsets_host,
                          const int64_t *period_offsets_host, int32_t n_curves);
@@ -475,7 +528,36 @@ int32_t gpfc_survey_capture(gpfc_plan *plan, gpfc_cnn *cnn, const double *t, con
                             const double *periods, int32_t nbins, const gpfc_survey_out *out,
                             void *stream);
 
-/* hipStreamSynchronize(stream); reports an asynchronous device error. */
+/*
+ * Roofline micro-benchmarks of the running GPU (the measured counterpart of
+ * the paper's breakdown of where its GPU fold spends its time, Sec. 2.4,
+ * Table 1): the denominators the fold's throughput is judged against.
+ *   GPFC_ROOF_LDS_U64   conflict-free 64-bit LDS integer atomics, in the
+ *                       fold's histogram layout (the fold's only operation
+ *                       per sample-period update): lane-ops/s
+ *   GPFC_ROOF_LDS_U32   the same with 32-bit integer atomics: lane-ops/s
+ *   GPFC_ROOF_LDS_F32   32-bit float LDS atomics (the FP32 study fold): lane-ops/s
+ *   GPFC_ROOF_FP64_FMA  independent FP64 FMAs: flop/s (2 per FMA)
+ *   GPFC_ROOF_HBM_COPY  a 1 GiB device-to-device copy: bytes read + written per s
+ * Synchronous on `stream` (device `device`); allocates and frees its own
+ * buffers (2 GiB for the copy). rate_out (host) gets the rate, ms_out (host,
+ * may be NULL) the average launch time.
+ */
+#define GPFC_ROOF_LDS_U64 0
+#define GPFC_ROOF_LDS_U32 1
+#define GPFC_ROOF_LDS_F32 2
+#define GPFC_ROOF_FP64_FMA 3
+#define GPFC_ROOF_HBM_COPY 4
+int32_t gpfc_roof_probe(int32_t device, int32_t kind, double *rate_out, double *ms_out,
+                        void *stream);
+
+/*
+ * hipStreamSynchronize(stream); reports an asynchronous device error
+ * (GPFC_EDEVICE), then GPFC_EINVAL if a curve statistics pass on the stream's
+ * device has seen a non-finite t or flux since the last gpfc_sync or
+ * gpfc_curve_stats (a per-device flag, which this call clears: with several
+ * streams on one device, the next gpfc_sync on any of them reports it).
+ */
 int32_t gpfc_sync(void *stream);
 
 #ifdef __cplusplus

@@ -15,9 +15,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgpfc.so")
 
 OK, EINVAL, ENOTSUP, ERANGE, ENOMEM, EDEVICE, EIO = 0, -1, -2, -3, -4, -5, -6
-MAX_SAMPLES = 262143
-MAX_NBINS = 256
-MAX_WIDTHS = 16
+MAX_SAMPLES = 2147483647
+MAX_PACKED = 262143
+MAX_NBINS = 4096
+FUSED_MAX_NBINS = 256
+MAX_WIDTHS = 24
 
 _lib = None
 
@@ -37,10 +39,19 @@ class Curve(ctypes.Structure):
     """Host mirror of ``gpfc_curve``."""
     _fields_ = [("mean", ctypes.c_double), ("sigma", ctypes.c_double), ("ref", ctypes.c_double),
                 ("qscale", ctypes.c_double), ("tmax", ctypes.c_double), ("maxdev", ctypes.c_double),
-                ("n", ctypes.c_int64), ("exact", ctypes.c_int32), ("finite", ctypes.c_int32)]
+                ("n", ctypes.c_int64), ("exact", ctypes.c_int32), ("finite", ctypes.c_int32),
+                ("words", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
+
+
+class PlanOpts(ctypes.Structure):
+    """Host mirror of ``gpfc_plan_opts``."""
+    _fields_ = [("device", ctypes.c_int32), ("nw", ctypes.c_int32),
+                ("widths", ctypes.c_int32 * MAX_WIDTHS), ("split", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("tune_cache", ctypes.c_char_p),
+                ("workspace_bytes", ctypes.c_int64)]
 
 
 class SurveyOut(ctypes.Structure):
@@ -67,6 +78,7 @@ def load():
         "gpfc_strerror": ([i32], ctypes.c_char_p),
         "gpfc_last_error": ([], ctypes.c_char_p),
         "gpfc_plan_create": ([ctypes.POINTER(vp), i32], i32),
+        "gpfc_plan_create_opts": ([ctypes.POINTER(vp), ctypes.POINTER(PlanOpts)], i32),
         "gpfc_plan_destroy": ([vp], i32),
         "gpfc_plan_set_widths": ([vp, ctypes.POINTER(ctypes.c_int32), i32], i32),
         "gpfc_curve_stats": ([vp, vp, vp, i64, ctypes.POINTER(Curve), vp], i32),
@@ -112,6 +124,7 @@ def load():
         "gpfc_cnn_train_step": ([vp, vp, i32, vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, vp, vp], i32),
         "gpfc_cnn_save": ([vp, ctypes.c_char_p, vp], i32),
+        "gpfc_roof_probe": ([i32, i32, ctypes.POINTER(f64), ctypes.POINTER(f64), vp], i32),
         "gpfc_cnn_load": ([vp, ctypes.c_char_p, vp], i32),
     }
     for name, (args, res) in sig.items():
@@ -125,6 +138,7 @@ def load():
 def exported_symbols():
     """Names the C ABI declares (see include/gpfc.h)."""
     return ["gpfc_version", "gpfc_strerror", "gpfc_last_error", "gpfc_plan_create",
+            "gpfc_plan_create_opts",
             "gpfc_plan_destroy", "gpfc_plan_set_widths", "gpfc_curve_stats", "gpfc_fold",
             "gpfc_score", "gpfc_fold_score", "gpfc_fold_naive", "gpfc_sync", "gpfc_prepare",
             "gpfc_fold_prepared", "gpfc_fold_score_prepared", "gpfc_fold_f32_prepared",
@@ -136,7 +150,20 @@ def exported_symbols():
             "gpfc_cnn_forward_fp8", "gpfc_cnn_set_fused", "gpfc_cnn_train_capture",
             "gpfc_cnn_train_replay", "gpfc_topk", "gpfc_plan_set_split",
             "gpfc_autotune", "gpfc_fold_eqcount_prepared", "gpfc_periodogram_peaks", "gpfc_survey_setup", "gpfc_survey_run",
-            "gpfc_survey_capture", "gpfc_cnn_train_step", "gpfc_cnn_save", "gpfc_cnn_load"]
+            "gpfc_survey_capture", "gpfc_cnn_train_step", "gpfc_cnn_save", "gpfc_cnn_load",
+            "gpfc_roof_probe"]
+
+
+ROOF_LDS_U64, ROOF_LDS_U32, ROOF_LDS_F32, ROOF_FP64_FMA, ROOF_HBM_COPY = 0, 1, 2, 3, 4
+
+
+def roof_probe(kind: int, device: int = 0):
+    """(rate, ms) of one roofline micro-benchmark (see gpfc_roof_probe)."""
+    rate = ctypes.c_double(0.0)
+    ms = ctypes.c_double(0.0)
+    _check(load().gpfc_roof_probe(device, int(kind), ctypes.byref(rate), ctypes.byref(ms), _stream()),
+           "gpfc_roof_probe")
+    return rate.value, ms.value
 
 
 def _check(rc, what):
@@ -168,11 +195,23 @@ def _need(x, dtype, name, dev):
 class Plan:
     """A library plan on one GPU (owns the device workspace and the width set)."""
 
-    def __init__(self, device: int = 0, widths=None):
+    def __init__(self, device: int = 0, widths=None, split: int = 0, tune_cache: str | None = None,
+                 workspace_bytes: int = 0):
         import torch
         self.lib = load()
         self.device = torch.device("cuda", device)
         h = ctypes.c_void_p()
+        if split or tune_cache or workspace_bytes:
+            w = list(widths or [])
+            o = PlanOpts(device=device, nw=len(w), split=int(split),
+                         tune_cache=tune_cache.encode() if tune_cache else None,
+                         workspace_bytes=int(workspace_bytes))
+            for i, x in enumerate(w):
+                o.widths[i] = int(x)
+            _check(self.lib.gpfc_plan_create_opts(ctypes.byref(h), ctypes.byref(o)),
+                   "gpfc_plan_create_opts")
+            self.h = h
+            return
         _check(self.lib.gpfc_plan_create(ctypes.byref(h), device), "gpfc_plan_create")
         self.h = h
         if widths is not None:

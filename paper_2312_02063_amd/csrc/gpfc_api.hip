@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/gpfc.h: argument checks (before
 // any HIP call), plans and their device workspace, error reporting.
 #include <math.h>
+#include <stddef.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -23,7 +24,8 @@ struct SurveyChunk {
 struct gpfc_plan {
     int32_t device = 0;
     gpfc::Rec* rec = nullptr;     // prepared curve: times and packed contributions
-    int64_t cap = 0;              // records rec can hold
+    uint64_t* lo = nullptr;       // low packed words of a two-word curve (parallel to rec)
+    int64_t cap = 0;              // records rec (and lo) can hold
     CurveInfo* info = nullptr;    // device-resident curve description
     int64_t n = -1;               // samples of the prepared curve (-1: none)
     int32_t widths[GPFC_MAX_WIDTHS];
@@ -41,6 +43,7 @@ struct gpfc_plan {
     int32_t* b_counter = nullptr;
     CurveInfo* b_info = nullptr;
     gpfc::Rec* b_rec = nullptr;
+    uint64_t* b_lo = nullptr;
     // survey (gpfc_survey_setup): shared period grid, curves in chunks
     bool b_survey = false;
     int64_t s_k = 0;                   // periods per curve
@@ -56,6 +59,12 @@ struct gpfc_plan {
     char device_name[64] = "";
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    // general path (nbins > 256 or n > GPFC_MAX_PACKED): per-chunk integer
+    // histograms and materialised folds
+    void* w_buf = nullptr;
+    size_t w_cap = 0;
+    int64_t w_limit = int64_t(1) << 30;       // bytes a chunk's workspace may take
+    char tune_cache[512] = "";                // default autotuner cache path ("" none)
 };
 
 namespace {
@@ -69,6 +78,11 @@ int32_t device_error(hipError_t e, const char* what) {
 
 bool pow2_in_range(int32_t nbins) {
     return nbins >= 1 && nbins <= GPFC_MAX_NBINS && (nbins & (nbins - 1)) == 0;
+}
+
+// The fused kernels take nbins <= 256 and curves of at most GPFC_MAX_PACKED samples.
+bool fused_shape(int64_t n, int32_t nbins) {
+    return nbins <= gpfc::kFineBins && n <= GPFC_MAX_PACKED;
 }
 
 // Distinct integers nearest sqrt(2)^j in [1, max(1, nbins/2)], ascending.
@@ -87,11 +101,18 @@ Widths default_widths(int32_t nbins) {
     return w;
 }
 
+// The plan's widths that fit nbins (w < nbins), in order.
 Widths plan_widths(const gpfc_plan* p, int32_t nbins) {
     if (p->nw == 0) return default_widths(nbins);
     Widths w{};
-    for (int i = 0; i < p->nw; ++i) w.w[w.n++] = p->widths[i];
+    for (int i = 0; i < p->nw; ++i)
+        if (p->widths[i] < nbins) w.w[w.n++] = p->widths[i];
     return w;
+}
+
+// The fused scorer holds kFusedWidths widths; more go to the general scorer.
+bool fused_widths(const gpfc_plan* p, int32_t nbins) {
+    return plan_widths(p, nbins).n <= gpfc::kFusedWidths;
 }
 
 int32_t check_fold_args(const gpfc_plan* p, const void* t, const void* flux, int64_t n,
@@ -103,7 +124,7 @@ int32_t check_fold_args(const gpfc_plan* p, const void* t, const void* flux, int
     if (nbins < 1) return GPFC_EINVAL;
     if (!pow2_in_range(nbins)) return GPFC_ENOTSUP;
     if (n > GPFC_MAX_SAMPLES) return GPFC_ERANGE;
-    if ((k + 63) / 64 > 0x7fffffffLL) return GPFC_ERANGE;
+    if (k > 0x7fffffffLL) return GPFC_ERANGE;
     return GPFC_OK;
 }
 
@@ -120,18 +141,25 @@ int32_t prepare_curve(gpfc_plan* p, const double* t, const float* flux, int64_t 
     if (need > p->cap) {
         const int64_t want = need < 8192 ? 8192 : need;
         gpfc::Rec* buf = nullptr;
+        uint64_t* lbuf = nullptr;
         e = hipMalloc(&buf, (size_t)want * sizeof(gpfc::Rec));
-        if (e != hipSuccess) return e == hipErrorOutOfMemory ? GPFC_ENOMEM : device_error(e, "hipMalloc");
+        if (e == hipSuccess) e = hipMalloc(&lbuf, (size_t)want * sizeof(uint64_t));
+        if (e != hipSuccess) {
+            if (buf) (void)hipFree(buf);
+            return e == hipErrorOutOfMemory ? GPFC_ENOMEM : device_error(e, "hipMalloc");
+        }
         if (p->rec) {
             (void)hipDeviceSynchronize();
             (void)hipFree(p->rec);
+            (void)hipFree(p->lo);
         }
         p->rec = buf;
+        p->lo = lbuf;
         p->cap = want;
     }
     e = gpfc::launch_curve_stats(t, flux, n, p->info, s);
     if (e != hipSuccess) return device_error(e, "k_curve_stats launch");
-    e = gpfc::launch_pack(t, flux, n, p->info, p->rec, s);
+    e = gpfc::launch_pack(t, flux, n, p->info, p->rec, p->lo, s);
     if (e != hipSuccess) return device_error(e, "k_pack launch");
     p->n = n;
     return GPFC_OK;
@@ -140,7 +168,79 @@ int32_t prepare_curve(gpfc_plan* p, const double* t, const float* flux, int64_t 
 int32_t check_prepared(const gpfc_plan* p, const void* periods, int64_t k, int32_t nbins) {
     if (!p || p->n < 0 || k < 0 || (k > 0 && !periods) || nbins < 1) return GPFC_EINVAL;
     if (!pow2_in_range(nbins)) return GPFC_ENOTSUP;
-    if ((k + 63) / 64 > 0x7fffffffLL) return GPFC_ERANGE;
+    if (k > 0x7fffffffLL) return GPFC_ERANGE;
+    return GPFC_OK;
+}
+
+// Device address of the prepared curve's sigma.
+const double* sigma_dev(const gpfc_plan* p) {
+    return (const double*)((const char*)p->info + offsetof(CurveInfo, sigma));
+}
+
+// Make the general path's workspace hold `bytes`.
+int32_t wide_reserve(gpfc_plan* p, size_t bytes) {
+    if (bytes <= p->w_cap) return GPFC_OK;
+    void* buf = nullptr;
+    hipError_t e = hipMalloc(&buf, bytes);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? GPFC_ENOMEM : device_error(e, "hipMalloc");
+    if (p->w_buf) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(p->w_buf);
+    }
+    p->w_buf = buf;
+    p->w_cap = bytes;
+    return GPFC_OK;
+}
+
+// General path of the prepared curve (any n, nbins up to 4096): per chunk of
+// periods, every part of fewer than 2^18 samples is folded into integer
+// histograms (high words, then low words of a two-word curve), which become
+// sums / counts / means, then box-SNR and normalised folds. Materialised
+// outputs (sums, counts, means) go to the caller's buffers when given,
+// otherwise to the workspace; snr != NULL scores, zfold != NULL normalises.
+int32_t wide_run(gpfc_plan* p, const double* periods, int64_t k, int32_t nbins, double* sums,
+                 int32_t* counts, double* means, float* snr, int32_t* start, int32_t* width,
+                 float* depth, uint16_t* zfold, hipStream_t s) {
+    if (k == 0) return GPFC_OK;
+    const bool own = sums == nullptr;   // materialise into the workspace
+    const int64_t per_period = (int64_t)nbins * (4 + 8 + 8 + (own ? 8 + 4 : 0));
+    int64_t kc = std::max<int64_t>(64, p->w_limit / per_period) / 64 * 64;
+    kc = std::min<int64_t>(kc, (k + 63) / 64 * 64);
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t b_cnt = al((size_t)kc * nbins * 4), b_s = al((size_t)kc * nbins * 8);
+    const size_t total = b_cnt + 2 * b_s + (own ? b_s + b_cnt : 0);
+    int32_t rc = wide_reserve(p, total);
+    if (rc != GPFC_OK) return rc;
+    char* base = (char*)p->w_buf;
+    uint32_t* cnt = (uint32_t*)base;
+    int64_t* shi = (int64_t*)(base + b_cnt);
+    int64_t* slo = (int64_t*)(base + b_cnt + b_s);
+    double* wsums = own ? (double*)(base + b_cnt + 2 * b_s) : nullptr;
+    int32_t* wcounts = own ? (int32_t*)(base + b_cnt + 3 * b_s) : nullptr;
+    const int64_t recs = gpfc::prepared_len(p->n);
+    const Widths W = plan_widths(p, nbins);
+    for (int64_t c0 = 0; c0 < k; c0 += kc) {
+        const int64_t kn = std::min(kc, k - c0);
+        const double* per = periods + c0;
+        hipError_t e = hipSuccess;
+        for (int64_t r0 = 0; r0 < recs && e == hipSuccess; r0 += gpfc::kPartSamples) {
+            const int64_t r1 = std::min(recs, r0 + gpfc::kPartSamples);
+            for (int use_lo = 0; use_lo < 2 && e == hipSuccess; ++use_lo)
+                e = gpfc::launch_fold_wide(p->rec, p->lo, r0, r1, per, kn, nbins, p->info, use_lo,
+                                           r0 == 0, cnt, shi, slo, s);
+        }
+        if (e != hipSuccess) return device_error(e, "k_fold_wide launch");
+        double* os = own ? wsums : sums + c0 * nbins;
+        int32_t* oc = own ? wcounts : counts + c0 * nbins;
+        double* om = (own || !means) ? nullptr : means + c0 * nbins;
+        e = gpfc::launch_wide_finish(cnt, shi, slo, per, kn, nbins, p->info, os, oc, om, s);
+        if (e == hipSuccess && snr)
+            e = gpfc::launch_score_wide(os, oc, kn, nbins, 0.0, sigma_dev(p), W, snr + c0,
+                                        start + c0, width + c0, depth + c0, s);
+        if (e == hipSuccess && zfold)
+            e = gpfc::launch_zfold_rows(os, oc, kn, nbins, zfold + c0 * nbins, s);
+        if (e != hipSuccess) return device_error(e, "general path launch");
+    }
     return GPFC_OK;
 }
 
@@ -154,8 +254,8 @@ const char* gpfc_strerror(int32_t code) {
     switch (code) {
         case GPFC_OK: return "ok";
         case GPFC_EINVAL: return "invalid argument";
-        case GPFC_ENOTSUP: return "nbins must be a power of two in [1, 256]";
-        case GPFC_ERANGE: return "size out of range (n > 262143 samples or too many periods)";
+        case GPFC_ENOTSUP: return "nbins not supported (a power of two in [1, 4096]; [1, 256] or [16, 256] for some calls)";
+        case GPFC_ERANGE: return "size out of range (too many samples or periods for the call)";
         case GPFC_ENOMEM: return "device memory allocation failed";
         case GPFC_EDEVICE: return "HIP device error";
         case GPFC_EIO: return "network file could not be written or read, or is not a network file";
@@ -183,11 +283,12 @@ int32_t gpfc_plan_create(gpfc_plan** out, int32_t device) {
     for (char* c = p->device_name; *c; ++c)
         if (*c == ' ' || *c == ':') *c = '_';
     e = hipSetDevice(device);
-    const size_t gh_bytes = (size_t)p->n_cu * gpfc::kFineBins * 64 * sizeof(unsigned long long);
+    // two 32-period halves per tile (a two-word curve merges them separately)
+    const size_t gh_bytes = (size_t)2 * p->n_cu * gpfc::kFineBins * 64 * sizeof(unsigned long long);
     if (e == hipSuccess) e = hipMalloc(&p->split_gh, gh_bytes);
-    if (e == hipSuccess) e = hipMalloc(&p->split_arrivals, sizeof(int32_t) * p->n_cu);
+    if (e == hipSuccess) e = hipMalloc(&p->split_arrivals, sizeof(int32_t) * 2 * p->n_cu);
     if (e == hipSuccess) e = hipMemset(p->split_gh, 0, gh_bytes);
-    if (e == hipSuccess) e = hipMemset(p->split_arrivals, 0, sizeof(int32_t) * p->n_cu);
+    if (e == hipSuccess) e = hipMemset(p->split_arrivals, 0, sizeof(int32_t) * 2 * p->n_cu);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         if (p->split_gh) (void)hipFree(p->split_gh);
@@ -199,12 +300,38 @@ int32_t gpfc_plan_create(gpfc_plan** out, int32_t device) {
     return GPFC_OK;
 }
 
+int32_t gpfc_plan_create_opts(gpfc_plan** out, const gpfc_plan_opts* o) {
+    if (!out) return GPFC_EINVAL;
+    *out = nullptr;
+    if (!o || o->nw < 0 || o->nw > GPFC_MAX_WIDTHS || o->split < 0 || o->split > GPFC_MAX_SPLIT ||
+        o->workspace_bytes < 0)
+        return GPFC_EINVAL;
+    if (o->tune_cache && strlen(o->tune_cache) >= sizeof(((gpfc_plan*)nullptr)->tune_cache))
+        return GPFC_EINVAL;
+    for (int i = 0; i < o->nw; ++i) {
+        if (o->widths[i] < 1 || o->widths[i] >= GPFC_MAX_NBINS) return GPFC_EINVAL;
+        if (i > 0 && o->widths[i] <= o->widths[i - 1]) return GPFC_EINVAL;
+    }
+    gpfc_plan* p = nullptr;
+    const int32_t rc = gpfc_plan_create(&p, o->device);
+    if (rc != GPFC_OK) return rc;
+    for (int i = 0; i < o->nw; ++i) p->widths[i] = o->widths[i];
+    p->nw = o->nw;
+    p->split = o->split;
+    if (o->tune_cache) snprintf(p->tune_cache, sizeof(p->tune_cache), "%s", o->tune_cache);
+    if (o->workspace_bytes > 0) p->w_limit = o->workspace_bytes;
+    *out = p;
+    return GPFC_OK;
+}
+
 int32_t gpfc_plan_destroy(gpfc_plan* p) {
     if (!p) return GPFC_OK;
     (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
     if (p->rec) (void)hipFree(p->rec);
+    if (p->lo) (void)hipFree(p->lo);
     if (p->info) (void)hipFree(p->info);
+    if (p->w_buf) (void)hipFree(p->w_buf);
     if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->b_dev) (void)hipFree(p->b_dev);
@@ -246,6 +373,12 @@ int32_t gpfc_curve_stats(gpfc_plan* p, const double* t, const float* flux, int64
     out->n = ci.n;
     out->exact = ci.exact;
     out->finite = ci.finite;
+    out->words = ci.words;
+    if (!ci.finite) {
+        int32_t fault = 0;
+        (void)gpfc::take_input_fault(&fault);   // reported here, not again at gpfc_sync
+        return GPFC_EINVAL;
+    }
     return GPFC_OK;
 }
 
@@ -262,7 +395,10 @@ int32_t gpfc_fold_prepared(gpfc_plan* p, const double* periods, int64_t k, int32
     if (k > 0 && (!sums || !counts)) return GPFC_EINVAL;
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return device_error(e, "hipSetDevice");
-    e = gpfc::launch_fold(p->rec, p->n, periods, k, nbins, p->info, sums, counts, means,
+    if (!fused_shape(p->n, nbins))
+        return wide_run(p, periods, k, nbins, sums, counts, means, nullptr, nullptr, nullptr,
+                        nullptr, nullptr, (hipStream_t)stream);
+    e = gpfc::launch_fold(p->rec, p->lo, p->n, periods, k, nbins, p->info, sums, counts, means,
                           (hipStream_t)stream);
     if (e != hipSuccess) return device_error(e, "k_fold launch");
     return GPFC_OK;
@@ -296,11 +432,24 @@ static hipError_t enqueue_fold_score(gpfc_plan* p, int64_t n, const double* peri
                                      int32_t nbins, float* snr, int32_t* start, int32_t* width,
                                      float* depth, uint16_t* zfold, int32_t split, hipStream_t s) {
     if (split <= 1)
-        return gpfc::launch_fold_score(p->rec, n, periods, k, nbins, p->info, plan_widths(p, nbins),
-                                       snr, start, width, depth, zfold, s);
-    return gpfc::launch_fold_score_split(p->rec, n, periods, k, nbins, p->info, plan_widths(p, nbins),
-                                         split, p->split_gh, p->split_arrivals, snr, start, width,
-                                         depth, zfold, s);
+        return gpfc::launch_fold_score(p->rec, p->lo, n, periods, k, nbins, p->info,
+                                       plan_widths(p, nbins), snr, start, width, depth, zfold, s);
+    return gpfc::launch_fold_score_split(p->rec, p->lo, n, periods, k, nbins, p->info,
+                                         plan_widths(p, nbins), split, p->split_gh,
+                                         p->split_arrivals, snr, start, width, depth, zfold, s);
+}
+
+// Fold + score of the prepared curve: the fused kernels, or the general path
+// for shapes they do not take.
+static int32_t run_fold_score(gpfc_plan* p, const double* periods, int64_t k, int32_t nbins,
+                              float* snr, int32_t* start, int32_t* width, float* depth,
+                              uint16_t* zfold, hipStream_t s) {
+    if (!fused_shape(p->n, nbins) || !fused_widths(p, nbins))
+        return wide_run(p, periods, k, nbins, nullptr, nullptr, nullptr, snr, start, width, depth,
+                        zfold, s);
+    const hipError_t e = enqueue_fold_score(p, p->n, periods, k, nbins, snr, start, width, depth,
+                                            zfold, resolve_split(p, p->n, k, nbins), s);
+    return e == hipSuccess ? GPFC_OK : device_error(e, "k_fold_score launch");
 }
 
 int32_t gpfc_fold_score_prepared(gpfc_plan* p, const double* periods, int64_t k, int32_t nbins,
@@ -309,13 +458,11 @@ int32_t gpfc_fold_score_prepared(gpfc_plan* p, const double* periods, int64_t k,
     int32_t rc = check_prepared(p, periods, k, nbins);
     if (rc != GPFC_OK) return rc;
     if (k > 0 && (!snr || !start || !width || !depth)) return GPFC_EINVAL;
-    if (zfold && nbins < 16) return GPFC_ENOTSUP;
+    if (zfold && (nbins < 16 || nbins > gpfc::kFineBins)) return GPFC_ENOTSUP;
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return device_error(e, "hipSetDevice");
-    e = enqueue_fold_score(p, p->n, periods, k, nbins, snr, start, width, depth, zfold,
-                           resolve_split(p, p->n, k, nbins), (hipStream_t)stream);
-    if (e != hipSuccess) return device_error(e, "k_fold_score launch");
-    return GPFC_OK;
+    return run_fold_score(p, periods, k, nbins, snr, start, width, depth, zfold,
+                          (hipStream_t)stream);
 }
 
 // Cache lines: "<device> <n> <k> <nbins> <split>".
@@ -346,7 +493,10 @@ int32_t gpfc_autotune(gpfc_plan* p, const double* periods, int64_t k, int32_t nb
     const int64_t tiles = (k + 63) / 64;
     int32_t best = 1;
     float best_ms = -1.0f;
-    if (cache_lookup(cache_path, p->device_name, p->n, k, nbins, &best)) {
+    if (!cache_path && p->tune_cache[0]) cache_path = p->tune_cache;
+    if (!fused_shape(p->n, nbins) || !fused_widths(p, nbins)) {
+        // the general path has no sample split to tune
+    } else if (cache_lookup(cache_path, p->device_name, p->n, k, nbins, &best)) {
         // known shape: no timing
     } else if (tiles >= 1 && tiles <= p->n_cu) {
         hipStream_t s = (hipStream_t)stream;
@@ -405,11 +555,12 @@ int32_t gpfc_fold_f32_prepared(gpfc_plan* p, const double* periods, int64_t k, i
                                void* stream) {
     int32_t rc = check_prepared(p, periods, k, nbins);
     if (rc != GPFC_OK) return rc;
+    if (nbins > gpfc::kFineBins) return GPFC_ENOTSUP;
     if (k > 0 && (!sums || !counts)) return GPFC_EINVAL;
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return device_error(e, "hipSetDevice");
-    e = gpfc::launch_fold_f32(p->rec, p->n, periods, k, nbins, compensated, p->info, sums, counts,
-                              means, (hipStream_t)stream);
+    e = gpfc::launch_fold_f32(p->rec, p->lo, p->n, periods, k, nbins, compensated, p->info, sums,
+                              counts, means, (hipStream_t)stream);
     if (e != hipSuccess) return device_error(e, "k_fold_f32 launch");
     return GPFC_OK;
 }
@@ -423,7 +574,11 @@ int32_t gpfc_fold(gpfc_plan* p, const double* t, const float* flux, int64_t n,
     hipStream_t s = (hipStream_t)stream;
     rc = prepare_curve(p, t, flux, n, s);
     if (rc != GPFC_OK) return rc;
-    hipError_t e = gpfc::launch_fold(p->rec, n, periods, k, nbins, p->info, sums, counts, means, s);
+    if (!fused_shape(n, nbins))
+        return wide_run(p, periods, k, nbins, sums, counts, means, nullptr, nullptr, nullptr,
+                        nullptr, nullptr, s);
+    hipError_t e = gpfc::launch_fold(p->rec, p->lo, n, periods, k, nbins, p->info, sums, counts,
+                                     means, s);
     if (e != hipSuccess) return device_error(e, "k_fold launch");
     return GPFC_OK;
 }
@@ -431,12 +586,12 @@ int32_t gpfc_fold(gpfc_plan* p, const double* t, const float* flux, int64_t n,
 int32_t gpfc_fold_eqcount_prepared(gpfc_plan* p, const double* periods, int64_t k, int32_t nbins,
                                    double* means, uint16_t* zfold, void* stream) {
     if (!p || p->n < 0 || k < 0 || (k > 0 && !periods)) return GPFC_EINVAL;
-    if (nbins < 1 || nbins > GPFC_MAX_NBINS) return GPFC_ENOTSUP;
+    if (nbins < 1 || nbins > gpfc::kFineBins) return GPFC_ENOTSUP;
     if (k > 0 && !means && !zfold) return GPFC_EINVAL;
-    if ((k + 3) / 4 > 0x7fffffffLL) return GPFC_ERANGE;
+    if ((k + 3) / 4 > 0x7fffffffLL || p->n > GPFC_MAX_PACKED) return GPFC_ERANGE;
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return device_error(e, "hipSetDevice");
-    e = gpfc::launch_fold_eqcount(p->rec, p->n, periods, k, nbins, p->info, means, zfold,
+    e = gpfc::launch_fold_eqcount(p->rec, p->lo, p->n, periods, k, nbins, p->info, means, zfold,
                                   (hipStream_t)stream);
     if (e != hipSuccess) return device_error(e, "k_fold_eqcount launch");
     return GPFC_OK;
@@ -457,10 +612,7 @@ int32_t gpfc_fold_score(gpfc_plan* p, const double* t, const float* flux, int64_
     hipStream_t s = (hipStream_t)stream;
     rc = prepare_curve(p, t, flux, n, s);
     if (rc != GPFC_OK) return rc;
-    hipError_t e = enqueue_fold_score(p, n, periods, k, nbins, snr, start, width, depth, nullptr,
-                                      resolve_split(p, n, k, nbins), s);
-    if (e != hipSuccess) return device_error(e, "k_fold_score launch");
-    return GPFC_OK;
+    return run_fold_score(p, periods, k, nbins, snr, start, width, depth, nullptr, s);
 }
 
 int32_t gpfc_score(gpfc_plan* p, const double* sums, const int32_t* counts, int64_t k,
@@ -469,11 +621,15 @@ int32_t gpfc_score(gpfc_plan* p, const double* sums, const int32_t* counts, int6
     if (!p || k < 0 || nbins < 1) return GPFC_EINVAL;
     if (!pow2_in_range(nbins)) return GPFC_ENOTSUP;
     if (k > 0 && (!sums || !counts || !snr || !start || !width || !depth)) return GPFC_EINVAL;
-    if ((k + 63) / 64 > 0x7fffffffLL) return GPFC_ERANGE;
+    if (k > 0x7fffffffLL) return GPFC_ERANGE;
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return device_error(e, "hipSetDevice");
-    e = gpfc::launch_score(sums, counts, k, nbins, sigma, plan_widths(p, nbins), snr, start, width,
-                           depth, (hipStream_t)stream);
+    if (nbins > gpfc::kFineBins || !fused_widths(p, nbins))
+        e = gpfc::launch_score_wide(sums, counts, k, nbins, sigma, nullptr, plan_widths(p, nbins),
+                                    snr, start, width, depth, (hipStream_t)stream);
+    else
+        e = gpfc::launch_score(sums, counts, k, nbins, sigma, plan_widths(p, nbins), snr, start,
+                               width, depth, (hipStream_t)stream);
     if (e != hipSuccess) return device_error(e, "k_score launch");
     return GPFC_OK;
 }
@@ -513,7 +669,8 @@ static int32_t batch_upload(gpfc_plan* p, const int64_t* soff, int32_t n_curves,
     const size_t sz_ctr = 256;
     const size_t sz_inf = al(sizeof(CurveInfo) * (n_curves > 0 ? n_curves : 1));
     const size_t sz_rec = al(sizeof(gpfc::Rec) * (recs > 0 ? recs : 1));
-    const size_t total = 2 * sz_off + sz_cur + sz_it + sz_ctr + sz_inf + sz_rec + al(extra);
+    const size_t sz_lo = al(sizeof(uint64_t) * (recs > 0 ? recs : 1));
+    const size_t total = 2 * sz_off + sz_cur + sz_it + sz_ctr + sz_inf + sz_rec + sz_lo + al(extra);
     if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
     if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
     if (p->b_dev) {
@@ -539,6 +696,7 @@ static int32_t batch_upload(gpfc_plan* p, const int64_t* soff, int32_t n_curves,
     p->b_counter = (int32_t*)base; base += sz_ctr;
     p->b_info = (CurveInfo*)base; base += sz_inf;
     p->b_rec = (gpfc::Rec*)base; base += sz_rec;
+    p->b_lo = (uint64_t*)base; base += sz_lo;
     *extra_ptr = extra ? (void*)base : nullptr;
     e = hipMemcpy(p->b_soff, soff, sizeof(int64_t) * (n_curves + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->b_roff, roff.data(), sizeof(int64_t) * (n_curves + 1), hipMemcpyHostToDevice);
@@ -579,7 +737,7 @@ int32_t gpfc_batch_setup(gpfc_plan* p, const int64_t* soff, const int64_t* poff,
         const int64_t n = soff[c + 1] - soff[c];
         const int64_t k = poff[c + 1] - poff[c];
         if (n < 0 || k < 0) return GPFC_EINVAL;
-        if (n > GPFC_MAX_SAMPLES) return GPFC_ERANGE;
+        if (n > GPFC_MAX_PACKED) return GPFC_ERANGE;
         curves[c] = gpfc::BatchCurve{recs, gpfc::slice_len(n), poff[c], k, poff[c], poff[c]};
         recs += gpfc::prepared_len(n);
         roff[c + 1] = recs;
@@ -609,7 +767,7 @@ int32_t gpfc_survey_setup(gpfc_plan* p, const int64_t* soff, int32_t n_curves, i
     for (int32_t c = 0; c < n_curves; ++c) {
         const int64_t n = soff[c + 1] - soff[c];
         if (n < 0) return GPFC_EINVAL;
-        if (n > GPFC_MAX_SAMPLES) return GPFC_ERANGE;
+        if (n > GPFC_MAX_PACKED) return GPFC_ERANGE;
         const int64_t first = c - c % per_chunk;   // first curve of this curve's chunk
         curves[c] = gpfc::BatchCurve{recs, gpfc::slice_len(n), 0, k, (int64_t)c * k, (c - first) * k};
         recs += gpfc::prepared_len(n);
@@ -627,7 +785,7 @@ int32_t gpfc_survey_setup(gpfc_plan* p, const int64_t* soff, int32_t n_curves, i
     }
     void* z = nullptr;
     int32_t rc = batch_upload(p, soff, n_curves, roff, curves, it, (int64_t)n_curves * k,
-                              (size_t)zfolds * GPFC_MAX_NBINS * sizeof(uint16_t), &z);
+                              (size_t)zfolds * gpfc::kFineBins * sizeof(uint16_t), &z);
     if (rc != GPFC_OK) return rc;
     p->b_survey = true;
     p->s_k = k;
@@ -641,9 +799,9 @@ static int32_t batch_enqueue(gpfc_plan* p, const double* t, const float* flux, c
                              int32_t nbins, float* snr, int32_t* start, int32_t* width, float* depth,
                              uint16_t* zfold, hipStream_t s) {
     hipError_t e = gpfc::launch_batch_prepare(t, flux, p->b_soff, p->b_roff, p->b_curves,
-                                              p->b_max_records, p->b_info, p->b_rec, s);
+                                              p->b_max_records, p->b_info, p->b_rec, p->b_lo, s);
     if (e != hipSuccess) return device_error(e, "batch prepare launch");
-    e = gpfc::launch_batch_fold_score(p->b_rec, p->b_curve, p->b_item, p->b_items, p->b_counter,
+    e = gpfc::launch_batch_fold_score(p->b_rec, p->b_lo, p->b_curve, p->b_item, p->b_items, p->b_counter,
                                       p->b_info, periods, nbins, plan_widths(p, nbins), p->n_cu, snr,
                                       start, width, depth, zfold, s);
     if (e != hipSuccess) return device_error(e, "batch fold_score launch");
@@ -657,8 +815,9 @@ static int32_t check_batch(const gpfc_plan* p, const void* t, const void* flux, 
     if (p->b_samples > 0 && (!t || !flux)) return GPFC_EINVAL;
     if (p->b_periods > 0 && (!periods || !snr || !start || !width || !depth)) return GPFC_EINVAL;
     if (nbins < 1) return GPFC_EINVAL;
-    if (!pow2_in_range(nbins)) return GPFC_ENOTSUP;
+    if (!pow2_in_range(nbins) || nbins > gpfc::kFineBins) return GPFC_ENOTSUP;
     if (zfold && nbins < 16) return GPFC_ENOTSUP;
+    if (!fused_widths(p, nbins)) return GPFC_ENOTSUP;
     return GPFC_OK;
 }
 
@@ -718,9 +877,10 @@ static int32_t check_survey(const gpfc_plan* p, const gpfc_cnn* cnn, const doubl
     if (p->b_periods > 0 && (!periods || !o->snr || !o->start || !o->width || !o->depth))
         return GPFC_EINVAL;
     if (nbins < 1) return GPFC_EINVAL;
-    if (!pow2_in_range(nbins)) return GPFC_ENOTSUP;
+    if (!pow2_in_range(nbins) || nbins > gpfc::kFineBins) return GPFC_ENOTSUP;
+    if (!fused_widths(p, nbins)) return GPFC_ENOTSUP;
     const bool net = o->logits != nullptr;
-    if (net && (!cnn || nbins != GPFC_MAX_NBINS || p->s_zfolds == 0)) return GPFC_EINVAL;
+    if (net && (!cnn || nbins != gpfc::kFineBins || p->s_zfolds == 0)) return GPFC_EINVAL;
     if (o->top < 0 || o->top > GPFC_MAX_TOP) return GPFC_EINVAL;
     if (o->top > 0) {
         if (!o->box_val || !o->box_idx) return GPFC_EINVAL;
@@ -735,12 +895,12 @@ static int32_t survey_enqueue(gpfc_plan* p, gpfc_cnn* cnn, const double* t, cons
                               const double* periods, int32_t nbins, const gpfc_survey_out& o,
                               hipStream_t s) {
     hipError_t e = gpfc::launch_batch_prepare(t, flux, p->b_soff, p->b_roff, p->b_curves,
-                                              p->b_max_records, p->b_info, p->b_rec, s);
+                                              p->b_max_records, p->b_info, p->b_rec, p->b_lo, s);
     if (e != hipSuccess) return device_error(e, "survey prepare launch");
     const bool net = o.logits != nullptr;
     const int64_t K = p->s_k;
     for (const SurveyChunk& ch : p->s_chunks) {
-        e = gpfc::launch_batch_fold_score(p->b_rec, p->b_curve, p->b_item + ch.i0, ch.i1 - ch.i0,
+        e = gpfc::launch_batch_fold_score(p->b_rec, p->b_lo, p->b_curve, p->b_item + ch.i0, ch.i1 - ch.i0,
                                           p->b_counter, p->b_info, periods, nbins,
                                           plan_widths(p, nbins), p->n_cu, o.snr, o.start, o.width,
                                           o.depth, net ? p->s_zbuf : nullptr, s);
@@ -750,7 +910,7 @@ static int32_t survey_enqueue(gpfc_plan* p, gpfc_cnn* cnn, const double* t, cons
         const int64_t mb = gpfc::cnn_max_batch(cnn);
         for (int64_t f0 = 0; f0 < folds; f0 += mb) {
             const int64_t B = std::min<int64_t>(mb, folds - f0);
-            const uint16_t* x = p->s_zbuf + f0 * GPFC_MAX_NBINS;
+            const uint16_t* x = p->s_zbuf + f0 * gpfc::kFineBins;
             float* lg = o.logits + (int64_t)ch.c0 * K + f0;
             const int32_t rc = o.cnn_fp8 ? gpfc_cnn_forward_fp8(cnn, x, 0, B, lg, s)
                                          : gpfc_cnn_forward(cnn, x, 0, B, lg, s);
@@ -851,6 +1011,7 @@ int32_t gpfc_batch_curve_stats(gpfc_plan* p, gpfc_curve* out, void* stream) {
         out[c].n = ci[c].n;
         out[c].exact = ci[c].exact;
         out[c].finite = ci[c].finite;
+        out[c].words = ci[c].words;
     }
     return GPFC_OK;
 }
@@ -858,7 +1019,19 @@ int32_t gpfc_batch_curve_stats(gpfc_plan* p, gpfc_curve* out, void* stream) {
 int32_t gpfc_sync(void* stream) {
     hipError_t e = hipStreamSynchronize((hipStream_t)stream);
     if (e != hipSuccess) return device_error(e, "hipStreamSynchronize");
-    return GPFC_OK;
+    int dev = -1, cur = -1;
+    if (stream) {
+        e = hipStreamGetDevice((hipStream_t)stream, &dev);
+        if (e != hipSuccess) return device_error(e, "hipStreamGetDevice");
+        e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+        if (e != hipSuccess) return device_error(e, "hipSetDevice");
+    }
+    int32_t fault = 0;
+    e = gpfc::take_input_fault(&fault);
+    if (stream && cur >= 0 && cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return device_error(e, "input check");
+    return fault ? GPFC_EINVAL : GPFC_OK;
 }
 
 }  // extern "C"

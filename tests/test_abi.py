@@ -53,11 +53,14 @@ def test_null_plan_and_bad_arguments_rejected_on_host():
     assert lib.gpfc_fold(p, p, p, 5, None, 3, 64, None, None, None, None) == _lib.EINVAL
     assert lib.gpfc_fold(p, p, p, 5, p, 3, 0, p, p, None, None) == _lib.EINVAL
     assert lib.gpfc_fold(p, p, p, 5, p, 3, 48, p, p, None, None) == _lib.ENOTSUP
-    assert lib.gpfc_fold(p, p, p, 5, p, 3, 512, p, p, None, None) == _lib.ENOTSUP
+    assert lib.gpfc_fold(p, p, p, 5, p, 3, 8192, p, p, None, None) == _lib.ENOTSUP
+    assert lib.gpfc_fold(p, p, p, 5, p, 3, 6144, p, p, None, None) == _lib.ENOTSUP
     assert lib.gpfc_fold(p, p, p, _lib.MAX_SAMPLES + 1, p, 3, 64, p, p, None, None) == _lib.ERANGE
+    assert lib.gpfc_fold(p, p, p, 5, p, 2**31, 64, p, p, None, None) == _lib.ERANGE
     assert lib.gpfc_fold(p, p, p, 5, p, 3, 64, None, p, None, None) == _lib.EINVAL
     assert lib.gpfc_fold_score(p, p, p, 5, p, 3, 64, p, None, p, p, None) == _lib.EINVAL
     assert lib.gpfc_score(p, p, p, 3, 100, 1.0, p, p, p, p, None) == _lib.ENOTSUP
+    assert lib.gpfc_score(p, p, p, 3, 8192, 1.0, p, p, p, p, None) == _lib.ENOTSUP
     assert lib.gpfc_score(p, p, p, -1, 64, 1.0, p, p, p, p, None) == _lib.EINVAL
 
 
@@ -68,8 +71,36 @@ def test_width_validation():
     assert lib.gpfc_plan_set_widths(p, arr, 4) == _lib.EINVAL        # not strictly ascending
     arr = (ctypes.c_int32 * 2)(0, 3)
     assert lib.gpfc_plan_set_widths(p, arr, 2) == _lib.EINVAL        # w < 1
-    arr = (ctypes.c_int32 * 17)(*range(1, 18))
-    assert lib.gpfc_plan_set_widths(p, arr, 17) == _lib.EINVAL       # too many
+    arr = (ctypes.c_int32 * 25)(*range(1, 26))
+    assert lib.gpfc_plan_set_widths(p, arr, 25) == _lib.EINVAL       # too many
+    arr = (ctypes.c_int32 * 2)(3, 4096)
+    assert lib.gpfc_plan_set_widths(p, arr, 2) == _lib.EINVAL        # not below the largest nbins
+
+
+def test_plan_options_validated_on_host():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.gpfc_plan_create_opts(None, None) == _lib.EINVAL
+    assert lib.gpfc_plan_create_opts(ctypes.byref(h), None) == _lib.EINVAL
+    o = _lib.PlanOpts(device=0, nw=2, split=0)
+    o.widths[0], o.widths[1] = 4, 4                                    # not ascending
+    assert lib.gpfc_plan_create_opts(ctypes.byref(h), ctypes.byref(o)) == _lib.EINVAL
+    o = _lib.PlanOpts(device=0, nw=0, split=65)                         # split too large
+    assert lib.gpfc_plan_create_opts(ctypes.byref(h), ctypes.byref(o)) == _lib.EINVAL
+    o = _lib.PlanOpts(device=0, nw=0, split=0, workspace_bytes=-1)
+    assert lib.gpfc_plan_create_opts(ctypes.byref(h), ctypes.byref(o)) == _lib.EINVAL
+    o = _lib.PlanOpts(device=0, nw=_lib.MAX_WIDTHS + 1)
+    assert lib.gpfc_plan_create_opts(ctypes.byref(h), ctypes.byref(o)) == _lib.EINVAL
+    assert h.value is None
+
+
+def test_batch_curves_longer_than_one_packed_pass_rejected():
+    lib = _lib.load()
+    p = ctypes.c_void_p(1)
+    so = (ctypes.c_int64 * 3)(0, 100, 100 + _lib.MAX_PACKED + 1)
+    po = (ctypes.c_int64 * 3)(0, 10, 20)
+    assert lib.gpfc_batch_setup(p, so, po, 2) == _lib.ERANGE
+    assert lib.gpfc_survey_setup(p, so, 2, 10, 0) == _lib.ERANGE
 
 
 def test_product_path_has_no_cpu_fallback():
