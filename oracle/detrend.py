@@ -134,7 +134,7 @@ def detrend(t, flux, transit=None, spacings=SPACINGS, cadence=CADENCE, edge=EDGE
         out[s0:s1] = fs / cont
         k = ~clip
         k[:edge] = False
-        k[-edge:] = False
+        k[k.size - edge:] = False      # (k[-edge:] would clear every point when edge = 0)
         keep[s0:s1] = k
         recs.append((s0, s1, h))
     return out, keep, recs
