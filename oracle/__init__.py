@@ -20,7 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gpfc_oracle.c")
-_SRCS = [_SRC, os.path.join(_HERE, "cnn_oracle.c")]
+_SRCS = [_SRC, os.path.join(_HERE, "cnn_oracle.c"), os.path.join(_HERE, "pnet_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -86,6 +86,18 @@ def _load():
     lib.oracle_adam.restype = None
     lib.oracle_grid_size.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
     lib.oracle_grid_size.restype = ctypes.c_double
+    cfgp = ctypes.POINTER(PnetCfg)
+    lib.oracle_pnet_nparams.argtypes = [cfgp]
+    lib.oracle_pnet_nparams.restype = i64
+    lib.oracle_pnet_conv2d_circ.argtypes = [dp, dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_int, dp]
+    lib.oracle_pnet_conv2d_circ.restype = None
+    lib.oracle_pnet_forward.argtypes = [cfgp, dp, dp, i64, dp, dp]
+    lib.oracle_pnet_forward.restype = None
+    lib.oracle_pnet_features.argtypes = [cfgp, dp, dp, dp, dp, dp]
+    lib.oracle_pnet_features.restype = None
+    lib.oracle_pnet_loss_grad.argtypes = [cfgp, dp, dp, dp, i64, dp, dp]
+    lib.oracle_pnet_loss_grad.restype = ctypes.c_double
     _lib = lib
     return lib
 
@@ -341,3 +353,90 @@ def adam(p, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
     lib.oracle_adam(_p(p, ctypes.c_double), _p(g, ctypes.c_double), _p(m, ctypes.c_double),
                     _p(v, ctypes.c_double), p.size, int(step), float(lr), float(b1), float(b2),
                     float(eps))
+
+
+# ---------------------------------------------------------------- the paper's network (Sec. 2.5)
+
+class PnetCfg(ctypes.Structure):
+    """Sizes of the paper's network (pnet_oracle.c): image side S, filters
+    F1, F2 (= S*S), F3, F4, kernel sides K1, K2, hidden units H."""
+    _fields_ = [(n, ctypes.c_int32) for n in ("S", "F1", "F2", "F3", "F4", "K1", "K2", "H")]
+
+
+PNET_FULL = dict(S=16, F1=128, F2=256, F3=128, F4=256, K1=3, K2=5, H=128)
+
+
+def _cfg(cfg):
+    c = PnetCfg(**(cfg or PNET_FULL))
+    assert c.F2 == c.S * c.S, "F2 must equal S*S (the pooled values form an S x S image)"
+    return c
+
+
+def pnet_nparams(cfg=None) -> int:
+    c = _cfg(cfg)
+    return int(_load().oracle_pnet_nparams(ctypes.byref(c)))
+
+
+def pnet_conv2d_circ(x, w, b):
+    """Circular 2-D convolution (cross-correlation, wrap-around padding, same
+    size): x [Ci][S][S], w [Co][Ci][K][K], b [Co] -> [Co][S][S]."""
+    x, w, b = _f64(x), _f64(w), _f64(b)
+    ci, S, _ = x.shape
+    co, _, K, _ = w.shape
+    y = np.empty((co, S, S))
+    _load().oracle_pnet_conv2d_circ(_p(x, ctypes.c_double), _p(w, ctypes.c_double),
+                                    _p(b, ctypes.c_double), ci, co, K, S, _p(y, ctypes.c_double))
+    return y
+
+
+def pnet_forward(params, x, cfg=None, mask=None):
+    """Logits of the paper's network for inputs x [B][S*S]; mask [B][H] is
+    the dropout keep mask already scaled by 1/(1 - rate) (None: inference)."""
+    c = _cfg(cfg)
+    params, x = _f64(params), _f64(x)
+    B = x.shape[0]
+    out = np.empty(B)
+    m = None if mask is None else _f64(mask)
+    _load().oracle_pnet_forward(ctypes.byref(c), _p(params, ctypes.c_double), _p(x, ctypes.c_double), B,
+                                None if m is None else _p(m, ctypes.c_double), _p(out, ctypes.c_double))
+    return out
+
+
+def pnet_features(params, x, cfg=None):
+    """First and second global max-pool outputs and the hidden layer of one
+    input x [S*S]: (g1 [F2], g2 [F4], h [H])."""
+    c = _cfg(cfg)
+    params, x = _f64(params), _f64(x)
+    g1, g2, h = np.empty(c.F2), np.empty(c.F4), np.empty(c.H)
+    _load().oracle_pnet_features(ctypes.byref(c), _p(params, ctypes.c_double), _p(x, ctypes.c_double),
+                                 _p(g1, ctypes.c_double), _p(g2, ctypes.c_double), _p(h, ctypes.c_double))
+    return g1, g2, h
+
+
+def pnet_loss_grad(params, x, y, cfg=None, mask=None):
+    """(mean BCE-with-logits loss, gradient) of the paper's network."""
+    c = _cfg(cfg)
+    params, x, y = _f64(params), _f64(x), _f64(y)
+    g = np.empty(params.size)
+    m = None if mask is None else _f64(mask)
+    loss = _load().oracle_pnet_loss_grad(ctypes.byref(c), _p(params, ctypes.c_double),
+                                         _p(x, ctypes.c_double), _p(y, ctypes.c_double), x.shape[0],
+                                         None if m is None else _p(m, ctypes.c_double),
+                                         _p(g, ctypes.c_double))
+    return loss, g
+
+
+def pnet_split(params, cfg=None):
+    """The flat parameter vector as named arrays (views)."""
+    c = cfg or PNET_FULL
+    S, F1, F2, F3, F4, K1, K2, H = (c[k] for k in ("S", "F1", "F2", "F3", "F4", "K1", "K2", "H"))
+    shapes = [("w1", (F1, 1, K1, K1)), ("b1", (F1,)), ("w2", (F2, F1, K1, K1)), ("b2", (F2,)),
+              ("w3", (F3, 1, K2, K2)), ("b3", (F3,)), ("w4", (F4, F3, K2, K2)), ("b4", (F4,)),
+              ("w5", (H, F4)), ("b5", (H,)), ("w6", (H,)), ("b6", (1,))]
+    out, o = {}, 0
+    for name, shp in shapes:
+        n = int(np.prod(shp))
+        out[name] = params[o:o + n].reshape(shp)
+        o += n
+    assert o == params.size
+    return out
