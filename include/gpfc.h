@@ -552,6 +552,30 @@ int32_t gpfc_roof_probe(int32_t device, int32_t kind, double *rate_out, double *
                         void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code being captured into a
+ * HIP graph, tight serving loops, harnesses that forbid hipMalloc): the fused
+ * fold + score of gpfc_fold_score with no plan and no allocation. The curve
+ * statistics and the prepared curve go to a static device buffer the library
+ * owns, GPFC_NOALLOC_BYTES on each GPU it runs on, held until the process
+ * ends; the caller passes device inputs and outputs as for gpfc_fold_score.
+ * Runs on the current HIP device, asynchronously on `stream`, with the
+ * default box widths and one block per 64 periods. Results equal those of
+ * gpfc_fold_score with the default widths, bit for bit.
+ * Limits: n <= GPFC_NOALLOC_MAX_SAMPLES (GPFC_ERANGE beyond), nbins a power of
+ * two in [1, 256] (GPFC_ENOTSUP otherwise), k < 2^31; argument errors are
+ * returned before any HIP call. Every call on one GPU shares that GPU's
+ * buffer, which keeps the last call's contents (nothing in it needs to start
+ * at zero): calls that overlap on one GPU (two streams, or two host threads)
+ * race and give wrong results, so serialise them. Non-finite input is
+ * reported by the next gpfc_sync.
+ */
+#define GPFC_NOALLOC_MAX_SAMPLES 131072
+#define GPFC_NOALLOC_BYTES 3146496   /* 256 + (131072 + 16) x 24 bytes, rounded up to 256 */
+int32_t gpfc_fold_score_noalloc(const double *t, const float *flux, int64_t n,
+                                const double *periods, int64_t k, int32_t nbins, float *snr,
+                                int32_t *start, int32_t *width, float *depth, void *stream);
+
+/*
  * hipStreamSynchronize(stream); reports an asynchronous device error
  * (GPFC_EDEVICE), then GPFC_EINVAL if a curve statistics pass on the stream's
  * device has seen a non-finite t or flux since the last gpfc_sync or

@@ -126,6 +126,7 @@ def load():
         "gpfc_cnn_save": ([vp, ctypes.c_char_p, vp], i32),
         "gpfc_roof_probe": ([i32, i32, ctypes.POINTER(f64), ctypes.POINTER(f64), vp], i32),
         "gpfc_cnn_load": ([vp, ctypes.c_char_p, vp], i32),
+        "gpfc_fold_score_noalloc": ([vp, vp, i64, vp, i64, i32, vp, vp, vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -151,7 +152,7 @@ def exported_symbols():
             "gpfc_cnn_train_replay", "gpfc_topk", "gpfc_plan_set_split",
             "gpfc_autotune", "gpfc_fold_eqcount_prepared", "gpfc_periodogram_peaks", "gpfc_survey_setup", "gpfc_survey_run",
             "gpfc_survey_capture", "gpfc_cnn_train_step", "gpfc_cnn_save", "gpfc_cnn_load",
-            "gpfc_roof_probe"]
+            "gpfc_roof_probe", "gpfc_fold_score_noalloc"]
 
 
 ROOF_LDS_U64, ROOF_LDS_U32, ROOF_LDS_F32, ROOF_FP64_FMA, ROOF_HBM_COPY = 0, 1, 2, 3, 4
@@ -506,6 +507,23 @@ class Plan:
 
     def sync(self):
         _check(self.lib.gpfc_sync(_stream()), "gpfc_sync")
+
+
+def fold_score_noalloc(t, flux, periods, nbins: int, out):
+    """gpfc_fold_score_noalloc: fused fold + box-SNR on the current device with
+    no allocation; ``out`` = (snr f32, start i32, width i32, depth f32), each [k],
+    allocated by the caller."""
+    import torch
+    lib = load()
+    dev = t.device
+    _need(t, torch.float64, "t", dev)
+    _need(flux, torch.float32, "flux", dev)
+    _need(periods, torch.float64, "periods", dev)
+    snr, start, width, depth = out
+    _check(lib.gpfc_fold_score_noalloc(_ptr(t), _ptr(flux), t.numel(), _ptr(periods), periods.numel(),
+                                       nbins, _ptr(snr), _ptr(start), _ptr(width), _ptr(depth),
+                                       _stream()), "gpfc_fold_score_noalloc")
+    return snr, start, width, depth
 
 
 def topk(values, top: int = 1, gate=None, gate_min: float = 0.0):

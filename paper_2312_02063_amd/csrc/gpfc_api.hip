@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -241,6 +242,45 @@ int32_t wide_run(gpfc_plan* p, const double* periods, int64_t k, int32_t nbins, 
             e = gpfc::launch_zfold_rows(os, oc, kn, nbins, zfold + c0 * nbins, s);
         if (e != hipSuccess) return device_error(e, "general path launch");
     }
+    return GPFC_OK;
+}
+
+// Device buffer of gpfc_fold_score_noalloc: CurveInfo (padded to 256 bytes),
+// then the prepared records and low words of up to GPFC_NOALLOC_MAX_SAMPLES
+// samples (prepared_len pads a curve to whole 256-sample blocks plus 16).
+constexpr size_t kNoAllocInfoBytes = 256;
+constexpr int64_t kNoAllocRecs = (GPFC_NOALLOC_MAX_SAMPLES + 255) / 256 * 256 + 16;
+static_assert(sizeof(CurveInfo) <= kNoAllocInfoBytes, "CurveInfo must fit its slot");
+static_assert(kNoAllocInfoBytes + kNoAllocRecs * (sizeof(gpfc::Rec) + sizeof(uint64_t)) <=
+                  (size_t)GPFC_NOALLOC_BYTES,
+              "GPFC_NOALLOC_BYTES must hold the statistics and the records");
+
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+char* g_noalloc_ptr[kNoAllocDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[GPFC_NOALLOC_BYTES];
+
+namespace {
+
+// Device address of `scratch` on the current device, looked up once per device
+// (with that device current) and kept.
+int32_t noalloc_base(char** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_error(e, "hipGetDevice");
+    if (dev < 0 || dev >= kNoAllocDevices) return GPFC_EINVAL;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return device_error(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return device_error(hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        g_noalloc_ptr[dev] = static_cast<char*>(ptr);
+    }
+    *out = g_noalloc_ptr[dev];
     return GPFC_OK;
 }
 
@@ -1014,6 +1054,36 @@ int32_t gpfc_batch_curve_stats(gpfc_plan* p, gpfc_curve* out, void* stream) {
         out[c].words = ci[c].words;
     }
     return GPFC_OK;
+}
+
+// Allocation-free fold + score: the curve statistics, the prepared records
+// and their low words live in `scratch`, one copy per GPU at the address
+// hipGetSymbolAddress reports on that device (the array's name is only a host
+// stand-in and is never passed to a kernel). Layout: CurveInfo at 0, records
+// at 256, low words after the records.
+int32_t gpfc_fold_score_noalloc(const double* t, const float* flux, int64_t n,
+                                const double* periods, int64_t k, int32_t nbins, float* snr,
+                                int32_t* start, int32_t* width, float* depth, void* stream) {
+    if (n < 0 || k < 0 || nbins < 1) return GPFC_EINVAL;
+    if (n > 0 && (!t || !flux)) return GPFC_EINVAL;
+    if (k > 0 && (!periods || !snr || !start || !width || !depth)) return GPFC_EINVAL;
+    if (!pow2_in_range(nbins) || nbins > gpfc::kFineBins) return GPFC_ENOTSUP;
+    if (n > GPFC_NOALLOC_MAX_SAMPLES || k > 0x7fffffffLL) return GPFC_ERANGE;
+    if (gpfc::prepared_len(n) > kNoAllocRecs) return GPFC_ERANGE;
+    char* base = nullptr;
+    const int32_t rc = noalloc_base(&base);
+    if (rc != GPFC_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    CurveInfo* info = reinterpret_cast<CurveInfo*>(base);
+    gpfc::Rec* rec = reinterpret_cast<gpfc::Rec*>(base + kNoAllocInfoBytes);
+    uint64_t* lo = reinterpret_cast<uint64_t*>(base + kNoAllocInfoBytes + kNoAllocRecs * sizeof(gpfc::Rec));
+    hipError_t e = gpfc::launch_curve_stats(t, flux, n, info, s);
+    if (e != hipSuccess) return device_error(e, "k_curve_stats launch");
+    e = gpfc::launch_pack(t, flux, n, info, rec, lo, s);
+    if (e != hipSuccess) return device_error(e, "k_pack launch");
+    e = gpfc::launch_fold_score(rec, lo, n, periods, k, nbins, info, default_widths(nbins), snr,
+                                start, width, depth, nullptr, s);
+    return e == hipSuccess ? GPFC_OK : device_error(e, "k_fold_score launch");
 }
 
 int32_t gpfc_sync(void* stream) {

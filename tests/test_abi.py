@@ -130,3 +130,19 @@ def test_topk_and_survey_argument_checks():
     out = _lib.SurveyOut()
     assert lib.gpfc_survey_run(None, None, p, p, p, 256, ctypes.byref(out), None) == _lib.EINVAL
     assert lib.gpfc_survey_run(p, None, p, p, p, 256, None, None) == _lib.EINVAL
+
+
+def test_noalloc_arguments_rejected_on_host():
+    """gpfc_fold_score_noalloc checks its arguments before any HIP call: its
+    sample limit, the fused kernel's nbins range and missing pointers."""
+    lib = _lib.load()
+    p = ctypes.c_void_p(1)        # never dereferenced
+    f = lib.gpfc_fold_score_noalloc
+    assert f(p, p, -1, p, 3, 64, p, p, p, p, None) == _lib.EINVAL
+    assert f(None, p, 5, p, 3, 64, p, p, p, p, None) == _lib.EINVAL
+    assert f(p, p, 5, p, 3, 64, p, p, None, p, None) == _lib.EINVAL
+    assert f(p, p, 5, p, 3, 0, p, p, p, p, None) == _lib.EINVAL
+    assert f(p, p, 5, p, 3, 48, p, p, p, p, None) == _lib.ENOTSUP
+    assert f(p, p, 5, p, 3, 512, p, p, p, p, None) == _lib.ENOTSUP
+    assert f(p, p, 131073, p, 3, 64, p, p, p, p, None) == _lib.ERANGE
+    assert f(p, p, 5, p, 2**31, 64, p, p, p, p, None) == _lib.ERANGE
