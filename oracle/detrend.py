@@ -9,10 +9,12 @@ The paper's steps, in its order, with the readings its text leaves open:
 1. Segments (Sec. 2.2): scanning in time order, a new segment starts where
    the time step exceeds 30 cadences (30 x 0.020428 d, about 14.7 h) or the
    flux step exceeds 5 standard deviations of the curve's flux. Reading: the
-   curve is time-sorted; the standard deviation is the sample std (ddof 1)
-   of the samples outside known transits, and known-transit samples neither
-   start a segment nor serve as the previous sample of a step (so a masked
-   transit does not split its segment).
+   curve is time-sorted; the time step is taken from the previous sample,
+   known transit or not (a gap is a gap in the observations); the flux step
+   is taken only between samples outside known transits, from the previous
+   such sample (so a masked transit's dip does not split its segment); the
+   standard deviation is the sample std (ddof 1) of the samples outside known
+   transits.
 2. Spline continuum of each segment with known transits masked, outliers
    beyond 3 sigma removed iteratively, the smoothing chosen by BIC. Reading:
    a least-squares cubic B-spline with uniform knots; the smoothing parameter
@@ -60,12 +62,13 @@ def segments(t, flux, transit=None, cadence=CADENCE, gap_cadences=GAP_CADENCES,
     sd = free.std(ddof=1) if free.size > 1 else 0.0
     out, start, prev = [], 0, -1
     for i in range(n):
-        if tr[i]:
-            continue
-        if prev >= 0 and (t[i] - t[prev] > gap_cadences * cadence or abs(f[i] - f[prev]) > jump_sigma * sd):
-            out.append((start, i))     # masked samples before i stay with the earlier segment
+        opens = i > 0 and t[i] - t[i - 1] > gap_cadences * cadence
+        if not tr[i]:
+            opens = opens or (prev >= 0 and abs(f[i] - f[prev]) > jump_sigma * sd)
+            prev = i
+        if opens:
+            out.append((start, i))
             start = i
-        prev = i
     out.append((start, n))
     return out
 

@@ -144,3 +144,21 @@ def test_edges_cropped_and_short_segments_dropped():
     assert keep[60:121].sum() <= 1 and not keep[60:90].any() and not keep[91:121].any()
     assert not keep[121:151].any() and not keep[591:].any()
     assert keep[151:591].sum() >= 430
+
+
+def test_transit_after_a_gap_opens_the_next_segment():
+    # a gap is a gap in the observations whether or not the samples after it are
+    # masked: a known transit right after a 2-day gap starts the next segment
+    # (kept with the segment before the gap, its continuum would be unconstrained)
+    rng = np.random.default_rng(9)
+    t = np.concatenate([_grid(1000), _grid(1000, 22.0)])
+    f = (1.0 + 3e-3 * np.sin(t / 4.0) + rng.normal(0, 2e-4, t.size)).astype(np.float32)
+    tr = np.zeros(t.size, bool)
+    tr[1000:1008] = True
+    assert od.segments(t, f, tr) == [(0, 1000), (1000, 2000)]
+    # a masked sample does not serve as the previous sample of a flux step
+    g = f.copy()
+    g[500:504] -= np.float32(0.05)
+    m = np.zeros(t.size, bool)
+    m[500:504] = True
+    assert od.segments(t, g, m) == [(0, 1000), (1000, 2000)]
