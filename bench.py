@@ -174,7 +174,7 @@ def cnn_training_row(dev, reps, B=16_384):
             "tflops": tf, "peak_tflops": MFMA_BF16_PEAK_TFLOPS, "frac": tf / MFMA_BF16_PEAK_TFLOPS}
 
 
-def measure_rows(plan, t, f, pp, periods, survey_stars):
+def measure_rows(plan, t, f, pp, periods, survey_stars, learned_gain=True):
     """Each step of the path on its own at the benchmark shapes (and the
     many-star survey), with the roofline that bounds it."""
     import numpy as np
@@ -280,7 +280,21 @@ def measure_rows(plan, t, f, pp, periods, survey_stars):
         t0 = time.perf_counter()
         r = sp.survey_run(ts, fs, grid, NBINS, cnn=snet, top=4, judge_snr=4.0)
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        wall_eager = time.perf_counter() - t0
+        # the same survey captured once as a HIP graph and replayed (how a
+        # catalogue search runs it): the timed figure
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            rg = sp.survey_capture(ts, fs, grid, NBINS, cnn=snet, top=4, judge_snr=4.0)
+            sp.batch_replay()
+            side.synchronize()
+            t0 = time.perf_counter()
+            sp.batch_replay()
+            side.synchronize()
+            wall = time.perf_counter() - t0
+        replay_equal = bool(torch.equal(rg["box_idx"], r["box_idx"]) and torch.equal(rg["logits"], r["logits"]))
+        del rg
         upd = float(so[-1]) * ks
         folds = survey_stars * ks
         truth = [s.truth for s in stars]
@@ -292,10 +306,22 @@ def measure_rows(plan, t, f, pp, periods, survey_stars):
                 p_best = gp[idx[j]]
                 found += int(abs(p_best - tr["period"]) / tr["period"] < 2e-3)
         rows["a10_survey"] = {"stars": survey_stars, "periods_per_star": ks, "samples": int(so[-1]),
-                              "seconds": wall, "updates_per_s": upd / wall,
+                              "seconds": wall, "timed": "graph replay", "eager_seconds": wall_eager,
+                              "replay_equals_eager": replay_equal, "updates_per_s": upd / wall,
                               "folds_scored_per_s": folds / wall,
                               "box_best_at_injected_period": f"{found}/{sum(1 for x in truth if x.get('has_transit'))}"}
         del r, sp, snet
+    if learned_gain:
+        # C3: the trained network against the box statistic, as the paper judges its network
+        from paper_2312_02063_amd import learn
+        g = learn.learned_gain(plan, n_eval=10000)
+        rows["c3_learned_gain"] = {
+            "recall_at_1pct_fpr": {"cnn": g["cnn"]["recall_at_1pct_fpr"], "box": g["box"]["recall_at_1pct_fpr"],
+                                   "box_judged_cnn": g["judged"]["recall_at_1pct_fpr"]},
+            "auc": {"cnn": g["cnn"]["auc"], "box": g["box"]["auc"], "box_judged_cnn": g["judged"]["auc"]},
+            "eval": "10,000 transit + 10,000 noise held-out curves (4,000 samples) x 1,000 periods",
+            "train": "400,000 + 400,000 kernel folds, 8 epochs, 4 hard-negative rounds",
+            "train_seconds": g["train_seconds"], "eval_seconds": g["eval_seconds"]}
     return rows
 
 
@@ -308,6 +334,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=20_000, help="oracle sample in periods (0: skip)")
     ap.add_argument("--naive-k", type=int, default=20_000, help="periods for the plain-fold rate (0: skip)")
     ap.add_argument("--rows", type=int, default=1, help="also measure each step on its own (0: skip)")
+    ap.add_argument("--learned-gain", type=int, default=1,
+                    help="train the learned scorer and compare it with box-SNR (0: skip)")
     ap.add_argument("--survey-stars", type=int, default=512,
                     help="stars in the many-star survey measurement (0: skip)")
     ap.add_argument("--cnn-only", action="store_true",
@@ -404,7 +432,8 @@ def main():
     roof = roof_probes()
     u64_rate = roof["lds_u64_atomic"]["rate"]
 
-    rows = measure_rows(plan, t, f, pp, periods, args.survey_stars) if args.rows else None
+    rows = (measure_rows(plan, t, f, pp, periods, args.survey_stars, bool(args.learned_gain))
+            if args.rows else None)
 
     cpu = None
     if args.cpu_sample > 0:

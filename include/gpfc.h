@@ -429,6 +429,54 @@ int32_t gpfc_cnn_train_capture(gpfc_cnn *cnn, const void *x, int32_t x_f32, cons
                                float *loss_out, void *stream);
 int32_t gpfc_cnn_train_replay(gpfc_cnn *cnn, void *stream);
 
+/*
+ * The paper's own scoring network (Sec. 2.5, Fig. 5): the 256-bin normalised
+ * fold read row-major as a 16 x 16 image; circular (wrap-around in both axes,
+ * same-size) 2-D convolutions of 128 then 256 filters with 3 x 3 kernels, each
+ * followed by ReLU; a global max-pool over the 256 positions, whose 256 values
+ * are read row-major as a new one-channel 16 x 16 image; the same with 5 x 5
+ * kernels (128 then 256 filters, global max-pool); a dense layer of 128 ReLU
+ * units, dropout, and a dense output unit whose sigmoid is the transit
+ * probability. The kernel sides, the reshape order and the hidden width are
+ * readings: the text names the layer types and filter counts only.
+ * Parameters (FP32, flat, gpfc_pnet_nparams() = 1,152,257 values): w1
+ * [128][1][3][3], b1 [128], w2 [256][128][3][3], b2 [256], w3 [128][1][5][5],
+ * b3 [128], w4 [256][128][5][5], b4 [256], w5 [128][256], b5 [128], w6 [128],
+ * b6 [1]; a convolution is a cross-correlation,
+ *   y[f][r][c] = b[f] + sum w[f][i][u][v] x[i][(r+u-p) mod 16][(c+v-p) mod 16], p = (side-1)/2;
+ * a global max-pool routes its gradient to the first position of the maximum
+ * in row-major order. precision: GPFC_CNN_BF16 (matrix cores on bf16 weights
+ * and activations, FP32 accumulation, biases FP32) or GPFC_CNN_FP32.
+ * max_batch: inputs per internal pass (device memory ~160 KB per input in
+ * bf16, twice that in FP32); forward takes any batch in passes of it,
+ * backward at most max_batch. All arrays are device pointers; calls are
+ * asynchronous on `stream`. x: [B][256] bf16 bits (x_f32 = 0) or FP32.
+ */
+typedef struct gpfc_pnet gpfc_pnet;
+int32_t gpfc_pnet_nparams(void);
+const char *gpfc_pnet_last_error(void);
+int32_t gpfc_pnet_create(gpfc_pnet **out, int32_t device, int32_t precision, int64_t max_batch);
+int32_t gpfc_pnet_destroy(gpfc_pnet *net);
+/* Copy in FP32 parameters (device, flat order above); resets Adam. */
+int32_t gpfc_pnet_set_params(gpfc_pnet *net, const float *params, void *stream);
+int32_t gpfc_pnet_get_params(gpfc_pnet *net, float *params, void *stream);
+/* Logits f32 [B] (inference: no dropout). GPFC_EINVAL before set_params. */
+int32_t gpfc_pnet_forward(gpfc_pnet *net, const void *x, int32_t x_f32, int64_t B, float *logits,
+                          void *stream);
+/*
+ * Forward with the dropout keep mask keep [B][128] (each entry 0 or
+ * 1/(1 - rate), drawn by the caller; NULL: no dropout), then the gradient of
+ * the mean binary cross-entropy with logits (labels f32 [B] in {0, 1}) into
+ * the network's gradient buffer (gpfc_pnet_get_grads). logits [B] receives
+ * the forward's logits, loss (device f32, may be NULL) the mean loss.
+ * B <= max_batch (GPFC_ERANGE beyond).
+ */
+int32_t gpfc_pnet_backward(gpfc_pnet *net, const void *x, int32_t x_f32, const float *labels,
+                           const float *keep, int64_t B, float *logits, float *loss, void *stream);
+int32_t gpfc_pnet_get_grads(gpfc_pnet *net, float *grads, void *stream);
+/* One Adam step (bias-corrected) on the FP32 masters from the last gradient. */
+int32_t gpfc_pnet_adam(gpfc_pnet *net, float lr, float beta1, float beta2, float eps, void *stream);
+
 /* ------------------------------------------------------------------------
  * Per-curve reduction (Sec. 2.1: a curve's detection is the trial period
  * with the best score; Sec. 3.2: the maximum score over trial periods is the
@@ -574,6 +622,64 @@ int32_t gpfc_roof_probe(int32_t device, int32_t kind, double *rate_out, double *
 int32_t gpfc_fold_score_noalloc(const double *t, const float *flux, int64_t n,
                                 const double *periods, int64_t k, int32_t nbins, float *snr,
                                 int32_t *start, int32_t *width, float *depth, void *stream);
+
+/*
+ * Light-curve pre-processing (Sec. 2.2, Fig. 3): segments, spline continuum,
+ * division, edge crop, for one time-sorted curve t f64[n], flux f32[n], with
+ * optional known-transit flags transit u8[n] (nonzero: masked; may be NULL).
+ *  1. A new segment starts where the time step from the previous sample
+ *     exceeds gap_cadences x cadence, or where an unmasked sample's flux step
+ *     from the previous unmasked sample exceeds jump_sigma standard deviations
+ *     (sample std, ddof 1, of the unmasked flux): a masked transit's dip does
+ *     not split its segment.
+ *  2. Per segment and per knot spacing h of the list: a least-squares cubic
+ *     B-spline with uniform knots (L = max(1, ceil(span / h)) spans, L + 3
+ *     basis functions) fitted to the unmasked, unclipped points; points with
+ *     |residual| > clip_sigma x the residual scatter (ddof 0) of the fitted
+ *     points are clipped (masked points never) and the fit repeated until the
+ *     clipped set repeats, at most max_fits fits (the last fit and the set it
+ *     used are kept); BIC = n ln(RSS / n) + m ln n over its n fitted points and
+ *     m basis functions. A spacing with fewer than 2m fitted points, or whose
+ *     normal equations are singular, is not tried; the smallest BIC wins
+ *     (ties: the earlier spacing).
+ *  3. flux_out f64[n] = flux / continuum over each segment (0 in dropped
+ *     segments).
+ *  4. keep_out u8[n] = 1 for points at least `edge` points from both ends of
+ *     their segment and not clipped by the chosen fit; a segment of at most
+ *     2 edge points, or with no tried spacing, is dropped (all 0).
+ * The kept points in time order are the stitched curve (step 5). FP64
+ * arithmetic; results are deterministic. opts_host NULL takes the defaults
+ * (cadence 0.020428 d, 30 cadences, 5 sigma, 3 sigma, edge 30, 10 fits,
+ * spacings 0.5, 0.75, 1, 1.5, 2, 3, 5 d); otherwise every field is used as
+ * given (cadence, gap, jump and clip > 0; edge >= 0; 1 <= max_fits <= 100;
+ * 1 <= n_spacings <= 8 ascending spacings > 0). Synchronous (waits for
+ * `stream`); uses the plan's workspace (about 34 bytes per sample per
+ * spacing). Returns GPFC_ERANGE if a segment would need more than 2048 basis
+ * functions at some spacing. info_host (may be NULL) receives the segment
+ * count, the number of kept segments and the status bits (1: basis limit,
+ * 2: a singular system was skipped).
+ */
+#define GPFC_DETREND_MAX_SPACINGS 8
+typedef struct gpfc_detrend_opts {
+    double cadence;
+    double gap_cadences;
+    double jump_sigma;
+    double clip_sigma;
+    int32_t edge;
+    int32_t max_fits;
+    int32_t n_spacings;
+    int32_t pad;
+    double spacings[GPFC_DETREND_MAX_SPACINGS];
+} gpfc_detrend_opts;
+typedef struct gpfc_detrend_info {
+    int32_t n_segments;
+    int32_t n_kept_segments;
+    int32_t status;
+    int32_t pad;
+} gpfc_detrend_info;
+int32_t gpfc_detrend(gpfc_plan *plan, const double *t, const float *flux, const uint8_t *transit,
+                     int64_t n, const gpfc_detrend_opts *opts_host, double *flux_out,
+                     uint8_t *keep_out, gpfc_detrend_info *info_host, void *stream);
 
 /*
  * hipStreamSynchronize(stream); reports an asynchronous device error

@@ -54,6 +54,20 @@ class PlanOpts(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_int64)]
 
 
+class DetrendOpts(ctypes.Structure):
+    """Host mirror of ``gpfc_detrend_opts``."""
+    _fields_ = [("cadence", ctypes.c_double), ("gap_cadences", ctypes.c_double),
+                ("jump_sigma", ctypes.c_double), ("clip_sigma", ctypes.c_double),
+                ("edge", ctypes.c_int32), ("max_fits", ctypes.c_int32), ("n_spacings", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("spacings", ctypes.c_double * 8)]
+
+
+class DetrendInfo(ctypes.Structure):
+    """Host mirror of ``gpfc_detrend_info``."""
+    _fields_ = [("n_segments", ctypes.c_int32), ("n_kept_segments", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
 class SurveyOut(ctypes.Structure):
     """Host mirror of ``gpfc_survey_out`` (device pointers)."""
     _fields_ = [("snr", ctypes.c_void_p), ("start", ctypes.c_void_p), ("width", ctypes.c_void_p),
@@ -127,6 +141,18 @@ def load():
         "gpfc_roof_probe": ([i32, i32, ctypes.POINTER(f64), ctypes.POINTER(f64), vp], i32),
         "gpfc_cnn_load": ([vp, ctypes.c_char_p, vp], i32),
         "gpfc_fold_score_noalloc": ([vp, vp, i64, vp, i64, i32, vp, vp, vp, vp, vp], i32),
+        "gpfc_detrend": ([vp, vp, vp, vp, i64, ctypes.POINTER(DetrendOpts), vp, vp,
+                          ctypes.POINTER(DetrendInfo), vp], i32),
+        "gpfc_pnet_nparams": ([], i32),
+        "gpfc_pnet_last_error": ([], ctypes.c_char_p),
+        "gpfc_pnet_create": ([ctypes.POINTER(vp), i32, i32, i64], i32),
+        "gpfc_pnet_destroy": ([vp], i32),
+        "gpfc_pnet_set_params": ([vp, vp, vp], i32),
+        "gpfc_pnet_get_params": ([vp, vp, vp], i32),
+        "gpfc_pnet_forward": ([vp, vp, i32, i64, vp, vp], i32),
+        "gpfc_pnet_backward": ([vp, vp, i32, vp, vp, i64, vp, vp, vp], i32),
+        "gpfc_pnet_get_grads": ([vp, vp, vp], i32),
+        "gpfc_pnet_adam": ([vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -152,7 +178,10 @@ def exported_symbols():
             "gpfc_cnn_train_replay", "gpfc_topk", "gpfc_plan_set_split",
             "gpfc_autotune", "gpfc_fold_eqcount_prepared", "gpfc_periodogram_peaks", "gpfc_survey_setup", "gpfc_survey_run",
             "gpfc_survey_capture", "gpfc_cnn_train_step", "gpfc_cnn_save", "gpfc_cnn_load",
-            "gpfc_roof_probe", "gpfc_fold_score_noalloc"]
+            "gpfc_roof_probe", "gpfc_fold_score_noalloc", "gpfc_pnet_nparams", "gpfc_pnet_last_error",
+            "gpfc_pnet_create", "gpfc_pnet_destroy", "gpfc_pnet_set_params", "gpfc_pnet_get_params",
+            "gpfc_pnet_forward", "gpfc_pnet_backward", "gpfc_pnet_get_grads", "gpfc_pnet_adam",
+            "gpfc_detrend"]
 
 
 ROOF_LDS_U64, ROOF_LDS_U32, ROOF_LDS_F32, ROOF_FP64_FMA, ROOF_HBM_COPY = 0, 1, 2, 3, 4
@@ -490,6 +519,30 @@ class Plan:
                                             _stream()), "gpfc_survey_capture")
         return r
 
+    def detrend(self, t, flux, transit=None, cadence: float = 0.020428, gap_cadences: float = 30.0,
+                jump_sigma: float = 5.0, clip_sigma: float = 3.0, edge: int = 30, max_fits: int = 10,
+                spacings=(0.5, 0.75, 1.0, 1.5, 2.0, 3.0, 5.0)):
+        """Pre-processing of a time-sorted curve (gpfc_detrend): returns
+        (flux / continuum f64 [n], keep uint8 [n], info dict)."""
+        import torch
+        self._inputs(t, flux)
+        if transit is not None:
+            _need(transit, torch.uint8, "transit", self.device)
+        n = t.numel()
+        o = DetrendOpts(cadence=cadence, gap_cadences=gap_cadences, jump_sigma=jump_sigma,
+                        clip_sigma=clip_sigma, edge=int(edge), max_fits=int(max_fits),
+                        n_spacings=len(spacings))
+        for i, h in enumerate(spacings):
+            o.spacings[i] = float(h)
+        out = torch.empty(n, dtype=torch.float64, device=self.device)
+        keep = torch.empty(n, dtype=torch.uint8, device=self.device)
+        info = DetrendInfo()
+        _check(self.lib.gpfc_detrend(self.h, _ptr(t), _ptr(flux), _ptr(transit), n, ctypes.byref(o),
+                                     _ptr(out), _ptr(keep), ctypes.byref(info), _stream()),
+               "gpfc_detrend")
+        return out, keep, {"n_segments": info.n_segments, "n_kept_segments": info.n_kept_segments,
+                           "status": info.status}
+
     def fold_naive(self, t, flux, periods, nbins: int, out=None):
         """Plain global-atomic GPU fold (baseline): (sums, counts)."""
         import torch
@@ -714,3 +767,96 @@ class Cnn:
     def load(self, path: str):
         """Read a network file written by save (resets the Adam state)."""
         _check(self.lib.gpfc_cnn_load(self.h, str(path).encode(), _stream()), "gpfc_cnn_load")
+
+
+class PNet:
+    """The paper's own network (gpfc_pnet_*): 16 x 16 image of the fold,
+    circular 2-D convolutions of 128 and 256 filters (3 x 3, then 5 x 5) with
+    global max-pools, a dense ReLU layer with dropout and a sigmoid output;
+    FP32 master weights, bf16 (or FP32) matrix-core forward, Adam."""
+
+    def __init__(self, device: int = 0, precision: int = CNN_BF16, max_batch: int = 1024):
+        import torch
+        self.lib = load()
+        self.device = torch.device("cuda", device)
+        self.max_batch = max_batch
+        self.n_params = int(self.lib.gpfc_pnet_nparams())
+        h = ctypes.c_void_p()
+        rc = self.lib.gpfc_pnet_create(ctypes.byref(h), device, precision, max_batch)
+        _check(rc, "gpfc_pnet_create")
+        self.h = h
+        self._loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.gpfc_pnet_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        import torch
+        p = torch.as_tensor(params, dtype=torch.float32, device=self.device).contiguous()
+        if p.numel() != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters")
+        _check(self.lib.gpfc_pnet_set_params(self.h, _ptr(p), _stream()), "gpfc_pnet_set_params")
+        torch.cuda.current_stream().synchronize()
+
+    def get_params(self):
+        import torch
+        out = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        _check(self.lib.gpfc_pnet_get_params(self.h, _ptr(out), _stream()), "gpfc_pnet_get_params")
+        return out
+
+    def get_grads(self):
+        import torch
+        out = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        _check(self.lib.gpfc_pnet_get_grads(self.h, _ptr(out), _stream()), "gpfc_pnet_get_grads")
+        return out
+
+    @staticmethod
+    def _xf(x):
+        import torch
+        if x.dtype == torch.uint16:
+            return 0
+        if x.dtype == torch.float32:
+            return 1
+        raise TypeError("x must be uint16 (bfloat16 bits) or float32")
+
+    def forward(self, x, out=None):
+        """Logits f32[B] for x [B][256] (no dropout)."""
+        import torch
+        xf = self._xf(x)
+        _need(x, x.dtype, "x", self.device)
+        B = x.shape[0]
+        logits = out if out is not None else torch.empty(B, dtype=torch.float32, device=self.device)
+        _check(self.lib.gpfc_pnet_forward(self.h, _ptr(x), xf, B, _ptr(logits), _stream()),
+               "gpfc_pnet_forward")
+        return logits
+
+    def backward(self, x, labels, keep=None, logits=None):
+        """Gradient of the mean BCE at x with dropout keep mask `keep` [B][128]
+        (None: no dropout); returns the loss as a device scalar tensor."""
+        import torch
+        xf = self._xf(x)
+        _need(x, x.dtype, "x", self.device)
+        _need(labels, torch.float32, "labels", self.device)
+        if keep is not None:
+            _need(keep, torch.float32, "keep", self.device)
+        B = x.shape[0]
+        lg = logits if logits is not None else torch.empty(B, dtype=torch.float32, device=self.device)
+        _check(self.lib.gpfc_pnet_backward(self.h, _ptr(x), xf, _ptr(labels), _ptr(keep), B, _ptr(lg),
+                                           _ptr(self._loss), _stream()), "gpfc_pnet_backward")
+        return self._loss
+
+    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        _check(self.lib.gpfc_pnet_adam(self.h, lr, beta1, beta2, eps, _stream()), "gpfc_pnet_adam")
+
+    def train_step(self, x, labels, lr: float, keep=None):
+        loss = self.backward(x, labels, keep)
+        self.adam(lr)
+        return loss

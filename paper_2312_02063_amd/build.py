@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgpfc.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("gpfc_api.hip", "gpfc_kernels.hip", "gpfc_cnn.hip", "gpfc_reduce.hip", "gpfc_roof.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("gpfc_api.hip", "gpfc_kernels.hip", "gpfc_cnn.hip", "gpfc_reduce.hip", "gpfc_roof.hip", "gpfc_pnet.hip", "gpfc_detrend.hip")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

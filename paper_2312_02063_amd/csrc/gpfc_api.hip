@@ -49,7 +49,10 @@ struct gpfc_plan {
     bool b_survey = false;
     int64_t s_k = 0;                   // periods per curve
     uint16_t* s_zbuf = nullptr;        // normalised folds of one chunk (inside b_dev)
+    uint16_t* s_zbuf2 = nullptr;       // a second chunk buffer (several chunks: double buffering)
     int64_t s_zfolds = 0;              // folds s_zbuf holds (0: no workspace)
+    hipStream_t s_net = nullptr;       // the network's stream in a pipelined survey
+    hipEvent_t s_ev[4] = {};           // fold done / network done, per chunk buffer
     std::vector<SurveyChunk> s_chunks;
     // sample split of the single-curve fold + score (k_fold_score_split)
     int32_t split = 0;                 // 0: automatic
@@ -66,6 +69,9 @@ struct gpfc_plan {
     size_t w_cap = 0;
     int64_t w_limit = int64_t(1) << 30;       // bytes a chunk's workspace may take
     char tune_cache[512] = "";                // default autotuner cache path ("" none)
+    // pre-processing (gpfc_detrend)
+    void* d_buf = nullptr;
+    size_t d_cap = 0;
 };
 
 namespace {
@@ -372,11 +378,15 @@ int32_t gpfc_plan_destroy(gpfc_plan* p) {
     if (p->lo) (void)hipFree(p->lo);
     if (p->info) (void)hipFree(p->info);
     if (p->w_buf) (void)hipFree(p->w_buf);
+    if (p->d_buf) (void)hipFree(p->d_buf);
     if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->b_dev) (void)hipFree(p->b_dev);
     if (p->split_gh) (void)hipFree(p->split_gh);
     if (p->split_arrivals) (void)hipFree(p->split_arrivals);
+    for (hipEvent_t& ev : p->s_ev)
+        if (ev) (void)hipEventDestroy(ev);
+    if (p->s_net) (void)hipStreamDestroy(p->s_net);
     delete p;
     return GPFC_OK;
 }
@@ -454,7 +464,10 @@ static int32_t pow2_floor(int64_t x) {
 // Sample split for a fold + score of the prepared curve (n samples) at k
 // periods: the forced value, else the autotuned one for this shape, else
 // enough blocks per 64-period tile to give every compute unit one block,
-// keeping at least 512 records per wave per part.
+// keeping at least 256 records per wave per part. Measured on MI355X: a
+// 4,000-sample curve (256 records per wave) is fastest unsplit even at 16
+// tiles (35 us; split 2 takes 47 us), a 65,000-sample one at 16 tiles with 8
+// parts (119 us against 293 us unsplit), a 20,000-sample one with 4.
 static int32_t resolve_split(const gpfc_plan* p, int64_t n, int64_t k, int32_t nbins) {
     const int64_t tiles = (k + 63) / 64;
     if (tiles == 0 || tiles > p->n_cu) return 1;
@@ -463,7 +476,7 @@ static int32_t resolve_split(const gpfc_plan* p, int64_t n, int64_t k, int32_t n
     else if (p->tuned_n == n && p->tuned_k == k && p->tuned_nbins == nbins) sp = p->tuned_split;
     else {
         const int64_t per = gpfc::slice_len(n);
-        sp = pow2_floor(std::max<int64_t>(1, std::min<int64_t>(p->n_cu / tiles, per / 512)));
+        sp = pow2_floor(std::max<int64_t>(1, std::min<int64_t>(p->n_cu / tiles, per / 256)));
     }
     return std::max(1, std::min(sp, GPFC_MAX_SPLIT));
 }
@@ -721,6 +734,7 @@ static int32_t batch_upload(gpfc_plan* p, const int64_t* soff, int32_t n_curves,
     p->b_curves = -1;
     p->b_survey = false;
     p->s_zbuf = nullptr;
+    p->s_zbuf2 = nullptr;
     p->s_zfolds = 0;
     p->s_chunks.clear();
     e = hipMalloc(&p->b_dev, total);
@@ -823,13 +837,25 @@ int32_t gpfc_survey_setup(gpfc_plan* p, const int64_t* soff, int32_t n_curves, i
         push_items(it, soff, (int32_t)c0, c1, curves);
         chunks.push_back(SurveyChunk{(int32_t)c0, c1, i0, (int32_t)it.size()});
     }
+    // two chunk buffers when there are several chunks: the network of one chunk
+    // runs on its own stream while the next chunk is folded into the other buffer
+    const int nbuf = chunks.size() > 1 ? 2 : 1;
+    const size_t zbytes = ((size_t)zfolds * gpfc::kFineBins * sizeof(uint16_t) + 255) & ~size_t(255);
     void* z = nullptr;
     int32_t rc = batch_upload(p, soff, n_curves, roff, curves, it, (int64_t)n_curves * k,
-                              (size_t)zfolds * gpfc::kFineBins * sizeof(uint16_t), &z);
+                              nbuf * zbytes, &z);
     if (rc != GPFC_OK) return rc;
+    if (zfolds > 0 && nbuf == 2) {
+        hipError_t e = hipSuccess;
+        if (!p->s_net) e = hipStreamCreateWithFlags(&p->s_net, hipStreamNonBlocking);
+        for (hipEvent_t& ev : p->s_ev)
+            if (e == hipSuccess && !ev) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) return device_error(e, "survey stream setup");
+    }
     p->b_survey = true;
     p->s_k = k;
     p->s_zbuf = (uint16_t*)z;
+    p->s_zbuf2 = (zfolds > 0 && nbuf == 2) ? (uint16_t*)((char*)z + zbytes) : nullptr;
     p->s_zfolds = zfolds;
     p->s_chunks = chunks;
     return GPFC_OK;
@@ -939,23 +965,57 @@ static int32_t survey_enqueue(gpfc_plan* p, gpfc_cnn* cnn, const double* t, cons
     if (e != hipSuccess) return device_error(e, "survey prepare launch");
     const bool net = o.logits != nullptr;
     const int64_t K = p->s_k;
-    for (const SurveyChunk& ch : p->s_chunks) {
-        e = gpfc::launch_batch_fold_score(p->b_rec, p->b_lo, p->b_curve, p->b_item + ch.i0, ch.i1 - ch.i0,
-                                          p->b_counter, p->b_info, periods, nbins,
-                                          plan_widths(p, nbins), p->n_cu, o.snr, o.start, o.width,
-                                          o.depth, net ? p->s_zbuf : nullptr, s);
-        if (e != hipSuccess) return device_error(e, "survey fold_score launch");
-        if (!net) continue;
+    // Several chunks with a network: chunk j is folded on `s` into buffer j % 2
+    // while the network scores chunk j - 1 from the other buffer on p->s_net.
+    // Events order the two: the network of chunk j waits for its fold, the fold
+    // of chunk j + 2 waits for the network of chunk j (same buffer), and `s`
+    // waits for the last networks before the per-curve best-K.
+    const bool pipe = net && p->s_zbuf2 != nullptr;
+    auto net_chunk = [&](const SurveyChunk& ch, const uint16_t* zb, hipStream_t ns) -> int32_t {
         const int64_t folds = (int64_t)(ch.c1 - ch.c0) * K;
         const int64_t mb = gpfc::cnn_max_batch(cnn);
         for (int64_t f0 = 0; f0 < folds; f0 += mb) {
             const int64_t B = std::min<int64_t>(mb, folds - f0);
-            const uint16_t* x = p->s_zbuf + f0 * gpfc::kFineBins;
+            const uint16_t* x = zb + f0 * gpfc::kFineBins;
             float* lg = o.logits + (int64_t)ch.c0 * K + f0;
-            const int32_t rc = o.cnn_fp8 ? gpfc_cnn_forward_fp8(cnn, x, 0, B, lg, s)
-                                         : gpfc_cnn_forward(cnn, x, 0, B, lg, s);
+            const int32_t rc = o.cnn_fp8 ? gpfc_cnn_forward_fp8(cnn, x, 0, B, lg, ns)
+                                         : gpfc_cnn_forward(cnn, x, 0, B, lg, ns);
             if (rc != GPFC_OK) return rc;
         }
+        return GPFC_OK;
+    };
+    for (size_t j = 0; j < p->s_chunks.size(); ++j) {
+        const SurveyChunk& ch = p->s_chunks[j];
+        const int b = (int)(j & 1);
+        uint16_t* zb = (pipe && b) ? p->s_zbuf2 : p->s_zbuf;
+        if (pipe && j >= 2) {
+            e = hipStreamWaitEvent(s, p->s_ev[2 + b], 0);
+            if (e != hipSuccess) return device_error(e, "survey stream wait");
+        }
+        e = gpfc::launch_batch_fold_score(p->b_rec, p->b_lo, p->b_curve, p->b_item + ch.i0, ch.i1 - ch.i0,
+                                          p->b_counter, p->b_info, periods, nbins,
+                                          plan_widths(p, nbins), p->n_cu, o.snr, o.start, o.width,
+                                          o.depth, net ? zb : nullptr, s);
+        if (e != hipSuccess) return device_error(e, "survey fold_score launch");
+        if (!net) continue;
+        if (!pipe) {
+            const int32_t rc = net_chunk(ch, zb, s);
+            if (rc != GPFC_OK) return rc;
+            continue;
+        }
+        e = hipEventRecord(p->s_ev[b], s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(p->s_net, p->s_ev[b], 0);
+        if (e != hipSuccess) return device_error(e, "survey stream fork");
+        const int32_t rc = net_chunk(ch, zb, p->s_net);
+        if (rc != GPFC_OK) return rc;
+        e = hipEventRecord(p->s_ev[2 + b], p->s_net);
+        if (e != hipSuccess) return device_error(e, "survey event record");
+    }
+    if (pipe) {
+        // join: the best-K below reads every chunk's logits
+        e = hipStreamWaitEvent(s, p->s_ev[2], 0);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, p->s_ev[3], 0);
+        if (e != hipSuccess) return device_error(e, "survey stream join");
     }
     if (o.top > 0) {
         const int64_t rows = p->b_curves;
@@ -1084,6 +1144,78 @@ int32_t gpfc_fold_score_noalloc(const double* t, const float* flux, int64_t n,
     e = gpfc::launch_fold_score(rec, lo, n, periods, k, nbins, info, default_widths(nbins), snr,
                                 start, width, depth, nullptr, s);
     return e == hipSuccess ? GPFC_OK : device_error(e, "k_fold_score launch");
+}
+
+int32_t gpfc_detrend(gpfc_plan* p, const double* t, const float* flux, const uint8_t* transit,
+                     int64_t n, const gpfc_detrend_opts* o, double* flux_out, uint8_t* keep_out,
+                     gpfc_detrend_info* info, void* stream) {
+    if (!p || n < 0 || (n > 0 && (!t || !flux || !flux_out || !keep_out))) return GPFC_EINVAL;
+    if (n > 0x7ffffffeLL) return GPFC_ERANGE;
+    gpfc::DetrendParams prm{};
+    const double defaults[] = {0.5, 0.75, 1.0, 1.5, 2.0, 3.0, 5.0};
+    if (!o) {
+        prm.cadence = 0.020428;
+        prm.gap_cadences = 30.0;
+        prm.jump_sigma = 5.0;
+        prm.clip_sigma = 3.0;
+        prm.edge = 30;
+        prm.max_fits = 10;
+        prm.n_spacings = 7;
+        for (int i = 0; i < 7; ++i) prm.spacings[i] = defaults[i];
+    } else {
+        if (!(o->cadence > 0.0) || !(o->gap_cadences > 0.0) || !(o->jump_sigma > 0.0) ||
+            !(o->clip_sigma > 0.0) || o->edge < 0 || o->max_fits < 1 || o->max_fits > 100 ||
+            o->n_spacings < 1 || o->n_spacings > GPFC_DETREND_MAX_SPACINGS)
+            return GPFC_EINVAL;
+        for (int i = 0; i < o->n_spacings; ++i)
+            if (!(o->spacings[i] > 0.0) || !isfinite(o->spacings[i]) ||
+                (i > 0 && !(o->spacings[i] > o->spacings[i - 1])))
+                return GPFC_EINVAL;
+        prm.cadence = o->cadence;
+        prm.gap_cadences = o->gap_cadences;
+        prm.jump_sigma = o->jump_sigma;
+        prm.clip_sigma = o->clip_sigma;
+        prm.edge = o->edge;
+        prm.max_fits = o->max_fits;
+        prm.n_spacings = o->n_spacings;
+        for (int i = 0; i < o->n_spacings; ++i) prm.spacings[i] = o->spacings[i];
+    }
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return device_error(e, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = gpfc::detrend_workspace_bytes(n, prm.n_spacings);
+    if (bytes > p->d_cap) {
+        void* buf = nullptr;
+        e = hipMalloc(&buf, bytes);
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? GPFC_ENOMEM : device_error(e, "hipMalloc");
+        if (p->d_buf) {
+            (void)hipDeviceSynchronize();
+            (void)hipFree(p->d_buf);
+        }
+        p->d_buf = buf;
+        p->d_cap = bytes;
+    }
+    const gpfc::DetrendWs w = gpfc::detrend_carve(p->d_buf, n, prm.n_spacings);
+    e = gpfc::launch_detrend(t, flux, transit, n, prm, w, flux_out, keep_out, s);
+    if (e != hipSuccess) return device_error(e, "detrend launch");
+    int32_t st[2] = {0, 0};
+    e = hipMemcpyAsync(st, w.status, sizeof(st), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_error(e, "detrend status");
+    if (info) {
+        info->n_segments = st[1];
+        info->status = st[0];
+        info->pad = 0;
+        int32_t kept = 0;
+        if (st[1] > 0) {
+            std::vector<int32_t> ch((size_t)st[1]);
+            e = hipMemcpy(ch.data(), w.chosen, sizeof(int32_t) * st[1], hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return device_error(e, "detrend segments");
+            for (int32_t c : ch) kept += c >= 0;
+        }
+        info->n_kept_segments = kept;
+    }
+    return (st[0] & 1) ? GPFC_ERANGE : GPFC_OK;
 }
 
 int32_t gpfc_sync(void* stream) {

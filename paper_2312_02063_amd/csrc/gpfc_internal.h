@@ -72,6 +72,31 @@ struct Widths {
     int32_t n;
 };
 
+// Light-curve pre-processing (gpfc_detrend.hip).
+constexpr int kDetrendMaxBasis = 2048;   // spline basis functions a segment's fit may use
+constexpr int kDetrendMaxSpacings = 8;
+struct DetrendParams {
+    double cadence, gap_cadences, jump_sigma, clip_sigma;
+    int32_t edge, max_fits, n_spacings, pad;
+    double spacings[kDetrendMaxSpacings];
+};
+struct DetrendWs {
+    int32_t* seg;       // segment starts [n + 2]
+    int32_t* status;    // bit 0: a segment needed more than kDetrendMaxBasis functions;
+                        // bit 1: a normal-equation system was singular
+    int32_t* nseg;      // segments found
+    int32_t* chosen;    // spacing index chosen per segment (-1: dropped)
+    double* bic;
+    double* coef;
+    uint8_t* clip;
+    int8_t* state;
+};
+size_t detrend_workspace_bytes(int64_t n, int32_t ns);
+DetrendWs detrend_carve(void* ws, int64_t n, int32_t ns);
+hipError_t launch_detrend(const double* t, const float* flux, const uint8_t* tr, int64_t n,
+                          const DetrendParams& prm, const DetrendWs& w, double* out, uint8_t* keep,
+                          hipStream_t s);
+
 // Whether a curve statistics pass on the current device has seen a
 // non-finite time or flux since the last call (which clears the flag);
 // synchronous.

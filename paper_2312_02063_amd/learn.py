@@ -230,6 +230,126 @@ def evaluate(plan, net, n_pos: int, n_neg: int, seed: int, periods: np.ndarray, 
     return {key: np.concatenate(v) for key, v in out.items()}
 
 
+def train_scorer(plan, periods: np.ndarray, n_train: int = 400000, epochs: int = 8,
+                 hard_rounds: int = 4, hard_curves: int = 30000, hard_per_curve: int = 4,
+                 hard_epochs: int = 2, lr: float = 1e-3, batch: int = 256, snr_cut: float = 0.0,
+                 seed: int = 1003, log=None):
+    """The learned scorer's training recipe: n_train kernel folds of each class,
+    `epochs` of Adam, then `hard_rounds` rounds of hard-negative mining (each
+    adds the `hard_per_curve` best-scoring folds of `hard_curves` fresh noise
+    curves searched over the whole grid, with as many fresh positives, and
+    trains `hard_epochs` more at half the rate). Returns the network."""
+    import torch
+    z, y, _ = make_training_set(plan, n_train, n_train, seed=seed, periods=periods, snr_cut=snr_cut)
+    net = Cnn(0, CNN_BF16, max_batch=65536)
+    net.set_params(synth.cnn_init(seed).astype(np.float32))
+    train(net, z, y, epochs, batch, lr, log=log)
+    for rnd in range(hard_rounds):
+        hard = mine_hard_negatives(plan, net, hard_curves, hard_per_curve, seed=2000 + rnd,
+                                   periods=periods)
+        zp, yp, _ = make_training_set(plan, hard.shape[0], 0, seed=3000 + rnd, periods=periods,
+                                      snr_cut=snr_cut)
+        z = torch.cat([z, hard, zp])
+        y = torch.cat([y, torch.zeros(hard.shape[0], dtype=torch.float32, device=z.device), yp])
+        if log:
+            log(f"hard-negative round {rnd}: +{hard.shape[0]} negatives, +{zp.shape[0]} positives")
+        train(net, z, y, hard_epochs, batch, lr * 0.5, seed=11 + rnd, log=log)
+    return net
+
+
+def train_pnet(plan, periods: np.ndarray, n_train: int = 100000, epochs: int = 3,
+               hard_rounds: int = 1, hard_curves: int = 3000, hard_per_curve: int = 4,
+               hard_epochs: int = 1, lr: float = 2e-4, batch: int = 256, dropout: float = 0.5,
+               seed: int = 1003, log=None):
+    """Train the paper's own network (Sec. 2.5, PNet) on kernel folds with
+    dropout (keep masks drawn from a seeded generator and passed in), then
+    hard-negative rounds as train_scorer does. Returns the network."""
+    import torch
+    from ._lib import PNet
+    z, y, _ = make_training_set(plan, n_train, n_train, seed=seed, periods=periods)
+    net = PNet(0, CNN_BF16, max_batch=batch)
+    net.set_params(synth.pnet_init(seed).astype(np.float32))
+    gen = torch.Generator(device=z.device)
+    gen.manual_seed(seed)
+
+    def run(z, y, n_ep, rate, rseed):
+        rng = np.random.Generator(np.random.PCG64(rseed))
+        xbuf = torch.empty((batch, z.shape[1]), dtype=z.dtype, device=z.device)
+        ybuf = torch.empty(batch, dtype=torch.float32, device=z.device)
+        for ep in range(n_ep):
+            perm = torch.as_tensor(rng.permutation(z.shape[0]), device=z.device)
+            acc, steps = torch.zeros(1, device=z.device), 0
+            for i in range(0, z.shape[0] - batch + 1, batch):
+                idx = perm[i:i + batch]
+                torch.index_select(z, 0, idx, out=xbuf)
+                torch.index_select(y, 0, idx, out=ybuf)
+                keep = (torch.rand((batch, 128), generator=gen, device=z.device) >= dropout).float()
+                keep /= (1.0 - dropout)
+                acc += net.train_step(xbuf, ybuf, rate, keep=keep)
+                steps += 1
+            if log:
+                log(f"pnet epoch {ep}: mean loss {(acc / max(steps, 1)).item():.5f}")
+
+    run(z, y, epochs, lr, 7)
+    for rnd in range(hard_rounds):
+        hard = mine_hard_negatives(plan, net, hard_curves, hard_per_curve, seed=2000 + rnd,
+                                   periods=periods, cnn_batch=batch)
+        zp, yp, _ = make_training_set(plan, hard.shape[0], 0, seed=3000 + rnd, periods=periods)
+        z = torch.cat([z, hard, zp])
+        y = torch.cat([y, torch.zeros(hard.shape[0], dtype=torch.float32, device=z.device), yp])
+        run(z, y, hard_epochs, lr * 0.5, 11 + rnd)
+    return net
+
+
+def compare_networks(plan, n_eval: int = 2000, periods: np.ndarray | None = None, log=None,
+                     pnet_recipe: dict | None = None, cnn_recipe: dict | None = None):
+    """The configured 1-D network and the paper's own 2-D network, each trained
+    on kernel folds, judged with the box statistic on the same held-out curves
+    (n_eval with a transit, n_eval without, each searched over the grid):
+    recall at 1% false positives and AUC of each. Returns a dictionary."""
+    import torch
+    periods = grid(1000) if periods is None else periods
+    t0 = time.time()
+    cnn = train_scorer(plan, periods, log=log, **(cnn_recipe or {}))
+    t1 = time.time()
+    pnet = train_pnet(plan, periods, log=log, **(pnet_recipe or {}))
+    torch.cuda.synchronize()
+    t2 = time.time()
+    ev_c = evaluate(plan, cnn, n_eval, n_eval, seed=1013, periods=periods)
+    t3 = time.time()
+    ev_p = evaluate(plan, pnet, n_eval, n_eval, seed=1013, periods=periods, cnn_batch=pnet.max_batch * 64)
+    t4 = time.time()
+    sc, sp = summarize(ev_c), summarize(ev_p)
+    out = {"box": sc["box"], "cnn_1d": sc["cnn"], "cnn_1d_box_judged": sc["judged"],
+           "pnet_2d": sp["cnn"], "pnet_2d_box_judged": sp["judged"],
+           "seconds": {"train_cnn": t1 - t0, "train_pnet": t2 - t1, "eval_cnn": t3 - t2,
+                       "eval_pnet": t4 - t3},
+           "eval_curves": 2 * n_eval, "periods": int(periods.size)}
+    cnn.close()
+    pnet.close()
+    return out
+
+
+def learned_gain(plan, n_eval: int = 10000, periods: np.ndarray | None = None, log=None, **recipe):
+    """What the trained network gains over the box statistic: train with
+    train_scorer's recipe, then search n_eval held-out transit curves and n_eval
+    noise curves over the grid and compare the best network score per curve
+    with the best box-SNR per curve (recall at 1% false positives, AUC).
+    Returns summarize()'s dictionary plus timings."""
+    import torch
+    periods = grid(1000) if periods is None else periods
+    t0 = time.time()
+    net = train_scorer(plan, periods, log=log, **recipe)
+    torch.cuda.synchronize()
+    t1 = time.time()
+    ev = evaluate(plan, net, n_eval, n_eval, seed=1013, periods=periods)
+    res = summarize(ev)
+    res.update({"train_seconds": t1 - t0, "eval_seconds": time.time() - t1,
+                "eval_curves": 2 * n_eval, "periods": int(periods.size)})
+    net.close()
+    return res
+
+
 def auc_vs_periods(plan, net, ks, n_eval: int, seed: int = 1013, log=None):
     """Detection quality as the trial grid grows (Sec. 3.2): for each grid
     size k, the same held-out curves are folded over k periods and judged by

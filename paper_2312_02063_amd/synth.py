@@ -143,6 +143,35 @@ def kepler_long_curve(seed: int = 1002, n_keep: int = 65000, span_d: float = 147
                       n_in=int(inb[keep].sum())))
 
 
+def trended_curve(seed: int = 2002, n: int = 12000, cadence: float = 0.020428, sigma: float = 2e-4,
+                  n_gaps: int = 3, n_jumps: int = 1, n_outliers: int = 12, period: float = 3.7,
+                  depth: float = 3e-3, duration: float = 0.15):
+    """A raw (undetrended) Kepler-like curve for the pre-processing (Sec. 2.2):
+    a slow multiplicative trend (a few sinusoids of 2-20 d), white noise,
+    `n_gaps` gaps of 1-3 d, `n_jumps` flux steps of 5-10 % lasting to the
+    next gap or the end, `n_outliers` single-cadence spikes of 8-20 sigma and
+    a box transit whose samples are flagged as known. Returns (t f64, flux f32,
+    transit mask bool)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = cadence * np.arange(n, dtype=np.float64)
+    for _ in range(n_gaps):
+        at = rng.integers(n // 10, 9 * n // 10)
+        t[at:] += rng.uniform(1.0, 3.0)
+    trend = np.ones(n)
+    for _ in range(3):
+        trend += rng.uniform(1e-3, 6e-3) * np.sin(2 * np.pi * t / rng.uniform(2.0, 20.0) + rng.uniform(0, 6.3))
+    f = trend + rng.normal(0.0, sigma, n)
+    for _ in range(n_jumps):
+        at = rng.integers(n // 5, 4 * n // 5)
+        f[at:] *= 1.0 + rng.uniform(0.05, 0.10) * rng.choice([-1.0, 1.0])
+    epoch = rng.uniform(0, period)
+    tr = box_mask(t, period, epoch, duration)
+    f[tr] *= 1.0 - depth
+    idx = rng.choice(np.flatnonzero(~tr), size=n_outliers, replace=False)
+    f[idx] += rng.uniform(8.0, 20.0, n_outliers) * sigma * rng.choice([-1.0, 1.0], n_outliers)
+    return t, f.astype(np.float32), tr
+
+
 def multi_star(seed: int = 1005, n_stars: int = 512, nmin: int = 20000, nmax: int = 70000,
                n_transit: int = 51, alpha: tuple = (7.0, 20.0), pmin: float = 0.2,
                pmax: float = 1.0) -> list:
@@ -260,6 +289,24 @@ def cnn_init(seed: int = 1003) -> np.ndarray:
         shape = (cout, cin, 5) if kind == "conv" else (cout, cin)
         parts.append(rng.normal(0.0, np.sqrt(2.0 / fan_in), size=shape).ravel())
         parts.append(np.zeros(cout))
+    return np.concatenate(parts)
+
+
+# Parameter tensors of the paper's own network, in its flat order: (name, shape, fan-in).
+PNET_LAYERS = [("w1", (128, 1, 3, 3), 9), ("b1", (128,), 0), ("w2", (256, 128, 3, 3), 1152),
+               ("b2", (256,), 0), ("w3", (128, 1, 5, 5), 25), ("b3", (128,), 0),
+               ("w4", (256, 128, 5, 5), 3200), ("b4", (256,), 0), ("w5", (128, 256), 256),
+               ("b5", (128,), 0), ("w6", (128,), 128), ("b6", (1,), 0)]
+
+
+def pnet_init(seed: int = 1003) -> np.ndarray:
+    """He-normal initial weights of the paper's network (std sqrt(2 / fan_in)),
+    zero biases, float64, flat."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for _, shape, fan_in in PNET_LAYERS:
+        n = int(np.prod(shape))
+        parts.append(rng.normal(0.0, np.sqrt(2.0 / fan_in), size=n) if fan_in else np.zeros(n))
     return np.concatenate(parts)
 
 
