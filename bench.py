@@ -174,6 +174,44 @@ def cnn_training_row(dev, reps, B=16_384):
             "tflops": tf, "peak_tflops": MFMA_BF16_PEAK_TFLOPS, "frac": tf / MFMA_BF16_PEAK_TFLOPS}
 
 
+def eqcount_row(dev, reps, ke=200_000):
+    """The two-tier equal-count fold (4096 -> 256 bins) of the Kepler-long curve."""
+    import torch
+    from paper_2312_02063_amd import Plan, synth
+    c = synth.kepler_long_curve(seed=1002)
+    plan = Plan(0)
+    plan.prepare(torch.tensor(c.t, dtype=torch.float64, device=dev),
+                 torch.tensor(c.flux, dtype=torch.float32, device=dev))
+    pe = torch.tensor(synth.freq_grid(FMIN, FMAX, ke), dtype=torch.float64, device=dev)
+    me = torch.empty((ke, NBINS), dtype=torch.uint16, device=dev)
+    ms = _events_ms(lambda: plan.fold_eqcount_prepared(pe, NBINS, means=False, zfold=me), reps)
+    return {"row": "next_equal_count_fold", "periods_per_s": ke / ms * 1e3, "ms": ms, "periods": ke,
+            "updates_per_s": float(N_SAMPLES) * ke / ms * 1e3}
+
+
+PNET_FWD_FLOP = 2 * (256 * 128 * 9 + 256 * 256 * 1152 + 256 * 128 * 25 + 256 * 256 * 3200
+                     + 128 * 256 + 128)   # 572 MFLOP per input
+
+
+def pnet_rows(dev, reps, B=4096):
+    """The paper's 2-D network: bf16 inference and a training step at batch B."""
+    import numpy as np
+    import torch
+    from paper_2312_02063_amd import CNN_BF16, PNet, synth
+    net = PNet(0, CNN_BF16, max_batch=B)
+    net.set_params(synth.pnet_init(1003).astype(np.float32))
+    x = torch.randn(B, NBINS, device=dev).to(torch.bfloat16).view(torch.uint16)
+    y = (torch.arange(B, device=dev) % 2).float()
+    lg = torch.empty(B, dtype=torch.float32, device=dev)
+    ms_f = _events_ms(lambda: net.forward(x, out=lg), reps)
+    ms_t = _events_ms(lambda: net.train_step(x, y, 1e-5), reps)
+    tf = B * PNET_FWD_FLOP / ms_f / 1e9
+    net.close()
+    return {"row": "paper_network_bf16", "batch": B, "inference_ms": ms_f, "folds_per_s": B / ms_f * 1e3,
+            "tflops": tf, "peak_tflops": MFMA_BF16_PEAK_TFLOPS, "frac": tf / MFMA_BF16_PEAK_TFLOPS,
+            "train_step_ms": ms_t, "train_samples_per_s": B / ms_t * 1e3}
+
+
 def measure_rows(plan, t, f, pp, periods, survey_stars, learned_gain=True):
     """Each step of the path on its own at the benchmark shapes (and the
     many-star survey), with the roofline that bounds it."""
@@ -311,6 +349,7 @@ def measure_rows(plan, t, f, pp, periods, survey_stars, learned_gain=True):
                               "folds_scored_per_s": folds / wall,
                               "box_best_at_injected_period": f"{found}/{sum(1 for x in truth if x.get('has_transit'))}"}
         del r, sp, snet
+    rows["paper_network_bf16"] = pnet_rows(dev, 3)
     if learned_gain:
         # C3: the trained network against the box statistic, as the paper judges its network
         from paper_2312_02063_amd import learn
@@ -344,6 +383,10 @@ def main():
                     help="only the bf16 training step at batch 16,384 (for trace runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (HBM counter calibration)")
+    ap.add_argument("--eqcount-only", action="store_true",
+                    help="only the equal-count fold at 200,000 periods (for counter runs)")
+    ap.add_argument("--pnet-only", action="store_true",
+                    help="only the paper's 2-D network: inference and a training step")
     ap.add_argument("--roof", action="store_true",
                     help="only the roofline micro-benchmarks (LDS atomics, FP64 FMA, HBM copy)")
     args = ap.parse_args()
@@ -369,6 +412,12 @@ def main():
         return
     if args.train_only:
         print(json.dumps(cnn_training_row(dev, max(1, args.steps))), flush=True)
+        return
+    if args.eqcount_only:
+        print(json.dumps(eqcount_row(dev, max(1, args.steps))), flush=True)
+        return
+    if args.pnet_only:
+        print(json.dumps(pnet_rows(dev, max(1, args.steps))), flush=True)
         return
     c = synth.kepler_long_curve(seed=1002)
     assert c.t.size == N_SAMPLES

@@ -426,6 +426,9 @@ def main():
     ap.add_argument("--data", choices=("folds", "direct"), default="folds",
                     help="training set: kernel folds of synthetic curves, or vectors made directly "
                          "(noise + trapezoid at SNR 6-10, weak-transit and pure-noise negatives, cut 5)")
+    ap.add_argument("--compare-pnet", action="store_true",
+                    help="train the configured 1-D network and the paper's 2-D network and judge both "
+                         "with box-SNR on the same --eval held-out curves")
     ap.add_argument("--auc-vs-periods", type=str, default="",
                     help="comma-separated grid sizes: AUC of CNN and box-SNR per size (--eval curves)")
     args = ap.parse_args()
@@ -436,6 +439,10 @@ def main():
 
     periods = grid(args.periods)
     plan = Plan(0)
+    if args.compare_pnet:
+        res = compare_networks(plan, n_eval=args.eval, periods=periods, log=log)
+        print(json.dumps(res), flush=True)
+        return
     t0 = time.time()
     if args.data == "direct":
         z, y, _ = make_direct_set(args.train, args.train, seed=1003,
