@@ -1257,7 +1257,11 @@ __device__ __forceinline__ uint32_t mid_bin_ieee(double t, double P) {
 
 // One pass of the equal-count fold over `np` of the block's periods
 // (np = 4, one word; np = 2, two words: region 2 + p of the LDS histogram
-// holds period p's low words).
+// holds period p's low words). The four regions are interleaved by bin
+// (slot 4 b + region): lane = (record stream, region), so one 16-lane pass of
+// a 64-bit atomic carries 4 records x 4 regions, each record's four slots one
+// aligned 32-byte group of banks; only records whose bins agree mod 8 meet on
+// a bank (with one record per lane and random bins, 16 lanes did).
 template <bool kTwo>
 __device__ void eqcount_pass(uint64_t* hist, EqBoundary (*bnd)[kEqMaxBins + 1], int64_t* eqn,
                              const Rec* __restrict__ rec, const uint64_t* __restrict__ lo,
@@ -1267,10 +1271,10 @@ __device__ void eqcount_pass(uint64_t* hist, EqBoundary (*bnd)[kEqMaxBins + 1], 
     constexpr int np = kTwo ? kEqPeriods / 2 : kEqPeriods;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int pw = wave & (kEqPeriods - 1);           // the wave's histogram region
-    const int pp = kTwo ? (pw & 1) : pw;              // its period within the pass
-    const bool lo_word = kTwo && pw >= 2;
-    const int quarter = wave >> 2;                    // its share of the records
+    const int reg = lane & (kEqPeriods - 1);           // the lane's histogram region
+    const int pp = kTwo ? (reg & 1) : reg;             // its period within the pass
+    const bool lo_word = kTwo && reg >= 2;
+    const int strm = wave * 16 + (lane >> 2);          // its record stream (256 per block)
     for (int i = threadIdx.x; i < kEqPeriods * kMid; i += kThreads) hist[i] = 0;
     const int64_t kk = kbase + pp;
     double P = kk < k ? periods[kk] : 1.0;
@@ -1280,17 +1284,15 @@ __device__ void eqcount_pass(uint64_t* hist, EqBoundary (*bnd)[kEqMaxBins + 1], 
     const double zmax = info->tmax * rB;
     const uint32_t lim = zmax < 0x1p34 ? 65536u - 2u : 0u;
     __syncthreads();
-    uint64_t* h = hist + pw * kMid;
-    const int64_t per_q = (nrec + 3) / 4;
-    const int64_t i0 = quarter * per_q, i1 = min(nrec, i0 + per_q);
     if (valid) {
-        for (int64_t i = i0 + lane; i < i1; i += 64) {
+        for (int64_t i = strm; i < nrec; i += 256) {
             const Rec r = rec[i];
             const uint64_t c = lo_word ? lo[i] : r.c;
             const uint32_t lw = fast_lo(r.t, rB);   // the certified path, at 4096 bins
             uint32_t b = (lw >> 16) & (kMid - 1);
             if ((lw & 0xFFFFu) >= lim) b = mid_bin_ieee(r.t, P);
-            __hip_atomic_fetch_add(h + b, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(hist + b * kEqPeriods + reg, c, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
     __syncthreads();
@@ -1299,16 +1301,24 @@ __device__ void eqcount_pass(uint64_t* hist, EqBoundary (*bnd)[kEqMaxBins + 1], 
         const int64_t k2 = kbase + p2;
         const double P2 = k2 < k ? periods[k2] : 1.0;
         const bool v2 = k2 < k && P2 > 0.0 && isfinite(P2);
-        const uint64_t* hh = hist + p2 * kMid;
-        const uint64_t* hl = hist + (p2 + 2) * kMid;   // low words (kTwo)
-        // lane owns bins [64 lane, 64 lane + 64): its totals, then wave prefixes
+        // bin b of region r is hist[4 b + r]; lane owns bins [64 lane, 64 lane + 64)
+        const uint64_t* hh = hist + p2;
+        const uint64_t* hl = hist + p2 + 2;           // low words (kTwo)
+        auto bin_at = [&](int b, int64_t& c, int64_t& d, int64_t& dl) {
+            const uint64_t v = hh[b * kEqPeriods];
+            c = (int64_t)(v >> kCountShift);
+            d = (int64_t)(v & kSumMask) - c * kBias;
+            dl = kTwo ? (int64_t)(hl[b * kEqPeriods] & kSumMask) - c * kBias : 0;
+        };
+        // the lane's totals, its bins read from a lane-dependent start (integer
+        // sums: any order), so the lanes' reads spread over the banks
         int64_t lc = 0, ls = 0, ll = 0;
-        for (int b = lane * 64; b < lane * 64 + 64; ++b) {
-            const uint64_t v = hh[b];
-            const int64_t c = (int64_t)(v >> kCountShift);
+        for (int j = 0; j < 64; ++j) {
+            int64_t c, d, dl;
+            bin_at(lane * 64 + ((j + lane) & 63), c, d, dl);
             lc += c;
-            ls += (int64_t)(v & kSumMask) - c * kBias;
-            if (kTwo) ll += (int64_t)(hl[b] & kSumMask) - c * kBias;
+            ls += d;
+            ll += dl;
         }
         int64_t pc = lc, ps = ls, pl = ll;   // inclusive prefix over lanes
         for (int d = 1; d < 64; d <<= 1) {
@@ -1322,11 +1332,9 @@ __device__ void eqcount_pass(uint64_t* hist, EqBoundary (*bnd)[kEqMaxBins + 1], 
         int64_t C = pc - lc, S = ps - ls, SL = pl - ll;   // exclusive: before the lane's first bin
         if (v2 && N > 0) {
             for (int b = lane * 64; b < lane * 64 + 64; ++b) {
-                const uint64_t v = hh[b];
-                const int64_t c = (int64_t)(v >> kCountShift);
+                int64_t c, d, dl;
+                bin_at(b, c, d, dl);
                 if (c == 0) continue;
-                const int64_t d = (int64_t)(v & kSumMask) - c * kBias;
-                const int64_t dl = kTwo ? (int64_t)(hl[b] & kSumMask) - c * kBias : 0;
                 // the bin's deviation in units of the high word
                 const double dd = kTwo ? (double)d + ldexp((double)dl, -kLoBits) : (double)d;
                 const int64_t u0 = C * nbins, u1 = (C + c) * nbins;   // the bin's units
