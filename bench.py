@@ -309,9 +309,15 @@ def measure_rows(plan, t, f, pp, periods, survey_stars, learned_gain=True):
         ts = torch.tensor(np.concatenate([s.t for s in stars]), dtype=torch.float64, device=dev)
         fs = torch.tensor(np.concatenate([s.flux for s in stars]), dtype=torch.float32, device=dev)
         sp = Plan(0)
-        sp.survey_setup(so, ks, chunk_folds=4_000_000)
-        snet = Cnn(0, CNN_BF16, 1 << 20)
+        snet = Cnn(0, CNN_BF16, 1 << 21)
         snet.set_params(synth.cnn_init(1003).astype(np.float32))
+        # the survey's chunk and network pass sizes from the autotuner (gpfc_survey_autotune:
+        # 4 chunk sizes x 3 pass sizes timed on MI355X, kept in the shipped cache; a device or
+        # shape the cache does not hold is timed here)
+        tune_cache = os.path.join(ROOT, "paper_2312_02063_amd", "tune_mi355x.txt")
+        chunk, net_batch, tune_ms = sp.survey_autotune(
+            so, ts, fs, grid, NBINS, cnn=snet, chunks=(2_000_000, 4_000_000, 8_000_000, 16_000_000),
+            nets=(262_144, 1_048_576, 2_097_152), cache_path=tune_cache)
         r = sp.survey_run(ts, fs, grid, NBINS, cnn=snet, top=4, judge_snr=4.0)
         torch.cuda.synchronize()
         del r
@@ -345,6 +351,8 @@ def measure_rows(plan, t, f, pp, periods, survey_stars, learned_gain=True):
                 found += int(abs(p_best - tr["period"]) / tr["period"] < 2e-3)
         rows["a10_survey"] = {"stars": survey_stars, "periods_per_star": ks, "samples": int(so[-1]),
                               "seconds": wall, "timed": "graph replay", "eager_seconds": wall_eager,
+                              "chunk_folds": chunk, "network_pass": net_batch,
+                              "shape_from": "autotuner cache" if tune_ms < 0 else "autotuner timing",
                               "replay_equals_eager": replay_equal, "updates_per_s": upd / wall,
                               "folds_scored_per_s": folds / wall,
                               "box_best_at_injected_period": f"{found}/{sum(1 for x in truth if x.get('has_transit'))}"}

@@ -577,6 +577,29 @@ int32_t gpfc_survey_capture(gpfc_plan *plan, gpfc_cnn *cnn, const double *t, con
                             void *stream);
 
 /*
+ * Autotuner of the survey's shapes (the many-star batch of form 2): for every
+ * chunk size chunks_host[i] (folds per chunk, >= k with a network) and every
+ * network pass size nets_host[j] (inputs per network call, <= the network's
+ * max_batch; n_net = 0: the max_batch alone), sets the survey up (as
+ * gpfc_survey_setup with sample_offsets_host[n_curves + 1]) and times
+ * gpfc_survey_run with HIP events on `stream` (one warm-up run, one timed
+ * run, scratch outputs); keeps the fastest pair: the plan is left set up with
+ * that chunk size and later survey runs call the network with that pass size.
+ * A cache file (cache_path, else the plan's tune cache; NULL: none) holds
+ * lines "<device> survey <curves> <samples> <k> <nbins> <chunk> <net batch>";
+ * a cached shape is taken without timing, a new one appended. cnn NULL tunes
+ * nothing (one launch, no network). Synchronous; allocates 20 bytes per fold
+ * of scratch outputs while timing. chunk_out, net_out, ms_out: host, may be
+ * NULL (ms_out -1 when the shape came from the cache).
+ */
+int32_t gpfc_survey_autotune(gpfc_plan *plan, gpfc_cnn *cnn, const int64_t *sample_offsets_host,
+                             int32_t n_curves, const double *t, const float *flux,
+                             const double *periods, int64_t k, int32_t nbins,
+                             const int64_t *chunks_host, int32_t n_chunk, const int64_t *nets_host,
+                             int32_t n_net, const char *cache_path, int64_t *chunk_out,
+                             int64_t *net_out, float *ms_out, void *stream);
+
+/*
  * Roofline micro-benchmarks of the running GPU (the measured counterpart of
  * the paper's breakdown of where its GPU fold spends its time, Sec. 2.4,
  * Table 1): the denominators the fold's throughput is judged against.

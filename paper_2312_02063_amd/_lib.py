@@ -143,6 +143,10 @@ def load():
         "gpfc_fold_score_noalloc": ([vp, vp, i64, vp, i64, i32, vp, vp, vp, vp, vp], i32),
         "gpfc_detrend": ([vp, vp, vp, vp, i64, ctypes.POINTER(DetrendOpts), vp, vp,
                           ctypes.POINTER(DetrendInfo), vp], i32),
+        "gpfc_survey_autotune": ([vp, vp, ctypes.POINTER(ctypes.c_int64), i32, vp, vp, vp, i64, i32,
+                                  ctypes.POINTER(ctypes.c_int64), i32, ctypes.POINTER(ctypes.c_int64), i32,
+                                  ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_float), vp], i32),
         "gpfc_pnet_nparams": ([], i32),
         "gpfc_pnet_last_error": ([], ctypes.c_char_p),
         "gpfc_pnet_create": ([ctypes.POINTER(vp), i32, i32, i64], i32),
@@ -181,7 +185,7 @@ def exported_symbols():
             "gpfc_roof_probe", "gpfc_fold_score_noalloc", "gpfc_pnet_nparams", "gpfc_pnet_last_error",
             "gpfc_pnet_create", "gpfc_pnet_destroy", "gpfc_pnet_set_params", "gpfc_pnet_get_params",
             "gpfc_pnet_forward", "gpfc_pnet_backward", "gpfc_pnet_get_grads", "gpfc_pnet_adam",
-            "gpfc_detrend"]
+            "gpfc_detrend", "gpfc_survey_autotune"]
 
 
 ROOF_LDS_U64, ROOF_LDS_U32, ROOF_LDS_F32, ROOF_FP64_FMA, ROOF_HBM_COPY = 0, 1, 2, 3, 4
@@ -467,6 +471,30 @@ class Plan:
         self.survey_n = len(so) - 1
         self.survey_k = int(k)
         self.survey_samples = so[-1]
+
+    def survey_autotune(self, sample_offsets, t, flux, periods, nbins: int = 256, cnn=None,
+                        chunks=(2_000_000, 4_000_000, 8_000_000), nets=(), cache_path: str | None = None):
+        """Time the survey's chunk sizes and network pass sizes, keep the fastest
+        (the plan is left set up with it); returns (chunk, net_batch, ms)."""
+        import torch
+        _need(t, torch.float64, "t", self.device)
+        _need(flux, torch.float32, "flux", self.device)
+        _need(periods, torch.float64, "periods", self.device)
+        so = [int(x) for x in sample_offsets]
+        a = (ctypes.c_int64 * len(so))(*so)
+        ch = (ctypes.c_int64 * len(chunks))(*[int(c) for c in chunks])
+        nt = (ctypes.c_int64 * max(1, len(nets)))(*([int(v) for v in nets] or [0]))
+        co, no, ms = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_float(0.0)
+        _check(self.lib.gpfc_survey_autotune(self.h, cnn.h if cnn is not None else None, a, len(so) - 1,
+                                             _ptr(t), _ptr(flux), _ptr(periods), periods.numel(), nbins,
+                                             ch, len(chunks), nt, len(nets),
+                                             cache_path.encode() if cache_path else None,
+                                             ctypes.byref(co), ctypes.byref(no), ctypes.byref(ms),
+                                             _stream()), "gpfc_survey_autotune")
+        self.survey_n = len(so) - 1
+        self.survey_k = int(periods.numel())
+        self.survey_samples = so[-1]
+        return co.value, no.value, ms.value
 
     def _survey_args(self, t, flux, periods, cnn, top, judge_snr, fp8):
         import torch

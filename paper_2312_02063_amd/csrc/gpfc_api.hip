@@ -52,6 +52,7 @@ struct gpfc_plan {
     uint16_t* s_zbuf2 = nullptr;       // a second chunk buffer (several chunks: double buffering)
     int64_t s_zfolds = 0;              // folds s_zbuf holds (0: no workspace)
     hipStream_t s_net = nullptr;       // the network's stream in a pipelined survey
+    int64_t s_net_batch = 0;           // inputs per network call (0: the network's max_batch)
     hipEvent_t s_ev[4] = {};           // fold done / network done, per chunk buffer
     std::vector<SurveyChunk> s_chunks;
     // sample split of the single-curve fold + score (k_fold_score_split)
@@ -524,12 +525,13 @@ static bool cache_lookup(const char* path, const char* dev, int64_t n, int64_t k
     if (!path) return false;
     FILE* f = fopen(path, "r");
     if (!f) return false;
-    char name[64];
+    char line[512], name[64], extra[8];
     long long cn, ck;
     int cb, cs;
     bool found = false;
-    while (fscanf(f, "%63s %lld %lld %d %d", name, &cn, &ck, &cb, &cs) == 5)
-        if (!strcmp(name, dev) && cn == n && ck == k && cb == nbins && cs >= 1 && cs <= GPFC_MAX_SPLIT) {
+    while (fgets(line, sizeof(line), f))   // fold lines have exactly five fields
+        if (sscanf(line, "%63s %lld %lld %d %d %7s", name, &cn, &ck, &cb, &cs, extra) == 5 &&
+            !strcmp(name, dev) && cn == n && ck == k && cb == nbins && cs >= 1 && cs <= GPFC_MAX_SPLIT) {
             *split = cs;
             found = true;
         }
@@ -973,7 +975,8 @@ static int32_t survey_enqueue(gpfc_plan* p, gpfc_cnn* cnn, const double* t, cons
     const bool pipe = net && p->s_zbuf2 != nullptr;
     auto net_chunk = [&](const SurveyChunk& ch, const uint16_t* zb, hipStream_t ns) -> int32_t {
         const int64_t folds = (int64_t)(ch.c1 - ch.c0) * K;
-        const int64_t mb = gpfc::cnn_max_batch(cnn);
+        const int64_t cmb = gpfc::cnn_max_batch(cnn);
+        const int64_t mb = p->s_net_batch > 0 ? std::min(p->s_net_batch, cmb) : cmb;
         for (int64_t f0 = 0; f0 < folds; f0 += mb) {
             const int64_t B = std::min<int64_t>(mb, folds - f0);
             const uint16_t* x = zb + f0 * gpfc::kFineBins;
@@ -1121,6 +1124,109 @@ int32_t gpfc_batch_curve_stats(gpfc_plan* p, gpfc_curve* out, void* stream) {
 // hipGetSymbolAddress reports on that device (the array's name is only a host
 // stand-in and is never passed to a kernel). Layout: CurveInfo at 0, records
 // at 256, low words after the records.
+// Cache lines of the survey tuner: "<device> survey <curves> <samples> <k> <nbins> <chunk> <net batch>".
+static bool survey_cache_lookup(const char* path, const char* dev, int32_t n_curves, int64_t samples,
+                                int64_t k, int32_t nbins, int64_t* chunk, int64_t* net) {
+    if (!path) return false;
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[512], name[64], tag[16];
+    long long cc, cs, ck, ch, cn;
+    int cb;
+    bool found = false;
+    while (fgets(line, sizeof(line), f))
+        if (sscanf(line, "%63s %15s %lld %lld %lld %d %lld %lld", name, tag, &cc, &cs, &ck, &cb, &ch,
+                   &cn) == 8 &&
+            !strcmp(name, dev) && !strcmp(tag, "survey") && cc == n_curves && cs == samples && ck == k &&
+            cb == nbins && ch >= 0 && cn >= 0) {
+            *chunk = ch;
+            *net = cn;
+            found = true;
+        }
+    fclose(f);
+    return found;
+}
+
+int32_t gpfc_survey_autotune(gpfc_plan* p, gpfc_cnn* cnn, const int64_t* soff, int32_t n_curves,
+                             const double* t, const float* flux, const double* periods, int64_t k,
+                             int32_t nbins, const int64_t* chunks, int32_t n_chunk, const int64_t* nets,
+                             int32_t n_net, const char* cache_path, int64_t* chunk_out,
+                             int64_t* net_out, float* ms_out, void* stream) {
+    if (!p || !soff || n_curves < 1 || k < 1 || !chunks || n_chunk < 1 || n_chunk > 16 || n_net < 0 ||
+        n_net > 16 || (n_net > 0 && !nets) || !t || !flux || !periods)
+        return GPFC_EINVAL;
+    if (!pow2_in_range(nbins) || nbins > gpfc::kFineBins) return GPFC_ENOTSUP;
+    if (cnn && nbins != gpfc::kFineBins) return GPFC_EINVAL;
+    const int64_t cmb = cnn ? gpfc::cnn_max_batch(cnn) : 0;
+    for (int i = 0; i < n_chunk; ++i)
+        if (chunks[i] < (cnn ? k : 0)) return GPFC_EINVAL;
+    for (int i = 0; i < n_net; ++i)
+        if (nets[i] < 1 || nets[i] > cmb) return GPFC_EINVAL;
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return device_error(e, "hipSetDevice");
+    if (!cache_path && p->tune_cache[0]) cache_path = p->tune_cache;
+    const int64_t samples = soff[n_curves];
+    int64_t best_c = chunks[0], best_n = n_net > 0 ? nets[0] : 0;
+    float best_ms = -1.0f;
+    if (!survey_cache_lookup(cache_path, p->device_name, n_curves, samples, k, nbins, &best_c, &best_n)) {
+        hipStream_t s = (hipStream_t)stream;
+        const int64_t m = (int64_t)n_curves * k;
+        void* out = nullptr;
+        e = hipMalloc(&out, (size_t)m * 20);
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? GPFC_ENOMEM : device_error(e, "hipMalloc");
+        gpfc_survey_out o{};
+        o.snr = (float*)out;
+        o.start = (int32_t*)(o.snr + m);
+        o.width = o.start + m;
+        o.depth = (float*)(o.width + m);
+        o.logits = cnn ? o.depth + m : nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        int32_t rc = GPFC_OK;
+        const int nn = n_net > 0 ? n_net : 1;
+        for (int ci = 0; ci < n_chunk && rc == GPFC_OK && e == hipSuccess; ++ci) {
+            rc = gpfc_survey_setup(p, soff, n_curves, k, cnn ? chunks[ci] : 0);
+            for (int ni = 0; ni < nn && rc == GPFC_OK && e == hipSuccess; ++ni) {
+                p->s_net_batch = n_net > 0 ? nets[ni] : 0;
+                rc = survey_enqueue(p, cnn, t, flux, periods, nbins, o, s);   // warm-up
+                if (rc == GPFC_OK) e = hipEventRecord(e0, s);
+                if (rc == GPFC_OK && e == hipSuccess) rc = survey_enqueue(p, cnn, t, flux, periods, nbins, o, s);
+                if (rc == GPFC_OK && e == hipSuccess) e = hipEventRecord(e1, s);
+                if (rc == GPFC_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.0f;
+                if (rc == GPFC_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (rc == GPFC_OK && e == hipSuccess && (best_ms < 0.0f || ms < best_ms)) {
+                    best_ms = ms;
+                    best_c = chunks[ci];
+                    best_n = p->s_net_batch;
+                }
+            }
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(out);
+        if (rc != GPFC_OK) return rc;
+        if (e != hipSuccess) return device_error(e, "survey autotune");
+        if (cache_path) {
+            FILE* f = fopen(cache_path, "a");
+            if (f) {
+                fprintf(f, "%s survey %d %lld %lld %d %lld %lld\n", p->device_name, n_curves,
+                        (long long)samples, (long long)k, nbins, (long long)best_c, (long long)best_n);
+                fclose(f);
+            }
+        }
+    }
+    const int32_t rc = gpfc_survey_setup(p, soff, n_curves, k, cnn ? best_c : 0);
+    if (rc != GPFC_OK) return rc;
+    p->s_net_batch = best_n;
+    if (chunk_out) *chunk_out = best_c;
+    if (net_out) *net_out = best_n;
+    if (ms_out) *ms_out = best_ms;
+    return GPFC_OK;
+}
+
 int32_t gpfc_fold_score_noalloc(const double* t, const float* flux, int64_t n,
                                 const double* periods, int64_t k, int32_t nbins, float* snr,
                                 int32_t* start, int32_t* width, float* depth, void* stream) {

@@ -311,3 +311,35 @@ def test_survey_replay_uses_current_weights(torch_dev):
     torch.cuda.synchronize()
     assert torch.equal(gr["logits"], er["logits"])
     assert torch.equal(gr["cnn_idx"], er["cnn_idx"])
+
+
+def test_survey_autotune_keeps_results_and_caches(torch_dev, tmp_path):
+    """The survey tuner times chunk sizes x network pass sizes, leaves the plan
+    set up with the fastest; a survey with the tuned shape equals one with any
+    other shape bit for bit, and a second call takes the shape from the cache."""
+    from paper_2312_02063_amd import Plan
+    torch = torch_dev
+    stars = _stars(9, seed=41)
+    k = 333
+    net = _net(torch, max_batch=2048)
+    periods = synth.freq_grid(1.0, 5.0, k)
+    so = np.concatenate([[0], np.cumsum([s.t.size for s in stars])]).astype(np.int64)
+    t = _dev(torch, np.concatenate([s.t for s in stars]), torch.float64)
+    f = _dev(torch, np.concatenate([s.flux for s in stars]), torch.float32)
+    p = _dev(torch, periods, torch.float64)
+    cache = str(tmp_path / "tune.txt")
+    plan = Plan(0)
+    _say("survey autotune: 3 chunk sizes x 2 network pass sizes")
+    c, nb, ms = plan.survey_autotune(so, t, f, p, 256, cnn=net, chunks=(333, 999, 3000), nets=(512, 2048),
+                                     cache_path=cache)
+    assert c in (333, 999, 3000) and nb in (512, 2048) and ms > 0
+    r = plan.survey_run(t, f, p, 256, cnn=net, top=4, judge_snr=3.0)
+    _, ref, _ = _survey(torch, stars, k, 999, net=net, top=4, judge=3.0)
+    torch.cuda.synchronize()
+    for key in ("snr", "logits", "box_idx", "cnn_idx", "judged_idx"):
+        assert np.array_equal(r[key].cpu().numpy(), ref[key]), key
+    again = Plan(0)
+    c2, nb2, ms2 = again.survey_autotune(so, t, f, p, 256, cnn=net, chunks=(333, 999, 3000),
+                                         nets=(512, 2048), cache_path=cache)
+    assert (c2, nb2, ms2) == (c, nb, -1.0)
+    assert open(cache).read().count(" survey ") == 1
