@@ -457,6 +457,12 @@ int32_t gpfc_pnet_nparams(void);
 const char *gpfc_pnet_last_error(void);
 int32_t gpfc_pnet_create(gpfc_pnet **out, int32_t device, int32_t precision, int64_t max_batch);
 int32_t gpfc_pnet_destroy(gpfc_pnet *net);
+/*
+ * bf16 forward path: on = 1 (default) runs each convolution pair as one fused
+ * kernel per input (activation tile in LDS, pooling in the epilogue); on = 0
+ * layer by layer through HBM. Same results bit for bit.
+ */
+int32_t gpfc_pnet_set_fused(gpfc_pnet *net, int32_t on);
 /* Copy in FP32 parameters (device, flat order above); resets Adam. */
 int32_t gpfc_pnet_set_params(gpfc_pnet *net, const float *params, void *stream);
 int32_t gpfc_pnet_get_params(gpfc_pnet *net, float *params, void *stream);

@@ -151,6 +151,7 @@ def load():
         "gpfc_pnet_last_error": ([], ctypes.c_char_p),
         "gpfc_pnet_create": ([ctypes.POINTER(vp), i32, i32, i64], i32),
         "gpfc_pnet_destroy": ([vp], i32),
+        "gpfc_pnet_set_fused": ([vp, i32], i32),
         "gpfc_pnet_set_params": ([vp, vp, vp], i32),
         "gpfc_pnet_get_params": ([vp, vp, vp], i32),
         "gpfc_pnet_forward": ([vp, vp, i32, i64, vp, vp], i32),
@@ -183,7 +184,7 @@ def exported_symbols():
             "gpfc_autotune", "gpfc_fold_eqcount_prepared", "gpfc_periodogram_peaks", "gpfc_survey_setup", "gpfc_survey_run",
             "gpfc_survey_capture", "gpfc_cnn_train_step", "gpfc_cnn_save", "gpfc_cnn_load",
             "gpfc_roof_probe", "gpfc_fold_score_noalloc", "gpfc_pnet_nparams", "gpfc_pnet_last_error",
-            "gpfc_pnet_create", "gpfc_pnet_destroy", "gpfc_pnet_set_params", "gpfc_pnet_get_params",
+            "gpfc_pnet_create", "gpfc_pnet_destroy", "gpfc_pnet_set_fused", "gpfc_pnet_set_params", "gpfc_pnet_get_params",
             "gpfc_pnet_forward", "gpfc_pnet_backward", "gpfc_pnet_get_grads", "gpfc_pnet_adam",
             "gpfc_detrend", "gpfc_survey_autotune"]
 
@@ -839,6 +840,10 @@ class PNet:
         out = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
         _check(self.lib.gpfc_pnet_get_params(self.h, _ptr(out), _stream()), "gpfc_pnet_get_params")
         return out
+
+    def set_fused(self, on: bool):
+        """bf16 forward: fused convolution pairs (default) or layer by layer."""
+        _check(self.lib.gpfc_pnet_set_fused(self.h, int(bool(on))), "gpfc_pnet_set_fused")
 
     def get_grads(self):
         import torch

@@ -232,6 +232,150 @@ __global__ __launch_bounds__(128) void k_head(const typename P::T* __restrict__ 
     }
 }
 
+// Fused pair for bf16 networks: one input per block of 8 waves. The
+// one-channel convolution (KS1 x KS1, 128 filters, ReLU) writes the input's
+// whole activation tile (256 positions x 128 channels bf16, 64 KB) into LDS,
+// rows XOR-swizzled by 16-byte chunk (chunk ^ (position & 15)), optionally
+// also to HBM for the backward pass; the wide convolution (KS2 x KS2, 256
+// filters) then runs on the matrix cores with A fragments from that tile (the
+// tap's circular shift applied to the position) and B fragments from k-chunks
+// of 32 weights per filter staged in LDS (double-buffered, rows of 96 bytes:
+// a 32 mod 64-byte stride keeps the fragment reads conflict-free), each chunk
+// loaded while the previous one is multiplied. Waves: 2 (positions, 128 rows
+// each) x 4 (filters, 64 columns each). The epilogue pools as the layer
+// path's EpGmax does (same MFMA chains in the same k order, same keys), through
+// 64-bit LDS atomic maxima, and writes the pooled values and positions: the
+// result equals the layer path's bit for bit.
+constexpr int kPairThreads = 512;
+constexpr int kBRow = 48;   // staged weight row: 32 bf16 + 16 of padding (96 bytes)
+
+template <int KS1, int KS2, bool kWrite>
+__global__ __launch_bounds__(kPairThreads, 1) void k_pair_bf16(
+    const void* __restrict__ x, int in_f32, const float* __restrict__ w1,
+    const float* __restrict__ b1, const uint16_t* __restrict__ w2p, const float* __restrict__ b2,
+    uint16_t* __restrict__ g, int32_t* __restrict__ arg, uint16_t* __restrict__ act) {
+    constexpr int K = KS2 * KS2 * 128;
+    constexpr int NK = K / 32;
+    constexpr int p1 = (KS1 - 1) / 2, p2 = (KS2 - 1) / 2;
+    __shared__ __attribute__((aligned(16))) uint16_t At[NPOS * 128];
+    __shared__ __attribute__((aligned(16))) uint16_t Bt[2][256 * kBRow];
+    __shared__ float img[NPOS];
+    __shared__ float ws[128 * KS1 * KS1];
+    __shared__ float bs[128];
+    __shared__ unsigned long long keys[256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, q = lane >> 4;
+    const int64_t inp = blockIdx.x;
+    if (tid < NPOS) img[tid] = in_val<BF16>(x, in_f32, inp * NPOS + tid);
+    for (int i = tid; i < 128 * KS1 * KS1; i += kPairThreads) ws[i] = w1[i];
+    if (tid < 128) bs[tid] = b1[tid];
+    if (tid < 256) keys[tid] = 0ull;
+    // the first weight chunk into registers: thread t stages half (t & 1) of filter t >> 1
+    const int bn = tid >> 1, bh = tid & 1;
+    const uint4* bsrc = reinterpret_cast<const uint4*>(w2p + (int64_t)bn * K + 16 * bh);
+    uint4 pf0 = bsrc[0], pf1 = bsrc[1];
+    __syncthreads();
+    // one-channel convolution + ReLU: thread t computes channels 64 (t & 1) .. + 63 at position t >> 1
+    {
+        const int pos = tid >> 1, h = tid & 1;
+        const int rr = pos >> 4, cc = pos & 15;
+        float v[KS1 * KS1];
+#pragma unroll
+        for (int u = 0; u < KS1; ++u)
+#pragma unroll
+            for (int w = 0; w < KS1; ++w) v[u * KS1 + w] = img[wrap16(rr + u - p1) * S + wrap16(cc + w - p1)];
+        for (int f0 = 64 * h; f0 < 64 * h + 64; f0 += 8) {
+            float a8[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                float a = bs[f0 + j];
+#pragma unroll
+                for (int t = 0; t < KS1 * KS1; ++t) a += ws[(f0 + j) * KS1 * KS1 + t] * v[t];
+                a8[j] = fmaxf(a, 0.0f);
+            }
+            uint4 pk;
+            pk.x = gcnn::f2bf2(a8[0], a8[1]);
+            pk.y = gcnn::f2bf2(a8[2], a8[3]);
+            pk.z = gcnn::f2bf2(a8[4], a8[5]);
+            pk.w = gcnn::f2bf2(a8[6], a8[7]);
+            const int chunk = f0 >> 3;
+            *reinterpret_cast<uint4*>(At + pos * 128 + ((chunk ^ (pos & 15)) << 3)) = pk;
+            if (kWrite) *reinterpret_cast<uint4*>(act + (inp * NPOS + pos) * 128 + f0) = pk;
+        }
+    }
+    {
+        uint4* d = reinterpret_cast<uint4*>(&Bt[0][bn * kBRow + 16 * bh]);
+        d[0] = pf0;
+        d[1] = pf1;
+    }
+    __syncthreads();
+    const int wm = wave & 1, wn = wave >> 1;
+    f32x4 acc[8][4];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    int cur = 0;
+    for (int s = 0; s < NK; ++s) {
+        if (s + 1 < NK) {
+            pf0 = bsrc[4 * (s + 1)];
+            pf1 = bsrc[4 * (s + 1) + 1];
+        }
+        const int tap = s >> 2;
+        const int du = tap / KS2 - p2, dv = tap % KS2 - p2;
+        const int chunk = ((s & 3) << 2) + q;
+        bf16x8 bfr[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            bfr[j] = *reinterpret_cast<const bf16x8*>(&Bt[cur][(wn * 64 + j * 16 + r) * kBRow + q * 8]);
+        const int qc = wrap16(r + dv);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int qpos = wrap16(wm * 8 + i + du) * S + qc;
+            const bf16x8 afr =
+                *reinterpret_cast<const bf16x8*>(At + qpos * 128 + ((chunk ^ (qpos & 15)) << 3));
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr[j], acc[i][j], 0, 0, 0);
+        }
+        if (s + 1 < NK) {
+            uint4* d = reinterpret_cast<uint4*>(&Bt[cur ^ 1][bn * kBRow + 16 * bh]);
+            d[0] = pf0;
+            d[1] = pf1;
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    // pool: each column's first maximum over the block's 256 positions
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int n = wn * 64 + j * 16 + r;
+        const float bb = b2[n];
+        uint64_t best = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint64_t kq = pool_key(acc[i][j][e] + bb, wm * 128 + i * 16 + 4 * q + e);
+                best = kq > best ? kq : best;
+            }
+        uint64_t o = __shfl_xor(best, 16);
+        best = o > best ? o : best;
+        o = __shfl_xor(best, 32);
+        best = o > best ? o : best;
+        if (q == 0) atomicMax(&keys[n], (unsigned long long)best);
+    }
+    __syncthreads();
+    if (tid < 256) {
+        const uint64_t k = keys[tid];
+        const float z = ord_float((uint32_t)(k >> 32));
+        const int pos = (int)(0xffffffffu - (uint32_t)k);
+        const bool ok = z > 0.0f;
+        g[inp * 256 + tid] = gcnn::f2bf(ok ? z : 0.0f);
+        arg[inp * 256 + tid] = ok ? pos : -1;
+    }
+}
+
 // ------------------------------------------------------------------ backward
 
 // Output layer and dense layer, one block of 256 threads per input: the
@@ -282,6 +426,20 @@ __global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ part, 
     out[c] = a * scale;
 }
 
+// First stage of a column sum over many rows: rows cut into gridDim.y fixed
+// chunks, each summed in order (the second stage, k_colsum over the chunks,
+// adds them in chunk order: a fixed order, so the result is deterministic).
+__global__ __launch_bounds__(256) void k_colsum_parts(const float* __restrict__ part, int64_t B, int ncol,
+                                                      float* __restrict__ out) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= ncol) return;
+    const int64_t per = (B + gridDim.y - 1) / gridDim.y;
+    const int64_t b0 = (int64_t)blockIdx.y * per, b1 = b0 + per < B ? b0 + per : B;
+    float a = 0.0f;
+    for (int64_t b = b0; b < b1; ++b) a += part[b * ncol + c];
+    out[(int64_t)blockIdx.y * ncol + c] = a;
+}
+
 // dW5[j][f] = sum_b dh[b][j] g2[b][f], batch in order; one thread per weight.
 template <class P>
 __global__ __launch_bounds__(256) void k_w5_grad(const float* __restrict__ dh,
@@ -296,10 +454,13 @@ __global__ __launch_bounds__(256) void k_w5_grad(const float* __restrict__ dh,
 }
 
 // Weight and bias gradients of a wide convolution from the routed pool
-// gradient: for filter f (one block), dW[f][i][u][v] = sum_b dg[b][f]
-// act[b][arg[b][f] + (u-p, v-p)][i] over the inputs whose pooled value is
-// positive, in input order; db[f] = sum_b dg[b][f] over the same inputs.
-// Threads take (u, v, i) with i fastest (coalesced channel rows).
+// gradient: for filter f (block x) and a chunk of the batch (block y),
+// dW[f][i][u][v] = sum_b dg[b][f] act[b][arg[b][f] + (u-p, v-p)][i] over the
+// chunk's inputs whose pooled value is positive, in input order; db[f] =
+// sum_b dg[b][f] over the same inputs. Chunk y writes its part at
+// dw + y (F NE + F) in the parameter layout (weights, then biases); the parts
+// are added in chunk order afterwards. Threads take (u, v, i) with i fastest
+// (coalesced channel rows).
 template <class P, int KS>
 __global__ __launch_bounds__(256) void k_wide_dw(const typename P::T* __restrict__ act,
                                                  const float* __restrict__ dg,
@@ -310,6 +471,12 @@ __global__ __launch_bounds__(256) void k_wide_dw(const typename P::T* __restrict
     constexpr int PER = (NE + 255) / 256;
     const int f = blockIdx.x;
     const int tid = threadIdx.x;
+    // batch part blockIdx.y of gridDim.y (fixed chunks of inputs, each in order)
+    const int64_t per_part = (B + gridDim.y - 1) / gridDim.y;
+    const int64_t bb0 = (int64_t)blockIdx.y * per_part;
+    const int64_t bb1 = bb0 + per_part < B ? bb0 + per_part : B;
+    dw += (int64_t)blockIdx.y * ((int64_t)gridDim.x * NE + gridDim.x);
+    db = dw + (int64_t)gridDim.x * NE;
     float acc[PER];
     int off[PER];
 #pragma unroll
@@ -321,7 +488,7 @@ __global__ __launch_bounds__(256) void k_wide_dw(const typename P::T* __restrict
         if (e >= NE) off[j] = -1;
     }
     float bsum = 0.0f;
-    for (int64_t b = 0; b < B; ++b) {
+    for (int64_t b = bb0; b < bb1; ++b) {
         const int a = arg[b * 256 + f];
         if (a < 0) continue;
         const float g = dg[b * 256 + f];
@@ -371,30 +538,66 @@ __global__ __launch_bounds__(1024) void k_conv_bwd(
     __shared__ float gsc[256];
     __shared__ int32_t asc[256];
     __shared__ float dg1s[256];
+    __shared__ int32_t hoff[NPOS + 1];     // per position: its (filter, tap) list in ent
+    __shared__ int32_t ent[256 * K2 * K2];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t inp = blockIdx.x;
     using T = typename P::T;
 
-    // scatter of a wide convolution's routed gradient into da (zeroed first)
+    // Scatter of a wide convolution's routed gradient into da: filter f adds
+    // dg[f] w[f][i][u][v] at position arg[f] + (u - p, v - p). Each position
+    // first lists, in filter order, the (filter, tap) pairs that reach it
+    // (thread per position; a block scan turns the counts into offsets); then
+    // a wave takes (position, 64 channels) and sums its list in registers, so
+    // every da[q][i] is one sum over the filters in order and no two threads
+    // write the same element.
     auto scatter = [&](const float* gsrc, const int32_t* asrc, const T* wp, int ks) {
-        for (int i = tid; i < NPOS * 128; i += 1024) da[i] = 0.0f;
         if (tid < 256) { gsc[tid] = gsrc[tid]; asc[tid] = asrc[tid]; }
         __syncthreads();
         const int p = (ks - 1) / 2, ne = ks * ks * 128;
-        for (int f = 0; f < 256; ++f) {
-            const int a = asc[f];
-            if (a < 0) continue;   // uniform over the block
-            const float g = gsc[f];
-            const int ar = a >> 4, ac = a & 15;
-            const T* wr = wp + (int64_t)f * ne;
-            for (int e = tid; e < ne; e += 1024) {
-                const int tap = e >> 7, i = e & 127;
-                const int u = tap / ks, v = tap - u * ks;
-                const int q = wrap16(ar + u - p) * S + wrap16(ac + v - p);
-                da[q * 128 + i] += g * P::to_f(wr[e]);
+        int cnt = 0;
+        const int qr = tid >> 4, qc = tid & 15;
+        if (tid < NPOS)
+            for (int f = 0; f < 256; ++f) {
+                const int a = asc[f];
+                if (a < 0) continue;
+                const int u = (qr - (a >> 4) + p) & 15, v = (qc - (a & 15) + p) & 15;
+                cnt += (u < ks && v < ks);
             }
-            __syncthreads();   // the next filter may touch the same positions
+        // exclusive prefix of the 256 counts (waves 0-3), offsets in hoff
+        int incl = cnt;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int o = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += o;
         }
+        if (tid < NPOS && lane == 63) hoff[wave] = incl;   // per-wave totals, briefly
+        __syncthreads();
+        int wbase = 0;
+        for (int w = 0; w < wave && w < 4; ++w) wbase += hoff[w];
+        __syncthreads();
+        if (tid < NPOS) {
+            int o = wbase + incl - cnt;
+            hoff[tid] = o;
+            if (tid == NPOS - 1) hoff[NPOS] = o + cnt;
+            for (int f = 0; f < 256; ++f) {
+                const int a = asc[f];
+                if (a < 0) continue;
+                const int u = (qr - (a >> 4) + p) & 15, v = (qc - (a & 15) + p) & 15;
+                if (u < ks && v < ks) ent[o++] = (f << 8) | (u * ks + v);
+            }
+        }
+        __syncthreads();
+        for (int task = wave; task < 2 * NPOS; task += 16) {
+            const int q = task >> 1, i = ((task & 1) << 6) + lane;
+            float acc = 0.0f;
+            for (int e = hoff[q]; e < hoff[q + 1]; ++e) {
+                const int en = ent[e];
+                const int f = en >> 8, tap = en & 255;
+                acc += gsc[f] * P::to_f(wp[(int64_t)f * ne + tap * 128 + i]);
+            }
+            da[q * 128 + i] = acc;
+        }
+        __syncthreads();
     };
 
     // 1-2: second pair
@@ -550,7 +753,10 @@ struct gpfc_pnet {
     float* part1 = nullptr;       // [B][1280]
     float* part3 = nullptr;       // [B][3328]
     float* scalar = nullptr;      // the mean loss
+    float* cparts = nullptr;      // [64][3328] chunk sums of the per-input gradient parts
+    float* dwparts = nullptr;     // [16][F4 K2 K2 F3 + F4] batch-chunk parts of a wide weight gradient
     bool packed = false;
+    bool fused = true;            // bf16: the fused pair kernels (false: layer by layer)
 };
 
 namespace {
@@ -563,6 +769,9 @@ int32_t pnet_err(hipError_t e, const char* what) {
 }
 
 size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+constexpr int kColParts = 64;   // first-stage chunks of a column sum over the batch
+constexpr int kDwParts = 16;    // batch chunks of a wide convolution's weight gradient
 
 template <class P>
 hipError_t pack(gpfc_pnet* n, hipStream_t s) {
@@ -585,6 +794,30 @@ hipError_t forward(gpfc_pnet* n, const void* x, int in_f32, int64_t B, const flo
     using T = typename P::T;
     const float* r = n->rest;
     const unsigned nb = (unsigned)B;
+    if constexpr (sizeof(T) == 2) {
+        if (n->fused) {
+            const uint16_t* w2 = (const uint16_t*)n->w2p;
+            const uint16_t* w4 = (const uint16_t*)n->w4p;
+            uint16_t* g1 = (uint16_t*)n->g1;
+            uint16_t* g2 = (uint16_t*)n->g2;
+            if (training) {
+                hipLaunchKernelGGL((k_pair_bf16<K1, K1, true>), dim3(nb), dim3(kPairThreads), 0, s, x, in_f32,
+                                   r + W1, r + B1, w2, r + B2, g1, n->arg1, (uint16_t*)n->a1);
+                hipLaunchKernelGGL((k_pair_bf16<K2, K2, true>), dim3(nb), dim3(kPairThreads), 0, s,
+                                   (const void*)g1, 0, r + W3, r + B3, w4, r + B4, g2, n->arg2,
+                                   (uint16_t*)n->a3);
+            } else {
+                hipLaunchKernelGGL((k_pair_bf16<K1, K1, false>), dim3(nb), dim3(kPairThreads), 0, s, x, in_f32,
+                                   r + W1, r + B1, w2, r + B2, g1, n->arg1, (uint16_t*)nullptr);
+                hipLaunchKernelGGL((k_pair_bf16<K2, K2, false>), dim3(nb), dim3(kPairThreads), 0, s,
+                                   (const void*)g1, 0, r + W3, r + B3, w4, r + B4, g2, n->arg2,
+                                   (uint16_t*)nullptr);
+            }
+            hipLaunchKernelGGL(k_head<P>, dim3(nb), dim3(128), 0, s, (const T*)n->g2, r + W5, r + B5, r + W6,
+                               r + B6, keep, training ? n->h : nullptr, logits);
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL((k_conv1ch<P, K1, F1>), dim3(nb), dim3(256), 0, s, x, in_f32, r + W1, r + B1,
                        (T*)n->a1);
     const int64_t nk = B * 256;
@@ -630,23 +863,36 @@ hipError_t backward(gpfc_pnet* n, const void* x, int in_f32, const float* labels
     float* g = n->grad;
     hipLaunchKernelGGL(k_head_bwd, dim3(nb), dim3(256), 0, s, logits_tmp, labels, n->h, keep, r + W5,
                        r + W6, B, n->lossp, n->dz, n->dw6p, n->dh, n->dg2);
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, s, n->lossp, B, 1, n->scalar, 1.0f / (float)B);
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, s, n->dw6p, B, H, g + W6, 1.0f);
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, s, n->dh, B, H, g + B5, 1.0f);
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, s, n->dz, B, 1, g + B6, 1.0f);
+    // column sums over the batch: fixed chunks summed in order, then the chunks in order
+    const int np = (int)std::min<int64_t>(kColParts, B);
+    auto colsum = [&](const float* part, int ncol, float* dst, float scale) {
+        const unsigned cb = (unsigned)((ncol + 255) / 256);
+        hipLaunchKernelGGL(k_colsum_parts, dim3(cb, (unsigned)np), dim3(256), 0, s, part, B, ncol, n->cparts);
+        hipLaunchKernelGGL(k_colsum, dim3(cb), dim3(256), 0, s, (const float*)n->cparts, (int64_t)np, ncol,
+                           dst, scale);
+    };
+    colsum(n->lossp, 1, n->scalar, 1.0f / (float)B);
+    colsum(n->dw6p, H, g + W6, 1.0f);
+    colsum(n->dh, H, g + B5, 1.0f);
+    colsum(n->dz, 1, g + B6, 1.0f);
     hipLaunchKernelGGL(k_w5_grad<P>, dim3(H * F4 / 256), dim3(256), 0, s, n->dh, (const T*)n->g2, B,
                        g + W5);
-    hipLaunchKernelGGL((k_wide_dw<P, K2>), dim3(F4), dim3(256), 0, s, (const T*)n->a3, n->dg2, n->arg2,
-                       B, g + W4, g + B4);
+    // wide convolutions' weight gradients: batch chunks in parallel, then the chunks in order
+    const int nd = (int)std::min<int64_t>(kDwParts, B);
+    const int n4 = F4 * F3 * K2 * K2 + F4, n2 = F2 * F1 * K1 * K1 + F2;
+    hipLaunchKernelGGL((k_wide_dw<P, K2>), dim3(F4, (unsigned)nd), dim3(256), 0, s, (const T*)n->a3, n->dg2,
+                       n->arg2, B, n->dwparts, (float*)nullptr);
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s,
+                       (const float*)n->dwparts, (int64_t)nd, n4, g + W4, 1.0f);
     hipLaunchKernelGGL(k_conv_bwd<P>, dim3(nb), dim3(1024), 0, s, x, in_f32, (const T*)n->a1,
                        (const T*)n->g1, n->arg1, (const T*)n->a3, n->dg2, n->arg2, (const T*)n->w2p,
                        r + W3, (const T*)n->w4p, n->dg1, n->part3, n->part1);
-    hipLaunchKernelGGL((k_wide_dw<P, K1>), dim3(F2), dim3(256), 0, s, (const T*)n->a1, n->dg1, n->arg1,
-                       B, g + W2, g + B2);
-    hipLaunchKernelGGL(k_colsum, dim3((F3 * K2 * K2 + F3 + 255) / 256), dim3(256), 0, s, n->part3, B,
-                       F3 * K2 * K2 + F3, g + W3, 1.0f);
-    hipLaunchKernelGGL(k_colsum, dim3((F1 * K1 * K1 + F1 + 255) / 256), dim3(256), 0, s, n->part1, B,
-                       F1 * K1 * K1 + F1, g + W1, 1.0f);
+    hipLaunchKernelGGL((k_wide_dw<P, K1>), dim3(F2, (unsigned)nd), dim3(256), 0, s, (const T*)n->a1, n->dg1,
+                       n->arg1, B, n->dwparts, (float*)nullptr);
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s,
+                       (const float*)n->dwparts, (int64_t)nd, n2, g + W2, 1.0f);
+    colsum(n->part3, F3 * K2 * K2 + F3, g + W3, 1.0f);
+    colsum(n->part1, F1 * K1 * K1 + F1, g + W1, 1.0f);
     return hipGetLastError();
 }
 
@@ -688,7 +934,8 @@ int32_t gpfc_pnet_create(gpfc_pnet** out, int32_t device, int32_t precision, int
         al256((size_t)B * 256 * 4), al256((size_t)B * 256 * 4),                        // dg1 dg2
         al256((size_t)B * 4), al256((size_t)B * 4),                                    // dz lossp
         al256((size_t)B * (F1 * K1 * K1 + F1) * 4), al256((size_t)B * (F3 * K2 * K2 + F3) * 4),
-        256};
+        256, al256((size_t)kColParts * (F3 * K2 * K2 + F3) * 4),
+        al256((size_t)kDwParts * ((size_t)F4 * F3 * K2 * K2 + F4) * 4)};
     size_t total = 0;
     for (size_t z : sizes) total += z;
     e = hipMalloc(&n->mem, total);
@@ -723,6 +970,8 @@ int32_t gpfc_pnet_create(gpfc_pnet** out, int32_t device, int32_t precision, int
     n->part1 = (float*)take();
     n->part3 = (float*)take();
     n->scalar = (float*)take();
+    n->cparts = (float*)take();
+    n->dwparts = (float*)take();
     e = hipMemset(n->mem, 0, total);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -731,6 +980,12 @@ int32_t gpfc_pnet_create(gpfc_pnet** out, int32_t device, int32_t precision, int
         return pnet_err(e, "hipMemset");
     }
     *out = n;
+    return GPFC_OK;
+}
+
+int32_t gpfc_pnet_set_fused(gpfc_pnet* n, int32_t on) {
+    if (!n || on < 0 || on > 1) return GPFC_EINVAL;
+    n->fused = on != 0;
     return GPFC_OK;
 }
 

@@ -134,3 +134,30 @@ def test_pnet_bf16_training_lowers_the_loss(torch_dev):
     print(f"training loss {first:.4f} -> {last:.4f}")
     assert last < 0.5 * first
     net.close()
+
+
+def test_pnet_fused_pairs_equal_layer_path(torch_dev):
+    """The fused convolution-pair kernels (activation tile in LDS, pooling in the
+    epilogue) against the layer-by-layer path: identical logits for bf16 and
+    FP32 inputs, identical gradients with a dropout mask."""
+    torch = torch_dev
+    from paper_2312_02063_amd import CNN_BF16, synth
+    p = synth.pnet_init(21)
+    x, y = _inputs(22, 37)
+    rng = np.random.default_rng(23)
+    keep = torch.tensor((rng.random((37, 128)) >= 0.5) * 2.0, dtype=torch.float32, device="cuda")
+    _say("pnet fused pairs vs layer path, 37 inputs")
+    net = _net(torch, CNN_BF16, p, max_batch=64)
+    xf = torch.tensor(x, dtype=torch.float32, device="cuda")
+    xb = xf.to(torch.bfloat16).view(torch.uint16)
+    yt = torch.tensor(y, dtype=torch.float32, device="cuda")
+    out = {}
+    for fused in (True, False):
+        net.set_fused(fused)
+        zb = net.forward(xb).cpu().numpy()
+        zf = net.forward(xf).cpu().numpy()
+        net.backward(xb, yt, keep=keep)
+        out[fused] = (zb, zf, net.get_grads().cpu().numpy())
+    for a, b, name in zip(out[True], out[False], ("bf16 logits", "f32 logits", "gradients")):
+        assert np.array_equal(a.view(np.int32), b.view(np.int32)), name
+    net.close()
