@@ -448,8 +448,8 @@ int32_t gpfc_cnn_train_replay(gpfc_cnn *cnn, void *stream);
  * in row-major order. precision: GPFC_CNN_BF16 (matrix cores on bf16 weights
  * and activations, FP32 accumulation, biases FP32) or GPFC_CNN_FP32.
  * max_batch: inputs per internal pass (device memory ~160 KB per input in
- * bf16, twice that in FP32); forward takes any batch in passes of it,
- * backward at most max_batch. All arrays are device pointers; calls are
+ * bf16, twice that in FP32, plus 230 MB of gradient chunk sums); forward
+ * takes any batch in passes of it, backward at most max_batch. All arrays are device pointers; calls are
  * asynchronous on `stream`. x: [B][256] bf16 bits (x_f32 = 0) or FP32.
  */
 typedef struct gpfc_pnet gpfc_pnet;

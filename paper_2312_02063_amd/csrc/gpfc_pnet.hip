@@ -440,7 +440,9 @@ __global__ __launch_bounds__(256) void k_colsum_parts(const float* __restrict__ 
     out[(int64_t)blockIdx.y * ncol + c] = a;
 }
 
-// dW5[j][f] = sum_b dh[b][j] g2[b][f], batch in order; one thread per weight.
+// dW5[j][f] = sum_b dh[b][j] g2[b][f] over the batch chunk blockIdx.y (inputs
+// in order), one thread per weight, into part y of dw5 ([gridDim.y][H F4]);
+// the chunks are added in order afterwards.
 template <class P>
 __global__ __launch_bounds__(256) void k_w5_grad(const float* __restrict__ dh,
                                                  const typename P::T* __restrict__ g2, int64_t B,
@@ -448,9 +450,11 @@ __global__ __launch_bounds__(256) void k_w5_grad(const float* __restrict__ dh,
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= H * F4) return;
     const int j = e / F4, f = e - j * F4;
+    const int64_t per = (B + gridDim.y - 1) / gridDim.y;
+    const int64_t b0 = (int64_t)blockIdx.y * per, b1 = b0 + per < B ? b0 + per : B;
     float a = 0.0f;
-    for (int64_t b = 0; b < B; ++b) a += dh[b * H + j] * P::to_f(g2[b * F4 + f]);
-    dw5[e] = a;
+    for (int64_t b = b0; b < b1; ++b) a += dh[b * H + j] * P::to_f(g2[b * F4 + f]);
+    dw5[(int64_t)blockIdx.y * (H * F4) + e] = a;
 }
 
 // Weight and bias gradients of a wide convolution from the routed pool
@@ -590,10 +594,23 @@ __global__ __launch_bounds__(1024) void k_conv_bwd(
         for (int task = wave; task < 2 * NPOS; task += 16) {
             const int q = task >> 1, i = ((task & 1) << 6) + lane;
             float acc = 0.0f;
-            for (int e = hoff[q]; e < hoff[q + 1]; ++e) {
+            int e = hoff[q];
+            const int e1 = hoff[q + 1];
+            // four entries' weights in flight at once, added in list order
+            for (; e + 4 <= e1; e += 4) {
+                float wv[4], gv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int en = ent[e + u];
+                    gv[u] = gsc[en >> 8];
+                    wv[u] = P::to_f(wp[(int64_t)(en >> 8) * ne + (en & 255) * 128 + i]);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc += gv[u] * wv[u];
+            }
+            for (; e < e1; ++e) {
                 const int en = ent[e];
-                const int f = en >> 8, tap = en & 255;
-                acc += gsc[f] * P::to_f(wp[(int64_t)f * ne + tap * 128 + i]);
+                acc += gsc[en >> 8] * P::to_f(wp[(int64_t)(en >> 8) * ne + (en & 255) * 128 + i]);
             }
             da[q * 128 + i] = acc;
         }
@@ -754,7 +771,7 @@ struct gpfc_pnet {
     float* part3 = nullptr;       // [B][3328]
     float* scalar = nullptr;      // the mean loss
     float* cparts = nullptr;      // [64][3328] chunk sums of the per-input gradient parts
-    float* dwparts = nullptr;     // [16][F4 K2 K2 F3 + F4] batch-chunk parts of a wide weight gradient
+    float* dwparts = nullptr;     // [64][F4 K2 K2 F3 + F4] batch-chunk parts of a weight gradient
     bool packed = false;
     bool fused = true;            // bf16: the fused pair kernels (false: layer by layer)
 };
@@ -771,7 +788,7 @@ int32_t pnet_err(hipError_t e, const char* what) {
 size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr int kColParts = 64;   // first-stage chunks of a column sum over the batch
-constexpr int kDwParts = 16;    // batch chunks of a wide convolution's weight gradient
+constexpr int kDwParts = 64;    // batch chunks of a wide convolution's weight gradient
 
 template <class P>
 hipError_t pack(gpfc_pnet* n, hipStream_t s) {
@@ -875,8 +892,10 @@ hipError_t backward(gpfc_pnet* n, const void* x, int in_f32, const float* labels
     colsum(n->dw6p, H, g + W6, 1.0f);
     colsum(n->dh, H, g + B5, 1.0f);
     colsum(n->dz, 1, g + B6, 1.0f);
-    hipLaunchKernelGGL(k_w5_grad<P>, dim3(H * F4 / 256), dim3(256), 0, s, n->dh, (const T*)n->g2, B,
-                       g + W5);
+    hipLaunchKernelGGL(k_w5_grad<P>, dim3(H * F4 / 256, (unsigned)np), dim3(256), 0, s, n->dh,
+                       (const T*)n->g2, B, n->dwparts);
+    hipLaunchKernelGGL(k_colsum, dim3(H * F4 / 256), dim3(256), 0, s, (const float*)n->dwparts, (int64_t)np,
+                       H * F4, g + W5, 1.0f);
     // wide convolutions' weight gradients: batch chunks in parallel, then the chunks in order
     const int nd = (int)std::min<int64_t>(kDwParts, B);
     const int n4 = F4 * F3 * K2 * K2 + F4, n2 = F2 * F1 * K1 * K1 + F2;
