@@ -1274,7 +1274,6 @@ __device__ void eqcount_pass(uint64_t* hist, EqBoundary (*bnd)[kEqMaxBins + 1], 
     const int reg = lane & (kEqPeriods - 1);           // the lane's histogram region
     const int pp = kTwo ? (reg & 1) : reg;             // its period within the pass
     const bool lo_word = kTwo && reg >= 2;
-    const int strm = wave * 16 + (lane >> 2);          // its record stream (256 per block)
     for (int i = threadIdx.x; i < kEqPeriods * kMid; i += kThreads) hist[i] = 0;
     const int64_t kk = kbase + pp;
     double P = kk < k ? periods[kk] : 1.0;
@@ -1283,16 +1282,60 @@ __device__ void eqcount_pass(uint64_t* hist, EqBoundary (*bnd)[kEqMaxBins + 1], 
     const double rB = (1.0 / P) * (double)kMid;
     const double zmax = info->tmax * rB;
     const uint32_t lim = zmax < 0x1p34 ? 65536u - 2u : 0u;
+    // The wave takes 16 consecutive records per instruction; the 4 lanes of a
+    // 16-lane pass that share the period take records d apart (d = 1, 2 or 4,
+    // a bijection of the 16), with d chosen so that the bins of records spaced
+    // by one cadence (the first two records' spacing), d, 2d and 3d apart differ
+    // mod 8 - a bank conflict needs equal bins mod 8. Any d gives the same sums.
+    int d = 1;
+    if (nrec > 1) {
+        const double step = (rec[1].t - rec[0].t) * rB;   // bins per record, about
+        int best = 99;
+        for (int dd = 1; dd <= 4; dd <<= 1) {
+            int coll = 0;
+            for (int f4 = 0; f4 < 4; ++f4) {               // a few phases of the first bin
+                int seen = 0;
+                for (int kq = 0; kq < 4; ++kq) {
+                    const double b = 0.25 * f4 + kq * dd * step;
+                    const int m = (int)(b - 8.0 * floor(b / 8.0)) & 7;
+                    coll += (seen >> m) & 1;
+                    seen |= 1 << m;
+                }
+            }
+            if (coll < best) { best = coll; d = dd; }
+        }
+    }
+    const int sl = lane >> 2, pr = sl >> 2, kq = sl & 3;   // pass and place within it
+    const int off = d == 1 ? 4 * pr + kq : (d == 2 ? (pr & 1) + 8 * (pr >> 1) + 2 * kq : pr + 4 * kq);
+    const int strm = wave * 16 + off;                  // its record stream (256 per block)
     __syncthreads();
     if (valid) {
-        for (int64_t i = strm; i < nrec; i += 256) {
-            const Rec r = rec[i];
-            const uint64_t c = lo_word ? lo[i] : r.c;
-            const uint32_t lw = fast_lo(r.t, rB);   // the certified path, at 4096 bins
-            uint32_t b = (lw >> 16) & (kMid - 1);
-            if ((lw & 0xFFFFu) >= lim) b = mid_bin_ieee(r.t, P);
-            __hip_atomic_fetch_add(hist + b * kEqPeriods + reg, c, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        // kEqU records per lane per step, all loaded before their updates, so
+        // their load latencies overlap
+        constexpr int kEqU = 8;
+        for (int64_t i0 = strm; i0 < nrec; i0 += 256 * kEqU) {
+            double tv[kEqU];
+            uint64_t cv[kEqU];
+#pragma unroll
+            for (int u = 0; u < kEqU; ++u) {
+                const int64_t i = i0 + 256 * u;
+                tv[u] = 0.0;
+                cv[u] = 0;
+                if (i < nrec) {
+                    const Rec r = rec[i];
+                    tv[u] = r.t;
+                    cv[u] = lo_word ? lo[i] : r.c;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kEqU; ++u) {
+                const uint32_t lw = fast_lo(tv[u], rB);   // the certified path, at 4096 bins
+                uint32_t b = (lw >> 16) & (kMid - 1);
+                if ((lw & 0xFFFFu) >= lim) b = mid_bin_ieee(tv[u], P);
+                if (cv[u])
+                    __hip_atomic_fetch_add(hist + b * kEqPeriods + reg, cv[u], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
         }
     }
     __syncthreads();
@@ -1331,19 +1374,25 @@ __device__ void eqcount_pass(uint64_t* hist, EqBoundary (*bnd)[kEqMaxBins + 1], 
         const int64_t Ltot = kTwo ? __shfl(pl, 63) : 0;
         int64_t C = pc - lc, S = ps - ls, SL = pl - ll;   // exclusive: before the lane's first bin
         if (v2 && N > 0) {
+            // the next boundary j N at or after the lane's first unit (one division
+            // per lane; later boundaries follow by steps of N)
+            int64_t j = (C * nbins + N - 1) / N;
+            int64_t jN = j * N;
             for (int b = lane * 64; b < lane * 64 + 64; ++b) {
                 int64_t c, d, dl;
                 bin_at(b, c, d, dl);
                 if (c == 0) continue;
-                // the bin's deviation in units of the high word
-                const double dd = kTwo ? (double)d + ldexp((double)dl, -kLoBits) : (double)d;
                 const int64_t u0 = C * nbins, u1 = (C + c) * nbins;   // the bin's units
                 // interior boundaries j N (0 < j < nbins) inside [u0, u1)
-                for (int64_t j = (u0 + N - 1) / N; j * N < u1; ++j) {
-                    if (j == 0) continue;
-                    bnd[p2][j].ipart = S;
-                    bnd[p2][j].ilo = SL;
-                    bnd[p2][j].frac = (double)(j * N - u0) / (double)(c * nbins) * dd;
+                if (jN < u1) {
+                    // the bin's deviation in units of the high word
+                    const double dd = kTwo ? (double)d + ldexp((double)dl, -kLoBits) : (double)d;
+                    for (; jN < u1; ++j, jN += N) {
+                        if (j == 0) continue;
+                        bnd[p2][j].ipart = S;
+                        bnd[p2][j].ilo = SL;
+                        bnd[p2][j].frac = (double)(jN - u0) / (double)(c * nbins) * dd;
+                    }
                 }
                 C += c;
                 S += d;
