@@ -55,6 +55,13 @@ constexpr int64_t F1W = 33536, F1B = 295680, F2W = 295936, F2B = 312320, F3W = 3
 // bit for bit; the training mask is taken from the same pair separately.
 __device__ __forceinline__ float pool_relu(float p0, float p1) { return fmaxf(fmaxf(p0, p1), 0.0f); }
 
+// Mask byte of one pooled output: bit 0 = the winning position (1: the odd
+// one, chosen only when its ReLU output is strictly larger), bit 1 = the
+// winner's pre-activation is > 0, which is the pooled value being > 0.
+__device__ __forceinline__ uint32_t pool_mask(float p0, float p1, float pooled) {
+    return (p1 > p0 && p1 > 0.0f ? 1u : 0u) | (pooled > 0.0f ? 2u : 0u);
+}
+
 // Implicit-GEMM rows of a circular conv input: row m = (b, x), k = dx*C + c
 // -> act[b][(x + sgn*(dx - 2)) mod L][c]; sgn = +1 forward, -1 for the
 // gradient with respect to the input.
@@ -172,12 +179,9 @@ struct EpConvFwd {
             if (mm >= M) continue;
             const float p0 = a[2 * h] * cs + bias[n], p1 = a[2 * h + 1] * cs + bias[n];
             const int64_t o = (int64_t)(mm >> 1) * C + n;
-            out[o] = P::from_f(pool_relu(p0, p1));
-            if (mask) {
-                const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
-                const int w = r0 >= r1 ? 0 : 1;
-                mask[o] = (uint8_t)(w | ((w ? p1 : p0) > 0.0f ? 2 : 0));
-            }
+            const float pooled = pool_relu(p0, p1);
+            out[o] = P::from_f(pooled);
+            if (mask) mask[o] = (uint8_t)pool_mask(p0, p1, pooled);
         }
     }
 };
@@ -312,6 +316,19 @@ struct EpConvDWB {
     }
 };
 
+// Weight and bias gradients of a dense layer reduced together: partial rows
+// hold [M][N] weight sums (the weight-gradient epilogue's layout), then M
+// bias sums (M = 1, N = M*N + M in the reduction's terms).
+struct EpFcDWB {
+    EpFcDW w;
+    float* gb;
+    int N, mn;
+    __device__ __forceinline__ void store(int, int j, float v) const {
+        if (j >= mn) { gb[j - mn] = v; return; }
+        w.store(j / N, j - (j / N) * N, v);
+    }
+};
+
 // ------------------------------------------------------------------ small kernels
 
 // Conv block 1 (one input channel) on the vector units: x [B][256] (bf16
@@ -340,12 +357,9 @@ __global__ __launch_bounds__(256) void k_conv1_fwd(const void* __restrict__ x, i
         }
         pre[h] = s;
     }
-    out[idx] = P::from_f(pool_relu(pre[0], pre[1]));
-    if (mask) {
-        const float r0 = fmaxf(pre[0], 0.0f), r1 = fmaxf(pre[1], 0.0f);
-        const int wn = r0 >= r1 ? 0 : 1;
-        mask[idx] = (uint8_t)(wn | ((wn ? pre[1] : pre[0]) > 0.0f ? 2 : 0));
-    }
+    const float pooled = pool_relu(pre[0], pre[1]);
+    out[idx] = P::from_f(pooled);
+    if (mask) mask[idx] = (uint8_t)pool_mask(pre[0], pre[1], pooled);
 }
 
 // Output layer of a training step, loss and its gradient (h2 [B][64] post-ReLU),
@@ -636,7 +650,8 @@ constexpr int kWP = 8;                           // waves (inputs in flight) per
 struct WaveSlice {
     uint16_t xs[256];                            // the input (bf16)
     uint16_t buf0[32 * kA3Ld];                   // a1 [128][16], then a3 [32][64] (swizzled rows)
-    uint16_t buf1[64 * kA2Ld];                   // a2 [64][32] (swizzled rows)
+    uint16_t buf1[64 * kA2Ld];                   // a2 [64][32], then a4 [16][64] (swizzled rows)
+    uint8_t mk[64 * 32];                         // a training step's pooling masks of one block
 };
 
 struct ConvStackLdsW {
@@ -656,17 +671,14 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // One conv layer of one input by one wave: rows x < L, tiles of RB x CB MFMA
-// blocks, as conv_tile (same k order, same epilogue).
-// kTrain: also write each pooled output to gout (if not null: the layer's
-// activation in HBM, [L/2][COUT]) and its mask byte to gmask (bit 0: the
-// winning position's parity, bit 1: the winner's pre-activation is > 0), as
-// EpConvFwd does for the backward pass.
-template <int L, int CIN, int ILD, int COUT, int WLD, int OLD, int RB, int CB, bool kTrain = false,
-          bool kOutLds = true>
+// blocks, as conv_tile (same k order, same epilogue). The pooled output goes
+// to out (LDS, act_off rows of OLD channels); with kTrain each output's mask
+// byte (bit 0: the winning position's parity, bit 1: the winner's
+// pre-activation is > 0, as EpConvFwd stores it) goes to mlds [L/2][COUT].
+template <int L, int CIN, int ILD, int COUT, int WLD, int OLD, int RB, int CB, bool kTrain = false>
 __device__ __forceinline__ void conv_one(const uint16_t* __restrict__ in, const uint16_t* __restrict__ w,
                                          const float* __restrict__ bias, uint16_t* __restrict__ out,
-                                         uint16_t* __restrict__ gout = nullptr,
-                                         uint8_t* __restrict__ gmask = nullptr) {
+                                         uint8_t* __restrict__ mlds = nullptr) {
     constexpr int K = 5 * CIN;
     constexpr int KSTEPS = (K + 31) / 32;
     constexpr int NRT = L / (16 * RB), NCT = COUT / (16 * CB);
@@ -701,20 +713,35 @@ __device__ __forceinline__ void conv_one(const uint16_t* __restrict__ in, const 
                 const float bn = bias[n];
                 for (int h = 0; h < 2; ++h) {
                     const float p0 = acc[i][j][2 * h] + bn, p1 = acc[i][j][2 * h + 1] + bn;
-                    const uint16_t hv = f2bf(pool_relu(p0, p1));
                     const int row = (x0 >> 1) + h;
-                    out[kOutLds ? act_off<OLD>(row, n & ~7) + (n & 7) : row * OLD + n] = hv;
-                    if constexpr (kTrain) {
-                        const int po = ((x0 >> 1) + h) * COUT + n;
-                        if (gout) gout[po] = hv;
-                        const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
-                        const int wn = r0 >= r1 ? 0 : 1;
-                        gmask[po] = (uint8_t)(wn | ((wn ? p1 : p0) > 0.0f ? 2 : 0));
-                    }
+                    const float pooled = pool_relu(p0, p1);
+                    out[act_off<OLD>(row, n & ~7) + (n & 7)] = f2bf(pooled);
+                    if constexpr (kTrain) mlds[row * COUT + n] = (uint8_t)pool_mask(p0, p1, pooled);
                 }
             }
         }
     }
+}
+
+// One wave copies a pooled activation [ROWS][C] from LDS (act_off rows of C
+// channels) to g [ROWS][C] in HBM, 16 bytes per lane and store.
+template <int ROWS, int C>
+__device__ __forceinline__ void act_to_hbm(const uint16_t* __restrict__ lds, uint16_t* __restrict__ g) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int t = lane; t < ROWS * C / 8; t += 64) {
+        const int row = t / (C / 8), c0 = (t - row * (C / 8)) * 8;
+        *reinterpret_cast<uint4*>(g + row * C + c0) = *reinterpret_cast<const uint4*>(lds + act_off<C>(row, c0));
+    }
+}
+
+// One wave copies BYTES bytes (a multiple of 16) from LDS to HBM.
+template <int BYTES>
+__device__ __forceinline__ void bytes_to_hbm(const uint8_t* __restrict__ lds, uint8_t* __restrict__ g) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int t = lane; t < BYTES / 16; t += 64)
+        reinterpret_cast<uint4*>(g)[t] = reinterpret_cast<const uint4*>(lds)[t];
 }
 
 // kTrain: the forward pass of a training step: besides a4, every block's
@@ -751,7 +778,7 @@ __global__ __launch_bounds__(kWP * 64, 1) void k_convstack_bf16_w(
     // 8 bytes per lane are loaded while the current one is computed
     int64_t fi = (int64_t)blockIdx.x * kWP + wave;
     auto load_in = [&](int64_t f) -> uint2 {
-        if (f >= B) return make_uint2(0u, 0u);
+        f = f < B ? f : B - 1;   // (past the batch: read again, never used)
         const int64_t o = f * 256 + lane * 4;
         if (xf32) {
             const float4 v = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(x) + o);
@@ -779,12 +806,7 @@ __global__ __launch_bounds__(kWP * 64, 1) void k_convstack_bf16_w(
                     p1 = __builtin_fmaf(w1[co * 5 + dx], v[dx + 1], p1);
                 }
                 pooled[co] = pool_relu(p0, p1);
-                if constexpr (kTrain) {
-                    const float r0 = fmaxf(p0, 0.0f), r1 = fmaxf(p1, 0.0f);
-                    const int wn = r0 >= r1 ? 0 : 1;
-                    const uint32_t byte = (uint32_t)(wn | ((wn ? p1 : p0) > 0.0f ? 2 : 0));
-                    mk[co >> 2] |= byte << (8 * (co & 3));
-                }
+                if constexpr (kTrain) mk[co >> 2] |= pool_mask(p0, p1, pooled[co]) << (8 * (co & 3));
             }
             uint32_t packed[8];
             for (int j = 0; j < 8; ++j) packed[j] = f2bf2(pooled[2 * j], pooled[2 * j + 1]);
@@ -800,15 +822,27 @@ __global__ __launch_bounds__(kWP * 64, 1) void k_convstack_bf16_w(
             }
         }
         wave_lds_sync();
-        conv_one<128, 16, kA1Ld, 32, kW2Ld, kA2Ld, 8, 2, kTrain>(
-            ws.buf0, sm.w2, b2, ws.buf1, kTrain ? a2g + fi * 2048 : nullptr, kTrain ? m2 + fi * 2048 : nullptr);
+        // each block's pooled output (and, training, its masks) is formed in
+        // LDS, then copied to HBM in 16-byte stores
+        conv_one<128, 16, kA1Ld, 32, kW2Ld, kA2Ld, 8, 2, kTrain>(ws.buf0, sm.w2, b2, ws.buf1, ws.mk);
         wave_lds_sync();
-        conv_one<64, 32, kA2Ld, 64, kW3Ld, kA3Ld, 4, 4, kTrain>(
-            ws.buf1, sm.w3, b3, ws.buf0, kTrain ? a3g + fi * 2048 : nullptr, kTrain ? m3 + fi * 2048 : nullptr);
+        if constexpr (kTrain) {
+            act_to_hbm<64, 32>(ws.buf1, a2g + fi * 2048);
+            bytes_to_hbm<2048>(ws.mk, m2 + fi * 2048);
+            wave_lds_sync();
+        }
+        conv_one<64, 32, kA2Ld, 64, kW3Ld, kA3Ld, 4, 4, kTrain>(ws.buf1, sm.w3, b3, ws.buf0, ws.mk);
         wave_lds_sync();
-        conv_one<32, 64, kA3Ld, 64, kW4Ld, 64, 2, 4, kTrain, false>(ws.buf0, sm.w4, b4, a4 + fi * 1024, nullptr,
-                                                             kTrain ? m4 + fi * 1024 : nullptr);
-        wave_lds_sync();   // buf0 and xs are reused by the next input
+        if constexpr (kTrain) {
+            act_to_hbm<32, 64>(ws.buf0, a3g + fi * 2048);
+            bytes_to_hbm<2048>(ws.mk, m3 + fi * 2048);
+            wave_lds_sync();
+        }
+        conv_one<32, 64, kA3Ld, 64, kW4Ld, kA3Ld, 2, 4, kTrain>(ws.buf0, sm.w4, b4, ws.buf1, ws.mk);
+        wave_lds_sync();
+        act_to_hbm<16, 64>(ws.buf1, a4 + fi * 1024);
+        if constexpr (kTrain) bytes_to_hbm<1024>(ws.mk, m4 + fi * 1024);
+        wave_lds_sync();   // buf0, buf1, mk and xs are reused by the next input
     }
 }
 
@@ -1178,6 +1212,16 @@ static_assert(kM3Off + 32 * 64 <= 128 * 32 * 2, "dpre4 and m3 share buf0");
 static_assert(kM3Off % 16 == 0 && sizeof(BwdSlice) % 16 == 0, "16-byte LDS groups");
 static_assert(sizeof(BwdLds) <= 160 * 1024, "LDS budget");
 
+// Byte offset of (row, byte) in an LDS copy of a pooling mask with rows of C
+// bytes: the 16-byte groups of a row are XOR-swizzled by the row so that the
+// epilogue's 4-byte reads (16 consecutive rows, 4 groups of 4 channels) hit
+// 64 distinct banks.
+template <int C>
+__device__ __forceinline__ int mask_off(int row, int byte) {
+    static_assert(C == 32 || C == 64, "mask rows");
+    return row * C + (byte ^ ((C == 64 ? (row >> 2) & 3 : (row >> 3) & 1) << 4));
+}
+
 // The values of 8 channels kept at the position whose mask bits 0-1 equal
 // sel (2: the even one, 3: the odd one); the others are 0.
 __device__ __forceinline__ uint4 unpool_at(uint4 g, uint2 k, uint32_t sel) {
@@ -1241,13 +1285,17 @@ __device__ __forceinline__ void convT_one(const uint16_t* __restrict__ dpre, con
                 const uint32_t h23 = f2bf2(acc[j][i][2], acc[j][i][3]);
                 *reinterpret_cast<uint2*>(gout + xx * CIN + n0) = make_uint2(h01, h23);
                 if constexpr (kNext) {
-                    const uint32_t mk = *reinterpret_cast<const uint32_t*>(mask + xx * CIN + n0);
+                    const uint32_t mk = *reinterpret_cast<const uint32_t*>(mask + mask_off<CIN>(xx, n0));
                     const uint4 ev = unpool_at(make_uint4(h01, h23, 0u, 0u), make_uint2(mk, 0u), 2u);
                     const uint4 od = unpool_at(make_uint4(h01, h23, 0u, 0u), make_uint2(mk, 0u), 3u);
-                    *reinterpret_cast<uint2*>(next + act_off<NLD>(2 * xx, n0 & ~7) + (n0 & 7)) =
-                        make_uint2(ev.x, ev.y);
-                    *reinterpret_cast<uint2*>(next + act_off<NLD>(2 * xx + 1, n0 & ~7) + (n0 & 7)) =
-                        make_uint2(od.x, od.y);
+                    // lanes of rows q and q + 1 (16 lanes apart) hold channels
+                    // 0-3 and 4-7 of one 8-channel group: swap so that the
+                    // first has the group's even position and the second its
+                    // odd one, each stored as one 16-byte write
+                    const auto s0 = __builtin_amdgcn_permlane16_swap(ev.x, od.x, false, false);
+                    const auto s1 = __builtin_amdgcn_permlane16_swap(ev.y, od.y, false, false);
+                    *reinterpret_cast<uint4*>(next + act_off<NLD>(2 * xx + (q & 1), n0 & ~7)) =
+                        make_uint4(s0[0], s1[0], s0[1], s1[1]);
                 }
             }
         }
@@ -1317,8 +1365,8 @@ __global__ __launch_bounds__(kBP * 64, 1) void k_convstack_bwd_bf16(
     load(fi);
     for (; fi < B; fi += stride) {
         for (int h = 0; h < 2; ++h) {
-            *reinterpret_cast<uint4*>(m3s + h * 1024 + lane * 16) = nk3[h];
-            *reinterpret_cast<uint4*>(ws.m2 + h * 1024 + lane * 16) = nk2[h];
+            *reinterpret_cast<uint4*>(m3s + mask_off<64>(h * 16 + (lane >> 2), (lane & 3) * 16)) = nk3[h];
+            *reinterpret_cast<uint4*>(ws.m2 + mask_off<32>(h * 32 + (lane >> 1), (lane & 1) * 16)) = nk2[h];
             const int e0 = h * 512 + lane * 8, xp = e0 >> 6, c0 = e0 & 63;
             uint4 ev, od;
             unpool8(ng[h], nk4[h], ev, od);
@@ -1634,6 +1682,138 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
     }
 }
 
+// Weight and bias gradients of a dense layer (bf16): C[m][n] = sum_b
+// A[b][m] Bt[b][n] and c[m] = sum_b A[b][m] over a range of the batch, with
+// A = the output gradient [K][M] and Bt = the layer's input [K][N], both
+// row-major with the batch as rows. A block owns a BM x 128 tile and one
+// batch range of kc rows; 64 rows at a time are loaded as 8 x 8 units (8
+// rows of 16 bytes per thread, one step ahead in registers), transposed in
+// registers and stored to LDS as [column][64 rows] (16-byte chunks XOR-
+// swizzled by the column), double-buffered so that one barrier per step
+// suffices. Blocks of the tiles' first column also sum A's columns (the bias
+// gradient), each thread over its 8 rows in order, then over the 8 row
+// groups in order. Block z of the batch writes ws[z][M*N + M]: the weight
+// sums [M][N], then the bias sums (deterministic; added up in z order by the
+// reduction). Blocks are mapped so that the tiles of one batch range share
+// an XCD (its L2 holds the range's rows once).
+template <int BM>
+__global__ __launch_bounds__(256, 2) void k_fc_dw_bf16(int K, int M, int N, int kc, int tiles_n,
+                                                       const uint16_t* __restrict__ A,
+                                                       const uint16_t* __restrict__ Bt,
+                                                       float* __restrict__ ws) {
+    constexpr int BN = 128, BK = 64, ROWS = BM + BN;
+    constexpr int AU = (BM / 8) * (BK / 8), BU = (BN / 8) * (BK / 8);   // 8 x 8 units per step
+    static_assert(AU + BU <= 256, "one unit per thread");
+    constexpr int WM = BM / 2, MT = WM / 16, NT = 4;                  // waves 2 x 2, 64 columns each
+    __shared__ uint4 lds[2][ROWS * (BK / 8)];
+    __shared__ float bred[8][BM];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, q = lane >> 4;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int logical = (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
+    const int tiles = (M / BM) * tiles_n;
+    const int tile = logical % tiles, z = logical / tiles;
+    const int mt = tile / tiles_n, nt = tile - mt * tiles_n;
+    const int k0 = z * kc, k1 = min(K, k0 + kc);
+    // this thread's load unit: 8 rows x 8 columns of A or of Bt
+    const bool isA = tid < AU, isB = !isA && tid < AU + BU;
+    const int u = isA ? tid : tid - AU;
+    const int cg = isA ? u % (BM / 8) : u % (BN / 8), kg = isA ? u / (BM / 8) : u / (BN / 8);
+    // (threads without a unit read A's first columns and store nothing)
+    const uint16_t* src = isA || !isB ? A + (int64_t)mt * BM + (isA ? cg * 8 : 0) : Bt + (int64_t)nt * BN + cg * 8;
+    const int ld = isA || !isB ? M : N;
+    const int row0 = isA ? cg * 8 : BM + cg * 8;   // LDS row of this unit's first column
+    const bool bias = isA && nt == 0;
+    float bsum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    f32x4 acc[MT][NT];
+    for (int i = 0; i < MT; ++i)
+        for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    // two register sets: the loads for step st + 2 are issued while step st
+    // is computed (about 64 KB in flight per block)
+    const int steps = k1 > k0 ? (k1 - k0 + BK - 1) / BK : 0;
+    // LDS row `row` keeps its 16-byte chunk c at c ^ swz(row): the fragment
+    // reads (16 consecutive rows, one chunk) stay conflict-free and the
+    // transposing writes (8 rows apart, one chunk per row group) are 2-way
+    auto slot = [](int row, int c) { return row * 8 + (c ^ (((row >> 3) * 2 + (row >> 1) * 2) & 7)); };
+    uint4 v0[8], v1[8];
+    // loads are unconditional (rows past the range re-read its last row and
+    // are zeroed at use), so the wait before a step covers only its own loads
+    auto load = [&](uint4 (&v)[8], int st) {
+        const int kb = k0 + st * BK;
+        for (int s = 0; s < 8; ++s) {
+            const int k = min(kb + kg * 8 + s, k1 - 1);
+            v[s] = *reinterpret_cast<const uint4*>(src + (int64_t)k * ld);
+        }
+    };
+    auto run_step = [&](uint4 (&v)[8], int st) {
+        uint4* buf = lds[st & 1];
+        const int kb = k0 + st * BK;
+        for (int s = 0; s < 8; ++s) {
+            const uint32_t keep = kb + kg * 8 + s < k1 ? ~0u : 0u;
+            v[s] = make_uint4(v[s].x & keep, v[s].y & keep, v[s].z & keep, v[s].w & keep);
+        }
+        if (isA || isB) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) buf[slot(row0 + j, kg)] = tr8(v, j);
+            if (bias)
+#pragma unroll
+                for (int s = 0; s < 8; ++s) {
+                    const uint32_t w4[4] = {v[s].x, v[s].y, v[s].z, v[s].w};
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) bsum[j] += bf2f((uint16_t)(w4[j >> 1] >> (16 * (j & 1))));
+                }
+        }
+        __syncthreads();   // this step's tile is stored; the other buffer is free
+        load(v, st + 2);   // (past the end: the range's last row again, never used)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            bf16x8 a[MT], bb[NT];
+            for (int i = 0; i < MT; ++i) {
+                a[i] = __builtin_bit_cast(bf16x8, buf[slot(wm * WM + i * 16 + r, ks * 4 + q)]);
+            }
+            for (int j = 0; j < NT; ++j) {
+                bb[j] = __builtin_bit_cast(bf16x8, buf[slot(BM + wn * 64 + j * 16 + r, ks * 4 + q)]);
+            }
+            for (int i = 0; i < MT; ++i)
+                for (int j = 0; j < NT; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bb[j], acc[i][j], 0, 0, 0);
+        }
+    };
+    // every path issues the same loads, so the compiler's waits before a
+    // step count only the loads that step needs (an odd count gets one step
+    // of zero rows)
+    if (steps > 0) {
+        load(v0, 0);
+        load(v1, 1);
+    }
+#pragma unroll 1
+    for (int st = 0; st < steps; st += 2) {
+        run_step(v0, st);
+        run_step(v1, st + 1);
+    }
+    const int64_t mn = (int64_t)M * N;
+    float* out = ws + (int64_t)z * (mn + M);
+    for (int i = 0; i < MT; ++i)
+        for (int j = 0; j < NT; ++j) {
+            const int n = nt * BN + wn * 64 + j * 16 + r;
+            for (int e = 0; e < 4; ++e) {
+                const int m = mt * BM + wm * WM + i * 16 + q * 4 + e;
+                out[(int64_t)m * N + n] = acc[i][j][e];
+            }
+        }
+    if (nt == 0) {
+        if (isA)
+            for (int j = 0; j < 8; ++j) bred[kg][cg * 8 + j] = bsum[j];
+        __syncthreads();
+        if (tid < BM) {
+            float t = 0.0f;
+            for (int g = 0; g < 8; ++g) t += bred[g][tid];
+            out[mn + mt * BM + tid] = t;
+        }
+    }
+}
+
 // Working copies of the weights from the FP32 masters.
 template <class P>
 __global__ __launch_bounds__(256) void k_pack(const float* __restrict__ w, typename P::T* __restrict__ wf2,
@@ -1715,26 +1895,44 @@ __global__ __launch_bounds__(256) void k_quant_rows(const uint16_t* __restrict__
 }
 
 // Adam with the step count on the device (so a captured training step can be
-// replayed): k_step_inc advances it, k_adam derives the bias corrections.
-__global__ void k_step_inc(int32_t* __restrict__ step) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1;
-}
-
+// replayed). step[0] holds the steps taken; every block reads it, applies
+// step t = step[0] + 1 (the bias corrections worked out once per block) to
+// its stripes of the parameters, and the last block to finish (counted in
+// step[1]) stores t and clears the count, so no block of this launch sees
+// the new value. Launch with kAdamBlocks blocks (few: the count is one
+// memory-side atomic per block, with no cache maintenance).
+constexpr int kAdamBlocks = 256;
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
                                               float* __restrict__ m, float* __restrict__ v, int64_t n,
                                               float lr, float b1, float b2, float eps,
-                                              const int32_t* __restrict__ step) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const double t = (double)*step;
-    const float c1 = (float)(1.0 - pow((double)b1, t));
-    const float c2 = (float)(1.0 - pow((double)b2, t));
-    const float gi = g[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+                                              int32_t* __restrict__ step) {
+    __shared__ float corr[2];
+    __shared__ int32_t t_sh;
+    if (threadIdx.x == 0) {
+        const int32_t t = __hip_atomic_load(step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+        corr[0] = (float)(1.0 - pow((double)b1, (double)t));
+        corr[1] = (float)(1.0 - pow((double)b2, (double)t));
+        t_sh = t;
+    }
+    __syncthreads();
+    const float c1 = corr[0], c2 = corr[1];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+    // thread 0 read step[0] before the barrier above, so its block has read
+    // it before it is counted
+    if (threadIdx.x == 0) {
+        const int32_t done = __hip_atomic_fetch_add(step + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (done == (int32_t)gridDim.x - 1) {
+            __hip_atomic_store(step + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(step, t_sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 }
 
 __global__ void k_copy_f32(const float* __restrict__ src, float* __restrict__ dst, int n) {
@@ -1742,8 +1940,9 @@ __global__ void k_copy_f32(const float* __restrict__ src, float* __restrict__ ds
     if (i < n) dst[i] = src[i];
 }
 
-__global__ void k_set_i32c(int32_t* __restrict__ p, int32_t v) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+// Adam's step count and its finished-block count back to zero.
+__global__ void k_reset_step(int32_t* __restrict__ p) {
+    if (threadIdx.x < 2 && blockIdx.x == 0) p[threadIdx.x] = 0;
 }
 
 __global__ __launch_bounds__(256) void k_fill(float* __restrict__ p, int64_t n, float v) {
@@ -1777,6 +1976,35 @@ hipError_t bias_grad(const typename P::T* d, int64_t rows, int C, float* g, floa
 
 // Split-K workspace (floats) every network holds.
 constexpr int64_t kSplitWs = int64_t(8) << 20;
+
+// Weight and bias gradients of a bf16 dense layer with M outputs and N
+// inputs (M a multiple of 64, N of 128) from its output gradient d [B][M]
+// and input act [B][N]: batch ranges over enough blocks to fill the chip
+// (at least 256 rows each), then the partials summed in range order.
+inline hipError_t fc_dw_bf16(int B, int M, int N, const uint16_t* d, const uint16_t* act, EpFcDW ep,
+                             float* gb, float* ws, hipStream_t s) {
+    const bool wide = M % 128 == 0;
+    const int tiles_n = N / 128, tiles = (wide ? M / 128 : M / 64) * tiles_n;
+    const int64_t row = (int64_t)M * N + M;
+    int S = std::max(1, std::min(B / 256, std::max(1, 256 / tiles)));
+    S = (int)std::min<int64_t>(S, kSplitWs / row);
+    int kc = (B + S - 1) / S;
+    kc = (kc + 63) / 64 * 64;
+    S = (B + kc - 1) / kc;
+    const dim3 grid((unsigned)(tiles * S));
+    if (wide)
+        hipLaunchKernelGGL(k_fc_dw_bf16<128>, grid, dim3(256), 0, s, B, M, N, kc, tiles_n, d, act, ws);
+    else
+        hipLaunchKernelGGL(k_fc_dw_bf16<64>, grid, dim3(256), 0, s, B, M, N, kc, tiles_n, d, act, ws);
+    const EpFcDWB epb{ep, gb, N, M * N};
+    if (S >= 16)
+        hipLaunchKernelGGL(k_splitk_reduce_w<EpFcDWB>, dim3((unsigned)((row + 63) / 64)), dim3(1024), 0, s, ws, S,
+                           1, (int)row, epb);
+    else
+        hipLaunchKernelGGL(k_splitk_reduce<EpFcDWB>, dim3(blocks_for(row)), dim3(256), 0, s, ws, S, 1, (int)row,
+                           epb);
+    return hipGetLastError();
+}
 
 // Weight-gradient GEMM with a long K (the batch, or batch x positions): the
 // K range is split over enough blocks to fill the chip, partial tiles go to
@@ -2038,20 +2266,34 @@ int32_t backward(gpfc_cnn* c, const void* x, int xf32, int B, hipStream_t s) {
     float* g = c->grad;
     // dh2 (already masked) is in d_a [B][64]
     T* dh2 = (T*)c->d_a;
-    e = gemm_splitk<P>(64, 256, B, Cols<P>{dh2, 64, 64, B}, Cols<P>{(const T*)c->h1, 256, 256, B},
-                       EpFcDW{g + F2W, 256, false}, c->ws, s);
+    // bf16 (both paths): the staged weight-gradient kernel, bias sums included
+    constexpr bool kBf = __is_same(P, BF16);
+    if constexpr (kBf)
+        e = fc_dw_bf16(B, 64, 256, (const uint16_t*)dh2, (const uint16_t*)c->h1, EpFcDW{g + F2W, 256, false},
+                       g + F2B, c->ws, s);
+    else
+        e = gemm_splitk<P>(64, 256, B, Cols<P>{dh2, 64, 64, B}, Cols<P>{(const T*)c->h1, 256, 256, B},
+                           EpFcDW{g + F2W, 256, false}, c->ws, s);
     if (e != hipSuccess) return cnn_err(e, "fc2 dW");
-    e = bias_grad<P>(dh2, B, 64, g + F2B, c->ws, s);
-    if (e != hipSuccess) return cnn_err(e, "fc2 bias grad");
+    if constexpr (!kBf) {
+        e = bias_grad<P>(dh2, B, 64, g + F2B, c->ws, s);
+        if (e != hipSuccess) return cnn_err(e, "fc2 bias grad");
+    }
     T* dh1 = (T*)c->d_b;   // [B][256], masked by h1 > 0
     e = gemm<P>(B, 256, 64, Rows<P>{dh2, B, 64, 64}, Rows<P>{(const T*)c->f2b, 256, 64, 64},
                 EpStore<P>{dh1, (const T*)c->h1, 256}, s);
     if (e != hipSuccess) return cnn_err(e, "fc2 dX");
-    e = gemm_splitk<P>(256, 1024, B, Cols<P>{dh1, 256, 256, B},
-                       Cols<P>{(const T*)c->a4, 1024, 1024, B}, EpFcDW{g + F1W, 1024, true}, c->ws, s);
+    if constexpr (kBf)
+        e = fc_dw_bf16(B, 256, 1024, (const uint16_t*)dh1, (const uint16_t*)c->a4, EpFcDW{g + F1W, 1024, true},
+                       g + F1B, c->ws, s);
+    else
+        e = gemm_splitk<P>(256, 1024, B, Cols<P>{dh1, 256, 256, B},
+                           Cols<P>{(const T*)c->a4, 1024, 1024, B}, EpFcDW{g + F1W, 1024, true}, c->ws, s);
     if (e != hipSuccess) return cnn_err(e, "fc1 dW");
-    e = bias_grad<P>(dh1, B, 256, g + F1B, c->ws, s);
-    if (e != hipSuccess) return cnn_err(e, "fc1 bias grad");
+    if constexpr (!kBf) {
+        e = bias_grad<P>(dh1, B, 256, g + F1B, c->ws, s);
+        if (e != hipSuccess) return cnn_err(e, "fc1 bias grad");
+    }
     T* dact = (T*)c->d_a;  // [B][1024] = pooled gradient of block 4, position-major
     // bf16: the staged kernel (same MFMA chains and rounding as the GEMM)
     if (__is_same(P, BF16) && c->fused) {
@@ -2151,7 +2393,7 @@ int32_t gpfc_cnn_create(gpfc_cnn** out, int32_t device, int32_t precision, int64
     const size_t qsz[5] = {32 * 80, 64 * 160, 64 * 320, 256 * 1024, 64 * 256};
     const size_t csz[5] = {32, 64, 64, 256, 64};
     for (int i = 0; i < 5; ++i) total += al(qsz[i]) + al(csz[i] * sizeof(float));
-    total += 256;
+    total += 2 * 256;                           // activation maxima, Adam step count
     void* base = nullptr;
     e = hipMalloc(&base, total);
     if (e != hipSuccess) {
@@ -2183,6 +2425,18 @@ int32_t gpfc_cnn_create(gpfc_cnn** out, int32_t device, int32_t precision, int64
     }
     c->act_max = (uint32_t*)take(256);
     c->step_dev = (int32_t*)take(256);
+    if ((size_t)(p - (char*)base) > total) {   // the views must lie inside the allocation
+        (void)hipFree(base);
+        delete c;
+        snprintf(g_cnn_err, sizeof(g_cnn_err), "gpfc_cnn_create: workspace layout exceeds its allocation");
+        return GPFC_EDEVICE;
+    }
+    e = hipMemset(c->step_dev, 0, 256);   // no steps taken, no blocks counted
+    if (e != hipSuccess) {
+        (void)hipFree(base);
+        delete c;
+        return cnn_err(e, "hipMemset");
+    }
     *out = c;
     return GPFC_OK;
 }
@@ -2204,7 +2458,7 @@ static int32_t reset_after_params(gpfc_cnn* c, hipStream_t s) {
     const unsigned nb = gcnn::blocks_for(gcnn::kNP);
     hipLaunchKernelGGL(gcnn::k_fill, dim3(nb), dim3(256), 0, s, c->m, (int64_t)gcnn::kNP, 0.0f);
     hipLaunchKernelGGL(gcnn::k_fill, dim3(nb), dim3(256), 0, s, c->v, (int64_t)gcnn::kNP, 0.0f);
-    hipLaunchKernelGGL(gcnn::k_set_i32c, dim3(1), dim3(64), 0, s, c->step_dev, 0);
+    hipLaunchKernelGGL(gcnn::k_reset_step, dim3(1), dim3(64), 0, s, c->step_dev);
     c->packed = false;
     c->quantized = false;
     const hipError_t e = hipGetLastError();
@@ -2291,8 +2545,7 @@ int32_t gpfc_cnn_backward(gpfc_cnn* c, const void* x, int32_t x_f32, const float
                           float* loss_out, float* grad_out, void* stream) {
     if (!c || B < 1 || B > c->max_batch || !x || !labels) return GPFC_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(gcnn::k_fill, dim3(gcnn::blocks_for(gcnn::kNP)), dim3(256), 0, s, c->grad,
-                       (int64_t)gcnn::kNP, 0.0f);
+    // every gradient entry is stored (not accumulated) by exactly one kernel
     int32_t rc = c->prec ? forward<gcnn::F32>(c, x, x_f32, (int)B, nullptr, labels, s)
                          : forward<gcnn::BF16>(c, x, x_f32, (int)B, nullptr, labels, s);
     if (rc != GPFC_OK) return rc;
@@ -2311,8 +2564,7 @@ static bool adam_args_ok(float lr, float beta1, float beta2) {
 }
 
 static int32_t enqueue_adam(gpfc_cnn* c, float lr, float beta1, float beta2, float eps, hipStream_t s) {
-    hipLaunchKernelGGL(gcnn::k_step_inc, dim3(1), dim3(64), 0, s, c->step_dev);
-    hipLaunchKernelGGL(gcnn::k_adam, dim3(gcnn::blocks_for(gcnn::kNP)), dim3(256), 0, s, c->params,
+    hipLaunchKernelGGL(gcnn::k_adam, dim3(gcnn::kAdamBlocks), dim3(256), 0, s, c->params,
                        c->grad, c->m, c->v, (int64_t)gcnn::kNP, lr, beta1, beta2, eps, c->step_dev);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cnn_err(e, "k_adam");
