@@ -1386,17 +1386,19 @@ __global__ __launch_bounds__(kBP * 64, 1) void k_convstack_bwd_bf16(
 
 // Weight and bias gradients of conv block l = 2 .. 4 (bf16). The batch is cut
 // into groups of 8 inputs and each block takes a contiguous range of groups.
-// For 32 output positions at a time, the gradient at the block's
-// pre-activations (its pooled gradient unpooled with the mask) and the
-// block's input at those positions -2 .. +2 are staged in LDS with the 8
-// inputs innermost ([position][channel][8]), so that an MFMA k-step is 4
-// positions x 8 inputs and every operand fragment is one aligned 16-byte
-// read. Channel slots are XOR-swizzled within groups of 8 by the position,
-// which keeps both the transposing writes and the fragment reads free of
-// most bank conflicts. The waves split the output columns (n = dx*CIN + ci)
-// in WN parts and the k-steps in WK; each block writes one row of FP32 sums
-// to part_out: [COUT][5 CIN] weight sums, then COUT bias sums; the rows are
-// added up in block order (deterministic).
+// An item is 32 output positions of one group: the gradient at the block's
+// pre-activations there (its pooled gradient unpooled with the mask) and the
+// block's input at those positions -2 .. +2, staged in LDS with the 8 inputs
+// innermost ([position][channel][8]), so that an MFMA k-step is 4 positions x
+// 8 inputs and every operand fragment is one aligned 16-byte read. Channel
+// slots are XOR-swizzled within groups of 8 by the position, which keeps both
+// the transposing writes and the fragment reads free of most bank conflicts.
+// In k_conv_dw_bf16 a block of 4 waves stages an item, then runs its MFMAs
+// (several blocks per CU overlap one's loads with another's matrix work).
+// The waves split the output columns (n = dx*CIN + ci) in WN parts and the
+// k-steps in WK; each block writes one row of FP32 sums to part_out:
+// [COUT][5 CIN] weight sums, then COUT bias sums; the rows are added up in
+// block order (deterministic).
 __device__ __forceinline__ int dw_slot(int pos, int c, int C) {
     return pos * C + (c ^ (((c >> 3) + pos) & 7));
 }
@@ -1569,6 +1571,236 @@ __global__ __launch_bounds__(256, CIN == 16 ? 3 : 2) void k_conv_dw_bf16(int B, 
         float s = 0.0f;
         for (int t = og; t < 256; t += COUT / 4) s += red[t * 4 + j];
         part_out[(int64_t)blockIdx.x * (COUT * (5 * CIN) + COUT) + COUT * (5 * CIN) + tid] = s;
+    }
+}
+
+// k_conv_dw_pipe_bf16: the same items, sums and output rows, with a block of
+// 8 waves: waves 4-7 stage item i + 1 into one of two LDS stages (its loads
+// issued while item i - 1's matrix work runs) while waves 0-3 run item i's
+// MFMAs on the other, one barrier per item; the bias sums are formed by the
+// staging waves.
+template <int L, int CIN, int COUT, int WN, int WK>
+struct DwPipeShape {
+    static constexpr int MT = COUT / 16, NT = 5 * CIN / 16, NTW = NT / WN;
+    static constexpr int DQ = 32 * COUT * 8, AQ = 36 * CIN * 8;           // bf16 elements per stage
+    static constexpr int STAGE = 2 * (DQ + AQ);                          // bytes per stage
+    static constexpr int RED = (WK - 1) * WN * MT * NTW * 256;            // floats
+    static constexpr int REDB = 4 * RED, DBB = 4 * 256 * 4;
+    static constexpr int BYTES = 2 * STAGE > REDB ? (2 * STAGE > DBB ? 2 * STAGE : DBB) : (REDB > DBB ? REDB : DBB);
+    // staging units per item: input positions -2 .. 33 of the item (for a
+    // 32-position block, whose one item wraps around, its 32 positions, each
+    // also written to the halo slots it lands in); gradient units
+    static constexpr bool WRAP = L == 32;
+    static constexpr int NA = (WRAP ? 32 : 36) * (CIN / 8), ND = 16 * (COUT / 4);
+    static constexpr int UA = (NA + 255) / 256, UD = (ND + 255) / 256;    // per staging thread
+};
+
+template <int L, int CIN, int COUT, int WN, int WK>
+__global__ __launch_bounds__(512, 1) void k_conv_dw_pipe_bf16(
+    int B, int groups_per_block, const uint16_t* __restrict__ dact, const uint8_t* __restrict__ mask,
+    const uint16_t* __restrict__ act, float* __restrict__ part_out) {
+    using S = DwPipeShape<L, CIN, COUT, WN, WK>;
+    constexpr int MT = S::MT, NTW = S::NTW, CH = L / 32;
+    static_assert(WN * WK == 4 && S::NT % WN == 0, "wave split");
+    static_assert(L % 32 == 0 && CIN % 16 == 0 && COUT % 16 == 0, "tile shapes");
+    __shared__ __attribute__((aligned(16))) uint8_t smem[S::BYTES];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool stager = wave >= 4;
+    const int st = tid - 256;   // staging thread index
+    const int ngroups = (B + 7) / 8;
+    const int g0 = blockIdx.x * groups_per_block;
+    const int n_it = max(0, min(ngroups, g0 + groups_per_block) - g0) * CH;
+    float db[4] = {0, 0, 0, 0};
+    // Staging. A thread holds up to UA input units (8 inputs x 8 channels)
+    // and UD gradient units (8 inputs x 4 channels) of one item in
+    // registers: load() issues every load of item `it` unconditionally
+    // (indices past the item's units or the batch are clamped, and their
+    // values dropped at use), so the waits count exactly; stage() turns them
+    // into item it's LDS stage. The loads of item i + 2 are issued right
+    // after item i + 1 is staged, so their latency passes during the matrix
+    // work of item i.
+    uint4 va[S::UA][8];
+    uint2 gv[S::UD][8];
+    uint32_t kv[S::UD][8];
+    auto load = [&](int it) {
+        const int g = g0 + it / CH, c = it - (it / CH) * CH;
+#pragma unroll
+        for (int u = 0; u < S::UA; ++u) {
+            const int t = min(st + u * 256, S::NA - 1);
+            const int pi = t / (CIN / 8), cg = t - pi * (CIN / 8);
+            int pos = S::WRAP ? pi : c * 32 + pi - 2;
+            pos = pos < 0 ? pos + L : (pos >= L ? pos - L : pos);
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int64_t b = min<int64_t>((int64_t)g * 8 + s, B - 1);
+                va[u][s] = *reinterpret_cast<const uint4*>(act + (b * L + pos) * CIN + cg * 8);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < S::UD; ++u) {
+            const int t = min(st + u * 256, S::ND - 1);
+            const int xi = t / (COUT / 4), og = t - xi * (COUT / 4);
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int64_t b = min<int64_t>((int64_t)g * 8 + s, B - 1);
+                const int64_t o = (b * (L / 2) + c * 16 + xi) * COUT + og * 4;
+                gv[u][s] = *reinterpret_cast<const uint2*>(dact + o);
+                kv[u][s] = *reinterpret_cast<const uint32_t*>(mask + o);
+            }
+        }
+    };
+    auto stage = [&](int it) {
+        const int g = g0 + it / CH;
+        uint16_t* dq = reinterpret_cast<uint16_t*>(smem + (it & 1) * S::STAGE);
+        uint16_t* aq = dq + S::DQ;
+        // inputs past the batch contribute zeros
+        const int nval = (int)min<int64_t>(8, (int64_t)B - (int64_t)g * 8);
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+            if (s >= nval) {
+#pragma unroll
+                for (int u = 0; u < S::UA; ++u) va[u][s] = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+                for (int u = 0; u < S::UD; ++u) kv[u][s] = 0u;
+            }
+#pragma unroll
+        for (int u = 0; u < S::UA; ++u) {
+            const int t = st + u * 256;
+            if (t < S::NA) {
+                const int pi = t / (CIN / 8), cg = t - pi * (CIN / 8);
+                if constexpr (S::WRAP) {
+                    // position p sits at slot p + 2, and at p + 34 or p - 30
+                    // when that is a halo slot (0, 1, 34, 35)
+                    const int p2 = pi < 2 ? pi + 34 : (pi >= 30 ? pi - 30 : -1);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const uint4 w = tr8(va[u], j);
+                        *reinterpret_cast<uint4*>(aq + dw_slot(pi + 2, cg * 8 + j, CIN) * 8) = w;
+                        if (p2 >= 0) *reinterpret_cast<uint4*>(aq + dw_slot(p2, cg * 8 + j, CIN) * 8) = w;
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        *reinterpret_cast<uint4*>(aq + dw_slot(pi, cg * 8 + j, CIN) * 8) = tr8(va[u], j);
+                }
+            }
+        }
+        // gradient at pre-activation positions c*32 ... c*32 + 31, 4 channels
+        // of one pooled position per unit (a zero mask keeps nothing): the
+        // even positions' values, then the odd ones'
+#pragma unroll
+        for (int u = 0; u < S::UD; ++u) {
+            const int t = st + u * 256;
+            if (t < S::ND) {
+                const int xi = t / (COUT / 4), og = t - xi * (COUT / 4);
+#pragma unroll
+                for (int s = 0; s < 8; ++s)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const uint32_t h = (j < 2 ? gv[u][s].x : gv[u][s].y) >> (16 * (j & 1));
+                        db[j] += (kv[u][s] >> (8 * j) & 2u) ? bf2f((uint16_t)h) : 0.0f;
+                    }
+#pragma unroll
+                for (int par = 0; par < 2; ++par) {
+                    const uint32_t sel = 2u | (uint32_t)par;
+                    uint32_t e[8][4];
+#pragma unroll
+                    for (int s = 0; s < 8; ++s)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const uint32_t h = ((j < 2 ? gv[u][s].x : gv[u][s].y) >> (16 * (j & 1))) & 0xffffu;
+                            e[s][j] = ((kv[u][s] >> (8 * j)) & 3u) == sel ? h : 0u;
+                        }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        *reinterpret_cast<uint4*>(dq + dw_slot(2 * xi + par, og * 4 + j, COUT) * 8) =
+                            make_uint4(e[0][j] | (e[1][j] << 16), e[2][j] | (e[3][j] << 16),
+                                       e[4][j] | (e[5][j] << 16), e[6][j] | (e[7][j] << 16));
+                }
+            }
+        }
+    };
+    f32x4 acc[MT][NTW];
+    for (int i = 0; i < MT; ++i)
+        for (int j = 0; j < NTW; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int r = lane & 15, q = lane >> 4;
+    const int nw = wave % WN, kw = (wave & 3) / WN;
+    // byte offsets (within a stage) of the lane's A and B fragments for
+    // k-steps kw and kw + WK
+    int abase[2][MT], bbase[2][NTW];
+    for (int hm = 0; hm < 2; ++hm) {
+        const int p = (kw + hm * WK) * 4 + q;   // position within the item
+        for (int i = 0; i < MT; ++i) abase[hm][i] = dw_slot(p, i * 16 + r, COUT) * 16;
+        for (int j = 0; j < NTW; ++j) {
+            const int n = (nw * NTW + j) * 16 + r;
+            const int dx = n / CIN, ci = n - dx * CIN;
+            bbase[hm][j] = S::DQ * 2 + dw_slot(p + dx, ci, CIN) * 16;
+        }
+    }
+    if (stager && n_it > 0) {
+        load(0);
+        stage(0);
+        load(min(1, n_it - 1));
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int it = 0; it < n_it; ++it) {
+        if (stager) {
+            if (it + 1 < n_it) {
+                stage(it + 1);
+                load(min(it + 2, n_it - 1));   // (past the end: the last item again, never staged)
+            }
+        } else {
+            // wave kw takes k-steps kw + m*WK (4 positions each); steps m and
+            // m + 2 are 8*WK positions apart and use the same swizzle, so the
+            // fragment addresses are two per-lane bases plus constant offsets
+            const uint8_t* stg = smem + (it & 1) * S::STAGE;
+#pragma unroll 2
+            for (int m = 0; m < 8 / WK; ++m) {
+                const int hm = m & 1, step = (m >> 1) * 8 * WK * 16;   // 8 WK positions, 16 bytes a slot
+                bf16x8 a[MT], bb[NTW];
+                for (int i = 0; i < MT; ++i)
+                    a[i] = *reinterpret_cast<const bf16x8*>(stg + abase[hm][i] + step * COUT);
+                for (int j = 0; j < NTW; ++j)
+                    bb[j] = *reinterpret_cast<const bf16x8*>(stg + bbase[hm][j] + step * CIN);
+                for (int i = 0; i < MT; ++i)
+                    for (int j = 0; j < NTW; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bb[j], acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();   // stage it & 1 is free, stage (it + 1) & 1 is full
+    }
+    // (the stages become reduction space: every wave is past the last barrier)
+    float* red = reinterpret_cast<float*>(smem);
+    constexpr int TILES = MT * NTW;
+    if constexpr (WK > 1) {
+        if (!stager && kw > 0)
+            for (int i = 0; i < MT; ++i)
+                for (int j = 0; j < NTW; ++j)
+                    for (int e = 0; e < 4; ++e)
+                        red[(((kw - 1) * WN + nw) * TILES + i * NTW + j) * 256 + e * 64 + lane] = acc[i][j][e];
+        __syncthreads();
+    }
+    if (!stager && kw == 0) {
+        float* out = part_out + (int64_t)blockIdx.x * (COUT * (5 * CIN) + COUT);
+        for (int i = 0; i < MT; ++i)
+            for (int j = 0; j < NTW; ++j)
+                for (int e = 0; e < 4; ++e) {
+                    float v = acc[i][j][e];
+                    for (int z = 1; z < WK; ++z) v += red[(((z - 1) * WN + nw) * TILES + i * NTW + j) * 256 + e * 64 + lane];
+                    const int m = i * 16 + q * 4 + e, n = (nw * NTW + j) * 16 + r;
+                    out[m * (5 * CIN) + n] = v;
+                }
+    }
+    __syncthreads();
+    if (stager)
+        for (int j = 0; j < 4; ++j) red[st * 4 + j] = db[j];
+    __syncthreads();
+    if (tid < COUT) {
+        const int og = tid >> 2, j = tid & 3;
+        float t = 0.0f;
+        for (int u = og; u < 256; u += COUT / 4) t += red[u * 4 + j];
+        part_out[(int64_t)blockIdx.x * (COUT * (5 * CIN) + COUT) + COUT * (5 * CIN) + tid] = t;
     }
 }
 
@@ -2215,11 +2447,20 @@ hipError_t conv_dw_bf16(const gpfc_cnn* c, int B, const uint16_t* dact, const ui
     const int64_t mn = (int64_t)COUT * 5 * CIN;
     const int groups = (B + 7) / 8;
     const int64_t row = mn + COUT;
-    int blocks = (int)std::min<int64_t>(std::min(groups, (CIN == 16 ? 3 : 2) * c->n_cu), kSplitWs / row);
+    // block 4 (one 32-position item per group): the staged pipeline, one
+    // block of 8 waves per CU; blocks 2 and 3: several 4-wave blocks per CU,
+    // each staging and computing in turn (faster for their small items)
+    constexpr bool kPipe = L == 32;
+    const int per_cu = kPipe ? 1 : (CIN == 16 ? 3 : 2);
+    int blocks = (int)std::min<int64_t>(std::min(groups, per_cu * c->n_cu), kSplitWs / row);
     const int gpb = (groups + blocks - 1) / blocks;
     blocks = (groups + gpb - 1) / gpb;
-    hipLaunchKernelGGL((k_conv_dw_bf16<L, CIN, COUT, WN, WK>), dim3((unsigned)blocks), dim3(256), 0, s, B, gpb,
-                       dact, mask, act, c->ws);
+    if constexpr (kPipe)
+        hipLaunchKernelGGL((k_conv_dw_pipe_bf16<L, CIN, COUT, WN, WK>), dim3((unsigned)blocks), dim3(512), 0, s, B,
+                           gpb, dact, mask, act, c->ws);
+    else
+        hipLaunchKernelGGL((k_conv_dw_bf16<L, CIN, COUT, WN, WK>), dim3((unsigned)blocks), dim3(256), 0, s, B, gpb,
+                           dact, mask, act, c->ws);
     hipLaunchKernelGGL((k_splitk_reduce_w<EpConvDWB>), dim3((unsigned)((row + 63) / 64)), dim3(1024), 0, s,
                        c->ws, blocks, 1, (int)row, EpConvDWB{gw, gb, CIN, (int)mn});
     return hipGetLastError();
