@@ -369,7 +369,8 @@ __global__ __launch_bounds__(256) void k_conv1_fwd(const void* __restrict__ x, i
 //   rows[0, B) and the loss term max(z, 0) - z y + log1p(exp(-|z|)) into
 //   rows[B, 2B);
 // k_head_dh2: dh2[b][i] = dz[b] w3[i] where h2[b][i] > 0, else 0;
-// k_head_parts: row parts' sums of dz h2[.][i] (64), dz and the loss terms;
+// k_head_parts: sums of dz h2[.][i] (64), dz and the loss terms over parts
+//   of kHeadRowsPerPart rows;
 // k_head_final: the part sums added in part order into dW3, db3 and the loss.
 template <class P>
 __global__ __launch_bounds__(256) void k_head_rows(const typename P::T* __restrict__ h2, int B,
@@ -399,6 +400,7 @@ __global__ __launch_bounds__(256) void k_head_dh2(const typename P::T* __restric
 }
 
 constexpr int kHeadSums = 66;   // dW3[64], db3, loss
+constexpr int kHeadRowsPerPart = 128;   // rows per part: one part per block of the fused layer
 
 // Block = one part of the rows; thread (row lane rl of 4, column i): sums over
 // the part's rows rl, rl + 4, ...; lanes merged in order in LDS.
@@ -408,7 +410,7 @@ __global__ __launch_bounds__(256) void k_head_parts(const typename P::T* __restr
                                                     float* __restrict__ part_out) {
     __shared__ float red[4][kHeadSums];
     const int i = threadIdx.x & 63, rl = threadIdx.x >> 6;
-    const int64_t per = ((int64_t)B + gridDim.x - 1) / gridDim.x;
+    constexpr int64_t per = kHeadRowsPerPart;
     const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min((int64_t)B, r0 + per);
     float sw = 0.0f, sb = 0.0f, sl = 0.0f;
     for (int64_t r = r0 + rl; r < r1; r += 4) {
@@ -858,15 +860,21 @@ constexpr int kFcBK = 64, kFcLd = kFcBK + 16;   // rows of 160 bytes: conflict-f
 // kFcStore (plain store: a data gradient, as EpStore) or kFcHead (bias +
 // ReLU of the second dense layer, then the output layer on the block's rows:
 // hw holds the 64 output weights and the bias, logits receives one value per
-// row, out is not written; needs BN = 64 and one column tile). Blocks along y
+// row, out is not written; needs BN = 64 and one column tile) or
+// kFcHeadTrain (the same layer of a training step: the output layer, the
+// loss and its gradient on the block's 128 rows, as k_head_rows, k_head_dh2
+// and k_head_parts with parts of 128 rows do them: out receives dh2 [M][64],
+// parts the block's kHeadSums sums; labels as k_head_rows). Blocks along y
 // take further column tiles of BN.
-constexpr int kFcRelu = 0, kFcStore = 1, kFcHead = 2;
+constexpr int kFcRelu = 0, kFcStore = 1, kFcHead = 2, kFcHeadTrain = 3;
 template <int BN, int EPI = kFcRelu>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_fc_bf16(int M, int K, const uint16_t* __restrict__ A,
                                                  const uint16_t* __restrict__ W,
                                                  const float* __restrict__ bias,
                                                  uint16_t* __restrict__ out, int ldo,
-                                                 const float* __restrict__ hw, float* __restrict__ logits) {
+                                                 const float* __restrict__ hw, float* __restrict__ logits,
+                                                 const float* __restrict__ labels = nullptr,
+                                                 float* __restrict__ parts = nullptr) {
     constexpr int BM = 128;
     constexpr int WN = BN / 2;                 // columns per wave
     constexpr int NJ = WN / 16;                // MFMA column blocks per wave
@@ -962,6 +970,60 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
             }
             logits[m0 + tid] = z;
         }
+    } else if constexpr (EPI == kFcHeadTrain) {
+        static_assert(BN == 64, "the output layer reads whole 64-wide rows");
+        constexpr int kHLd = 72;
+        uint16_t* hs = sa[0];
+        float* rowv = reinterpret_cast<float*>(sb[0]);   // dz [128], loss terms [128], then [4][kHeadSums]
+        static_assert(256 + 4 * kHeadSums <= BN * kFcLd / 2, "fits the first W buffer");
+        __syncthreads();   // every wave has finished its last fragment reads
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < NJ; ++j) {
+                const int n = wn * WN + j * 16 + r;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    hs[(wm * 64 + i * 16 + q * 4 + e) * kHLd + n] = f2bf(fmaxf(acc[i][j][e] + bias[n], 0.0f));
+            }
+        __syncthreads();
+        if (tid < BM) {
+            float dz = 0.0f, lt = 0.0f;
+            if (m0 + tid < M) {
+                float z = hw[64];
+                for (int i = 0; i < 64; ++i) z += bf2f(hs[tid * kHLd + i]) * hw[i];
+                if (logits) logits[m0 + tid] = z;
+                const float y = labels[m0 + tid];
+                lt = fmaxf(z, 0.0f) - z * y + log1pf(expf(-fabsf(z)));
+                dz = (1.0f / (1.0f + expf(-z)) - y) / (float)M;
+            }
+            rowv[tid] = dz;
+            rowv[BM + tid] = lt;
+        }
+        __syncthreads();
+        for (int k = 0; k < BM * 64 / 256; ++k) {
+            const int idx = tid + k * 256, row = idx >> 6, i = idx & 63;
+            if (m0 + row < M)
+                out[(int64_t)(m0 + row) * 64 + i] =
+                    f2bf(bf2f(hs[row * kHLd + i]) > 0.0f ? rowv[row] * hw[i] : 0.0f);
+        }
+        float* red = rowv + 2 * BM;
+        {
+            const int i = tid & 63, rl = tid >> 6;
+            const int nrows = min(BM, M - m0);
+            float sw = 0.0f, sbias = 0.0f, sl = 0.0f;
+            for (int rr = rl; rr < nrows; rr += 4) {
+                const float dz = rowv[rr];
+                sw += dz * bf2f(hs[rr * kHLd + i]);
+                if (i == 0) { sbias += dz; sl += rowv[BM + rr]; }
+            }
+            red[rl * kHeadSums + i] = sw;
+            if (i == 0) { red[rl * kHeadSums + 64] = sbias; red[rl * kHeadSums + 65] = sl; }
+        }
+        __syncthreads();
+        if (tid < kHeadSums) {
+            float t = 0.0f;
+            for (int l = 0; l < 4; ++l) t += red[l * kHeadSums + tid];
+            parts[(int64_t)blockIdx.x * kHeadSums + tid] = t;
+        }
     } else {
     for (int i = 0; i < 4; ++i)
         for (int j = 0; j < NJ; ++j) {
@@ -991,18 +1053,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 // output.
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) void glb_void_t;
-constexpr int kF1BN = 256, kF1BK = 32, kF1Stages = 4;
+constexpr int kF1BN = 256, kF1BK = 32;
 
-// BM = 256 (16 waves) when the rows fill the chip, else 128 (8 waves).
+// BM = 256 (16 waves), 128 (8 waves) or 64 (4 waves): the largest whose
+// blocks fill the chip.
+// Smaller row tiles keep more stages (LDS allowing), so that about as many
+// bytes stay in flight per CU.
 template <int BM>
 __global__ __launch_bounds__(BM * 4, 1) void k_fc1_bf16(int M, int K, const uint16_t* __restrict__ A,
                                                       const uint16_t* __restrict__ W,
                                                       const float* __restrict__ bias,
                                                       uint16_t* __restrict__ out) {
+    constexpr int kF1Stages = BM == 64 ? 7 : (BM == 128 ? 5 : 4);
     constexpr int kWaves = BM / 16;                   // 16 rows of A per wave per step
     constexpr int kWLoads = kF1BN / 16 / kWaves;      // W loads per wave per step
     constexpr int kLoads = 1 + kWLoads;               // loads per wave per step
     constexpr int kStageA = BM * kF1BK * 2, kStageB = kF1BN * kF1BK * 2;   // bytes per stage
+    static_assert((kF1Stages - 2) * kLoads <= 63, "vmcnt range");
     __shared__ __attribute__((aligned(1024))) char smem[kF1Stages * (kStageA + kStageB)];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, q = lane >> 4;
@@ -1014,15 +1081,16 @@ __global__ __launch_bounds__(BM * 4, 1) void k_fc1_bf16(int M, int K, const uint
     const int lr = lane >> 2;
     const int lchunk = (lane & 3) ^ (((lr >> 2) & 1) << 1);
     const uint16_t* ga = A + (int64_t)min(m0 + wave * 16 + lr, M - 1) * K + lchunk * 8;   // rows past M: never stored
+    // W is k-blocked ([K/32][256][32]): a step's slice is contiguous
     const uint16_t* gw[kWLoads];
-    for (int j = 0; j < kWLoads; ++j) gw[j] = W + (int64_t)((wave * kWLoads + j) * 16 + lr) * K + lchunk * 8;
+    for (int j = 0; j < kWLoads; ++j) gw[j] = W + ((wave * kWLoads + j) * 16 + lr) * kF1BK + lchunk * 8;
     auto stage_a = [&](int st) { return smem + st * (kStageA + kStageB); };
     auto stage_b = [&](int st) { return smem + st * (kStageA + kStageB) + kStageA; };
     auto issue = [&](int step) {
         const int st = step % kF1Stages, k0 = step * kF1BK;
         __builtin_amdgcn_global_load_lds((glb_void_t*)(ga + k0), (lds_void_t*)(stage_a(st) + wave * 1024), 16, 0, 0);
         for (int j = 0; j < kWLoads; ++j)
-            __builtin_amdgcn_global_load_lds((glb_void_t*)(gw[j] + k0),
+            __builtin_amdgcn_global_load_lds((glb_void_t*)(gw[j] + (int64_t)step * kF1BN * kF1BK),
                                              (lds_void_t*)(stage_b(st) + (wave * kWLoads + j) * 1024), 16, 0, 0);
     };
     auto frag = [&](const char* base, int rw, int chunk) {
@@ -1034,13 +1102,21 @@ __global__ __launch_bounds__(BM * 4, 1) void k_fc1_bf16(int M, int K, const uint
     const int steps = K / kF1BK;
     for (int i = 0; i < kF1Stages - 1 && i < steps; ++i) issue(i);
     for (int st = 0; st < steps; ++st) {
-        // this wave's loads of step st are done (2 per step; those of the
-        // next steps may still be in flight), then every wave's, and every
-        // wave is done reading the stage that step st + 3 refills (a bare
-        // barrier: __syncthreads' fence would also wait for the later loads)
-        if (st + 2 < steps) __builtin_amdgcn_s_waitcnt(0x0F70 | (2 * kLoads));   // vmcnt(2 steps)
-        else if (st + 1 < steps) __builtin_amdgcn_s_waitcnt(0x0F70 | kLoads);   // vmcnt(1 step)
-        else __builtin_amdgcn_s_waitcnt(0x0F70);                                // vmcnt(0)
+        // this wave's loads of step st are done (kLoads per step; those of
+        // the next steps may still be in flight), then every wave's, and
+        // every wave is done reading the stage that step st + stages - 1
+        // refills (a bare barrier: __syncthreads' fence would also wait for
+        // the later loads)
+        const int ahead = min(kF1Stages - 2, steps - 1 - st);   // later steps already issued
+        switch (ahead) {
+            case 5: __builtin_amdgcn_s_waitcnt(0x0F70 | (5 * kLoads)); break;
+            case 4: __builtin_amdgcn_s_waitcnt(0x0F70 | (4 * kLoads)); break;
+            case 3: __builtin_amdgcn_s_waitcnt(0x0F70 | (3 * kLoads)); break;
+            case 2: __builtin_amdgcn_s_waitcnt(0x0F70 | (2 * kLoads)); break;
+            case 1: __builtin_amdgcn_s_waitcnt(0x0F70 | kLoads); break;
+            default: __builtin_amdgcn_s_waitcnt(0x0F70); break;
+        }
+        static_assert(kF1Stages - 2 <= 5, "waits listed above");
         __builtin_amdgcn_sched_barrier(0);
         __builtin_amdgcn_s_barrier();
         __builtin_amdgcn_sched_barrier(0);
@@ -1431,6 +1507,11 @@ __global__ __launch_bounds__(256, CIN == 16 ? 3 : 2) void k_conv_dw_bf16(int B, 
                                                          float* __restrict__ part_out) {
     using S = DwShape<L, CIN, COUT, WN, WK>;
     constexpr int MT = S::MT, NTW = S::NTW;
+    constexpr int NA = 36 * (CIN / 8), ND = 16 * (COUT / 4);   // staging units per chunk
+    static_assert(NA <= 256 && ND <= 256, "one unit of each kind per thread");
+    // CIN 32: both units' loads issued together (two blocks per CU); CIN 16:
+    // one unit after the other, in the registers three blocks per CU allow
+    constexpr bool kHoist = CIN == 32;
     static_assert(WN * WK == 4 && S::NT % WN == 0, "wave split");
     static_assert(L % 32 == 0 && CIN % 16 == 0 && COUT % 16 == 0, "tile shapes");
     __shared__ __attribute__((aligned(16))) uint8_t smem[S::BYTES];
@@ -1461,66 +1542,131 @@ __global__ __launch_bounds__(256, CIN == 16 ? 3 : 2) void k_conv_dw_bf16(int B, 
     for (int g = g0; g < g1; ++g) {
 #pragma unroll 1
         for (int c = 0; c < L / 32; ++c) {
-            __syncthreads();   // the previous chunk's fragments are read
-            // input positions c*32 - 2 ... c*32 + 33 (circular)
-#pragma unroll 1
-            for (int t = tid; t < 36 * (CIN / 8); t += 256) {
-                const int pi = t / (CIN / 8), cg = t - pi * (CIN / 8);
+            if constexpr (kHoist) {
+                // a thread has at most one input unit (8 inputs x 8 channels at
+                // one of positions c*32 - 2 ... c*32 + 33, circular) and one
+                // gradient unit (8 inputs x 4 channels of one pooled position);
+                // both are loaded before either is used (indices past the units
+                // or the batch are clamped and their values dropped), so one
+                // memory latency is paid per chunk
+                const int ta = min(tid, NA - 1), td = min(tid, ND - 1);
+                const int pi = ta / (CIN / 8), cg = ta - pi * (CIN / 8);
                 int pos = c * 32 + pi - 2;
                 pos = pos < 0 ? pos + L : (pos >= L ? pos - L : pos);
+                const int xi = td / (COUT / 4), og = td - xi * (COUT / 4);
                 uint4 v[8];
-                for (int s = 0; s < 8; ++s) {
-                    const int64_t b = (int64_t)g * 8 + s;
-                    v[s] = b < B ? *reinterpret_cast<const uint4*>(act + (b * L + pos) * CIN + cg * 8)
-                                 : make_uint4(0u, 0u, 0u, 0u);
-                }
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    *reinterpret_cast<uint4*>(aq + dw_slot(pi, cg * 8 + j, CIN) * 8) = tr8(v, j);
-            }
-            // gradient at pre-activation positions c*32 ... c*32 + 31, 4
-            // channels of one pooled position per task: the even positions'
-            // values are formed and stored, then the odd ones'
-#pragma unroll 1
-            for (int t = tid; t < 16 * (COUT / 4); t += 256) {
-                const int xi = t / (COUT / 4), og = t - xi * (COUT / 4);
-                const int xp = c * 16 + xi;
                 uint2 gv[8];
                 uint32_t kv[8];
-#pragma unroll
+    #pragma unroll
                 for (int s = 0; s < 8; ++s) {
-                    const int64_t b = (int64_t)g * 8 + s;
-                    gv[s] = make_uint2(0u, 0u);
-                    kv[s] = 0u;
-                    if (b < B) {
-                        const int64_t o = (b * (L / 2) + xp) * COUT + og * 4;
-                        gv[s] = *reinterpret_cast<const uint2*>(dact + o);
-                        kv[s] = *reinterpret_cast<const uint32_t*>(mask + o);
+                    const int64_t b = min<int64_t>((int64_t)g * 8 + s, B - 1);
+                    v[s] = *reinterpret_cast<const uint4*>(act + (b * L + pos) * CIN + cg * 8);
+                    const int64_t o = (b * (L / 2) + c * 16 + xi) * COUT + og * 4;
+                    gv[s] = *reinterpret_cast<const uint2*>(dact + o);
+                    kv[s] = *reinterpret_cast<const uint32_t*>(mask + o);
+                }
+                const int nval = (int)min<int64_t>(8, (int64_t)B - (int64_t)g * 8);
+    #pragma unroll
+                for (int s = 0; s < 8; ++s)
+                    if (s >= nval) {
+                        v[s] = make_uint4(0u, 0u, 0u, 0u);
+                        kv[s] = 0u;   // a zero mask keeps nothing
+                    }
+                __syncthreads();   // the previous chunk's fragments are read
+                if (tid < NA)
+    #pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        *reinterpret_cast<uint4*>(aq + dw_slot(pi, cg * 8 + j, CIN) * 8) = tr8(v, j);
+                // gradient at pre-activation positions c*32 ... c*32 + 31: the
+                // even positions' values are formed and stored, then the odd ones'
+                if (tid < ND) {
+    #pragma unroll
+                    for (int s = 0; s < 8; ++s)
+    #pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const uint32_t h = (j < 2 ? gv[s].x : gv[s].y) >> (16 * (j & 1));
+                            db[j] += (kv[s] >> (8 * j) & 2u) ? bf2f((uint16_t)h) : 0.0f;
+                        }
+    #pragma unroll
+                    for (int par = 0; par < 2; ++par) {
+                        const uint32_t sel = 2u | (uint32_t)par;
+                        uint32_t e[8][4];
+    #pragma unroll
+                        for (int s = 0; s < 8; ++s)
+    #pragma unroll
+                            for (int j = 0; j < 4; ++j) {
+                                const uint32_t h = ((j < 2 ? gv[s].x : gv[s].y) >> (16 * (j & 1))) & 0xffffu;
+                                e[s][j] = ((kv[s] >> (8 * j)) & 3u) == sel ? h : 0u;
+                            }
+    #pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            *reinterpret_cast<uint4*>(dq + dw_slot(2 * xi + par, og * 4 + j, COUT) * 8) =
+                                make_uint4(e[0][j] | (e[1][j] << 16), e[2][j] | (e[3][j] << 16),
+                                           e[4][j] | (e[5][j] << 16), e[6][j] | (e[7][j] << 16));
                     }
                 }
-#pragma unroll
-                for (int s = 0; s < 8; ++s)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const uint32_t h = (j < 2 ? gv[s].x : gv[s].y) >> (16 * (j & 1));
-                        db[j] += (kv[s] >> (8 * j) & 2u) ? bf2f((uint16_t)h) : 0.0f;
+            } else {
+                __syncthreads();   // the previous chunk's fragments are read
+                // input positions c*32 - 2 ... c*32 + 33 (circular)
+    #pragma unroll 1
+                for (int t = tid; t < 36 * (CIN / 8); t += 256) {
+                    const int pi = t / (CIN / 8), cg = t - pi * (CIN / 8);
+                    int pos = c * 32 + pi - 2;
+                    pos = pos < 0 ? pos + L : (pos >= L ? pos - L : pos);
+                    uint4 v[8];
+                    for (int s = 0; s < 8; ++s) {
+                        const int64_t b = (int64_t)g * 8 + s;
+                        v[s] = b < B ? *reinterpret_cast<const uint4*>(act + (b * L + pos) * CIN + cg * 8)
+                                     : make_uint4(0u, 0u, 0u, 0u);
                     }
-#pragma unroll
-                for (int par = 0; par < 2; ++par) {
-                    const uint32_t sel = 2u | (uint32_t)par;
-                    uint32_t e[8][4];
-#pragma unroll
-                    for (int s = 0; s < 8; ++s)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const uint32_t h = ((j < 2 ? gv[s].x : gv[s].y) >> (16 * (j & 1))) & 0xffffu;
-                            e[s][j] = ((kv[s] >> (8 * j)) & 3u) == sel ? h : 0u;
+    #pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        *reinterpret_cast<uint4*>(aq + dw_slot(pi, cg * 8 + j, CIN) * 8) = tr8(v, j);
+                }
+                // gradient at pre-activation positions c*32 ... c*32 + 31, 4
+                // channels of one pooled position per task: the even positions'
+                // values are formed and stored, then the odd ones'
+    #pragma unroll 1
+                for (int t = tid; t < 16 * (COUT / 4); t += 256) {
+                    const int xi = t / (COUT / 4), og = t - xi * (COUT / 4);
+                    const int xp = c * 16 + xi;
+                    uint2 gv[8];
+                    uint32_t kv[8];
+    #pragma unroll
+                    for (int s = 0; s < 8; ++s) {
+                        const int64_t b = (int64_t)g * 8 + s;
+                        gv[s] = make_uint2(0u, 0u);
+                        kv[s] = 0u;
+                        if (b < B) {
+                            const int64_t o = (b * (L / 2) + xp) * COUT + og * 4;
+                            gv[s] = *reinterpret_cast<const uint2*>(dact + o);
+                            kv[s] = *reinterpret_cast<const uint32_t*>(mask + o);
                         }
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        *reinterpret_cast<uint4*>(dq + dw_slot(2 * xi + par, og * 4 + j, COUT) * 8) =
-                            make_uint4(e[0][j] | (e[1][j] << 16), e[2][j] | (e[3][j] << 16),
-                                       e[4][j] | (e[5][j] << 16), e[6][j] | (e[7][j] << 16));
+                    }
+    #pragma unroll
+                    for (int s = 0; s < 8; ++s)
+    #pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const uint32_t h = (j < 2 ? gv[s].x : gv[s].y) >> (16 * (j & 1));
+                            db[j] += (kv[s] >> (8 * j) & 2u) ? bf2f((uint16_t)h) : 0.0f;
+                        }
+    #pragma unroll
+                    for (int par = 0; par < 2; ++par) {
+                        const uint32_t sel = 2u | (uint32_t)par;
+                        uint32_t e[8][4];
+    #pragma unroll
+                        for (int s = 0; s < 8; ++s)
+    #pragma unroll
+                            for (int j = 0; j < 4; ++j) {
+                                const uint32_t h = ((j < 2 ? gv[s].x : gv[s].y) >> (16 * (j & 1))) & 0xffffu;
+                                e[s][j] = ((kv[s] >> (8 * j)) & 3u) == sel ? h : 0u;
+                            }
+    #pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            *reinterpret_cast<uint4*>(dq + dw_slot(2 * xi + par, og * 4 + j, COUT) * 8) =
+                                make_uint4(e[0][j] | (e[1][j] << 16), e[2][j] | (e[3][j] << 16),
+                                           e[4][j] | (e[5][j] << 16), e[6][j] | (e[7][j] << 16));
+                    }
                 }
             }
             __syncthreads();
@@ -1826,10 +1972,13 @@ __device__ __forceinline__ float wave_sum_dpp(float v) {
 // channels. Per-block sums go to part_out[block][96] (80 weights [co][dx],
 // then 16 biases: the canonical order), added up in block order.
 template <bool kXF32>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_conv1_dw_bf16(
+__global__ __launch_bounds__(256, 2) void k_conv1_dw_bf16(
     const uint16_t* __restrict__ dact, const uint8_t* __restrict__ mask, const void* __restrict__ x, int B,
     int groups_per_block, float* __restrict__ part_out) {
-    __shared__ __attribute__((aligned(16))) uint16_t sd[8 * 128 * 16];
+    // the gradients' two 16-byte halves (channels 0-7, 8-15) in two arrays,
+    // the second 8 slots further on: conflict-free writes and reads
+    constexpr int kHalf2 = 1024 + 8;
+    __shared__ __attribute__((aligned(16))) uint16_t sd[(kHalf2 + 1024) * 8];
     __shared__ __attribute__((aligned(16))) uint8_t smk[8 * 128 * 16];
     __shared__ __attribute__((aligned(16))) uint16_t sx[8 * 256];
     __shared__ float red[96][4];
@@ -1870,7 +2019,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
     };
     if (g0 < g1) load(g0);
     for (int g = g0; g < g1; ++g) {
-        for (int i = 0; i < 8; ++i) reinterpret_cast<uint4*>(sd)[tid + i * 256] = rd[i];
+        for (int i = 0; i < 8; ++i) {
+            const int c = tid + i * 256;
+            reinterpret_cast<uint4*>(sd)[(c & 1) * kHalf2 + (c >> 1)] = rd[i];
+        }
         for (int i = 0; i < 4; ++i) reinterpret_cast<uint4*>(smk)[tid + i * 256] = rm[i];
         reinterpret_cast<uint4*>(sx)[tid] = rx;
         __syncthreads();
@@ -1883,8 +2035,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
                 xv[2 * h] = bf2f((uint16_t)(v & 0xffffu));
                 xv[2 * h + 1] = bf2f((uint16_t)(v >> 16));
             }
-            const uint4 ga = reinterpret_cast<const uint4*>(sd)[p * 2];
-            const uint4 gb = reinterpret_cast<const uint4*>(sd)[p * 2 + 1];
+            const uint4 ga = reinterpret_cast<const uint4*>(sd)[p];
+            const uint4 gb = reinterpret_cast<const uint4*>(sd)[kHalf2 + p];
             const uint4 mk = reinterpret_cast<const uint4*>(smk)[p];
             const uint32_t gw[8] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
             const uint32_t kw[4] = {mk.x, mk.y, mk.z, mk.w};
@@ -2053,7 +2205,7 @@ __global__ __launch_bounds__(256) void k_pack(const float* __restrict__ w, typen
                                               typename P::T* __restrict__ wb3, typename P::T* __restrict__ wf4,
                                               typename P::T* __restrict__ wb4, typename P::T* __restrict__ f1f,
                                               typename P::T* __restrict__ f1b, typename P::T* __restrict__ f2f,
-                                              typename P::T* __restrict__ f2b) {
+                                              typename P::T* __restrict__ f2b, typename P::T* __restrict__ f1k) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     // conv l = 2..4: canonical [co][ci][dx]
     typename P::T* wf[5] = {nullptr, nullptr, wf2, wf3, wf4};
@@ -2074,6 +2226,9 @@ __global__ __launch_bounds__(256) void k_pack(const float* __restrict__ w, typen
         const typename P::T v = P::from_f(w[F1W + i]);
         f1f[(int64_t)o * 1024 + j] = v;
         f1b[(int64_t)j * 256 + o] = v;
+        // k-blocked copy for k_fc1_bf16: [j / 32][o][j % 32], one 32-column
+        // slice of the layer a contiguous 16 KB
+        f1k[((int64_t)(j >> 5) * 256 + o) * 32 + (j & 31)] = v;
     }
     if (i < 64 * 256) {
         const int o = (int)(i >> 8), ii = (int)(i & 255);
@@ -2288,6 +2443,7 @@ struct gpfc_cnn {
     int32_t n_cu = 256;
     // views into work (element type per prec)
     void *wf2, *wb2, *wf3, *wb3, *wf4, *wb4, *f1f, *f1b, *f2f, *f2b;
+    void* f1k;                                // the first dense layer, k-blocked (k_fc1_bf16)
     void *a1, *a2, *a3, *a4, *h1, *h2;       // activations
     void *d_a, *d_b;                          // gradient scratch (largest activation size)
     uint8_t *m1, *m2, *m3, *m4;
@@ -2323,7 +2479,7 @@ int32_t pack(gpfc_cnn* c, hipStream_t s) {
     using T = typename P::T;
     hipLaunchKernelGGL((gcnn::k_pack<P>), dim3(gcnn::blocks_for(256 * 1024)), dim3(256), 0, s,
                        c->params, (T*)c->wf2, (T*)c->wb2, (T*)c->wf3, (T*)c->wb3, (T*)c->wf4,
-                       (T*)c->wb4, (T*)c->f1f, (T*)c->f1b, (T*)c->f2f, (T*)c->f2b);
+                       (T*)c->wb4, (T*)c->f1f, (T*)c->f1b, (T*)c->f2f, (T*)c->f2b, (T*)c->f1k);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cnn_err(e, "k_pack");
     c->packed = !capturing(s);   // a captured pack runs only when the graph does
@@ -2388,24 +2544,28 @@ int32_t forward(gpfc_cnn* c, const void* x, int xf32, int B, float* logits, cons
         // batches 128 x 64 tiles of the generic staged kernel (same bits)
         if ((B + 255) / 256 >= c->n_cu)
             hipLaunchKernelGGL(k_fc1_bf16<256>, dim3((unsigned)((B + 255) / 256)), dim3(1024), 0, s, B, 1024,
-                               (const uint16_t*)c->a4, (const uint16_t*)c->f1f, w + F1B, (uint16_t*)c->h1);
-        else if ((B + 127) / 128 >= c->n_cu / 2)
+                               (const uint16_t*)c->a4, (const uint16_t*)c->f1k, w + F1B, (uint16_t*)c->h1);
+        else if ((B + 127) / 128 >= c->n_cu)
             hipLaunchKernelGGL(k_fc1_bf16<128>, dim3((unsigned)((B + 127) / 128)), dim3(512), 0, s, B, 1024,
-                               (const uint16_t*)c->a4, (const uint16_t*)c->f1f, w + F1B, (uint16_t*)c->h1);
+                               (const uint16_t*)c->a4, (const uint16_t*)c->f1k, w + F1B, (uint16_t*)c->h1);
+        else if ((B + 63) / 64 >= c->n_cu / 2)
+            hipLaunchKernelGGL(k_fc1_bf16<64>, dim3((unsigned)((B + 63) / 64)), dim3(256), 0, s, B, 1024,
+                               (const uint16_t*)c->a4, (const uint16_t*)c->f1k, w + F1B, (uint16_t*)c->h1);
         else
             hipLaunchKernelGGL((k_fc_bf16<64, kFcRelu>), dim3((unsigned)((B + 127) / 128), 4), dim3(256), 0, s, B,
                                1024, (const uint16_t*)c->a4, (const uint16_t*)c->f1f, w + F1B, (uint16_t*)c->h1, 256,
                                nullptr, nullptr);
         // inference: the output layer runs in the second dense layer's
-        // epilogue (h2 never reaches memory); training keeps h2 for backward
+        // epilogue (h2 never reaches memory); training: the output layer,
+        // loss and dh2 in the same epilogue, then the part sums added up
         if (!train)
             hipLaunchKernelGGL((k_fc_bf16<64, kFcHead>), dim3((unsigned)((B + 127) / 128), 1), dim3(256), 0, s, B,
                                256, (const uint16_t*)c->h1, (const uint16_t*)c->f2f, w + F2B, nullptr, 64, w + F3W,
-                               logits);
+                               logits, nullptr, nullptr);
         else
-            hipLaunchKernelGGL(k_fc_bf16<64>, dim3((unsigned)((B + 127) / 128), 1), dim3(256), 0, s, B, 256,
-                               (const uint16_t*)c->h1, (const uint16_t*)c->f2f, w + F2B, (uint16_t*)c->h2,
-                               64, nullptr, nullptr);
+            hipLaunchKernelGGL((k_fc_bf16<64, kFcHeadTrain>), dim3((unsigned)((B + 127) / 128), 1), dim3(256), 0, s,
+                               B, 256, (const uint16_t*)c->h1, (const uint16_t*)c->f2f, w + F2B, (uint16_t*)c->d_a,
+                               64, w + F3W, logits, labels, c->ws);
         e = hipGetLastError();
         if (e != hipSuccess) return cnn_err(e, "fc gemm");
     } else {
@@ -2417,16 +2577,21 @@ int32_t forward(gpfc_cnn* c, const void* x, int xf32, int B, float* logits, cons
     if (e != hipSuccess) return cnn_err(e, "fc2 gemm");
     }
     if (train) {
-        // workspace: rows [2 B], then the part sums [parts][kHeadSums]
-        const int parts = (int)std::max<int64_t>(1, std::min<int64_t>(1024, B / 256));
-        float* rows = c->ws;
-        float* psum = c->ws + 2 * (int64_t)B;
-        hipLaunchKernelGGL((k_head_rows<P>), dim3(blocks_for(B)), dim3(256), 0, s, (const T*)c->h2, B,
-                           w + F3W, w + F3B, labels, logits, rows);
-        hipLaunchKernelGGL((k_head_dh2<P>), dim3(blocks_for((int64_t)B * 64)), dim3(256), 0, s,
-                           (const T*)c->h2, B, w + F3W, rows, (T*)c->d_a);
-        hipLaunchKernelGGL((k_head_parts<P>), dim3((unsigned)parts), dim3(256), 0, s, (const T*)c->h2, B,
-                           rows, psum);
+        // parts of kHeadRowsPerPart rows; the fused layer left their sums at
+        // the start of the workspace, the layer path keeps rows [2 B] there
+        // and the part sums after them
+        const int parts = (int)((B + kHeadRowsPerPart - 1) / kHeadRowsPerPart);
+        float* psum = c->ws;
+        if (!fused) {
+            float* rows = c->ws;
+            psum = c->ws + 2 * (int64_t)B;
+            hipLaunchKernelGGL((k_head_rows<P>), dim3(blocks_for(B)), dim3(256), 0, s, (const T*)c->h2, B,
+                               w + F3W, w + F3B, labels, logits, rows);
+            hipLaunchKernelGGL((k_head_dh2<P>), dim3(blocks_for((int64_t)B * 64)), dim3(256), 0, s,
+                               (const T*)c->h2, B, w + F3W, rows, (T*)c->d_a);
+            hipLaunchKernelGGL((k_head_parts<P>), dim3((unsigned)parts), dim3(256), 0, s, (const T*)c->h2, B,
+                               rows, psum);
+        }
         hipLaunchKernelGGL(k_head_final, dim3((kHeadSums + 3) / 4), dim3(256), 0, s, psum, parts, B,
                            c->grad, c->loss);
     } else if (logits && !fused)
@@ -2617,8 +2782,8 @@ int32_t gpfc_cnn_create(gpfc_cnn** out, int32_t device, int32_t precision, int64
     const size_t E = elt(c);
     const int64_t Bm = max_batch;
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    size_t wsz[10] = {32 * 80, 16 * 160, 64 * 160, 32 * 320, 64 * 320, 64 * 320,
-                      256 * 1024, 1024 * 256, 64 * 256, 256 * 64};
+    size_t wsz[11] = {32 * 80, 16 * 160, 64 * 160, 32 * 320, 64 * 320, 64 * 320,
+                      256 * 1024, 1024 * 256, 64 * 256, 256 * 64, 256 * 1024};
     size_t asz[6] = {(size_t)Bm * 128 * 16, (size_t)Bm * 64 * 32, (size_t)Bm * 32 * 64,
                      (size_t)Bm * 16 * 64, (size_t)Bm * 256, (size_t)Bm * 64};
     const size_t dsz = (size_t)Bm * 256 * 16;   // largest pre-pool gradient (block 1)
@@ -2629,7 +2794,8 @@ int32_t gpfc_cnn_create(gpfc_cnn** out, int32_t device, int32_t precision, int64
     for (int i = 0; i < 4; ++i) total += al(asz[i]);   // masks
     const size_t fsz = al(sizeof(float) * gcnn::kNP);
     // the reduction workspace also holds the output layer's rows and part sums
-    const int64_t wsn = std::max<int64_t>(gcnn::kSplitWs, 2 * Bm + 1024 * gcnn::kHeadSums);
+    const int64_t wsn = std::max<int64_t>(
+        gcnn::kSplitWs, 2 * Bm + (Bm / gcnn::kHeadRowsPerPart + 1) * gcnn::kHeadSums);
     total += 4 * fsz + 256 + al(sizeof(float) * wsn);
     const size_t qsz[5] = {32 * 80, 64 * 160, 64 * 320, 256 * 1024, 64 * 256};
     const size_t csz[5] = {32, 64, 64, 256, 64};
@@ -2650,8 +2816,9 @@ int32_t gpfc_cnn_create(gpfc_cnn** out, int32_t device, int32_t precision, int64
     c->v = (float*)take(sizeof(float) * gcnn::kNP);
     c->loss = (float*)take(256);
     c->ws = (float*)take(sizeof(float) * wsn);
-    void** wv[10] = {&c->wf2, &c->wb2, &c->wf3, &c->wb3, &c->wf4, &c->wb4, &c->f1f, &c->f1b, &c->f2f, &c->f2b};
-    for (int i = 0; i < 10; ++i) *wv[i] = take(wsz[i] * E);
+    void** wv[11] = {&c->wf2, &c->wb2, &c->wf3, &c->wb3, &c->wf4, &c->wb4, &c->f1f, &c->f1b, &c->f2f, &c->f2b,
+                     &c->f1k};
+    for (int i = 0; i < 11; ++i) *wv[i] = take(wsz[i] * E);
     void** av[6] = {&c->a1, &c->a2, &c->a3, &c->a4, &c->h1, &c->h2};
     for (int i = 0; i < 6; ++i) *av[i] = take(asz[i] * E);
     c->d_a = take(dsz * E);
