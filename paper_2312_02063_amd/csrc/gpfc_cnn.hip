@@ -897,7 +897,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 #pragma unroll
         for (int c = 0; c < BCH; ++c) {
             const int idx = tid + c * 256, row = idx >> 3, col = (idx & 7) * 8;
-            rb[c] = *reinterpret_cast<const uint4*>(W + (int64_t)(n0 + row) * K + k0 + col);
+            rb[c] = ld_u4(W + (int64_t)(n0 + row) * K + k0 + col);
         }
     };
     auto store = [&](int buf) {
@@ -1025,7 +1025,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
             parts[(int64_t)blockIdx.x * kHeadSums + tid] = t;
         }
     } else {
+#pragma unroll
     for (int i = 0; i < 4; ++i)
+#pragma unroll
         for (int j = 0; j < NJ; ++j) {
             const int n = n0 + wn * WN + j * 16 + r;
             const int mb = m0 + wm * 64 + i * 16 + q * 4;

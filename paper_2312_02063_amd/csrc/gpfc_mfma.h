@@ -12,6 +12,15 @@ namespace gcnn {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
+
+// A 16-byte load as a value. Assigning *reinterpret_cast<const uint4*>(p) to
+// an array element copies the struct with a memcpy that keeps the array in
+// scratch memory; loading a vector and rebuilding the uint4 does not.
+__device__ __forceinline__ uint4 ld_u4(const void* p) {
+    const u32x4v v = *reinterpret_cast<const u32x4v*>(p);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 // Round to nearest even bfloat16, NaN kept NaN: gfx950's v_cvt_pk_bf16_f32,
