@@ -302,6 +302,54 @@ __global__ __launch_bounds__(1024) void k_splitk_reduce_w(const float* __restric
     }
 }
 
+// The same sums, 4 consecutive outputs per lane (16-byte loads of each
+// partial row; M*N a multiple of 4): 256 outputs per block, each summed in
+// exactly the order of k_splitk_reduce_w (same bits). Launch with
+// ceil(M*N / 256) blocks of 1024.
+template <class EP>
+__global__ __launch_bounds__(1024) void k_splitk_reduce_w4(const float* __restrict__ ws, int S, int M, int N,
+                                                           EP ep) {
+    __shared__ float4 red[16][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t mn = (int64_t)M * N;
+    const int64_t i = ((int64_t)blockIdx.x * 64 + lane) * 4;
+    float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (i < mn)
+        for (int z = wave; z < S; z += 16) {
+            const float4 p = *reinterpret_cast<const float4*>(ws + z * mn + i);
+            v.x += p.x;
+            v.y += p.y;
+            v.z += p.z;
+            v.w += p.w;
+        }
+    red[wave][lane] = v;
+    __syncthreads();
+    if (wave == 0 && i < mn) {
+        float t[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int w = 0; w < 16; ++w) {
+            const float4 u = red[w][lane];
+            t[0] += u.x;
+            t[1] += u.y;
+            t[2] += u.z;
+            t[3] += u.w;
+        }
+        for (int c = 0; c < 4; ++c) ep.store((int)((i + c) / N), (int)((i + c) % N), t[c]);
+    }
+}
+
+// k_splitk_reduce_w4 where the outputs allow it and still give it blocks
+// enough to fill the chip, else k_splitk_reduce_w (4x the blocks).
+template <class EP>
+inline void reduce_partials_w(const float* ws, int S, int M, int N, EP ep, hipStream_t s) {
+    const int64_t mn = (int64_t)M * N;
+    if (mn % 4 == 0 && mn >= 512 * 256)
+        hipLaunchKernelGGL((k_splitk_reduce_w4<EP>), dim3((unsigned)((mn + 255) / 256)), dim3(1024), 0, s, ws, S, M,
+                           N, ep);
+    else
+        hipLaunchKernelGGL((k_splitk_reduce_w<EP>), dim3((unsigned)((mn + 63) / 64)), dim3(1024), 0, s, ws, S, M, N,
+                           ep);
+}
+
 // Weight and bias gradients of a conv block reduced together: partial rows
 // hold [COUT][5 CIN] weight sums, then COUT bias sums (M = 1, N = mn + COUT).
 struct EpConvDWB {
@@ -2387,8 +2435,7 @@ inline hipError_t fc_dw_bf16(int B, int M, int N, const uint16_t* d, const uint1
         hipLaunchKernelGGL(k_fc_dw_bf16<64>, grid, dim3(256), 0, s, B, M, N, kc, tiles_n, d, act, ws);
     const EpFcDWB epb{ep, gb, N, M * N};
     if (S >= 16)
-        hipLaunchKernelGGL(k_splitk_reduce_w<EpFcDWB>, dim3((unsigned)((row + 63) / 64)), dim3(1024), 0, s, ws, S,
-                           1, (int)row, epb);
+        reduce_partials_w(ws, S, 1, (int)row, epb, s);
     else
         hipLaunchKernelGGL(k_splitk_reduce<EpFcDWB>, dim3(blocks_for(row)), dim3(256), 0, s, ws, S, 1, (int)row,
                            epb);
@@ -2413,8 +2460,7 @@ hipError_t gemm_splitk(int M, int N, int K, LA la, LB lb, EP ep, float* ws, hipS
     hipLaunchKernelGGL((k_gemm<P, LA, LB, EpPartial>), grid, dim3(256), 0, s, M, N, K, kc, la, lb,
                        EpPartial{ws});
     if (S >= 16)
-        hipLaunchKernelGGL((k_splitk_reduce_w<EP>), dim3((unsigned)(((int64_t)M * N + 63) / 64)), dim3(1024), 0,
-                           s, ws, S, M, N, ep);
+        reduce_partials_w(ws, S, M, N, ep, s);
     else
         hipLaunchKernelGGL((k_splitk_reduce<EP>), dim3(blocks_for((int64_t)M * N)), dim3(256), 0, s, ws,
                            S, M, N, ep);
@@ -2628,8 +2674,7 @@ hipError_t conv_dw_bf16(const gpfc_cnn* c, int B, const uint16_t* dact, const ui
     else
         hipLaunchKernelGGL((k_conv_dw_bf16<L, CIN, COUT, WN, WK>), dim3((unsigned)blocks), dim3(256), 0, s, B, gpb,
                            dact, mask, act, c->ws);
-    hipLaunchKernelGGL((k_splitk_reduce_w<EpConvDWB>), dim3((unsigned)((row + 63) / 64)), dim3(1024), 0, s,
-                       c->ws, blocks, 1, (int)row, EpConvDWB{gw, gb, CIN, (int)mn});
+    reduce_partials_w(c->ws, blocks, 1, (int)row, EpConvDWB{gw, gb, CIN, (int)mn}, s);
     return hipGetLastError();
 }
 
