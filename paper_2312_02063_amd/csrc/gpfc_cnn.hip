@@ -34,6 +34,7 @@
 
 #include <algorithm>
 #include <new>
+#include <type_traits>
 #include <string.h>
 
 #include "../../include/gpfc.h"
@@ -708,6 +709,7 @@ struct ConvStackLdsW {
     uint16_t w2[32 * kW2Ld];
     uint16_t w3[64 * kW3Ld];
     uint16_t w4[64 * kW4Ld];
+    float bias[32 + 64 + 64];                    // blocks 2, 3, 4 (LDS reads: no wait on HBM stores)
     WaveSlice wv[kWP];
 };
 static_assert(128 * kA1Ld <= 32 * kA3Ld, "a1 must fit where a3 goes");
@@ -798,9 +800,12 @@ __device__ __forceinline__ void bytes_to_hbm(const uint8_t* __restrict__ lds, ui
 // pooled activations (a1 [B][128][16], a2 [B][64][32], a3 [B][32][64]) and
 // pooling masks (m1 ... m4, the same layouts) go to HBM for the backward
 // pass, with the values k_conv1_fwd and the EpConvFwd GEMMs would store.
-template <bool kTrain>
+// kXF32: the inputs are FP32 (rounded to bf16 when staged), else bf16 (a
+// template flag: a branch between the two loads made the compiler wait for
+// every store of the previous input before staging the next one).
+template <bool kTrain, bool kXF32>
 __global__ __launch_bounds__(kWP * 64, 1) void k_convstack_bf16_w(
-    const void* __restrict__ x, int xf32, int B, const float* __restrict__ w1,
+    const void* __restrict__ x, int B, const float* __restrict__ w1,
     const float* __restrict__ b1, const uint16_t* __restrict__ wf2, const float* __restrict__ b2,
     const uint16_t* __restrict__ wf3, const float* __restrict__ b3,
     const uint16_t* __restrict__ wf4, const float* __restrict__ b4, uint16_t* __restrict__ a4,
@@ -821,25 +826,37 @@ __global__ __launch_bounds__(kWP * 64, 1) void k_convstack_bf16_w(
         const int n = i / kW4Ld, k = i - n * kW4Ld;
         sm.w4[i] = k < 320 ? wf4[n * 320 + k] : (uint16_t)0;
     }
+    // the biases too: read from HBM in the loop, their waits would also wait
+    // for the stores issued before them
+    if (tid < 160) sm.bias[tid] = tid < 32 ? b2[tid] : (tid < 96 ? b3[tid - 32] : b4[tid - 96]);
     __syncthreads();   // the only block-wide wait: weights staged
     WaveSlice& ws = sm.wv[wave];
     const int64_t stride = (int64_t)gridDim.x * kWP;
     // the wave's inputs: blockIdx * kWP + wave, + stride, ...; the next one's
     // 8 bytes per lane are loaded while the current one is computed
     int64_t fi = (int64_t)blockIdx.x * kWP + wave;
-    auto load_in = [&](int64_t f) -> uint2 {
+    // (FP32 inputs are kept as loaded and rounded when staged, so the load
+    // is not waited for where it is issued)
+    using XT = typename std::conditional<kXF32, float4, uint2>::type;
+    auto load_in = [&](int64_t f) -> XT {
         f = f < B ? f : B - 1;   // (past the batch: read again, never used)
         const int64_t o = f * 256 + lane * 4;
-        if (xf32) {
-            const float4 v = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(x) + o);
-            return make_uint2((uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16),
-                              (uint32_t)f2bf(v.z) | ((uint32_t)f2bf(v.w) << 16));
+        if constexpr (kXF32) {
+            const u32x4v v = *reinterpret_cast<const u32x4v*>(reinterpret_cast<const float*>(x) + o);
+            return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z),
+                               __uint_as_float(v.w));
+        } else {
+            return *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(x) + o);
         }
-        return *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(x) + o);
     };
-    uint2 xnext = load_in(fi);
+    XT xnext = load_in(fi);
     for (; fi < B; fi += stride) {
-        reinterpret_cast<uint2*>(ws.xs)[lane] = xnext;
+        if constexpr (kXF32)
+            reinterpret_cast<uint2*>(ws.xs)[lane] =
+                make_uint2((uint32_t)f2bf(xnext.x) | ((uint32_t)f2bf(xnext.y) << 16),
+                           (uint32_t)f2bf(xnext.z) | ((uint32_t)f2bf(xnext.w) << 16));
+        else
+            reinterpret_cast<uint2*>(ws.xs)[lane] = xnext;
         xnext = load_in(fi + stride);
         wave_lds_sync();
         // conv1: lane = 2 pooled positions, all 16 channels (as k_conv1_fwd;
@@ -874,21 +891,21 @@ __global__ __launch_bounds__(kWP * 64, 1) void k_convstack_bf16_w(
         wave_lds_sync();
         // each block's pooled output (and, training, its masks) is formed in
         // LDS, then copied to HBM in 16-byte stores
-        conv_one<128, 16, kA1Ld, 32, kW2Ld, kA2Ld, 8, 2, kTrain>(ws.buf0, sm.w2, b2, ws.buf1, ws.mk);
+        conv_one<128, 16, kA1Ld, 32, kW2Ld, kA2Ld, 8, 2, kTrain>(ws.buf0, sm.w2, sm.bias, ws.buf1, ws.mk);
         wave_lds_sync();
         if constexpr (kTrain) {
             act_to_hbm<64, 32>(ws.buf1, a2g + fi * 2048);
             bytes_to_hbm<2048>(ws.mk, m2 + fi * 2048);
             wave_lds_sync();
         }
-        conv_one<64, 32, kA2Ld, 64, kW3Ld, kA3Ld, 4, 4, kTrain>(ws.buf1, sm.w3, b3, ws.buf0, ws.mk);
+        conv_one<64, 32, kA2Ld, 64, kW3Ld, kA3Ld, 4, 4, kTrain>(ws.buf1, sm.w3, sm.bias + 32, ws.buf0, ws.mk);
         wave_lds_sync();
         if constexpr (kTrain) {
             act_to_hbm<32, 64>(ws.buf0, a3g + fi * 2048);
             bytes_to_hbm<2048>(ws.mk, m3 + fi * 2048);
             wave_lds_sync();
         }
-        conv_one<32, 64, kA3Ld, 64, kW4Ld, kA3Ld, 2, 4, kTrain>(ws.buf0, sm.w4, b4, ws.buf1, ws.mk);
+        conv_one<32, 64, kA3Ld, 64, kW4Ld, kA3Ld, 2, 4, kTrain>(ws.buf0, sm.w4, sm.bias + 96, ws.buf1, ws.mk);
         wave_lds_sync();
         act_to_hbm<16, 64>(ws.buf1, a4 + fi * 1024);
         if constexpr (kTrain) bytes_to_hbm<1024>(ws.mk, m4 + fi * 1024);
@@ -2558,18 +2575,20 @@ int32_t forward(gpfc_cnn* c, const void* x, int xf32, int B, float* logits, cons
     if (fused) {
         const int ntiles = (B + kTileF - 1) / kTileF;
         const dim3 wgrid((unsigned)std::min<int64_t>((B + kWP - 1) / kWP, c->n_cu));
+        auto stack = [&](auto kernel, bool with_train_outputs) {
+            hipLaunchKernelGGL(kernel, wgrid, dim3(kWP * 64), 0, s, x, B, w + kConvW[1], w + conv_b(1),
+                               (const uint16_t*)c->wf2, w + conv_b(2), (const uint16_t*)c->wf3, w + conv_b(3),
+                               (const uint16_t*)c->wf4, w + conv_b(4), (uint16_t*)c->a4,
+                               with_train_outputs ? (uint16_t*)c->a1 : nullptr,
+                               with_train_outputs ? (uint16_t*)c->a2 : nullptr,
+                               with_train_outputs ? (uint16_t*)c->a3 : nullptr, with_train_outputs ? c->m1 : nullptr,
+                               with_train_outputs ? c->m2 : nullptr, with_train_outputs ? c->m3 : nullptr,
+                               with_train_outputs ? c->m4 : nullptr);
+        };
         if (train)
-            hipLaunchKernelGGL(k_convstack_bf16_w<true>, wgrid, dim3(kWP * 64), 0, s, x, xf32, B,
-                               w + kConvW[1], w + conv_b(1), (const uint16_t*)c->wf2, w + conv_b(2),
-                               (const uint16_t*)c->wf3, w + conv_b(3), (const uint16_t*)c->wf4,
-                               w + conv_b(4), (uint16_t*)c->a4, (uint16_t*)c->a1, (uint16_t*)c->a2,
-                               (uint16_t*)c->a3, c->m1, c->m2, c->m3, c->m4);
+            xf32 ? stack(k_convstack_bf16_w<true, true>, true) : stack(k_convstack_bf16_w<true, false>, true);
         else if (c->fused_mode == 1)
-            hipLaunchKernelGGL(k_convstack_bf16_w<false>, wgrid, dim3(kWP * 64), 0, s, x, xf32, B,
-                               w + kConvW[1], w + conv_b(1), (const uint16_t*)c->wf2, w + conv_b(2),
-                               (const uint16_t*)c->wf3, w + conv_b(3), (const uint16_t*)c->wf4,
-                               w + conv_b(4), (uint16_t*)c->a4, nullptr, nullptr, nullptr, nullptr,
-                               nullptr, nullptr, nullptr);
+            xf32 ? stack(k_convstack_bf16_w<false, true>, false) : stack(k_convstack_bf16_w<false, false>, false);
         else
             hipLaunchKernelGGL(k_convstack_bf16, dim3((unsigned)std::min(ntiles, c->n_cu)),
                                dim3(kFusedThreads), 0, s, x, xf32, B, w + kConvW[1], w + conv_b(1),
