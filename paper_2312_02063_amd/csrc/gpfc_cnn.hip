@@ -1492,17 +1492,16 @@ __global__ __launch_bounds__(kBP * 64, 1) void k_convstack_bwd_bf16(
     // of blocks 3 and 2 (two 16-byte groups each)
     uint4 ng[2], nk3[2], nk2[2];
     uint2 nk4[2];
+    // (unconditional: past the batch the last input is read again and never
+    // used, so the compiler counts the loads exactly and the wait for them
+    // leaves the stores issued after them in flight)
     auto load = [&](int64_t f) {
+        f = f < B ? f : B - 1;
         for (int h = 0; h < 2; ++h) {
-            if (f < B) {
-                ng[h] = *reinterpret_cast<const uint4*>(d4 + f * 1024 + h * 512 + lane * 8);
-                nk4[h] = *reinterpret_cast<const uint2*>(m4 + f * 1024 + h * 512 + lane * 8);
-                nk3[h] = *reinterpret_cast<const uint4*>(m3 + f * 2048 + h * 1024 + lane * 16);
-                nk2[h] = *reinterpret_cast<const uint4*>(m2 + f * 2048 + h * 1024 + lane * 16);
-            } else {
-                ng[h] = nk3[h] = nk2[h] = make_uint4(0u, 0u, 0u, 0u);
-                nk4[h] = make_uint2(0u, 0u);
-            }
+            ng[h] = ld_u4(d4 + f * 1024 + h * 512 + lane * 8);
+            nk4[h] = *reinterpret_cast<const uint2*>(m4 + f * 1024 + h * 512 + lane * 8);
+            nk3[h] = ld_u4(m3 + f * 2048 + h * 1024 + lane * 16);
+            nk2[h] = ld_u4(m2 + f * 2048 + h * 1024 + lane * 16);
         }
     };
     load(fi);
@@ -1516,6 +1515,7 @@ __global__ __launch_bounds__(kBP * 64, 1) void k_convstack_bwd_bf16(
             *reinterpret_cast<uint4*>(ws.buf0 + act_off<64>(2 * xp, c0)) = ev;
             *reinterpret_cast<uint4*>(ws.buf0 + act_off<64>(2 * xp + 1, c0)) = od;
         }
+        __builtin_amdgcn_sched_barrier(0);   // the loads stay after the staging (register pressure)
         load(fi + stride);
         wave_lds_sync();
         convT_one<32, 64, 64, 64, kB4Ld, 64, 2, 4, true>(ws.buf0, sm.w4, d3 + fi * 2048, m3s, ws.buf1);
