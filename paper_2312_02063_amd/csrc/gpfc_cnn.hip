@@ -20,8 +20,8 @@
 // layers as LDS-tiled GEMMs (k_fc1_bf16, k_fc_bf16, the second with the
 // output layer in its epilogue). A bf16 training step runs
 // the same stack in a variant that also writes the activations and pooling
-// masks to device memory, the backward data gradients down the blocks in one
-// kernel (k_convstack_bwd_bf16) and the convolution weight gradients over LDS
+// masks to device memory, the backward data gradients down the blocks one
+// kernel per block (k_convT_bf16) and the convolution weight gradients over LDS
 // tiles of 8 interleaved inputs (k_conv_dw_bf16, k_conv1_dw_bf16); FP32
 // networks and the layer path (gpfc_cnn_set_fused(0)) run layer by layer
 // through device memory. A step can be replayed as one HIP graph. Every fused
@@ -1324,74 +1324,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 
 // ------------------------------------------------------------------ fused backward of the convolution blocks (bf16)
 //
-// Data gradients. One wave per input carries the pooled gradient of block 4
-// down to block 1, as k_convstack_bf16_w carries the input up: the block's
-// gradient is unpooled with its mask into LDS, the transposed circular
-// convolution runs on MFMA with the backward weights (k in the same 32-steps
-// as k_gemm with ConvRows and sgn -1, rounded as EpStore rounds: the result is
-// bit-identical to the layer path), and the result (the pooled gradient of
-// the block below) goes to HBM for that block's weight gradient and, unpooled
-// with that block's mask, into LDS for the next step down.
-// LDS layouts as in the forward stack: unpooled gradients dpre4 [32][64],
-// dpre3 [64][64], dpre2 [128][32] in rows of their exact length with the
-// act_off chunk swizzle; backward weights [Cin][5 Cout] in rows padded to a
-// stride of 32 mod 64 bytes.
-constexpr int kBP = 5;                                // waves (inputs in flight) per block
+// Data gradients, one kernel per block (k_convT_bf16): one wave per input
+// unpools the block's pooled gradient with its mask into LDS, runs the
+// transposed circular convolution on MFMA with the backward weights (k in the
+// same 32-steps as k_gemm with ConvRows and sgn -1, rounded as EpStore
+// rounds: the result is bit-identical to the layer path) and writes the
+// result, the pooled gradient of the block below, to HBM, where the block's
+// weight gradient and the next kernel read it. LDS layouts as in the forward
+// stack: unpooled gradients in rows of their exact length with the act_off
+// chunk swizzle; backward weights [Cin][5 Cout] in rows padded to a stride of
+// 32 mod 64 bytes.
 constexpr int kB4Ld = 336, kB3Ld = 336, kB2Ld = 176;  // rows of the backward weights
-
-struct BwdSlice {
-    uint16_t buf0[128 * 32];      // dpre4 [32][64] with m3 bytes [32][64] after it; then dpre2
-    uint16_t buf1[64 * 64];       // dpre3
-    uint8_t m2[64 * 32];
-};
-struct BwdLds {
-    uint16_t w4[64 * kB4Ld];
-    uint16_t w3[32 * kB3Ld];
-    uint16_t w2[16 * kB2Ld];
-    BwdSlice wv[kBP];
-};
-constexpr int kM3Off = 32 * 64 * 2;                  // byte offset of m3 in buf0
-static_assert(kM3Off + 32 * 64 <= 128 * 32 * 2, "dpre4 and m3 share buf0");
-static_assert(kM3Off % 16 == 0 && sizeof(BwdSlice) % 16 == 0, "16-byte LDS groups");
-static_assert(sizeof(BwdLds) <= 160 * 1024, "LDS budget");
-
-// Byte offset of (row, byte) in an LDS copy of a pooling mask with rows of C
-// bytes: the 16-byte groups of a row are XOR-swizzled by the row so that the
-// epilogue's 4-byte reads (16 consecutive rows, 4 groups of 4 channels) hit
-// 64 distinct banks.
-template <int C>
-__device__ __forceinline__ int mask_off(int row, int byte) {
-    static_assert(C == 32 || C == 64, "mask rows");
-    return row * C + (byte ^ ((C == 64 ? (row >> 2) & 3 : (row >> 3) & 1) << 4));
-}
-
-// The values of 8 channels kept at the position whose mask bits 0-1 equal
-// sel (2: the even one, 3: the odd one); the others are 0.
-__device__ __forceinline__ uint4 unpool_at(uint4 g, uint2 k, uint32_t sel) {
-    const uint32_t gv[4] = {g.x, g.y, g.z, g.w};
-    uint32_t r[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const uint32_t kb = (j < 2 ? k.x : k.y) >> (16 * (j & 1));
-        r[j] = ((kb & 3u) == sel ? gv[j] & 0xffffu : 0u) | (((kb >> 8) & 3u) == sel ? gv[j] & 0xffff0000u : 0u);
-    }
-    return make_uint4(r[0], r[1], r[2], r[3]);
-}
 
 // The transposed conv of one input by one wave. dpre [L][PLD = COUT]
 // (act_off rows): gradient at the block's COUT pre-activations; w
-// [CIN][WLD]: backward weights, k =
-// dx*COUT + co. Output (x, ci) = sum_k dpre[(x - dx + 2) mod L][co] w[ci][k],
-// rounded to bf16, stored to gout [L][CIN]; with kNext also unpooled with the
-// lower block's mask ([L][CIN] bytes: bit 0 the winner's parity, bit 1 its
-// pre-activation > 0) into next [2L][NLD = CIN] (act_off rows). The MFMA takes the weights as its
-// first operand, so a lane ends with 4 consecutive channels of one position
-// (8-byte stores, one 4-byte mask read); the products and their k order are
-// those of k_gemm with ConvRows (sgn -1), whose output is the transpose.
-template <int L, int CIN, int COUT, int PLD, int WLD, int NLD, int RB, int CB, bool kNext>
+// [CIN][WLD]: backward weights, k = dx*COUT + co. Output (x, ci) = sum_k
+// dpre[(x - dx + 2) mod L][co] w[ci][k], rounded to bf16, stored to gout
+// [L][CIN]. The MFMA takes the weights as its first operand, so a lane ends
+// with 4 consecutive channels of one position (8-byte stores); the products
+// and their k order are those of k_gemm with ConvRows (sgn -1), whose output
+// is the transpose.
+template <int L, int CIN, int COUT, int PLD, int WLD, int RB, int CB>
 __device__ __forceinline__ void convT_one(const uint16_t* __restrict__ dpre, const uint16_t* __restrict__ w,
-                                          uint16_t* __restrict__ gout, const uint8_t* __restrict__ mask,
-                                          uint16_t* __restrict__ next) {
+                                          uint16_t* __restrict__ gout) {
     constexpr int K = 5 * COUT;
     static_assert(K % 32 == 0 && COUT % 8 == 0, "k steps within one dx");
     constexpr int KSTEPS = K / 32;
@@ -1424,22 +1379,8 @@ __device__ __forceinline__ void convT_one(const uint16_t* __restrict__ dpre, con
             const int n0 = ct * 16 * CB + j * 16 + q * 4;   // 4 channels n0 .. n0 + 3
             for (int i = 0; i < RB; ++i) {
                 const int xx = rt * 16 * RB + i * 16 + r;
-                const uint32_t h01 = f2bf2(acc[j][i][0], acc[j][i][1]);
-                const uint32_t h23 = f2bf2(acc[j][i][2], acc[j][i][3]);
-                *reinterpret_cast<uint2*>(gout + xx * CIN + n0) = make_uint2(h01, h23);
-                if constexpr (kNext) {
-                    const uint32_t mk = *reinterpret_cast<const uint32_t*>(mask + mask_off<CIN>(xx, n0));
-                    const uint4 ev = unpool_at(make_uint4(h01, h23, 0u, 0u), make_uint2(mk, 0u), 2u);
-                    const uint4 od = unpool_at(make_uint4(h01, h23, 0u, 0u), make_uint2(mk, 0u), 3u);
-                    // lanes of rows q and q + 1 (16 lanes apart) hold channels
-                    // 0-3 and 4-7 of one 8-channel group: swap so that the
-                    // first has the group's even position and the second its
-                    // odd one, each stored as one 16-byte write
-                    const auto s0 = __builtin_amdgcn_permlane16_swap(ev.x, od.x, false, false);
-                    const auto s1 = __builtin_amdgcn_permlane16_swap(ev.y, od.y, false, false);
-                    *reinterpret_cast<uint4*>(next + act_off<NLD>(2 * xx + (q & 1), n0 & ~7)) =
-                        make_uint4(s0[0], s1[0], s0[1], s1[1]);
-                }
+                *reinterpret_cast<uint2*>(gout + xx * CIN + n0) =
+                    make_uint2(f2bf2(acc[j][i][0], acc[j][i][1]), f2bf2(acc[j][i][2], acc[j][i][3]));
             }
         }
     }
@@ -1461,69 +1402,59 @@ __device__ __forceinline__ void unpool8(uint4 g, uint2 k, uint4& e0, uint4& e1) 
     e1 = make_uint4(r1[0], r1[1], r1[2], r1[3]);
 }
 
-// d4 [B][16][64], m4 [B][16][64], m3 [B][32][64], m2 [B][64][32] -> d3 [B][32][64],
-// d2 [B][64][32], d1 [B][128][16] (pooled gradients of blocks 3, 2, 1).
-__global__ __launch_bounds__(kBP * 64, 1) void k_convstack_bwd_bf16(
-    int B, const uint16_t* __restrict__ wb4, const uint16_t* __restrict__ wb3,
-    const uint16_t* __restrict__ wb2, const uint16_t* __restrict__ d4, const uint8_t* __restrict__ m4,
-    const uint8_t* __restrict__ m3, const uint8_t* __restrict__ m2, uint16_t* __restrict__ d3,
-    uint16_t* __restrict__ d2, uint16_t* __restrict__ d1) {
-    __shared__ __attribute__((aligned(16))) BwdLds sm;
+// One block's data gradient: each kernel holds only its block's backward
+// weights and one unpooled gradient per wave (4-8 KB), 16 waves per CU (a
+// single kernel for all three blocks held all their weights and 18 KB per
+// wave: 5 waves). d [B][LP][COUT], m [B][LP][COUT] (pooled gradient and mask
+// of the block's output) -> dout [B][2 LP][CIN] (pooled gradient of the
+// block below).
+constexpr int kTW = 16;   // waves per block
+template <int LP, int COUT, int CIN, int WLD, int RB, int CB>
+struct ConvTLds {
+    uint16_t w[CIN * WLD];
+    uint16_t dp[kTW][2 * LP * COUT];   // unpooled gradient [2 LP][COUT] (act_off rows)
+};
+
+template <int LP, int COUT, int CIN, int WLD, int RB, int CB>
+__global__ __launch_bounds__(kTW * 64, 1) void k_convT_bf16(int B, const uint16_t* __restrict__ wb,
+                                                        const uint16_t* __restrict__ d,
+                                                        const uint8_t* __restrict__ m,
+                                                        uint16_t* __restrict__ dout) {
+    constexpr int L = 2 * LP, K = 5 * COUT, E = LP * COUT, U = E / 512;   // 8 values per lane and unit
+    static_assert(E % 512 == 0 && sizeof(ConvTLds<LP, COUT, CIN, WLD, RB, CB>) <= 160 * 1024, "shapes");
+    __shared__ __attribute__((aligned(16))) ConvTLds<LP, COUT, CIN, WLD, RB, CB> sm;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int i = tid; i < 64 * kB4Ld; i += kBP * 64) {
-        const int n = i / kB4Ld, k = i - n * kB4Ld;
-        sm.w4[i] = k < 320 ? wb4[n * 320 + k] : (uint16_t)0;
-    }
-    for (int i = tid; i < 32 * kB3Ld; i += kBP * 64) {
-        const int n = i / kB3Ld, k = i - n * kB3Ld;
-        sm.w3[i] = k < 320 ? wb3[n * 320 + k] : (uint16_t)0;
-    }
-    for (int i = tid; i < 16 * kB2Ld; i += kBP * 64) {
-        const int n = i / kB2Ld, k = i - n * kB2Ld;
-        sm.w2[i] = k < 160 ? wb2[n * 160 + k] : (uint16_t)0;
+    for (int i = tid; i < CIN * WLD; i += kTW * 64) {
+        const int n = i / WLD, k = i - n * WLD;
+        sm.w[i] = k < K ? wb[n * K + k] : (uint16_t)0;
     }
     __syncthreads();   // the only block-wide wait: weights staged
-    BwdSlice& ws = sm.wv[wave];
-    uint8_t* m3s = reinterpret_cast<uint8_t*>(ws.buf0) + kM3Off;
-    const int64_t stride = (int64_t)gridDim.x * kBP;
-    int64_t fi = (int64_t)blockIdx.x * kBP + wave;
-    // the next input's data, loaded while the current one is computed: its
-    // gradient and mask of block 4 (two groups of 8 per lane) and the masks
-    // of blocks 3 and 2 (two 16-byte groups each)
-    uint4 ng[2], nk3[2], nk2[2];
-    uint2 nk4[2];
-    // (unconditional: past the batch the last input is read again and never
-    // used, so the compiler counts the loads exactly and the wait for them
-    // leaves the stores issued after them in flight)
-    auto load = [&](int64_t f) {
+    uint16_t* dp = sm.dp[wave];
+    const int64_t stride = (int64_t)gridDim.x * kTW;
+    int64_t fi = (int64_t)blockIdx.x * kTW + wave;
+    uint4 ng[U];
+    uint2 nk[U];
+    auto load = [&](int64_t f) {   // (unconditional: past the batch, read again and never used)
         f = f < B ? f : B - 1;
-        for (int h = 0; h < 2; ++h) {
-            ng[h] = ld_u4(d4 + f * 1024 + h * 512 + lane * 8);
-            nk4[h] = *reinterpret_cast<const uint2*>(m4 + f * 1024 + h * 512 + lane * 8);
-            nk3[h] = ld_u4(m3 + f * 2048 + h * 1024 + lane * 16);
-            nk2[h] = ld_u4(m2 + f * 2048 + h * 1024 + lane * 16);
+        for (int h = 0; h < U; ++h) {
+            ng[h] = ld_u4(d + f * E + h * 512 + lane * 8);
+            nk[h] = *reinterpret_cast<const uint2*>(m + f * E + h * 512 + lane * 8);
         }
     };
     load(fi);
     for (; fi < B; fi += stride) {
-        for (int h = 0; h < 2; ++h) {
-            *reinterpret_cast<uint4*>(m3s + mask_off<64>(h * 16 + (lane >> 2), (lane & 3) * 16)) = nk3[h];
-            *reinterpret_cast<uint4*>(ws.m2 + mask_off<32>(h * 32 + (lane >> 1), (lane & 1) * 16)) = nk2[h];
-            const int e0 = h * 512 + lane * 8, xp = e0 >> 6, c0 = e0 & 63;
+        for (int h = 0; h < U; ++h) {
+            const int e0 = h * 512 + lane * 8, xp = e0 / COUT, c0 = e0 - xp * COUT;
             uint4 ev, od;
-            unpool8(ng[h], nk4[h], ev, od);
-            *reinterpret_cast<uint4*>(ws.buf0 + act_off<64>(2 * xp, c0)) = ev;
-            *reinterpret_cast<uint4*>(ws.buf0 + act_off<64>(2 * xp + 1, c0)) = od;
+            unpool8(ng[h], nk[h], ev, od);
+            *reinterpret_cast<uint4*>(dp + act_off<COUT>(2 * xp, c0)) = ev;
+            *reinterpret_cast<uint4*>(dp + act_off<COUT>(2 * xp + 1, c0)) = od;
         }
-        __builtin_amdgcn_sched_barrier(0);   // the loads stay after the staging (register pressure)
+        __builtin_amdgcn_sched_barrier(0);
         load(fi + stride);
         wave_lds_sync();
-        convT_one<32, 64, 64, 64, kB4Ld, 64, 2, 4, true>(ws.buf0, sm.w4, d3 + fi * 2048, m3s, ws.buf1);
-        wave_lds_sync();
-        convT_one<64, 32, 64, 64, kB3Ld, 32, 4, 2, true>(ws.buf1, sm.w3, d2 + fi * 2048, ws.m2, ws.buf0);
-        wave_lds_sync();
-        convT_one<128, 16, 32, 32, kB2Ld, 16, 8, 1, false>(ws.buf0, sm.w2, d1 + fi * 2048, nullptr, nullptr);
-        wave_lds_sync();   // buf0 and the masks are reused by the next input
+        convT_one<L, CIN, COUT, COUT, WLD, RB, CB>(dp, sm.w, dout + fi * (L * CIN));
+        wave_lds_sync();   // dp is reused by the next input
     }
 }
 
@@ -2704,11 +2635,16 @@ int32_t backward_convs_bf16(gpfc_cnn* c, const void* x, int xf32, int B, hipStre
     uint16_t* d3 = (uint16_t*)c->d_b;                              // [B][32][64]
     uint16_t* d2 = (uint16_t*)c->d_b + (int64_t)B * 2048;          // [B][64][32]
     uint16_t* d1 = (uint16_t*)c->d_a + (int64_t)B * 2048;          // [B][128][16]
-    const dim3 grid((unsigned)std::min<int64_t>((B + kBP - 1) / kBP, c->n_cu));
-    hipLaunchKernelGGL(k_convstack_bwd_bf16, grid, dim3(kBP * 64), 0, s, B, (const uint16_t*)c->wb4,
-                       (const uint16_t*)c->wb3, (const uint16_t*)c->wb2, d4, c->m4, c->m3, c->m2, d3, d2, d1);
+    // the data gradients down the blocks, one kernel per block
+    const dim3 gt((unsigned)std::min<int64_t>((B + kTW - 1) / kTW, c->n_cu));
+    hipLaunchKernelGGL((k_convT_bf16<16, 64, 64, kB4Ld, 2, 4>), gt, dim3(kTW * 64), 0, s, B,
+                       (const uint16_t*)c->wb4, d4, c->m4, d3);
+    hipLaunchKernelGGL((k_convT_bf16<32, 64, 32, kB3Ld, 4, 2>), gt, dim3(kTW * 64), 0, s, B,
+                       (const uint16_t*)c->wb3, (const uint16_t*)d3, c->m3, d2);
+    hipLaunchKernelGGL((k_convT_bf16<64, 32, 16, kB2Ld, 8, 1>), gt, dim3(kTW * 64), 0, s, B,
+                       (const uint16_t*)c->wb2, (const uint16_t*)d2, c->m2, d1);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return cnn_err(e, "k_convstack_bwd_bf16");
+    if (e != hipSuccess) return cnn_err(e, "backward data gradients");
     e = conv_dw_bf16<32, 64, 64, 4, 1>(c, B, d4, c->m4, (const uint16_t*)c->a3, g + kConvW[4], g + conv_b(4), s);
     if (e == hipSuccess)
         e = conv_dw_bf16<64, 32, 64, 2, 2>(c, B, d3, c->m3, (const uint16_t*)c->a2, g + kConvW[3], g + conv_b(3), s);
