@@ -1118,6 +1118,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 // (chunk c of row r at slot c ^ 2*bit 2 of r), conflict-free for the fragment
 // reads. Same MFMA chains and epilogue as k_gemm with EpFcFwd: bit-identical
 // output.
+// s_waitcnt immediate that waits for vector memory operations only, until at
+// most n (< 64) remain: vmcnt bits 3:0 at 3:0 and 5:4 at 15:14, expcnt (6:4)
+// and lgkmcnt (11:8) at their maxima (no wait).
+constexpr int vmcnt_imm(int n) { return 0x0F70 | (n & 15) | ((n >> 4) & 3) << 14; }
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) void glb_void_t;
 constexpr int kF1BN = 256, kF1BK = 32;
@@ -1174,14 +1178,15 @@ __global__ __launch_bounds__(BM * 4, 1) void k_fc1_bf16(int M, int K, const uint
         // every wave is done reading the stage that step st + stages - 1
         // refills (a bare barrier: __syncthreads' fence would also wait for
         // the later loads)
+        // (s_waitcnt's vmcnt is 6 bits: bits 3:0 of the immediate, then 15:14)
         const int ahead = min(kF1Stages - 2, steps - 1 - st);   // later steps already issued
         switch (ahead) {
-            case 5: __builtin_amdgcn_s_waitcnt(0x0F70 | (5 * kLoads)); break;
-            case 4: __builtin_amdgcn_s_waitcnt(0x0F70 | (4 * kLoads)); break;
-            case 3: __builtin_amdgcn_s_waitcnt(0x0F70 | (3 * kLoads)); break;
-            case 2: __builtin_amdgcn_s_waitcnt(0x0F70 | (2 * kLoads)); break;
-            case 1: __builtin_amdgcn_s_waitcnt(0x0F70 | kLoads); break;
-            default: __builtin_amdgcn_s_waitcnt(0x0F70); break;
+            case 5: __builtin_amdgcn_s_waitcnt(vmcnt_imm(5 * kLoads)); break;
+            case 4: __builtin_amdgcn_s_waitcnt(vmcnt_imm(4 * kLoads)); break;
+            case 3: __builtin_amdgcn_s_waitcnt(vmcnt_imm(3 * kLoads)); break;
+            case 2: __builtin_amdgcn_s_waitcnt(vmcnt_imm(2 * kLoads)); break;
+            case 1: __builtin_amdgcn_s_waitcnt(vmcnt_imm(kLoads)); break;
+            default: __builtin_amdgcn_s_waitcnt(vmcnt_imm(0)); break;
         }
         static_assert(kF1Stages - 2 <= 5, "waits listed above");
         __builtin_amdgcn_sched_barrier(0);
