@@ -1263,7 +1263,7 @@ __device__ __forceinline__ uint32_t mid_bin_ieee(double t, double P) {
 // aligned 32-byte group of banks; only records whose bins agree mod 8 meet on
 // a bank (with one record per lane and random bins, 16 lanes did).
 template <bool kTwo>
-__device__ void eqcount_pass(uint64_t* hist, EqBoundary (*bnd)[kEqMaxBins + 1], int64_t* eqn,
+__device__ void eqcount_pass(uint64_t* hist, EqBoundary (*bnd)[kEqMaxBins + 1], int64_t* eqn, int* dsel,
                              const Rec* __restrict__ rec, const uint64_t* __restrict__ lo,
                              int64_t nrec, const double* __restrict__ periods, int64_t k,
                              int64_t kbase, int32_t nbins, const CurveInfo* __restrict__ info,
@@ -1287,31 +1287,40 @@ __device__ void eqcount_pass(uint64_t* hist, EqBoundary (*bnd)[kEqMaxBins + 1], 
     // a bijection of the 16), with d chosen so that the bins of records spaced
     // by one cadence (the first two records' spacing), d, 2d and 3d apart differ
     // mod 8 - a bank conflict needs equal bins mod 8. Any d gives the same sums.
-    int d = 1;
-    if (nrec > 1) {
-        const double step = (rec[1].t - rec[0].t) * rB;   // bins per record, about
-        int best = 99;
-        for (int dd = 1; dd <= 4; dd <<= 1) {
-            int coll = 0;
-            for (int f4 = 0; f4 < 4; ++f4) {               // a few phases of the first bin
-                int seen = 0;
-                for (int kq = 0; kq < 4; ++kq) {
-                    const double b = 0.25 * f4 + kq * dd * step;
-                    const int m = (int)(b - 8.0 * floor(b / 8.0)) & 7;
-                    coll += (seen >> m) & 1;
-                    seen |= 1 << m;
+    // (worked out once per region, by the block's first 4 threads, whose
+    // regions are 0-3, and read from LDS by every lane)
+    if (threadIdx.x < kEqPeriods) {
+        int d = 1;
+        if (nrec > 1) {
+            const double step = (rec[1].t - rec[0].t) * rB;   // bins per record, about
+            int best = 99;
+            for (int dd = 1; dd <= 4; dd <<= 1) {
+                int coll = 0;
+                for (int f4 = 0; f4 < 4; ++f4) {               // a few phases of the first bin
+                    int seen = 0;
+                    for (int kq = 0; kq < 4; ++kq) {
+                        const double b = 0.25 * f4 + kq * dd * step;
+                        const int m = (int)(b - 8.0 * floor(b / 8.0)) & 7;
+                        coll += (seen >> m) & 1;
+                        seen |= 1 << m;
+                    }
                 }
+                if (coll < best) { best = coll; d = dd; }
             }
-            if (coll < best) { best = coll; d = dd; }
         }
+        dsel[threadIdx.x] = d;
     }
+    __syncthreads();
+    const int d = dsel[reg];
     const int sl = lane >> 2, pr = sl >> 2, kq = sl & 3;   // pass and place within it
     const int off = d == 1 ? 4 * pr + kq : (d == 2 ? (pr & 1) + 8 * (pr >> 1) + 2 * kq : pr + 4 * kq);
     const int strm = wave * 16 + off;                  // its record stream (256 per block)
-    __syncthreads();
     if (valid) {
         // kEqU records per lane per step, all loaded before their updates, so
         // their load latencies overlap
+        // (loads are unconditional: indices past the curve re-read its last
+        // record and add 0; a zero contribution is added rather than skipped,
+        // which costs an atomic but no branch)
         constexpr int kEqU = 8;
         for (int64_t i0 = strm; i0 < nrec; i0 += 256 * kEqU) {
             double tv[kEqU];
@@ -1319,22 +1328,18 @@ __device__ void eqcount_pass(uint64_t* hist, EqBoundary (*bnd)[kEqMaxBins + 1], 
 #pragma unroll
             for (int u = 0; u < kEqU; ++u) {
                 const int64_t i = i0 + 256 * u;
-                tv[u] = 0.0;
-                cv[u] = 0;
-                if (i < nrec) {
-                    const Rec r = rec[i];
-                    tv[u] = r.t;
-                    cv[u] = lo_word ? lo[i] : r.c;
-                }
+                const int64_t ic = i < nrec ? i : nrec - 1;
+                const Rec r = rec[ic];
+                tv[u] = r.t;
+                cv[u] = i < nrec ? (lo_word ? lo[ic] : r.c) : 0;
             }
 #pragma unroll
             for (int u = 0; u < kEqU; ++u) {
                 const uint32_t lw = fast_lo(tv[u], rB);   // the certified path, at 4096 bins
                 uint32_t b = (lw >> 16) & (kMid - 1);
                 if ((lw & 0xFFFFu) >= lim) b = mid_bin_ieee(tv[u], P);
-                if (cv[u])
-                    __hip_atomic_fetch_add(hist + b * kEqPeriods + reg, cv[u], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_add(hist + b * kEqPeriods + reg, cv[u], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         }
     }
@@ -1456,14 +1461,15 @@ __global__ __launch_bounds__(kThreads, 1) void k_fold_eqcount(
     __shared__ __attribute__((aligned(16))) uint64_t hist[kEqPeriods * kMid];
     __shared__ EqBoundary bnd[kEqPeriods][kEqMaxBins + 1];
     __shared__ int64_t eqn[kEqPeriods];
+    __shared__ int dsel[kEqPeriods];
     const int64_t kbase = (int64_t)blockIdx.x * kEqPeriods;
     if (info->words == 2) {
-        eqcount_pass<true>(hist, bnd, eqn, rec, lo, nrec, periods, k, kbase, nbins, info, means, zfold);
-        eqcount_pass<true>(hist, bnd, eqn, rec, lo, nrec, periods, k, kbase + 2, nbins, info, means,
+        eqcount_pass<true>(hist, bnd, eqn, dsel, rec, lo, nrec, periods, k, kbase, nbins, info, means, zfold);
+        eqcount_pass<true>(hist, bnd, eqn, dsel, rec, lo, nrec, periods, k, kbase + 2, nbins, info, means,
                            zfold);
         return;
     }
-    eqcount_pass<false>(hist, bnd, eqn, rec, lo, nrec, periods, k, kbase, nbins, info, means, zfold);
+    eqcount_pass<false>(hist, bnd, eqn, dsel, rec, lo, nrec, periods, k, kbase, nbins, info, means, zfold);
 }
 
 // ------------------------------------------------------------------ general path
