@@ -8,6 +8,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "gpfc_internal.h"
 
@@ -1237,6 +1238,8 @@ __global__ __launch_bounds__(256) void k_fold_naive(const double* __restrict__ t
 // as an exact integer part (the bins before it) plus the interpolated share of
 // that bin; a final bin's sum is the difference of its two boundaries.
 constexpr int kMid = 4096;
+typedef uint32_t u32x4b __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2b __attribute__((ext_vector_type(2)));
 constexpr int kEqPeriods = 4;
 constexpr int kEqMaxBins = 256;
 
@@ -1258,12 +1261,13 @@ __device__ __forceinline__ uint32_t mid_bin_ieee(double t, double P) {
 // One pass of the equal-count fold over `np` of the block's periods
 // (np = 4, one word; np = 2, two words: region 2 + p of the LDS histogram
 // holds period p's low words). The four regions are interleaved by bin
-// (slot 4 b + region): lane = (record stream, region), so one 16-lane pass of
-// a 64-bit atomic carries 4 records x 4 regions, each record's four slots one
-// aligned 32-byte group of banks; only records whose bins agree mod 8 meet on
-// a bank (with one record per lane and random bins, 16 lanes did).
+// (slot 4 b + region): lane = (record, region), so one 16-lane pass of a
+// 64-bit atomic carries 4 records x 4 regions, and only records of one region
+// whose bins agree mod 4 meet on a bank (with one region per pass, 16 records
+// would share 16 banks).
 template <bool kTwo>
-__device__ void eqcount_pass(uint64_t* hist, EqBoundary (*bnd)[kEqMaxBins + 1], int64_t* eqn, int* dsel,
+__device__ __forceinline__ void eqcount_pass(uint64_t* hist, EqBoundary (*bnd)[kEqMaxBins + 1], int64_t* eqn, int* dsel,
+                             int64_t (*wtot)[3],
                              const Rec* __restrict__ rec, const uint64_t* __restrict__ lo,
                              int64_t nrec, const double* __restrict__ periods, int64_t k,
                              int64_t kbase, int32_t nbins, const CurveInfo* __restrict__ info,
@@ -1271,102 +1275,227 @@ __device__ void eqcount_pass(uint64_t* hist, EqBoundary (*bnd)[kEqMaxBins + 1], 
     constexpr int np = kTwo ? kEqPeriods / 2 : kEqPeriods;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int reg = lane & (kEqPeriods - 1);           // the lane's histogram region
-    const int pp = kTwo ? (reg & 1) : reg;             // its period within the pass
-    const bool lo_word = kTwo && reg >= 2;
     for (int i = threadIdx.x; i < kEqPeriods * kMid; i += kThreads) hist[i] = 0;
-    const int64_t kk = kbase + pp;
-    double P = kk < k ? periods[kk] : 1.0;
-    const bool valid = kk < k && P > 0.0 && isfinite(P);
-    if (!valid) P = 1.0;
-    const double rB = (1.0 / P) * (double)kMid;
-    const double zmax = info->tmax * rB;
-    const uint32_t lim = zmax < 0x1p34 ? 65536u - 2u : 0u;
-    // The wave takes 16 consecutive records per instruction; the 4 lanes of a
-    // 16-lane pass that share the period take records d apart (d = 1, 2 or 4,
-    // a bijection of the 16), with d chosen so that the bins of records spaced
-    // by one cadence (the first two records' spacing), d, 2d and 3d apart differ
-    // mod 8 - a bank conflict needs equal bins mod 8. Any d gives the same sums.
-    // (worked out once per region, by the block's first 4 threads, whose
-    // regions are 0-3, and read from LDS by every lane)
-    if (threadIdx.x < kEqPeriods) {
-        int d = 1;
+    // Each lane loads one record and adds it to all four regions, region
+    // (lane + j) mod 4 at its j-th update, so a 16-lane pass always holds 4
+    // records x the 4 regions and one record load serves 4 updates.
+    double rBj[4];
+    uint32_t limj[4], roffj[4];
+    bool vj[4];
+    bool allv = true;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int g = (lane + j) & 3;                  // the region
+        const int64_t kk = kbase + (kTwo ? (g & 1) : g);
+        double P = kk < k ? periods[kk] : 1.0;
+        vj[j] = kk < k && P > 0.0 && isfinite(P);
+        allv = allv && vj[j];
+        if (!vj[j]) P = 1.0;
+        rBj[j] = (1.0 / P) * (double)kMid;
+        limj[j] = info->tmax * rBj[j] < 0x1p34 ? 65536u - 2u : 0u;
+        roffj[j] = (uint32_t)g * (uint32_t)sizeof(uint64_t);
+    }
+    // Two lanes of a 16-lane pass of a 64-bit LDS atomic conflict when their
+    // slots agree mod 16: with slot 4 b + region, when two records of one
+    // region have bins that agree mod 4. A region's 4 records in a pass are a
+    // comb spaced a apart (a = 2^e <= 16; a wave's 64 records split into
+    // windows of 4a, each into a combs), with a chosen so that a times the bin
+    // advance per record is near 1 or 3 mod 4 for the block's periods: the
+    // comb's bins mod 4 are then x, x + D, x + 2 D, x + 3 D with D about 1 or 3,
+    // all distinct. Any a gives the same sums. (worked out once per block by
+    // its first thread)
+    if (threadIdx.x == 0) {
+        int e = 0;
         if (nrec > 1) {
-            const double step = (rec[1].t - rec[0].t) * rB;   // bins per record, about
-            int best = 99;
-            for (int dd = 1; dd <= 4; dd <<= 1) {
-                int coll = 0;
-                for (int f4 = 0; f4 < 4; ++f4) {               // a few phases of the first bin
-                    int seen = 0;
-                    for (int kq = 0; kq < 4; ++kq) {
-                        const double b = 0.25 * f4 + kq * dd * step;
-                        const int m = (int)(b - 8.0 * floor(b / 8.0)) & 7;
-                        coll += (seen >> m) & 1;
-                        seen |= 1 << m;
-                    }
+            double dt = rec[1].t - rec[0].t;                 // the cadence: the least of a few spacings
+            for (int64_t i = 2; i < 9 && i < nrec; ++i) dt = fmin(dt, rec[i].t - rec[i - 1].t);
+            double best = 1e30;
+            for (int ee = 0; ee <= 4; ++ee) {
+                double miss = 0.0;
+                for (int j = 0; j < 4; ++j) {
+                    const double dl = (double)(1 << ee) * dt * rBj[j];   // bins per comb step
+                    const double del = dl - 4.0 * floor(dl * 0.25);
+                    miss += fmin(fabs(del - 1.0), fabs(del - 3.0));
                 }
-                if (coll < best) { best = coll; d = dd; }
+                if (miss < best) { best = miss; e = ee; }
             }
         }
-        dsel[threadIdx.x] = d;
+        dsel[0] = e;
     }
     __syncthreads();
-    const int d = dsel[reg];
-    const int sl = lane >> 2, pr = sl >> 2, kq = sl & 3;   // pass and place within it
-    const int off = d == 1 ? 4 * pr + kq : (d == 2 ? (pr & 1) + 8 * (pr >> 1) + 2 * kq : pr + 4 * kq);
-    const int strm = wave * 16 + off;                  // its record stream (256 per block)
-    if (valid) {
-        // kEqU records per lane per step, all loaded before their updates, so
-        // their load latencies overlap
-        // (loads are unconditional: indices past the curve re-read its last
-        // record and add 0; a zero contribution is added rather than skipped,
-        // which costs an atomic but no branch)
-        constexpr int kEqU = 8;
-        for (int64_t i0 = strm; i0 < nrec; i0 += 256 * kEqU) {
+    const int e = dsel[0];
+    const int cm = ((lane >> 4) << 2) | (lane & 3), kq = (lane >> 2) & 3;   // comb, place in it
+    const int lrec = wave * 64 + ((cm >> e) << (e + 2)) + (cm & ((1 << e) - 1)) + (kq << e);
+    // kEqU records per lane per step, all loaded before their updates, so
+    // their load latencies overlap. Steps wholly inside the curve take no
+    // bounds checks; the last partial step re-reads the curve's last record
+    // for indices past it and adds 0 there. Every update goes to its fast-path
+    // bin; when some lane's fraction falls outside the certificate (rare) the
+    // step is repaired: each such update is taken back from the fast bin and
+    // added to the IEEE bin. Regions of invalid periods (only in a block past
+    // the grid's end or for a bad period) add 0.
+    constexpr int kEqU = 1;
+    auto repair = [&](int64_t i0) {
+#pragma unroll 1
+        for (int q = 0; q < kEqU * 4; ++q) {
+            const int64_t i = i0 + 1024 * (q >> 2) + lrec;
+            const int g = (lane + q) & 3;
+            const int64_t kk = kbase + (kTwo ? (g & 1) : g);
+            const double P = kk < k ? periods[kk] : 1.0;
+            if (i >= nrec || !(kk < k && P > 0.0 && isfinite(P))) continue;
+            const double rB = (1.0 / P) * (double)kMid;
+            const uint32_t lim = info->tmax * rB < 0x1p34 ? 65536u - 2u : 0u;
+            const double ti = rec[i].t;
+            const uint32_t lw = fast_lo(ti, rB);
+            if ((lw & 0xFFFFu) < lim) continue;
+            const uint64_t v = (kTwo && g >= 2) ? lo[i] : rec[i].c;
+            uint64_t* h = (uint64_t*)((char*)hist + (g * (int)sizeof(uint64_t)));
+            __hip_atomic_fetch_add(h + ((lw >> 16) & (kMid - 1)) * kEqPeriods, uint64_t(0) - v,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(h + mid_bin_ieee(ti, P) * kEqPeriods, v, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    };
+    auto updates = [&](auto kAll, int64_t i0, const double* tv, const uint64_t* cv, const uint64_t* lv) {
+        uint64_t bad = 0;   // lanes (any update) outside the certificate
+#pragma unroll
+        for (int u = 0; u < kEqU; ++u)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t lw = fast_lo(tv[u], rBj[j]);   // the certified path, at 4096 bins
+                bad |= __builtin_amdgcn_ballot_w64((lw & 0xFFFFu) >= limj[j]);
+                uint64_t v = cv[u];
+                if (kTwo && (((lane + j) & 3) >= 2)) v = lv[u];
+                if (!decltype(kAll)::value && !vj[j]) v = 0;
+                __hip_atomic_fetch_add((uint64_t*)((char*)hist + ((((lw >> 16) & (kMid - 1)) << 5) | roffj[j])), v,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        if (bad) repair(i0);
+    };
+    auto run = [&](auto kAll) {
+        int64_t i0 = 0;
+        if (nrec < (int64_t)1 << 27) {
+            // buffer loads: the lane's byte offset in a VGPR, the step's in an
+            // SGPR, so no vector address arithmetic per load (byte offsets stay
+            // below 2^31 for fewer than 2^27 records)
+            const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)rec, (short)0, (int)(nrec * (int64_t)sizeof(Rec)), 0x00020000);
+            const __amdgpu_buffer_rsrc_t rl =
+                __builtin_amdgcn_make_buffer_rsrc((void*)lo, (short)0, lo ? (int)(nrec * 8) : 0, 0x00020000);
+            const int boff = lrec * (int)sizeof(Rec), loff = lrec * 8;
+            // each step's records are requested before the previous step's updates
+            const int64_t nfull = nrec / (1024 * kEqU);   // whole steps
+            auto load = [&](int64_t s0, double* tv, uint64_t* cv, uint64_t* lv) {
+#pragma unroll
+                for (int u = 0; u < kEqU; ++u) {
+                    const int so = (int)(s0 + 1024 * u);
+                    const u32x4b r = __builtin_amdgcn_raw_buffer_load_b128(rr, boff, so * (int)sizeof(Rec), 0);
+                    tv[u] = __builtin_bit_cast(double, (uint64_t)r[0] | (uint64_t)r[1] << 32);
+                    cv[u] = (uint64_t)r[2] | (uint64_t)r[3] << 32;
+                    lv[u] = 0;
+                    if (kTwo) {
+                        const u32x2b l = __builtin_amdgcn_raw_buffer_load_b64(rl, loff, so * 8, 0);
+                        lv[u] = (uint64_t)l[0] | (uint64_t)l[1] << 32;
+                    }
+                }
+            };
+            if (nfull > 0) {
+                double tv[kEqU], tn[kEqU];
+                uint64_t cv[kEqU], lv[kEqU], cn[kEqU], ln[kEqU];
+                load(0, tv, cv, lv);
+                for (int64_t st = 0; st < nfull; ++st) {
+                    const int64_t nx = st + 1 < nfull ? st + 1 : st;   // the last step re-reads itself
+                    load(nx * 1024 * kEqU, tn, cn, ln);
+                    __builtin_amdgcn_sched_barrier(0);
+                    updates(kAll, st * 1024 * kEqU, tv, cv, lv);
+#pragma unroll
+                    for (int u = 0; u < kEqU; ++u) {
+                        tv[u] = tn[u];
+                        cv[u] = cn[u];
+                        lv[u] = ln[u];
+                    }
+                }
+                i0 = nfull * 1024 * kEqU;
+            }
+        } else {
+            for (; i0 + 1024 * kEqU <= nrec; i0 += 1024 * kEqU) {
+                double tv[kEqU];
+                uint64_t cv[kEqU], lv[kEqU];
+#pragma unroll
+                for (int u = 0; u < kEqU; ++u) {
+                    const Rec r = rec[i0 + 1024 * u + lrec];
+                    tv[u] = r.t;
+                    cv[u] = r.c;
+                    lv[u] = kTwo ? lo[i0 + 1024 * u + lrec] : 0;
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                updates(kAll, i0, tv, cv, lv);
+            }
+        }
+        if (i0 < nrec) {
             double tv[kEqU];
-            uint64_t cv[kEqU];
+            uint64_t cv[kEqU], lv[kEqU];
 #pragma unroll
             for (int u = 0; u < kEqU; ++u) {
-                const int64_t i = i0 + 256 * u;
+                const int64_t i = i0 + 1024 * u + lrec;
                 const int64_t ic = i < nrec ? i : nrec - 1;
                 const Rec r = rec[ic];
                 tv[u] = r.t;
-                cv[u] = i < nrec ? (lo_word ? lo[ic] : r.c) : 0;
+                cv[u] = i < nrec ? r.c : 0;
+                lv[u] = kTwo && i < nrec ? lo[ic] : 0;
             }
-#pragma unroll
-            for (int u = 0; u < kEqU; ++u) {
-                const uint32_t lw = fast_lo(tv[u], rB);   // the certified path, at 4096 bins
-                uint32_t b = (lw >> 16) & (kMid - 1);
-                if ((lw & 0xFFFFu) >= lim) b = mid_bin_ieee(tv[u], P);
-                __hip_atomic_fetch_add(hist + b * kEqPeriods + reg, cv[u], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
+            updates(kAll, i0, tv, cv, lv);
         }
-    }
+    };
+    if (allv)
+        run(std::integral_constant<bool, true>());
+    else
+        run(std::integral_constant<bool, false>());
     __syncthreads();
-    if (wave < np) {
-        const int p2 = wave;
+    // The boundary scan, on all 16 waves: wave w takes period w mod np and
+    // part w / np of W = 16 / np equal parts of its bins, each lane a run of
+    // about BL bins in bin order, read once into registers. Runs start at
+    // BL lane + (lane mod 4) within the part, so a 16-lane pass reads bins of
+    // 4 residues mod 4 (a region's slots fall in 4 of the 16 bank groups of a
+    // 64-bit access: 4 lanes per group is the fewest possible, where runs
+    // starting at BL lane would put all 16 in one).
+    {
+        constexpr int W = kThreads / 64 / np;        // waves per period
+        constexpr int BW = kMid / W;                  // bins per wave
+        constexpr int BL = BW / 64;                   // bins per lane, about
+        const int p2 = wave % np, part = wave / np;
         const int64_t k2 = kbase + p2;
         const double P2 = k2 < k ? periods[k2] : 1.0;
         const bool v2 = k2 < k && P2 > 0.0 && isfinite(P2);
-        // bin b of region r is hist[4 b + r]; lane owns bins [64 lane, 64 lane + 64)
         const uint64_t* hh = hist + p2;
         const uint64_t* hl = hist + p2 + 2;           // low words (kTwo)
+        const int blo = part * BW + lane * BL + (lane & 3);
+        const int bhi = part * BW + (lane == 63 ? BW : (lane + 1) * BL + ((lane + 1) & 3));
         auto bin_at = [&](int b, int64_t& c, int64_t& d, int64_t& dl) {
             const uint64_t v = hh[b * kEqPeriods];
             c = (int64_t)(v >> kCountShift);
             d = (int64_t)(v & kSumMask) - c * kBias;
             dl = kTwo ? (int64_t)(hl[b * kEqPeriods] & kSumMask) - c * kBias : 0;
         };
-        // the lane's totals, its bins read from a lane-dependent start (integer
-        // sums: any order), so the lanes' reads spread over the banks
+        // the lane's totals: the run is BL - 3 to BL + 1 bins, all read at once
+        // (slots past the run re-read its last bin and add nothing)
         int64_t lc = 0, ls = 0, ll = 0;
-        for (int j = 0; j < 64; ++j) {
-            int64_t c, d, dl;
-            bin_at(lane * 64 + ((j + lane) & 63), c, d, dl);
-            lc += c;
-            ls += d;
-            ll += dl;
+        {
+            uint64_t hv[BL + 1], hlv[BL + 1];
+#pragma unroll
+            for (int i = 0; i < BL + 1; ++i) {
+                const int b = blo + i < bhi ? blo + i : bhi - 1;
+                hv[i] = hh[b * kEqPeriods];
+                hlv[i] = kTwo ? hl[b * kEqPeriods] : 0;
+            }
+#pragma unroll
+            for (int i = 0; i < BL + 1; ++i)
+                if (blo + i < bhi) {
+                    const int64_t c = (int64_t)(hv[i] >> kCountShift);
+                    lc += c;
+                    ls += (int64_t)(hv[i] & kSumMask) - c * kBias;
+                    if (kTwo) ll += (int64_t)(hlv[i] & kSumMask) - c * kBias;
+                }
         }
         int64_t pc = lc, ps = ls, pl = ll;   // inclusive prefix over lanes
         for (int d = 1; d < 64; d <<= 1) {
@@ -1374,41 +1503,59 @@ __device__ void eqcount_pass(uint64_t* hist, EqBoundary (*bnd)[kEqMaxBins + 1], 
             const int64_t ol = kTwo ? __shfl_up(pl, d) : 0;
             if (lane >= d) { pc += oc; ps += os; pl += ol; }
         }
-        const int64_t N = __shfl(pc, 63);
-        const int64_t Stot = __shfl(ps, 63);
-        const int64_t Ltot = kTwo ? __shfl(pl, 63) : 0;
-        int64_t C = pc - lc, S = ps - ls, SL = pl - ll;   // exclusive: before the lane's first bin
+        if (lane == 63) {
+            wtot[wave][0] = pc;
+            wtot[wave][1] = ps;
+            wtot[wave][2] = pl;
+        }
+        __syncthreads();
+        // the period's totals and those of its parts before this one
+        int64_t N = 0, Stot = 0, Ltot = 0, C = pc - lc, S = ps - ls, SL = pl - ll;
+        for (int q = 0; q < W; ++q) {
+            const int64_t* t3 = wtot[q * np + p2];
+            if (q < part) { C += t3[0]; S += t3[1]; SL += t3[2]; }
+            N += t3[0];
+            Stot += t3[1];
+            Ltot += t3[2];
+        }
         if (v2 && N > 0) {
             // the next boundary j N at or after the lane's first unit (one division
             // per lane; later boundaries follow by steps of N)
             int64_t j = (C * nbins + N - 1) / N;
             int64_t jN = j * N;
-            for (int b = lane * 64; b < lane * 64 + 64; ++b) {
-                int64_t c, d, dl;
-                bin_at(b, c, d, dl);
-                if (c == 0) continue;
-                const int64_t u0 = C * nbins, u1 = (C + c) * nbins;   // the bin's units
-                // interior boundaries j N (0 < j < nbins) inside [u0, u1)
-                if (jN < u1) {
-                    // the bin's deviation in units of the high word
-                    const double dd = kTwo ? (double)d + ldexp((double)dl, -kLoBits) : (double)d;
-                    for (; jN < u1; ++j, jN += N) {
-                        if (j == 0) continue;
-                        bnd[p2][j].ipart = S;
-                        bnd[p2][j].ilo = SL;
-                        bnd[p2][j].frac = (double)(jN - u0) / (double)(c * nbins) * dd;
+            // bins in order, each read one bin ahead of its use
+            int64_t c, d, dl;
+            bin_at(blo, c, d, dl);
+            for (int b = blo; b < bhi; ++b) {
+                int64_t cn, dn, dln;
+                bin_at(b + 1 < bhi ? b + 1 : b, cn, dn, dln);
+                if (c != 0) {
+                    const int64_t u0 = C * nbins, u1 = (C + c) * nbins;   // the bin's units
+                    // interior boundaries j N (0 < j < nbins) inside [u0, u1)
+                    if (jN < u1) {
+                        // the bin's deviation in units of the high word
+                        const double dd = kTwo ? (double)d + ldexp((double)dl, -kLoBits) : (double)d;
+                        for (; jN < u1; ++j, jN += N) {
+                            if (j == 0) continue;
+                            bnd[p2][j].ipart = S;
+                            bnd[p2][j].ilo = SL;
+                            bnd[p2][j].frac = (double)(jN - u0) / (double)(c * nbins) * dd;
+                        }
                     }
+                    C += c;
+                    S += d;
+                    SL += dl;
                 }
-                C += c;
-                S += d;
-                SL += dl;
+                c = cn;
+                d = dn;
+                dl = dln;
             }
-            if (lane == 0) {
+            if (part == 0 && lane == 0) {
                 bnd[p2][0] = EqBoundary{0, 0, 0.0};
                 bnd[p2][nbins] = EqBoundary{Stot, Ltot, 0.0};
             }
         }
-        if (lane == 0) eqn[p2] = (v2 && k2 < k) ? N : -1;
+        if (part == 0 && lane == 0) eqn[p2] = (v2 && k2 < k) ? N : -1;
     }
     __syncthreads();
     if (wave < np) {
@@ -1462,14 +1609,15 @@ __global__ __launch_bounds__(kThreads, 1) void k_fold_eqcount(
     __shared__ EqBoundary bnd[kEqPeriods][kEqMaxBins + 1];
     __shared__ int64_t eqn[kEqPeriods];
     __shared__ int dsel[kEqPeriods];
+    __shared__ int64_t wtot[kThreads / 64][3];
     const int64_t kbase = (int64_t)blockIdx.x * kEqPeriods;
     if (info->words == 2) {
-        eqcount_pass<true>(hist, bnd, eqn, dsel, rec, lo, nrec, periods, k, kbase, nbins, info, means, zfold);
-        eqcount_pass<true>(hist, bnd, eqn, dsel, rec, lo, nrec, periods, k, kbase + 2, nbins, info, means,
-                           zfold);
+        for (int h = 0; h < 2; ++h)
+            eqcount_pass<true>(hist, bnd, eqn, dsel, wtot, rec, lo, nrec, periods, k, kbase + 2 * h, nbins, info,
+                               means, zfold);
         return;
     }
-    eqcount_pass<false>(hist, bnd, eqn, dsel, rec, lo, nrec, periods, k, kbase, nbins, info, means, zfold);
+    eqcount_pass<false>(hist, bnd, eqn, dsel, wtot, rec, lo, nrec, periods, k, kbase, nbins, info, means, zfold);
 }
 
 // ------------------------------------------------------------------ general path
