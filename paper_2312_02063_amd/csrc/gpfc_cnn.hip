@@ -21,8 +21,9 @@
 // output layer in its epilogue). A bf16 training step runs
 // the same stack in a variant that also writes the activations and pooling
 // masks to device memory, the backward data gradients down the blocks one
-// kernel per block (k_convT_bf16) and the convolution weight gradients over LDS
-// tiles of 8 interleaved inputs (k_conv_dw_bf16, k_conv1_dw_bf16); FP32
+// kernel per block (k_convT_bf16, block 2's also giving block 1's weight
+// gradients) and the other convolution weight gradients over LDS tiles of 8
+// interleaved inputs (k_conv_dw_bf16, k_conv_dw_pipe_bf16); FP32
 // networks and the layer path (gpfc_cnn_set_fused(0)) run layer by layer
 // through device memory. A step can be replayed as one HIP graph. Every fused
 // path gives the same bits as the layer path, except the convolution weight
@@ -1414,38 +1415,76 @@ __device__ __forceinline__ void unpool8(uint4 g, uint2 k, uint4& e0, uint4& e1) 
 // of the block's output) -> dout [B][2 LP][CIN] (pooled gradient of the
 // block below).
 constexpr int kTW = 16;   // waves per block
-template <int LP, int COUT, int CIN, int WLD, int RB, int CB>
+// Block 2's kernel (C1 = 1: bf16 input, 2: FP32 input) also takes the
+// weight and bias gradients of conv block 1, whose pre-activation gradient is
+// its output (the pooled gradient of block 1) unpooled with block 1's mask:
+// per input an MFMA product G[16 ch][256 positions] x X[256][16], X[p][dx] =
+// x[(p + dx - 2) mod 256] for dx < 5, 1 in column 5 (the bias), 0 beyond;
+// G goes to the wave's LDS slice transposed (channel rows of 528 bytes:
+// conflict-free writes, fragment reads with at most 2 lanes per bank) and
+// x as two copies offset by one element, so every lane's 8-position window
+// is 4-byte aligned. A wave adds its inputs' products in order; the block
+// sums its waves in order into part_out[block][co*5+dx, then 80+co], added
+// up in block order by k_sum_parts. The block-1 gradient itself is not
+// written.
+constexpr int kXsDw = 136;   // dwords per x copy (268 elements used)
+template <int LP, int COUT, int CIN, int WLD, int RB, int CB, int C1>
 struct ConvTLds {
     uint16_t w[CIN * WLD];
-    uint16_t dp[kTW][2 * LP * COUT];   // unpooled gradient [2 LP][COUT] (act_off rows)
+    uint16_t dp[kTW][2 * LP * COUT + (C1 ? 128 : 0)];   // unpooled gradient [2 LP][COUT] (act_off rows)
+    uint32_t xs[C1 ? kTW : 1][2][kXsDw];
 };
 
-template <int LP, int COUT, int CIN, int WLD, int RB, int CB>
+template <int LP, int COUT, int CIN, int WLD, int RB, int CB, int C1 = 0>
 __global__ __launch_bounds__(kTW * 64, 1) void k_convT_bf16(int B, const uint16_t* __restrict__ wb,
                                                         const uint16_t* __restrict__ d,
                                                         const uint8_t* __restrict__ m,
-                                                        uint16_t* __restrict__ dout) {
+                                                        uint16_t* __restrict__ dout,
+                                                        const uint8_t* __restrict__ m1 = nullptr,
+                                                        const void* __restrict__ x = nullptr,
+                                                        float* __restrict__ part_out = nullptr) {
     constexpr int L = 2 * LP, K = 5 * COUT, E = LP * COUT, U = E / 512;   // 8 values per lane and unit
-    static_assert(E % 512 == 0 && sizeof(ConvTLds<LP, COUT, CIN, WLD, RB, CB>) <= 160 * 1024, "shapes");
-    __shared__ __attribute__((aligned(16))) ConvTLds<LP, COUT, CIN, WLD, RB, CB> sm;
+    static_assert(E % 512 == 0 && sizeof(ConvTLds<LP, COUT, CIN, WLD, RB, CB, C1>) <= 160 * 1024, "shapes");
+    static_assert(!C1 || (L == 128 && CIN == 16 && RB == 8 && CB == 1), "block-1 gradient: block 2's shape");
+    __shared__ __attribute__((aligned(16))) ConvTLds<LP, COUT, CIN, WLD, RB, CB, C1> sm;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, q = lane >> 4;
     for (int i = tid; i < CIN * WLD; i += kTW * 64) {
         const int n = i / WLD, k = i - n * WLD;
         sm.w[i] = k < K ? wb[n * K + k] : (uint16_t)0;
     }
-    __syncthreads();   // the only block-wide wait: weights staged
+    __syncthreads();   // weights staged
     uint16_t* dp = sm.dp[wave];
     const int64_t stride = (int64_t)gridDim.x * kTW;
     int64_t fi = (int64_t)blockIdx.x * kTW + wave;
     uint4 ng[U];
     uint2 nk[U];
+    // block 1: the input (4 positions per lane) and the mask words (tile i:
+    // position 16 i + r, channels 4q .. 4q + 3)
+    uint32_t nx[2], nm1[C1 ? 8 : 1];
     auto load = [&](int64_t f) {   // (unconditional: past the batch, read again and never used)
         f = f < B ? f : B - 1;
         for (int h = 0; h < U; ++h) {
             ng[h] = ld_u4(d + f * E + h * 512 + lane * 8);
             nk[h] = *reinterpret_cast<const uint2*>(m + f * E + h * 512 + lane * 8);
         }
+        if constexpr (C1 != 0) {
+            for (int i = 0; i < 8; ++i)
+                nm1[i] = *reinterpret_cast<const uint32_t*>(m1 + f * 2048 + (16 * i + r) * 16 + 4 * q);
+            if constexpr (C1 == 2) {
+                const float4 v =
+                    *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(x) + f * 256 + lane * 4);
+                nx[0] = f2bf2(v.x, v.y);
+                nx[1] = f2bf2(v.z, v.w);
+            } else {
+                const uint2 v =
+                    *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(x) + f * 256 + lane * 4);
+                nx[0] = v.x;
+                nx[1] = v.y;
+            }
+        }
     };
+    f32x4 g1 = f32x4{0.0f, 0.0f, 0.0f, 0.0f};   // block 1: D[ch 4q..4q+3][column r]
     load(fi);
     for (; fi < B; fi += stride) {
         for (int h = 0; h < U; ++h) {
@@ -1455,11 +1494,113 @@ __global__ __launch_bounds__(kTW * 64, 1) void k_convT_bf16(int B, const uint16_
             *reinterpret_cast<uint4*>(dp + act_off<COUT>(2 * xp, c0)) = ev;
             *reinterpret_cast<uint4*>(dp + act_off<COUT>(2 * xp + 1, c0)) = od;
         }
-        __builtin_amdgcn_sched_barrier(0);
-        load(fi + stride);
-        wave_lds_sync();
-        convT_one<L, CIN, COUT, COUT, WLD, RB, CB>(dp, sm.w, dout + fi * (L * CIN));
+        if constexpr (C1 == 0) {
+            __builtin_amdgcn_sched_barrier(0);
+            load(fi + stride);
+            wave_lds_sync();
+            convT_one<L, CIN, COUT, COUT, WLD, RB, CB>(dp, sm.w, dout + fi * (L * CIN));
+        } else {
+            const uint32_t cx0 = nx[0], cx1 = nx[1];
+            uint32_t cm1[8];
+            for (int i = 0; i < 8; ++i) cm1[i] = nm1[i];
+            // the lane's row and group, copied each input through an opaque move so
+            // that the LDS offsets below are worked out here, not held in
+            // registers across the loop
+            int r, q;
+            asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"(lane & 15));
+            asm volatile("v_mov_b32 %0, %1" : "=v"(q) : "v"(lane >> 4));
+            // x copies: xs[0][j] = x[(j - 4) mod 256], xs[1][j] = x[(j - 3) mod 256];
+            // lane l holds x[4l .. 4l + 3] and writes both copies' words 2l + 2, 2l + 3
+            // (lane 63 also words 0, 1 and lanes 0, 1 words 130 .. 133: the wrap)
+            {
+                const uint32_t nwx = __shfl(cx0, (lane + 1) & 63);   // x[4l + 4], x[4l + 5]
+                const uint2 c0v = make_uint2(cx0, cx1);
+                const uint2 c1v = make_uint2((cx0 >> 16) | (cx1 << 16), (cx1 >> 16) | (nwx << 16));
+                uint32_t* x0 = sm.xs[C1 ? wave : 0][0];
+                uint32_t* x1 = sm.xs[C1 ? wave : 0][1];
+                *reinterpret_cast<uint2*>(x0 + 2 * lane + 2) = c0v;
+                *reinterpret_cast<uint2*>(x1 + 2 * lane + 2) = c1v;
+                if (lane == 63) {
+                    *reinterpret_cast<uint2*>(x0) = c0v;
+                    *reinterpret_cast<uint2*>(x1) = c1v;
+                }
+                if (lane < 2) {
+                    *reinterpret_cast<uint2*>(x0 + 130 + 2 * lane) = c0v;
+                    *reinterpret_cast<uint2*>(x1 + 130 + 2 * lane) = c1v;
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            load(fi + stride);
+            wave_lds_sync();
+            // the data gradient as convT_one computes it (same products in the
+            // same order), in two halves of 4 row tiles so that fewer
+            // accumulators and operands are live; kept as bf16 pairs
+            uint32_t pk[8][2];   // tile i: channels (4q, 4q + 1), (4q + 2, 4q + 3) at position 16 i + r
+            for (int h = 0; h < 2; ++h) {
+                f32x4 acc[4];
+                for (int i = 0; i < 4; ++i) acc[i] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int ks = 0; ks < K / 32; ++ks) {
+                    const int k = ks * 32 + q * 8;
+                    const int dx = k / COUT, c0 = k - dx * COUT;
+                    bf16x8 a[4];
+                    for (int i = 0; i < 4; ++i) {
+                        int pos = (4 * h + i) * 16 + r - dx + 2;
+                        pos = pos < 0 ? pos + L : (pos >= L ? pos - L : pos);
+                        a[i] = *reinterpret_cast<const bf16x8*>(dp + act_off<COUT>(pos, c0));
+                    }
+                    const bf16x8 b = *reinterpret_cast<const bf16x8*>(sm.w + r * WLD + k);
+                    for (int i = 0; i < 4; ++i) acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b, a[i], acc[i], 0, 0, 0);
+                }
+                for (int i = 0; i < 4; ++i) {
+                    pk[4 * h + i][0] = f2bf2(acc[i][0], acc[i][1]);
+                    pk[4 * h + i][1] = f2bf2(acc[i][2], acc[i][3]);
+                }
+            }
+            wave_lds_sync();   // the wave's reads of dp are done
+            // block 1's pre-activation gradient, transposed: row ch (132 words)
+            // holds 256 positions; word pos of a row is pooled position pos
+            // (its even and odd position)
+            uint32_t* gt = reinterpret_cast<uint32_t*>(dp);
+            for (int i = 0; i < 8; ++i) {
+                const uint32_t v01 = pk[i][0], v23 = pk[i][1];
+                const int pos = 16 * i + r;
+                for (int e = 0; e < 4; ++e) {
+                    const int ch = 4 * q + e;
+                    const uint32_t g = ((e < 2 ? v01 : v23) >> (16 * (e & 1))) & 0xffffu;
+                    const uint32_t mb = (cm1[i] >> (8 * e)) & 3u;
+                    const uint32_t wv = (mb & 2u) ? ((mb & 1u) ? g << 16 : g) : 0u;
+                    gt[ch * 132 + pos] = wv;
+                }
+            }
+            wave_lds_sync();
+            const uint32_t* xsw = sm.xs[C1 ? wave : 0][0];
+            const int nn = r < 4 ? r : 4, dl = nn - 2, par = dl & 1;
+            for (int st = 0; st < 8; ++st) {
+                // row r, positions 32 st + 8 q .. + 7
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(gt + r * 132 + 16 * st + 4 * q);
+                const int j0 = 32 * st + 8 * q + dl + 4 - par;   // even
+                const uint32_t* xw = xsw + par * kXsDw + (j0 >> 1);
+                uint32_t bw[4] = {xw[0], xw[1], xw[2], xw[3]};
+                for (int t = 0; t < 4; ++t) bw[t] = r < 5 ? bw[t] : (r == 5 ? 0x3F803F80u : 0u);
+                const bf16x8 b = __builtin_bit_cast(bf16x8, make_uint4(bw[0], bw[1], bw[2], bw[3]));
+                g1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, g1, 0, 0, 0);
+            }
+        }
         wave_lds_sync();   // dp is reused by the next input
+    }
+    if constexpr (C1 != 0) {
+        // the block's waves in order (the wave tiles go where the gradients were)
+        __syncthreads();
+        float* red = reinterpret_cast<float*>(&sm.dp[0][0]);
+        for (int e = 0; e < 4; ++e) red[wave * 256 + (4 * q + e) * 16 + r] = g1[e];
+        __syncthreads();
+        if (tid < 96) {
+            const int ch = tid < 80 ? tid / 5 : tid - 80, col = tid < 80 ? tid - 5 * ch : 5;
+            float t = 0.0f;
+            for (int w = 0; w < kTW; ++w) t += red[w * 256 + ch * 16 + col];
+            part_out[(int64_t)blockIdx.x * 96 + tid] = t;
+        }
     }
 }
 
@@ -1950,122 +2091,6 @@ __global__ __launch_bounds__(512, 1) void k_conv_dw_pipe_bf16(
         float t = 0.0f;
         for (int u = og; u < 256; u += COUT / 4) t += red[u * 4 + j];
         part_out[(int64_t)blockIdx.x * (COUT * (5 * CIN) + COUT) + COUT * (5 * CIN) + tid] = t;
-    }
-}
-
-// Sum over a wave's 64 lanes, the same bits in every lane: within rows of 16
-// lanes by DPP (swap neighbours, swap pairs, mirror 8, mirror 16), then
-// across rows; a fixed order (deterministic).
-__device__ __forceinline__ float wave_sum_dpp(float v) {
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
-    return v;
-}
-
-// Weight and bias gradients of conv block 1 (one input channel) from its
-// pooled gradient and mask (the unpooling folded in). A block takes groups
-// of 8 consecutive inputs: their gradients (32 KB), masks (16 KB) and inputs
-// (rounded to bf16 as the forward pass saw them, 4 KB) are copied to LDS with
-// 16-byte loads issued together (the next group's while the current one is
-// computed), then thread = one pooled position of one input, all 16
-// channels. Per-block sums go to part_out[block][96] (80 weights [co][dx],
-// then 16 biases: the canonical order), added up in block order.
-template <bool kXF32>
-__global__ __launch_bounds__(256, 2) void k_conv1_dw_bf16(
-    const uint16_t* __restrict__ dact, const uint8_t* __restrict__ mask, const void* __restrict__ x, int B,
-    int groups_per_block, float* __restrict__ part_out) {
-    // the gradients' two 16-byte halves (channels 0-7, 8-15) in two arrays,
-    // the second 8 slots further on: conflict-free writes and reads
-    constexpr int kHalf2 = 1024 + 8;
-    __shared__ __attribute__((aligned(16))) uint16_t sd[(kHalf2 + 1024) * 8];
-    __shared__ __attribute__((aligned(16))) uint8_t smk[8 * 128 * 16];
-    __shared__ __attribute__((aligned(16))) uint16_t sx[8 * 256];
-    __shared__ float red[96][4];
-    const int tid = threadIdx.x;
-    const int ngroups = (B + 7) / 8;
-    const int g0 = blockIdx.x * groups_per_block;
-    const int g1 = min(ngroups, g0 + groups_per_block);
-    float acc[96];
-    for (int j = 0; j < 96; ++j) acc[j] = 0.0f;
-    uint4 rd[8], rm[4], rx;
-    auto load = [&](int g) {
-        const int64_t b0 = (int64_t)g * 8;
-        const int nb = (int)min<int64_t>(8, B - b0);   // inputs in the group
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {                  // 256 chunks of 16 B per input
-            const int c = tid + i * 256;
-            rd[i] = (c >> 8) < nb ? *reinterpret_cast<const uint4*>(dact + b0 * 2048 + (int64_t)c * 8)
-                                  : make_uint4(0u, 0u, 0u, 0u);
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {                  // 128 chunks per input
-            const int c = tid + i * 256;
-            rm[i] = (c >> 7) < nb ? *reinterpret_cast<const uint4*>(mask + b0 * 2048 + (int64_t)c * 16)
-                                  : make_uint4(0u, 0u, 0u, 0u);
-        }
-        rx = make_uint4(0u, 0u, 0u, 0u);               // 32 chunks of 8 values per input
-        if ((tid >> 5) < nb) {
-            if constexpr (kXF32) {
-                const float4* xf = reinterpret_cast<const float4*>(reinterpret_cast<const float*>(x) +
-                                                                   b0 * 256 + (int64_t)tid * 8);
-                const float4 u = xf[0], v = xf[1];
-                rx = make_uint4(f2bf2(u.x, u.y), f2bf2(u.z, u.w), f2bf2(v.x, v.y), f2bf2(v.z, v.w));
-            } else {
-                rx = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(x) + b0 * 256 +
-                                                     (int64_t)tid * 8);
-            }
-        }
-    };
-    if (g0 < g1) load(g0);
-    for (int g = g0; g < g1; ++g) {
-        for (int i = 0; i < 8; ++i) {
-            const int c = tid + i * 256;
-            reinterpret_cast<uint4*>(sd)[(c & 1) * kHalf2 + (c >> 1)] = rd[i];
-        }
-        for (int i = 0; i < 4; ++i) reinterpret_cast<uint4*>(smk)[tid + i * 256] = rm[i];
-        reinterpret_cast<uint4*>(sx)[tid] = rx;
-        __syncthreads();
-        if (g + 1 < g1) load(g + 1);
-        for (int j = 0; j < 4; ++j) {
-            const int p = tid + j * 256, sp = p >> 7, xp = p & 127;
-            float xv[6];   // input positions 2xp - 2 ... 2xp + 3: pairs xp - 1, xp, xp + 1 (circular)
-            for (int h = 0; h < 3; ++h) {
-                const uint32_t v = reinterpret_cast<const uint32_t*>(sx)[sp * 128 + ((xp + h - 1) & 127)];
-                xv[2 * h] = bf2f((uint16_t)(v & 0xffffu));
-                xv[2 * h + 1] = bf2f((uint16_t)(v >> 16));
-            }
-            const uint4 ga = reinterpret_cast<const uint4*>(sd)[p];
-            const uint4 gb = reinterpret_cast<const uint4*>(sd)[kHalf2 + p];
-            const uint4 mk = reinterpret_cast<const uint4*>(smk)[p];
-            const uint32_t gw[8] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
-            const uint32_t kw[4] = {mk.x, mk.y, mk.z, mk.w};
-#pragma unroll
-            for (int co = 0; co < 16; ++co) {
-                const uint32_t m = (kw[co >> 2] >> (8 * (co & 3))) & 3u;
-                const float gv = (m & 2u) ? bf2f((uint16_t)(gw[co >> 1] >> (16 * (co & 1)))) : 0.0f;
-                const int par = (int)(m & 1u);
-#pragma unroll
-                for (int dx = 0; dx < 5; ++dx) acc[co * 5 + dx] += gv * (par ? xv[dx + 1] : xv[dx]);
-                acc[80 + co] += gv;
-            }
-        }
-        __syncthreads();   // the group's LDS copy is read
-    }
-    const int lane = tid & 63, wave = tid >> 6;
-#pragma unroll
-    for (int j = 0; j < 96; ++j) {
-        const float v = wave_sum_dpp(acc[j]);
-        if (lane == 0) red[j][wave] = v;
-    }
-    __syncthreads();
-    if (tid < 96) {
-        float t = 0.0f;
-        for (int w = 0; w < 4; ++w) t += red[tid][w];
-        part_out[(int64_t)blockIdx.x * 96 + tid] = t;
     }
 }
 
@@ -2639,15 +2664,23 @@ int32_t backward_convs_bf16(gpfc_cnn* c, const void* x, int xf32, int B, hipStre
     const uint16_t* d4 = (const uint16_t*)c->d_a;                 // [B][16][64]
     uint16_t* d3 = (uint16_t*)c->d_b;                              // [B][32][64]
     uint16_t* d2 = (uint16_t*)c->d_b + (int64_t)B * 2048;          // [B][64][32]
-    uint16_t* d1 = (uint16_t*)c->d_a + (int64_t)B * 2048;          // [B][128][16]
     // the data gradients down the blocks, one kernel per block
     const dim3 gt((unsigned)std::min<int64_t>((B + kTW - 1) / kTW, c->n_cu));
     hipLaunchKernelGGL((k_convT_bf16<16, 64, 64, kB4Ld, 2, 4>), gt, dim3(kTW * 64), 0, s, B,
                        (const uint16_t*)c->wb4, d4, c->m4, d3);
     hipLaunchKernelGGL((k_convT_bf16<32, 64, 32, kB3Ld, 4, 2>), gt, dim3(kTW * 64), 0, s, B,
                        (const uint16_t*)c->wb3, (const uint16_t*)d3, c->m3, d2);
-    hipLaunchKernelGGL((k_convT_bf16<64, 32, 16, kB2Ld, 8, 1>), gt, dim3(kTW * 64), 0, s, B,
-                       (const uint16_t*)c->wb2, (const uint16_t*)d2, c->m2, d1);
+    // block 2's data gradient also gives block 1's weight gradients (per-block
+    // rows in c->ws, summed in block order before the other blocks use c->ws)
+    if (xf32)
+        hipLaunchKernelGGL((k_convT_bf16<64, 32, 16, kB2Ld, 8, 1, 2>), gt, dim3(kTW * 64), 0, s, B,
+                           (const uint16_t*)c->wb2, (const uint16_t*)d2, c->m2, (uint16_t*)nullptr, c->m1, x,
+                           c->ws);
+    else
+        hipLaunchKernelGGL((k_convT_bf16<64, 32, 16, kB2Ld, 8, 1, 1>), gt, dim3(kTW * 64), 0, s, B,
+                           (const uint16_t*)c->wb2, (const uint16_t*)d2, c->m2, (uint16_t*)nullptr, c->m1, x,
+                           c->ws);
+    hipLaunchKernelGGL(k_sum_parts, dim3(24), dim3(256), 0, s, c->ws, (int)gt.x, 96, g + kConvW[1]);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cnn_err(e, "backward data gradients");
     e = conv_dw_bf16<32, 64, 64, 4, 1>(c, B, d4, c->m4, (const uint16_t*)c->a3, g + kConvW[4], g + conv_b(4), s);
@@ -2655,20 +2688,7 @@ int32_t backward_convs_bf16(gpfc_cnn* c, const void* x, int xf32, int B, hipStre
         e = conv_dw_bf16<64, 32, 64, 2, 2>(c, B, d3, c->m3, (const uint16_t*)c->a2, g + kConvW[3], g + conv_b(3), s);
     if (e == hipSuccess)
         e = conv_dw_bf16<128, 16, 32, 1, 4>(c, B, d2, c->m2, (const uint16_t*)c->a1, g + kConvW[2], g + conv_b(2), s);
-    if (e != hipSuccess) return cnn_err(e, "k_conv_dw_bf16");
-    const int groups = (B + 7) / 8;
-    int parts = std::min(groups, 2 * c->n_cu);   // two blocks per CU overlap one's loads with the other's sums
-    const int gpb = (groups + parts - 1) / parts;
-    parts = (groups + gpb - 1) / gpb;
-    if (xf32)
-        hipLaunchKernelGGL(k_conv1_dw_bf16<true>, dim3((unsigned)parts), dim3(256), 0, s, d1, c->m1, x, B, gpb,
-                           c->ws);
-    else
-        hipLaunchKernelGGL(k_conv1_dw_bf16<false>, dim3((unsigned)parts), dim3(256), 0, s, d1, c->m1, x, B, gpb,
-                           c->ws);
-    hipLaunchKernelGGL(k_sum_parts, dim3(24), dim3(256), 0, s, c->ws, parts, 96, g + kConvW[1]);
-    e = hipGetLastError();
-    return e == hipSuccess ? GPFC_OK : cnn_err(e, "k_conv1_dw_bf16");
+    return e == hipSuccess ? GPFC_OK : cnn_err(e, "k_conv_dw_bf16");
 }
 
 template <class P>
