@@ -366,6 +366,73 @@ struct EpConvDWB {
     }
 };
 
+// The weight and bias gradients of the convolution blocks of a bf16 training
+// step reduced together: up to 4 jobs, each S partial rows of `row` floats
+// ([COUT][5 CIN] weight sums, then COUT bias sums) in its own region. Pass 1
+// (k_dw_seg) adds groups of kDwR consecutive rows into segment rows; pass 2
+// (k_dw_final) adds a job's segments in order and stores through EpConvDWB:
+// two launches for all the blocks, every sum in one fixed order.
+constexpr int kDwR = 8;
+struct DwJobs {
+    const float* ws[4];
+    float* seg[4];
+    float* gw[4];
+    float* gb[4];
+    int S[4], row[4], cin[4];
+    int ybase[5];   // pass 1: first segment (grid y) of each job
+    int xbase[5];   // pass 2: first 64-column tile (grid x) of each job
+    int n;
+};
+
+__device__ __forceinline__ int dw_job(const int* base, int n, int b) {
+    int j = 0;
+    while (j + 1 < n && b >= base[j + 1]) ++j;
+    return j;
+}
+
+__global__ __launch_bounds__(256) void k_dw_seg(DwJobs J) {
+    const int j = dw_job(J.ybase, J.n, blockIdx.y);
+    const int y = blockIdx.y - J.ybase[j], S = J.S[j];
+    const int64_t row = J.row[j];
+    const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+    if (i >= row) return;
+    const float* ws = J.ws[j];
+    const int z0 = y * kDwR;
+    float4 p[kDwR];
+#pragma unroll
+    for (int u = 0; u < kDwR; ++u)
+        p[u] = z0 + u < S ? *reinterpret_cast<const float4*>(ws + (z0 + u) * row + i)
+                          : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+    for (int u = 0; u < kDwR; ++u) {
+        v.x += p[u].x;
+        v.y += p[u].y;
+        v.z += p[u].z;
+        v.w += p[u].w;
+    }
+    *reinterpret_cast<float4*>(J.seg[j] + y * row + i) = v;
+}
+
+__global__ __launch_bounds__(1024) void k_dw_final(DwJobs J) {
+    __shared__ float red[16][64];
+    const int j = dw_job(J.xbase, J.n, blockIdx.x);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = J.row[j], G = (J.S[j] + kDwR - 1) / kDwR;
+    const int i = (blockIdx.x - J.xbase[j]) * 64 + lane;
+    float v = 0.0f;
+    if (i < row)
+        for (int z = wave; z < G; z += 16) v += J.seg[j][(int64_t)z * row + i];
+    red[wave][lane] = v;
+    __syncthreads();
+    if (wave == 0 && i < row) {
+        float t = 0.0f;
+        for (int w = 0; w < 16; ++w) t += red[w][lane];
+        const int cin = J.cin[j], cout = row / (5 * cin + 1);
+        EpConvDWB{J.gw[j], J.gb[j], cin, cout * 5 * cin}.store(0, i, t);
+    }
+}
+
 // Weight and bias gradients of a dense layer reduced together: partial rows
 // hold [M][N] weight sums (the weight-gradient epilogue's layout), then M
 // bias sums (M = 1, N = M*N + M in the reduction's terms).
@@ -490,14 +557,18 @@ __device__ __forceinline__ float wave_sum_parts(const float* __restrict__ parts,
 }
 
 __global__ __launch_bounds__(256) void k_head_final(const float* __restrict__ parts, int nparts, int B,
-                                                    float* __restrict__ grad, float* __restrict__ loss) {
+                                                    float* __restrict__ grad, float* __restrict__ loss,
+                                                    float* __restrict__ loss2) {
     const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (j >= kHeadSums) return;
     const float v = wave_sum_parts(parts, nparts, kHeadSums, j, lane);
     if (lane) return;
     if (j < 64) grad[F3W + j] = v;
     else if (j == 64) grad[F3B] = v;
-    else *loss = v / (float)B;
+    else {
+        *loss = v / (float)B;
+        if (loss2) *loss2 = v / (float)B;   // the caller's copy (no separate copy launch)
+    }
 }
 
 // ------------------------------------------------------------------ fused inference
@@ -2391,6 +2462,13 @@ hipError_t bias_grad(const typename P::T* d, int64_t rows, int C, float* g, floa
 
 // Split-K workspace (floats) every network holds.
 constexpr int64_t kSplitWs = int64_t(8) << 20;
+// The convolution weight-gradient workspace of a bf16 step: block 1's rows
+// (one per data-gradient block), blocks 4, 3 and 2's partial rows (several
+// blocks per CU each), then the segment rows of the two-pass reduction (an
+// eighth of the rest, plus one per job).
+constexpr int64_t kDwCap[4] = {int64_t(1) << 16, int64_t(6) << 20, int64_t(6) << 20, int64_t(3) << 20};
+constexpr int64_t kDwWs = kDwCap[0] + kDwCap[1] + kDwCap[2] + kDwCap[3] +
+                          (kDwCap[0] + kDwCap[1] + kDwCap[2] + kDwCap[3]) / 8 + 4 * 20544;
 
 // Weight and bias gradients of a bf16 dense layer with M outputs and N
 // inputs (M a multiple of 64, N of 128) from its output gradient d [B][M]
@@ -2461,7 +2539,9 @@ struct gpfc_cnn {
     float* m = nullptr;
     float* v = nullptr;
     float* loss = nullptr;
+    float* loss_out = nullptr;   // during one backward call: the caller's loss buffer
     float* ws = nullptr;         // split-K partial sums (kSplitWs floats)
+    float* wsd = nullptr;        // convolution weight-gradient rows of a bf16 step (kDwWs floats)
     void* work = nullptr;        // packed weights + activations
     bool packed = false;
     bool fused = true;           // bf16 inference through the fused convolution stack
@@ -2621,7 +2701,7 @@ int32_t forward(gpfc_cnn* c, const void* x, int xf32, int B, float* logits, cons
                                rows, psum);
         }
         hipLaunchKernelGGL(k_head_final, dim3((kHeadSums + 3) / 4), dim3(256), 0, s, psum, parts, B,
-                           c->grad, c->loss);
+                           c->grad, c->loss, c->loss_out);
     } else if (logits && !fused)
         hipLaunchKernelGGL((k_head_infer<P>), dim3(blocks_for(B)), dim3(256), 0, s, (const T*)c->h2,
                            B, w + F3W, w + F3B, logits);
@@ -2634,28 +2714,27 @@ int32_t forward(gpfc_cnn* c, const void* x, int xf32, int B, float* logits, cons
 // blocks, then each block's weight and bias gradients from its pooled
 // gradient, mask and input.
 template <int L, int CIN, int COUT, int WN, int WK>
-hipError_t conv_dw_bf16(const gpfc_cnn* c, int B, const uint16_t* dact, const uint8_t* mask,
-                        const uint16_t* act, float* gw, float* gb, hipStream_t s) {
+int conv_dw_bf16(const gpfc_cnn* c, int B, const uint16_t* dact, const uint8_t* mask, const uint16_t* act,
+                 float* ws, int64_t cap, hipStream_t s) {
     using namespace gcnn;
-    const int64_t mn = (int64_t)COUT * 5 * CIN;
+    const int64_t row = (int64_t)COUT * 5 * CIN + COUT;
+    static_assert(COUT % 4 == 0, "rows of whole 16-byte units");
     const int groups = (B + 7) / 8;
-    const int64_t row = mn + COUT;
     // block 4 (one 32-position item per group): the staged pipeline, one
     // block of 8 waves per CU; blocks 2 and 3: several 4-wave blocks per CU,
     // each staging and computing in turn (faster for their small items)
     constexpr bool kPipe = L == 32;
     const int per_cu = kPipe ? 1 : (CIN == 16 ? 3 : 2);
-    int blocks = (int)std::min<int64_t>(std::min(groups, per_cu * c->n_cu), kSplitWs / row);
+    int blocks = (int)std::min<int64_t>(std::min(groups, per_cu * c->n_cu), cap / row);
     const int gpb = (groups + blocks - 1) / blocks;
     blocks = (groups + gpb - 1) / gpb;
     if constexpr (kPipe)
         hipLaunchKernelGGL((k_conv_dw_pipe_bf16<L, CIN, COUT, WN, WK>), dim3((unsigned)blocks), dim3(512), 0, s, B,
-                           gpb, dact, mask, act, c->ws);
+                           gpb, dact, mask, act, ws);
     else
         hipLaunchKernelGGL((k_conv_dw_bf16<L, CIN, COUT, WN, WK>), dim3((unsigned)blocks), dim3(256), 0, s, B, gpb,
-                           dact, mask, act, c->ws);
-    reduce_partials_w(c->ws, blocks, 1, (int)row, EpConvDWB{gw, gb, CIN, (int)mn}, s);
-    return hipGetLastError();
+                           dact, mask, act, ws);
+    return blocks;   // partial rows
 }
 
 int32_t backward_convs_bf16(gpfc_cnn* c, const void* x, int xf32, int B, hipStream_t s) {
@@ -2670,25 +2749,54 @@ int32_t backward_convs_bf16(gpfc_cnn* c, const void* x, int xf32, int B, hipStre
                        (const uint16_t*)c->wb4, d4, c->m4, d3);
     hipLaunchKernelGGL((k_convT_bf16<32, 64, 32, kB3Ld, 4, 2>), gt, dim3(kTW * 64), 0, s, B,
                        (const uint16_t*)c->wb3, (const uint16_t*)d3, c->m3, d2);
-    // block 2's data gradient also gives block 1's weight gradients (per-block
-    // rows in c->ws, summed in block order before the other blocks use c->ws)
+    // block 2's data gradient also gives block 1's weight gradients (one row
+    // of 96 sums per block)
+    float* wd = c->wsd;
+    const int64_t cap1 = kDwCap[0], capw[3] = {kDwCap[1], kDwCap[2], kDwCap[3]};
+    if ((int64_t)gt.x * 96 > cap1) return GPFC_ERANGE;   // more data-gradient blocks than rows
     if (xf32)
         hipLaunchKernelGGL((k_convT_bf16<64, 32, 16, kB2Ld, 8, 1, 2>), gt, dim3(kTW * 64), 0, s, B,
-                           (const uint16_t*)c->wb2, (const uint16_t*)d2, c->m2, (uint16_t*)nullptr, c->m1, x,
-                           c->ws);
+                           (const uint16_t*)c->wb2, (const uint16_t*)d2, c->m2, (uint16_t*)nullptr, c->m1, x, wd);
     else
         hipLaunchKernelGGL((k_convT_bf16<64, 32, 16, kB2Ld, 8, 1, 1>), gt, dim3(kTW * 64), 0, s, B,
-                           (const uint16_t*)c->wb2, (const uint16_t*)d2, c->m2, (uint16_t*)nullptr, c->m1, x,
-                           c->ws);
-    hipLaunchKernelGGL(k_sum_parts, dim3(24), dim3(256), 0, s, c->ws, (int)gt.x, 96, g + kConvW[1]);
+                           (const uint16_t*)c->wb2, (const uint16_t*)d2, c->m2, (uint16_t*)nullptr, c->m1, x, wd);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cnn_err(e, "backward data gradients");
-    e = conv_dw_bf16<32, 64, 64, 4, 1>(c, B, d4, c->m4, (const uint16_t*)c->a3, g + kConvW[4], g + conv_b(4), s);
-    if (e == hipSuccess)
-        e = conv_dw_bf16<64, 32, 64, 2, 2>(c, B, d3, c->m3, (const uint16_t*)c->a2, g + kConvW[3], g + conv_b(3), s);
-    if (e == hipSuccess)
-        e = conv_dw_bf16<128, 16, 32, 1, 4>(c, B, d2, c->m2, (const uint16_t*)c->a1, g + kConvW[2], g + conv_b(2), s);
-    return e == hipSuccess ? GPFC_OK : cnn_err(e, "k_conv_dw_bf16");
+    // blocks 4, 3, 2: partial rows in their own regions, then one two-pass
+    // reduction of all four blocks' rows
+    float* r4 = wd + cap1;
+    float* r3 = r4 + capw[0];
+    float* r2 = r3 + capw[1];
+    float* segs = r2 + capw[2];
+    DwJobs J{};
+    J.n = 4;
+    J.ws[0] = wd;  J.S[0] = (int)gt.x;  J.row[0] = 96;      J.cin[0] = 1;
+    J.gw[0] = g + kConvW[1];  J.gb[0] = g + kConvW[1] + 80;
+    J.ws[1] = r4;  J.S[1] = conv_dw_bf16<32, 64, 64, 4, 1>(c, B, d4, c->m4, (const uint16_t*)c->a3, r4, capw[0], s);
+    J.row[1] = 64 * 320 + 64;  J.cin[1] = 64;  J.gw[1] = g + kConvW[4];  J.gb[1] = g + conv_b(4);
+    J.ws[2] = r3;  J.S[2] = conv_dw_bf16<64, 32, 64, 2, 2>(c, B, d3, c->m3, (const uint16_t*)c->a2, r3, capw[1], s);
+    J.row[2] = 64 * 160 + 64;  J.cin[2] = 32;  J.gw[2] = g + kConvW[3];  J.gb[2] = g + conv_b(3);
+    J.ws[3] = r2;  J.S[3] = conv_dw_bf16<128, 16, 32, 1, 4>(c, B, d2, c->m2, (const uint16_t*)c->a1, r2, capw[2], s);
+    J.row[3] = 32 * 80 + 32;  J.cin[3] = 16;  J.gw[3] = g + kConvW[2];  J.gb[3] = g + conv_b(2);
+    e = hipGetLastError();
+    if (e != hipSuccess) return cnn_err(e, "k_conv_dw_bf16");
+    int ymax = 0, xcols = 0;
+    J.ybase[0] = 0;
+    J.xbase[0] = 0;
+    for (int j = 0; j < 4; ++j) {
+        const int G = (J.S[j] + kDwR - 1) / kDwR;
+        J.seg[j] = segs;
+        segs += (int64_t)G * J.row[j];
+        J.ybase[j + 1] = J.ybase[j] + G;
+        J.xbase[j + 1] = J.xbase[j] + (J.row[j] + 63) / 64;
+        ymax = std::max(ymax, (J.row[j] / 4 + 255) / 256);
+        xcols = J.xbase[j + 1];
+    }
+    // (segment rows: sum of ceil(S_j / 8) row_j <= sum of cap_j / 8 + 4 rows <= what kDwWs leaves)
+    hipLaunchKernelGGL(k_dw_seg, dim3((unsigned)ymax, (unsigned)J.ybase[4]), dim3(256), 0, s, J);
+    hipLaunchKernelGGL(k_dw_final, dim3((unsigned)xcols), dim3(1024), 0, s, J);
+    e = hipGetLastError();
+    return e == hipSuccess ? GPFC_OK : cnn_err(e, "conv weight-gradient reduction");
 }
 
 template <class P>
@@ -2823,7 +2931,7 @@ int32_t gpfc_cnn_create(gpfc_cnn** out, int32_t device, int32_t precision, int64
     // the reduction workspace also holds the output layer's rows and part sums
     const int64_t wsn = std::max<int64_t>(
         gcnn::kSplitWs, 2 * Bm + (Bm / gcnn::kHeadRowsPerPart + 1) * gcnn::kHeadSums);
-    total += 4 * fsz + 256 + al(sizeof(float) * wsn);
+    total += 4 * fsz + 256 + al(sizeof(float) * wsn) + al(sizeof(float) * gcnn::kDwWs);
     const size_t qsz[5] = {32 * 80, 64 * 160, 64 * 320, 256 * 1024, 64 * 256};
     const size_t csz[5] = {32, 64, 64, 256, 64};
     for (int i = 0; i < 5; ++i) total += al(qsz[i]) + al(csz[i] * sizeof(float));
@@ -2843,6 +2951,7 @@ int32_t gpfc_cnn_create(gpfc_cnn** out, int32_t device, int32_t precision, int64
     c->v = (float*)take(sizeof(float) * gcnn::kNP);
     c->loss = (float*)take(256);
     c->ws = (float*)take(sizeof(float) * wsn);
+    c->wsd = (float*)take(sizeof(float) * gcnn::kDwWs);
     void** wv[11] = {&c->wf2, &c->wb2, &c->wf3, &c->wb3, &c->wf4, &c->wb4, &c->f1f, &c->f1b, &c->f2f, &c->f2b,
                      &c->f1k};
     for (int i = 0; i < 11; ++i) *wv[i] = take(wsz[i] * E);
@@ -2980,16 +3089,18 @@ int32_t gpfc_cnn_backward(gpfc_cnn* c, const void* x, int32_t x_f32, const float
                           float* loss_out, float* grad_out, void* stream) {
     if (!c || B < 1 || B > c->max_batch || !x || !labels) return GPFC_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    // every gradient entry is stored (not accumulated) by exactly one kernel
+    // every gradient entry is stored (not accumulated) by exactly one kernel;
+    // the loss also goes straight to loss_out
+    c->loss_out = loss_out;
     int32_t rc = c->prec ? forward<gcnn::F32>(c, x, x_f32, (int)B, nullptr, labels, s)
                          : forward<gcnn::BF16>(c, x, x_f32, (int)B, nullptr, labels, s);
+    c->loss_out = nullptr;
     if (rc != GPFC_OK) return rc;
     rc = c->prec ? backward<gcnn::F32>(c, x, x_f32, (int)B, s)
                  : backward<gcnn::BF16>(c, x, x_f32, (int)B, s);
     if (rc != GPFC_OK) return rc;
     hipError_t e = hipSuccess;
-    if (loss_out) e = hipMemcpyAsync(loss_out, c->loss, sizeof(float), hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess && grad_out)
+    if (grad_out)
         e = hipMemcpyAsync(grad_out, c->grad, sizeof(float) * gcnn::kNP, hipMemcpyDeviceToDevice, s);
     return e == hipSuccess ? GPFC_OK : cnn_err(e, "copy out");
 }
