@@ -307,8 +307,9 @@ def test_train_step_equals_backward_then_adam(torch_dev):
     assert torch.equal(a.get_params(), b.get_params())
 
 
-@pytest.mark.parametrize("B", [1, 7, 257, 300, 5000])
-def test_fused_training_matches_layer_path(torch_dev, B):
+@pytest.mark.parametrize("B,xbf16", [(1, False), (7, False), (257, False), (300, False), (5000, False),
+                                     (300, True), (4099, True)])
+def test_fused_training_matches_layer_path(torch_dev, B, xbf16):
     """A bf16 training step through the fused kernels (the convolution stack
     forward, which also writes the activations and pooling masks; the
     backward data gradients carried down the blocks in one pass; per-block
@@ -316,17 +317,20 @@ def test_fused_training_matches_layer_path(torch_dev, B):
     layer: the loss and the fully connected layers' gradients are identical
     bit for bit, the convolution gradients differ only by FP32 summation
     order (the data gradients they are formed from are bit-identical, so a
-    relative difference above 1e-5 would mean a wrong term)."""
+    relative difference above 1e-5 would mean a wrong term). Inputs in FP32
+    or as bf16 bits (block 1's weight gradients read either form)."""
     torch = torch_dev
     from paper_2312_02063_amd import CNN_BF16
     p = _params(35)
     x, y = _inputs(36, B)
     xt = torch.tensor(x, dtype=torch.float32, device="cuda")
+    if xbf16:
+        xt = xt.to(torch.bfloat16).view(torch.uint16)
     yt = torch.tensor(y, dtype=torch.float32, device="cuda")
     a = _net(torch, CNN_BF16, p, max(B, 512))
     b = _net(torch, CNN_BF16, p, max(B, 512))
     b.set_fused(False)
-    _say(f"cnn fused vs layered backward B={B}")
+    _say(f"cnn fused vs layered backward B={B} bf16 input {xbf16}")
     ga = torch.empty(a.n_params, dtype=torch.float32, device="cuda")
     gb = torch.empty(b.n_params, dtype=torch.float32, device="cuda")
     la = a.backward(xt, yt, grad_out=ga).clone()
