@@ -1261,10 +1261,10 @@ __device__ __forceinline__ uint32_t mid_bin_ieee(double t, double P) {
 // One pass of the equal-count fold over `np` of the block's periods
 // (np = 4, one word; np = 2, two words: region 2 + p of the LDS histogram
 // holds period p's low words). The four regions are interleaved by bin
-// (slot 4 b + region): lane = (record, region), so one 16-lane pass of a
-// 64-bit atomic carries 4 records x 4 regions, and only records of one region
-// whose bins agree mod 4 meet on a bank (with one region per pass, 16 records
-// would share 16 banks).
+// (slot 4 b + region) and each lane adds its record to the four regions in
+// rotation, so one 16-lane pass of a 64-bit atomic carries 4 records x 4
+// regions, and only records of one region whose bins agree mod 4 meet on a
+// bank group (with one region per pass, 16 records would share 4 groups).
 template <bool kTwo>
 __device__ __forceinline__ void eqcount_pass(uint64_t* hist, EqBoundary (*bnd)[kEqMaxBins + 1], int64_t* eqn, int* dsel,
                              int64_t (*wtot)[3],
@@ -1326,8 +1326,9 @@ __device__ __forceinline__ void eqcount_pass(uint64_t* hist, EqBoundary (*bnd)[k
     const int e = dsel[0];
     const int cm = ((lane >> 4) << 2) | (lane & 3), kq = (lane >> 2) & 3;   // comb, place in it
     const int lrec = wave * 64 + ((cm >> e) << (e + 2)) + (cm & ((1 << e) - 1)) + (kq << e);
-    // kEqU records per lane per step, all loaded before their updates, so
-    // their load latencies overlap. Steps wholly inside the curve take no
+    // kEqU records per lane per step; the next step's records are requested
+    // before this step's updates, so their latency overlaps them (more records
+    // per step measured slower). Steps wholly inside the curve take no
     // bounds checks; the last partial step re-reads the curve's last record
     // for indices past it and adds 0 there. Every update goes to its fast-path
     // bin; when some lane's fraction falls outside the certificate (rare) the
