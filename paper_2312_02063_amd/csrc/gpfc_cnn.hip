@@ -1496,8 +1496,8 @@ constexpr int kTW = 16;   // waves per block
 // x as two copies offset by one element, so every lane's 8-position window
 // is 4-byte aligned. A wave adds its inputs' products in order; the block
 // sums its waves in order into part_out[block][co*5+dx, then 80+co], added
-// up in block order by k_sum_parts. The block-1 gradient itself is not
-// written.
+// up in block order with the other blocks' rows (k_dw_seg, k_dw_final). The
+// block-1 gradient itself is not written.
 constexpr int kXsDw = 136;   // dwords per x copy (268 elements used)
 template <int LP, int COUT, int CIN, int WLD, int RB, int CB, int C1>
 struct ConvTLds {
