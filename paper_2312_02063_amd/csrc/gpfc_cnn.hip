@@ -2297,44 +2297,55 @@ __global__ __launch_bounds__(256, 2) void k_fc_dw_bf16(int K, int M, int N, int 
     }
 }
 
-// Working copies of the weights from the FP32 masters.
+// Working copies of the weights from the FP32 masters: the copies of master
+// parameter gi (value v already in the working type), if it is a weight of
+// conv blocks 2-4 or of the two dense layers.
 template <class P>
-__global__ __launch_bounds__(256) void k_pack(const float* __restrict__ w, typename P::T* __restrict__ wf2,
-                                              typename P::T* __restrict__ wb2, typename P::T* __restrict__ wf3,
-                                              typename P::T* __restrict__ wb3, typename P::T* __restrict__ wf4,
-                                              typename P::T* __restrict__ wb4, typename P::T* __restrict__ f1f,
-                                              typename P::T* __restrict__ f1b, typename P::T* __restrict__ f2f,
-                                              typename P::T* __restrict__ f2b, typename P::T* __restrict__ f1k) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+struct PackDst {
+    typename P::T *wf2, *wb2, *wf3, *wb3, *wf4, *wb4, *f1f, *f1b, *f2f, *f2b, *f1k;
+};
+
+template <class P>
+__device__ __forceinline__ void pack_one(int64_t gi, typename P::T v, const PackDst<P>& d) {
     // conv l = 2..4: canonical [co][ci][dx]
-    typename P::T* wf[5] = {nullptr, nullptr, wf2, wf3, wf4};
-    typename P::T* wb[5] = {nullptr, nullptr, wb2, wb3, wb4};
+    typename P::T* wf[5] = {nullptr, nullptr, d.wf2, d.wf3, d.wf4};
+    typename P::T* wb[5] = {nullptr, nullptr, d.wb2, d.wb3, d.wb4};
+#pragma unroll
     for (int l = 2; l <= 4; ++l) {
         const int Cin = CH[l - 1], Cout = CH[l];
-        const int64_t n = (int64_t)Cout * Cin * 5;
-        if (i < n) {
+        const int64_t i = gi - kConvW[l];
+        if (i >= 0 && i < (int64_t)Cout * Cin * 5) {
             const int dx = (int)(i % 5), ci = (int)((i / 5) % Cin), co = (int)(i / (5 * Cin));
-            const typename P::T v = P::from_f(w[kConvW[l] + i]);
             wf[l][(int64_t)co * (5 * Cin) + dx * Cin + ci] = v;
             wb[l][(int64_t)ci * (5 * Cout) + dx * Cout + co] = v;
         }
     }
-    if (i < 256 * 1024) {
-        const int o = (int)(i >> 10), ic = (int)(i & 1023);          // canonical c*16 + x
-        const int j = (ic & 15) * 64 + (ic >> 4);                      // position-major x*64 + c
-        const typename P::T v = P::from_f(w[F1W + i]);
-        f1f[(int64_t)o * 1024 + j] = v;
-        f1b[(int64_t)j * 256 + o] = v;
-        // k-blocked copy for k_fc1_bf16: [j / 32][o][j % 32], one 32-column
-        // slice of the layer a contiguous 16 KB
-        f1k[((int64_t)(j >> 5) * 256 + o) * 32 + (j & 31)] = v;
+    {
+        const int64_t i = gi - F1W;
+        if (i >= 0 && i < 256 * 1024) {
+            const int o = (int)(i >> 10), ic = (int)(i & 1023);          // canonical c*16 + x
+            const int j = (ic & 15) * 64 + (ic >> 4);                      // position-major x*64 + c
+            d.f1f[(int64_t)o * 1024 + j] = v;
+            d.f1b[(int64_t)j * 256 + o] = v;
+            // k-blocked copy for k_fc1_bf16: [j / 32][o][j % 32], one 32-column
+            // slice of the layer a contiguous 16 KB
+            d.f1k[((int64_t)(j >> 5) * 256 + o) * 32 + (j & 31)] = v;
+        }
     }
-    if (i < 64 * 256) {
-        const int o = (int)(i >> 8), ii = (int)(i & 255);
-        const typename P::T v = P::from_f(w[F2W + i]);
-        f2f[i] = v;
-        f2b[(int64_t)ii * 64 + o] = v;
+    {
+        const int64_t i = gi - F2W;
+        if (i >= 0 && i < 64 * 256) {
+            const int o = (int)(i >> 8), ii = (int)(i & 255);
+            d.f2f[i] = v;
+            d.f2b[(int64_t)ii * 64 + o] = v;
+        }
     }
+}
+
+template <class P>
+__global__ __launch_bounds__(256) void k_pack(const float* __restrict__ w, PackDst<P> d) {
+    const int64_t gi = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (gi < kNP) pack_one<P>(gi, P::from_f(w[gi]), d);
 }
 
 // Largest value of a non-negative bf16 activation tensor (float bits order
@@ -2388,10 +2399,13 @@ __global__ __launch_bounds__(256) void k_quant_rows(const uint16_t* __restrict__
 // the new value. Launch with kAdamBlocks blocks (few: the count is one
 // memory-side atomic per block, with no cache maintenance).
 constexpr int kAdamBlocks = 256;
+// PK: the updated weights' working copies are written too (as k_pack writes
+// them), so the next forward pass need not re-pack.
+template <class P, bool PK>
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
                                               float* __restrict__ m, float* __restrict__ v, int64_t n,
                                               float lr, float b1, float b2, float eps,
-                                              int32_t* __restrict__ step) {
+                                              int32_t* __restrict__ step, PackDst<P> d) {
     __shared__ float corr[2];
     __shared__ int32_t t_sh;
     if (threadIdx.x == 0) {
@@ -2408,7 +2422,9 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
         const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
         m[i] = mi;
         v[i] = vi;
-        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        const float pn = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        p[i] = pn;
+        if constexpr (PK) pack_one<P>(i, P::from_f(pn), d);
     }
     // thread 0 read step[0] before the barrier above, so its block has read
     // it before it is counted
@@ -2572,6 +2588,13 @@ int32_t cnn_err(hipError_t e, const char* what) {
     return GPFC_EDEVICE;
 }
 
+template <class P>
+gcnn::PackDst<P> pack_dst(gpfc_cnn* c) {
+    using T = typename P::T;
+    return gcnn::PackDst<P>{(T*)c->wf2, (T*)c->wb2, (T*)c->wf3, (T*)c->wb3, (T*)c->wf4, (T*)c->wb4,
+                            (T*)c->f1f, (T*)c->f1b, (T*)c->f2f, (T*)c->f2b, (T*)c->f1k};
+}
+
 // True while `s` records into a graph: work enqueued now has not run yet, so
 // the working copies it makes cannot be marked ready, and a graph must make
 // its own (each replay then uses the network's current weights).
@@ -2583,9 +2606,8 @@ bool capturing(hipStream_t s) {
 template <class P>
 int32_t pack(gpfc_cnn* c, hipStream_t s) {
     using T = typename P::T;
-    hipLaunchKernelGGL((gcnn::k_pack<P>), dim3(gcnn::blocks_for(256 * 1024)), dim3(256), 0, s,
-                       c->params, (T*)c->wf2, (T*)c->wb2, (T*)c->wf3, (T*)c->wb3, (T*)c->wf4,
-                       (T*)c->wb4, (T*)c->f1f, (T*)c->f1b, (T*)c->f2f, (T*)c->f2b, (T*)c->f1k);
+    hipLaunchKernelGGL((gcnn::k_pack<P>), dim3(gcnn::blocks_for(gcnn::kNP)), dim3(256), 0, s, c->params,
+                       pack_dst<P>(c));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cnn_err(e, "k_pack");
     c->packed = !capturing(s);   // a captured pack runs only when the graph does
@@ -3110,11 +3132,29 @@ static bool adam_args_ok(float lr, float beta1, float beta2) {
 }
 
 static int32_t enqueue_adam(gpfc_cnn* c, float lr, float beta1, float beta2, float eps, hipStream_t s) {
-    hipLaunchKernelGGL(gcnn::k_adam, dim3(gcnn::kAdamBlocks), dim3(256), 0, s, c->params,
-                       c->grad, c->m, c->v, (int64_t)gcnn::kNP, lr, beta1, beta2, eps, c->step_dev);
+    // outside a graph capture the update also writes the working copies (a
+    // captured forward packs its own: each replay uses the current weights)
+    const bool pk = !capturing(s);
+    if (c->prec)
+        if (pk)
+            hipLaunchKernelGGL((gcnn::k_adam<gcnn::F32, true>), dim3(gcnn::kAdamBlocks), dim3(256), 0, s, c->params,
+                               c->grad, c->m, c->v, (int64_t)gcnn::kNP, lr, beta1, beta2, eps, c->step_dev,
+                               pack_dst<gcnn::F32>(c));
+        else
+            hipLaunchKernelGGL((gcnn::k_adam<gcnn::F32, false>), dim3(gcnn::kAdamBlocks), dim3(256), 0, s,
+                               c->params, c->grad, c->m, c->v, (int64_t)gcnn::kNP, lr, beta1, beta2, eps,
+                               c->step_dev, pack_dst<gcnn::F32>(c));
+    else if (pk)
+        hipLaunchKernelGGL((gcnn::k_adam<gcnn::BF16, true>), dim3(gcnn::kAdamBlocks), dim3(256), 0, s, c->params,
+                           c->grad, c->m, c->v, (int64_t)gcnn::kNP, lr, beta1, beta2, eps, c->step_dev,
+                           pack_dst<gcnn::BF16>(c));
+    else
+        hipLaunchKernelGGL((gcnn::k_adam<gcnn::BF16, false>), dim3(gcnn::kAdamBlocks), dim3(256), 0, s,
+                           c->params, c->grad, c->m, c->v, (int64_t)gcnn::kNP, lr, beta1, beta2, eps,
+                           c->step_dev, pack_dst<gcnn::BF16>(c));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cnn_err(e, "k_adam");
-    c->packed = false;
+    c->packed = pk;
     c->quantized = false;
     return GPFC_OK;
 }
